@@ -1,0 +1,45 @@
+"""Writes tests/golden/oracle_ipm.json: the FP64 oracle's interior-point results
+on the seeded workloads (iterations, objective, final residuals, mu trace).
+
+Calls only the oracle and the instance generator.  Run from the repository
+root:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import ipm  # noqa: E402
+from paper_2412_07731_amd import gen  # noqa: E402
+
+
+def run(config, seed):
+    inst = gen.generate(config, seed)
+    t = time.time()
+    r = ipm.solve(inst)
+    return dict(config=config, seed=seed, status=r.status, iterations=r.iterations,
+                pobj=r.pobj, dobj=r.dobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
+                mu=r.mu, fstar=inst.fstar, refine_steps=r.refine_steps,
+                max_bkerr=r.max_bkerr, pivots=r.pivots,
+                mu_trace=[h["mu"] for h in r.history],
+                seconds=round(time.time() - t, 2))
+
+
+def main():
+    out = {"note": "FP64 oracle results; written by tests/golden/make_golden.py",
+           "runs": []}
+    for seed in range(8):
+        out["runs"].append(run("tiny", seed))
+    if "--quick" not in sys.argv:
+        out["runs"].append(run("n512", 0))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_ipm.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()
