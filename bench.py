@@ -1,0 +1,168 @@
+"""Benchmark: interior-point iterations/sec and Schur-assembly TFLOP/s of the
+Newton-system solve on the N=512 time-block LP (256 x 512 blocks at 10%
+density stored dense, 16 local links per pair, 32 linking variables), FP64 and
+FP32 MFMA + FP64 refinement, on one GPU.
+
+A step is one complete interior-point solve (Mehrotra start, then iterations
+until relative gap, primal and dual infeasibility are all <= 1e-8).  Every
+iteration runs the whole hot path: residuals, D-scaling and link columns, block
+SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
+factorization, predictor and corrector solves with FP64 refinement.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--profile]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def flops(inst):
+    """Algorithmic flops of one factorization, LAPACK counting (block SYRK,
+    POTRF, TRSM against the linking columns, Schur SYRK), dense-stored blocks."""
+    syrk = potrf = trsm = schur = 0.0
+    N = inst.N
+    for i in range(N):
+        m, n = float(inst.m[i]), float(inst.n[i])
+        k = float((inst.l[i - 1] if i >= 1 else 0) + (inst.l[i] if i < N - 1 else 0) + inst.n0)
+        syrk += m * (m + 1) * n
+        potrf += m ** 3 / 3 + m ** 2 / 2 + m / 6
+        trsm += m * m * k
+        schur += k * (k + 1) * m
+    return dict(syrk=syrk, potrf=potrf, trsm=trsm, schur=schur, total=syrk + potrf + trsm + schur)
+
+
+def cpu_baseline(inst, iters):
+    """The FP64 oracle on the host cores: Mehrotra start plus `iters` iterations
+    of the same instance; iterations/sec."""
+    from threadpoolctl import threadpool_info
+    from oracle import ipm as oipm
+    t = time.perf_counter()
+    r = oipm.solve(inst, max_iter=iters)
+    dt = time.perf_counter() - t
+    threads = max((i.get("num_threads", 1) for i in threadpool_info()
+                   if "numpy" in i.get("filepath", "")), default=1)
+    return {"value": r.iterations / dt, "unit": "IPM iterations/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"start point + {r.iterations} iterations of the N=512 instance (seed 0), "
+                      f"{dt:.1f} s; NumPy/SciPy OpenBLAS FP64"}
+
+
+def run(P, steps, warmup, **opts):
+    import torch
+    for _ in range(warmup):
+        P.ipm(**opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        results.append(P.ipm(**opts)[3])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true", help="short run for profilers")
+    ap.add_argument("--fp32", action="store_true", help="time the FP32+refine path as the main line")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(every box here has one GPU); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2412_07731_amd import gen
+    from paper_2412_07731_amd.ahlp import FP32_REFINE, FP64, Problem
+
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_ipm.json")
+    if os.path.exists(gpath):
+        for r in json.load(open(gpath))["runs"]:
+            if r["config"] == "n512" and r["seed"] == 0:
+                golden = r
+    inst = gen.generate("n512", 0)
+    fl = flops(inst)
+    torch.cuda.set_device(0)
+    P = Problem(inst)
+    if args.profile:
+        args.steps, args.warmup = 1, 0
+    main_prec = FP32_REFINE if args.fp32 else FP64
+    dt, res = run(P, args.steps, args.warmup, precision=main_prec, timing=1)
+    iters = sum(r["iterations"] for r in res)
+    r0 = res[-1]
+    ok = all(r["status"] == 0 for r in res)
+
+    # per-stage device times (HIP events on the library's stream, timed region)
+    st = {k: sum(r["t_stage_ms"][k] for r in res) for k in r0["t_stage_ms"]}
+    cnt = {k: sum(r["n_stage"][k] for r in res) for k in r0["n_stage"]}
+    nfact = max(cnt["syrk"], 1)
+    t_asm_ms = (st["prep"] + st["syrk"] + st["factor"] + st["schur"]) / nfact
+    # prep and schur stages hold two launches each per factorization
+    asm_tflops = fl["total"] / (t_asm_ms * 1e-3) / 1e12
+    syrk_ms = st["syrk"] / nfact
+    syrk_tflops = fl["syrk"] / (syrk_ms * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if main_prec == FP32_REFINE else PEAK_FP64_TFLOPS
+
+    line = {
+        "metric": "IPM iterations/sec + Schur-assembly TFLOP/s at N=512 (FP64 vs FP32+refine)",
+        "value": iters / dt,
+        "unit": "IPM iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if main_prec == FP32_REFINE else "f64",
+        "data": "synthetic",
+        "config": {"workload": "n512: N=512 blocks 256x512 (10% nonzero, stored dense), "
+                               "16 local links per pair, 32 linking variables, seed 0",
+                   "N": 512, "m_i": 256, "n_i": 512, "l": 16, "n0": 32, "density": 0.1,
+                   "precision": "fp32+refine" if main_prec == FP32_REFINE else "fp64"},
+        "iterations_per_solve": r0["iterations"],
+        "converged": ok,
+        "objective": r0["primal_obj"],
+        "objective_rel_err_vs_oracle": (abs(r0["primal_obj"] - golden["pobj"]) / max(1.0, abs(golden["pobj"]))
+                                        if golden else None),
+        "oracle_iterations": golden["iterations"] if golden else None,
+        "schur_assembly": {"gflop_per_factor": fl["total"] / 1e9, "ms_per_factor": t_asm_ms,
+                           "tflops": asm_tflops, "frac_of_peak": asm_tflops / peak},
+        "stage_ms_per_solve": {k: v / args.steps for k, v in st.items()},
+        "stage_launches_per_solve": {k: v / args.steps for k, v in cnt.items()},
+        "roofline": {"kernel": "k_syrk (block SYRK M_i = A_i D_i A_i')", "bound": "mfma",
+                     "achieved": syrk_tflops, "peak": peak, "unit": "TFLOP/s",
+                     "frac": syrk_tflops / peak, "traffic": None,
+                     "flop_per_launch": fl["syrk"], "avg_launch_ms": syrk_ms},
+    }
+    if not args.profile and not args.fp32:
+        dt32, res32 = run(P, args.steps, args.warmup, precision=FP32_REFINE, timing=0)
+        it32 = sum(r["iterations"] for r in res32)
+        r32 = res32[-1]
+        line["fp32_refine"] = {
+            "value": it32 / dt32, "unit": "IPM iterations/s",
+            "iterations_per_solve": r32["iterations"], "fp32_iterations": r32["fp32_iterations"],
+            "refine_steps": r32["refine_steps"], "converged": all(r["status"] == 0 for r in res32),
+            "objective_rel_err_vs_oracle": (abs(r32["primal_obj"] - golden["pobj"]) / max(1.0, abs(golden["pobj"]))
+                                            if golden else None),
+            "speedup_vs_fp64": (it32 / dt32) / (iters / dt)}
+    if not args.no_cpu and not args.profile:
+        line["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters)
+    P.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * ahlp.h -- C ABI of libahlp: the per-iteration Newton-system solve of a
+ * primal-dual interior-point method for arrowhead linear programs with local
+ * linking structure, on one AMD MI355X (gfx950).
+ *
+ * The LP (Sec. 2.2 standard form with the block structure of Sec. 3.2,
+ * equality rows and local two-link constraints of Sec. 3.3):
+ *
+ *     min c'x   s.t.  A_i x_i + C_i x_0                        = b_i    i = 0..N-1
+ *                     FR_j x_j + FL_j x_{j+1} + F0_j x_0       = b_Lj   j = 0..N-2
+ *                     x >= 0
+ *
+ * (A_i is the paper's B_i, C_i its A_i, FR_j its local block F_j, FL_j its F'_j,
+ * F0 the local part of its F_0.)  Canonical vector order:
+ *     x, z = [x_0-block .. x_{N-1}-block, x_0]       length n_tot = sum n_i + n0
+ *     y    = [y_0 .. y_{N-1}, y_L(pair 0) .. y_L(pair N-2)]   m_tot = sum m_i + sum l_j
+ *
+ * Conventions for every call:
+ *   - Status codes: 0 on success, negative on error, positive for warnings whose
+ *     outputs are valid.  On error ahlp_last_error() returns a message
+ *     (thread-local; valid until the next call on the same thread).
+ *   - "device" pointers are HIP device memory on the device that was current
+ *     when the problem was created; "host" pointers are ordinary CPU memory.
+ *   - Calls are stream ordered on the given stream (0 = the null stream).
+ *     ahlp_kkt_factor and ahlp_kkt_solve return after enqueueing unless noted;
+ *     ahlp_problem_create and ahlp_ipm_solve synchronize the stream.
+ *   - A handle is not thread safe; distinct handles are independent.
+ *   - Results are bitwise reproducible for the same inputs, device and stream
+ *     (fixed-order reductions; no floating-point atomics).
+ */
+#ifndef AHLP_H
+#define AHLP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ahlp_problem_s* ahlp_problem_t;   /* opaque, library owned */
+
+typedef enum {
+  AHLP_OK = 0,
+  AHLP_EINVAL = -1,    /* null or inconsistent arguments, unsupported sizes     */
+  AHLP_ENOMEM = -2,    /* device or host allocation failed                        */
+  AHLP_EHIP = -3,      /* HIP runtime or launch error                             */
+  AHLP_ESTATE = -4,    /* call out of order (e.g. solve before factor)            */
+  AHLP_ENUMERIC = -5,  /* non-finite data, or x <= 0 / z <= 0 handed to factor     */
+  AHLP_WMAXITER = 1,   /* interior-point loop stopped at max_iter                  */
+  AHLP_WSTALL = 2      /* interior-point step length collapsed                     */
+} ahlp_status_t;
+
+typedef enum {
+  AHLP_FP64 = 0,         /* every stage in FP64                                    */
+  AHLP_FP32_REFINE = 1   /* block SYRK / Cholesky / TRSM in FP32 MFMA with FP32
+                            accumulation; Schur assembly and factorization,
+                            residuals and refinement in FP64                        */
+} ahlp_precision_t;
+
+/* Problem data for ahlp_problem_create.  All arrays are HOST memory, FP64,
+ * row-major per block, blocks concatenated in order.  Limits: N >= 1,
+ * 1 <= m_i <= n_i, 0 <= l_j <= min(n_j, n_{j+1}, 64), 0 <= n0 <= 128. */
+typedef struct {
+  int32_t N;              /* number of diagonal blocks                              */
+  int32_t n0;             /* number of linking variables x_0                        */
+  const int32_t* m;       /* [N]   rows of A_i                                      */
+  const int32_t* n;       /* [N]   columns of A_i                                   */
+  const int32_t* l;       /* [N-1] local linking rows between blocks j and j+1 (may
+                             be NULL when N == 1)                                   */
+  const double* A;        /* concat_i A_i   (m_i x n_i)                             */
+  const double* C;        /* concat_i C_i   (m_i x n0); NULL iff n0 == 0             */
+  const double* FR;       /* concat_j FR_j  (l_j x n_j)      block j's part of pair j */
+  const double* FL;       /* concat_j FL_j  (l_j x n_{j+1})  block j+1's part        */
+  const double* F0;       /* (sum l) x n0 coupling of link rows to x_0; NULL = 0     */
+  const double* b;        /* [m_tot]                                                 */
+  const double* c;        /* [n_tot]                                                 */
+} ahlp_problem_desc_t;
+
+/* Regularization of the factorization (a reading: the paper leaves pivot
+ * handling to its sparse solvers).  With D = (Z/X + rho)^-1 the block matrices
+ * are M_i = A_i D_i A_i' + delta I and the link part of the Schur complement
+ * gets + delta I. */
+typedef struct {
+  ahlp_precision_t precision;
+  double rho;             /* primal regularization, >= 0                           */
+  double delta;           /* dual regularization, >= 0                             */
+} ahlp_factor_opts_t;
+
+typedef struct {
+  double tol;             /* stop when relgap, pinf and dinf are all <= tol (1e-8)   */
+  int32_t max_iter;       /* 100                                                     */
+  double eta;             /* step damping 0.99                                       */
+  double rho, delta;      /* 1e-8, 1e-6                                              */
+  int32_t max_refine;     /* refinement corrections per solve (5)                    */
+  double refine_tol;      /* backward-error target (1e-10)                           */
+  ahlp_precision_t precision;
+  double mu_switch;       /* FP32 mode: switch to FP64 blocks for good once mu < this */
+  int32_t start;          /* 0 = Mehrotra starting point, 1 = use x, y, z as given    */
+  int32_t verbose;        /* 1 = one log line per iteration on stderr                */
+  int32_t timing;         /* 1 = record per-stage device times (HIP events)          */
+} ahlp_ipm_opts_t;
+
+/* Stage indices of ahlp_ipm_result_t.t_stage_ms / n_stage. */
+enum {
+  AHLP_ST_PREP = 0,       /* D-scaling, link columns (a1)                            */
+  AHLP_ST_SYRK = 1,       /* M_i = A_i D_i A_i' (a2)                                 */
+  AHLP_ST_FACTOR = 2,     /* Cholesky of M_i and W_i = L_i^-1 B_i (a3, a4)            */
+  AHLP_ST_SCHUR = 3,      /* W_i' W_i and assembly of S (a5)                          */
+  AHLP_ST_TFACTOR = 4,    /* block-tridiagonal + border factorization of S (a6)       */
+  AHLP_ST_SOLVE = 5,      /* solve phase (a7)                                         */
+  AHLP_ST_RESID = 6,      /* residuals, reductions, refinement residuals (a8)         */
+  AHLP_ST_COUNT = 8
+};
+
+typedef struct {
+  int32_t status;         /* ahlp_status_t of the run                                */
+  int32_t iterations;     /* factorizations after the starting point                 */
+  int32_t refine_steps;   /* refinement corrections, all solves                      */
+  int32_t pivots_modified;/* pivots replaced by the pivot rule                        */
+  int32_t fp32_iterations;/* iterations whose blocks were factored in FP32           */
+  double primal_obj, dual_obj, rel_gap, rel_pinf, rel_dinf, mu;
+  double max_bkerr;       /* largest backward error after refinement                 */
+  double t_total_ms;      /* wall time of the call                                   */
+  double t_stage_ms[AHLP_ST_COUNT];   /* summed device time per stage (timing=1)     */
+  int32_t n_stage[AHLP_ST_COUNT];     /* number of timed launches per stage         */
+} ahlp_ipm_result_t;
+
+/* Fills *opts with the defaults listed above. */
+void ahlp_ipm_default_opts(ahlp_ipm_opts_t* opts);
+
+/* Packs the problem into library-owned device memory (tile-major blocks; link
+ * rows as compressed sparse rows and columns).  The caller may free desc's
+ * arrays on return.  Synchronizes `stream`.  Errors: AHLP_EINVAL for sizes out
+ * of range, AHLP_ENUMERIC for non-finite data, AHLP_ENOMEM, AHLP_EHIP. */
+ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* desc, hipStream_t stream,
+                                  ahlp_problem_t* out);
+
+/* Releases everything the handle owns.  NULL is accepted. */
+ahlp_status_t ahlp_problem_destroy(ahlp_problem_t p);
+
+/* Factorization, Alg. 2 of Sec. 3.2 in the normal-equation form: per block
+ * M_i = A_i D_i A_i' (+ delta I) and its Cholesky factor, W_i = L_i^-1 B_i with
+ * B_i = [A_i D_i F_i' | C_i], the Schur complement S = K0' - sum W_i' W_i (block
+ * tridiagonal over the link pairs plus the x_0 border, App. A), and its
+ * factorization.  x, z: DEVICE [n_tot], copied; must be finite and positive
+ * (checked on the device; reported by the next synchronizing call as
+ * AHLP_ENUMERIC).  The factors stay in the handle until the next factor call. */
+ahlp_status_t ahlp_kkt_factor(ahlp_problem_t p, const double* x, const double* z,
+                              const ahlp_factor_opts_t* opts, hipStream_t stream);
+
+/* Solve, Alg. 3 of Sec. 3.2: (dx, dy, dz) for the Newton system of Sec. 2.3
+ *     [0 A' I; A 0 0; Z 0 X] [dx; dy; dz] = [rx; ry; rz]
+ * at the (x, z) of the last factorization.  All six vectors are DEVICE memory
+ * (rx, dx, rz, dz: [n_tot]; ry, dy: [m_tot]); outputs must not alias inputs.
+ * With max_refine > 0 the direction is refined in FP64 against the
+ * unregularized matrix until the backward error is <= refine_tol (this
+ * synchronizes the stream once per correction).  *bkerr (host, may be NULL)
+ * receives the final backward error when max_refine > 0.
+ * AHLP_ESTATE if no factorization exists. */
+ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* ry,
+                             const double* rz, double* dx, double* dy, double* dz,
+                             int32_t max_refine, double refine_tol, double* bkerr,
+                             hipStream_t stream);
+
+/* The Mehrotra predictor-corrector loop (Sec. 2.3) around factor and solve.
+ * x, z: DEVICE [n_tot], y: DEVICE [m_tot]; outputs, and inputs when
+ * opts->start == 1.  Synchronous.  res (host) receives the summary.
+ * Returns AHLP_OK, AHLP_WMAXITER, AHLP_WSTALL or an error. */
+ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* opts, double* x,
+                             double* y, double* z, ahlp_ipm_result_t* res,
+                             hipStream_t stream);
+
+/* Last error message of this thread ("" when none). */
+const char* ahlp_last_error(void);
+
+/* ---- inspection (tests and profiling; synchronize the stream) ------------
+ * Copy intermediate results of the last factorization to HOST memory in the
+ * canonical dense layouts below.  They exist so that every stage can be
+ * compared with an independent implementation. */
+
+/* Sizes: n_tot, m_tot, number of link rows sum(l), n0. */
+ahlp_status_t ahlp_problem_sizes(ahlp_problem_t p, int64_t* n_tot, int64_t* m_tot,
+                                 int64_t* n_link, int32_t* n0);
+
+/* Block i: L (m_i x m_i, row-major, lower triangle; upper part zero) and
+ * W = L^-1 B_i (m_i x k_i row-major, k_i = l_{i-1} + l_i + n0, columns ordered
+ * [pair i-1 | pair i | x_0]).  Either pointer may be NULL.  FP32 factors are
+ * widened to FP64. */
+ahlp_status_t ahlp_debug_block(ahlp_problem_t p, int32_t i, double* L, double* W);
+
+/* The assembled Schur complement S = K0' - sum W_i' W_i as one dense
+ * (sum l + n0)^2 row-major array (small problems only), before factorization. */
+ahlp_status_t ahlp_debug_schur(ahlp_problem_t p, double* S);
+
+/* Pivots replaced by the pivot rule in the last factorization (synchronizes). */
+ahlp_status_t ahlp_debug_pivots(ahlp_problem_t p, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AHLP_H */

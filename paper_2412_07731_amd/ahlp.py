@@ -1,0 +1,220 @@
+"""ctypes binding of libahlp.so (declared in include/ahlp.h).
+
+Only argument marshalling lives here: every step of the Newton solve and of the
+interior-point loop runs in the library's HIP kernels.  PyTorch supplies device
+memory and the stream.  There is no fallback: if the library is missing or no
+GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libahlp.so")
+
+FP64, FP32_REFINE = 0, 1
+STATUS = {0: "ok", -1: "einval", -2: "enomem", -3: "ehip", -4: "estate", -5: "enumeric",
+          1: "wmaxiter", 2: "wstall"}
+STAGES = ["prep", "syrk", "factor", "schur", "tfactor", "solve", "resid", "other"]
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+
+
+class Desc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("n0", C.c_int32), ("m", _i32p), ("n", _i32p), ("l", _i32p),
+                ("A", _f64p), ("C", _f64p), ("FR", _f64p), ("FL", _f64p), ("F0", _f64p),
+                ("b", _f64p), ("c", _f64p)]
+
+
+class FactorOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("rho", C.c_double), ("delta", C.c_double)]
+
+
+class IpmOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("eta", C.c_double),
+                ("rho", C.c_double), ("delta", C.c_double), ("max_refine", C.c_int32),
+                ("refine_tol", C.c_double), ("precision", C.c_int), ("mu_switch", C.c_double),
+                ("start", C.c_int32), ("verbose", C.c_int32), ("timing", C.c_int32)]
+
+
+class IpmResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("refine_steps", C.c_int32),
+                ("pivots_modified", C.c_int32), ("fp32_iterations", C.c_int32),
+                ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("rel_gap", C.c_double),
+                ("rel_pinf", C.c_double), ("rel_dinf", C.c_double), ("mu", C.c_double),
+                ("max_bkerr", C.c_double), ("t_total_ms", C.c_double),
+                ("t_stage_ms", C.c_double * 8), ("n_stage", C.c_int32 * 8)]
+
+
+# Every exported symbol with its signature (argtypes, restype).
+SIGNATURES = {
+    "ahlp_ipm_default_opts": ([C.POINTER(IpmOpts)], None),
+    "ahlp_problem_create": ([C.POINTER(Desc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "ahlp_problem_destroy": ([C.c_void_p], C.c_int),
+    "ahlp_kkt_factor": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(FactorOpts), C.c_void_p],
+                        C.c_int),
+    "ahlp_kkt_solve": ([C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_double,
+                                                          C.POINTER(C.c_double), C.c_void_p],
+                       C.c_int),
+    "ahlp_ipm_solve": ([C.c_void_p, C.POINTER(IpmOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                        C.POINTER(IpmResult), C.c_void_p], C.c_int),
+    "ahlp_last_error": ([], C.c_char_p),
+    "ahlp_problem_sizes": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                            C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
+    "ahlp_debug_block": ([C.c_void_p, C.c_int32, _f64p, _f64p], C.c_int),
+    "ahlp_debug_schur": ([C.c_void_p, _f64p], C.c_int),
+    "ahlp_debug_pivots": ([C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
+}
+
+_lib = None
+
+
+class AHLPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libahlp.so (built by paper_2412_07731_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run python -m paper_2412_07731_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code, allow_warn=False):
+    if code == 0 or (allow_warn and code > 0):
+        return code
+    raise AHLPError(code, lib().ahlp_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_f64p) if a is not None else None
+
+
+def _cat(blocks):
+    if not blocks:
+        return np.zeros(1)
+    return np.ascontiguousarray(np.concatenate([np.ascontiguousarray(b, dtype=np.float64).ravel()
+                                                for b in blocks]))
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "need contiguous cuda float64"
+    return C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A packed arrowhead LP on the current HIP device (see include/ahlp.h)."""
+
+    def __init__(self, inst, stream=None):
+        L = lib()
+        self.N, self.n0 = int(inst.N), int(inst.n0)
+        m = np.ascontiguousarray(inst.m, dtype=np.int32)
+        n = np.ascontiguousarray(inst.n, dtype=np.int32)
+        l = np.ascontiguousarray(inst.l if len(inst.l) else np.zeros(1), dtype=np.int32)
+        A = _cat(inst.A)
+        Cm = _cat(inst.C) if self.n0 > 0 else None
+        FR, FL = _cat(inst.FR), _cat(inst.FL)
+        F0 = np.ascontiguousarray(inst.F0, dtype=np.float64) if inst.F0 is not None else None
+        b = np.ascontiguousarray(inst.b, dtype=np.float64)
+        c = np.ascontiguousarray(inst.c, dtype=np.float64)
+        self._keep = (m, n, l, A, Cm, FR, FL, F0, b, c)
+        d = Desc(self.N, self.n0, m.ctypes.data_as(_i32p), n.ctypes.data_as(_i32p),
+                 l.ctypes.data_as(_i32p), _ptr(A), _ptr(Cm), _ptr(FR), _ptr(FL), _ptr(F0),
+                 _ptr(b), _ptr(c))
+        h = C.c_void_p()
+        _check(L.ahlp_problem_create(C.byref(d), _stream(stream), C.byref(h)))
+        self._keep = None
+        self.h = h
+        nt, mt, nl, n0 = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(L.ahlp_problem_sizes(h, C.byref(nt), C.byref(mt), C.byref(nl), C.byref(n0)))
+        self.n_tot, self.m_tot, self.n_link = nt.value, mt.value, nl.value
+        self.m = m.copy()
+        self.kdims = [int((inst.l[i - 1] if i >= 1 else 0) + (inst.l[i] if i < self.N - 1 else 0)
+                          + self.n0) for i in range(self.N)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ahlp_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- calls
+    def factor(self, x, z, rho=0.0, delta=0.0, precision=FP64, stream=None):
+        o = FactorOpts(precision, rho, delta)
+        _check(lib().ahlp_kkt_factor(self.h, _dptr(x), _dptr(z), C.byref(o), _stream(stream)))
+
+    def solve(self, rx, ry, rz, max_refine=0, refine_tol=1e-10, stream=None, out=None):
+        import torch
+        if out is None:
+            out = (torch.empty_like(rx), torch.empty_like(ry), torch.empty_like(rz))
+        dx, dy, dz = out
+        be = C.c_double(-1.0)
+        _check(lib().ahlp_kkt_solve(self.h, _dptr(rx), _dptr(ry), _dptr(rz), _dptr(dx), _dptr(dy),
+                                    _dptr(dz), int(max_refine), float(refine_tol), C.byref(be),
+                                    _stream(stream)))
+        return dx, dy, dz, be.value
+
+    def ipm(self, x=None, y=None, z=None, stream=None, **opts):
+        import torch
+        o = IpmOpts()
+        lib().ahlp_ipm_default_opts(C.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        x = x if x is not None else torch.zeros(self.n_tot, dtype=torch.float64, device=dev)
+        y = y if y is not None else torch.zeros(self.m_tot, dtype=torch.float64, device=dev)
+        z = z if z is not None else torch.zeros(self.n_tot, dtype=torch.float64, device=dev)
+        r = IpmResult()
+        code = lib().ahlp_ipm_solve(self.h, C.byref(o), _dptr(x), _dptr(y), _dptr(z), C.byref(r),
+                                    _stream(stream))
+        _check(code, allow_warn=True)
+        res = {f: getattr(r, f) for f, _ in IpmResult._fields_ if f not in ("t_stage_ms", "n_stage")}
+        res["status_name"] = STATUS.get(code, str(code))
+        res["t_stage_ms"] = {STAGES[i]: r.t_stage_ms[i] for i in range(8)}
+        res["n_stage"] = {STAGES[i]: r.n_stage[i] for i in range(8)}
+        return x, y, z, res
+
+    # --- inspection
+    def debug_block(self, i):
+        mi, k = int(self.m[i]), self.kdims[i]
+        Lm = np.zeros((mi, mi))
+        W = np.zeros((mi, max(k, 1)))
+        _check(lib().ahlp_debug_block(self.h, int(i), Lm.ctypes.data_as(_f64p), W.ctypes.data_as(_f64p)))
+        return Lm, W[:, :k]
+
+    def debug_schur(self):
+        dim = self.n_link + self.n0
+        S = np.zeros((max(dim, 1), max(dim, 1)))
+        _check(lib().ahlp_debug_schur(self.h, S.ctypes.data_as(_f64p)))
+        return S[:dim, :dim]
+
+    def pivots(self):
+        c = C.c_int32()
+        _check(lib().ahlp_debug_pivots(self.h, C.byref(c)))
+        return c.value

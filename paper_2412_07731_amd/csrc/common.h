@@ -1,0 +1,111 @@
+// Shared definitions of libahlp's device code and host orchestration.
+//
+// Device data layout (all dense block matrices): 16x16 tiles, column-major
+// inside a tile (element (i, k) at k*16 + i), 256 elements per tile.  With this
+// layout the operands of a 16x16x4 MFMA are contiguous: for k-step s a lane l
+// reads element 64*s + l of the tile, for both the A operand (rows of C) and the
+// B operand of a product with a transposed tile (C += X Y').  Block rows are
+// padded to a multiple of 16 with zero rows, block columns likewise.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ahlp {
+
+constexpr int TS = 16;          // tile edge
+constexpr int TE = 256;         // elements per tile
+constexpr double PIVOT_REL = 1e-30;
+constexpr double PIVOT_BIG = 1e128;
+constexpr int LMAX = 64;        // largest link pair handled by the chain kernels
+constexpr int N0MAX = 128;      // largest number of linking variables
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Per-block geometry, offsets and section layout (host computes, device reads).
+struct BlockInfo {
+  int m, n;          // real rows / columns of A_i
+  int mt, nt;        // tile counts of the padded block (16 mt x 16 nt)
+  int kt, rt;        // link-column tiles (kp = 16 kt) and bordered tile rows mt + kt
+  int lL, lR;        // real rows of the left pair (i-1) and right pair (i); 0 at the ends
+  int ktL, ktR, kt0; // tiles of the left, right and x_0 sections of the link columns
+  int pairL, pairR;  // pair indices, -1 when absent
+  int csr_off;       // this block's kp+1 link-row pointers start here in linkptr
+  int csc_off;       // this block's n+1 link-column pointers start here in lcolptr
+  long long xoff, yoff;   // offsets in the canonical x and y vectors
+  long long dpoff;        // offset in the padded D vector (multiple of 16)
+  long long aoff;         // A tiles (mt x nt, row-of-tiles major)
+  long long coff;         // C tiles (mt x kt0)
+  long long lboff;        // bordered factor: lower-trapezoid tile columns, packed
+  long long linvoff;      // mt inverted diagonal tiles of L_i
+  long long pqoff;        // kt x kt tiles of the Schur contribution F D F' - W'W
+  long long loffL, loffR; // start of the left / right pair inside y_L (-1 if none)
+  long long voff;         // offset of the block in padded block-row vectors (sum 16 mt)
+  long long qoff;         // offset in link-column vectors (sum 16 kt)
+};
+
+// Column c of the bordered factor holds tile rows c..rt-1 contiguously.
+__host__ __device__ inline long long lb_tile(const BlockInfo& b, int r, int c) {
+  long long colstart = (long long)c * b.rt - (long long)c * (c - 1) / 2;
+  return b.lboff + (colstart + (r - c)) * TE;
+}
+__host__ __device__ inline long long lb_tiles(int mt, int rt) {
+  return (long long)mt * rt - (long long)mt * (mt - 1) / 2;
+}
+__host__ __device__ inline long long a_tile(const BlockInfo& b, int I, int K) {
+  return b.aoff + ((long long)I * b.nt + K) * TE;
+}
+__host__ __device__ inline long long c_tile(const BlockInfo& b, int I, int Q) {
+  return b.coff + ((long long)I * b.kt0 + Q) * TE;
+}
+__host__ __device__ inline long long pq_tile(const BlockInfo& b, int r, int c) {
+  return b.pqoff + ((long long)r * b.kt + c) * TE;
+}
+
+// Link-column section of row q (0 <= q < 16 kt): 0 left pair, 1 right pair,
+// 2 x_0; *idx receives the index inside the section and *real whether it is a
+// real (not padding) row.
+__host__ __device__ inline int link_section(const BlockInfo& b, int q, int* idx, int n0, bool* real) {
+  int qL = TS * b.ktL, qR = TS * b.ktR;
+  if (q < qL) { *idx = q; *real = q < b.lL; return 0; }
+  q -= qL;
+  if (q < qR) { *idx = q; *real = q < b.lR; return 1; }
+  q -= qR;
+  *idx = q; *real = q < n0; return 2;
+}
+
+// D += A B for a 16x16x4 block: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// the result follows acc_index below.
+__device__ inline d4 mfma(double a, double b, d4 c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+#else
+  return c;
+#endif
+}
+__device__ inline f4 mfma(float a, float b, f4 c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+#else
+  return c;
+#endif
+}
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4 type; };
+template <> struct Acc<float> { typedef f4 type; };
+
+// Index inside a column-major tile of accumulator element r of lane l:
+// the 16x16 MFMA result holds (row 4*(l/16) + r, column l%16).
+__host__ __device__ inline int acc_index(int lane, int r) {
+  return (lane & 15) * TS + 4 * (lane >> 4) + r;
+}
+
+// Status/info word shared by all kernels of one handle.
+struct DevInfo {
+  int pivots;       // pivots replaced by the pivot rule
+  int nonfinite;    // x or z not finite / not positive at factor
+};
+
+}  // namespace ahlp

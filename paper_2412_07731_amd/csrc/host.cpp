@@ -1,0 +1,1081 @@
+// Host side of libahlp: problem packing, stage orchestration on one HIP
+// stream, FP64 iterative refinement and the Mehrotra predictor-corrector loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ahlp.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace ahlp;
+
+namespace {
+
+thread_local std::string g_err;
+
+ahlp_status_t fail(ahlp_status_t st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? AHLP_ENOMEM : AHLP_EHIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define CHK(expr)                      \
+  do {                                 \
+    ahlp_status_t s_ = (expr);         \
+    if (s_ != AHLP_OK) return s_;      \
+  } while (0)
+
+inline long long r16(long long v) { return (v + 15) / 16 * 16; }
+
+// Device allocation registry: everything is freed by destroy.
+struct DevMem {
+  std::vector<void*> ptrs;
+  ~DevMem() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  ahlp_status_t alloc(T** out, long long count) {
+    *out = nullptr;
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)count * sizeof(T));
+    if (e != hipSuccess)
+      return fail(AHLP_ENOMEM, "hipMalloc of %lld bytes failed: %s", (long long)(count * sizeof(T)),
+                  hipGetErrorString(e));
+    ptrs.push_back(p);
+    *out = static_cast<T*>(p);
+    return AHLP_OK;
+  }
+};
+
+struct StageTimer {
+  bool on = false;
+  hipStream_t st = nullptr;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[AHLP_ST_COUNT] = {0};
+  int cnt[AHLP_ST_COUNT] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int stage) {
+    if (!on) return;
+    Rec r{stage, get(), get()};
+    (void)hipEventRecord(r.a, st);
+    pending.push_back(r);
+  }
+  void end() {
+    if (!on || pending.empty()) return;
+    (void)hipEventRecord(pending.back().b, st);
+  }
+  // call after a stream synchronization
+  void collect() {
+    for (auto& r : pending) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.stage] += t;
+        cnt[r.stage] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    collect();
+    for (int i = 0; i < AHLP_ST_COUNT; ++i) { ms[i] = 0; cnt[i] = 0; }
+  }
+  ~StageTimer() {
+    for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct ahlp_problem_s {
+  int device = 0;
+  int N = 0, n0 = 0, n0p = 0, P = 0, G = 0;
+  std::vector<int> m, n, l;
+  std::vector<BlockInfo> hb;
+  std::vector<long long> loff, tdoff, tooff, eoff, zoff, suboff;
+  std::vector<int2> seg;
+  long long n_tot = 0, m_tot = 0, nl = 0, mblk = 0, x0off = 0, d0off = 0, dp_total = 0;
+  long long vp_total = 0, q_total = 0, a_total = 0, c_total = 0, lb_total = 0, linv_total = 0,
+            pq_total = 0;
+  int max_rt = 0, lmax = 0;
+  double colabs1_max = 1.0, rowabs_max = 0.0, b_inf = 0.0, c_inf = 0.0;
+  DevMem mem;
+
+  // problem data
+  BlockInfo* blk = nullptr;
+  double *A = nullptr, *C = nullptr, *F0 = nullptr, *b = nullptr, *c = nullptr;
+  float* A32 = nullptr;
+  int *lptr = nullptr, *lcol = nullptr, *cptr = nullptr, *crow = nullptr;
+  double *lval = nullptr, *cval = nullptr;
+  int4* syrk_items = nullptr;
+  int nsyrk = 0;
+  int2* link_items = nullptr;
+  int nlink = 0;
+  int2 *rowtiles = nullptr, *coltiles = nullptr;
+  int nrt = 0, nct = 0;
+  int* d_l = nullptr;
+  long long *d_loff = nullptr, *d_tdoff = nullptr, *d_tooff = nullptr, *d_eoff = nullptr,
+            *d_zoff = nullptr, *d_suboff = nullptr;
+  int2* d_seg = nullptr;
+
+  // factorization
+  double *Dp = nullptr, *xs = nullptr, *zs = nullptr;
+  double *LB = nullptr, *LINV = nullptr, *PQ = nullptr;
+  float *LB32 = nullptr, *LINV32 = nullptr;
+  double *Td = nullptr, *To = nullptr, *E = nullptr, *S00 = nullptr, *thrT = nullptr;
+  double *CL = nullptr, *CLi = nullptr, *CYn = nullptr, *CZ = nullptr, *CG = nullptr,
+         *CSub = nullptr, *Lb = nullptr, *Lbi = nullptr, *S00w = nullptr, *segout = nullptr;
+  DevInfo* info = nullptr;
+  bool factored = false;
+  int fprec = AHLP_FP64;
+  double rho = 0, delta = 0;
+  int pivots_seen = 0;
+
+  // solve workspace
+  double *rhx = nullptr, *vx = nullptr, *tv = nullptr, *qn = nullptr, *s = nullptr, *w = nullptr,
+         *u = nullptr, *dyp = nullptr, *g = nullptr, *part = nullptr, *segrhs = nullptr,
+         *xp = nullptr;
+  // refinement / driver workspace
+  double *ex = nullptr, *ey = nullptr, *ez = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;
+  double *ones = nullptr, *zerosn = nullptr;
+  double *rp = nullptr, *rd = nullptr, *rzv = nullptr, *dxa = nullptr, *dya = nullptr,
+         *dza = nullptr, *dx = nullptr, *dy = nullptr, *dz = nullptr;
+  double *red_part = nullptr, *scal = nullptr;
+  double* h_scal = nullptr;   // pinned host mirror of scal
+  StageTimer timer;
+};
+
+namespace {
+
+constexpr int NSCAL = 32;
+
+ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
+  DevInfo h{};
+  HIPCHK(hipMemcpyAsync(&h, p->info, sizeof h, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  p->pivots_seen = h.pivots;
+  if (nonfinite) *nonfinite = h.nonfinite != 0;
+  return AHLP_OK;
+}
+
+// ------------------------------------------------------------- factor
+template <typename T>
+ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, const T* A) {
+  p->timer.begin(AHLP_ST_SYRK);
+  launch_syrk<T>(st, p->blk, p->syrk_items, p->nsyrk, A, p->Dp, LB, p->delta);
+  p->timer.end();
+  p->timer.begin(AHLP_ST_PREP);
+  launch_link<T>(st, p->blk, p->link_items, p->nlink, p->n0, p->A, p->C, p->lptr, p->lcol,
+                 p->lval, p->Dp, LB, p->PQ);
+  p->timer.end();
+  p->timer.begin(AHLP_ST_FACTOR);
+  launch_block_factor<T>(st, p->blk, p->N, p->max_rt, LB, LINV, p->info);
+  p->timer.end();
+  p->timer.begin(AHLP_ST_SCHUR);
+  launch_schur_contrib<T>(st, p->blk, p->N, LB, p->PQ);
+  p->timer.end();
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
+ChainArgs chain_args(ahlp_problem_t p) {
+  ChainArgs c{};
+  c.P = p->P; c.G = p->G; c.n0 = p->n0;
+  c.l = p->d_l; c.tdoff = p->d_tdoff; c.tooff = p->d_tooff; c.eoff = p->d_eoff;
+  c.zoff = p->d_zoff; c.suboff = p->d_suboff; c.seg = p->d_seg;
+  c.Td = p->Td; c.To = p->To; c.E = p->E; c.S00 = p->S00; c.thrT = p->thrT;
+  c.CL = p->CL; c.CLi = p->CLi; c.CYn = p->CYn; c.CZ = p->CZ; c.CG = p->CG; c.CSub = p->CSub;
+  c.Lb = p->Lb; c.Lbi = p->Lbi; c.S00w = p->S00w; c.segout = p->segout;
+  c.lmax = std::max(p->lmax, 1);
+  c.info = p->info;
+  return c;
+}
+
+ahlp_status_t ensure_fp32(ahlp_problem_t p, hipStream_t st) {
+  if (!p->A32) {
+    CHK(p->mem.alloc(&p->A32, p->a_total));
+    launch_convert_f32(st, p->a_total, p->A, p->A32);
+  }
+  if (!p->LB32) CHK(p->mem.alloc(&p->LB32, p->lb_total));
+  if (!p->LINV32) CHK(p->mem.alloc(&p->LINV32, p->linv_total));
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
+ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int prec, double rho,
+                        double delta, hipStream_t st) {
+  p->rho = rho;
+  p->delta = delta;
+  p->fprec = prec;
+  HIPCHK(hipMemsetAsync(p->info, 0, sizeof(DevInfo), st));
+  p->timer.begin(AHLP_ST_PREP);
+  launch_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, rho, p->Dp, p->xs, p->zs,
+              p->info);
+  p->timer.end();
+  if (prec == AHLP_FP32_REFINE) {
+    CHK(ensure_fp32(p, st));
+    CHK(factor_blocks<float>(p, st, p->LB32, p->LINV32, p->A32));
+  } else {
+    CHK(factor_blocks<double>(p, st, p->LB, p->LINV, p->A));
+  }
+  p->timer.begin(AHLP_ST_SCHUR);
+  launch_assemble(st, p->blk, p->N, p->n0, p->d_l, p->d_tdoff, p->d_tooff, p->d_eoff, p->PQ,
+                  p->F0, p->d_loff, delta, p->Dp + p->d0off, p->Td, p->To, p->E, p->S00,
+                  p->thrT);
+  p->timer.end();
+  p->timer.begin(AHLP_ST_TFACTOR);
+  launch_chain_factor(st, chain_args(p));
+  p->timer.end();
+  HIPCHK(hipGetLastError());
+  p->factored = true;
+  return AHLP_OK;
+}
+
+// ------------------------------------------------------------- solve
+// One pass of Alg. 3 (no refinement).  Also leaves g = A' dy in p->g.
+template <typename T>
+void solve_blocks_fwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV) {
+  launch_block_fwd<T>(st, p->blk, p->N, p->max_rt, LB, LINV, p->tv, p->qn);
+}
+template <typename T>
+void solve_blocks_bwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV, double* dy) {
+  launch_block_bwd<T>(st, p->blk, p->N, p->n0, p->nl, p->max_rt, LB, LINV, p->tv, p->u, dy,
+                      p->dyp);
+}
+
+ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
+                         double* dx, double* dy, double* dz, hipStream_t st) {
+  const bool f32 = p->fprec == AHLP_FP32_REFINE;
+  p->timer.begin(AHLP_ST_SOLVE);
+  launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->xs, p->Dp, p->rhx, p->vx);
+  // t_i = ry_i + A_i D_i rhx_i (padded), s_L = ry_L + F D rhx
+  launch_rows(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->vx, p->d0off, ry, 1.0, 0, 1, p->tv);
+  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->vx,
+                  nullptr, nullptr, ry + p->mblk, 1.0, p->s);
+  if (f32) solve_blocks_fwd<float>(p, st, p->LB32, p->LINV32);
+  else solve_blocks_fwd<double>(p, st, p->LB, p->LINV);
+  launch_schur_rhs(st, p->blk, p->N, p->n0, p->d_l, p->d_loff, p->nl, p->qn, p->rhx + p->x0off,
+                   p->s);
+  ChainSolveArgs a{};
+  a.c = chain_args(p);
+  a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.w = p->w; a.u = p->u; a.segrhs = p->segrhs;
+  launch_chain_solve(st, a);
+  if (f32) solve_blocks_bwd<float>(p, st, p->LB32, p->LINV32, dy);
+  else solve_blocks_bwd<double>(p, st, p->LB, p->LINV, dy);
+  launch_copy(st, p->nl, p->u, dy + p->mblk);
+  // dx_i = D_i (A_i' dy_i + F_i' dy_L - rhx_i);  g = A' dy
+  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, p->u, p->cptr, p->crow, p->cval, 2,
+              p->rhx, nullptr, p->Dp, p->g, dx);
+  launch_x0(st, p->blk, p->N, p->n0, p->nl, p->C, p->dyp, p->part, p->F0, p->u, 0, nullptr,
+            nullptr, p->x0off, p->g, nullptr);
+  launch_copy(st, p->n0, p->u + p->nl, dx + p->x0off);
+  launch_dz(st, p->n_tot, rz, p->zs, p->xs, dx, dz);
+  p->timer.end();
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
+// g = A' y (canonical), using the padded copy of the block rows.
+void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
+              const double* zvec, double* out, hipStream_t st) {
+  launch_pad_y(st, p->blk, p->N, y, p->dyp);
+  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, y + p->mblk, p->cptr, p->crow,
+              p->cval, mode, cvec, zvec, p->Dp, mode == 0 ? out : nullptr,
+              mode == 0 ? nullptr : out);
+  launch_x0(st, p->blk, p->N, p->n0, p->nl, p->C, p->dyp, p->part, p->F0, y + p->mblk, mode, cvec,
+            zvec, p->x0off, mode == 0 ? out : nullptr, mode == 0 ? nullptr : out);
+}
+
+// out = base + alpha * A x (canonical)
+void apply_A(ahlp_problem_t p, const double* x, const double* base, double alpha, double* out,
+             hipStream_t st) {
+  launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->xp, nullptr);
+  launch_rows(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->xp, p->d0off, base, alpha, 1, 0, out);
+  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
+                  p->xp + p->d0off, p->F0, base ? base + p->mblk : nullptr, alpha, out + p->mblk);
+}
+
+ahlp_status_t read_scal(ahlp_problem_t p, int count, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(p->h_scal, p->scal, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  p->timer.collect();
+  return AHLP_OK;
+}
+
+void red(ahlp_problem_t p, int op, long long n, const double* a, const double* b, int slot,
+         hipStream_t st, const double* c = nullptr, const double* d = nullptr, double s1 = 0,
+         double s2 = 0) {
+  launch_reduce(st, op, n, a, b, c, d, s1, s2, p->red_part, p->scal + slot);
+}
+
+// Refined solve.  d = (dx, dy, dz) receives the result.  knorm: |K|_inf.
+ahlp_status_t solve_refined(ahlp_problem_t p, const double* rx, const double* ry,
+                            const double* rz, double* dx, double* dy, double* dz, int max_refine,
+                            double refine_tol, double knorm, double* bkerr, int* steps_out,
+                            hipStream_t st) {
+  CHK(solve_once(p, rx, ry, rz, dx, dy, dz, st));
+  int steps = 0;
+  if (max_refine <= 0) {
+    if (bkerr) *bkerr = -1.0;
+    if (steps_out) *steps_out = 0;
+    return AHLP_OK;
+  }
+  p->timer.begin(AHLP_ST_RESID);
+  red(p, RED_MAXABS, p->n_tot, rx, nullptr, 0, st);
+  red(p, RED_MAXABS, p->m_tot, ry, nullptr, 1, st);
+  red(p, RED_MAXABS, p->n_tot, rz, nullptr, 2, st);
+  p->timer.end();
+  double be = 0.0;
+  while (true) {
+    p->timer.begin(AHLP_ST_RESID);
+    // e = r - K d:  ex = rx - A'dy - dz,  ey = ry - A dx,  ez = rz - Z dx - X dz
+    launch_res_x(st, p->n_tot, rx, rz, p->g, dx, dz, p->xs, p->zs, p->ex, p->ez);
+    apply_A(p, dx, ry, -1.0, p->ey, st);
+    red(p, RED_MAXABS, p->n_tot, p->ex, nullptr, 3, st);
+    red(p, RED_MAXABS, p->m_tot, p->ey, nullptr, 4, st);
+    red(p, RED_MAXABS, p->n_tot, p->ez, nullptr, 5, st);
+    red(p, RED_MAXABS, p->n_tot, dx, nullptr, 6, st);
+    red(p, RED_MAXABS, p->m_tot, dy, nullptr, 7, st);
+    red(p, RED_MAXABS, p->n_tot, dz, nullptr, 8, st);
+    p->timer.end();
+    CHK(read_scal(p, 9, st));
+    const double* h = p->h_scal;
+    const double rn = std::max(h[0], std::max(h[1], h[2]));
+    const double en = std::max(h[3], std::max(h[4], h[5]));
+    const double dn = std::max(h[6], std::max(h[7], h[8]));
+    const double den = knorm * dn + rn;
+    be = den > 0 ? en / den : 0.0;
+    if (!(be > refine_tol) || steps >= max_refine) break;
+    CHK(solve_once(p, p->ex, p->ey, p->ez, p->cx, p->cy, p->cz, st));
+    launch_axpy(st, p->n_tot, 1.0, p->cx, dx);
+    launch_axpy(st, p->m_tot, 1.0, p->cy, dy);
+    launch_axpy(st, p->n_tot, 1.0, p->cz, dz);
+    // g = A' dy for the corrected direction
+    p->timer.begin(AHLP_ST_RESID);
+    apply_At(p, dy, 0, nullptr, nullptr, p->g, st);
+    p->timer.end();
+    ++steps;
+  }
+  if (bkerr) *bkerr = be;
+  if (steps_out) *steps_out = steps;
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
+ahlp_status_t kkt_norm(ahlp_problem_t p, hipStream_t st, double* out) {
+  red(p, RED_MAXSUM, p->n_tot, p->xs, p->zs, 9, st);
+  HIPCHK(hipMemcpyAsync(p->h_scal + 9, p->scal + 9, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *out = std::max(p->colabs1_max, std::max(p->rowabs_max, p->h_scal[9]));
+  return AHLP_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+const char* ahlp_last_error(void) { return g_err.c_str(); }
+
+void ahlp_ipm_default_opts(ahlp_ipm_opts_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->tol = 1e-8;
+  o->max_iter = 100;
+  o->eta = 0.99;
+  o->rho = 1e-8;
+  o->delta = 1e-6;
+  o->max_refine = 5;
+  o->refine_tol = 1e-10;
+  o->precision = AHLP_FP64;
+  o->mu_switch = 1e-6;
+  o->start = 0;
+  o->verbose = 0;
+  o->timing = 0;
+}
+
+ahlp_status_t ahlp_problem_destroy(ahlp_problem_t p) {
+  if (!p) return AHLP_OK;
+  if (p->h_scal) (void)hipHostFree(p->h_scal);
+  delete p;
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
+                                  ahlp_problem_t* out) {
+  g_err.clear();
+  if (!d || !out) return fail(AHLP_EINVAL, "null argument");
+  *out = nullptr;
+  const int N = d->N, n0 = d->n0;
+  if (N < 1) return fail(AHLP_EINVAL, "N must be >= 1 (got %d)", N);
+  if (n0 < 0 || n0 > N0MAX) return fail(AHLP_EINVAL, "n0 must be in [0, %d] (got %d)", N0MAX, n0);
+  if (!d->m || !d->n || !d->A || !d->b || !d->c) return fail(AHLP_EINVAL, "missing m, n, A, b or c");
+  if (N > 1 && (!d->l || !d->FR || !d->FL)) return fail(AHLP_EINVAL, "missing l, FR or FL");
+  if (n0 > 0 && !d->C) return fail(AHLP_EINVAL, "n0 > 0 needs C");
+  auto up = std::make_unique<ahlp_problem_s>();
+  ahlp_problem_t p = up.get();
+  HIPCHK(hipGetDevice(&p->device));
+  p->N = N; p->n0 = n0; p->n0p = (int)r16(n0); p->P = N - 1;
+  p->m.assign(d->m, d->m + N);
+  p->n.assign(d->n, d->n + N);
+  if (N > 1) p->l.assign(d->l, d->l + N - 1);
+  for (int i = 0; i < N; ++i)
+    if (p->m[i] < 1 || p->n[i] < p->m[i])
+      return fail(AHLP_EINVAL, "block %d: need 1 <= m <= n (m=%d n=%d)", i, p->m[i], p->n[i]);
+  for (int j = 0; j < N - 1; ++j)
+    if (p->l[j] < 0 || p->l[j] > LMAX || p->l[j] > std::min(p->n[j], p->n[j + 1]))
+      return fail(AHLP_EINVAL, "pair %d: need 0 <= l <= min(n_j, n_j+1, %d) (l=%d)", j, LMAX, p->l[j]);
+  p->lmax = 0;
+  for (int v : p->l) p->lmax = std::max(p->lmax, v);
+  int dev_lds = 0;
+  HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  const size_t chain_sh = chain_factor_smem(std::max(p->lmax, 1), n0);
+  if (chain_sh > (size_t)dev_lds)
+    return fail(AHLP_EINVAL, "link pairs (max %d) with %d linking variables exceed the %d bytes of LDS",
+                p->lmax, n0, dev_lds);
+
+  // ---- geometry
+  long long xo = 0, yo = 0, dpo = 0, ao = 0, co = 0, lbo = 0, lio = 0, pqo = 0, vo = 0, qo = 0;
+  p->loff.assign(std::max(N, 1), 0);
+  for (int j = 0; j < N - 1; ++j) p->loff[j + 1] = p->loff[j] + p->l[j];
+  p->nl = N > 1 ? p->loff[N - 1] : 0;
+  const int kt0 = (n0 + 15) / 16;
+  p->hb.resize(N);
+  int csr_off = 0, csc_off = 0;
+  for (int i = 0; i < N; ++i) {
+    BlockInfo& b = p->hb[i];
+    b.m = p->m[i]; b.n = p->n[i];
+    b.mt = (b.m + 15) / 16; b.nt = (b.n + 15) / 16;
+    b.lL = i >= 1 ? p->l[i - 1] : 0;
+    b.lR = i <= N - 2 ? p->l[i] : 0;
+    b.ktL = (b.lL + 15) / 16; b.ktR = (b.lR + 15) / 16; b.kt0 = kt0;
+    b.kt = b.ktL + b.ktR + b.kt0;
+    b.rt = b.mt + b.kt;
+    b.pairL = i >= 1 ? i - 1 : -1;
+    b.pairR = i <= N - 2 ? i : -1;
+    b.csr_off = csr_off; csr_off += 16 * b.kt + 1;
+    b.csc_off = csc_off; csc_off += b.n + 1;
+    b.xoff = xo; xo += b.n;
+    b.yoff = yo; yo += b.m;
+    b.dpoff = dpo; dpo += 16LL * b.nt;
+    b.aoff = ao; ao += 256LL * b.mt * b.nt;
+    b.coff = co; co += 256LL * b.mt * b.kt0;
+    b.lboff = lbo; lbo += 256LL * lb_tiles(b.mt, b.rt);
+    b.linvoff = lio; lio += 256LL * b.mt;
+    b.pqoff = pqo; pqo += 256LL * b.kt * b.kt;
+    b.loffL = i >= 1 ? p->loff[i - 1] : -1;
+    b.loffR = i <= N - 2 ? p->loff[i] : -1;
+    b.voff = vo; vo += 16LL * b.mt;
+    b.qoff = qo; qo += 16LL * b.kt;
+    p->max_rt = std::max(p->max_rt, b.rt);
+  }
+  p->x0off = xo; p->n_tot = xo + n0;
+  p->mblk = yo; p->m_tot = yo + p->nl;
+  p->d0off = dpo; p->dp_total = dpo + p->n0p;
+  p->a_total = ao; p->c_total = co; p->lb_total = lbo; p->linv_total = lio; p->pq_total = pqo;
+  p->vp_total = vo; p->q_total = qo;
+
+  // ---- host packing: A and C into tile-major, link rows into CSR/CSC
+  std::vector<double> hA((size_t)ao, 0.0), hC((size_t)std::max(co, 1LL), 0.0);
+  std::vector<double> rowabs((size_t)p->m_tot, 0.0), colabs((size_t)p->n_tot, 0.0);
+  {
+    long long aoffs = 0, coffs = 0;
+    for (int i = 0; i < N; ++i) {
+      const BlockInfo& b = p->hb[i];
+      const double* Ai = d->A + aoffs;
+      for (int r = 0; r < b.m; ++r)
+        for (int c = 0; c < b.n; ++c) {
+          const double v = Ai[(long long)r * b.n + c];
+          if (!std::isfinite(v)) return fail(AHLP_ENUMERIC, "non-finite A in block %d", i);
+          hA[b.aoff + ((long long)(r / 16) * b.nt + c / 16) * 256 + (c % 16) * 16 + r % 16] = v;
+          rowabs[b.yoff + r] += std::fabs(v);
+          colabs[b.xoff + c] += std::fabs(v);
+        }
+      aoffs += (long long)b.m * b.n;
+      if (n0 > 0) {
+        const double* Ci = d->C + coffs;
+        for (int r = 0; r < b.m; ++r)
+          for (int c = 0; c < n0; ++c) {
+            const double v = Ci[(long long)r * n0 + c];
+            if (!std::isfinite(v)) return fail(AHLP_ENUMERIC, "non-finite C in block %d", i);
+            hC[b.coff + ((long long)(r / 16) * kt0 + c / 16) * 256 + (c % 16) * 16 + r % 16] = v;
+            rowabs[b.yoff + r] += std::fabs(v);
+            colabs[p->x0off + c] += std::fabs(v);
+          }
+        coffs += (long long)b.m * n0;
+      }
+    }
+  }
+  // CSR of each block's link sections (rows q in [0, 16 kt), padded rows empty)
+  std::vector<int> hptr((size_t)csr_off, 0), hcol;
+  std::vector<double> hval;
+  std::vector<std::vector<std::pair<long long, double>>> colents((size_t)p->x0off);
+  {
+    long long froff = 0, floff = 0;
+    std::vector<long long> fr_start(N > 1 ? N - 1 : 1, 0), fl_start(N > 1 ? N - 1 : 1, 0);
+    for (int j = 0; j < N - 1; ++j) {
+      fr_start[j] = froff; froff += (long long)p->l[j] * p->n[j];
+      fl_start[j] = floff; floff += (long long)p->l[j] * p->n[j + 1];
+    }
+    for (int i = 0; i < N; ++i) {
+      const BlockInfo& b = p->hb[i];
+      for (int q = 0; q < 16 * b.kt; ++q) {
+        hptr[b.csr_off + q] = (int)hcol.size();
+        int qi;
+        bool real;
+        const int sec = link_section(b, q, &qi, n0, &real);
+        if (!real || sec == 2) continue;
+        const int pair = sec == 0 ? i - 1 : i;
+        const double* row = sec == 0 ? d->FL + fl_start[pair] + (long long)qi * b.n
+                                     : d->FR + fr_start[pair] + (long long)qi * b.n;
+        const long long grow = p->loff[pair] + qi;   // link row inside y_L
+        for (int c = 0; c < b.n; ++c) {
+          const double v = row[c];
+          if (v == 0.0) continue;
+          if (!std::isfinite(v)) return fail(AHLP_ENUMERIC, "non-finite link coefficient");
+          hcol.push_back(c);
+          hval.push_back(v);
+          colents[b.xoff + c].push_back({grow, v});
+          rowabs[p->mblk + grow] += std::fabs(v);
+          colabs[b.xoff + c] += std::fabs(v);
+        }
+      }
+      hptr[b.csr_off + 16 * b.kt] = (int)hcol.size();
+    }
+  }
+  std::vector<int> hcptr((size_t)csc_off, 0), hcrow;
+  std::vector<double> hcval;
+  for (int i = 0; i < N; ++i) {
+    const BlockInfo& b = p->hb[i];
+    for (int c = 0; c < b.n; ++c) {
+      hcptr[b.csc_off + c] = (int)hcrow.size();
+      for (auto& e : colents[b.xoff + c]) {
+        hcrow.push_back((int)e.first);
+        hcval.push_back(e.second);
+      }
+    }
+    hcptr[b.csc_off + b.n] = (int)hcrow.size();
+  }
+  if (d->F0 && n0 > 0) {
+    for (long long r = 0; r < p->nl; ++r)
+      for (int c = 0; c < n0; ++c) {
+        const double v = d->F0[r * n0 + c];
+        if (!std::isfinite(v)) return fail(AHLP_ENUMERIC, "non-finite F0");
+        rowabs[p->mblk + r] += std::fabs(v);
+        colabs[p->x0off + c] += std::fabs(v);
+      }
+  }
+  for (long long i = 0; i < p->m_tot; ++i) {
+    if (!std::isfinite(d->b[i])) return fail(AHLP_ENUMERIC, "non-finite b");
+    p->b_inf = std::max(p->b_inf, std::fabs(d->b[i]));
+  }
+  for (long long i = 0; i < p->n_tot; ++i) {
+    if (!std::isfinite(d->c[i])) return fail(AHLP_ENUMERIC, "non-finite c");
+    p->c_inf = std::max(p->c_inf, std::fabs(d->c[i]));
+  }
+  p->rowabs_max = 0.0;
+  for (double v : rowabs) p->rowabs_max = std::max(p->rowabs_max, v);
+  p->colabs1_max = 1.0;
+  for (double v : colabs) p->colabs1_max = std::max(p->colabs1_max, v + 1.0);
+
+  // ---- work lists
+  std::vector<int4> hsyrk;
+  std::vector<int2> hlink, hrow, hcolt;
+  for (int i = 0; i < N; ++i) {
+    const BlockInfo& b = p->hb[i];
+    const int MT = (b.mt + 3) / 4;
+    for (int r = 0; r < MT; ++r)
+      for (int c = 0; c <= r; ++c) hsyrk.push_back(int4{i, r, c, 0});
+    for (int r = 0; r < b.kt; ++r) hlink.push_back(int2{i, r});
+    for (int r = 0; r < b.mt; ++r) hrow.push_back(int2{i, r});
+    for (int c = 0; c < b.nt; ++c) hcolt.push_back(int2{i, c});
+  }
+  p->nsyrk = (int)hsyrk.size(); p->nlink = (int)hlink.size();
+  p->nrt = (int)hrow.size(); p->nct = (int)hcolt.size();
+
+  // ---- Schur complement geometry and segments
+  const int P = p->P;
+  p->tdoff.assign(std::max(P, 1), 0);
+  p->tooff.assign(std::max(P, 1), 0);
+  p->eoff.assign(std::max(P, 1), 0);
+  p->zoff.assign(std::max(P, 1), 0);
+  long long td = 0, to = 0, zo = 0;
+  for (int j = 0; j < P; ++j) {
+    p->tdoff[j] = td; td += (long long)p->l[j] * p->l[j];
+    p->tooff[j] = to; if (j + 1 < P) to += (long long)p->l[j + 1] * p->l[j];
+    p->eoff[j] = p->loff[j] * n0;
+  }
+  if (P > 0) {
+    int Ls = P <= 8 ? P : std::max(2, (int)std::lround(std::sqrt((double)P)));
+    int start = 0;
+    while (start < P) {
+      const int a = start;
+      int bnd = std::min(start + Ls, P);
+      if (bnd + 1 < P) {
+        p->seg.push_back(int2{a, bnd});
+        start = bnd + 1;
+      } else {
+        p->seg.push_back(int2{a, P});
+        start = P;
+      }
+    }
+  }
+  p->G = (int)p->seg.size();
+  for (int g = 0; g < p->G; ++g) {
+    const int a = p->seg[g].x, b = p->seg[g].y;
+    const int lsL = g > 0 ? p->l[a - 1] : 0;
+    for (int k = a; k < b; ++k) { p->zoff[k] = zo; zo += (long long)lsL * p->l[k]; }
+  }
+  p->suboff.assign(std::max(p->G, 1), 0);
+  long long so = 0;
+  for (int s = 1; s < p->G - 1; ++s) {
+    p->suboff[s] = so;
+    so += (long long)p->l[p->seg[s].y] * p->l[p->seg[s - 1].y];
+  }
+
+  // ---- device allocations and uploads
+  DevMem& M = p->mem;
+  CHK(M.alloc(&p->blk, N));
+  CHK(M.alloc(&p->A, ao));
+  CHK(M.alloc(&p->C, std::max(co, 1LL)));
+  CHK(M.alloc(&p->lptr, csr_off));
+  CHK(M.alloc(&p->lcol, std::max<long long>(hcol.size(), 1)));
+  CHK(M.alloc(&p->lval, std::max<long long>(hval.size(), 1)));
+  CHK(M.alloc(&p->cptr, csc_off));
+  CHK(M.alloc(&p->crow, std::max<long long>(hcrow.size(), 1)));
+  CHK(M.alloc(&p->cval, std::max<long long>(hcval.size(), 1)));
+  if (d->F0 && n0 > 0 && p->nl > 0) CHK(M.alloc(&p->F0, p->nl * n0));
+  CHK(M.alloc(&p->b, p->m_tot));
+  CHK(M.alloc(&p->c, p->n_tot));
+  CHK(M.alloc(&p->syrk_items, p->nsyrk));
+  CHK(M.alloc(&p->link_items, std::max(p->nlink, 1)));
+  CHK(M.alloc(&p->rowtiles, p->nrt));
+  CHK(M.alloc(&p->coltiles, p->nct));
+  CHK(M.alloc(&p->d_l, std::max(P, 1)));
+  CHK(M.alloc(&p->d_loff, std::max(N, 1)));
+  CHK(M.alloc(&p->d_tdoff, std::max(P, 1)));
+  CHK(M.alloc(&p->d_tooff, std::max(P, 1)));
+  CHK(M.alloc(&p->d_eoff, std::max(P, 1)));
+  CHK(M.alloc(&p->d_zoff, std::max(P, 1)));
+  CHK(M.alloc(&p->d_suboff, std::max(p->G, 1)));
+  CHK(M.alloc(&p->d_seg, std::max(p->G, 1)));
+
+  CHK(M.alloc(&p->Dp, p->dp_total));
+  CHK(M.alloc(&p->xs, p->n_tot));
+  CHK(M.alloc(&p->zs, p->n_tot));
+  CHK(M.alloc(&p->LB, p->lb_total));
+  CHK(M.alloc(&p->LINV, p->linv_total));
+  CHK(M.alloc(&p->PQ, p->pq_total));
+  CHK(M.alloc(&p->Td, std::max(td, 1LL)));
+  CHK(M.alloc(&p->To, std::max(to, 1LL)));
+  CHK(M.alloc(&p->E, std::max(p->nl * n0, 1LL)));
+  CHK(M.alloc(&p->S00, std::max(n0 * n0, 1)));
+  CHK(M.alloc(&p->thrT, std::max(P, 1)));
+  CHK(M.alloc(&p->CL, std::max(td, 1LL)));
+  CHK(M.alloc(&p->CLi, std::max(td, 1LL)));
+  CHK(M.alloc(&p->CYn, std::max(to, 1LL)));
+  CHK(M.alloc(&p->CZ, std::max(zo, 1LL)));
+  CHK(M.alloc(&p->CG, std::max(p->nl * n0, 1LL)));
+  CHK(M.alloc(&p->CSub, std::max(so, 1LL)));
+  CHK(M.alloc(&p->Lb, std::max(n0 * n0, 1)));
+  CHK(M.alloc(&p->Lbi, std::max(n0 * n0, 1)));
+  CHK(M.alloc(&p->S00w, std::max(n0 * n0, 1)));
+  CHK(M.alloc(&p->segout, (long long)std::max(p->G, 1) * SEG_STRIDE));
+  CHK(M.alloc(&p->info, 1));
+
+  CHK(M.alloc(&p->rhx, p->n_tot));
+  CHK(M.alloc(&p->vx, p->dp_total));
+  CHK(M.alloc(&p->xp, p->dp_total));
+  CHK(M.alloc(&p->tv, p->vp_total));
+  CHK(M.alloc(&p->dyp, p->vp_total));
+  CHK(M.alloc(&p->qn, p->q_total));
+  CHK(M.alloc(&p->s, p->nl + n0));
+  CHK(M.alloc(&p->w, p->nl + n0));
+  CHK(M.alloc(&p->u, p->nl + n0));
+  CHK(M.alloc(&p->g, p->n_tot));
+  CHK(M.alloc(&p->part, (long long)N * std::max(n0, 1)));
+  CHK(M.alloc(&p->segrhs, (long long)std::max(p->G, 1) * SEGRHS_STRIDE));
+  for (double** v : {&p->ex, &p->ez, &p->cx, &p->cz, &p->ones, &p->zerosn, &p->rd, &p->rzv,
+                     &p->dxa, &p->dza, &p->dx, &p->dz})
+    CHK(M.alloc(v, p->n_tot));
+  for (double** v : {&p->ey, &p->cy, &p->rp, &p->dya, &p->dy}) CHK(M.alloc(v, p->m_tot));
+  CHK(M.alloc(&p->red_part, RED_PARTIALS));
+  CHK(M.alloc(&p->scal, NSCAL));
+  HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
+
+  HIPCHK(hipMemcpyAsync(p->blk, p->hb.data(), sizeof(BlockInfo) * N, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->A, hA.data(), sizeof(double) * ao, hipMemcpyHostToDevice, st));
+  if (co > 0) HIPCHK(hipMemcpyAsync(p->C, hC.data(), sizeof(double) * co, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->lptr, hptr.data(), sizeof(int) * csr_off, hipMemcpyHostToDevice, st));
+  if (!hcol.empty()) {
+    HIPCHK(hipMemcpyAsync(p->lcol, hcol.data(), sizeof(int) * hcol.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->lval, hval.data(), sizeof(double) * hval.size(), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(p->cptr, hcptr.data(), sizeof(int) * csc_off, hipMemcpyHostToDevice, st));
+  if (!hcrow.empty()) {
+    HIPCHK(hipMemcpyAsync(p->crow, hcrow.data(), sizeof(int) * hcrow.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->cval, hcval.data(), sizeof(double) * hcval.size(), hipMemcpyHostToDevice, st));
+  }
+  if (p->F0) HIPCHK(hipMemcpyAsync(p->F0, d->F0, sizeof(double) * p->nl * n0, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->b, d->b, sizeof(double) * p->m_tot, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->c, d->c, sizeof(double) * p->n_tot, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->syrk_items, hsyrk.data(), sizeof(int4) * hsyrk.size(), hipMemcpyHostToDevice, st));
+  if (!hlink.empty())
+    HIPCHK(hipMemcpyAsync(p->link_items, hlink.data(), sizeof(int2) * hlink.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->rowtiles, hrow.data(), sizeof(int2) * hrow.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->coltiles, hcolt.data(), sizeof(int2) * hcolt.size(), hipMemcpyHostToDevice, st));
+  if (P > 0) {
+    HIPCHK(hipMemcpyAsync(p->d_l, p->l.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_tdoff, p->tdoff.data(), sizeof(long long) * P, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_tooff, p->tooff.data(), sizeof(long long) * P, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_eoff, p->eoff.data(), sizeof(long long) * P, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_zoff, p->zoff.data(), sizeof(long long) * P, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(p->d_loff, p->loff.data(), sizeof(long long) * std::max(N, 1), hipMemcpyHostToDevice, st));
+  if (p->G > 0) {
+    HIPCHK(hipMemcpyAsync(p->d_seg, p->seg.data(), sizeof(int2) * p->G, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_suboff, p->suboff.data(), sizeof(long long) * p->G, hipMemcpyHostToDevice, st));
+  }
+  launch_fill(st, p->n_tot, 1.0, p->ones);
+  launch_fill(st, p->n_tot, 0.0, p->zerosn);
+  HIPCHK(hipMemsetAsync(p->info, 0, sizeof(DevInfo), st));
+  if (chain_sh > 64 * 1024) set_chain_smem_limits(chain_sh);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  p->timer.st = st;
+  *out = up.release();
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_kkt_factor(ahlp_problem_t p, const double* x, const double* z,
+                              const ahlp_factor_opts_t* o, hipStream_t st) {
+  g_err.clear();
+  if (!p || !x || !z) return fail(AHLP_EINVAL, "null argument");
+  const int prec = o ? o->precision : AHLP_FP64;
+  const double rho = o ? o->rho : 0.0, delta = o ? o->delta : 0.0;
+  if (!(rho >= 0.0) || !(delta >= 0.0)) return fail(AHLP_EINVAL, "rho and delta must be >= 0");
+  if (prec != AHLP_FP64 && prec != AHLP_FP32_REFINE) return fail(AHLP_EINVAL, "unknown precision");
+  p->timer.st = st;
+  return do_factor(p, x, z, prec, rho, delta, st);
+}
+
+ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* ry,
+                             const double* rz, double* dx, double* dy, double* dz,
+                             int32_t max_refine, double refine_tol, double* bkerr,
+                             hipStream_t st) {
+  g_err.clear();
+  if (!p || !rx || !ry || !rz || !dx || !dy || !dz) return fail(AHLP_EINVAL, "null argument");
+  if (!p->factored) return fail(AHLP_ESTATE, "solve before factor");
+  p->timer.st = st;
+  if (max_refine > 0) {
+    bool bad = false;
+    CHK(check_info(p, st, &bad));
+    if (bad) return fail(AHLP_ENUMERIC, "the factorization saw x <= 0, z <= 0 or non-finite values");
+    double kn = 0;
+    CHK(kkt_norm(p, st, &kn));
+    return solve_refined(p, rx, ry, rz, dx, dy, dz, max_refine, refine_tol, kn, bkerr, nullptr, st);
+  }
+  return solve_once(p, rx, ry, rz, dx, dy, dz, st);
+}
+
+ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double* x, double* y,
+                             double* z, ahlp_ipm_result_t* res, hipStream_t st) {
+  g_err.clear();
+  if (!p || !o || !x || !y || !z) return fail(AHLP_EINVAL, "null argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  ahlp_ipm_result_t R;
+  std::memset(&R, 0, sizeof R);
+  p->timer.st = st;
+  p->timer.on = o->timing != 0;
+  p->timer.reset();
+  const long long n = p->n_tot, m = p->m_tot;
+  int total_piv = 0;
+  double max_bk = 0.0;
+  int refine_total = 0;
+  auto account = [&](double be, int steps) {
+    refine_total += steps;
+    if (be > max_bk) max_bk = be;
+  };
+  auto factor_checked = [&](const double* xx, const double* zz, int prec, double rho,
+                            double delta) -> ahlp_status_t {
+    CHK(do_factor(p, xx, zz, prec, rho, delta, st));
+    bool bad = false;
+    CHK(check_info(p, st, &bad));
+    p->timer.collect();
+    total_piv += p->pivots_seen;
+    if (bad) return fail(AHLP_ENUMERIC, "x or z left the positive orthant or became non-finite");
+    return AHLP_OK;
+  };
+
+  // ---- starting point
+  if (o->start == 0) {
+    CHK(factor_checked(p->ones, p->ones, AHLP_FP64, 0.0, 0.0));
+    double kn = 0;
+    CHK(kkt_norm(p, st, &kn));
+    double be;
+    int steps;
+    // x~ from rhs (0, b, 0), y~ from rhs (c, 0, 0)
+    CHK(solve_refined(p, p->zerosn, p->b, p->zerosn, p->dxa, p->dya, p->dza, o->max_refine,
+                      o->refine_tol, kn, &be, &steps, st));
+    account(be, steps);
+    HIPCHK(hipMemsetAsync(p->rp, 0, sizeof(double) * m, st));
+    CHK(solve_refined(p, p->c, p->rp, p->zerosn, p->dx, p->dy, p->dz, o->max_refine,
+                      o->refine_tol, kn, &be, &steps, st));
+    account(be, steps);
+    launch_copy(st, n, p->dxa, x);
+    launch_copy(st, m, p->dy, y);
+    apply_At(p, y, 1, p->c, p->zerosn, z, st);   // z~ = c - A'y~
+    red(p, RED_MIN, n, x, nullptr, 0, st);
+    red(p, RED_MIN, n, z, nullptr, 1, st);
+    CHK(read_scal(p, 2, st));
+    const double sx = std::max(-1.5 * p->h_scal[0], 0.0), sz = std::max(-1.5 * p->h_scal[1], 0.0);
+    launch_addscalar(st, n, sx, x);
+    launch_addscalar(st, n, sz, z);
+    red(p, RED_DOT, n, x, z, 0, st);
+    red(p, RED_DOT, n, x, p->ones, 1, st);
+    red(p, RED_DOT, n, z, p->ones, 2, st);
+    CHK(read_scal(p, 3, st));
+    const double xz = p->h_scal[0], sumx = p->h_scal[1], sumz = p->h_scal[2];
+    launch_addscalar(st, n, sumz > 0 ? 0.5 * xz / sumz : 0.0, x);
+    launch_addscalar(st, n, sumx > 0 ? 0.5 * xz / sumx : 0.0, z);
+    red(p, RED_MIN, n, x, nullptr, 0, st);
+    red(p, RED_MIN, n, z, nullptr, 1, st);
+    CHK(read_scal(p, 2, st));
+    if (p->h_scal[0] <= 0.0 || p->h_scal[1] <= 0.0) {
+      launch_addscalar(st, n, 1.0, x);
+      launch_addscalar(st, n, 1.0, z);
+    }
+  }
+
+  // ---- main loop
+  const double bn = 1.0 + p->b_inf, cn = 1.0 + p->c_inf;
+  bool fp32_live = o->precision == AHLP_FP32_REFINE;
+  int k = 0;
+  ahlp_status_t status = AHLP_WMAXITER;
+  double mu = 0, pobj = 0, dobj = 0, relgap = 0, pinf = 0, dinf = 0;
+  while (true) {
+    p->timer.begin(AHLP_ST_RESID);
+    apply_A(p, x, p->b, -1.0, p->rp, st);                 // r_p = b - A x
+    apply_At(p, y, 1, p->c, z, p->rd, st);                // r_d = c - A'y - z
+    red(p, RED_DOT, n, x, z, 0, st);
+    red(p, RED_DOT, n, p->c, x, 1, st);
+    red(p, RED_DOT, m, p->b, y, 2, st);
+    red(p, RED_MAXABS, m, p->rp, nullptr, 3, st);
+    red(p, RED_MAXABS, n, p->rd, nullptr, 4, st);
+    p->timer.end();
+    CHK(read_scal(p, 5, st));
+    mu = p->h_scal[0] / (double)n;
+    pobj = p->h_scal[1];
+    dobj = p->h_scal[2];
+    relgap = std::fabs(pobj - dobj) / std::max(1.0, std::fabs(pobj));
+    pinf = p->h_scal[3] / bn;
+    dinf = p->h_scal[4] / cn;
+    if (o->verbose)
+      fprintf(stderr, "ahlp it %3d mu %.3e gap %.3e pinf %.3e dinf %.3e%s\n", k, mu, relgap, pinf,
+              dinf, fp32_live ? " fp32" : "");
+    if (relgap <= o->tol && pinf <= o->tol && dinf <= o->tol) {
+      status = AHLP_OK;
+      break;
+    }
+    if (k >= o->max_iter) break;
+    if (fp32_live && mu < o->mu_switch) fp32_live = false;
+    const int prec = fp32_live ? AHLP_FP32_REFINE : AHLP_FP64;
+    if (fp32_live) R.fp32_iterations++;
+    CHK(factor_checked(x, z, prec, o->rho, o->delta));
+    double kn = 0;
+    CHK(kkt_norm(p, st, &kn));
+    double be;
+    int steps;
+    // predictor
+    launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);
+    CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine,
+                      o->refine_tol, kn, &be, &steps, st));
+    account(be, steps);
+    red(p, RED_RATIO, n, x, p->dxa, 0, st);
+    red(p, RED_RATIO, n, z, p->dza, 1, st);
+    CHK(read_scal(p, 2, st));
+    const double ap_aff = std::min(1.0, p->h_scal[0]), ad_aff = std::min(1.0, p->h_scal[1]);
+    red(p, RED_MUAFF, n, x, p->dxa, 0, st, z, p->dza, ap_aff, ad_aff);
+    CHK(read_scal(p, 1, st));
+    const double mu_aff = p->h_scal[0] / (double)n;
+    const double sigma = std::pow(mu_aff / mu, 3.0);
+    // corrector
+    launch_rz(st, n, 1, x, z, p->dxa, p->dza, sigma * mu, p->rzv);
+    CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine,
+                      o->refine_tol, kn, &be, &steps, st));
+    account(be, steps);
+    red(p, RED_RATIO, n, x, p->dx, 0, st);
+    red(p, RED_RATIO, n, z, p->dz, 1, st);
+    CHK(read_scal(p, 2, st));
+    const double ap = std::min(1.0, o->eta * p->h_scal[0]);
+    const double ad = std::min(1.0, o->eta * p->h_scal[1]);
+    launch_axpy(st, n, ap, p->dx, x);
+    launch_axpy(st, m, ad, p->dy, y);
+    launch_axpy(st, n, ad, p->dz, z);
+    ++k;
+    if (ap < 1e-12 && ad < 1e-12) {
+      status = AHLP_WSTALL;
+      break;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  p->timer.collect();
+  R.status = status;
+  R.iterations = k;
+  R.refine_steps = refine_total;
+  R.pivots_modified = total_piv;
+  R.primal_obj = pobj;
+  R.dual_obj = dobj;
+  R.rel_gap = relgap;
+  R.rel_pinf = pinf;
+  R.rel_dinf = dinf;
+  R.mu = mu;
+  R.max_bkerr = max_bk;
+  for (int i = 0; i < AHLP_ST_COUNT; ++i) {
+    R.t_stage_ms[i] = p->timer.ms[i];
+    R.n_stage[i] = p->timer.cnt[i];
+  }
+  p->timer.on = false;
+  R.t_total_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (res) *res = R;
+  return status;
+}
+
+// ---------------------------------------------------------------- inspection
+ahlp_status_t ahlp_problem_sizes(ahlp_problem_t p, int64_t* n_tot, int64_t* m_tot,
+                                 int64_t* n_link, int32_t* n0) {
+  if (!p) return fail(AHLP_EINVAL, "null handle");
+  if (n_tot) *n_tot = p->n_tot;
+  if (m_tot) *m_tot = p->m_tot;
+  if (n_link) *n_link = p->nl;
+  if (n0) *n0 = p->n0;
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_debug_pivots(ahlp_problem_t p, int32_t* count) {
+  if (!p || !count) return fail(AHLP_EINVAL, "null argument");
+  CHK(check_info(p, p->timer.st, nullptr));
+  *count = p->pivots_seen;
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_debug_block(ahlp_problem_t p, int32_t i, double* L, double* W) {
+  if (!p || i < 0 || i >= p->N) return fail(AHLP_EINVAL, "bad block index");
+  if (!p->factored) return fail(AHLP_ESTATE, "no factorization");
+  const BlockInfo& b = p->hb[i];
+  const long long ntile = lb_tiles(b.mt, b.rt) * 256;
+  std::vector<double> h((size_t)ntile);
+  HIPCHK(hipDeviceSynchronize());
+  if (p->fprec == AHLP_FP32_REFINE) {
+    std::vector<float> hf((size_t)ntile);
+    HIPCHK(hipMemcpy(hf.data(), p->LB32 + b.lboff, sizeof(float) * ntile, hipMemcpyDeviceToHost));
+    for (long long t = 0; t < ntile; ++t) h[t] = hf[t];
+  } else {
+    HIPCHK(hipMemcpy(h.data(), p->LB + b.lboff, sizeof(double) * ntile, hipMemcpyDeviceToHost));
+  }
+  auto at = [&](int r, int c) {  // element (r, c) of the bordered factor, r >= c
+    BlockInfo b0 = b;
+    b0.lboff = 0;
+    return h[lb_tile(b0, r / 16, c / 16) + (c % 16) * 16 + r % 16];
+  };
+  if (L) {
+    for (int r = 0; r < b.m; ++r)
+      for (int c = 0; c < b.m; ++c) L[(long long)r * b.m + c] = (c <= r) ? at(r, c) : 0.0;
+  }
+  if (W) {
+    const int k = b.lL + b.lR + p->n0;
+    for (int a = 0; a < b.m; ++a)
+      for (int col = 0; col < k; ++col) {
+        int q;
+        if (col < b.lL) q = col;
+        else if (col < b.lL + b.lR) q = 16 * b.ktL + (col - b.lL);
+        else q = 16 * (b.ktL + b.ktR) + (col - b.lL - b.lR);
+        W[(long long)a * k + col] = at(16 * b.mt + q, a);
+      }
+  }
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_debug_schur(ahlp_problem_t p, double* S) {
+  if (!p || !S) return fail(AHLP_EINVAL, "null argument");
+  if (!p->factored) return fail(AHLP_ESTATE, "no factorization");
+  const long long dim = p->nl + p->n0;
+  HIPCHK(hipDeviceSynchronize());
+  std::vector<double> Td, To, E, S00;
+  auto fetch = [&](std::vector<double>& v, const double* src, long long cnt) -> ahlp_status_t {
+    v.resize((size_t)std::max(cnt, 1LL));
+    if (cnt > 0) HIPCHK(hipMemcpy(v.data(), src, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+    return AHLP_OK;
+  };
+  const int P = p->P, n0 = p->n0;
+  long long tdn = P > 0 ? p->tdoff[P - 1] + (long long)p->l[P - 1] * p->l[P - 1] : 0;
+  long long ton = P > 1 ? p->tooff[P - 2] + (long long)p->l[P - 1] * p->l[P - 2] : 0;
+  CHK(fetch(Td, p->Td, tdn));
+  CHK(fetch(To, p->To, ton));
+  CHK(fetch(E, p->E, p->nl * n0));
+  CHK(fetch(S00, p->S00, (long long)n0 * n0));
+  std::fill(S, S + dim * dim, 0.0);
+  for (int j = 0; j < P; ++j) {
+    const int l = p->l[j];
+    const long long o = p->loff[j];
+    for (int a = 0; a < l; ++a)
+      for (int c = 0; c < l; ++c) S[(o + a) * dim + o + c] = Td[p->tdoff[j] + a + (long long)c * l];
+    if (j + 1 < P) {
+      const int l2 = p->l[j + 1];
+      const long long o2 = p->loff[j + 1];
+      for (int a = 0; a < l2; ++a)
+        for (int c = 0; c < l; ++c) {
+          const double v = To[p->tooff[j] + a + (long long)c * l2];
+          S[(o2 + a) * dim + o + c] = v;
+          S[(o + c) * dim + o2 + a] = v;
+        }
+    }
+    for (int a = 0; a < l; ++a)
+      for (int c = 0; c < n0; ++c) {
+        const double v = E[p->eoff[j] + a + (long long)c * l];
+        S[(o + a) * dim + p->nl + c] = v;
+        S[(p->nl + c) * dim + o + a] = v;
+      }
+  }
+  for (int a = 0; a < n0; ++a)
+    for (int c = 0; c < n0; ++c) S[(p->nl + a) * dim + p->nl + c] = S00[a + (long long)c * n0];
+  return AHLP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,513 @@
+// Factorization kernels: D-scaling (a1), block SYRK (a2), link columns (a1),
+// bordered block Cholesky = Cholesky of M_i and W_i = L_i^-1 B_i (a3, a4),
+// Schur contributions W_i' W_i and their deterministic assembly (a5).
+//
+// Per block i the "bordered" matrix
+//     [ M_i    B_i ]      M_i = A_i D_i A_i' (+ delta I),   B_i = [A_i D_i F_i' | C_i]
+//     [ B_i'   *   ]
+// is stored as lower tiles packed by tile columns (columns 0..mt-1 only): the
+// first mt tile rows hold M_i, the next kt tile rows hold B_i'.  A left-looking
+// Cholesky over the first mt columns turns them into L_i and W_i' = B_i' L_i^-T
+// in place; this is the partial factorization of the bordered matrix that
+// stops after the m_i pivots of the block (Sec. 3.2 discusses the same
+// construction with an incomplete LU of [K_i L_i'; L_i 0]).
+#include "common.h"
+#include "kernels.h"
+
+namespace ahlp {
+
+// ---------------------------------------------------------------- a1: D
+// One workgroup per block (and one for x_0).  Fills the padded D and keeps a
+// copy of x and z for the solve phase; flags non-positive or non-finite input.
+__global__ void k_prep(const BlockInfo* __restrict__ blk, int N, int n0, long long x0off,
+                       long long d0off, const double* __restrict__ x,
+                       const double* __restrict__ z, double rho, double* __restrict__ Dp,
+                       double* __restrict__ xs, double* __restrict__ zs, DevInfo* info) {
+  int i = blockIdx.x;
+  long long xoff, dpoff;
+  int n, np;
+  if (i < N) {
+    xoff = blk[i].xoff; dpoff = blk[i].dpoff; n = blk[i].n; np = TS * blk[i].nt;
+  } else {
+    xoff = x0off; dpoff = d0off; n = n0; np = (n0 + TS - 1) / TS * TS;
+  }
+  int bad = 0;
+  for (int c = threadIdx.x; c < np; c += blockDim.x) {
+    double d = 0.0;
+    if (c < n) {
+      double xv = x[xoff + c], zv = z[xoff + c];
+      xs[xoff + c] = xv;
+      zs[xoff + c] = zv;
+      if (!(xv > 0.0) || !(zv > 0.0) || !isfinite(xv) || !isfinite(zv)) bad = 1;
+      d = 1.0 / (zv / xv + rho);
+    }
+    Dp[dpoff + c] = d;
+  }
+  if (bad) atomicOr(&info->nonfinite, 1);
+}
+
+// ---------------------------------------------------------------- a2: SYRK
+// One 64x64 lower macro tile of one block per workgroup (4 waves, each 32x32 =
+// 2x2 MFMA tiles).  A-row panels are staged through LDS (double buffered); D
+// scales the B operand in registers.  Work items are ordered so that
+// consecutive items of one block land on the same XCD (its private L2 then
+// serves the repeated panel reads).
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
+                                              const int4* __restrict__ items, int nitems,
+                                              const T* __restrict__ A,
+                                              const double* __restrict__ Dp,
+                                              T* __restrict__ LB, double delta) {
+  int w = blockIdx.x;
+  int per = gridDim.x / 8;
+  int g = (w % 8) * per + (w / 8);
+  if (g >= nitems) return;
+  const int4 it = items[g];
+  const BlockInfo b = blk[it.x];
+  const int R0 = it.y * 4, C0 = it.z * 4;
+  const bool diag = (it.y == it.z);
+  __shared__ T sA[2][8][TE];
+  __shared__ double sD[2][TS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const bool active = !(diag && wr < wc);
+  const int ntl = diag ? 4 : 8;
+
+  typedef typename Acc<T>::type AT;
+  AT acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) acc[a][c] = AT{0, 0, 0, 0};
+
+  T regs[8];
+  double dreg = 0.0;
+  auto load = [&](int K) {
+#pragma unroll
+    for (int tt = 0; tt < 8; ++tt) {
+      if (tt < ntl) {
+        int I = tt < 4 ? R0 + tt : C0 + tt - 4;
+        regs[tt] = (I < b.mt) ? A[a_tile(b, I, K) + tid] : T(0);
+      }
+    }
+    if (tid < TS) dreg = Dp[b.dpoff + (long long)K * TS + tid];
+  };
+  load(0);
+  for (int K = 0; K < b.nt; ++K) {
+    const int buf = K & 1;
+#pragma unroll
+    for (int tt = 0; tt < 8; ++tt)
+      if (tt < ntl) sA[buf][tt][tid] = regs[tt];
+    if (tid < TS) sD[buf][tid] = dreg;
+    __syncthreads();
+    if (K + 1 < b.nt) load(K + 1);
+    if (active) {
+      const T* ra0 = sA[buf][2 * wr];
+      const T* ra1 = sA[buf][2 * wr + 1];
+      const T* cb0 = diag ? sA[buf][2 * wc] : sA[buf][4 + 2 * wc];
+      const T* cb1 = cb0 + TE;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        T a0 = ra0[64 * s + lane], a1 = ra1[64 * s + lane];
+        T dd = (T)sD[buf][4 * s + (lane >> 4)];
+        T b0 = cb0[64 * s + lane] * dd, b1 = cb1[64 * s + lane] * dd;
+        acc[0][0] = mfma(a0, b0, acc[0][0]);
+        acc[0][1] = mfma(a0, b1, acc[0][1]);
+        acc[1][0] = mfma(a1, b0, acc[1][0]);
+        acc[1][1] = mfma(a1, b1, acc[1][1]);
+      }
+    }
+  }
+  if (!active) return;
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr) {
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc) {
+      const int I = R0 + 2 * wr + tr, J = C0 + 2 * wc + tc;
+      if (I >= b.mt || J >= b.mt || I < J) continue;
+      T* dst = LB + lb_tile(b, I, J);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T v = acc[tr][tc][r];
+        const int i = 4 * (lane >> 4) + r, j = lane & 15;
+        if (I == J && i == j) v = (TS * I + i < b.m) ? (T)(v + delta) : T(1);
+        dst[acc_index(lane, r)] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- a1: B_i'
+// One workgroup per (block, tile row of the link columns).  Writes B_i' =
+// [F_i D_i A_i' ; C_i'] into the bordered rows and F_i D_i F_i' (FP64) into the
+// Schur-contribution tiles.  Link rows are sparse (compressed rows, sorted
+// columns), so the products are gathers rather than GEMMs.
+template <typename T>
+__global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
+                                              const int2* __restrict__ items, int n0,
+                                              const double* __restrict__ A,
+                                              const double* __restrict__ C,
+                                              const int* __restrict__ lptr,
+                                              const int* __restrict__ lcol,
+                                              const double* __restrict__ lval,
+                                              const double* __restrict__ Dp,
+                                              T* __restrict__ LB, double* __restrict__ PQ) {
+  const int2 it = items[blockIdx.x];
+  const BlockInfo b = blk[it.x];
+  const int rr = it.y, r = b.mt + rr;
+  const int t = threadIdx.x, ql = t & 15, al = t >> 4;
+  const int q = TS * rr + ql;
+  int qi;
+  bool real;
+  const int sec = link_section(b, q, &qi, n0, &real);
+  int p0 = 0, p1 = 0;
+  if (real && sec < 2) {
+    p0 = lptr[b.csr_off + q];
+    p1 = lptr[b.csr_off + q + 1];
+  }
+  for (int c = 0; c < b.mt; ++c) {
+    const int a = TS * c + al;
+    double v = 0.0;
+    if (real && a < b.m) {
+      if (sec < 2) {
+        for (int e = p0; e < p1; ++e) {
+          const int j = lcol[e];
+          v += lval[e] * Dp[b.dpoff + j] * A[a_tile(b, a >> 4, j >> 4) + (j & 15) * TS + (a & 15)];
+        }
+      } else {
+        v = C[c_tile(b, a >> 4, qi >> 4) + (qi & 15) * TS + (a & 15)];
+      }
+    }
+    LB[lb_tile(b, r, c) + t] = (T)v;
+  }
+  // F D F' for tiles (rr, cc), cc <= rr
+  for (int cc = 0; cc <= rr; ++cc) {
+    const int q2 = TS * cc + al;
+    int qi2;
+    bool real2;
+    const int sec2 = link_section(b, q2, &qi2, n0, &real2);
+    double v = 0.0;
+    if (real && real2 && sec < 2 && sec2 < 2) {
+      int e1 = p0, e2 = lptr[b.csr_off + q2];
+      const int e2end = lptr[b.csr_off + q2 + 1];
+      while (e1 < p1 && e2 < e2end) {
+        const int j1 = lcol[e1], j2 = lcol[e2];
+        if (j1 == j2) {
+          v += lval[e1] * Dp[b.dpoff + j1] * lval[e2];
+          ++e1; ++e2;
+        } else if (j1 < j2) {
+          ++e1;
+        } else {
+          ++e2;
+        }
+      }
+    }
+    PQ[pq_tile(b, rr, cc) + t] = v;
+  }
+}
+
+// ---------------------------------------------------------------- a3 + a4
+__device__ inline double bcast(double v, int src) {
+  union { double d; int i[2]; } u;
+  u.d = v;
+  u.i[0] = __builtin_amdgcn_readlane(u.i[0], src);
+  u.i[1] = __builtin_amdgcn_readlane(u.i[1], src);
+  return u.d;
+}
+__device__ inline float bcast(float v, int src) {
+  union { float f; int i; } u;
+  u.f = v;
+  u.i = __builtin_amdgcn_readlane(u.i, src);
+  return u.f;
+}
+
+// Cholesky of one 16x16 tile (column-major in LDS) by one wave with the pivot
+// rule, followed by the inverse of the factor.  Lanes 0..15 own rows.
+template <typename T>
+__device__ void tile_chol_inv(T* P, T* Linv, double thr, int* cnt) {
+  const int lane = threadIdx.x & 63;
+  T a[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) a[k] = (lane < 16) ? P[k * TS + lane] : T(0);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    T d = bcast(a[j], j);
+    if (!((double)d > thr)) {
+      d = (T)PIVOT_BIG;
+      if (lane == 0) ++(*cnt);
+    }
+    const T ljj = (T)sqrt((double)d);
+    if (lane == j) a[j] = ljj;
+    else if (lane > j) a[j] = a[j] / ljj;
+#pragma unroll
+    for (int kk = j + 1; kk < 16; ++kk) {
+      const T lk = bcast(a[j], kk);
+      if (lane >= kk) a[kk] -= a[j] * lk;
+    }
+  }
+  // inverse: lane k builds column k from rows broadcast by lane i
+  T cinv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    T s = (lane == i) ? T(1) : T(0);
+#pragma unroll
+    for (int j = 0; j < i; ++j) s -= bcast(a[j], i) * cinv[j];
+    cinv[i] = s / bcast(a[i], i);
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) P[k * TS + lane] = (k <= lane) ? a[k] : T(0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Linv[lane * TS + i] = cinv[i];
+  }
+}
+
+// One workgroup per block: left-looking blocked Cholesky over the mt tile
+// columns of the bordered matrix.  Column panel p is first updated with the
+// finished columns (MFMA, A operand = L(r,q), B operand = L(p,q)'), its
+// diagonal tile is factored and inverted by one wave, and the tiles below are
+// multiplied by the inverse's transpose (MFMA).  The inverted diagonal tiles
+// are kept for the solve phase.
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restrict__ blk,
+                                                      T* __restrict__ LB, T* __restrict__ LINV,
+                                                      DevInfo* info) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BlockInfo b = blk[blockIdx.x];
+  T* panel = reinterpret_cast<T*>(smem_raw);
+  T* linv = panel + (size_t)b.rt * TE;
+  __shared__ double s_max[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  typedef typename Acc<T>::type AT;
+
+  // pivot threshold from the largest real diagonal entry of M_i
+  double md = 0.0;
+  for (int idx = tid; idx < b.m; idx += blockDim.x) {
+    const int p = idx >> 4, i = idx & 15;
+    md = fmax(md, (double)LB[lb_tile(b, p, p) + i * 17]);
+  }
+  for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off));
+  if (lane == 0) s_max[wave] = md;
+  __syncthreads();
+  const double thr = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
+  int cnt = 0;
+
+  for (int p = 0; p < b.mt; ++p) {
+    for (int r = p + wave; r < b.rt; r += 4) {
+      AT acc;
+      const T* src = LB + lb_tile(b, r, p);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] = src[acc_index(lane, k)];
+      for (int q = 0; q < p; ++q) {
+        const T* X = LB + lb_tile(b, r, q);
+        const T* Y = LB + lb_tile(b, p, q);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = mfma(-X[64 * s + lane], Y[64 * s + lane], acc);
+      }
+      T* dst = panel + (size_t)(r - p) * TE;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[acc_index(lane, k)] = acc[k];
+    }
+    __syncthreads();
+    if (wave == 0) tile_chol_inv<T>(panel, linv, thr, &cnt);
+    __syncthreads();
+    LB[lb_tile(b, p, p) + tid] = panel[tid];
+    LINV[b.linvoff + (long long)p * TE + tid] = linv[tid];
+    for (int r = p + 1 + wave; r < b.rt; r += 4) {
+      AT acc = AT{0, 0, 0, 0};
+      const T* X = panel + (size_t)(r - p) * TE;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma(X[64 * s + lane], linv[64 * s + lane], acc);
+      T* dst = LB + lb_tile(b, r, p);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[acc_index(lane, k)] = acc[k];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && cnt) atomicAdd(&info->pivots, cnt);
+}
+
+// ---------------------------------------------------------------- a5
+// Schur contribution of block i: PQ = F D F' - X X' with X = W_i' (the
+// bordered rows of the factor), in FP64 whatever the factor precision.
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur_contrib(const BlockInfo* __restrict__ blk,
+                                                       const T* __restrict__ LB,
+                                                       double* __restrict__ PQ) {
+  const BlockInfo b = blk[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ntiles = b.kt * (b.kt + 1) / 2;
+  for (int t = wave; t < ntiles; t += 4) {
+    int rr = 0;
+    while ((rr + 1) * (rr + 2) / 2 <= t) ++rr;
+    const int cc = t - rr * (rr + 1) / 2;
+    d4 acc;
+    double* dst = PQ + pq_tile(b, rr, cc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = dst[acc_index(lane, k)];
+    for (int q = 0; q < b.mt; ++q) {
+      const T* X = LB + lb_tile(b, b.mt + rr, q);
+      const T* Y = LB + lb_tile(b, b.mt + cc, q);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc = mfma(-(double)X[64 * s + lane], (double)Y[64 * s + lane], acc);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[acc_index(lane, k)] = acc[k];
+  }
+}
+
+// Element (q, q2) of block i's symmetric contribution (lower tiles stored).
+__device__ inline double pq_get(const double* PQ, const BlockInfo& b, int q, int q2) {
+  if ((q >> 4) < (q2 >> 4)) { int t = q; q = q2; q2 = t; }
+  return PQ[pq_tile(b, q >> 4, q2 >> 4) + (q2 & 15) * TS + (q & 15)];
+}
+
+// One workgroup per link pair j: T_jj (col-major, + delta I), T_{j+1,j}
+// (col-major) and E_j (l_j x n0, col-major), each entry the fixed-order sum of
+// its two contributing blocks, and the pivot threshold of the pair.
+__global__ __launch_bounds__(256) void k_assemble_pairs(
+    const BlockInfo* __restrict__ blk, int P, int n0, const int* __restrict__ lsz,
+    const long long* __restrict__ tdoff, const long long* __restrict__ tooff,
+    const long long* __restrict__ eoff, const double* __restrict__ PQ,
+    const double* __restrict__ F0, const long long* __restrict__ loff, double delta,
+    double* __restrict__ Td, double* __restrict__ To, double* __restrict__ E,
+    double* __restrict__ thrT) {
+  const int j = blockIdx.x;
+  const BlockInfo bl = blk[j], br = blk[j + 1];
+  const int l = lsz[j];
+  const int offR = TS * bl.ktL;          // pair j inside block j (its right section)
+  const int x0l = TS * (bl.ktL + bl.ktR), x0r = TS * (br.ktL + br.ktR);
+  __shared__ double s_max[4];
+  double md = 0.0;
+  for (int idx = threadIdx.x; idx < l * l; idx += blockDim.x) {
+    const int a = idx % l, c = idx / l;
+    double v = pq_get(PQ, bl, offR + a, offR + c) + pq_get(PQ, br, a, c);
+    if (a == c) {
+      v += delta;
+      md = fmax(md, v);
+    }
+    Td[tdoff[j] + idx] = v;
+  }
+  if (j + 1 < P) {
+    const int l2 = lsz[j + 1];
+    const int offR2 = TS * br.ktL;
+    for (int idx = threadIdx.x; idx < l2 * l; idx += blockDim.x) {
+      const int a = idx % l2, c = idx / l2;
+      To[tooff[j] + idx] = pq_get(PQ, br, offR2 + a, c);
+    }
+  }
+  for (int idx = threadIdx.x; idx < l * n0; idx += blockDim.x) {
+    const int a = idx % l, c = idx / l;
+    double v = pq_get(PQ, bl, offR + a, x0l + c) + pq_get(PQ, br, a, x0r + c);
+    if (F0) v += F0[(loff[j] + a) * n0 + c];
+    E[eoff[j] + idx] = v;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off));
+  if (lane == 0) s_max[wave] = md;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    thrT[j] = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
+}
+
+// S00 = -D_0^-1 + sum_i (F D F' - W'W)_i[x0, x0], summed in increasing i.
+__global__ __launch_bounds__(256) void k_assemble_s00(const BlockInfo* __restrict__ blk, int N,
+                                                      int n0, const double* __restrict__ PQ,
+                                                      const double* __restrict__ D0,
+                                                      double* __restrict__ S00) {
+  for (int idx = threadIdx.x + blockIdx.x * blockDim.x; idx < n0 * n0;
+       idx += blockDim.x * gridDim.x) {
+    const int a = idx % n0, c = idx / n0;
+    double v = (a == c) ? -1.0 / D0[a] : 0.0;
+    for (int i = 0; i < N; ++i) {
+      const BlockInfo b = blk[i];
+      const int x0 = TS * (b.ktL + b.ktR);
+      v += pq_get(PQ, b, x0 + a, x0 + c);
+    }
+    S00[idx] = v;
+  }
+}
+
+// FP32 shadow of the constraint blocks (FP32 mode).
+__global__ void k_convert_f32(long long n, const double* __restrict__ src, float* __restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+// ------------------------------------------------------------- launchers
+void launch_convert_f32(hipStream_t st, long long n, const double* src, float* dst) {
+  long long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (n > 0) hipLaunchKernelGGL(k_convert_f32, dim3((int)g), dim3(256), 0, st, n, src, dst);
+}
+
+void launch_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                 long long d0off, const double* x, const double* z, double rho, double* Dp,
+                 double* xs, double* zs, DevInfo* info) {
+  hipLaunchKernelGGL(k_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, z,
+                     rho, Dp, xs, zs, info);
+}
+
+template <typename T>
+void launch_syrk(hipStream_t st, const BlockInfo* blk, const int4* items, int nitems,
+                 const T* A, const double* Dp, T* LB, double delta) {
+  const int grid = 8 * ((nitems + 7) / 8);
+  hipLaunchKernelGGL(k_syrk<T>, dim3(grid), dim3(256), 0, st, blk, items, nitems, A, Dp, LB,
+                     delta);
+}
+template void launch_syrk<double>(hipStream_t, const BlockInfo*, const int4*, int, const double*,
+                                  const double*, double*, double);
+template void launch_syrk<float>(hipStream_t, const BlockInfo*, const int4*, int, const float*,
+                                 const double*, float*, double);
+
+template <typename T>
+void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int n0,
+                 const double* A, const double* C, const int* lptr, const int* lcol,
+                 const double* lval, const double* Dp, T* LB, double* PQ) {
+  if (nitems == 0) return;
+  hipLaunchKernelGGL(k_link<T>, dim3(nitems), dim3(256), 0, st, blk, items, n0, A, C, lptr, lcol,
+                     lval, Dp, LB, PQ);
+}
+template void launch_link<double>(hipStream_t, const BlockInfo*, const int2*, int, int,
+                                  const double*, const double*, const int*, const int*,
+                                  const double*, const double*, double*, double*);
+template void launch_link<float>(hipStream_t, const BlockInfo*, const int2*, int, int,
+                                 const double*, const double*, const int*, const int*,
+                                 const double*, const double*, float*, double*);
+
+template <typename T>
+void launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
+                         T* LINV, DevInfo* info) {
+  const size_t shmem = (size_t)(max_rt + 1) * TE * sizeof(T);
+  hipLaunchKernelGGL(k_block_factor<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, info);
+}
+template void launch_block_factor<double>(hipStream_t, const BlockInfo*, int, int, double*,
+                                          double*, DevInfo*);
+template void launch_block_factor<float>(hipStream_t, const BlockInfo*, int, int, float*, float*,
+                                         DevInfo*);
+
+template <typename T>
+void launch_schur_contrib(hipStream_t st, const BlockInfo* blk, int N, const T* LB, double* PQ) {
+  hipLaunchKernelGGL(k_schur_contrib<T>, dim3(N), dim3(256), 0, st, blk, LB, PQ);
+}
+template void launch_schur_contrib<double>(hipStream_t, const BlockInfo*, int, const double*,
+                                           double*);
+template void launch_schur_contrib<float>(hipStream_t, const BlockInfo*, int, const float*,
+                                          double*);
+
+void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
+                     const long long* tdoff, const long long* tooff, const long long* eoff,
+                     const double* PQ, const double* F0, const long long* loff, double delta,
+                     const double* D0, double* Td, double* To, double* E, double* S00,
+                     double* thrT) {
+  const int P = N - 1;
+  if (P > 0)
+    hipLaunchKernelGGL(k_assemble_pairs, dim3(P), dim3(256), 0, st, blk, P, n0, lsz, tdoff,
+                       tooff, eoff, PQ, F0, loff, delta, Td, To, E, thrT);
+  if (n0 > 0) {
+    const int grid = (n0 * n0 + 255) / 256;
+    hipLaunchKernelGGL(k_assemble_s00, dim3(grid), dim3(256), 0, st, blk, N, n0, PQ, D0, S00);
+  }
+}
+
+}  // namespace ahlp

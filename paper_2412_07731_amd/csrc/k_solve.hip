@@ -1,0 +1,623 @@
+// Solve phase (a7) and interior-point glue (a8): products with the constraint
+// operator, per-block substitutions with the bordered factors, assembly of the
+// Schur right-hand side, elementwise updates and deterministic reductions.
+//
+// Vectors come in two layouts.  Canonical (the ABI's): x = [x_blocks, x_0],
+// y = [y_blocks, y_L].  Padded (internal): every block padded to whole tiles,
+// x_0 and block rows likewise, so tile products need no bounds checks.
+#include "common.h"
+#include "kernels.h"
+
+namespace ahlp {
+
+// ------------------------------------------------------------ layouts
+// x-space: block i at dpoff (16 nt slots), x_0 at d0off (n0p slots).
+__global__ void k_pad_x(const BlockInfo* __restrict__ blk, int N, int n0, long long x0off,
+                        long long d0off, const double* __restrict__ x, double* __restrict__ xp,
+                        const double* __restrict__ scale) {
+  const int i = blockIdx.x;
+  long long xo, po;
+  int n, np;
+  if (i < N) { xo = blk[i].xoff; po = blk[i].dpoff; n = blk[i].n; np = TS * blk[i].nt; }
+  else { xo = x0off; po = d0off; n = n0; np = (n0 + TS - 1) / TS * TS; }
+  for (int c = threadIdx.x; c < np; c += blockDim.x) {
+    double v = 0.0;
+    if (c < n) v = x[xo + c] * (scale ? scale[po + c] : 1.0);
+    xp[po + c] = v;
+  }
+}
+
+// y-space block rows: block i at voff (16 mt slots).
+__global__ void k_pad_y(const BlockInfo* __restrict__ blk, const double* __restrict__ y,
+                        double* __restrict__ yp) {
+  const BlockInfo b = blk[blockIdx.x];
+  for (int r = threadIdx.x; r < TS * b.mt; r += blockDim.x)
+    yp[b.voff + r] = (r < b.m) ? y[b.yoff + r] : 0.0;
+}
+
+// rhx = rx - rz / x (canonical) and vx = D * rhx (padded).
+__global__ void k_rhx(const BlockInfo* __restrict__ blk, int N, int n0, long long x0off,
+                      long long d0off, const double* __restrict__ rx,
+                      const double* __restrict__ rz, const double* __restrict__ xs,
+                      const double* __restrict__ Dp, double* __restrict__ rhx,
+                      double* __restrict__ vx) {
+  const int i = blockIdx.x;
+  long long xo, po;
+  int n, np;
+  if (i < N) { xo = blk[i].xoff; po = blk[i].dpoff; n = blk[i].n; np = TS * blk[i].nt; }
+  else { xo = x0off; po = d0off; n = n0; np = (n0 + TS - 1) / TS * TS; }
+  for (int c = threadIdx.x; c < np; c += blockDim.x) {
+    double v = 0.0;
+    if (c < n) {
+      const double h = rx[xo + c] - rz[xo + c] / xs[xo + c];
+      rhx[xo + c] = h;
+      v = Dp[po + c] * h;
+    }
+    vx[po + c] = v;
+  }
+}
+
+// ------------------------------------------------------------ block rows
+// out = base + alpha * (A_i xp_i [+ C_i xp_0]) for one 16-row tile per wave.
+// Lane l reads element 64 s + l of each tile: row l%16, column 4 s + l/16.
+// padded_out: write to voff + row (rows >= m get 0); else to yoff + row, row < m.
+__global__ __launch_bounds__(256) void k_rows(const BlockInfo* __restrict__ blk,
+                                              const int2* __restrict__ rowtiles, int nrt,
+                                              const double* __restrict__ A,
+                                              const double* __restrict__ C,
+                                              const double* __restrict__ xp, long long d0off,
+                                              const double* __restrict__ base, double alpha,
+                                              int with_C, int padded_out,
+                                              double* __restrict__ out) {
+  const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wt >= nrt) return;
+  const int lane = threadIdx.x & 63;
+  const int2 rt = rowtiles[wt];
+  const BlockInfo b = blk[rt.x];
+  const int I = rt.y;
+  double acc = 0.0;
+  const double* xb = xp + b.dpoff;
+  const double* At = A + a_tile(b, I, 0);
+  for (int K = 0; K < b.nt; ++K) {
+    const double* tile = At + (long long)K * TE;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc += tile[64 * s + lane] * xb[K * TS + 4 * s + (lane >> 4)];
+  }
+  if (with_C) {
+    const double* x0 = xp + d0off;
+    for (int Q = 0; Q < b.kt0; ++Q) {
+      const double* tile = C + c_tile(b, I, Q);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc += tile[64 * s + lane] * x0[Q * TS + 4 * s + (lane >> 4)];
+    }
+  }
+  acc += __shfl_xor(acc, 16);
+  acc += __shfl_xor(acc, 32);
+  if (lane < 16) {
+    const int row = TS * I + lane;
+    if (padded_out) {
+      double v = 0.0;
+      if (row < b.m) v = (base ? base[b.yoff + row] : 0.0) + alpha * acc;
+      out[b.voff + row] = v;
+    } else if (row < b.m) {
+      out[b.yoff + row] = (base ? base[b.yoff + row] : 0.0) + alpha * acc;
+    }
+  }
+}
+
+// Link rows: out[j-th pair, row a] = base + alpha * (FR_j xp_j + FL_j xp_{j+1} [+ F0 x0]).
+__global__ void k_linkrows(const BlockInfo* __restrict__ blk, int P, int n0,
+                           const int* __restrict__ lsz, const long long* __restrict__ loff,
+                           const int* __restrict__ lptr, const int* __restrict__ lcol,
+                           const double* __restrict__ lval, const double* __restrict__ xp,
+                           const double* __restrict__ x0, const double* __restrict__ F0,
+                           const double* __restrict__ base, double alpha,
+                           double* __restrict__ out) {
+  for (int j = blockIdx.x; j < P; j += gridDim.x) {
+    const BlockInfo bl = blk[j], br = blk[j + 1];
+    const int l = lsz[j];
+    for (int a = threadIdx.x; a < l; a += blockDim.x) {
+      double s = 0.0;
+      const int qr = TS * bl.ktL + a;   // right section of block j
+      for (int e = lptr[bl.csr_off + qr]; e < lptr[bl.csr_off + qr + 1]; ++e)
+        s += lval[e] * xp[bl.dpoff + lcol[e]];
+      for (int e = lptr[br.csr_off + a]; e < lptr[br.csr_off + a + 1]; ++e)
+        s += lval[e] * xp[br.dpoff + lcol[e]];
+      if (F0 && x0)
+        for (int c = 0; c < n0; ++c) s += F0[(loff[j] + a) * n0 + c] * x0[c];
+      const long long o = loff[j] + a;
+      out[o] = (base ? base[o] : 0.0) + alpha * s;
+    }
+  }
+}
+
+// ------------------------------------------------------------ block columns
+// g = A_i' yp_i + F_i' yL for one 16-column tile per wave, then by mode:
+//   0: out = g          1: out = cvec - g - zvec       2: out = D (g - rhx)
+// gout (optional) receives g.
+__global__ __launch_bounds__(256) void k_cols(const BlockInfo* __restrict__ blk,
+                                              const int2* __restrict__ coltiles, int nct,
+                                              const double* __restrict__ A,
+                                              const double* __restrict__ yp,
+                                              const double* __restrict__ yL,
+                                              const int* __restrict__ cptr,
+                                              const int* __restrict__ crow,
+                                              const double* __restrict__ cval, int mode,
+                                              const double* __restrict__ cvec,
+                                              const double* __restrict__ zvec,
+                                              const double* __restrict__ Dp,
+                                              double* __restrict__ gout,
+                                              double* __restrict__ out) {
+  const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wt >= nct) return;
+  const int lane = threadIdx.x & 63;
+  const int2 ct = coltiles[wt];
+  const BlockInfo b = blk[ct.x];
+  const int K = ct.y;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* yb = yp + b.voff;
+  for (int I = 0; I < b.mt; ++I) {
+    const double* tile = A + a_tile(b, I, K);
+    const double yv = yb[I * TS + (lane & 15)];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] += tile[64 * s + lane] * yv;
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double v = acc[s];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    acc[s] = v;
+  }
+  // lane 16*g holds column 4 s + g of the tile
+  if ((lane & 15) == 0) {
+    const int gidx = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = TS * K + 4 * s + gidx;
+      if (col >= b.n) continue;
+      double g = acc[s];
+      for (int e = cptr[b.csc_off + col]; e < cptr[b.csc_off + col + 1]; ++e)
+        g += cval[e] * yL[crow[e]];
+      const long long o = b.xoff + col;
+      if (gout) gout[o] = g;
+      double v = g;
+      if (mode == 1) v = cvec[o] - g - zvec[o];
+      else if (mode == 2) v = Dp[b.dpoff + col] * (g - cvec[o]);
+      if (out) out[o] = v;
+    }
+  }
+}
+
+// Per-block partial sums C_i' yp_i (one workgroup per block) for the x_0 columns.
+__global__ void k_x0_partial(const BlockInfo* __restrict__ blk, int n0,
+                             const double* __restrict__ C, const double* __restrict__ yp,
+                             double* __restrict__ part) {
+  const BlockInfo b = blk[blockIdx.x];
+  for (int c = threadIdx.x; c < n0; c += blockDim.x) {
+    double s = 0.0;
+    for (int a = 0; a < b.m; ++a)
+      s += C[c_tile(b, a >> 4, c >> 4) + (c & 15) * TS + (a & 15)] * yp[b.voff + a];
+    part[(long long)blockIdx.x * n0 + c] = s;
+  }
+}
+
+// g0 = sum_i partial_i + F0' yL (fixed order), then by mode as in k_cols
+// (mode 2 is not used for x_0: dx_0 comes from the Schur solve).
+__global__ void k_x0_finish(int N, int n0, long long nl, const double* __restrict__ part,
+                            const double* __restrict__ F0, const double* __restrict__ yL,
+                            int mode, const double* __restrict__ cvec,
+                            const double* __restrict__ zvec, long long x0off,
+                            double* __restrict__ gout, double* __restrict__ out) {
+  for (int c = threadIdx.x + blockIdx.x * blockDim.x; c < n0; c += blockDim.x * gridDim.x) {
+    double g = 0.0;
+    for (int i = 0; i < N; ++i) g += part[(long long)i * n0 + c];
+    if (F0)
+      for (long long r = 0; r < nl; ++r) g += F0[r * n0 + c] * yL[r];
+    const long long o = x0off + c;
+    if (gout) gout[o] = g;
+    if (out) out[o] = (mode == 1) ? cvec[o] - g - zvec[o] : g;
+  }
+}
+
+// ------------------------------------------------------------ substitutions
+// Forward substitution with the bordered factor of block i: v = L_i^-1 t and,
+// on the bordered rows, qn = -W_i' v.  t arrives in the padded block-row vector
+// and is overwritten by v.
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__ blk,
+                                                   const T* __restrict__ LB,
+                                                   const T* __restrict__ LINV,
+                                                   double* __restrict__ tv,
+                                                   double* __restrict__ qn) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* t = reinterpret_cast<double*>(smem_raw);
+  const BlockInfo b = blk[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nr = TS * b.rt, nm = TS * b.mt;
+  for (int r = tid; r < nr; r += blockDim.x) t[r] = (r < nm) ? tv[b.voff + r] : 0.0;
+  __syncthreads();
+  for (int p = 0; p < b.mt; ++p) {
+    if (wave == 0) {
+      const T* Li = LINV + b.linvoff + (long long)p * TE;
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += (double)Li[64 * k + lane] * t[TS * p + 4 * k + (lane >> 4)];
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      // all lanes have read t[p-block]; lanes 0..15 now overwrite it
+      if (lane < 16) t[TS * p + lane] = s;
+    }
+    __syncthreads();
+    for (int r = p + 1 + wave; r < b.rt; r += 4) {
+      const T* L = LB + lb_tile(b, r, p);
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += (double)L[64 * k + lane] * t[TS * p + 4 * k + (lane >> 4)];
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      if (lane < 16) t[TS * r + lane] -= s;
+    }
+    __syncthreads();
+  }
+  for (int r = tid; r < nm; r += blockDim.x) tv[b.voff + r] = t[r];
+  for (int r = nm + tid; r < nr; r += blockDim.x) qn[b.qoff + (r - nm)] = t[r];
+}
+
+// Backward substitution: y = L_i^-T (v - W_i u_i), where u_i (the block's view
+// of the Schur solution: left pair, right pair, x_0) fills the bordered rows.
+// Writes dy (canonical) and the padded copy dyp.
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__ blk, int n0,
+                                                   long long nl, const T* __restrict__ LB,
+                                                   const T* __restrict__ LINV,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ u,
+                                                   double* __restrict__ dy,
+                                                   double* __restrict__ dyp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* y = reinterpret_cast<double*>(smem_raw);
+  __shared__ double part[4][TS];
+  const BlockInfo b = blk[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nr = TS * b.rt, nm = TS * b.mt;
+  for (int r = tid; r < nr; r += blockDim.x) {
+    double val;
+    if (r < nm) {
+      val = v[b.voff + r];
+    } else {
+      int qi;
+      bool real;
+      const int sec = link_section(b, r - nm, &qi, n0, &real);
+      val = 0.0;
+      if (real) {
+        if (sec == 0) val = u[b.loffL + qi];
+        else if (sec == 1) val = u[b.loffR + qi];
+        else val = u[nl + qi];
+      }
+    }
+    y[r] = val;
+  }
+  __syncthreads();
+  for (int p = b.mt - 1; p >= 0; --p) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = p + 1 + wave; r < b.rt; r += 4) {
+      const T* L = LB + lb_tile(b, r, p);
+      const double yv = y[TS * r + (lane & 15)];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] += (double)L[64 * s + lane] * yv;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double x = acc[s];
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      x += __shfl_xor(x, 8);
+      if ((lane & 15) == 0) part[wave][4 * s + (lane >> 4)] = x;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // w = v_p - sum over waves (fixed order); y_p = Linv_p' w
+      const int kcol = lane & 15;
+      const double w = y[TS * p + kcol] - (part[0][kcol] + part[1][kcol] + part[2][kcol] + part[3][kcol]);
+      // element (i, k) of Linv at 64 s + l:  i = l%16, k = 4 s + l/16;  y_p[k] = sum_i Linv[i][k] w[i]
+      const T* Li = LINV + b.linvoff + (long long)p * TE;
+      double s4[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double wi = __shfl(w, lane & 15);
+        double x = (double)Li[64 * s + lane] * wi;
+        x += __shfl_xor(x, 1);
+        x += __shfl_xor(x, 2);
+        x += __shfl_xor(x, 4);
+        x += __shfl_xor(x, 8);
+        s4[s] = x;
+      }
+      if ((lane & 15) == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) part[0][4 * s + (lane >> 4)] = s4[s];
+      }
+    }
+    __syncthreads();
+    if (tid < TS) y[TS * p + tid] = part[0][tid];
+    __syncthreads();
+  }
+  for (int r = tid; r < nm; r += blockDim.x) {
+    dyp[b.voff + r] = (r < b.m) ? y[r] : 0.0;
+    if (r < b.m) dy[b.yoff + r] = y[r];
+  }
+}
+
+// Schur right-hand side: s_L[pair j] += qn_j[right section] + qn_{j+1}[left section];
+// s_0 = rhx_0 + sum_i qn_i[x_0 section] (fixed order).
+__global__ void k_schur_rhs(const BlockInfo* __restrict__ blk, int N, int n0,
+                            const int* __restrict__ lsz, const long long* __restrict__ loff,
+                            long long nl, const double* __restrict__ qn,
+                            const double* __restrict__ rhx0, double* __restrict__ s) {
+  const int P = N - 1;
+  for (int j = blockIdx.x; j < P; j += gridDim.x) {
+    const BlockInfo bl = blk[j], br = blk[j + 1];
+    for (int a = threadIdx.x; a < lsz[j]; a += blockDim.x)
+      s[loff[j] + a] += qn[bl.qoff + TS * bl.ktL + a] + qn[br.qoff + a];
+  }
+  if (blockIdx.x == 0) {
+    for (int c = threadIdx.x; c < n0; c += blockDim.x) {
+      double v = rhx0[c];
+      for (int i = 0; i < N; ++i) {
+        const BlockInfo b = blk[i];
+        v += qn[b.qoff + TS * (b.ktL + b.ktR) + c];
+      }
+      s[nl + c] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void k_axpy(long long n, double a, const double* __restrict__ x,
+                       double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+// dz = (rz - zs dx) / xs
+__global__ void k_dz(long long n, const double* __restrict__ rz, const double* __restrict__ zs,
+                     const double* __restrict__ xs, const double* __restrict__ dx,
+                     double* __restrict__ dz) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dz[i] = (rz[i] - zs[i] * dx[i]) / xs[i];
+}
+
+// Refinement residual pieces in x-space: ex = rx - g - dz;  ez = rz - zs dx - xs dz.
+__global__ void k_res_x(long long n, const double* __restrict__ rx, const double* __restrict__ rz,
+                        const double* __restrict__ g, const double* __restrict__ dx,
+                        const double* __restrict__ dz, const double* __restrict__ xs,
+                        const double* __restrict__ zs, double* __restrict__ ex,
+                        double* __restrict__ ez) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    ex[i] = rx[i] - g[i] - dz[i];
+    ez[i] = rz[i] - (zs[i] * dx[i] + xs[i] * dz[i]);
+  }
+}
+
+// Copy x0 part of the Schur solution into dx.
+__global__ void k_copy(long long n, const double* __restrict__ src, double* __restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Predictor/corrector complementarity right-hand sides:
+//   mode 0: rz = -x z;   mode 1: rz = sigma mu - x z - dxa dza  (sigma*mu in *smu)
+__global__ void k_rz(long long n, int mode, const double* __restrict__ x,
+                     const double* __restrict__ z, const double* __restrict__ dxa,
+                     const double* __restrict__ dza, double sm, double* __restrict__ rz) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v = -x[i] * z[i];
+    if (mode == 1) v += sm - dxa[i] * dza[i];
+    rz[i] = v;
+  }
+}
+
+__global__ void k_fill(long long n, double v, double* __restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+__global__ void k_addscalar(long long n, double v, double* __restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] += v;
+}
+
+// ------------------------------------------------------------ reductions
+// Fixed grid and fixed per-thread ranges; partials reduced in a fixed tree.
+// ops: 0 sum a*b, 1 max |a|, 2 min over b<0 of -a/b (inf if none),
+//      3 sum (a + s1 b)(c + s2 d)  [mu_aff], 4 max (a + b), 5 min a
+constexpr int RED_BLOCKS = RED_PARTIALS;
+constexpr int RED_THREADS = 256;
+
+__device__ inline double red_combine(int op, double x, double y) {
+  return (op == 0 || op == 3) ? x + y : ((op == 2 || op == 5) ? fmin(x, y) : fmax(x, y));
+}
+__device__ inline double red_identity(int op) {
+  return (op == 0 || op == 3) ? 0.0 : ((op == 2 || op == 5) ? INFINITY : (op == 4 ? -INFINITY : 0.0));
+}
+
+struct RedArgs {
+  int op;
+  long long n;
+  const double* a; const double* b; const double* c; const double* d;
+  double s1, s2;                        // step lengths (op 3)
+  double* partial;                      // [RED_BLOCKS]
+  double* out;                          // device scalar
+};
+
+__device__ double block_reduce(int op, double v) {
+  __shared__ double sh[RED_THREADS / 64];
+  for (int off = 32; off > 0; off >>= 1) v = red_combine(op, v, __shfl_xor(v, off));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = red_identity(op);
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) r = red_combine(op, r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce1(RedArgs r) {
+  const long long chunk = (r.n + gridDim.x - 1) / gridDim.x;
+  const long long lo = blockIdx.x * chunk;
+  const long long hi = lo + chunk < r.n ? lo + chunk : r.n;
+  const double s1 = r.s1, s2 = r.s2;
+  double v = red_identity(r.op);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double t;
+    switch (r.op) {
+      case 0: t = r.a[i] * r.b[i]; break;
+      case 1: t = fabs(r.a[i]); break;
+      case 2: t = (r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY; break;
+      case 3: t = (r.a[i] + s1 * r.b[i]) * (r.c[i] + s2 * r.d[i]); break;
+      case 4: t = r.a[i] + r.b[i]; break;
+      default: t = r.a[i]; break;
+    }
+    v = red_combine(r.op, v, t);
+  }
+  v = block_reduce(r.op, v);
+  if (threadIdx.x == 0) r.partial[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce2(RedArgs r, int nparts) {
+  double v = red_identity(r.op);
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v = red_combine(r.op, v, r.partial[i]);
+  v = block_reduce(r.op, v);
+  if (threadIdx.x == 0) *r.out = v;
+}
+
+// ------------------------------------------------------------ launchers
+static inline int grid1d(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+void launch_pad_x(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                  long long d0off, const double* x, double* xp, const double* scale) {
+  hipLaunchKernelGGL(k_pad_x, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, xp, scale);
+}
+void launch_pad_y(hipStream_t st, const BlockInfo* blk, int N, const double* y, double* yp) {
+  hipLaunchKernelGGL(k_pad_y, dim3(N), dim3(256), 0, st, blk, y, yp);
+}
+void launch_rhx(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                long long d0off, const double* rx, const double* rz, const double* xs,
+                const double* Dp, double* rhx, double* vx) {
+  hipLaunchKernelGGL(k_rhx, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, rx, rz, xs,
+                     Dp, rhx, vx);
+}
+void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
+                 const double* A, const double* C, const double* xp, long long d0off,
+                 const double* base, double alpha, int with_C, int padded_out, double* out) {
+  hipLaunchKernelGGL(k_rows, dim3((nrt + 3) / 4), dim3(256), 0, st, blk, rowtiles, nrt, A, C, xp,
+                     d0off, base, alpha, with_C, padded_out, out);
+}
+void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int n0, const int* lsz,
+                     const long long* loff, const int* lptr, const int* lcol,
+                     const double* lval, const double* xp, const double* x0, const double* F0,
+                     const double* base, double alpha, double* out) {
+  if (P <= 0) return;
+  const int grid = P < 1024 ? P : 1024;
+  hipLaunchKernelGGL(k_linkrows, dim3(grid), dim3(64), 0, st, blk, P, n0, lsz, loff, lptr, lcol,
+                     lval, xp, x0, F0, base, alpha, out);
+}
+void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int nct,
+                 const double* A, const double* yp, const double* yL, const int* cptr,
+                 const int* crow, const double* cval, int mode, const double* cvec,
+                 const double* zvec, const double* Dp, double* gout, double* out) {
+  hipLaunchKernelGGL(k_cols, dim3((nct + 3) / 4), dim3(256), 0, st, blk, coltiles, nct, A, yp, yL,
+                     cptr, crow, cval, mode, cvec, zvec, Dp, gout, out);
+}
+void launch_x0(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl, const double* C,
+               const double* yp, double* part, const double* F0, const double* yL, int mode,
+               const double* cvec, const double* zvec, long long x0off, double* gout,
+               double* out) {
+  if (n0 <= 0) return;
+  hipLaunchKernelGGL(k_x0_partial, dim3(N), dim3(64), 0, st, blk, n0, C, yp, part);
+  hipLaunchKernelGGL(k_x0_finish, dim3(1), dim3(128), 0, st, N, n0, nl, part, F0, yL, mode, cvec,
+                     zvec, x0off, gout, out);
+}
+template <typename T>
+void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, const T* LB,
+                      const T* LINV, double* tv, double* qn) {
+  const size_t sh = (size_t)TS * max_rt * sizeof(double);
+  hipLaunchKernelGGL(k_block_fwd<T>, dim3(N), dim3(256), sh, st, blk, LB, LINV, tv, qn);
+}
+template <typename T>
+void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl,
+                      int max_rt, const T* LB, const T* LINV, const double* v, const double* u,
+                      double* dy, double* dyp) {
+  const size_t sh = (size_t)TS * max_rt * sizeof(double);
+  hipLaunchKernelGGL(k_block_bwd<T>, dim3(N), dim3(256), sh, st, blk, n0, nl, LB, LINV, v, u, dy,
+                     dyp);
+}
+template void launch_block_fwd<double>(hipStream_t, const BlockInfo*, int, int, const double*,
+                                       const double*, double*, double*);
+template void launch_block_fwd<float>(hipStream_t, const BlockInfo*, int, int, const float*,
+                                      const float*, double*, double*);
+template void launch_block_bwd<double>(hipStream_t, const BlockInfo*, int, int, long long, int,
+                                       const double*, const double*, const double*,
+                                       const double*, double*, double*);
+template void launch_block_bwd<float>(hipStream_t, const BlockInfo*, int, int, long long, int,
+                                      const float*, const float*, const double*, const double*,
+                                      double*, double*);
+void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
+                      const long long* loff, long long nl, const double* qn, const double* rhx0,
+                      double* s) {
+  const int P = N - 1;
+  const int grid = P > 0 ? (P < 1024 ? P : 1024) : 1;
+  hipLaunchKernelGGL(k_schur_rhs, dim3(grid), dim3(64), 0, st, blk, N, n0, lsz, loff, nl, qn,
+                     rhx0, s);
+}
+void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid1d(n)), dim3(256), 0, st, n, a, x, y);
+}
+void launch_dz(hipStream_t st, long long n, const double* rz, const double* zs, const double* xs,
+               const double* dx, double* dz) {
+  hipLaunchKernelGGL(k_dz, dim3(grid1d(n)), dim3(256), 0, st, n, rz, zs, xs, dx, dz);
+}
+void launch_res_x(hipStream_t st, long long n, const double* rx, const double* rz,
+                  const double* g, const double* dx, const double* dz, const double* xs,
+                  const double* zs, double* ex, double* ez) {
+  hipLaunchKernelGGL(k_res_x, dim3(grid1d(n)), dim3(256), 0, st, n, rx, rz, g, dx, dz, xs, zs, ex,
+                     ez);
+}
+void launch_copy(hipStream_t st, long long n, const double* src, double* dst) {
+  if (n > 0) hipLaunchKernelGGL(k_copy, dim3(grid1d(n)), dim3(256), 0, st, n, src, dst);
+}
+void launch_rz(hipStream_t st, long long n, int mode, const double* x, const double* z,
+               const double* dxa, const double* dza, double smu, double* rz) {
+  hipLaunchKernelGGL(k_rz, dim3(grid1d(n)), dim3(256), 0, st, n, mode, x, z, dxa, dza, smu, rz);
+}
+void launch_fill(hipStream_t st, long long n, double v, double* dst) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(256), 0, st, n, v, dst);
+}
+void launch_addscalar(hipStream_t st, long long n, double v, double* dst) {
+  if (n > 0) hipLaunchKernelGGL(k_addscalar, dim3(grid1d(n)), dim3(256), 0, st, n, v, dst);
+}
+void launch_reduce(hipStream_t st, int op, long long n, const double* a, const double* b,
+                   const double* c, const double* d, double s1, double s2,
+                   double* partial, double* out) {
+  RedArgs r{op, n, a, b, c, d, s1, s2, partial, out};
+  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, r);
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(RED_THREADS), 0, st, r, RED_BLOCKS);
+}
+
+}  // namespace ahlp

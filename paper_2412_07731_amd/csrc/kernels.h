@@ -1,0 +1,127 @@
+// Host-callable launchers of the device kernels (one stream each).
+#pragma once
+
+#include "common.h"
+
+namespace ahlp {
+
+// factorization (k_factor.hip)
+void launch_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                 long long d0off, const double* x, const double* z, double rho, double* Dp,
+                 double* xs, double* zs, DevInfo* info);
+template <typename T>
+void launch_syrk(hipStream_t st, const BlockInfo* blk, const int4* items, int nitems,
+                 const T* A, const double* Dp, T* LB, double delta);
+template <typename T>
+void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int n0,
+                 const double* A, const double* C, const int* lptr, const int* lcol,
+                 const double* lval, const double* Dp, T* LB, double* PQ);
+template <typename T>
+void launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
+                         T* LINV, DevInfo* info);
+template <typename T>
+void launch_schur_contrib(hipStream_t st, const BlockInfo* blk, int N, const T* LB, double* PQ);
+void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
+                     const long long* tdoff, const long long* tooff, const long long* eoff,
+                     const double* PQ, const double* F0, const long long* loff, double delta,
+                     const double* D0, double* Td, double* To, double* E, double* S00,
+                     double* thrT);
+void launch_convert_f32(hipStream_t st, long long n, const double* src, float* dst);
+
+// Schur complement (k_chain.hip)
+struct ChainArgs {
+  int P, G, n0;
+  const int* l;            // [P]
+  const long long* tdoff;  // [P]    l_j^2 blocks (T_jj, L_j, L_j^-1)
+  const long long* tooff;  // [P-1]  l_{j+1} x l_j blocks (T_{j+1,j}, Yn_j)
+  const long long* eoff;   // [P]    l_j x n0 blocks (E_j, G_j)
+  const long long* zoff;   // [P]    l_{left separator} x l_j blocks (Z_j)
+  const long long* suboff; // [G]    separator couplings
+  const int2* seg;         // [G]    interior pairs [a, b)
+  const double* Td; const double* To; const double* E; const double* S00; const double* thrT;
+  double* CL; double* CLi; double* CYn; double* CZ; double* CG; double* CSub;
+  double* Lb; double* Lbi; double* S00w;
+  double* segout;          // per segment: SEG_STRIDE doubles
+  int lmax;
+  DevInfo* info;
+};
+
+constexpr int SEG_STRIDE = 3 * LMAX * LMAX + 2 * LMAX * N0MAX + N0MAX * N0MAX;
+// segment output slot layout (compact, leading dimension = actual size)
+__device__ inline double* so_diagL(double* s) { return s; }
+__device__ inline double* so_EL(double* s) { return s + LMAX * LMAX; }
+__device__ inline double* so_diagR(double* s) { return s + LMAX * LMAX + LMAX * N0MAX; }
+__device__ inline double* so_ER(double* s) { return s + 2 * LMAX * LMAX + LMAX * N0MAX; }
+__device__ inline double* so_off(double* s) { return s + 2 * LMAX * LMAX + 2 * LMAX * N0MAX; }
+__device__ inline double* so_S00(double* s) { return s + 3 * LMAX * LMAX + 2 * LMAX * N0MAX; }
+
+// rhs s and solution u: [pairs (offsets loff) | x_0 (offset nl)]; w: forward
+// intermediate in the same layout.
+struct ChainSolveArgs {
+  ChainArgs c;
+  const long long* loff;
+  long long nl;
+  const double* s;
+  double* w;
+  double* u;
+  double* segrhs;      // per segment: 2*LMAX + N0MAX doubles (dsL, dsR, ds0)
+};
+constexpr int SEGRHS_STRIDE = 2 * LMAX + N0MAX;
+
+
+size_t chain_factor_smem(int lmax, int n0);
+void launch_chain_factor(hipStream_t st, const ChainArgs& c);
+void launch_chain_solve(hipStream_t st, const ChainSolveArgs& a);
+void set_chain_smem_limits(size_t bytes);
+
+// solve phase and glue (k_solve.hip)
+void launch_pad_x(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                  long long d0off, const double* x, double* xp, const double* scale);
+void launch_pad_y(hipStream_t st, const BlockInfo* blk, int N, const double* y, double* yp);
+void launch_rhx(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                long long d0off, const double* rx, const double* rz, const double* xs,
+                const double* Dp, double* rhx, double* vx);
+void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
+                 const double* A, const double* C, const double* xp, long long d0off,
+                 const double* base, double alpha, int with_C, int padded_out, double* out);
+void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int n0, const int* lsz,
+                     const long long* loff, const int* lptr, const int* lcol,
+                     const double* lval, const double* xp, const double* x0, const double* F0,
+                     const double* base, double alpha, double* out);
+void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int nct,
+                 const double* A, const double* yp, const double* yL, const int* cptr,
+                 const int* crow, const double* cval, int mode, const double* cvec,
+                 const double* zvec, const double* Dp, double* gout, double* out);
+void launch_x0(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl, const double* C,
+               const double* yp, double* part, const double* F0, const double* yL, int mode,
+               const double* cvec, const double* zvec, long long x0off, double* gout,
+               double* out);
+template <typename T>
+void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, const T* LB,
+                      const T* LINV, double* tv, double* qn);
+template <typename T>
+void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl,
+                      int max_rt, const T* LB, const T* LINV, const double* v, const double* u,
+                      double* dy, double* dyp);
+void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
+                      const long long* loff, long long nl, const double* qn, const double* rhx0,
+                      double* s);
+void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y);
+void launch_dz(hipStream_t st, long long n, const double* rz, const double* zs, const double* xs,
+               const double* dx, double* dz);
+void launch_res_x(hipStream_t st, long long n, const double* rx, const double* rz,
+                  const double* g, const double* dx, const double* dz, const double* xs,
+                  const double* zs, double* ex, double* ez);
+void launch_copy(hipStream_t st, long long n, const double* src, double* dst);
+void launch_rz(hipStream_t st, long long n, int mode, const double* x, const double* z,
+               const double* dxa, const double* dza, double smu, double* rz);
+void launch_fill(hipStream_t st, long long n, double v, double* dst);
+void launch_addscalar(hipStream_t st, long long n, double v, double* dst);
+void launch_reduce(hipStream_t st, int op, long long n, const double* a, const double* b,
+                   const double* c, const double* d, double s1, double s2, double* partial,
+                   double* out);
+
+enum RedOp { RED_DOT = 0, RED_MAXABS = 1, RED_RATIO = 2, RED_MUAFF = 3, RED_MAXSUM = 4, RED_MIN = 5 };
+constexpr int RED_PARTIALS = 256;
+
+}  // namespace ahlp
