@@ -96,10 +96,15 @@ template <typename T> struct Acc;
 template <> struct Acc<double> { typedef d4 type; };
 template <> struct Acc<float> { typedef f4 type; };
 
-// Index inside a column-major tile of accumulator element r of lane l:
-// the 16x16 MFMA result holds (row 4*(l/16) + r, column l%16).
-__host__ __device__ inline int acc_index(int lane, int r) {
-  return (lane & 15) * TS + 4 * (lane >> 4) + r;
+// Row of accumulator element r of lane l (the column is always l%16).  The two
+// 16x16x4 MFMA variants differ: FP32 returns rows 4*(l/16) + r, FP64 returns
+// rows 4*r + l/16 (checked on gfx950 with a one-wave layout probe).
+template <typename T> __host__ __device__ inline int acc_row(int lane, int r);
+template <> __host__ __device__ inline int acc_row<double>(int lane, int r) { return 4 * r + (lane >> 4); }
+template <> __host__ __device__ inline int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+// Index inside a column-major tile of accumulator element r of lane l.
+template <typename T> __host__ __device__ inline int acc_index(int lane, int r) {
+  return (lane & 15) * TS + acc_row<T>(lane, r);
 }
 
 // Status/info word shared by all kernels of one handle.

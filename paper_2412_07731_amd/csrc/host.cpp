@@ -146,8 +146,8 @@ struct ahlp_problem_s {
   int nsyrk = 0;
   int2* link_items = nullptr;
   int nlink = 0;
-  int2 *rowtiles = nullptr, *coltiles = nullptr;
-  int nrt = 0, nct = 0;
+  int2 *rowtiles = nullptr, *coltiles = nullptr, *c0tiles = nullptr;
+  int nrt = 0, nct = 0, nc0 = 0;
   int* d_l = nullptr;
   long long *d_loff = nullptr, *d_tdoff = nullptr, *d_tooff = nullptr, *d_eoff = nullptr,
             *d_zoff = nullptr, *d_suboff = nullptr;
@@ -160,6 +160,12 @@ struct ahlp_problem_s {
   double *Td = nullptr, *To = nullptr, *E = nullptr, *S00 = nullptr, *thrT = nullptr;
   double *CL = nullptr, *CLi = nullptr, *CYn = nullptr, *CZ = nullptr, *CG = nullptr,
          *CSub = nullptr, *Lb = nullptr, *Lbi = nullptr, *S00w = nullptr, *segout = nullptr;
+  // tile path of the Schur factorization (pairs <= 16 rows, n0 <= 64)
+  bool fast = false;
+  int t0 = 0, s00_chunk = 16, s00_parts = 0;
+  double *FLi = nullptr, *FYn = nullptr, *FZ = nullptr, *FGt = nullptr,
+         *FSub = nullptr, *FLb = nullptr, *FLbi = nullptr, *fsegout = nullptr, *s00part = nullptr,
+         *fsegrhs = nullptr;
   DevInfo* info = nullptr;
   bool factored = false;
   int fprec = AHLP_FP64;
@@ -226,6 +232,17 @@ ChainArgs chain_args(ahlp_problem_t p) {
   return c;
 }
 
+FChainArgs fchain_args(ahlp_problem_t p) {
+  FChainArgs c{};
+  c.P = p->P; c.G = p->G; c.n0 = p->n0; c.t0 = p->t0;
+  c.l = p->d_l; c.tdoff = p->d_tdoff; c.tooff = p->d_tooff; c.eoff = p->d_eoff; c.seg = p->d_seg;
+  c.Td = p->Td; c.To = p->To; c.E = p->E; c.S00 = p->S00; c.thrT = p->thrT;
+  c.FLi = p->FLi; c.FYn = p->FYn; c.FZ = p->FZ; c.FGt = p->FGt; c.FSub = p->FSub;
+  c.FLb = p->FLb; c.FLbi = p->FLbi; c.segout = p->fsegout; c.s00part = p->s00part;
+  c.info = p->info;
+  return c;
+}
+
 ahlp_status_t ensure_fp32(ahlp_problem_t p, hipStream_t st) {
   if (!p->A32) {
     CHK(p->mem.alloc(&p->A32, p->a_total));
@@ -259,7 +276,8 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
                   p->thrT);
   p->timer.end();
   p->timer.begin(AHLP_ST_TFACTOR);
-  launch_chain_factor(st, chain_args(p));
+  if (p->fast) launch_fchain_factor(st, fchain_args(p), p->s00_parts, p->s00_chunk);
+  else launch_chain_factor(st, chain_args(p));
   p->timer.end();
   HIPCHK(hipGetLastError());
   p->factored = true;
@@ -291,18 +309,26 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   else solve_blocks_fwd<double>(p, st, p->LB, p->LINV);
   launch_schur_rhs(st, p->blk, p->N, p->n0, p->d_l, p->d_loff, p->nl, p->qn, p->rhx + p->x0off,
                    p->s);
-  ChainSolveArgs a{};
-  a.c = chain_args(p);
-  a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.w = p->w; a.u = p->u; a.segrhs = p->segrhs;
-  launch_chain_solve(st, a);
+  if (p->fast) {
+    FChainSolveArgs a{};
+    a.c = fchain_args(p);
+    a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.w = p->w; a.u = p->u; a.segrhs = p->fsegrhs;
+    launch_fchain_solve(st, a);
+  } else {
+    ChainSolveArgs a{};
+    a.c = chain_args(p);
+    a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.w = p->w; a.u = p->u; a.segrhs = p->segrhs;
+    launch_chain_solve(st, a);
+  }
   if (f32) solve_blocks_bwd<float>(p, st, p->LB32, p->LINV32, dy);
   else solve_blocks_bwd<double>(p, st, p->LB, p->LINV, dy);
   launch_copy(st, p->nl, p->u, dy + p->mblk);
   // dx_i = D_i (A_i' dy_i + F_i' dy_L - rhx_i);  g = A' dy
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, p->u, p->cptr, p->crow, p->cval, 2,
               p->rhx, nullptr, p->Dp, p->g, dx);
-  launch_x0(st, p->blk, p->N, p->n0, p->nl, p->C, p->dyp, p->part, p->F0, p->u, 0, nullptr,
-            nullptr, p->x0off, p->g, nullptr);
+  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
+  launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, p->u, 0, nullptr, nullptr, p->x0off,
+                p->g, nullptr);
   launch_copy(st, p->n0, p->u + p->nl, dx + p->x0off);
   launch_dz(st, p->n_tot, rz, p->zs, p->xs, dx, dz);
   p->timer.end();
@@ -317,8 +343,9 @@ void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, y + p->mblk, p->cptr, p->crow,
               p->cval, mode, cvec, zvec, p->Dp, mode == 0 ? out : nullptr,
               mode == 0 ? nullptr : out);
-  launch_x0(st, p->blk, p->N, p->n0, p->nl, p->C, p->dyp, p->part, p->F0, y + p->mblk, mode, cvec,
-            zvec, p->x0off, mode == 0 ? out : nullptr, mode == 0 ? nullptr : out);
+  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
+  launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
+                mode == 0 ? out : nullptr, mode == 0 ? nullptr : out);
 }
 
 // out = base + alpha * A x (canonical)
@@ -615,7 +642,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
 
   // ---- work lists
   std::vector<int4> hsyrk;
-  std::vector<int2> hlink, hrow, hcolt;
+  std::vector<int2> hlink, hrow, hcolt, hc0;
   for (int i = 0; i < N; ++i) {
     const BlockInfo& b = p->hb[i];
     const int MT = (b.mt + 3) / 4;
@@ -624,9 +651,10 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     for (int r = 0; r < b.kt; ++r) hlink.push_back(int2{i, r});
     for (int r = 0; r < b.mt; ++r) hrow.push_back(int2{i, r});
     for (int c = 0; c < b.nt; ++c) hcolt.push_back(int2{i, c});
+    for (int q = 0; q < b.kt0; ++q) hc0.push_back(int2{i, q});
   }
   p->nsyrk = (int)hsyrk.size(); p->nlink = (int)hlink.size();
-  p->nrt = (int)hrow.size(); p->nct = (int)hcolt.size();
+  p->nrt = (int)hrow.size(); p->nct = (int)hcolt.size(); p->nc0 = (int)hc0.size();
 
   // ---- Schur complement geometry and segments
   const int P = p->P;
@@ -642,6 +670,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   }
   if (P > 0) {
     int Ls = P <= 8 ? P : std::max(2, (int)std::lround(std::sqrt((double)P)));
+    Ls = std::min(Ls, fchain_max_segment());
     int start = 0;
     while (start < P) {
       const int a = start;
@@ -686,6 +715,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->link_items, std::max(p->nlink, 1)));
   CHK(M.alloc(&p->rowtiles, p->nrt));
   CHK(M.alloc(&p->coltiles, p->nct));
+  CHK(M.alloc(&p->c0tiles, std::max(p->nc0, 1)));
   CHK(M.alloc(&p->d_l, std::max(P, 1)));
   CHK(M.alloc(&p->d_loff, std::max(N, 1)));
   CHK(M.alloc(&p->d_tdoff, std::max(P, 1)));
@@ -715,7 +745,26 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->Lb, std::max(n0 * n0, 1)));
   CHK(M.alloc(&p->Lbi, std::max(n0 * n0, 1)));
   CHK(M.alloc(&p->S00w, std::max(n0 * n0, 1)));
-  CHK(M.alloc(&p->segout, (long long)std::max(p->G, 1) * SEG_STRIDE));
+  p->fast = fchain_supported(p->lmax, n0);
+  p->t0 = (n0 + 15) / 16;
+  if (p->fast) {
+    const long long Pt = std::max(P, 1);
+    p->s00_parts = P > 0 ? (P + p->s00_chunk - 1) / p->s00_chunk : 0;
+    CHK(M.alloc(&p->FLi, Pt * 256));
+    CHK(M.alloc(&p->FYn, Pt * 256));
+    CHK(M.alloc(&p->FZ, Pt * 256));
+    CHK(M.alloc(&p->FGt, Pt * std::max(p->t0, 1) * 256));
+    CHK(M.alloc(&p->FSub, (long long)std::max(p->G, 1) * 256));
+    CHK(M.alloc(&p->fsegout, (long long)std::max(p->G, 1) * fchain_seg_stride()));
+    CHK(M.alloc(&p->fsegrhs, (long long)std::max(p->G, 1) * fchain_segrhs_stride()));
+    CHK(M.alloc(&p->s00part, (long long)std::max(p->s00_parts, 1) * std::max(p->t0 * p->t0, 1) * 256));
+    CHK(M.alloc(&p->FLb, (long long)std::max(p->t0 * p->t0, 1) * 256));
+    CHK(M.alloc(&p->FLbi, (long long)std::max(p->t0 * p->t0, 1) * 256));
+    set_fchain_smem_limits(0);
+    CHK(M.alloc(&p->segout, 1));
+  } else {
+    CHK(M.alloc(&p->segout, (long long)std::max(p->G, 1) * SEG_STRIDE));
+  }
   CHK(M.alloc(&p->info, 1));
 
   CHK(M.alloc(&p->rhx, p->n_tot));
@@ -759,6 +808,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     HIPCHK(hipMemcpyAsync(p->link_items, hlink.data(), sizeof(int2) * hlink.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->rowtiles, hrow.data(), sizeof(int2) * hrow.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->coltiles, hcolt.data(), sizeof(int2) * hcolt.size(), hipMemcpyHostToDevice, st));
+  if (!hc0.empty())
+    HIPCHK(hipMemcpyAsync(p->c0tiles, hc0.data(), sizeof(int2) * hc0.size(), hipMemcpyHostToDevice, st));
   if (P > 0) {
     HIPCHK(hipMemcpyAsync(p->d_l, p->l.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(p->d_tdoff, p->tdoff.data(), sizeof(long long) * P, hipMemcpyHostToDevice, st));
@@ -906,8 +957,8 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     pinf = p->h_scal[3] / bn;
     dinf = p->h_scal[4] / cn;
     if (o->verbose)
-      fprintf(stderr, "ahlp it %3d mu %.3e gap %.3e pinf %.3e dinf %.3e%s\n", k, mu, relgap, pinf,
-              dinf, fp32_live ? " fp32" : "");
+      fprintf(stderr, "ahlp it %3d mu %.3e gap %.3e pinf %.3e dinf %.3e pobj %.10e%s\n", k, mu,
+              relgap, pinf, dinf, pobj, fp32_live ? " fp32" : "");
     if (relgap <= o->tol && pinf <= o->tol && dinf <= o->tol) {
       status = AHLP_OK;
       break;
@@ -921,11 +972,23 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     CHK(kkt_norm(p, st, &kn));
     double be;
     int steps;
-    // predictor
+    // predictor.  An FP32-factored solve that cannot reach the refinement
+    // target within max_refine corrections switches the run to FP64 factors
+    // for good and is repeated.
     launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);
     CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine,
                       o->refine_tol, kn, &be, &steps, st));
     account(be, steps);
+    if (o->verbose > 1) fprintf(stderr, "ahlp   predictor bkerr %.2e refine %d\n", be, steps);
+    if (fp32_live && be > o->refine_tol) {
+      fp32_live = false;
+      R.fp32_iterations--;
+      if (o->verbose) fprintf(stderr, "ahlp   FP32 refinement stalled (%.2e): FP64 from here\n", be);
+      CHK(factor_checked(x, z, AHLP_FP64, o->rho, o->delta));
+      CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine,
+                        o->refine_tol, kn, &be, &steps, st));
+      account(be, steps);
+    }
     red(p, RED_RATIO, n, x, p->dxa, 0, st);
     red(p, RED_RATIO, n, z, p->dza, 1, st);
     CHK(read_scal(p, 2, st));
@@ -939,6 +1002,16 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine,
                       o->refine_tol, kn, &be, &steps, st));
     account(be, steps);
+    if (o->verbose > 1) fprintf(stderr, "ahlp   corrector bkerr %.2e refine %d\n", be, steps);
+    if (fp32_live && be > o->refine_tol) {
+      fp32_live = false;
+      R.fp32_iterations--;
+      if (o->verbose) fprintf(stderr, "ahlp   FP32 refinement stalled (%.2e): FP64 from here\n", be);
+      CHK(factor_checked(x, z, AHLP_FP64, o->rho, o->delta));
+      CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine,
+                        o->refine_tol, kn, &be, &steps, st));
+      account(be, steps);
+    }
     red(p, RED_RATIO, n, x, p->dx, 0, st);
     red(p, RED_RATIO, n, z, p->dz, 1, st);
     CHK(read_scal(p, 2, st));

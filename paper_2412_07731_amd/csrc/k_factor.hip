@@ -13,6 +13,7 @@
 // construction with an incomplete LU of [K_i L_i'; L_i 0]).
 #include "common.h"
 #include "kernels.h"
+#include "tile_chol.h"
 
 namespace ahlp {
 
@@ -127,9 +128,9 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         T v = acc[tr][tc][r];
-        const int i = 4 * (lane >> 4) + r, j = lane & 15;
+        const int i = acc_row<T>(lane, r), j = lane & 15;
         if (I == J && i == j) v = (TS * I + i < b.m) ? (T)(v + delta) : T(1);
-        dst[acc_index(lane, r)] = v;
+        dst[acc_index<T>(lane, r)] = v;
       }
     }
   }
@@ -205,61 +206,6 @@ __global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
 }
 
 // ---------------------------------------------------------------- a3 + a4
-__device__ inline double bcast(double v, int src) {
-  union { double d; int i[2]; } u;
-  u.d = v;
-  u.i[0] = __builtin_amdgcn_readlane(u.i[0], src);
-  u.i[1] = __builtin_amdgcn_readlane(u.i[1], src);
-  return u.d;
-}
-__device__ inline float bcast(float v, int src) {
-  union { float f; int i; } u;
-  u.f = v;
-  u.i = __builtin_amdgcn_readlane(u.i, src);
-  return u.f;
-}
-
-// Cholesky of one 16x16 tile (column-major in LDS) by one wave with the pivot
-// rule, followed by the inverse of the factor.  Lanes 0..15 own rows.
-template <typename T>
-__device__ void tile_chol_inv(T* P, T* Linv, double thr, int* cnt) {
-  const int lane = threadIdx.x & 63;
-  T a[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) a[k] = (lane < 16) ? P[k * TS + lane] : T(0);
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    T d = bcast(a[j], j);
-    if (!((double)d > thr)) {
-      d = (T)PIVOT_BIG;
-      if (lane == 0) ++(*cnt);
-    }
-    const T ljj = (T)sqrt((double)d);
-    if (lane == j) a[j] = ljj;
-    else if (lane > j) a[j] = a[j] / ljj;
-#pragma unroll
-    for (int kk = j + 1; kk < 16; ++kk) {
-      const T lk = bcast(a[j], kk);
-      if (lane >= kk) a[kk] -= a[j] * lk;
-    }
-  }
-  // inverse: lane k builds column k from rows broadcast by lane i
-  T cinv[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    T s = (lane == i) ? T(1) : T(0);
-#pragma unroll
-    for (int j = 0; j < i; ++j) s -= bcast(a[j], i) * cinv[j];
-    cinv[i] = s / bcast(a[i], i);
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) P[k * TS + lane] = (k <= lane) ? a[k] : T(0);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Linv[lane * TS + i] = cinv[i];
-  }
-}
-
 // One workgroup per block: left-looking blocked Cholesky over the mt tile
 // columns of the bordered matrix.  Column panel p is first updated with the
 // finished columns (MFMA, A operand = L(r,q), B operand = L(p,q)'), its
@@ -275,6 +221,7 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
   T* panel = reinterpret_cast<T*>(smem_raw);
   T* linv = panel + (size_t)b.rt * TE;
   __shared__ double s_max[4];
+  __shared__ T xbuf[48];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   typedef typename Acc<T>::type AT;
 
@@ -295,7 +242,7 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
       AT acc;
       const T* src = LB + lb_tile(b, r, p);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] = src[acc_index(lane, k)];
+      for (int k = 0; k < 4; ++k) acc[k] = src[acc_index<T>(lane, k)];
       for (int q = 0; q < p; ++q) {
         const T* X = LB + lb_tile(b, r, q);
         const T* Y = LB + lb_tile(b, p, q);
@@ -304,10 +251,10 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
       }
       T* dst = panel + (size_t)(r - p) * TE;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) dst[acc_index(lane, k)] = acc[k];
+      for (int k = 0; k < 4; ++k) dst[acc_index<T>(lane, k)] = acc[k];
     }
     __syncthreads();
-    if (wave == 0) tile_chol_inv<T>(panel, linv, thr, &cnt);
+    if (wave == 0) cnt += wave_chol_tile<T>(panel, panel, linv, thr, xbuf);
     __syncthreads();
     LB[lb_tile(b, p, p) + tid] = panel[tid];
     LINV[b.linvoff + (long long)p * TE + tid] = linv[tid];
@@ -318,7 +265,7 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
       for (int s = 0; s < 4; ++s) acc = mfma(X[64 * s + lane], linv[64 * s + lane], acc);
       T* dst = LB + lb_tile(b, r, p);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) dst[acc_index(lane, k)] = acc[k];
+      for (int k = 0; k < 4; ++k) dst[acc_index<T>(lane, k)] = acc[k];
     }
     __syncthreads();
   }
@@ -342,7 +289,7 @@ __global__ __launch_bounds__(256) void k_schur_contrib(const BlockInfo* __restri
     d4 acc;
     double* dst = PQ + pq_tile(b, rr, cc);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = dst[acc_index(lane, k)];
+    for (int k = 0; k < 4; ++k) acc[k] = dst[acc_index<double>(lane, k)];
     for (int q = 0; q < b.mt; ++q) {
       const T* X = LB + lb_tile(b, b.mt + rr, q);
       const T* Y = LB + lb_tile(b, b.mt + cc, q);
@@ -351,7 +298,7 @@ __global__ __launch_bounds__(256) void k_schur_contrib(const BlockInfo* __restri
         acc = mfma(-(double)X[64 * s + lane], (double)Y[64 * s + lane], acc);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) dst[acc_index(lane, k)] = acc[k];
+    for (int k = 0; k < 4; ++k) dst[acc_index<double>(lane, k)] = acc[k];
   }
 }
 
@@ -409,21 +356,31 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(
     thrT[j] = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
 }
 
-// S00 = -D_0^-1 + sum_i (F D F' - W'W)_i[x0, x0], summed in increasing i.
+// S00 = -D_0^-1 + sum_i (F D F' - W'W)_i[x0, x0]: one workgroup per entry, each
+// thread a fixed strided subset of the blocks, then a fixed reduction tree.
 __global__ __launch_bounds__(256) void k_assemble_s00(const BlockInfo* __restrict__ blk, int N,
                                                       int n0, const double* __restrict__ PQ,
                                                       const double* __restrict__ D0,
                                                       double* __restrict__ S00) {
-  for (int idx = threadIdx.x + blockIdx.x * blockDim.x; idx < n0 * n0;
-       idx += blockDim.x * gridDim.x) {
-    const int a = idx % n0, c = idx / n0;
-    double v = (a == c) ? -1.0 / D0[a] : 0.0;
-    for (int i = 0; i < N; ++i) {
-      const BlockInfo b = blk[i];
-      const int x0 = TS * (b.ktL + b.ktR);
-      v += pq_get(PQ, b, x0 + a, x0 + c);
-    }
-    S00[idx] = v;
+  __shared__ double sh[4];
+  const int idx = blockIdx.x;
+  const int a = idx % n0, c = idx / n0;
+  if (c > a) return;   // lower triangle computed, mirrored below
+  double v = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const BlockInfo& b = blk[i];
+    const int x0 = TS * (b.ktL + b.ktR);
+    v += pq_get(PQ, b, x0 + a, x0 + c);
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = (a == c) ? -1.0 / D0[a] : 0.0;
+    t += ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+    S00[a + c * n0] = t;
+    S00[c + a * n0] = t;
   }
 }
 
@@ -504,10 +461,8 @@ void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const 
   if (P > 0)
     hipLaunchKernelGGL(k_assemble_pairs, dim3(P), dim3(256), 0, st, blk, P, n0, lsz, tdoff,
                        tooff, eoff, PQ, F0, loff, delta, Td, To, E, thrT);
-  if (n0 > 0) {
-    const int grid = (n0 * n0 + 255) / 256;
-    hipLaunchKernelGGL(k_assemble_s00, dim3(grid), dim3(256), 0, st, blk, N, n0, PQ, D0, S00);
-  }
+  if (n0 > 0)
+    hipLaunchKernelGGL(k_assemble_s00, dim3(n0 * n0), dim3(256), 0, st, blk, N, n0, PQ, D0, S00);
 }
 
 }  // namespace ahlp

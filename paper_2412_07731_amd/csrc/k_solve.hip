@@ -191,6 +191,43 @@ __global__ __launch_bounds__(256) void k_cols(const BlockInfo* __restrict__ blk,
   }
 }
 
+// Per-block partial sums C_i' yp_i: one 16-column tile of C_i per wave.
+__global__ __launch_bounds__(256) void k_ccols(const BlockInfo* __restrict__ blk,
+                                               const int2* __restrict__ ctiles, int nctile, int n0,
+                                               const double* __restrict__ C,
+                                               const double* __restrict__ yp,
+                                               double* __restrict__ part) {
+  const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wt >= nctile) return;
+  const int lane = threadIdx.x & 63;
+  const int2 ct = ctiles[wt];
+  const BlockInfo b = blk[ct.x];
+  const int Q = ct.y;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int I = 0; I < b.mt; ++I) {
+    const double* tile = C + c_tile(b, I, Q);
+    const double yv = yp[b.voff + I * TS + (lane & 15)];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] += tile[64 * s + lane] * yv;
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double v = acc[s];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    acc[s] = v;
+  }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = TS * Q + 4 * s + (lane >> 4);
+      if (col < n0) part[(long long)ct.x * n0 + col] = acc[s];
+    }
+  }
+}
+
 // Per-block partial sums C_i' yp_i (one workgroup per block) for the x_0 columns.
 __global__ void k_x0_partial(const BlockInfo* __restrict__ blk, int n0,
                              const double* __restrict__ C, const double* __restrict__ yp,
@@ -216,6 +253,30 @@ __global__ void k_x0_finish(int N, int n0, long long nl, const double* __restric
     for (int i = 0; i < N; ++i) g += part[(long long)i * n0 + c];
     if (F0)
       for (long long r = 0; r < nl; ++r) g += F0[r * n0 + c] * yL[r];
+    const long long o = x0off + c;
+    if (gout) gout[o] = g;
+    if (out) out[o] = (mode == 1) ? cvec[o] - g - zvec[o] : g;
+  }
+}
+
+// g0[c] = sum_i part[i][c] + (F0' yL)[c] with one workgroup per column: each
+// thread sums a fixed strided subset, then a fixed tree; then by mode as k_cols.
+__device__ double block_reduce(int op, double v);
+__global__ __launch_bounds__(256) void k_x0_sum(int N, int n0, long long nl,
+                                                const double* __restrict__ part,
+                                                const double* __restrict__ F0,
+                                                const double* __restrict__ yL, int mode,
+                                                const double* __restrict__ cvec,
+                                                const double* __restrict__ zvec, long long x0off,
+                                                double* __restrict__ gout,
+                                                double* __restrict__ out) {
+  const int c = blockIdx.x;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) v += part[(long long)i * n0 + c];
+  if (F0)
+    for (long long r = threadIdx.x; r < nl; r += blockDim.x) v += F0[r * n0 + c] * yL[r];
+  const double g = block_reduce(0, v);
+  if (threadIdx.x == 0) {
     const long long o = x0off + c;
     if (gout) gout[o] = g;
     if (out) out[o] = (mode == 1) ? cvec[o] - g - zvec[o] : g;
@@ -363,16 +424,20 @@ __global__ void k_schur_rhs(const BlockInfo* __restrict__ blk, int N, int n0,
     for (int a = threadIdx.x; a < lsz[j]; a += blockDim.x)
       s[loff[j] + a] += qn[bl.qoff + TS * bl.ktL + a] + qn[br.qoff + a];
   }
-  if (blockIdx.x == 0) {
-    for (int c = threadIdx.x; c < n0; c += blockDim.x) {
-      double v = rhx0[c];
-      for (int i = 0; i < N; ++i) {
-        const BlockInfo b = blk[i];
-        v += qn[b.qoff + TS * (b.ktL + b.ktR) + c];
-      }
-      s[nl + c] = v;
-    }
+}
+
+__global__ __launch_bounds__(256) void k_schur_rhs0(const BlockInfo* __restrict__ blk, int N,
+                                                    long long nl, const double* __restrict__ qn,
+                                                    const double* __restrict__ rhx0,
+                                                    double* __restrict__ s) {
+  const int c = blockIdx.x;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const BlockInfo& b = blk[i];
+    v += qn[b.qoff + TS * (b.ktL + b.ktR) + c];
   }
+  const double t = block_reduce(0, v);
+  if (threadIdx.x == 0) s[nl + c] = rhx0[c] + t;
 }
 
 // ------------------------------------------------------------ elementwise
@@ -545,6 +610,19 @@ void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int
   hipLaunchKernelGGL(k_cols, dim3((nct + 3) / 4), dim3(256), 0, st, blk, coltiles, nct, A, yp, yL,
                      cptr, crow, cval, mode, cvec, zvec, Dp, gout, out);
 }
+void launch_ccols(hipStream_t st, const BlockInfo* blk, const int2* ctiles, int nctile, int n0,
+                  const double* C, const double* yp, double* part) {
+  if (nctile > 0 && n0 > 0)
+    hipLaunchKernelGGL(k_ccols, dim3((nctile + 3) / 4), dim3(256), 0, st, blk, ctiles, nctile, n0,
+                       C, yp, part);
+}
+void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, const double* part,
+                   const double* F0, const double* yL, int mode, const double* cvec,
+                   const double* zvec, long long x0off, double* gout, double* out) {
+  if (n0 > 0)
+    hipLaunchKernelGGL(k_x0_sum, dim3(n0), dim3(256), 0, st, N, n0, nl, part, F0, yL, mode, cvec,
+                       zvec, x0off, gout, out);
+}
 void launch_x0(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl, const double* C,
                const double* yp, double* part, const double* F0, const double* yL, int mode,
                const double* cvec, const double* zvec, long long x0off, double* gout,
@@ -582,9 +660,13 @@ void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int n0, const
                       const long long* loff, long long nl, const double* qn, const double* rhx0,
                       double* s) {
   const int P = N - 1;
-  const int grid = P > 0 ? (P < 1024 ? P : 1024) : 1;
-  hipLaunchKernelGGL(k_schur_rhs, dim3(grid), dim3(64), 0, st, blk, N, n0, lsz, loff, nl, qn,
-                     rhx0, s);
+  if (P > 0) {
+    const int grid = P < 1024 ? P : 1024;
+    hipLaunchKernelGGL(k_schur_rhs, dim3(grid), dim3(64), 0, st, blk, N, n0, lsz, loff, nl, qn,
+                       rhx0, s);
+  }
+  if (n0 > 0)
+    hipLaunchKernelGGL(k_schur_rhs0, dim3(n0), dim3(256), 0, st, blk, N, nl, qn, rhx0, s);
 }
 void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y) {
   if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid1d(n)), dim3(256), 0, st, n, a, x, y);

@@ -69,6 +69,38 @@ struct ChainSolveArgs {
 constexpr int SEGRHS_STRIDE = 2 * LMAX + N0MAX;
 
 
+// Tile path (pairs of at most 16 rows, at most 64 linking variables).
+struct FChainArgs {
+  int P, G, n0, t0;
+  const int* l;
+  const long long* tdoff;
+  const long long* tooff;
+  const long long* eoff;
+  const int2* seg;
+  const double* Td; const double* To; const double* E; const double* S00; const double* thrT;
+  double* FLi; double* FYn; double* FZ; double* FGt; double* FSub;
+  double* FLb; double* FLbi;
+  double* segout;          // per segment: fchain_seg_stride() doubles
+  double* s00part;         // per chunk of pairs: t0*t0 tiles
+  DevInfo* info;
+};
+struct FChainSolveArgs {
+  FChainArgs c;
+  const long long* loff;
+  long long nl;
+  const double* s;
+  double* w;
+  double* u;
+  double* segrhs;          // per segment: fchain_segrhs_stride() doubles
+};
+bool fchain_supported(int lmax, int n0);
+int fchain_seg_stride();
+int fchain_segrhs_stride();
+void launch_fchain_factor(hipStream_t st, const FChainArgs& c, int nparts, int chunk);
+void launch_fchain_solve(hipStream_t st, const FChainSolveArgs& a);
+int fchain_max_segment();
+void set_fchain_smem_limits(size_t bytes);
+
 size_t chain_factor_smem(int lmax, int n0);
 void launch_chain_factor(hipStream_t st, const ChainArgs& c);
 void launch_chain_solve(hipStream_t st, const ChainSolveArgs& a);
@@ -92,6 +124,11 @@ void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int
                  const double* A, const double* yp, const double* yL, const int* cptr,
                  const int* crow, const double* cval, int mode, const double* cvec,
                  const double* zvec, const double* Dp, double* gout, double* out);
+void launch_ccols(hipStream_t st, const BlockInfo* blk, const int2* ctiles, int nctile, int n0,
+                  const double* C, const double* yp, double* part);
+void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, const double* part,
+                   const double* F0, const double* yL, int mode, const double* cvec,
+                   const double* zvec, long long x0off, double* gout, double* out);
 void launch_x0(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl, const double* C,
                const double* yp, double* part, const double* F0, const double* yL, int mode,
                const double* cvec, const double* zvec, long long x0off, double* gout,

@@ -72,7 +72,7 @@ SHAPES = [
     dict(N=2, m=5, n=9, l=1, n0=0),
     dict(N=3, m=7, n=11, l=0, n0=4),
     dict(N=3, m=17, n=35, l=4, n0=1),             # ragged tiles (17 rows, 35 columns)
-    dict(N=6, m=(3, 40), n="2m", l=(1, 20), n0=5),  # uneven blocks and pairs
+    dict(N=6, m=(12, 40), n="2m", l=(1, 20), n0=5),  # uneven blocks and pairs
     dict(N=8, m=32, n=64, l=4, n0=8),              # the tiny workload
     dict(N=40, m=48, n=96, l=16, n0=32),           # several segments in the chain solve
 ]
