@@ -370,6 +370,23 @@ void red(ahlp_problem_t p, int op, long long n, const double* a, const double* b
   launch_reduce(st, op, n, a, b, c, d, s1, s2, p->red_part, p->scal + slot);
 }
 
+// Batches independent reductions into one pair of launches.
+struct Reds {
+  MultiRed m{};
+  Reds(ahlp_problem_t p) {
+    m.nred = 0;
+    m.partial = p->red_part;
+    m.out = p->scal;
+  }
+  Reds& add(int op, long long n, const double* a, const double* b, int slot,
+            const double* c = nullptr, const double* d = nullptr, double s1 = 0, double s2 = 0) {
+    RedSpec& r = m.r[m.nred++];
+    r.op = op; r.slot = slot; r.n = n; r.a = a; r.b = b; r.c = c; r.d = d; r.s1 = s1; r.s2 = s2;
+    return *this;
+  }
+  void launch(hipStream_t st) { launch_mreduce(st, m); }
+};
+
 // Refined solve.  d = (dx, dy, dz) receives the result.  knorm: |K|_inf.
 ahlp_status_t solve_refined(ahlp_problem_t p, const double* rx, const double* ry,
                             const double* rz, double* dx, double* dy, double* dz, int max_refine,
@@ -382,27 +399,26 @@ ahlp_status_t solve_refined(ahlp_problem_t p, const double* rx, const double* ry
     if (steps_out) *steps_out = 0;
     return AHLP_OK;
   }
-  p->timer.begin(AHLP_ST_RESID);
-  red(p, RED_MAXABS, p->n_tot, rx, nullptr, 0, st);
-  red(p, RED_MAXABS, p->m_tot, ry, nullptr, 1, st);
-  red(p, RED_MAXABS, p->n_tot, rz, nullptr, 2, st);
-  p->timer.end();
-  double be = 0.0;
+  double be = 0.0, rn = 0.0;
+  bool first = true;
   while (true) {
     p->timer.begin(AHLP_ST_RESID);
     // e = r - K d:  ex = rx - A'dy - dz,  ey = ry - A dx,  ez = rz - Z dx - X dz
     launch_res_x(st, p->n_tot, rx, rz, p->g, dx, dz, p->xs, p->zs, p->ex, p->ez);
     apply_A(p, dx, ry, -1.0, p->ey, st);
-    red(p, RED_MAXABS, p->n_tot, p->ex, nullptr, 3, st);
-    red(p, RED_MAXABS, p->m_tot, p->ey, nullptr, 4, st);
-    red(p, RED_MAXABS, p->n_tot, p->ez, nullptr, 5, st);
-    red(p, RED_MAXABS, p->n_tot, dx, nullptr, 6, st);
-    red(p, RED_MAXABS, p->m_tot, dy, nullptr, 7, st);
-    red(p, RED_MAXABS, p->n_tot, dz, nullptr, 8, st);
+    Reds R(p);
+    R.add(RED_MAXABS, p->n_tot, p->ex, nullptr, 3).add(RED_MAXABS, p->m_tot, p->ey, nullptr, 4)
+        .add(RED_MAXABS, p->n_tot, p->ez, nullptr, 5).add(RED_MAXABS, p->n_tot, dx, nullptr, 6)
+        .add(RED_MAXABS, p->m_tot, dy, nullptr, 7).add(RED_MAXABS, p->n_tot, dz, nullptr, 8);
+    if (first)
+      R.add(RED_MAXABS, p->n_tot, rx, nullptr, 0).add(RED_MAXABS, p->m_tot, ry, nullptr, 1)
+          .add(RED_MAXABS, p->n_tot, rz, nullptr, 2);
+    R.launch(st);
     p->timer.end();
     CHK(read_scal(p, 9, st));
     const double* h = p->h_scal;
-    const double rn = std::max(h[0], std::max(h[1], h[2]));
+    if (first) rn = std::max(h[0], std::max(h[1], h[2]));
+    first = false;
     const double en = std::max(h[3], std::max(h[4], h[5]));
     const double dn = std::max(h[6], std::max(h[7], h[8]));
     const double den = knorm * dn + rn;
@@ -783,7 +799,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
                      &p->dxa, &p->dza, &p->dx, &p->dz})
     CHK(M.alloc(v, p->n_tot));
   for (double** v : {&p->ey, &p->cy, &p->rp, &p->dya, &p->dy}) CHK(M.alloc(v, p->m_tot));
-  CHK(M.alloc(&p->red_part, RED_PARTIALS));
+  CHK(M.alloc(&p->red_part, (long long)MAXRED * RED_PARTIALS));
   CHK(M.alloc(&p->scal, NSCAL));
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
 
@@ -911,21 +927,18 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     launch_copy(st, n, p->dxa, x);
     launch_copy(st, m, p->dy, y);
     apply_At(p, y, 1, p->c, p->zerosn, z, st);   // z~ = c - A'y~
-    red(p, RED_MIN, n, x, nullptr, 0, st);
-    red(p, RED_MIN, n, z, nullptr, 1, st);
+    Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, z, nullptr, 1).launch(st);
     CHK(read_scal(p, 2, st));
     const double sx = std::max(-1.5 * p->h_scal[0], 0.0), sz = std::max(-1.5 * p->h_scal[1], 0.0);
     launch_addscalar(st, n, sx, x);
     launch_addscalar(st, n, sz, z);
-    red(p, RED_DOT, n, x, z, 0, st);
-    red(p, RED_DOT, n, x, p->ones, 1, st);
-    red(p, RED_DOT, n, z, p->ones, 2, st);
+    Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, x, p->ones, 1).add(RED_DOT, n, z, p->ones, 2)
+        .launch(st);
     CHK(read_scal(p, 3, st));
     const double xz = p->h_scal[0], sumx = p->h_scal[1], sumz = p->h_scal[2];
     launch_addscalar(st, n, sumz > 0 ? 0.5 * xz / sumz : 0.0, x);
     launch_addscalar(st, n, sumx > 0 ? 0.5 * xz / sumx : 0.0, z);
-    red(p, RED_MIN, n, x, nullptr, 0, st);
-    red(p, RED_MIN, n, z, nullptr, 1, st);
+    Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, z, nullptr, 1).launch(st);
     CHK(read_scal(p, 2, st));
     if (p->h_scal[0] <= 0.0 || p->h_scal[1] <= 0.0) {
       launch_addscalar(st, n, 1.0, x);
@@ -943,13 +956,12 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     p->timer.begin(AHLP_ST_RESID);
     apply_A(p, x, p->b, -1.0, p->rp, st);                 // r_p = b - A x
     apply_At(p, y, 1, p->c, z, p->rd, st);                // r_d = c - A'y - z
-    red(p, RED_DOT, n, x, z, 0, st);
-    red(p, RED_DOT, n, p->c, x, 1, st);
-    red(p, RED_DOT, m, p->b, y, 2, st);
-    red(p, RED_MAXABS, m, p->rp, nullptr, 3, st);
-    red(p, RED_MAXABS, n, p->rd, nullptr, 4, st);
+    Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, p->c, x, 1).add(RED_DOT, m, p->b, y, 2)
+        .add(RED_MAXABS, m, p->rp, nullptr, 3).add(RED_MAXABS, n, p->rd, nullptr, 4)
+        .add(RED_MAXSUM, n, x, z, 5).launch(st);
     p->timer.end();
-    CHK(read_scal(p, 5, st));
+    CHK(read_scal(p, 6, st));
+    const double knorm_iter = std::max(p->colabs1_max, std::max(p->rowabs_max, p->h_scal[5]));
     mu = p->h_scal[0] / (double)n;
     pobj = p->h_scal[1];
     dobj = p->h_scal[2];
@@ -968,8 +980,7 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     const int prec = fp32_live ? AHLP_FP32_REFINE : AHLP_FP64;
     if (fp32_live) R.fp32_iterations++;
     CHK(factor_checked(x, z, prec, o->rho, o->delta));
-    double kn = 0;
-    CHK(kkt_norm(p, st, &kn));
+    const double kn = knorm_iter;
     double be;
     int steps;
     // predictor.  An FP32-factored solve that cannot reach the refinement
@@ -989,8 +1000,7 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
                         o->refine_tol, kn, &be, &steps, st));
       account(be, steps);
     }
-    red(p, RED_RATIO, n, x, p->dxa, 0, st);
-    red(p, RED_RATIO, n, z, p->dza, 1, st);
+    Reds(p).add(RED_RATIO, n, x, p->dxa, 0).add(RED_RATIO, n, z, p->dza, 1).launch(st);
     CHK(read_scal(p, 2, st));
     const double ap_aff = std::min(1.0, p->h_scal[0]), ad_aff = std::min(1.0, p->h_scal[1]);
     red(p, RED_MUAFF, n, x, p->dxa, 0, st, z, p->dza, ap_aff, ad_aff);
@@ -1012,8 +1022,7 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
                         o->refine_tol, kn, &be, &steps, st));
       account(be, steps);
     }
-    red(p, RED_RATIO, n, x, p->dx, 0, st);
-    red(p, RED_RATIO, n, z, p->dz, 1, st);
+    Reds(p).add(RED_RATIO, n, x, p->dx, 0).add(RED_RATIO, n, z, p->dz, 1).launch(st);
     CHK(read_scal(p, 2, st));
     const double ap = std::min(1.0, o->eta * p->h_scal[0]);
     const double ad = std::min(1.0, o->eta * p->h_scal[1]);

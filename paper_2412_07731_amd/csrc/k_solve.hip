@@ -78,6 +78,7 @@ __global__ __launch_bounds__(256) void k_rows(const BlockInfo* __restrict__ blk,
   double acc = 0.0;
   const double* xb = xp + b.dpoff;
   const double* At = A + a_tile(b, I, 0);
+#pragma unroll 8
   for (int K = 0; K < b.nt; ++K) {
     const double* tile = At + (long long)K * TE;
 #pragma unroll
@@ -156,6 +157,7 @@ __global__ __launch_bounds__(256) void k_cols(const BlockInfo* __restrict__ blk,
   const int K = ct.y;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const double* yb = yp + b.voff;
+#pragma unroll 8
   for (int I = 0; I < b.mt; ++I) {
     const double* tile = A + a_tile(b, I, K);
     const double yv = yb[I * TS + (lane & 15)];
@@ -204,6 +206,7 @@ __global__ __launch_bounds__(256) void k_ccols(const BlockInfo* __restrict__ blk
   const BlockInfo b = blk[ct.x];
   const int Q = ct.y;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
   for (int I = 0; I < b.mt; ++I) {
     const double* tile = C + c_tile(b, I, Q);
     const double yv = yp[b.voff + I * TS + (lane & 15)];
@@ -567,7 +570,48 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce2(RedArgs r, int nparts) 
   if (threadIdx.x == 0) *r.out = v;
 }
 
+// Several independent reductions in one pair of launches: blockIdx.y selects
+// the reduction; the per-reduction work split and trees are the same fixed
+// ones as k_reduce1/k_reduce2, so results do not depend on how many share a
+// launch.
+__global__ __launch_bounds__(RED_THREADS) void k_mreduce1(MultiRed m) {
+  const RedSpec& r = m.r[blockIdx.y];
+  const long long chunk = (r.n + gridDim.x - 1) / gridDim.x;
+  const long long lo = blockIdx.x * chunk;
+  const long long hi = lo + chunk < r.n ? lo + chunk : r.n;
+  double v = red_identity(r.op);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double t;
+    switch (r.op) {
+      case 0: t = r.a[i] * r.b[i]; break;
+      case 1: t = fabs(r.a[i]); break;
+      case 2: t = (r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY; break;
+      case 3: t = (r.a[i] + r.s1 * r.b[i]) * (r.c[i] + r.s2 * r.d[i]); break;
+      case 4: t = r.a[i] + r.b[i]; break;
+      default: t = r.a[i]; break;
+    }
+    v = red_combine(r.op, v, t);
+  }
+  v = block_reduce(r.op, v);
+  if (threadIdx.x == 0) m.partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_mreduce2(MultiRed m, int nparts) {
+  const RedSpec& r = m.r[blockIdx.x];
+  double v = red_identity(r.op);
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x)
+    v = red_combine(r.op, v, m.partial[(long long)blockIdx.x * nparts + i]);
+  v = block_reduce(r.op, v);
+  if (threadIdx.x == 0) m.out[r.slot] = v;
+}
+
 // ------------------------------------------------------------ launchers
+void launch_mreduce(hipStream_t st, const MultiRed& m) {
+  if (m.nred <= 0) return;
+  hipLaunchKernelGGL(k_mreduce1, dim3(RED_BLOCKS, m.nred), dim3(RED_THREADS), 0, st, m);
+  hipLaunchKernelGGL(k_mreduce2, dim3(m.nred), dim3(RED_THREADS), 0, st, m, RED_BLOCKS);
+}
+
 static inline int grid1d(long long n) {
   long long g = (n + 255) / 256;
   if (g > 4096) g = 4096;

@@ -158,6 +158,21 @@ void launch_reduce(hipStream_t st, int op, long long n, const double* a, const d
                    const double* c, const double* d, double s1, double s2, double* partial,
                    double* out);
 
+struct RedSpec {
+  int op, slot;          // operation, output slot
+  long long n;
+  const double* a; const double* b; const double* c; const double* d;
+  double s1, s2;
+};
+constexpr int MAXRED = 10;
+struct MultiRed {
+  int nred;
+  RedSpec r[MAXRED];
+  double* partial;       // [MAXRED * RED_PARTIALS]
+  double* out;
+};
+void launch_mreduce(hipStream_t st, const MultiRed& m);
+
 enum RedOp { RED_DOT = 0, RED_MAXABS = 1, RED_RATIO = 2, RED_MUAFF = 3, RED_MAXSUM = 4, RED_MIN = 5 };
 constexpr int RED_PARTIALS = 256;
 
