@@ -110,6 +110,8 @@ enum {
   AHLP_ST_TFACTOR = 4,    /* block-tridiagonal + border factorization of S (a6)       */
   AHLP_ST_SOLVE = 5,      /* solve phase (a7)                                         */
   AHLP_ST_RESID = 6,      /* residuals, reductions, refinement residuals (a8)         */
+  AHLP_ST_AROWS = 7,      /* each row pass out = base + A v over the dense blocks,    */
+                          /* timed alone; it also counts inside SOLVE and RESID       */
   AHLP_ST_COUNT = 8
 };
 

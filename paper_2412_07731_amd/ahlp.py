@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libahlp.so")
 FP64, FP32_REFINE = 0, 1
 STATUS = {0: "ok", -1: "einval", -2: "enomem", -3: "ehip", -4: "estate", -5: "enumeric",
           1: "wmaxiter", 2: "wstall"}
-STAGES = ["prep", "syrk", "factor", "schur", "tfactor", "solve", "resid", "other"]
+STAGES = ["prep", "syrk", "factor", "schur", "tfactor", "solve", "resid", "arows"]
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)

@@ -74,6 +74,7 @@ struct StageTimer {
   hipStream_t st = nullptr;
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> pending;
+  std::vector<size_t> open;   // indices into pending of records not yet ended (nesting)
   std::vector<hipEvent_t> pool;
   double ms[AHLP_ST_COUNT] = {0};
   int cnt[AHLP_ST_COUNT] = {0};
@@ -91,14 +92,17 @@ struct StageTimer {
     if (!on) return;
     Rec r{stage, get(), get()};
     (void)hipEventRecord(r.a, st);
+    open.push_back(pending.size());
     pending.push_back(r);
   }
   void end() {
-    if (!on || pending.empty()) return;
-    (void)hipEventRecord(pending.back().b, st);
+    if (!on || open.empty()) return;
+    (void)hipEventRecord(pending[open.back()].b, st);
+    open.pop_back();
   }
   // call after a stream synchronization
   void collect() {
+    open.clear();
     for (auto& r : pending) {
       float t = 0.f;
       if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
@@ -163,9 +167,9 @@ struct ahlp_problem_s {
   // tile path of the Schur factorization (pairs <= 16 rows, n0 <= 64)
   bool fast = false;
   int t0 = 0, s00_chunk = 16, s00_parts = 0;
-  double *FLi = nullptr, *FYn = nullptr, *FZ = nullptr, *FGt = nullptr,
-         *FSub = nullptr, *FLb = nullptr, *FLbi = nullptr, *fsegout = nullptr, *s00part = nullptr,
-         *fsegrhs = nullptr;
+  double *BD = nullptr, *BC = nullptr, *BEt = nullptr, *FLi = nullptr, *FXL = nullptr,
+         *FXR = nullptr, *FGt = nullptr, *FLb = nullptr, *FLbi = nullptr, *s00part = nullptr;
+  double *br = nullptr, *bw = nullptr, *bup = nullptr, *bpb = nullptr, *bu0p = nullptr;
   DevInfo* info = nullptr;
   bool factored = false;
   int fprec = AHLP_FP64;
@@ -232,13 +236,14 @@ ChainArgs chain_args(ahlp_problem_t p) {
   return c;
 }
 
-FChainArgs fchain_args(ahlp_problem_t p) {
-  FChainArgs c{};
-  c.P = p->P; c.G = p->G; c.n0 = p->n0; c.t0 = p->t0;
-  c.l = p->d_l; c.tdoff = p->d_tdoff; c.tooff = p->d_tooff; c.eoff = p->d_eoff; c.seg = p->d_seg;
+BcrArgs bcr_args(ahlp_problem_t p) {
+  BcrArgs c{};
+  c.P = p->P; c.n0 = p->n0; c.t0 = p->t0;
+  c.l = p->d_l; c.tdoff = p->d_tdoff; c.tooff = p->d_tooff; c.eoff = p->d_eoff;
   c.Td = p->Td; c.To = p->To; c.E = p->E; c.S00 = p->S00; c.thrT = p->thrT;
-  c.FLi = p->FLi; c.FYn = p->FYn; c.FZ = p->FZ; c.FGt = p->FGt; c.FSub = p->FSub;
-  c.FLb = p->FLb; c.FLbi = p->FLbi; c.segout = p->fsegout; c.s00part = p->s00part;
+  c.BD = p->BD; c.BC = p->BC; c.BEt = p->BEt;
+  c.FLi = p->FLi; c.FXL = p->FXL; c.FXR = p->FXR; c.FGt = p->FGt;
+  c.FLb = p->FLb; c.FLbi = p->FLbi; c.s00part = p->s00part;
   c.info = p->info;
   return c;
 }
@@ -276,7 +281,7 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
                   p->thrT);
   p->timer.end();
   p->timer.begin(AHLP_ST_TFACTOR);
-  if (p->fast) launch_fchain_factor(st, fchain_args(p), p->s00_parts, p->s00_chunk);
+  if (p->fast) launch_bcr_factor(st, bcr_args(p), p->s00_parts, p->s00_chunk);
   else launch_chain_factor(st, chain_args(p));
   p->timer.end();
   HIPCHK(hipGetLastError());
@@ -302,7 +307,9 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   p->timer.begin(AHLP_ST_SOLVE);
   launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->xs, p->Dp, p->rhx, p->vx);
   // t_i = ry_i + A_i D_i rhx_i (padded), s_L = ry_L + F D rhx
+  p->timer.begin(AHLP_ST_AROWS);
   launch_rows(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->vx, p->d0off, ry, 1.0, 0, 1, p->tv);
+  p->timer.end();
   launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->vx,
                   nullptr, nullptr, ry + p->mblk, 1.0, p->s);
   if (f32) solve_blocks_fwd<float>(p, st, p->LB32, p->LINV32);
@@ -310,10 +317,11 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   launch_schur_rhs(st, p->blk, p->N, p->n0, p->d_l, p->d_loff, p->nl, p->qn, p->rhx + p->x0off,
                    p->s);
   if (p->fast) {
-    FChainSolveArgs a{};
-    a.c = fchain_args(p);
-    a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.w = p->w; a.u = p->u; a.segrhs = p->fsegrhs;
-    launch_fchain_solve(st, a);
+    BcrSolveArgs a{};
+    a.c = bcr_args(p);
+    a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.u = p->u;
+    a.r = p->br; a.w = p->bw; a.up = p->bup; a.pb = p->bpb; a.u0p = p->bu0p;
+    launch_bcr_solve(st, a);
   } else {
     ChainSolveArgs a{};
     a.c = chain_args(p);
@@ -352,7 +360,9 @@ void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
 void apply_A(ahlp_problem_t p, const double* x, const double* base, double alpha, double* out,
              hipStream_t st) {
   launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->xp, nullptr);
+  p->timer.begin(AHLP_ST_AROWS);
   launch_rows(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->xp, p->d0off, base, alpha, 1, 0, out);
+  p->timer.end();
   launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
                   p->xp + p->d0off, p->F0, base ? base + p->mblk : nullptr, alpha, out + p->mblk);
 }
@@ -686,7 +696,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   }
   if (P > 0) {
     int Ls = P <= 8 ? P : std::max(2, (int)std::lround(std::sqrt((double)P)));
-    Ls = std::min(Ls, fchain_max_segment());
+    Ls = std::min(Ls, 24);
     int start = 0;
     while (start < P) {
       const int a = start;
@@ -761,22 +771,22 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->Lb, std::max(n0 * n0, 1)));
   CHK(M.alloc(&p->Lbi, std::max(n0 * n0, 1)));
   CHK(M.alloc(&p->S00w, std::max(n0 * n0, 1)));
-  p->fast = fchain_supported(p->lmax, n0);
+  p->fast = bcr_supported(p->lmax, n0);
   p->t0 = (n0 + 15) / 16;
   if (p->fast) {
     const long long Pt = std::max(P, 1);
     p->s00_parts = P > 0 ? (P + p->s00_chunk - 1) / p->s00_chunk : 0;
-    CHK(M.alloc(&p->FLi, Pt * 256));
-    CHK(M.alloc(&p->FYn, Pt * 256));
-    CHK(M.alloc(&p->FZ, Pt * 256));
-    CHK(M.alloc(&p->FGt, Pt * std::max(p->t0, 1) * 256));
-    CHK(M.alloc(&p->FSub, (long long)std::max(p->G, 1) * 256));
-    CHK(M.alloc(&p->fsegout, (long long)std::max(p->G, 1) * fchain_seg_stride()));
-    CHK(M.alloc(&p->fsegrhs, (long long)std::max(p->G, 1) * fchain_segrhs_stride()));
+    const long long T0 = std::max(p->t0, 1);
+    for (double** v : {&p->BD, &p->BC, &p->FLi, &p->FXL, &p->FXR}) CHK(M.alloc(v, Pt * 256));
+    CHK(M.alloc(&p->BEt, Pt * T0 * 256));
+    CHK(M.alloc(&p->FGt, Pt * T0 * 256));
+    for (double** v : {&p->br, &p->bw, &p->bup}) CHK(M.alloc(v, Pt * 16));
+    CHK(M.alloc(&p->bpb, Pt * T0 * 16));
+    CHK(M.alloc(&p->bu0p, T0 * 16));
     CHK(M.alloc(&p->s00part, (long long)std::max(p->s00_parts, 1) * std::max(p->t0 * p->t0, 1) * 256));
     CHK(M.alloc(&p->FLb, (long long)std::max(p->t0 * p->t0, 1) * 256));
     CHK(M.alloc(&p->FLbi, (long long)std::max(p->t0 * p->t0, 1) * 256));
-    set_fchain_smem_limits(0);
+    set_bcr_smem_limits();
     CHK(M.alloc(&p->segout, 1));
   } else {
     CHK(M.alloc(&p->segout, (long long)std::max(p->G, 1) * SEG_STRIDE));

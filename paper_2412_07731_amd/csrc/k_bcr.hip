@@ -1,0 +1,635 @@
+// Block cyclic reduction of the Schur complement (a6) for link pairs of at
+// most 16 rows and at most 64 linking variables.
+//
+// The assembled Schur complement is S = [T E; E' S00] with T block
+// tridiagonal over the P link pairs (App. A) and E, S00 the x_0 border.  T is
+// eliminated by odd-even reduction: at level v the active pairs are
+// j = k 2^v (k = 0 .. n_v - 1); the pairs at odd positions k are eliminated
+// all at once (each is coupled only to its two active neighbours), which
+// updates the even ones and couples neighbouring even pairs; the evens form
+// level v + 1.  This is the elimination of Alg. 3 of the Schur solve in a
+// symmetric permutation of T that turns its dependent chain of P steps into
+// ceil(log2 P) levels of independent steps.  For an eliminated pair o with
+// active neighbours L (left) and R (right):
+//   T'_oo = L_o L_o',  X_L = L_o^-1 T'_oL,  X_R = L_o^-1 T'_oR,  Z = L_o^-1 E'_o
+//   T'_LL -= X_L'X_L,  T'_RR -= X_R'X_R,  T'_RL = -X_R'X_L,
+//   E'_L -= X_L'Z,  E'_R -= X_R'Z,  S00 - sum over all pairs of Z'Z.
+// The border Schur complement S00 - E'T^-1 E is negative definite (the
+// system is quasi-definite) and is factorized as -(S00 - sum Z'Z) = Lb Lb'.
+//
+// Storage: 16x16 column-major tiles per pair j, padded with the identity.
+//   BD[j], BC[j], BEt[j][q]   working diagonal, coupling T'[next active, j]
+//                             and border rows (transposed, t0 tiles)
+//   FLi[o], FXL[o], FXR[o]    L_o^-1, X_L, X_R of the eliminated pair o
+//   FGt[o][q]                 Z' of pair o (t0 tiles), the final pair included
+//   FLb, FLbi                 border factor and its inverse, tiles (r, c) at c*t0 + r
+// Wide levels (more than TAIL_WAVES eliminations) run as one launch per level
+// (factor: both eliminations next to an even pair and its update in one
+// workgroup); the narrow levels, the final pair and (in the solve) the border
+// run inside one workgroup.  Every sum is taken in a fixed order.
+#include "common.h"
+#include "kernels.h"
+#include "tile_chol.h"
+#include "tile_ops.h"
+
+namespace ahlp {
+
+namespace {
+
+constexpr int BT_MAXT0 = 4;      // border tiles (n0 <= 64)
+constexpr int TAIL_WAVES = 8;    // waves of the single-workgroup tail kernels
+constexpr int ELIM_LDS = 256 + 256 + 48;   // doubles of LDS per eliminating wave
+
+// ---------------------------------------------------------------- factor
+// Working tiles from the assembled parts (one wave per tile).
+__global__ __launch_bounds__(256) void k_bcr_init(BcrArgs c) {
+  const int per = 2 + c.t0;
+  const long long wt = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wt >= (long long)c.P * per) return;
+  const int j = (int)(wt / per), kind = (int)(wt % per), lj = c.l[j];
+  if (kind == 0) {
+    acc_store(c.BD + (long long)j * 256, acc_load_exact(c.Td + c.tdoff[j], lj, lj, lj, true));
+  } else if (kind == 1) {
+    if (j + 1 < c.P) {
+      const int ln = c.l[j + 1];
+      acc_store(c.BC + (long long)j * 256, acc_load_exact(c.To + c.tooff[j], ln, lj, ln, false));
+    }
+  } else {
+    const int q = kind - 2;
+    acc_store(c.BEt + ((long long)j * c.t0 + q) * 256,
+              acc_load_exact_t(c.E + c.eoff[j] + 16LL * q * lj, min(16, c.n0 - 16 * q), lj, lj));
+  }
+}
+
+// Tile operands in registers: ld_a(X) gives X as the A operand of X*Y or
+// X*Y' (and Y as the B operand of X*Y'); ld_b(X) gives X as the B operand of
+// Y*X or the A/B operand of X'*Y.  All operands of a step are loaded before
+// any of them is used, so a step waits on memory once.
+struct T4 { double v[4]; };
+__device__ __forceinline__ T4 ld_a(const double* __restrict__ t) {
+  const int lane = threadIdx.x & 63;
+  T4 o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[64 * s + lane];
+  return o;
+}
+__device__ __forceinline__ T4 ld_b(const double* __restrict__ t) {
+  const int lane = threadIdx.x & 63;
+  const int idx = (lane & 15) * TS + (lane >> 4);
+  T4 o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[idx + 4 * s];
+  return o;
+}
+__device__ __forceinline__ T4 t4_zero() { return T4{{0.0, 0.0, 0.0, 0.0}}; }
+// acc + alpha * (product with the given operands)
+__device__ __forceinline__ d4 mm(d4 acc, const T4& a, const T4& b, double alpha) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma(alpha * a.v[s], b.v[s], acc);
+  return acc;
+}
+
+// Eliminate pair o (active neighbours L if needXL, R if hasR): factor its
+// working diagonal and form X_L = L_o^-1 T'[o,L], X_R = L_o^-1 T'[R,o]' and
+// G_q = (L_o^-1 E'_o)' (accumulator layout).  scr: ELIM_LDS doubles of this
+// wave; L_o^-1 is left in scr + 256.  Returns replaced pivots.
+__device__ int elim_core(const BcrArgs& c, long long o, long long L, bool needXL, bool hasR,
+                         double* scr, d4& XL, d4& XR, d4* G) {
+  double* cur = scr;
+  double* Li = scr + 256;
+  double* xbuf = scr + 512;
+  const double* __restrict__ BC = c.BC;
+  const double* __restrict__ BEt = c.BEt;
+  const d4 D = acc_load(c.BD + o * 256);
+  const double thr = c.thrT[o];
+  T4 cl = t4_zero(), cr = t4_zero(), et[BT_MAXT0];
+  if (needXL) cl = ld_b(BC + L * 256);
+  if (hasR) cr = ld_a(BC + o * 256);
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q) et[q] = q < c.t0 ? ld_a(BEt + (o * c.t0 + q) * 256) : t4_zero();
+  acc_store(cur, D);
+  wave_order();
+  const int cnt = wave_chol_tile<double>(cur, cur, Li, thr, xbuf);
+  const T4 li = ld_a(Li);
+  XL = needXL ? mm(acc_zero(), li, cl, 1.0) : acc_zero();
+  XR = hasR ? mm(acc_zero(), li, cr, 1.0) : acc_zero();
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q) G[q] = q < c.t0 ? mm(acc_zero(), et[q], li, 1.0) : acc_zero();
+  return cnt;
+}
+
+// store the factor of pair o (L^-1 from LDS)
+__device__ void store_factor(const BcrArgs& c, long long o, const double* Li, const d4& XL,
+                             const d4& XR, bool hasR, const d4* G) {
+  tile_copy(c.FLi + o * 256, Li);
+  acc_store(c.FXL + o * 256, XL);
+  if (hasR) acc_store(c.FXR + o * 256, XR);
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q)
+    if (q < c.t0) acc_store(c.FGt + (o * c.t0 + q) * 256, G[q]);
+}
+
+// One wide level (n active pairs): a workgroup of two waves per even position
+// k.  Wave 0 eliminates the right neighbour o_r (and stores its factor: every
+// odd pair has exactly one left neighbour), wave 1 eliminates the left one
+// o_l again; both leave their products in LDS and the update of the even pair
+// is split: wave 0 the diagonal and the new coupling, wave 1 the border rows.
+__global__ __launch_bounds__(128) void k_bcr_level(BcrArgs c, int lvl, int n) {
+  __shared__ double scr[2][ELIM_LDS];
+  __shared__ double xr_[2][(2 + BT_MAXT0) * 256];   // per wave: X_L, X_R, G_q
+  const int wave = threadIdx.x >> 6, k = 2 * blockIdx.x;
+  const long long s = 1LL << lvl, e = k * s;
+  const bool hl = k >= 1, hr = k + 1 < n, hrr = k + 2 < n;
+  int cnt = 0;
+  // the even pair's own tiles, loaded before the elimination
+  d4 Dp = acc_zero(), etp[BT_MAXT0];
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q) etp[q] = acc_zero();
+  if (wave == 0) {
+    Dp = acc_load(c.BD + e * 256);
+  } else {
+#pragma unroll
+    for (int q = 0; q < BT_MAXT0; ++q)
+      if (q < c.t0) etp[q] = acc_load(c.BEt + (e * c.t0 + q) * 256);
+  }
+  const bool mine = wave == 0 ? hr : hl;
+  if (mine) {
+    d4 XL, XR, G[BT_MAXT0];
+    const long long o = wave == 0 ? (k + 1) * s : (k - 1) * s;
+    const bool needXL = wave == 0, hasR = wave == 0 ? hrr : true;
+    cnt = elim_core(c, o, e, needXL, hasR, scr[wave], XL, XR, G);
+    double* x = xr_[wave];
+    acc_store(x, XL);
+    acc_store(x + 256, XR);
+#pragma unroll
+    for (int q = 0; q < BT_MAXT0; ++q)
+      if (q < c.t0) acc_store(x + (2 + q) * 256, G[q]);
+    if (wave == 0) store_factor(c, o, scr[0] + 256, XL, XR, hasR, G);
+  }
+  __syncthreads();
+  const double* xo = xr_[0];   // products of o_r
+  const double* xl = xr_[1];   // products of o_l
+  if (wave == 0) {
+    d4 D = Dp;
+    const T4 a = hl ? ld_b(xl + 256) : t4_zero();   // X_R(o_l)
+    const T4 b = hr ? ld_b(xo) : t4_zero();         // X_L(o_r)
+    if (hl) D = mm(D, a, a, -1.0);
+    if (hr) D = mm(D, b, b, -1.0);
+    acc_store(c.BD + e * 256, D);
+    if (hr && hrr) acc_store(c.BC + e * 256, mm(acc_zero(), ld_b(xo + 256), b, -1.0));
+  } else {
+    d4 et[BT_MAXT0];
+#pragma unroll
+    for (int q = 0; q < BT_MAXT0; ++q) et[q] = etp[q];
+    const T4 a = hl ? ld_b(xl + 256) : t4_zero();
+    const T4 b = hr ? ld_b(xo) : t4_zero();
+#pragma unroll
+    for (int q = 0; q < BT_MAXT0; ++q)
+      if (q < c.t0) {
+        if (hl) et[q] = mm(et[q], ld_a(xl + (2 + q) * 256), a, -1.0);
+        if (hr) et[q] = mm(et[q], ld_a(xo + (2 + q) * 256), b, -1.0);
+        acc_store(c.BEt + (e * c.t0 + q) * 256, et[q]);
+      }
+  }
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
+}
+
+// Narrow levels from lvl (n active pairs) down to one pair, then the final
+// pair; one workgroup of TAIL_WAVES waves: odd pairs eliminated (factor
+// stored), barrier, even pairs updated from the stored products, barrier.
+__global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail(BcrArgs c, int lvl, int n) {
+  __shared__ double scr[TAIL_WAVES][ELIM_LDS];
+  const int wave = threadIdx.x >> 6;
+  int cnt = 0;
+  for (; n > 1; ++lvl, n = (n + 1) / 2) {
+    const long long s = 1LL << lvl;
+    for (int w = wave; w < n / 2; w += TAIL_WAVES) {
+      const int k = 2 * w + 1;
+      const bool hasR = k + 1 < n;
+      d4 XL, XR, G[BT_MAXT0];
+      cnt += elim_core(c, k * s, (k - 1) * s, true, hasR, scr[wave], XL, XR, G);
+      store_factor(c, k * s, scr[wave] + 256, XL, XR, hasR, G);
+      wave_order();
+    }
+    __syncthreads();
+    for (int w = wave; w < (n + 1) / 2; w += TAIL_WAVES) {
+      const int k = 2 * w;
+      const long long e = k * s, ol = (k - 1) * s, orr = (k + 1) * s;
+      const bool hl = k >= 1, hr = k + 1 < n, hrr = k + 2 < n;
+      const double* __restrict__ FXL = c.FXL;
+      const double* __restrict__ FXR = c.FXR;
+      const double* __restrict__ FGt = c.FGt;
+      d4 D = acc_load(c.BD + e * 256);
+      const T4 a = hl ? ld_b(FXR + ol * 256) : t4_zero();
+      const T4 b = hr ? ld_b(FXL + orr * 256) : t4_zero();
+      const T4 xrr = (hr && hrr) ? ld_b(FXR + orr * 256) : t4_zero();
+      d4 et[BT_MAXT0];
+      T4 gl[BT_MAXT0], gr[BT_MAXT0];
+#pragma unroll
+      for (int q = 0; q < BT_MAXT0; ++q) {
+        const bool on = q < c.t0;
+        et[q] = on ? acc_load(c.BEt + (e * c.t0 + q) * 256) : acc_zero();
+        gl[q] = (on && hl) ? ld_a(FGt + (ol * c.t0 + q) * 256) : t4_zero();
+        gr[q] = (on && hr) ? ld_a(FGt + (orr * c.t0 + q) * 256) : t4_zero();
+      }
+      if (hl) D = mm(D, a, a, -1.0);
+      if (hr) D = mm(D, b, b, -1.0);
+      acc_store(c.BD + e * 256, D);
+      if (hr && hrr) acc_store(c.BC + e * 256, mm(acc_zero(), xrr, b, -1.0));
+#pragma unroll
+      for (int q = 0; q < BT_MAXT0; ++q)
+        if (q < c.t0) {
+          if (hl) et[q] = mm(et[q], gl[q], a, -1.0);
+          if (hr) et[q] = mm(et[q], gr[q], b, -1.0);
+          acc_store(c.BEt + (e * c.t0 + q) * 256, et[q]);
+        }
+    }
+    __syncthreads();
+  }
+  if (n == 1 && wave == 0) {
+    d4 XL, XR, G[BT_MAXT0];
+    cnt += elim_core(c, 0, 0, false, false, scr[0], XL, XR, G);
+    tile_copy(c.FLi, scr[0] + 256);
+#pragma unroll
+    for (int q = 0; q < BT_MAXT0; ++q)
+      if (q < c.t0) acc_store(c.FGt + q * 256, G[q]);
+  }
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
+}
+
+// Partial sums of Z_j'Z_j = FGt_j FGt_j' over contiguous chunks of pairs.
+__global__ __launch_bounds__(64) void k_bcr_s00_partial(BcrArgs c, int chunk) {
+  const int t0 = c.t0;
+  const int k0 = blockIdx.x * chunk, k1 = min(c.P, k0 + chunk);
+  double* out = c.s00part + (long long)blockIdx.x * t0 * t0 * 256;
+  for (int q = 0; q < t0; ++q)
+    for (int q2 = 0; q2 < t0; ++q2) {
+      d4 acc = acc_zero();
+      for (int k = k0; k < k1; ++k)
+        acc = mma_xyt(acc, c.FGt + ((long long)k * t0 + q) * 256,
+                      c.FGt + ((long long)k * t0 + q2) * 256, 1.0);
+      acc_store(out + (q * t0 + q2) * 256, acc);
+    }
+}
+
+// Border: B = -(S00 - sum of the partials) in t0 x t0 tiles (all four waves,
+// fixed order), then one wave: blocked Cholesky with tile inverses and the
+// block inverse of the factor.
+__global__ __launch_bounds__(256) void k_bcr_border(BcrArgs c, int nparts) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n0 = c.n0, t0 = c.t0, lane = threadIdx.x & 63;
+  double* B = reinterpret_cast<double*>(smem_raw);   // t0*t0 tiles (r, c) at c*t0 + r
+  double* X = B + t0 * t0 * 256;                      // inverse tiles
+  double* Ld = X + t0 * t0 * 256;                     // inverted diagonal tiles
+  double* tmp = Ld + t0 * 256;
+  double* xbuf = tmp + 256;
+  __shared__ double s_max;
+  for (int idx = threadIdx.x; idx < 256 * t0 * t0; idx += blockDim.x) {
+    const int tile = idx / 256, e = idx % 256;
+    const int r = tile % t0, cc = tile / t0;
+    const int i = 16 * r + (e & 15), j = 16 * cc + (e >> 4);
+    double v;
+    if (i < n0 && j < n0) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      const double* src = c.s00part + (long long)(r * t0 + cc) * 256 + e;
+      const long long stride = (long long)t0 * t0 * 256;
+      int pp = 0;
+      for (; pp + 4 <= nparts; pp += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += src[(pp + u) * stride];
+      }
+      for (; pp < nparts; ++pp) acc[0] += src[pp * stride];
+      v = -(c.S00[i + j * n0] - ((acc[0] + acc[1]) + (acc[2] + acc[3])));
+    } else {
+      v = (i == j) ? 1.0 : 0.0;
+    }
+    B[idx] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 64) return;   // one wave from here on (wave-scope ordering only)
+  if (lane == 0) {
+    double md = 0.0;
+    for (int i = 0; i < n0; ++i) {
+      const int r = i >> 4;
+      md = fmax(md, B[(r * t0 + r) * 256 + (i & 15) * 17]);
+    }
+    s_max = md;
+  }
+  wave_order();
+  const double thr = PIVOT_REL * fmax(s_max, 0.0);
+  int cnt = 0;
+  for (int p = 0; p < t0; ++p) {
+    double* Bpp = B + (p * t0 + p) * 256;
+    cnt += wave_chol_tile<double>(Bpp, Bpp, Ld + p * 256, thr, xbuf);
+    for (int r = p + 1; r < t0; ++r) {
+      d4 acc = mma_xyt(acc_zero(), B + (p * t0 + r) * 256, Ld + p * 256, 1.0);
+      wave_order();
+      acc_store(B + (p * t0 + r) * 256, acc);
+    }
+    wave_order();
+    for (int r = p + 1; r < t0; ++r)
+      for (int cc = p + 1; cc <= r; ++cc) {
+        d4 acc = acc_load(B + (cc * t0 + r) * 256);
+        acc = mma_xyt(acc, B + (p * t0 + r) * 256, B + (p * t0 + cc) * 256, -1.0);
+        wave_order();
+        acc_store(B + (cc * t0 + r) * 256, acc);
+      }
+    wave_order();
+  }
+  // X = L^-1 by block columns
+  for (int cc = 0; cc < t0; ++cc) {
+    for (int r = 0; r < t0; ++r) {
+      if (r < cc) {
+        for (int s = 0; s < 4; ++s) X[(cc * t0 + r) * 256 + 64 * s + lane] = 0.0;
+      } else if (r == cc) {
+        tile_copy(X + (cc * t0 + r) * 256, Ld + r * 256);
+      } else {
+        d4 acc = acc_zero();
+        for (int q = cc; q < r; ++q) acc = mma_xy(acc, B + (q * t0 + r) * 256, X + (cc * t0 + q) * 256, 1.0);
+        acc_store(tmp, acc);
+        wave_order();
+        d4 x = mma_xy(acc_zero(), Ld + r * 256, tmp, -1.0);
+        wave_order();
+        acc_store(X + (cc * t0 + r) * 256, x);
+      }
+      wave_order();
+    }
+  }
+  for (int idx = lane; idx < 256 * t0 * t0; idx += 64) {
+    const int tile = idx / 256;
+    const int r = tile % t0, cc = tile / t0;
+    c.FLb[idx] = (r >= cc) ? B[idx] : 0.0;
+    c.FLbi[idx] = X[idx];
+  }
+  if (lane == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
+}
+
+// ----------------------------------------------------------------- solve
+// Forward: r_e -= X_R(o_l)' w_{o_l} + X_L(o_r)' w_{o_r} with w_o = L_o^-1 r_o;
+// backward: u_o = L_o^-T (w_o - X_L u_L - X_R u_R - Z_o u0).  The pair vectors
+// r, w, u are padded to 16 per pair; level 0 reads the exact right-hand side.
+struct VecLds { double v0[16], v1[16], sc[16], ua[16], ub[16]; };
+
+__device__ __forceinline__ double rvec(const BcrSolveArgs& A, int lvl, long long j) {
+  if (lvl == 0) return vec_get_exact(A.s + A.loff[j], A.c.l[j]);
+  return A.r[j * 16 + (threadIdx.x & 15)];
+}
+
+// even position k of level lvl: updates r_e; stores w and the border
+// partial Z'w of its right neighbour (each odd pair has exactly one left one).
+// All loads of the step are issued first.
+__device__ void bcr_fwd_even(const BcrSolveArgs& A, int lvl, int n, int k, VecLds& V) {
+  const BcrArgs& c = A.c;
+  const int lane = threadIdx.x & 63;
+  const long long s = 1LL << lvl, e = k * s, ol = (k - 1) * s, orr = (k + 1) * s;
+  const bool hl = k >= 1, hr = k + 1 < n;
+  const double re = rvec(A, lvl, e);
+  const double rl = hl ? rvec(A, lvl, ol) : 0.0;
+  const double rr = hr ? rvec(A, lvl, orr) : 0.0;
+  Op lil{}, xrl{}, lir{}, xlr{}, g[BT_MAXT0];
+  if (hl) {
+    lil = op_load(c.FLi + ol * 256);
+    xrl = op_load(c.FXR + ol * 256);
+  }
+  if (hr) {
+    lir = op_load(c.FLi + orr * 256);
+    xlr = op_load(c.FXL + orr * 256);
+  }
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q)
+    if (hr && q < c.t0) g[q] = op_load(c.FGt + (orr * c.t0 + q) * 256);
+  vec_put(V.v0, rl);
+  vec_put(V.ua, rr);
+  wave_order();
+  const double wl = hl ? op_mv(lil, V.v0) : 0.0;
+  const double wr = hr ? op_mv(lir, V.ua) : 0.0;
+  vec_put(V.v1, wl);
+  vec_put(V.ub, wr);
+  wave_order();
+  double acc = re;
+  if (hl) acc -= op_mtv(xrl, V.v1, V.sc);
+  if (hr) {
+    acc -= op_mtv(xlr, V.ub, V.sc);
+    if (lane < 16) A.w[orr * 16 + lane] = wr;
+#pragma unroll
+    for (int q = 0; q < BT_MAXT0; ++q)
+      if (q < c.t0) {
+        const double pq = op_mv(g[q], V.ub);
+        if (lane < 16) A.pb[(orr * c.t0 + q) * 16 + lane] = pq;
+      }
+  }
+  wave_order();
+  if (lane < 16) A.r[e * 16 + lane] = acc;
+}
+
+// the final pair (j = 0) forward: w_0 and its border partial
+__device__ void bcr_final_fwd(const BcrSolveArgs& A, int lvl, VecLds& V) {
+  const BcrArgs& c = A.c;
+  const int lane = threadIdx.x & 63;
+  const double r0 = rvec(A, lvl, 0);
+  const Op li = op_load(c.FLi);
+  Op g[BT_MAXT0];
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q)
+    if (q < c.t0) g[q] = op_load(c.FGt + q * 256);
+  vec_put(V.v0, r0);
+  wave_order();
+  const double w = op_mv(li, V.v0);
+  vec_put(V.v1, w);
+  wave_order();
+  if (lane < 16) A.w[lane] = w;
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q)
+    if (q < c.t0) {
+      const double pq = op_mv(g[q], V.v1);
+      if (lane < 16) A.pb[q * 16 + lane] = pq;
+    }
+  wave_order();
+}
+
+// u_o from w_o, the neighbours' u (L, R < 0: no such neighbour) and u0
+__device__ void bcr_bwd_pair(const BcrSolveArgs& A, long long o, long long L, long long R,
+                             const double* u0, VecLds& V) {
+  const BcrArgs& c = A.c;
+  const int lane = threadIdx.x & 63;
+  const double wv = A.w[o * 16 + (lane & 15)];
+  const double ul = L >= 0 ? A.up[L * 16 + (lane & 15)] : 0.0;
+  const double ur = R >= 0 ? A.up[R * 16 + (lane & 15)] : 0.0;
+  Op xl{}, xr{}, g[BT_MAXT0];
+  if (L >= 0) xl = op_load(c.FXL + o * 256);
+  if (R >= 0) xr = op_load(c.FXR + o * 256);
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q)
+    if (q < c.t0) g[q] = op_load(c.FGt + (o * c.t0 + q) * 256);
+  const Op li = op_load(c.FLi + o * 256);
+  vec_put(V.ua, ul);
+  vec_put(V.ub, ur);
+  wave_order();
+  double v = wv;
+  if (L >= 0) v -= op_mv(xl, V.ua);
+  if (R >= 0) v -= op_mv(xr, V.ub);
+#pragma unroll
+  for (int q = 0; q < BT_MAXT0; ++q)
+    if (q < c.t0) v -= op_mtv(g[q], u0 + 16 * q, V.sc);
+  vec_put(V.v1, v);
+  wave_order();
+  const double u = op_mtv(li, V.v1, V.sc);
+  if (lane < 16) A.up[o * 16 + lane] = u;
+  if (lane < c.l[o]) A.u[A.loff[o] + lane] = u;
+  wave_order();
+}
+
+__global__ __launch_bounds__(256) void k_bcr_fwd(BcrSolveArgs A, int lvl, int n) {
+  __shared__ VecLds V[4];
+  const int wave = threadIdx.x >> 6, w = blockIdx.x * 4 + wave;
+  if (w >= (n + 1) / 2) return;
+  bcr_fwd_even(A, lvl, n, 2 * w, V[wave]);
+}
+
+__global__ __launch_bounds__(256) void k_bcr_bwd(BcrSolveArgs A, int lvl, int n) {
+  __shared__ VecLds V[4];
+  __shared__ double u0[16 * BT_MAXT0];
+  const int wave = threadIdx.x >> 6, w = blockIdx.x * 4 + wave;
+  for (int i = threadIdx.x; i < 16 * A.c.t0; i += blockDim.x) u0[i] = A.u0p[i];
+  __syncthreads();
+  if (w >= n / 2) return;
+  const int k = 2 * w + 1;
+  const long long s = 1LL << lvl;
+  bcr_bwd_pair(A, k * s, (k - 1) * s, k + 1 < n ? (k + 1) * s : -1, u0, V[wave]);
+}
+
+// Narrow forward levels from lvl (n active pairs), the final pair, the border
+// right-hand side s0 - sum_j Z_j'w_j (fixed order), the border solve
+// w0 = Lb^-1 s0, u0 = -Lb^-T w0, the final pair backward and the narrow
+// backward levels.  One workgroup of TAIL_WAVES waves.
+__global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail_solve(BcrSolveArgs A, int lvl, int n) {
+  const BcrArgs& c = A.c;
+  __shared__ VecLds V[TAIL_WAVES];
+  __shared__ double part[64 * TAIL_WAVES];
+  __shared__ double s0[16 * BT_MAXT0], w0[16 * BT_MAXT0], u0[16 * BT_MAXT0];
+  __shared__ int lv_n[32];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, t0 = c.t0, n0 = c.n0;
+  const int lvl0 = lvl;
+  int nlev = 0;
+  for (; n > 1; ++lvl, n = (n + 1) / 2) {
+    if (threadIdx.x == 0) lv_n[nlev] = n;
+    ++nlev;
+    for (int w = wave; w < (n + 1) / 2; w += TAIL_WAVES) bcr_fwd_even(A, lvl, n, 2 * w, V[wave]);
+    __syncthreads();
+  }
+  if (n == 1 && wave == 0) bcr_final_fwd(A, lvl, V[0]);
+  __syncthreads();
+  // border right-hand side
+  const int nb = 16 * t0;
+  if (nb > 0) {
+    const int nch = (64 * TAIL_WAVES) / nb;
+    const int ch = threadIdx.x / nb, i = threadIdx.x % nb;
+    if (ch < nch) {
+      const int per = (c.P + nch - 1) / nch;
+      const int j0 = ch * per, j1 = min(c.P, j0 + per);
+      double acc = 0.0;
+      for (int j = j0; j < j1; ++j) acc += A.pb[(long long)j * nb + i];
+      part[ch * nb + i] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < nb) {
+      double acc = 0.0;
+      for (int ch2 = 0; ch2 < nch; ++ch2) acc += part[ch2 * nb + threadIdx.x];
+      s0[threadIdx.x] = (threadIdx.x < n0 ? A.s[A.nl + threadIdx.x] : 0.0) - acc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // w0 = Lbi s0, u0 = -Lbi' w0 (lower block-triangular tiles)
+      for (int rr = 0; rr < t0; ++rr) {
+        double acc = 0.0;
+        for (int cc = 0; cc <= rr; ++cc) acc += op_mv(op_load(c.FLbi + (cc * t0 + rr) * 256), s0 + 16 * cc);
+        wave_order();
+        if (lane < 16) w0[16 * rr + lane] = acc;
+        wave_order();
+      }
+      for (int cc = 0; cc < t0; ++cc) {
+        double acc = 0.0;
+        for (int rr = cc; rr < t0; ++rr)
+          acc += op_mtv(op_load(c.FLbi + (cc * t0 + rr) * 256), w0 + 16 * rr, V[0].sc);
+        if (lane < 16) {
+          u0[16 * cc + lane] = -acc;
+          A.u0p[16 * cc + lane] = -acc;
+          if (16 * cc + lane < n0) A.u[A.nl + 16 * cc + lane] = -acc;
+        }
+        wave_order();
+      }
+    }
+    __syncthreads();
+  }
+  if (c.P >= 1 && wave == 0) bcr_bwd_pair(A, 0, -1, -1, u0, V[0]);
+  __syncthreads();
+  for (int li = nlev - 1; li >= 0; --li) {
+    const int nn = lv_n[li], lv = lvl0 + li;
+    const long long s = 1LL << lv;
+    for (int w = wave; w < nn / 2; w += TAIL_WAVES) {
+      const int k = 2 * w + 1;
+      bcr_bwd_pair(A, k * s, (k - 1) * s, k + 1 < nn ? (k + 1) * s : -1, u0, V[wave]);
+    }
+    __syncthreads();
+  }
+}
+
+size_t border_smem(int t0) {
+  return (size_t)(2 * t0 * t0 + t0 + 1) * 256 * sizeof(double) + 48 * sizeof(double);
+}
+
+// first level handled by the tail kernels: the first with at most TAIL_WAVES
+// eliminations
+int tail_level(int P, int* n_out) {
+  int lvl = 0, n = P;
+  while (n > 1 && n / 2 > TAIL_WAVES) {
+    ++lvl;
+    n = (n + 1) / 2;
+  }
+  *n_out = n;
+  return lvl;
+}
+
+}  // namespace
+
+bool bcr_supported(int lmax, int n0) { return lmax <= 16 && n0 <= 16 * BT_MAXT0; }
+
+void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk) {
+  if (c.P > 0) {
+    const long long tiles = (long long)c.P * (2 + c.t0);
+    hipLaunchKernelGGL(k_bcr_init, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, c);
+    int nt = 0;
+    const int lt = tail_level(c.P, &nt);
+    int n = c.P;
+    for (int lvl = 0; lvl < lt; ++lvl, n = (n + 1) / 2)
+      hipLaunchKernelGGL(k_bcr_level, dim3((n + 1) / 2), dim3(128), 0, st, c, lvl, n);
+    hipLaunchKernelGGL(k_bcr_tail, dim3(1), dim3(64 * TAIL_WAVES), 0, st, c, lt, nt);
+  }
+  if (c.n0 > 0) {
+    if (nparts > 0) hipLaunchKernelGGL(k_bcr_s00_partial, dim3(nparts), dim3(64), 0, st, c, chunk);
+    hipLaunchKernelGGL(k_bcr_border, dim3(1), dim3(256), border_smem(c.t0), st, c, nparts);
+  }
+}
+
+void launch_bcr_solve(hipStream_t st, const BcrSolveArgs& a) {
+  const int P = a.c.P;
+  int nt = 0;
+  const int lt = P > 0 ? tail_level(P, &nt) : 0;
+  int n = P;
+  for (int lvl = 0; lvl < lt; ++lvl, n = (n + 1) / 2)
+    hipLaunchKernelGGL(k_bcr_fwd, dim3(((n + 1) / 2 + 3) / 4), dim3(256), 0, st, a, lvl, n);
+  hipLaunchKernelGGL(k_bcr_tail_solve, dim3(1), dim3(64 * TAIL_WAVES), 0, st, a, lt, P > 0 ? nt : 0);
+  // wide backward levels, last to first
+  for (int lvl = lt - 1; lvl >= 0; --lvl) {
+    int nl = P;
+    for (int v = 0; v < lvl; ++v) nl = (nl + 1) / 2;
+    hipLaunchKernelGGL(k_bcr_bwd, dim3((nl / 2 + 3) / 4), dim3(256), 0, st, a, lvl, nl);
+  }
+}
+
+void set_bcr_smem_limits() {
+  hipFuncSetAttribute((const void*)k_bcr_border, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)border_smem(BT_MAXT0));
+}
+
+}  // namespace ahlp

@@ -70,36 +70,35 @@ constexpr int SEGRHS_STRIDE = 2 * LMAX + N0MAX;
 
 
 // Tile path (pairs of at most 16 rows, at most 64 linking variables).
-struct FChainArgs {
-  int P, G, n0, t0;
+// Block cyclic reduction of T and the border (k_bcr.hip), pairs of <= 16 rows,
+// n0 <= 64.  Tiles are 16x16 column-major, padded.
+struct BcrArgs {
+  int P, n0, t0;
   const int* l;
   const long long* tdoff;
   const long long* tooff;
   const long long* eoff;
-  const int2* seg;
   const double* Td; const double* To; const double* E; const double* S00; const double* thrT;
-  double* FLi; double* FYn; double* FZ; double* FGt; double* FSub;
-  double* FLb; double* FLbi;
-  double* segout;          // per segment: fchain_seg_stride() doubles
-  double* s00part;         // per chunk of pairs: t0*t0 tiles
+  double* BD; double* BC; double* BEt;            // working tiles (P, P, P*t0)
+  double* FLi; double* FXL; double* FXR; double* FGt;   // factor tiles (P, P, P, P*t0)
+  double* FLb; double* FLbi;                      // border factor, t0*t0 tiles each
+  double* s00part;                                // per chunk of pairs: t0*t0 tiles
   DevInfo* info;
 };
-struct FChainSolveArgs {
-  FChainArgs c;
+struct BcrSolveArgs {
+  BcrArgs c;
   const long long* loff;
   long long nl;
-  const double* s;
-  double* w;
-  double* u;
-  double* segrhs;          // per segment: fchain_segrhs_stride() doubles
+  const double* s;       // right-hand side (exact pair layout, then n0 border values)
+  double* u;             // solution, same layout
+  double* r; double* w; double* up;   // padded pair vectors, 16 per pair
+  double* pb;            // border partials Z_j' w_j, 16*t0 per pair
+  double* u0p;           // border solution, 16*t0
 };
-bool fchain_supported(int lmax, int n0);
-int fchain_seg_stride();
-int fchain_segrhs_stride();
-void launch_fchain_factor(hipStream_t st, const FChainArgs& c, int nparts, int chunk);
-void launch_fchain_solve(hipStream_t st, const FChainSolveArgs& a);
-int fchain_max_segment();
-void set_fchain_smem_limits(size_t bytes);
+bool bcr_supported(int lmax, int n0);
+void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk);
+void launch_bcr_solve(hipStream_t st, const BcrSolveArgs& a);
+void set_bcr_smem_limits();
 
 size_t chain_factor_smem(int lmax, int n0);
 void launch_chain_factor(hipStream_t st, const ChainArgs& c);

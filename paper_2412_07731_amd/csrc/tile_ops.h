@@ -1,0 +1,138 @@
+// One-wave operations on 16x16 FP64 tiles (column-major, 256 doubles) and on
+// 16-vectors, built on the 16x16x4 FP64 MFMA.
+//
+// Operand layout of v_mfma_f64_16x16x4f64: for the s-th of four K-steps lane l
+// supplies A(l%16, 4s + l/16) and B(4s + l/16, l%16); for a column-major tile X
+// these are X[64 s + l] (A = X) and X[(l%16)*16 + 4s + l/16] (B = X).  The
+// accumulator holds element (acc_row(l, r), l%16) in register r.
+#pragma once
+
+#include "common.h"
+#include "tile_chol.h"
+
+namespace ahlp {
+
+struct Op { double v[4]; };   // a tile as an A operand: element 64 s + lane
+
+__device__ __forceinline__ Op op_load(const double* t) {
+  const int lane = threadIdx.x & 63;
+  Op o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[64 * s + lane];
+  return o;
+}
+__device__ __forceinline__ d4 acc_zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ d4 acc_load(const double* t) {
+  const int lane = threadIdx.x & 63;
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) a[r] = t[acc_index<double>(lane, r)];
+  return a;
+}
+__device__ __forceinline__ void acc_store(double* t, d4 a) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[acc_index<double>(lane, r)] = a[r];
+}
+// padded tile of an exact column-major block (rows x cols, leading dimension
+// ld); identity on the padded part of the diagonal if diag
+__device__ __forceinline__ d4 acc_load_exact(const double* src, int rows, int cols, int ld,
+                                             bool diag) {
+  const int lane = threadIdx.x & 63;
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = acc_row<double>(lane, r), j = lane & 15;
+    double v = 0.0;
+    if (i < rows && j < cols) v = src[i + j * ld];
+    else if (diag && i == j) v = 1.0;
+    a[r] = v;
+  }
+  return a;
+}
+// transposed padded tile: element (i, j) = src[j + i*ld], i < rows, j < cols
+__device__ __forceinline__ d4 acc_load_exact_t(const double* src, int rows, int cols, int ld) {
+  const int lane = threadIdx.x & 63;
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = acc_row<double>(lane, r), j = lane & 15;
+    a[r] = (i < rows && j < cols) ? src[j + i * ld] : 0.0;
+  }
+  return a;
+}
+// acc += alpha X Y'
+__device__ __forceinline__ d4 mma_xyt(d4 acc, const double* X, const double* Y, double alpha) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma(alpha * X[64 * s + lane], Y[64 * s + lane], acc);
+  return acc;
+}
+// acc += alpha X Y
+__device__ __forceinline__ d4 mma_xy(d4 acc, const double* X, const double* Y, double alpha) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    acc = mfma(alpha * X[64 * s + lane], Y[(lane & 15) * TS + 4 * s + (lane >> 4)], acc);
+  return acc;
+}
+// acc += alpha X' Y
+__device__ __forceinline__ d4 mma_txy(d4 acc, const double* X, const double* Y, double alpha) {
+  const int lane = threadIdx.x & 63;
+  const int idx = (lane & 15) * TS + (lane >> 4);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma(alpha * X[idx + 4 * s], Y[idx + 4 * s], acc);
+  return acc;
+}
+__device__ __forceinline__ void tile_copy(double* dst, const double* src) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) dst[64 * s + lane] = src[64 * s + lane];
+}
+
+// y = X v (v: 16 values in LDS); every lane returns y[lane % 16]
+__device__ __forceinline__ double op_mv(const Op& X, const double* v) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s += X.v[k] * v[4 * k + (lane >> 4)];
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  return s;
+}
+// y = X' v (v: 16 values in LDS, sc: 16 values of LDS scratch); every lane
+// returns y[lane % 16]
+__device__ __forceinline__ double op_mtv(const Op& X, const double* v, double* sc) {
+  const int lane = threadIdx.x & 63;
+  const double vi = v[lane & 15];
+  double out[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double x = X.v[s] * vi;
+    x += __shfl_xor(x, 1);
+    x += __shfl_xor(x, 2);
+    x += __shfl_xor(x, 4);
+    x += __shfl_xor(x, 8);
+    out[s] = x;
+  }
+  wave_order();
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) sc[4 * s + (lane >> 4)] = out[s];
+  }
+  wave_order();
+  const double r = sc[lane & 15];
+  wave_order();
+  return r;
+}
+__device__ __forceinline__ void vec_put(double* dst, double y) {
+  const int lane = threadIdx.x & 63;
+  if (lane < 16) dst[lane] = y;
+}
+// element lane % 16 of an exact vector of len values, zero past the end
+__device__ __forceinline__ double vec_get_exact(const double* src, int len) {
+  const int i = threadIdx.x & 15;
+  return i < len ? src[i] : 0.0;
+}
+
+}  // namespace ahlp
