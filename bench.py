@@ -44,17 +44,6 @@ def flops(inst):
     return dict(syrk=syrk, potrf=potrf, trsm=trsm, schur=schur, total=syrk + potrf + trsm + schur)
 
 
-def rows_bytes(inst):
-    """Algorithmic HBM bytes of one row pass out = base + A v over the dense
-    blocks: the solve's pass (t = r_y + A D r_hx, no x_0 columns) and the
-    residual pass (base + A x with the C_i x_0 columns)."""
-    A = 8.0 * sum(int(m) * int(n) for m, n in zip(inst.m, inst.n))
-    C = 8.0 * inst.n0 * sum(int(m) for m in inst.m)
-    x = 8.0 * sum(int(n) for n in inst.n)
-    y = 8.0 * sum(int(m) for m in inst.m)
-    return dict(solve=A + x + 2 * y, resid=A + C + x + 8.0 * inst.n0 + 2 * y)
-
-
 def kernel_source_hash(path, name):
     """sha256 of one kernel's source text (from its signature to its closing brace)."""
     src = open(path).read()
@@ -162,12 +151,11 @@ def main():
     syrk_ms = st["syrk"] / nfact
     syrk_tflops = fl["syrk"] / (syrk_ms * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if main_prec == FP32_REFINE else PEAK_FP64_TFLOPS
-    # row pass: one launch per solve plus one per residual evaluation
-    rb = rows_bytes(inst)
+    # row passes: the library sums each timed launch's algorithmic bytes (A, the
+    # C columns where used, vectors read and written); time from HIP events
     n_rows = max(cnt["arows"], 1)
-    n_rows_solve = cnt["solve"]
     rows_ms = st["arows"] / n_rows
-    rows_bytes_avg = (n_rows_solve * rb["solve"] + (n_rows - n_rows_solve) * rb["resid"]) / n_rows
+    rows_bytes_avg = sum(r["rows_bytes"] for r in res) / n_rows
     rows_gbs = rows_bytes_avg / (rows_ms * 1e-3) / 1e9
 
     line = {
@@ -193,10 +181,11 @@ def main():
                            "tflops": asm_tflops, "frac_of_peak": asm_tflops / peak},
         "stage_ms_per_solve": {k: v / args.steps for k, v in st.items()},
         "stage_launches_per_solve": {k: v / args.steps for k, v in cnt.items()},
-        "roofline": {"kernel": "k_rows (row pass base + A v over the dense blocks)", "bound": "hbm",
+        "roofline": {"kernel": "k_rows_nv (row pass out_k = base_k + A v_k, 1-3 vectors per read of A)",
+                     "bound": "hbm",
                      "achieved": rows_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": rows_gbs / PEAK_HBM_GBS,
-                     "traffic": measured_traffic("k_rows", "n512"),
+                     "traffic": measured_traffic("k_rows_nv", "n512"),
                      "bytes_per_launch": rows_bytes_avg, "avg_launch_ms": rows_ms,
                      "launches_per_solve": n_rows / args.steps},
         "rooflines_other": [

@@ -126,6 +126,8 @@ typedef struct {
   double t_total_ms;      /* wall time of the call                                   */
   double t_stage_ms[AHLP_ST_COUNT];   /* summed device time per stage (timing=1)     */
   int32_t n_stage[AHLP_ST_COUNT];     /* number of timed launches per stage         */
+  double rows_bytes;      /* algorithmic HBM bytes of the timed row passes          */
+                          /* (AHLP_ST_AROWS): A and C read, vectors read and written */
 } ahlp_ipm_result_t;
 
 /* Fills *opts with the defaults listed above. */

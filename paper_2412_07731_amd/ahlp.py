@@ -47,7 +47,8 @@ class IpmResult(C.Structure):
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("rel_gap", C.c_double),
                 ("rel_pinf", C.c_double), ("rel_dinf", C.c_double), ("mu", C.c_double),
                 ("max_bkerr", C.c_double), ("t_total_ms", C.c_double),
-                ("t_stage_ms", C.c_double * 8), ("n_stage", C.c_int32 * 8)]
+                ("t_stage_ms", C.c_double * 8), ("n_stage", C.c_int32 * 8),
+                ("rows_bytes", C.c_double)]
 
 
 # Every exported symbol with its signature (argtypes, restype).

@@ -170,7 +170,7 @@ struct ahlp_problem_s {
   double *BD = nullptr, *BC = nullptr, *BEt = nullptr, *FLi = nullptr, *FXL = nullptr,
          *FXR = nullptr, *FGt = nullptr, *FLb = nullptr, *FLbi = nullptr, *s00part = nullptr;
   double *br = nullptr, *bw = nullptr, *bup = nullptr, *bpb = nullptr, *bu0p = nullptr;
-  DevInfo* info = nullptr;
+  DevInfo* info = nullptr;   // lives in the last slot of scal
   bool factored = false;
   int fprec = AHLP_FP64;
   double rho = 0, delta = 0;
@@ -183,16 +183,25 @@ struct ahlp_problem_s {
   // refinement / driver workspace
   double *ex = nullptr, *ey = nullptr, *ez = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;
   double *ones = nullptr, *zerosn = nullptr;
+  // predictor/corrector right-hand sides by linearity (padded v-space) and scaled vectors
+  double *ta = nullptr, *aw1 = nullptr, *aw2 = nullptr, *tc = nullptr, *w1p = nullptr,
+         *w2p = nullptr, *gc = nullptr;
   double *rp = nullptr, *rd = nullptr, *rzv = nullptr, *dxa = nullptr, *dya = nullptr,
          *dza = nullptr, *dx = nullptr, *dy = nullptr, *dz = nullptr;
   double *red_part = nullptr, *scal = nullptr;
   double* h_scal = nullptr;   // pinned host mirror of scal
   StageTimer timer;
+  double rows_bytes = 0.0;      // algorithmic bytes of the timed row passes
+  double a_bytes = 0, c_bytes = 0, xv_bytes = 0, x0_bytes = 0, yv_bytes = 0;
 };
 
 namespace {
 
 constexpr int NSCAL = 32;
+// scal slots: 0-5 residual stage, 9 |K| norm, 10-12 step lengths and mu_aff,
+// 20-28 refinement check (|r|, |e|, |d| per block row), 31 device info
+constexpr int S_AP = 10, S_AD = 11, S_MUAFF = 12, S_RN = 20, S_EN = 23, S_DN = 26;
+static_assert(sizeof(DevInfo) <= sizeof(double), "device info must fit one scal slot");
 
 ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
   DevInfo h{};
@@ -259,16 +268,24 @@ ahlp_status_t ensure_fp32(ahlp_problem_t p, hipStream_t st) {
   return AHLP_OK;
 }
 
-ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int prec, double rho,
-                        double delta, hipStream_t st) {
-  p->rho = rho;
-  p->delta = delta;
-  p->fprec = prec;
+// D-scaling of (x, z) and the info reset (a1); the factor assumes it ran.
+ahlp_status_t prep_scaling(ahlp_problem_t p, const double* x, const double* z, double rho,
+                           hipStream_t st) {
   HIPCHK(hipMemsetAsync(p->info, 0, sizeof(DevInfo), st));
   p->timer.begin(AHLP_ST_PREP);
   launch_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, rho, p->Dp, p->xs, p->zs,
               p->info);
   p->timer.end();
+  return AHLP_OK;
+}
+
+// prepped: prep_scaling already ran for this (x, z, rho)
+ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int prec, double rho,
+                        double delta, hipStream_t st, bool prepped = false) {
+  p->rho = rho;
+  p->delta = delta;
+  p->fprec = prec;
+  if (!prepped) CHK(prep_scaling(p, x, z, rho, st));
   if (prec == AHLP_FP32_REFINE) {
     CHK(ensure_fp32(p, st));
     CHK(factor_blocks<float>(p, st, p->LB32, p->LINV32, p->A32));
@@ -301,15 +318,49 @@ void solve_blocks_bwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LI
                       p->dyp);
 }
 
+// A row pass (AHLP_ST_AROWS) with its algorithmic bytes: the A tiles, the C
+// tiles if any vector takes the x_0 columns, each vector, each base read and
+// each output written (real sizes, not the tile padding).
+void rows_pass(ahlp_problem_t p, const RowsArgs& ra, hipStream_t st) {
+  p->timer.begin(AHLP_ST_AROWS);
+  launch_rows_multi(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->d0off, ra);
+  p->timer.end();
+  if (p->timer.on) {
+    bool anyC = false;
+    double b = p->a_bytes;
+    for (int k = 0; k < ra.nv; ++k) {
+      anyC = anyC || ra.with_C[k];
+      b += p->xv_bytes + (ra.with_C[k] ? p->x0_bytes : 0.0) + p->yv_bytes;
+      if (ra.base[k] && !ra.chain[k]) b += p->yv_bytes;
+    }
+    if (anyC) b += p->c_bytes;
+    p->rows_bytes += b;
+  }
+}
+void rows_pass1(ahlp_problem_t p, const double* v, const double* base, double alpha, int with_C,
+                int padded, double* out, hipStream_t st) {
+  RowsArgs ra{};
+  ra.nv = 1;
+  ra.v[0] = v; ra.base[0] = base; ra.alpha[0] = alpha; ra.out[0] = out;
+  ra.with_C[0] = with_C; ra.padded[0] = padded;
+  rows_pass(p, ra, st);
+}
+
+// tpre: precomputed t = r_y + A D rhx (padded v-space) or null; gout receives
+// g = A' dy (default p->g).
 ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
-                         double* dx, double* dy, double* dz, hipStream_t st) {
+                         double* dx, double* dy, double* dz, hipStream_t st,
+                         const double* tpre = nullptr, double* gout = nullptr) {
+  if (!gout) gout = p->g;
   const bool f32 = p->fprec == AHLP_FP32_REFINE;
   p->timer.begin(AHLP_ST_SOLVE);
   launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->xs, p->Dp, p->rhx, p->vx);
   // t_i = ry_i + A_i D_i rhx_i (padded), s_L = ry_L + F D rhx
-  p->timer.begin(AHLP_ST_AROWS);
-  launch_rows(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->vx, p->d0off, ry, 1.0, 0, 1, p->tv);
-  p->timer.end();
+  if (tpre) {
+    if (tpre != p->tv) launch_copy(st, p->vp_total, tpre, p->tv);
+  } else {
+    rows_pass1(p, p->vx, ry, 1.0, 0, 1, p->tv, st);
+  }
   launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->vx,
                   nullptr, nullptr, ry + p->mblk, 1.0, p->s);
   if (f32) solve_blocks_fwd<float>(p, st, p->LB32, p->LINV32);
@@ -333,10 +384,10 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   launch_copy(st, p->nl, p->u, dy + p->mblk);
   // dx_i = D_i (A_i' dy_i + F_i' dy_L - rhx_i);  g = A' dy
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, p->u, p->cptr, p->crow, p->cval, 2,
-              p->rhx, nullptr, p->Dp, p->g, dx);
+              p->rhx, nullptr, p->Dp, gout, dx);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
   launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, p->u, 0, nullptr, nullptr, p->x0off,
-                p->g, nullptr);
+                gout, nullptr);
   launch_copy(st, p->n0, p->u + p->nl, dx + p->x0off);
   launch_dz(st, p->n_tot, rz, p->zs, p->xs, dx, dz);
   p->timer.end();
@@ -360,15 +411,14 @@ void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
 void apply_A(ahlp_problem_t p, const double* x, const double* base, double alpha, double* out,
              hipStream_t st) {
   launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->xp, nullptr);
-  p->timer.begin(AHLP_ST_AROWS);
-  launch_rows(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->xp, p->d0off, base, alpha, 1, 0, out);
-  p->timer.end();
+  rows_pass1(p, p->xp, base, alpha, 1, 0, out, st);
   launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
                   p->xp + p->d0off, p->F0, base ? base + p->mblk : nullptr, alpha, out + p->mblk);
 }
 
 ahlp_status_t read_scal(ahlp_problem_t p, int count, hipStream_t st) {
-  HIPCHK(hipMemcpyAsync(p->h_scal, p->scal, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+  (void)count;   // the whole slot array (incl. the device info) is copied
+  HIPCHK(hipMemcpyAsync(p->h_scal, p->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   p->timer.collect();
   return AHLP_OK;
@@ -397,53 +447,96 @@ struct Reds {
   void launch(hipStream_t st) { launch_mreduce(st, m); }
 };
 
+// Refinement check of d = (dx, dy, dz) against r = (rx, ry, rz) on the
+// unregularized Newton system (p->g holds A'dy):  ex = rx - g - dz,
+// ey = ry - A dx, ez = rz - Z dx - X dz.  With w2 the same row pass also
+// forms aw2 = A (D dx dz / x) (the corrector's right-hand-side term).
+void check_pass(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
+                const double* dx, const double* dz, bool w2, hipStream_t st) {
+  p->timer.begin(AHLP_ST_RESID);
+  launch_res_x(st, p->n_tot, rx, rz, p->g, dx, dz, p->xs, p->zs, p->ex, p->ez);
+  launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, dx, p->xp, nullptr);
+  RowsArgs ra{};
+  ra.nv = 1;
+  ra.v[0] = p->xp; ra.base[0] = ry; ra.alpha[0] = -1.0; ra.out[0] = p->ey; ra.with_C[0] = 1;
+  if (w2) {
+    launch_wscaled(st, p->blk, p->N, p->n0, p->x0off, p->d0off, dx, dz, p->xs, p->Dp, p->w2p);
+    ra.nv = 2;
+    ra.v[1] = p->w2p; ra.alpha[1] = 1.0; ra.out[1] = p->aw2; ra.padded[1] = 1;
+  }
+  rows_pass(p, ra, st);
+  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
+                  p->xp + p->d0off, p->F0, ry + p->mblk, -1.0, p->ey + p->mblk);
+  p->timer.end();
+}
+
+// max-abs reductions of the check (and of r on the first check)
+void add_check_reds(ahlp_problem_t p, Reds& R, const double* rx, const double* ry,
+                    const double* rz, const double* dx, const double* dy, const double* dz,
+                    bool first) {
+  R.add(RED_MAXABS, p->n_tot, p->ex, nullptr, S_EN).add(RED_MAXABS, p->m_tot, p->ey, nullptr, S_EN + 1)
+      .add(RED_MAXABS, p->n_tot, p->ez, nullptr, S_EN + 2).add(RED_MAXABS, p->n_tot, dx, nullptr, S_DN)
+      .add(RED_MAXABS, p->m_tot, dy, nullptr, S_DN + 1).add(RED_MAXABS, p->n_tot, dz, nullptr, S_DN + 2);
+  if (first)
+    R.add(RED_MAXABS, p->n_tot, rx, nullptr, S_RN).add(RED_MAXABS, p->m_tot, ry, nullptr, S_RN + 1)
+        .add(RED_MAXABS, p->n_tot, rz, nullptr, S_RN + 2);
+}
+double check_rn(ahlp_problem_t p) {
+  const double* h = p->h_scal;
+  return std::max(h[S_RN], std::max(h[S_RN + 1], h[S_RN + 2]));
+}
+// backward error |r - K d| / (|K| |d| + |r|) from the last check in h_scal
+double check_bkerr(ahlp_problem_t p, double knorm, double rn) {
+  const double* h = p->h_scal;
+  const double en = std::max(h[S_EN], std::max(h[S_EN + 1], h[S_EN + 2]));
+  const double dn = std::max(h[S_DN], std::max(h[S_DN + 1], h[S_DN + 2]));
+  const double den = knorm * dn + rn;
+  return den > 0 ? en / den : 0.0;
+}
+
+// Iterative refinement from a checked d (its residual in ex, ey, ez):
+// d += solve(e), g += A'c_y, re-check; until the backward error is at most
+// tol or max_refine corrections were applied.
+ahlp_status_t refine(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
+                     double* dx, double* dy, double* dz, int max_refine, double tol,
+                     double knorm, double rn, bool w2, double* be, int* steps, hipStream_t st) {
+  while (*be > tol && *steps < max_refine) {
+    CHK(solve_once(p, p->ex, p->ey, p->ez, p->cx, p->cy, p->cz, st, nullptr, p->gc));
+    launch_axpy(st, p->n_tot, 1.0, p->cx, dx);
+    launch_axpy(st, p->m_tot, 1.0, p->cy, dy);
+    launch_axpy(st, p->n_tot, 1.0, p->cz, dz);
+    launch_axpy(st, p->n_tot, 1.0, p->gc, p->g);
+    check_pass(p, rx, ry, rz, dx, dz, w2, st);
+    Reds R(p);
+    add_check_reds(p, R, rx, ry, rz, dx, dy, dz, false);
+    R.launch(st);
+    CHK(read_scal(p, NSCAL, st));
+    *be = check_bkerr(p, knorm, rn);
+    ++*steps;
+  }
+  return AHLP_OK;
+}
+
 // Refined solve.  d = (dx, dy, dz) receives the result.  knorm: |K|_inf.
 ahlp_status_t solve_refined(ahlp_problem_t p, const double* rx, const double* ry,
                             const double* rz, double* dx, double* dy, double* dz, int max_refine,
                             double refine_tol, double knorm, double* bkerr, int* steps_out,
                             hipStream_t st) {
   CHK(solve_once(p, rx, ry, rz, dx, dy, dz, st));
-  int steps = 0;
   if (max_refine <= 0) {
     if (bkerr) *bkerr = -1.0;
     if (steps_out) *steps_out = 0;
     return AHLP_OK;
   }
-  double be = 0.0, rn = 0.0;
-  bool first = true;
-  while (true) {
-    p->timer.begin(AHLP_ST_RESID);
-    // e = r - K d:  ex = rx - A'dy - dz,  ey = ry - A dx,  ez = rz - Z dx - X dz
-    launch_res_x(st, p->n_tot, rx, rz, p->g, dx, dz, p->xs, p->zs, p->ex, p->ez);
-    apply_A(p, dx, ry, -1.0, p->ey, st);
-    Reds R(p);
-    R.add(RED_MAXABS, p->n_tot, p->ex, nullptr, 3).add(RED_MAXABS, p->m_tot, p->ey, nullptr, 4)
-        .add(RED_MAXABS, p->n_tot, p->ez, nullptr, 5).add(RED_MAXABS, p->n_tot, dx, nullptr, 6)
-        .add(RED_MAXABS, p->m_tot, dy, nullptr, 7).add(RED_MAXABS, p->n_tot, dz, nullptr, 8);
-    if (first)
-      R.add(RED_MAXABS, p->n_tot, rx, nullptr, 0).add(RED_MAXABS, p->m_tot, ry, nullptr, 1)
-          .add(RED_MAXABS, p->n_tot, rz, nullptr, 2);
-    R.launch(st);
-    p->timer.end();
-    CHK(read_scal(p, 9, st));
-    const double* h = p->h_scal;
-    if (first) rn = std::max(h[0], std::max(h[1], h[2]));
-    first = false;
-    const double en = std::max(h[3], std::max(h[4], h[5]));
-    const double dn = std::max(h[6], std::max(h[7], h[8]));
-    const double den = knorm * dn + rn;
-    be = den > 0 ? en / den : 0.0;
-    if (!(be > refine_tol) || steps >= max_refine) break;
-    CHK(solve_once(p, p->ex, p->ey, p->ez, p->cx, p->cy, p->cz, st));
-    launch_axpy(st, p->n_tot, 1.0, p->cx, dx);
-    launch_axpy(st, p->m_tot, 1.0, p->cy, dy);
-    launch_axpy(st, p->n_tot, 1.0, p->cz, dz);
-    // g = A' dy for the corrected direction
-    p->timer.begin(AHLP_ST_RESID);
-    apply_At(p, dy, 0, nullptr, nullptr, p->g, st);
-    p->timer.end();
-    ++steps;
-  }
+  check_pass(p, rx, ry, rz, dx, dz, false, st);
+  Reds R(p);
+  add_check_reds(p, R, rx, ry, rz, dx, dy, dz, true);
+  R.launch(st);
+  CHK(read_scal(p, NSCAL, st));
+  const double rn = check_rn(p);
+  double be = check_bkerr(p, knorm, rn);
+  int steps = 0;
+  CHK(refine(p, rx, ry, rz, dx, dy, dz, max_refine, refine_tol, knorm, rn, false, &be, &steps, st));
   if (bkerr) *bkerr = be;
   if (steps_out) *steps_out = steps;
   HIPCHK(hipGetLastError());
@@ -772,6 +865,13 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->Lbi, std::max(n0 * n0, 1)));
   CHK(M.alloc(&p->S00w, std::max(n0 * n0, 1)));
   p->fast = bcr_supported(p->lmax, n0);
+  for (int i = 0; i < N; ++i) {
+    p->a_bytes += 8.0 * p->m[i] * p->n[i];
+    p->c_bytes += 8.0 * p->m[i] * n0;
+    p->xv_bytes += 8.0 * p->n[i];
+    p->yv_bytes += 8.0 * p->m[i];
+  }
+  p->x0_bytes = 8.0 * n0;
   p->t0 = (n0 + 15) / 16;
   if (p->fast) {
     const long long Pt = std::max(P, 1);
@@ -791,7 +891,6 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   } else {
     CHK(M.alloc(&p->segout, (long long)std::max(p->G, 1) * SEG_STRIDE));
   }
-  CHK(M.alloc(&p->info, 1));
 
   CHK(M.alloc(&p->rhx, p->n_tot));
   CHK(M.alloc(&p->vx, p->dp_total));
@@ -811,6 +910,10 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (double** v : {&p->ey, &p->cy, &p->rp, &p->dya, &p->dy}) CHK(M.alloc(v, p->m_tot));
   CHK(M.alloc(&p->red_part, (long long)MAXRED * RED_PARTIALS));
   CHK(M.alloc(&p->scal, NSCAL));
+  p->info = reinterpret_cast<DevInfo*>(p->scal + NSCAL - 1);
+  for (double** v : {&p->ta, &p->aw1, &p->aw2, &p->tc}) CHK(M.alloc(v, p->vp_total));
+  for (double** v : {&p->w1p, &p->w2p}) CHK(M.alloc(v, p->dp_total));
+  CHK(M.alloc(&p->gc, p->n_tot));
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
 
   HIPCHK(hipMemcpyAsync(p->blk, p->hb.data(), sizeof(BlockInfo) * N, hipMemcpyHostToDevice, st));
@@ -900,6 +1003,7 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   p->timer.st = st;
   p->timer.on = o->timing != 0;
   p->timer.reset();
+  p->rows_bytes = 0.0;
   const long long n = p->n_tot, m = p->m_tot;
   int total_piv = 0;
   double max_bk = 0.0;
@@ -957,27 +1061,55 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   }
 
   // ---- main loop
+  // One iteration: a column pass for r_d, one row pass that forms r_p = b - A x,
+  // the predictor's t_a = r_p + A D rhx_a and A (D/x); the factorization; the
+  // predictor solve and its check (whose row pass also forms A (D dxa dza / x));
+  // the corrector's t_c = t_a - sigma mu A(D/x) + A(D dxa dza / x), which is
+  // its rhs term r_p + A D rhx_c written out by linearity (rhx = rx - rz / x);
+  // the corrector solve and check.  The host waits three times: after the
+  // residuals, after the predictor's check with its step lengths and mu_aff,
+  // and after the corrector's check with its step lengths.
   const double bn = 1.0 + p->b_inf, cn = 1.0 + p->c_inf;
   bool fp32_live = o->precision == AHLP_FP32_REFINE;
   int k = 0;
   ahlp_status_t status = AHLP_WMAXITER;
   double mu = 0, pobj = 0, dobj = 0, relgap = 0, pinf = 0, dinf = 0;
+  const DevInfo* hinfo = reinterpret_cast<const DevInfo*>(p->h_scal + NSCAL - 1);
+  const double* hs = p->h_scal;
   while (true) {
     p->timer.begin(AHLP_ST_RESID);
-    apply_A(p, x, p->b, -1.0, p->rp, st);                 // r_p = b - A x
-    apply_At(p, y, 1, p->c, z, p->rd, st);                // r_d = c - A'y - z
+    CHK(prep_scaling(p, x, z, o->rho, st));
+    apply_At(p, y, 1, p->c, z, p->rd, st);                          // r_d = c - A'y - z
+    launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);       // rz_a = -x z
+    launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, p->rd, p->rzv, p->xs, p->Dp, p->rhx,
+               p->vx);
+    launch_wscaled(st, p->blk, p->N, p->n0, p->x0off, p->d0off, nullptr, nullptr, p->xs, p->Dp,
+                   p->w1p);
+    launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->xp, nullptr);
+    {
+      RowsArgs ra{};
+      ra.nv = 3;
+      ra.v[0] = p->xp; ra.base[0] = p->b; ra.alpha[0] = -1.0; ra.out[0] = p->rp; ra.with_C[0] = 1;
+      ra.v[1] = p->vx; ra.alpha[1] = 1.0; ra.out[1] = p->ta; ra.padded[1] = 1; ra.chain[1] = 1;
+      ra.v[2] = p->w1p; ra.alpha[2] = 1.0; ra.out[2] = p->aw1; ra.padded[2] = 1;
+      rows_pass(p, ra, st);
+    }
+    launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
+                    p->xp + p->d0off, p->F0, p->b + p->mblk, -1.0, p->rp + p->mblk);
     Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, p->c, x, 1).add(RED_DOT, m, p->b, y, 2)
         .add(RED_MAXABS, m, p->rp, nullptr, 3).add(RED_MAXABS, n, p->rd, nullptr, 4)
         .add(RED_MAXSUM, n, x, z, 5).launch(st);
     p->timer.end();
-    CHK(read_scal(p, 6, st));
-    const double knorm_iter = std::max(p->colabs1_max, std::max(p->rowabs_max, p->h_scal[5]));
-    mu = p->h_scal[0] / (double)n;
-    pobj = p->h_scal[1];
-    dobj = p->h_scal[2];
+    CHK(read_scal(p, NSCAL, st));
+    if (hinfo->nonfinite)
+      return fail(AHLP_ENUMERIC, "x or z left the positive orthant or became non-finite");
+    const double knorm_iter = std::max(p->colabs1_max, std::max(p->rowabs_max, hs[5]));
+    mu = hs[0] / (double)n;
+    pobj = hs[1];
+    dobj = hs[2];
     relgap = std::fabs(pobj - dobj) / std::max(1.0, std::fabs(pobj));
-    pinf = p->h_scal[3] / bn;
-    dinf = p->h_scal[4] / cn;
+    pinf = hs[3] / bn;
+    dinf = hs[4] / cn;
     if (o->verbose)
       fprintf(stderr, "ahlp it %3d mu %.3e gap %.3e pinf %.3e dinf %.3e pobj %.10e%s\n", k, mu,
               relgap, pinf, dinf, pobj, fp32_live ? " fp32" : "");
@@ -987,55 +1119,90 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     }
     if (k >= o->max_iter) break;
     if (fp32_live && mu < o->mu_switch) fp32_live = false;
-    const int prec = fp32_live ? AHLP_FP32_REFINE : AHLP_FP64;
     if (fp32_live) R.fp32_iterations++;
-    CHK(factor_checked(x, z, prec, o->rho, o->delta));
+    CHK(do_factor(p, x, z, fp32_live ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st, true));
     const double kn = knorm_iter;
-    double be;
-    int steps;
-    // predictor.  An FP32-factored solve that cannot reach the refinement
-    // target within max_refine corrections switches the run to FP64 factors
-    // for good and is repeated.
-    launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);
-    CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine,
-                      o->refine_tol, kn, &be, &steps, st));
-    account(be, steps);
-    if (o->verbose > 1) fprintf(stderr, "ahlp   predictor bkerr %.2e refine %d\n", be, steps);
-    if (fp32_live && be > o->refine_tol) {
-      fp32_live = false;
-      R.fp32_iterations--;
-      if (o->verbose) fprintf(stderr, "ahlp   FP32 refinement stalled (%.2e): FP64 from here\n", be);
-      CHK(factor_checked(x, z, AHLP_FP64, o->rho, o->delta));
-      CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine,
-                        o->refine_tol, kn, &be, &steps, st));
-      account(be, steps);
+    double be = 0.0;
+    int steps = 0;
+
+    // predictor.  FP64: checked and refined.  FP32-factored: used as solved
+    // (it sets only sigma and the second-order term of the corrector); its
+    // A (D dxa dza / x) is formed by a row pass of its own.
+    CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, st, p->ta));
+    {
+      Reds Rp(p);
+      if (!fp32_live) {
+        check_pass(p, p->rd, p->rp, p->rzv, p->dxa, p->dza, true, st);
+        add_check_reds(p, Rp, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, true);
+      } else {
+        launch_wscaled(st, p->blk, p->N, p->n0, p->x0off, p->d0off, p->dxa, p->dza, p->xs, p->Dp,
+                       p->w2p);
+        rows_pass1(p, p->w2p, nullptr, 1.0, 0, 1, p->aw2, st);
+      }
+      Rp.add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
     }
-    Reds(p).add(RED_RATIO, n, x, p->dxa, 0).add(RED_RATIO, n, z, p->dza, 1).launch(st);
-    CHK(read_scal(p, 2, st));
-    const double ap_aff = std::min(1.0, p->h_scal[0]), ad_aff = std::min(1.0, p->h_scal[1]);
-    red(p, RED_MUAFF, n, x, p->dxa, 0, st, z, p->dza, ap_aff, ad_aff);
-    CHK(read_scal(p, 1, st));
-    const double mu_aff = p->h_scal[0] / (double)n;
+    auto muaff_launch = [&]() {
+      Reds Rm(p);
+      Rm.add(RED_MUAFF, n, x, p->dxa, S_MUAFF, z, p->dza);
+      Rm.m.r[0].ps1 = p->scal + S_AP;
+      Rm.m.r[0].ps2 = p->scal + S_AD;
+      Rm.launch(st);
+    };
+    muaff_launch();
+    CHK(read_scal(p, NSCAL, st));
+    if (!fp32_live) {
+      const double rn = check_rn(p);
+      be = check_bkerr(p, kn, rn);
+      if (be > o->refine_tol) {
+        CHK(refine(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine, o->refine_tol,
+                   kn, rn, true, &be, &steps, st));
+        Reds(p).add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
+        muaff_launch();
+        CHK(read_scal(p, NSCAL, st));
+      }
+      account(be, steps);
+      if (o->verbose > 1) fprintf(stderr, "ahlp   predictor bkerr %.2e refine %d\n", be, steps);
+    }
+    const double mu_aff = hs[S_MUAFF] / (double)n;
     const double sigma = std::pow(mu_aff / mu, 3.0);
+
     // corrector
-    launch_rz(st, n, 1, x, z, p->dxa, p->dza, sigma * mu, p->rzv);
-    CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine,
-                      o->refine_tol, kn, &be, &steps, st));
+    launch_rz(st, n, 1, x, z, p->dxa, p->dza, sigma * mu, p->rzv);   // rz_c
+    launch_combine(st, p->vp_total, p->ta, sigma * mu, p->aw1, p->aw2, p->tc);
+    auto corrector = [&]() -> ahlp_status_t {
+      CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, st, p->tc));
+      check_pass(p, p->rd, p->rp, p->rzv, p->dx, p->dz, false, st);
+      Reds Rc(p);
+      add_check_reds(p, Rc, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, true);
+      Rc.add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
+      CHK(read_scal(p, NSCAL, st));
+      const double rn = check_rn(p);
+      be = check_bkerr(p, kn, rn);
+      steps = 0;
+      if (be > o->refine_tol) {
+        CHK(refine(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine, o->refine_tol, kn,
+                   rn, false, &be, &steps, st));
+        Reds(p).add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
+        CHK(read_scal(p, NSCAL, st));
+      }
+      return AHLP_OK;
+    };
+    CHK(corrector());
     account(be, steps);
     if (o->verbose > 1) fprintf(stderr, "ahlp   corrector bkerr %.2e refine %d\n", be, steps);
     if (fp32_live && be > o->refine_tol) {
+      // FP32 factors could not bring the direction to the refinement target:
+      // FP64 factors from here on, and the corrector is solved again
       fp32_live = false;
       R.fp32_iterations--;
       if (o->verbose) fprintf(stderr, "ahlp   FP32 refinement stalled (%.2e): FP64 from here\n", be);
-      CHK(factor_checked(x, z, AHLP_FP64, o->rho, o->delta));
-      CHK(solve_refined(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine,
-                        o->refine_tol, kn, &be, &steps, st));
+      CHK(do_factor(p, x, z, AHLP_FP64, o->rho, o->delta, st, true));
+      CHK(corrector());
       account(be, steps);
     }
-    Reds(p).add(RED_RATIO, n, x, p->dx, 0).add(RED_RATIO, n, z, p->dz, 1).launch(st);
-    CHK(read_scal(p, 2, st));
-    const double ap = std::min(1.0, o->eta * p->h_scal[0]);
-    const double ad = std::min(1.0, o->eta * p->h_scal[1]);
+    total_piv += hinfo->pivots;
+    const double ap = std::min(1.0, o->eta * hs[S_AP]);
+    const double ad = std::min(1.0, o->eta * hs[S_AD]);
     launch_axpy(st, n, ap, p->dx, x);
     launch_axpy(st, m, ad, p->dy, y);
     launch_axpy(st, n, ad, p->dz, z);
@@ -1062,6 +1229,7 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     R.t_stage_ms[i] = p->timer.ms[i];
     R.n_stage[i] = p->timer.cnt[i];
   }
+  R.rows_bytes = p->rows_bytes;
   p->timer.on = false;
   R.t_total_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

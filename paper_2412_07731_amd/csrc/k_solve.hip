@@ -58,50 +58,76 @@ __global__ void k_rhx(const BlockInfo* __restrict__ blk, int N, int n0, long lon
 }
 
 // ------------------------------------------------------------ block rows
-// out = base + alpha * (A_i xp_i [+ C_i xp_0]) for one 16-row tile per wave.
-// Lane l reads element 64 s + l of each tile: row l%16, column 4 s + l/16.
-// padded_out: write to voff + row (rows >= m get 0); else to yoff + row, row < m.
-__global__ __launch_bounds__(256) void k_rows(const BlockInfo* __restrict__ blk,
-                                              const int2* __restrict__ rowtiles, int nrt,
-                                              const double* __restrict__ A,
-                                              const double* __restrict__ C,
-                                              const double* __restrict__ xp, long long d0off,
-                                              const double* __restrict__ base, double alpha,
-                                              int with_C, int padded_out,
-                                              double* __restrict__ out) {
+// Row pass over the dense blocks for up to RV_MAX vectors at once (A is read
+// once):  out_k = base_k + alpha_k (A_i v_k,i [+ C_i v_k,0]).
+// One 16-row tile panel per wave.  A is read in 16-byte pairs: lane l holds
+// rows 2(l%8), 2(l%8)+1 of tile columns l/8 and 8 + l/8, so a tile costs two
+// loads per lane; the partial sums are reduced over l/8.
+template <int NV>
+__global__ __launch_bounds__(256) void k_rows_nv(const BlockInfo* __restrict__ blk,
+                                                 const int2* __restrict__ rowtiles, int nrt,
+                                                 const double* __restrict__ A,
+                                                 const double* __restrict__ C, long long d0off,
+                                                 RowsArgs ra) {
   const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wt >= nrt) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, cb = lane >> 3, r2 = 2 * (lane & 7);
   const int2 rt = rowtiles[wt];
   const BlockInfo b = blk[rt.x];
   const int I = rt.y;
-  double acc = 0.0;
-  const double* xb = xp + b.dpoff;
-  const double* At = A + a_tile(b, I, 0);
-#pragma unroll 8
+  double acc[NV][2];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k][0] = acc[k][1] = 0.0;
+  const double2* At = reinterpret_cast<const double2*>(A + a_tile(b, I, 0));
+#pragma unroll 4
   for (int K = 0; K < b.nt; ++K) {
-    const double* tile = At + (long long)K * TE;
+    const double2 a0 = At[K * 128 + lane], a1 = At[K * 128 + 64 + lane];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc += tile[64 * s + lane] * xb[K * TS + 4 * s + (lane >> 4)];
-  }
-  if (with_C) {
-    const double* x0 = xp + d0off;
-    for (int Q = 0; Q < b.kt0; ++Q) {
-      const double* tile = C + c_tile(b, I, Q);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc += tile[64 * s + lane] * x0[Q * TS + 4 * s + (lane >> 4)];
+    for (int k = 0; k < NV; ++k) {
+      const double* xv = ra.v[k] + b.dpoff + K * TS;
+      const double x0 = xv[cb], x1 = xv[8 + cb];
+      acc[k][0] += a0.x * x0 + a1.x * x1;
+      acc[k][1] += a0.y * x0 + a1.y * x1;
     }
   }
-  acc += __shfl_xor(acc, 16);
-  acc += __shfl_xor(acc, 32);
-  if (lane < 16) {
-    const int row = TS * I + lane;
-    if (padded_out) {
-      double v = 0.0;
-      if (row < b.m) v = (base ? base[b.yoff + row] : 0.0) + alpha * acc;
-      out[b.voff + row] = v;
-    } else if (row < b.m) {
-      out[b.yoff + row] = (base ? base[b.yoff + row] : 0.0) + alpha * acc;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (!ra.with_C[k]) continue;
+    const double* x0v = ra.v[k] + d0off;
+    for (int Q = 0; Q < b.kt0; ++Q) {
+      const double2* ct = reinterpret_cast<const double2*>(C + c_tile(b, I, Q));
+      const double2 a0 = ct[lane], a1 = ct[64 + lane];
+      const double x0 = x0v[Q * TS + cb], x1 = x0v[Q * TS + 8 + cb];
+      acc[k][0] += a0.x * x0 + a1.x * x1;
+      acc[k][1] += a0.y * x0 + a1.y * x1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double v = acc[k][h];
+      v += __shfl_xor(v, 8);
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      acc[k][h] = v;
+    }
+  if (lane < 8) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int row = TS * I + r2 + h;
+      const bool in = row < b.m;
+      double prev = 0.0;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        double base = 0.0;
+        if (ra.chain[k]) base = prev;
+        else if (ra.base[k] && in) base = ra.base[k][b.yoff + row];
+        const double v = in ? base + ra.alpha[k] * acc[k][h] : 0.0;
+        prev = v;
+        if (ra.padded[k]) ra.out[k][b.voff + row] = v;
+        else if (in) ra.out[k][b.yoff + row] = v;
+      }
     }
   }
 }
@@ -151,36 +177,31 @@ __global__ __launch_bounds__(256) void k_cols(const BlockInfo* __restrict__ blk,
                                               double* __restrict__ out) {
   const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wt >= nct) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, cb = lane >> 3, r2 = 2 * (lane & 7);
   const int2 ct = coltiles[wt];
   const BlockInfo b = blk[ct.x];
   const int K = ct.y;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const double* yb = yp + b.voff;
+  double acc0 = 0.0, acc1 = 0.0;   // tile columns cb and 8 + cb
+  const double* yb = yp + b.voff + r2;
 #pragma unroll 8
   for (int I = 0; I < b.mt; ++I) {
-    const double* tile = A + a_tile(b, I, K);
-    const double yv = yb[I * TS + (lane & 15)];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] += tile[64 * s + lane] * yv;
+    const double2* tile = reinterpret_cast<const double2*>(A + a_tile(b, I, K));
+    const double2 a0 = tile[lane], a1 = tile[64 + lane];
+    const double2 yv = *reinterpret_cast<const double2*>(yb + I * TS);
+    acc0 += a0.x * yv.x + a0.y * yv.y;
+    acc1 += a1.x * yv.x + a1.y * yv.y;
   }
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    double v = acc[s];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 8);
-    acc[s] = v;
+  for (int sft = 1; sft < 8; sft <<= 1) {
+    acc0 += __shfl_xor(acc0, sft);
+    acc1 += __shfl_xor(acc1, sft);
   }
-  // lane 16*g holds column 4 s + g of the tile
-  if ((lane & 15) == 0) {
-    const int gidx = lane >> 4;
+  if ((lane & 7) == 0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int col = TS * K + 4 * s + gidx;
+    for (int h = 0; h < 2; ++h) {
+      const int col = TS * K + cb + 8 * h;
       if (col >= b.n) continue;
-      double g = acc[s];
+      double g = h ? acc1 : acc0;
       for (int e = cptr[b.csc_off + col]; e < cptr[b.csc_off + col + 1]; ++e)
         g += cval[e] * yL[crow[e]];
       const long long o = b.xoff + col;
@@ -201,32 +222,30 @@ __global__ __launch_bounds__(256) void k_ccols(const BlockInfo* __restrict__ blk
                                                double* __restrict__ part) {
   const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wt >= nctile) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, cb = lane >> 3, r2 = 2 * (lane & 7);
   const int2 ct = ctiles[wt];
   const BlockInfo b = blk[ct.x];
   const int Q = ct.y;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc0 = 0.0, acc1 = 0.0;
+  const double* yb = yp + b.voff + r2;
 #pragma unroll 8
   for (int I = 0; I < b.mt; ++I) {
-    const double* tile = C + c_tile(b, I, Q);
-    const double yv = yp[b.voff + I * TS + (lane & 15)];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] += tile[64 * s + lane] * yv;
+    const double2* tile = reinterpret_cast<const double2*>(C + c_tile(b, I, Q));
+    const double2 a0 = tile[lane], a1 = tile[64 + lane];
+    const double2 yv = *reinterpret_cast<const double2*>(yb + I * TS);
+    acc0 += a0.x * yv.x + a0.y * yv.y;
+    acc1 += a1.x * yv.x + a1.y * yv.y;
   }
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    double v = acc[s];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 8);
-    acc[s] = v;
+  for (int sft = 1; sft < 8; sft <<= 1) {
+    acc0 += __shfl_xor(acc0, sft);
+    acc1 += __shfl_xor(acc1, sft);
   }
-  if ((lane & 15) == 0) {
+  if ((lane & 7) == 0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int col = TS * Q + 4 * s + (lane >> 4);
-      if (col < n0) part[(long long)ct.x * n0 + col] = acc[s];
+    for (int h = 0; h < 2; ++h) {
+      const int col = TS * Q + cb + 8 * h;
+      if (col < n0) part[(long long)ct.x * n0 + col] = h ? acc1 : acc0;
     }
   }
 }
@@ -473,6 +492,32 @@ __global__ void k_res_x(long long n, const double* __restrict__ rx, const double
   }
 }
 
+// w = D (a b) / x in padded x-space (a null: w = D / x); the x_0 part is zero.
+__global__ void k_wscaled(const BlockInfo* __restrict__ blk, int N, int n0, long long x0off,
+                          long long d0off, const double* __restrict__ a,
+                          const double* __restrict__ b, const double* __restrict__ xs,
+                          const double* __restrict__ Dp, double* __restrict__ w) {
+  const int i = blockIdx.x;
+  long long xo, po;
+  int n, np;
+  if (i < N) { xo = blk[i].xoff; po = blk[i].dpoff; n = blk[i].n; np = TS * blk[i].nt; }
+  else { xo = x0off; po = d0off; n = 0; np = (n0 + TS - 1) / TS * TS; }
+  for (int c = threadIdx.x; c < np; c += blockDim.x) {
+    double v = 0.0;
+    if (c < n) v = Dp[po + c] * (a ? a[xo + c] * b[xo + c] : 1.0) / xs[xo + c];
+    w[po + c] = v;
+  }
+}
+
+// out = t - smu a + b
+__global__ void k_combine(long long n, const double* __restrict__ t, double smu,
+                          const double* __restrict__ a, const double* __restrict__ b,
+                          double* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (t[i] - smu * a[i]) + b[i];
+}
+
 // Copy x0 part of the Schur solution into dx.
 __global__ void k_copy(long long n, const double* __restrict__ src, double* __restrict__ dst) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -579,6 +624,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_mreduce1(MultiRed m) {
   const long long chunk = (r.n + gridDim.x - 1) / gridDim.x;
   const long long lo = blockIdx.x * chunk;
   const long long hi = lo + chunk < r.n ? lo + chunk : r.n;
+  const double s1 = r.ps1 ? fmin(1.0, *r.ps1) : r.s1;
+  const double s2 = r.ps2 ? fmin(1.0, *r.ps2) : r.s2;
   double v = red_identity(r.op);
   for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     double t;
@@ -586,7 +633,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_mreduce1(MultiRed m) {
       case 0: t = r.a[i] * r.b[i]; break;
       case 1: t = fabs(r.a[i]); break;
       case 2: t = (r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY; break;
-      case 3: t = (r.a[i] + r.s1 * r.b[i]) * (r.c[i] + r.s2 * r.d[i]); break;
+      case 3: t = (r.a[i] + s1 * r.b[i]) * (r.c[i] + s2 * r.d[i]); break;
       case 4: t = r.a[i] + r.b[i]; break;
       default: t = r.a[i]; break;
     }
@@ -623,6 +670,16 @@ void launch_pad_x(hipStream_t st, const BlockInfo* blk, int N, int n0, long long
                   long long d0off, const double* x, double* xp, const double* scale) {
   hipLaunchKernelGGL(k_pad_x, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, xp, scale);
 }
+void launch_wscaled(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                    long long d0off, const double* a, const double* b, const double* xs,
+                    const double* Dp, double* w) {
+  hipLaunchKernelGGL(k_wscaled, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, a, b, xs,
+                     Dp, w);
+}
+void launch_combine(hipStream_t st, long long n, const double* t, double smu, const double* a,
+                    const double* b, double* out) {
+  hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, st, n, t, smu, a, b, out);
+}
 void launch_pad_y(hipStream_t st, const BlockInfo* blk, int N, const double* y, double* yp) {
   hipLaunchKernelGGL(k_pad_y, dim3(N), dim3(256), 0, st, blk, y, yp);
 }
@@ -632,11 +689,21 @@ void launch_rhx(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x
   hipLaunchKernelGGL(k_rhx, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, rx, rz, xs,
                      Dp, rhx, vx);
 }
+void launch_rows_multi(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
+                       const double* A, const double* C, long long d0off, const RowsArgs& ra) {
+  const dim3 g((nrt + 3) / 4), b(256);
+  if (ra.nv == 1) hipLaunchKernelGGL(k_rows_nv<1>, g, b, 0, st, blk, rowtiles, nrt, A, C, d0off, ra);
+  else if (ra.nv == 2) hipLaunchKernelGGL(k_rows_nv<2>, g, b, 0, st, blk, rowtiles, nrt, A, C, d0off, ra);
+  else hipLaunchKernelGGL(k_rows_nv<3>, g, b, 0, st, blk, rowtiles, nrt, A, C, d0off, ra);
+}
 void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
                  const double* A, const double* C, const double* xp, long long d0off,
                  const double* base, double alpha, int with_C, int padded_out, double* out) {
-  hipLaunchKernelGGL(k_rows, dim3((nrt + 3) / 4), dim3(256), 0, st, blk, rowtiles, nrt, A, C, xp,
-                     d0off, base, alpha, with_C, padded_out, out);
+  RowsArgs ra{};
+  ra.nv = 1;
+  ra.v[0] = xp; ra.base[0] = base; ra.alpha[0] = alpha; ra.out[0] = out;
+  ra.with_C[0] = with_C; ra.padded[0] = padded_out; ra.chain[0] = 0;
+  launch_rows_multi(st, blk, rowtiles, nrt, A, C, d0off, ra);
 }
 void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int n0, const int* lsz,
                      const long long* loff, const int* lptr, const int* lcol,

@@ -112,6 +112,28 @@ void launch_pad_y(hipStream_t st, const BlockInfo* blk, int N, const double* y, 
 void launch_rhx(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
                 long long d0off, const double* rx, const double* rz, const double* xs,
                 const double* Dp, double* rhx, double* vx);
+// Row pass for up to RV_MAX vectors (one read of A):
+//   out_k = base_k + alpha_k (A_i v_k [+ C_i v_k,0]);  chain_k: base_k = output k-1 (same row)
+constexpr int RV_MAX = 3;
+struct RowsArgs {
+  int nv;
+  const double* v[RV_MAX];      // padded x-space vectors (x_0 part at d0off)
+  const double* base[RV_MAX];   // canonical y-space base, or null
+  double alpha[RV_MAX];
+  double* out[RV_MAX];
+  int with_C[RV_MAX];           // include the C_i x_0 columns
+  int padded[RV_MAX];           // output in padded v-space (rows >= m_i set to 0) or canonical
+  int chain[RV_MAX];
+};
+// w = D (a b) / x (padded x-space; a, b canonical, null a: w = D / x); x_0 part zero
+void launch_wscaled(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                    long long d0off, const double* a, const double* b, const double* xs,
+                    const double* Dp, double* w);
+// out = t - smu * a + b over n values
+void launch_combine(hipStream_t st, long long n, const double* t, double smu, const double* a,
+                    const double* b, double* out);
+void launch_rows_multi(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
+                       const double* A, const double* C, long long d0off, const RowsArgs& ra);
 void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
                  const double* A, const double* C, const double* xp, long long d0off,
                  const double* base, double alpha, int with_C, int padded_out, double* out);
@@ -162,8 +184,10 @@ struct RedSpec {
   long long n;
   const double* a; const double* b; const double* c; const double* d;
   double s1, s2;
+  const double* ps1;     // if set (op RED_MUAFF): s1 = min(1, *ps1), s2 = min(1, *ps2),
+  const double* ps2;     // read from the device (results of an earlier reduction)
 };
-constexpr int MAXRED = 10;
+constexpr int MAXRED = 12;
 struct MultiRed {
   int nred;
   RedSpec r[MAXRED];
