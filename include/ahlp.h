@@ -99,6 +99,11 @@ typedef struct {
   int32_t start;          /* 0 = Mehrotra starting point, 1 = use x, y, z as given    */
   int32_t verbose;        /* 1 = one log line per iteration on stderr                */
   int32_t timing;         /* 1 = record per-stage device times (HIP events)          */
+  double fp32_accept;     /* FP32 mode: a direction from FP32 factors is accepted      */
+                          /* once |r - K d|_inf <= fp32_accept * mu (inexact Newton;   */
+                          /* 0.1; 0 = only the refine_tol backward error).  FP32 that   */
+                          /* cannot reach either test switches the run to FP64 and     */
+                          /* the iteration is redone with FP64 factors.                */
 } ahlp_ipm_opts_t;
 
 /* Stage indices of ahlp_ipm_result_t.t_stage_ms / n_stage. */

@@ -38,7 +38,8 @@ class IpmOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("eta", C.c_double),
                 ("rho", C.c_double), ("delta", C.c_double), ("max_refine", C.c_int32),
                 ("refine_tol", C.c_double), ("precision", C.c_int), ("mu_switch", C.c_double),
-                ("start", C.c_int32), ("verbose", C.c_int32), ("timing", C.c_int32)]
+                ("start", C.c_int32), ("verbose", C.c_int32), ("timing", C.c_int32),
+                ("fp32_accept", C.c_double)]
 
 
 class IpmResult(C.Structure):

@@ -494,13 +494,22 @@ double check_bkerr(ahlp_problem_t p, double knorm, double rn) {
   return den > 0 ? en / den : 0.0;
 }
 
+double check_en(ahlp_problem_t p) {
+  const double* h = p->h_scal;
+  return std::max(h[S_EN], std::max(h[S_EN + 1], h[S_EN + 2]));
+}
+
 // Iterative refinement from a checked d (its residual in ex, ey, ez):
 // d += solve(e), g += A'c_y, re-check; until the backward error is at most
-// tol or max_refine corrections were applied.
+// tol (or the residual at most abs_tol, if abs_tol > 0) or max_refine
+// corrections were applied.  With stagnate, a correction that reduces the
+// backward error by less than 10x ends the loop.
 ahlp_status_t refine(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
                      double* dx, double* dy, double* dz, int max_refine, double tol,
-                     double knorm, double rn, bool w2, double* be, int* steps, hipStream_t st) {
-  while (*be > tol && *steps < max_refine) {
+                     double knorm, double rn, bool w2, double* be, int* steps, hipStream_t st,
+                     double abs_tol = 0.0, bool stagnate = false) {
+  while (*be > tol && !(abs_tol > 0.0 && check_en(p) <= abs_tol) && *steps < max_refine) {
+    const double be_prev = *be;
     CHK(solve_once(p, p->ex, p->ey, p->ez, p->cx, p->cy, p->cz, st, nullptr, p->gc));
     launch_axpy(st, p->n_tot, 1.0, p->cx, dx);
     launch_axpy(st, p->m_tot, 1.0, p->cy, dy);
@@ -513,6 +522,7 @@ ahlp_status_t refine(ahlp_problem_t p, const double* rx, const double* ry, const
     CHK(read_scal(p, NSCAL, st));
     *be = check_bkerr(p, knorm, rn);
     ++*steps;
+    if (stagnate && !(*be <= 0.1 * be_prev)) break;
   }
   return AHLP_OK;
 }
@@ -573,6 +583,7 @@ void ahlp_ipm_default_opts(ahlp_ipm_opts_t* o) {
   o->start = 0;
   o->verbose = 0;
   o->timing = 0;
+  o->fp32_accept = 0.1;
 }
 
 ahlp_status_t ahlp_problem_destroy(ahlp_problem_t p) {
@@ -1119,87 +1130,99 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     }
     if (k >= o->max_iter) break;
     if (fp32_live && mu < o->mu_switch) fp32_live = false;
-    if (fp32_live) R.fp32_iterations++;
-    CHK(do_factor(p, x, z, fp32_live ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st, true));
     const double kn = knorm_iter;
-    double be = 0.0;
-    int steps = 0;
 
-    // predictor.  FP64: checked and refined.  FP32-factored: used as solved
-    // (it sets only sigma and the second-order term of the corrector); its
-    // A (D dxa dza / x) is formed by a row pass of its own.
-    CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, st, p->ta));
-    {
-      Reds Rp(p);
-      if (!fp32_live) {
-        check_pass(p, p->rd, p->rp, p->rzv, p->dxa, p->dza, true, st);
+    // One predictor-corrector pass with FP64 or FP32 factors.  A direction is
+    // accepted at backward error <= refine_tol; with FP32 factors also at
+    // |r - K d| <= fp32_accept * mu (inexact Newton).  Otherwise it is refined;
+    // FP32 refinement that stagnates or runs out sets *ok = false.
+    auto pass = [&](bool f32, bool* ok) -> ahlp_status_t {
+      *ok = true;
+      CHK(do_factor(p, x, z, f32 ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st, true));
+      const double atol = f32 ? o->fp32_accept * mu : 0.0;
+      auto acceptable = [&](double b) {
+        return b <= o->refine_tol || (atol > 0.0 && check_en(p) <= atol);
+      };
+      double be = 0.0;
+      int steps = 0;
+      // predictor (rz_a = -x z; t_a from the residual pass)
+      launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);
+      CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, st, p->ta));
+      check_pass(p, p->rd, p->rp, p->rzv, p->dxa, p->dza, true, st);
+      auto muaff_launch = [&]() {
+        Reds Rm(p);
+        Rm.add(RED_MUAFF, n, x, p->dxa, S_MUAFF, z, p->dza);
+        Rm.m.r[0].ps1 = p->scal + S_AP;
+        Rm.m.r[0].ps2 = p->scal + S_AD;
+        Rm.launch(st);
+      };
+      {
+        Reds Rp(p);
         add_check_reds(p, Rp, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, true);
-      } else {
-        launch_wscaled(st, p->blk, p->N, p->n0, p->x0off, p->d0off, p->dxa, p->dza, p->xs, p->Dp,
-                       p->w2p);
-        rows_pass1(p, p->w2p, nullptr, 1.0, 0, 1, p->aw2, st);
+        Rp.add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
+        muaff_launch();
       }
-      Rp.add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
-    }
-    auto muaff_launch = [&]() {
-      Reds Rm(p);
-      Rm.add(RED_MUAFF, n, x, p->dxa, S_MUAFF, z, p->dza);
-      Rm.m.r[0].ps1 = p->scal + S_AP;
-      Rm.m.r[0].ps2 = p->scal + S_AD;
-      Rm.launch(st);
-    };
-    muaff_launch();
-    CHK(read_scal(p, NSCAL, st));
-    if (!fp32_live) {
-      const double rn = check_rn(p);
+      CHK(read_scal(p, NSCAL, st));
+      double rn = check_rn(p);
       be = check_bkerr(p, kn, rn);
-      if (be > o->refine_tol) {
+      if (!acceptable(be)) {
         CHK(refine(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine, o->refine_tol,
-                   kn, rn, true, &be, &steps, st));
+                   kn, rn, true, &be, &steps, st, atol, f32));
+        if (f32 && !acceptable(be)) {
+          refine_total += steps;   // spent, although the pass is redone in FP64
+          *ok = false;
+          return AHLP_OK;
+        }
         Reds(p).add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
         muaff_launch();
         CHK(read_scal(p, NSCAL, st));
       }
       account(be, steps);
       if (o->verbose > 1) fprintf(stderr, "ahlp   predictor bkerr %.2e refine %d\n", be, steps);
-    }
-    const double mu_aff = hs[S_MUAFF] / (double)n;
-    const double sigma = std::pow(mu_aff / mu, 3.0);
-
-    // corrector
-    launch_rz(st, n, 1, x, z, p->dxa, p->dza, sigma * mu, p->rzv);   // rz_c
-    launch_combine(st, p->vp_total, p->ta, sigma * mu, p->aw1, p->aw2, p->tc);
-    auto corrector = [&]() -> ahlp_status_t {
+      const double mu_aff = hs[S_MUAFF] / (double)n;
+      const double sigma = std::pow(mu_aff / mu, 3.0);
+      // corrector: rz_c and t_c = t_a - sigma mu A(D/x) + A(D dxa dza / x)
+      launch_rz(st, n, 1, x, z, p->dxa, p->dza, sigma * mu, p->rzv);
+      launch_combine(st, p->vp_total, p->ta, sigma * mu, p->aw1, p->aw2, p->tc);
       CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, st, p->tc));
       check_pass(p, p->rd, p->rp, p->rzv, p->dx, p->dz, false, st);
-      Reds Rc(p);
-      add_check_reds(p, Rc, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, true);
-      Rc.add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
+      {
+        Reds Rc(p);
+        add_check_reds(p, Rc, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, true);
+        Rc.add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
+      }
       CHK(read_scal(p, NSCAL, st));
-      const double rn = check_rn(p);
+      rn = check_rn(p);
       be = check_bkerr(p, kn, rn);
       steps = 0;
-      if (be > o->refine_tol) {
+      if (!acceptable(be)) {
         CHK(refine(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine, o->refine_tol, kn,
-                   rn, false, &be, &steps, st));
+                   rn, false, &be, &steps, st, atol, f32));
+        if (f32 && !acceptable(be)) {
+          refine_total += steps;   // spent, although the pass is redone in FP64
+          *ok = false;
+          return AHLP_OK;
+        }
         Reds(p).add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
         CHK(read_scal(p, NSCAL, st));
       }
+      account(be, steps);
+      if (o->verbose > 1) fprintf(stderr, "ahlp   corrector bkerr %.2e refine %d\n", be, steps);
       return AHLP_OK;
     };
-    CHK(corrector());
-    account(be, steps);
-    if (o->verbose > 1) fprintf(stderr, "ahlp   corrector bkerr %.2e refine %d\n", be, steps);
-    if (fp32_live && be > o->refine_tol) {
-      // FP32 factors could not bring the direction to the refinement target:
-      // FP64 factors from here on, and the corrector is solved again
-      fp32_live = false;
-      R.fp32_iterations--;
-      if (o->verbose) fprintf(stderr, "ahlp   FP32 refinement stalled (%.2e): FP64 from here\n", be);
-      CHK(do_factor(p, x, z, AHLP_FP64, o->rho, o->delta, st, true));
-      CHK(corrector());
-      account(be, steps);
+    bool ok = false;
+    if (fp32_live) {
+      CHK(pass(true, &ok));
+      if (ok) {
+        R.fp32_iterations++;
+      } else {
+        // FP32 factors cannot deliver acceptable directions any more: FP64
+        // factors from here on, and this iteration is redone with them
+        fp32_live = false;
+        if (o->verbose) fprintf(stderr, "ahlp   FP32 refinement stalled: FP64 from here\n");
+      }
     }
+    if (!ok) CHK(pass(false, &ok));
     total_piv += hinfo->pivots;
     const double ap = std::min(1.0, o->eta * hs[S_AP]);
     const double ad = std::min(1.0, o->eta * hs[S_AD]);
