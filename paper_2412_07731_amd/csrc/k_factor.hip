@@ -47,6 +47,13 @@ __global__ void k_prep(const BlockInfo* __restrict__ blk, int N, int n0, long lo
   if (bad) atomicOr(&info->nonfinite, 1);
 }
 
+template <typename T>
+__device__ __forceinline__ void tile_copy_t(T* __restrict__ dst, const T* __restrict__ src) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) dst[64 * s + lane] = src[64 * s + lane];
+}
+
 // ---------------------------------------------------------------- a2: SYRK
 // One 64x64 lower macro tile of one block per workgroup (4 waves, each 32x32 =
 // 2x2 MFMA tiles).  A-row panels are staged through LDS (double buffered); D
@@ -272,6 +279,161 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
   if (tid == 0 && cnt) atomicAdd(&info->pivots, cnt);
 }
 
+// Panel form of the same factorization for bordered blocks of at most
+// BF_RMAX*4 tile rows: left-looking by panels of BF_PW tile columns held in
+// registers (4 waves, panel rows dealt round-robin, at most BF_RMAX per wave).
+// The update of a panel by each earlier tile column k reads L(r, k) for the
+// wave's rows and L(c, k) for the panel columns, all issued together.  The panel is then factored
+// column by column: Cholesky of the diagonal tile (its owner wave), the rows
+// below times L_cc^-T (through a per-wave LDS conversion to operand layout),
+// and the next panel column updated from an LDS copy of the new column.
+// Two workgroups share a CU, so one block's tile Cholesky overlaps the
+// other's MFMA work.
+constexpr int BF_PW = 2, BF_RMAX = 5;
+template <typename T>
+struct BfOp { T v[4]; };
+template <typename T>
+__device__ __forceinline__ BfOp<T> bf_ld(const T* __restrict__ t) {
+  const int lane = threadIdx.x & 63;
+  BfOp<T> o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[64 * s + lane];
+  return o;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
+                                                               T* __restrict__ LB,
+                                                               T* __restrict__ LINV,
+                                                               DevInfo* info) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BlockInfo b = blk[blockIdx.x];
+  const int mt = b.mt, rt = b.rt;
+  T* colbuf = reinterpret_cast<T*>(smem_raw);          // rt tiles: the panel column just factored
+  T* li = colbuf + (size_t)rt * TE;                     // L_cc^-1
+  T* dt = li + TE;                                      // diagonal tile / its factor
+  T* scr = dt + TE;                                     // 4 tiles: per-wave conversion
+  T* xbuf = scr + 4 * TE;                               // 48 values: tile Cholesky
+  __shared__ double s_max[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  typedef typename Acc<T>::type AT;
+
+  double md = 0.0;
+  for (int idx = tid; idx < b.m; idx += blockDim.x) {
+    const int p = idx >> 4, i = idx & 15;
+    md = fmax(md, (double)LB[lb_tile(b, p, p) + i * 17]);
+  }
+  for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off));
+  if (lane == 0) s_max[w] = md;
+  __syncthreads();
+  const double thr = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
+  int cnt = 0;
+  T* myscr = scr + w * TE;
+
+  for (int c0 = 0; c0 < mt; c0 += BF_PW) {
+    const int pw = min(BF_PW, mt - c0);
+    // rows r = c0 + w + 4 t of this panel owned by the wave
+    AT acc[BF_RMAX][BF_PW];
+#pragma unroll
+    for (int t = 0; t < BF_RMAX; ++t) {
+      const int r = c0 + w + 4 * t;
+#pragma unroll
+      for (int j = 0; j < BF_PW; ++j) {
+        acc[t][j] = AT{0, 0, 0, 0};
+        if (r < rt && j < pw && r >= c0 + j) {
+          const T* src = LB + lb_tile(b, r, c0 + j);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[t][j][k] = src[acc_index<T>(lane, k)];
+        }
+      }
+    }
+    // left-looking update with the tile columns before the panel (all loads
+    // of a step issued together)
+    for (int k = 0; k < c0; ++k) {
+      BfOp<T> Ac[BF_RMAX], Bc[BF_PW];
+#pragma unroll
+      for (int t = 0; t < BF_RMAX; ++t) {
+        const int r = c0 + w + 4 * t;
+        if (r < rt) Ac[t] = bf_ld<T>(LB + lb_tile(b, r, k));
+      }
+#pragma unroll
+      for (int j = 0; j < BF_PW; ++j)
+        if (j < pw) Bc[j] = bf_ld<T>(LB + lb_tile(b, c0 + j, k));
+#pragma unroll
+      for (int t = 0; t < BF_RMAX; ++t) {
+        const int r = c0 + w + 4 * t;
+#pragma unroll
+        for (int j = 0; j < BF_PW; ++j)
+          if (r < rt && j < pw && r >= c0 + j)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[t][j] = mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
+      }
+    }
+    // factor the panel column by column
+#pragma unroll
+    for (int j = 0; j < BF_PW; ++j) {
+      if (j >= pw) break;
+      const int c = c0 + j;
+      const int ow = (c - c0) & 3, ot = (c - c0) >> 2;
+      if (w == ow) {
+#pragma unroll
+        for (int t = 0; t < BF_RMAX; ++t)
+          if (t == ot) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dt[acc_index<T>(lane, k)] = acc[t][j][k];
+          }
+        wave_order();
+        cnt += wave_chol_tile<T>(dt, dt, li, thr, xbuf);
+        tile_copy_t(LB + lb_tile(b, c, c), dt);
+        tile_copy_t(LINV + b.linvoff + (long long)c * TE, li);
+      }
+      __syncthreads();
+      // rows below: L(r, c) = acc(r, c) L_cc^-T
+      const BfOp<T> lio = bf_ld<T>(li);
+#pragma unroll
+      for (int t = 0; t < BF_RMAX; ++t) {
+        const int r = c0 + w + 4 * t;
+        if (r < rt && r > c) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) myscr[acc_index<T>(lane, k)] = acc[t][j][k];
+          wave_order();
+          const BfOp<T> x = bf_ld<T>(myscr);
+          AT l = AT{0, 0, 0, 0};
+#pragma unroll
+          for (int s = 0; s < 4; ++s) l = mfma(x.v[s], lio.v[s], l);
+          wave_order();
+          T* dst = LB + lb_tile(b, r, c);
+          T* cb = colbuf + (size_t)(r - c0) * TE;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            dst[acc_index<T>(lane, k)] = l[k];
+            cb[acc_index<T>(lane, k)] = l[k];
+          }
+        }
+      }
+      __syncthreads();
+      // the panel's later columns: acc(r, c') -= L(r, c) L(c', c)'
+#pragma unroll
+      for (int j2 = 0; j2 < BF_PW; ++j2) {
+        if (j2 <= j || j2 >= pw) continue;
+        const int c2 = c0 + j2;
+        const BfOp<T> y = bf_ld<T>(colbuf + (size_t)(c2 - c0) * TE);
+#pragma unroll
+        for (int t = 0; t < BF_RMAX; ++t) {
+          const int r = c0 + w + 4 * t;
+          if (r < rt && r >= c2) {
+            const BfOp<T> x = bf_ld<T>(colbuf + (size_t)(r - c0) * TE);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[t][j2] = mfma(-x.v[s], y.v[s], acc[t][j2]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0 && cnt) atomicAdd(&info->pivots, cnt);
+}
+
 // ---------------------------------------------------------------- a5
 // Schur contribution of block i: PQ = F D F' - X X' with X = W_i' (the
 // bordered rows of the factor), in FP64 whatever the factor precision.
@@ -435,6 +597,11 @@ template void launch_link<float>(hipStream_t, const BlockInfo*, const int2*, int
 template <typename T>
 void launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
                          T* LINV, DevInfo* info) {
+  if (max_rt <= 4 * BF_RMAX) {
+    const size_t shmem = (size_t)(max_rt + 6) * TE * sizeof(T) + 48 * sizeof(T);
+    hipLaunchKernelGGL(k_block_factor_panel<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, info);
+    return;
+  }
   const size_t shmem = (size_t)(max_rt + 1) * TE * sizeof(T);
   hipLaunchKernelGGL(k_block_factor<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, info);
 }
