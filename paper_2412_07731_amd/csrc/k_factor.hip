@@ -86,9 +86,10 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 2; ++c) acc[a][c] = AT{0, 0, 0, 0};
 
-  T regs[8];
-  double dreg = 0.0;
-  auto load = [&](int K) {
+  // two stages of A in flight: stage K is loaded during iterations K-2, K-1
+  T regs0[8], regs1[8];
+  double dreg0 = 0.0, dreg1 = 0.0;
+  auto load = [&](int K, T* regs, double& dreg) {
 #pragma unroll
     for (int tt = 0; tt < 8; ++tt) {
       if (tt < ntl) {
@@ -98,15 +99,14 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
     }
     if (tid < TS) dreg = Dp[b.dpoff + (long long)K * TS + tid];
   };
-  load(0);
-  for (int K = 0; K < b.nt; ++K) {
+  auto step = [&](int K, T* regs, double& dreg) {
     const int buf = K & 1;
 #pragma unroll
     for (int tt = 0; tt < 8; ++tt)
       if (tt < ntl) sA[buf][tt][tid] = regs[tt];
     if (tid < TS) sD[buf][tid] = dreg;
     __syncthreads();
-    if (K + 1 < b.nt) load(K + 1);
+    if (K + 2 < b.nt) load(K + 2, regs, dreg);
     if (active) {
       const T* ra0 = sA[buf][2 * wr];
       const T* ra1 = sA[buf][2 * wr + 1];
@@ -123,6 +123,12 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
         acc[1][1] = mfma(a1, b1, acc[1][1]);
       }
     }
+  };
+  load(0, regs0, dreg0);
+  if (b.nt > 1) load(1, regs1, dreg1);
+  for (int K = 0; K < b.nt; K += 2) {
+    step(K, regs0, dreg0);
+    if (K + 1 < b.nt) step(K + 1, regs1, dreg1);
   }
   if (!active) return;
 #pragma unroll
