@@ -309,8 +309,9 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
 // ------------------------------------------------------------- solve
 // One pass of Alg. 3 (no refinement).  Also leaves g = A' dy in p->g.
 template <typename T>
-void solve_blocks_fwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV) {
-  launch_block_fwd<T>(st, p->blk, p->N, p->max_rt, LB, LINV, p->tv, p->qn);
+void solve_blocks_fwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV,
+                      const double* tin) {
+  launch_block_fwd<T>(st, p->blk, p->N, p->max_rt, LB, LINV, tin, p->tv, p->qn);
 }
 template <typename T>
 void solve_blocks_bwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV, double* dy) {
@@ -356,15 +357,14 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   p->timer.begin(AHLP_ST_SOLVE);
   launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->xs, p->Dp, p->rhx, p->vx);
   // t_i = ry_i + A_i D_i rhx_i (padded), s_L = ry_L + F D rhx
-  if (tpre) {
-    if (tpre != p->tv) launch_copy(st, p->vp_total, tpre, p->tv);
-  } else {
+  if (!tpre) {
     rows_pass1(p, p->vx, ry, 1.0, 0, 1, p->tv, st);
+    tpre = p->tv;
   }
   launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->vx,
                   nullptr, nullptr, ry + p->mblk, 1.0, p->s);
-  if (f32) solve_blocks_fwd<float>(p, st, p->LB32, p->LINV32);
-  else solve_blocks_fwd<double>(p, st, p->LB, p->LINV);
+  if (f32) solve_blocks_fwd<float>(p, st, p->LB32, p->LINV32, tpre);
+  else solve_blocks_fwd<double>(p, st, p->LB, p->LINV, tpre);
   launch_schur_rhs(st, p->blk, p->N, p->n0, p->d_l, p->d_loff, p->nl, p->qn, p->rhx + p->x0off,
                    p->s);
   if (p->fast) {
@@ -381,15 +381,13 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   }
   if (f32) solve_blocks_bwd<float>(p, st, p->LB32, p->LINV32, dy);
   else solve_blocks_bwd<double>(p, st, p->LB, p->LINV, dy);
-  launch_copy(st, p->nl, p->u, dy + p->mblk);
-  // dx_i = D_i (A_i' dy_i + F_i' dy_L - rhx_i);  g = A' dy
+  // dx_i = D_i (A_i' dy_i + F_i' dy_L - rhx_i), dz = (rz - Z dx) / X;  g = A' dy
+  const DzArgs dzv{rz, p->zs, p->xs, dz};
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, p->u, p->cptr, p->crow, p->cval, 2,
-              p->rhx, nullptr, p->Dp, gout, dx);
+              p->rhx, nullptr, p->Dp, gout, dx, dzv);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
-  launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, p->u, 0, nullptr, nullptr, p->x0off,
-                gout, nullptr);
-  launch_copy(st, p->n0, p->u + p->nl, dx + p->x0off);
-  launch_dz(st, p->n_tot, rz, p->zs, p->xs, dx, dz);
+  launch_solve_tail(st, p->N, p->n0, p->nl, p->part, p->F0, p->u, p->x0off, p->mblk, gout, dx, dzv,
+                    dy);
   p->timer.end();
   HIPCHK(hipGetLastError());
   return AHLP_OK;
@@ -454,13 +452,12 @@ struct Reds {
 void check_pass(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
                 const double* dx, const double* dz, bool w2, hipStream_t st) {
   p->timer.begin(AHLP_ST_RESID);
-  launch_res_x(st, p->n_tot, rx, rz, p->g, dx, dz, p->xs, p->zs, p->ex, p->ez);
-  launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, dx, p->xp, nullptr);
+  launch_check_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->g, dx, dz, p->xs,
+                    p->zs, p->Dp, p->ex, p->ez, p->xp, w2 ? p->w2p : nullptr);
   RowsArgs ra{};
   ra.nv = 1;
   ra.v[0] = p->xp; ra.base[0] = ry; ra.alpha[0] = -1.0; ra.out[0] = p->ey; ra.with_C[0] = 1;
   if (w2) {
-    launch_wscaled(st, p->blk, p->N, p->n0, p->x0off, p->d0off, dx, dz, p->xs, p->Dp, p->w2p);
     ra.nv = 2;
     ra.v[1] = p->w2p; ra.alpha[1] = 1.0; ra.out[1] = p->aw2; ra.padded[1] = 1;
   }
@@ -1091,12 +1088,9 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     p->timer.begin(AHLP_ST_RESID);
     CHK(prep_scaling(p, x, z, o->rho, st));
     apply_At(p, y, 1, p->c, z, p->rd, st);                          // r_d = c - A'y - z
-    launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);       // rz_a = -x z
-    launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, p->rd, p->rzv, p->xs, p->Dp, p->rhx,
-               p->vx);
-    launch_wscaled(st, p->blk, p->N, p->n0, p->x0off, p->d0off, nullptr, nullptr, p->xs, p->Dp,
-                   p->w1p);
-    launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->xp, nullptr);
+    // rz_a = -x z, rhx_a, vx = D rhx_a, w1 = D / x, xp = x (padded)
+    launch_resid_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, p->rd, p->xs, p->Dp,
+                      p->rzv, p->rhx, p->vx, p->w1p, p->xp);
     {
       RowsArgs ra{};
       ra.nv = 3;

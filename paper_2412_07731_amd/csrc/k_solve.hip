@@ -174,7 +174,8 @@ __global__ __launch_bounds__(256) void k_cols(const BlockInfo* __restrict__ blk,
                                               const double* __restrict__ zvec,
                                               const double* __restrict__ Dp,
                                               double* __restrict__ gout,
-                                              double* __restrict__ out) {
+                                              double* __restrict__ out,
+                                              const DzArgs dzv) {
   const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wt >= nct) return;
   const int lane = threadIdx.x & 63, cb = lane >> 3, r2 = 2 * (lane & 7);
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(256) void k_cols(const BlockInfo* __restrict__ blk,
       if (mode == 1) v = cvec[o] - g - zvec[o];
       else if (mode == 2) v = Dp[b.dpoff + col] * (g - cvec[o]);
       if (out) out[o] = v;
+      if (dzv.dz) dzv.dz[o] = (dzv.rz[o] - dzv.zs[o] * v) / dzv.xs[o];
     }
   }
 }
@@ -250,37 +252,6 @@ __global__ __launch_bounds__(256) void k_ccols(const BlockInfo* __restrict__ blk
   }
 }
 
-// Per-block partial sums C_i' yp_i (one workgroup per block) for the x_0 columns.
-__global__ void k_x0_partial(const BlockInfo* __restrict__ blk, int n0,
-                             const double* __restrict__ C, const double* __restrict__ yp,
-                             double* __restrict__ part) {
-  const BlockInfo b = blk[blockIdx.x];
-  for (int c = threadIdx.x; c < n0; c += blockDim.x) {
-    double s = 0.0;
-    for (int a = 0; a < b.m; ++a)
-      s += C[c_tile(b, a >> 4, c >> 4) + (c & 15) * TS + (a & 15)] * yp[b.voff + a];
-    part[(long long)blockIdx.x * n0 + c] = s;
-  }
-}
-
-// g0 = sum_i partial_i + F0' yL (fixed order), then by mode as in k_cols
-// (mode 2 is not used for x_0: dx_0 comes from the Schur solve).
-__global__ void k_x0_finish(int N, int n0, long long nl, const double* __restrict__ part,
-                            const double* __restrict__ F0, const double* __restrict__ yL,
-                            int mode, const double* __restrict__ cvec,
-                            const double* __restrict__ zvec, long long x0off,
-                            double* __restrict__ gout, double* __restrict__ out) {
-  for (int c = threadIdx.x + blockIdx.x * blockDim.x; c < n0; c += blockDim.x * gridDim.x) {
-    double g = 0.0;
-    for (int i = 0; i < N; ++i) g += part[(long long)i * n0 + c];
-    if (F0)
-      for (long long r = 0; r < nl; ++r) g += F0[r * n0 + c] * yL[r];
-    const long long o = x0off + c;
-    if (gout) gout[o] = g;
-    if (out) out[o] = (mode == 1) ? cvec[o] - g - zvec[o] : g;
-  }
-}
-
 // g0[c] = sum_i part[i][c] + (F0' yL)[c] with one workgroup per column: each
 // thread sums a fixed strided subset, then a fixed tree; then by mode as k_cols.
 __device__ double block_reduce(int op, double v);
@@ -307,12 +278,13 @@ __global__ __launch_bounds__(256) void k_x0_sum(int N, int n0, long long nl,
 
 // ------------------------------------------------------------ substitutions
 // Forward substitution with the bordered factor of block i: v = L_i^-1 t and,
-// on the bordered rows, qn = -W_i' v.  t arrives in the padded block-row vector
-// and is overwritten by v.
+// on the bordered rows, qn = -W_i' v.  t is read from tin (padded block-row
+// vector) and v written to tv (tin may equal tv).
 template <typename T>
 __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__ blk,
                                                    const T* __restrict__ LB,
                                                    const T* __restrict__ LINV,
+                                                   const double* __restrict__ tin,
                                                    double* __restrict__ tv,
                                                    double* __restrict__ qn) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -320,7 +292,7 @@ __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__
   const BlockInfo b = blk[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nr = TS * b.rt, nm = TS * b.mt;
-  for (int r = tid; r < nr; r += blockDim.x) t[r] = (r < nm) ? tv[b.voff + r] : 0.0;
+  for (int r = tid; r < nr; r += blockDim.x) t[r] = (r < nm) ? tin[b.voff + r] : 0.0;
   __syncthreads();
   for (int p = 0; p < b.mt; ++p) {
     if (wave == 0) {
@@ -436,23 +408,25 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
 
 // Schur right-hand side: s_L[pair j] += qn_j[right section] + qn_{j+1}[left section];
 // s_0 = rhx_0 + sum_i qn_i[x_0 section] (fixed order).
-__global__ void k_schur_rhs(const BlockInfo* __restrict__ blk, int N, int n0,
-                            const int* __restrict__ lsz, const long long* __restrict__ loff,
-                            long long nl, const double* __restrict__ qn,
-                            const double* __restrict__ rhx0, double* __restrict__ s) {
+// Schur right-hand side (Alg. 3): s_L += the two blocks' bordered-row parts of
+// each link pair; s_0 = rhx_0 + sum over blocks (fixed order).  Blocks below
+// npb handle pairs, the next n0 blocks one x_0 entry each.
+__global__ __launch_bounds__(256) void k_schur_rhs(const BlockInfo* __restrict__ blk, int N, int n0,
+                                                   const int* __restrict__ lsz,
+                                                   const long long* __restrict__ loff, long long nl,
+                                                   int npb, const double* __restrict__ qn,
+                                                   const double* __restrict__ rhx0,
+                                                   double* __restrict__ s) {
   const int P = N - 1;
-  for (int j = blockIdx.x; j < P; j += gridDim.x) {
-    const BlockInfo bl = blk[j], br = blk[j + 1];
-    for (int a = threadIdx.x; a < lsz[j]; a += blockDim.x)
-      s[loff[j] + a] += qn[bl.qoff + TS * bl.ktL + a] + qn[br.qoff + a];
+  if ((int)blockIdx.x < npb) {
+    for (int j = blockIdx.x; j < P; j += npb) {
+      const BlockInfo bl = blk[j], br = blk[j + 1];
+      for (int a = threadIdx.x; a < lsz[j]; a += blockDim.x)
+        s[loff[j] + a] += qn[bl.qoff + TS * bl.ktL + a] + qn[br.qoff + a];
+    }
+    return;
   }
-}
-
-__global__ __launch_bounds__(256) void k_schur_rhs0(const BlockInfo* __restrict__ blk, int N,
-                                                    long long nl, const double* __restrict__ qn,
-                                                    const double* __restrict__ rhx0,
-                                                    double* __restrict__ s) {
-  const int c = blockIdx.x;
+  const int c = blockIdx.x - npb;
   double v = 0.0;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const BlockInfo& b = blk[i];
@@ -460,6 +434,101 @@ __global__ __launch_bounds__(256) void k_schur_rhs0(const BlockInfo* __restrict_
   }
   const double t = block_reduce(0, v);
   if (threadIdx.x == 0) s[nl + c] = rhx0[c] + t;
+}
+
+// End of a solve for the x_0 columns and the link rows: g_0 = sum of the
+// per-block partials C_i' dy_i + F0' dy_L (fixed order), dx_0 = u_0 and
+// dz_0 = (rz_0 - z_0 dx_0) / x_0 (blocks below n0, one entry each); the
+// remaining blocks copy the link part u_L of the Schur solution into dy.
+__global__ __launch_bounds__(256) void k_solve_tail(int N, int n0, long long nl,
+                                                    const double* __restrict__ part,
+                                                    const double* __restrict__ F0,
+                                                    const double* __restrict__ u, long long x0off,
+                                                    long long mblk, double* __restrict__ gout,
+                                                    double* __restrict__ dx, const DzArgs dzv,
+                                                    double* __restrict__ dy) {
+  if ((int)blockIdx.x < n0) {
+    const int c = blockIdx.x;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) v += part[(long long)i * n0 + c];
+    if (F0)
+      for (long long r = threadIdx.x; r < nl; r += blockDim.x) v += F0[r * n0 + c] * u[r];
+    const double g = block_reduce(0, v);
+    if (threadIdx.x == 0) {
+      const long long o = x0off + c;
+      gout[o] = g;
+      const double d = u[nl + c];
+      dx[o] = d;
+      dzv.dz[o] = (dzv.rz[o] - dzv.zs[o] * d) / dzv.xs[o];
+    }
+    return;
+  }
+  const long long stride = (long long)(gridDim.x - n0) * blockDim.x;
+  for (long long r = (long long)(blockIdx.x - n0) * blockDim.x + threadIdx.x; r < nl; r += stride)
+    dy[mblk + r] = u[r];
+}
+
+// Refinement-check prologue, per block of x-space (and the x_0 segment):
+// ex = rx - g - dz, ez = rz - zs dx - xs dz; xp = dx padded; w2p = D dx dz / x
+// padded (if requested, zero on the x_0 segment).
+__global__ void k_check_prep(const BlockInfo* __restrict__ blk, int N, int n0, long long x0off,
+                             long long d0off, const double* __restrict__ rx,
+                             const double* __restrict__ rz, const double* __restrict__ g,
+                             const double* __restrict__ dx, const double* __restrict__ dz,
+                             const double* __restrict__ xs, const double* __restrict__ zs,
+                             const double* __restrict__ Dp, double* __restrict__ ex,
+                             double* __restrict__ ez, double* __restrict__ xp,
+                             double* __restrict__ w2p) {
+  const int i = blockIdx.x;
+  long long xo, po;
+  int n, np;
+  if (i < N) { xo = blk[i].xoff; po = blk[i].dpoff; n = blk[i].n; np = TS * blk[i].nt; }
+  else { xo = x0off; po = d0off; n = n0; np = (n0 + TS - 1) / TS * TS; }
+  for (int c = threadIdx.x; c < np; c += blockDim.x) {
+    double v = 0.0, w = 0.0;
+    if (c < n) {
+      const long long o = xo + c;
+      const double d = dx[o], e = dz[o];
+      v = d;
+      if (i < N) w = Dp[po + c] * d * e / xs[o];
+      ex[o] = rx[o] - g[o] - e;
+      ez[o] = rz[o] - (zs[o] * d + xs[o] * e);
+    }
+    xp[po + c] = v;
+    if (w2p) w2p[po + c] = w;
+  }
+}
+
+// Residual-stage prologue, per block of x-space: rz_a = -x z; rhx = rd - rz_a / x;
+// vx = D rhx, w1 = D / x (zero on the x_0 segment) and xp = x, all padded.
+__global__ void k_resid_prep(const BlockInfo* __restrict__ blk, int N, int n0, long long x0off,
+                             long long d0off, const double* __restrict__ x,
+                             const double* __restrict__ z, const double* __restrict__ rd,
+                             const double* __restrict__ xs, const double* __restrict__ Dp,
+                             double* __restrict__ rzv, double* __restrict__ rhx,
+                             double* __restrict__ vx, double* __restrict__ w1p,
+                             double* __restrict__ xp) {
+  const int i = blockIdx.x;
+  long long xo, po;
+  int n, np;
+  if (i < N) { xo = blk[i].xoff; po = blk[i].dpoff; n = blk[i].n; np = TS * blk[i].nt; }
+  else { xo = x0off; po = d0off; n = n0; np = (n0 + TS - 1) / TS * TS; }
+  for (int c = threadIdx.x; c < np; c += blockDim.x) {
+    double hv = 0.0, w = 0.0, xv = 0.0;
+    if (c < n) {
+      const long long o = xo + c;
+      xv = x[o];
+      const double r = -xv * z[o];
+      rzv[o] = r;
+      const double h = rd[o] - r / xs[o];
+      rhx[o] = h;
+      hv = Dp[po + c] * h;
+      if (i < N) w = Dp[po + c] / xs[o];
+    }
+    vx[po + c] = hv;
+    w1p[po + c] = w;
+    xp[po + c] = xv;
+  }
 }
 
 // ------------------------------------------------------------ elementwise
@@ -717,9 +786,10 @@ void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int n0, const 
 void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int nct,
                  const double* A, const double* yp, const double* yL, const int* cptr,
                  const int* crow, const double* cval, int mode, const double* cvec,
-                 const double* zvec, const double* Dp, double* gout, double* out) {
+                 const double* zvec, const double* Dp, double* gout, double* out,
+                 const DzArgs& dzv) {
   hipLaunchKernelGGL(k_cols, dim3((nct + 3) / 4), dim3(256), 0, st, blk, coltiles, nct, A, yp, yL,
-                     cptr, crow, cval, mode, cvec, zvec, Dp, gout, out);
+                     cptr, crow, cval, mode, cvec, zvec, Dp, gout, out, dzv);
 }
 void launch_ccols(hipStream_t st, const BlockInfo* blk, const int2* ctiles, int nctile, int n0,
                   const double* C, const double* yp, double* part) {
@@ -734,20 +804,11 @@ void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, const double* pa
     hipLaunchKernelGGL(k_x0_sum, dim3(n0), dim3(256), 0, st, N, n0, nl, part, F0, yL, mode, cvec,
                        zvec, x0off, gout, out);
 }
-void launch_x0(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl, const double* C,
-               const double* yp, double* part, const double* F0, const double* yL, int mode,
-               const double* cvec, const double* zvec, long long x0off, double* gout,
-               double* out) {
-  if (n0 <= 0) return;
-  hipLaunchKernelGGL(k_x0_partial, dim3(N), dim3(64), 0, st, blk, n0, C, yp, part);
-  hipLaunchKernelGGL(k_x0_finish, dim3(1), dim3(128), 0, st, N, n0, nl, part, F0, yL, mode, cvec,
-                     zvec, x0off, gout, out);
-}
 template <typename T>
 void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, const T* LB,
-                      const T* LINV, double* tv, double* qn) {
+                      const T* LINV, const double* tin, double* tv, double* qn) {
   const size_t sh = (size_t)TS * max_rt * sizeof(double);
-  hipLaunchKernelGGL(k_block_fwd<T>, dim3(N), dim3(256), sh, st, blk, LB, LINV, tv, qn);
+  hipLaunchKernelGGL(k_block_fwd<T>, dim3(N), dim3(256), sh, st, blk, LB, LINV, tin, tv, qn);
 }
 template <typename T>
 void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl,
@@ -758,9 +819,9 @@ void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long 
                      dyp);
 }
 template void launch_block_fwd<double>(hipStream_t, const BlockInfo*, int, int, const double*,
-                                       const double*, double*, double*);
+                                       const double*, const double*, double*, double*);
 template void launch_block_fwd<float>(hipStream_t, const BlockInfo*, int, int, const float*,
-                                      const float*, double*, double*);
+                                      const float*, const double*, double*, double*);
 template void launch_block_bwd<double>(hipStream_t, const BlockInfo*, int, int, long long, int,
                                        const double*, const double*, const double*,
                                        const double*, double*, double*);
@@ -771,13 +832,34 @@ void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int n0, const
                       const long long* loff, long long nl, const double* qn, const double* rhx0,
                       double* s) {
   const int P = N - 1;
-  if (P > 0) {
-    const int grid = P < 1024 ? P : 1024;
-    hipLaunchKernelGGL(k_schur_rhs, dim3(grid), dim3(64), 0, st, blk, N, n0, lsz, loff, nl, qn,
-                       rhx0, s);
-  }
-  if (n0 > 0)
-    hipLaunchKernelGGL(k_schur_rhs0, dim3(n0), dim3(256), 0, st, blk, N, nl, qn, rhx0, s);
+  const int npb = P > 0 ? (P < 1024 ? P : 1024) : 0;
+  if (npb + n0 > 0)
+    hipLaunchKernelGGL(k_schur_rhs, dim3(npb + n0), dim3(256), 0, st, blk, N, n0, lsz, loff, nl,
+                       npb, qn, rhx0, s);
+}
+void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, const double* part,
+                       const double* F0, const double* u, long long x0off, long long mblk,
+                       double* gout, double* dx, const DzArgs& dzv, double* dy) {
+  long long nb = (nl + 255) / 256;
+  if (nb > 64) nb = 64;
+  const int grid = n0 + (int)nb;
+  if (grid > 0)
+    hipLaunchKernelGGL(k_solve_tail, dim3(grid), dim3(256), 0, st, N, n0, nl, part, F0, u, x0off,
+                       mblk, gout, dx, dzv, dy);
+}
+void launch_check_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                       long long d0off, const double* rx, const double* rz, const double* g,
+                       const double* dx, const double* dz, const double* xs, const double* zs,
+                       const double* Dp, double* ex, double* ez, double* xp, double* w2p) {
+  hipLaunchKernelGGL(k_check_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, rx, rz,
+                     g, dx, dz, xs, zs, Dp, ex, ez, xp, w2p);
+}
+void launch_resid_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                       long long d0off, const double* x, const double* z, const double* rd,
+                       const double* xs, const double* Dp, double* rzv, double* rhx, double* vx,
+                       double* w1p, double* xp) {
+  hipLaunchKernelGGL(k_resid_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, z,
+                     rd, xs, Dp, rzv, rhx, vx, w1p, xp);
 }
 void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y) {
   if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid1d(n)), dim3(256), 0, st, n, a, x, y);

@@ -141,22 +141,23 @@ void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int n0, const 
                      const long long* loff, const int* lptr, const int* lcol,
                      const double* lval, const double* xp, const double* x0, const double* F0,
                      const double* base, double alpha, double* out);
+// Optional fused output of the column pass (mode 2): dz = (rz - zs dx) / xs
+struct DzArgs {
+  const double* rz; const double* zs; const double* xs; double* dz;
+};
 void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int nct,
                  const double* A, const double* yp, const double* yL, const int* cptr,
                  const int* crow, const double* cval, int mode, const double* cvec,
-                 const double* zvec, const double* Dp, double* gout, double* out);
+                 const double* zvec, const double* Dp, double* gout, double* out,
+                 const DzArgs& dzv = DzArgs{});
 void launch_ccols(hipStream_t st, const BlockInfo* blk, const int2* ctiles, int nctile, int n0,
                   const double* C, const double* yp, double* part);
 void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, const double* part,
                    const double* F0, const double* yL, int mode, const double* cvec,
                    const double* zvec, long long x0off, double* gout, double* out);
-void launch_x0(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl, const double* C,
-               const double* yp, double* part, const double* F0, const double* yL, int mode,
-               const double* cvec, const double* zvec, long long x0off, double* gout,
-               double* out);
 template <typename T>
 void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, const T* LB,
-                      const T* LINV, double* tv, double* qn);
+                      const T* LINV, const double* tin, double* tv, double* qn);
 template <typename T>
 void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl,
                       int max_rt, const T* LB, const T* LINV, const double* v, const double* u,
@@ -164,6 +165,17 @@ void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long 
 void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
                       const long long* loff, long long nl, const double* qn, const double* rhx0,
                       double* s);
+void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, const double* part,
+                       const double* F0, const double* u, long long x0off, long long mblk,
+                       double* gout, double* dx, const DzArgs& dzv, double* dy);
+void launch_check_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                       long long d0off, const double* rx, const double* rz, const double* g,
+                       const double* dx, const double* dz, const double* xs, const double* zs,
+                       const double* Dp, double* ex, double* ez, double* xp, double* w2p);
+void launch_resid_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
+                       long long d0off, const double* x, const double* z, const double* rd,
+                       const double* xs, const double* Dp, double* rzv, double* rhx, double* vx,
+                       double* w1p, double* xp);
 void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y);
 void launch_dz(hipStream_t st, long long n, const double* rz, const double* zs, const double* xs,
                const double* dx, double* dz);
