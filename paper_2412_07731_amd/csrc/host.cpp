@@ -223,11 +223,13 @@ ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, co
                  p->lval, p->Dp, LB, p->PQ);
   p->timer.end();
   p->timer.begin(AHLP_ST_FACTOR);
-  launch_block_factor<T>(st, p->blk, p->N, p->max_rt, LB, LINV, p->info);
+  const bool pq_done = launch_block_factor<T>(st, p->blk, p->N, p->max_rt, LB, LINV, p->PQ, p->info);
   p->timer.end();
-  p->timer.begin(AHLP_ST_SCHUR);
-  launch_schur_contrib<T>(st, p->blk, p->N, LB, p->PQ);
-  p->timer.end();
+  if (!pq_done) {
+    p->timer.begin(AHLP_ST_SCHUR);
+    launch_schur_contrib<T>(st, p->blk, p->N, LB, p->PQ);
+    p->timer.end();
+  }
   HIPCHK(hipGetLastError());
   return AHLP_OK;
 }

@@ -177,20 +177,35 @@ __global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
     p0 = lptr[b.csr_off + q];
     p1 = lptr[b.csr_off + q + 1];
   }
-  for (int c = 0; c < b.mt; ++c) {
-    const int a = TS * c + al;
-    double v = 0.0;
-    if (real && a < b.m) {
-      if (sec < 2) {
-        for (int e = p0; e < p1; ++e) {
-          const int j = lcol[e];
-          v += lval[e] * Dp[b.dpoff + j] * A[a_tile(b, a >> 4, j >> 4) + (j & 15) * TS + (a & 15)];
+  // LINK_CB column tiles at a time, their gathers independent so that they
+  // are all in flight together; the sparse row is walked once per chunk
+  constexpr int LINK_CB = 8;
+  for (int c0 = 0; c0 < b.mt; c0 += LINK_CB) {
+    double v[LINK_CB];
+#pragma unroll
+    for (int u = 0; u < LINK_CB; ++u) v[u] = 0.0;
+    if (real && sec < 2) {
+      for (int e = p0; e < p1; ++e) {
+        const int j = lcol[e];
+        const double coef = lval[e] * Dp[b.dpoff + j];
+        const double* col = A + a_tile(b, 0, j >> 4) + (j & 15) * TS + al;
+#pragma unroll
+        for (int u = 0; u < LINK_CB; ++u) {
+          const int c = c0 + u;
+          if (c < b.mt && TS * c + al < b.m) v[u] += coef * col[(long long)c * b.nt * TE];
         }
-      } else {
-        v = C[c_tile(b, a >> 4, qi >> 4) + (qi & 15) * TS + (a & 15)];
+      }
+    } else if (real) {
+      const double* col = C + c_tile(b, 0, qi >> 4) + (qi & 15) * TS + al;
+#pragma unroll
+      for (int u = 0; u < LINK_CB; ++u) {
+        const int c = c0 + u;
+        if (c < b.mt && TS * c + al < b.m) v[u] = col[(long long)c * b.kt0 * TE];
       }
     }
-    LB[lb_tile(b, r, c) + t] = (T)v;
+#pragma unroll
+    for (int u = 0; u < LINK_CB; ++u)
+      if (c0 + u < b.mt) LB[lb_tile(b, r, c0 + u) + t] = (T)v[u];
   }
   // F D F' for tiles (rr, cc), cc <= rr
   for (int cc = 0; cc <= rr; ++cc) {
@@ -285,6 +300,76 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
   if (tid == 0 && cnt) atomicAdd(&info->pivots, cnt);
 }
 
+// Schur contribution of block i: PQ = F D F' - X X' with X = W_i' (the
+// bordered rows of the factor), in FP64 whatever the factor precision.  The
+// workgroup's four waves take the tile rows rr = w, w + 4, ...; row rr's tiles
+// (rr, cc), cc <= rr, go in groups of SC_G sharing the loads of X(rr, q), and
+// the tiles of step q + 1 are requested before the MFMAs of step q.
+template <typename T>
+__device__ __forceinline__ void schur_rows(const BlockInfo& b, const T* __restrict__ LB,
+                                           double* __restrict__ PQ, int w, int lane) {
+  constexpr int SC_G = 4;
+  for (int rr = w; rr < b.kt; rr += 4) {
+    for (int cg = 0; cg <= rr; cg += SC_G) {
+      const int ng = min(SC_G, rr + 1 - cg);
+      d4 acc[SC_G];
+#pragma unroll
+      for (int u = 0; u < SC_G; ++u) {
+        acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+        if (u < ng) {
+          const double* dst = PQ + pq_tile(b, rr, cg + u);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[u][k] = dst[acc_index<double>(lane, k)];
+        }
+      }
+      T xc[4], yc[SC_G][4], xn[4], yn[SC_G][4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xc[s] = LB[lb_tile(b, b.mt + rr, 0) + 64 * s + lane];
+#pragma unroll
+      for (int u = 0; u < SC_G; ++u)
+        if (u < ng) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) yc[u][s] = LB[lb_tile(b, b.mt + cg + u, 0) + 64 * s + lane];
+        }
+      for (int q = 0; q < b.mt; ++q) {
+        const bool more = q + 1 < b.mt;
+        if (more) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) xn[s] = LB[lb_tile(b, b.mt + rr, q + 1) + 64 * s + lane];
+#pragma unroll
+          for (int u = 0; u < SC_G; ++u)
+            if (u < ng) {
+#pragma unroll
+              for (int s = 0; s < 4; ++s) yn[u][s] = LB[lb_tile(b, b.mt + cg + u, q + 1) + 64 * s + lane];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SC_G; ++u)
+          if (u < ng) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[u] = mfma(-(double)xc[s], (double)yc[u][s], acc[u]);
+          }
+        if (more) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) xc[s] = xn[s];
+#pragma unroll
+          for (int u = 0; u < SC_G; ++u)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) yc[u][s] = yn[u][s];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SC_G; ++u)
+        if (u < ng) {
+          double* dst = PQ + pq_tile(b, rr, cg + u);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) dst[acc_index<double>(lane, k)] = acc[u][k];
+        }
+    }
+  }
+}
+
+
 // Panel form of the same factorization for bordered blocks of at most
 // BF_RMAX*4 tile rows: left-looking by panels of BF_PW tile columns held in
 // registers (4 waves, panel rows dealt round-robin, at most BF_RMAX per wave).
@@ -294,7 +379,8 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
 // below times L_cc^-T (through a per-wave LDS conversion to operand layout),
 // and the next panel column updated from an LDS copy of the new column.
 // Two workgroups share a CU, so one block's tile Cholesky overlaps the
-// other's MFMA work.
+// other's MFMA work.  The kernel ends with the block's Schur contribution
+// (schur_rows), so no separate a5 product pass is needed on this path.
 constexpr int BF_PW = 2, BF_RMAX = 5;
 template <typename T>
 struct BfOp { T v[4]; };
@@ -311,6 +397,7 @@ template <typename T>
 __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
                                                                T* __restrict__ LB,
                                                                T* __restrict__ LINV,
+                                                               double* __restrict__ PQ,
                                                                DevInfo* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const BlockInfo b = blk[blockIdx.x];
@@ -321,7 +408,8 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
   T* scr = dt + TE;                                     // 4 tiles: per-wave conversion
   T* xbuf = scr + 4 * TE;                               // 48 values: tile Cholesky
   __shared__ double s_max[4];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row and address arithmetic stays scalar
   typedef typename Acc<T>::type AT;
 
   double md = 0.0;
@@ -437,6 +525,9 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
       __syncthreads();
     }
   }
+  // the block's Schur contribution while its W' tiles are still in L2 (the
+  // loop's last barrier has made every wave's stores visible)
+  schur_rows<T>(b, LB, PQ, w, lane);
   if (tid == 0 && cnt) atomicAdd(&info->pivots, cnt);
 }
 
@@ -447,27 +538,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_schur_contrib(const BlockInfo* __restrict__ blk,
                                                        const T* __restrict__ LB,
                                                        double* __restrict__ PQ) {
-  const BlockInfo b = blk[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ntiles = b.kt * (b.kt + 1) / 2;
-  for (int t = wave; t < ntiles; t += 4) {
-    int rr = 0;
-    while ((rr + 1) * (rr + 2) / 2 <= t) ++rr;
-    const int cc = t - rr * (rr + 1) / 2;
-    d4 acc;
-    double* dst = PQ + pq_tile(b, rr, cc);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = dst[acc_index<double>(lane, k)];
-    for (int q = 0; q < b.mt; ++q) {
-      const T* X = LB + lb_tile(b, b.mt + rr, q);
-      const T* Y = LB + lb_tile(b, b.mt + cc, q);
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        acc = mfma(-(double)X[64 * s + lane], (double)Y[64 * s + lane], acc);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) dst[acc_index<double>(lane, k)] = acc[k];
-  }
+  const int tid = threadIdx.x, lane = tid & 63;
+  schur_rows<T>(blk[blockIdx.x], LB, PQ, __builtin_amdgcn_readfirstlane(tid >> 6), lane);
 }
 
 // Element (q, q2) of block i's symmetric contribution (lower tiles stored).
@@ -601,20 +673,22 @@ template void launch_link<float>(hipStream_t, const BlockInfo*, const int2*, int
                                  const double*, const double*, float*, double*);
 
 template <typename T>
-void launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
-                         T* LINV, DevInfo* info) {
+bool launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
+                         T* LINV, double* PQ, DevInfo* info) {
   if (max_rt <= 4 * BF_RMAX) {
     const size_t shmem = (size_t)(max_rt + 6) * TE * sizeof(T) + 48 * sizeof(T);
-    hipLaunchKernelGGL(k_block_factor_panel<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, info);
-    return;
+    hipLaunchKernelGGL(k_block_factor_panel<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, PQ,
+                       info);
+    return true;
   }
   const size_t shmem = (size_t)(max_rt + 1) * TE * sizeof(T);
   hipLaunchKernelGGL(k_block_factor<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, info);
+  return false;
 }
-template void launch_block_factor<double>(hipStream_t, const BlockInfo*, int, int, double*,
-                                          double*, DevInfo*);
-template void launch_block_factor<float>(hipStream_t, const BlockInfo*, int, int, float*, float*,
-                                         DevInfo*);
+template bool launch_block_factor<double>(hipStream_t, const BlockInfo*, int, int, double*,
+                                           double*, double*, DevInfo*);
+template bool launch_block_factor<float>(hipStream_t, const BlockInfo*, int, int, float*,
+                                          float*, double*, DevInfo*);
 
 template <typename T>
 void launch_schur_contrib(hipStream_t st, const BlockInfo* blk, int N, const T* LB, double* PQ) {

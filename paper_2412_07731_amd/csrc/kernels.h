@@ -16,9 +16,11 @@ template <typename T>
 void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int n0,
                  const double* A, const double* C, const int* lptr, const int* lcol,
                  const double* lval, const double* Dp, T* LB, double* PQ);
+// Returns true when the kernel also formed the Schur contributions PQ (the
+// panel path); otherwise launch_schur_contrib must follow.
 template <typename T>
-void launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
-                         T* LINV, DevInfo* info);
+bool launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
+                         T* LINV, double* PQ, DevInfo* info);
 template <typename T>
 void launch_schur_contrib(hipStream_t st, const BlockInfo* blk, int N, const T* LB, double* PQ);
 void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
