@@ -98,7 +98,9 @@ typedef struct {
   double mu_switch;       /* FP32 mode: switch to FP64 blocks for good once mu < this */
   int32_t start;          /* 0 = Mehrotra starting point, 1 = use x, y, z as given    */
   int32_t verbose;        /* 1 = one log line per iteration on stderr                */
-  int32_t timing;         /* 1 = record per-stage device times (HIP events)          */
+  int32_t timing;         /* 1 = record per-stage device times (HIP events); 2 = the  */
+                          /* factorization stages PREP, SYRK, FACTOR, SCHUR only      */
+                          /* (fewer events, so less perturbation of the run)          */
   double fp32_accept;     /* FP32 mode: a direction from FP32 factors is accepted      */
                           /* once |r - K d|_inf <= fp32_accept * mu (inexact Newton;   */
                           /* 0.1; 0 = only the refine_tol backward error).  FP32 that   */

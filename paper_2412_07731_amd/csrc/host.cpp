@@ -71,6 +71,7 @@ struct DevMem {
 
 struct StageTimer {
   bool on = false;
+  unsigned mask = ~0u;        // stages recorded while on (bit per AHLP_ST_*)
   hipStream_t st = nullptr;
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> pending;
@@ -88,8 +89,13 @@ struct StageTimer {
     (void)hipEventCreate(&e);
     return e;
   }
+  bool records(int stage) const { return on && ((mask >> stage) & 1u); }
   void begin(int stage) {
     if (!on) return;
+    if (!((mask >> stage) & 1u)) {   // keeps nesting balanced, records nothing
+      open.push_back(SIZE_MAX);
+      return;
+    }
     Rec r{stage, get(), get()};
     (void)hipEventRecord(r.a, st);
     open.push_back(pending.size());
@@ -97,7 +103,7 @@ struct StageTimer {
   }
   void end() {
     if (!on || open.empty()) return;
-    (void)hipEventRecord(pending[open.back()].b, st);
+    if (open.back() != SIZE_MAX) (void)hipEventRecord(pending[open.back()].b, st);
     open.pop_back();
   }
   // call after a stream synchronization
@@ -190,9 +196,23 @@ struct ahlp_problem_s {
          *dza = nullptr, *dx = nullptr, *dy = nullptr, *dz = nullptr;
   double *red_part = nullptr, *scal = nullptr;
   double* h_scal = nullptr;   // pinned host mirror of scal
+  // side stream (default priority) for the link-column gather, which runs
+  // beside the block SYRK: event fork from the caller's stream, join before
+  // the block factor
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   StageTimer timer;
   double rows_bytes = 0.0;      // algorithmic bytes of the timed row passes
   double a_bytes = 0, c_bytes = 0, xv_bytes = 0, x0_bytes = 0, yv_bytes = 0;
+
+  // host-side handles (device buffers are released by mem); also runs when
+  // creation fails part way
+  ~ahlp_problem_s() {
+    if (h_scal) (void)hipHostFree(h_scal);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 namespace {
@@ -215,14 +235,18 @@ ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
 // ------------------------------------------------------------- factor
 template <typename T>
 ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, const T* A) {
+  // the link gather (HBM-bound) runs on the side stream while the SYRK
+  // (MFMA-bound) runs on st; they write disjoint tiles of LB
+  HIPCHK(hipEventRecord(p->ev_fork, st));
+  HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+  launch_link<T>(p->side, p->blk, p->link_items, p->nlink, p->n0, p->A, p->C, p->lptr, p->lcol,
+                 p->lval, p->Dp, LB, p->PQ);
+  HIPCHK(hipEventRecord(p->ev_join, p->side));
   p->timer.begin(AHLP_ST_SYRK);
   launch_syrk<T>(st, p->blk, p->syrk_items, p->nsyrk, A, p->Dp, LB, p->delta);
   p->timer.end();
-  p->timer.begin(AHLP_ST_PREP);
-  launch_link<T>(st, p->blk, p->link_items, p->nlink, p->n0, p->A, p->C, p->lptr, p->lcol,
-                 p->lval, p->Dp, LB, p->PQ);
-  p->timer.end();
   p->timer.begin(AHLP_ST_FACTOR);
+  HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
   const bool pq_done = launch_block_factor<T>(st, p->blk, p->N, p->max_rt, LB, LINV, p->PQ, p->info);
   p->timer.end();
   if (!pq_done) {
@@ -328,7 +352,7 @@ void rows_pass(ahlp_problem_t p, const RowsArgs& ra, hipStream_t st) {
   p->timer.begin(AHLP_ST_AROWS);
   launch_rows_multi(st, p->blk, p->rowtiles, p->nrt, p->A, p->C, p->d0off, ra);
   p->timer.end();
-  if (p->timer.on) {
+  if (p->timer.records(AHLP_ST_AROWS)) {
     bool anyC = false;
     double b = p->a_bytes;
     for (int k = 0; k < ra.nv; ++k) {
@@ -587,7 +611,6 @@ void ahlp_ipm_default_opts(ahlp_ipm_opts_t* o) {
 
 ahlp_status_t ahlp_problem_destroy(ahlp_problem_t p) {
   if (!p) return AHLP_OK;
-  if (p->h_scal) (void)hipHostFree(p->h_scal);
   delete p;
   return AHLP_OK;
 }
@@ -925,6 +948,9 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (double** v : {&p->w1p, &p->w2p}) CHK(M.alloc(v, p->dp_total));
   CHK(M.alloc(&p->gc, p->n_tot));
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
 
   HIPCHK(hipMemcpyAsync(p->blk, p->hb.data(), sizeof(BlockInfo) * N, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->A, hA.data(), sizeof(double) * ao, hipMemcpyHostToDevice, st));
@@ -1012,6 +1038,10 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   std::memset(&R, 0, sizeof R);
   p->timer.st = st;
   p->timer.on = o->timing != 0;
+  // timing 2: the factorization stages a1-a5 only (fewer events in the stream)
+  p->timer.mask = o->timing == 2 ? ((1u << AHLP_ST_PREP) | (1u << AHLP_ST_SYRK) |
+                                    (1u << AHLP_ST_FACTOR) | (1u << AHLP_ST_SCHUR))
+                                 : ~0u;
   p->timer.reset();
   p->rows_bytes = 0.0;
   const long long n = p->n_tot, m = p->m_tot;
