@@ -10,6 +10,8 @@ Modules
   dense_kkt  brute-force dense solves of the Newton system (Sec. 2.3)
   newton     block elimination: factorization Alg. 2, solve Alg. 3 (Sec. 3.2)
   ipm        Mehrotra predictor-corrector driver (Sec. 2.3; constants are readings)
+  sensitivity  derivatives of the mu-fixed KKT map w.r.t. (b, c): forward and
+             transposed Newton solves, central-path re-solve for differences
 
 Everything is plain NumPy/SciPy in float64.  Library primitives (matmul,
 LAPACK Cholesky, triangular solves) serve as steps; there is no blocking,
@@ -22,4 +24,7 @@ Parity status
                                 KKT conditions, scipy's HiGHS on small cases;
                                 the iterate trajectory itself is parity unpinned
                                 (the paper prints no iterates or counts)
+  sensitivity.*                 pinned: dense LU of K', the adjoint identity,
+                                central differences of the central-path map,
+                                LP closed forms at a nondegenerate optimum
 """

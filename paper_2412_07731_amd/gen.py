@@ -27,6 +27,17 @@ block j and -1 on variable k of block j+1 (energy-system storage balance).
 Draw order (fixed; PCG64(seed)): random sizes (m_i, then l_j), then per block
 A_i (mask, values, zero-row redraws) and C_i (mask, values), then x* positions
 and values per block and for x_0, then z* values, then y*.
+
+Nondegenerate variant (``nondegenerate=True``, needs n0 = 0), for the
+sensitivity workload: block i gets exactly m_i + l_i positive x* entries (l_i
+of the pair on its right, 0 for the last block): its last l_i variables (the
+pair's boundary variables, forced in) and m_i others drawn from the variables
+that touch no link row (not the first l_{i-1}, not the last l_i), redrawn
+until A_i restricted to them is nonsingular.  The basis matrix A_B is then
+block diagonal with blocks [[A_i(:, R_i), A_i(:, bd_i)], [0, I]], so it is
+square and nonsingular, x*_B > 0 and z*_N > 0: the optimum is unique and
+strictly complementary.  Draws: the m_i others (and redraws) then the x*_B
+values per block, then z* values, then y*.
 """
 from __future__ import annotations
 
@@ -44,6 +55,11 @@ CONFIGS = {
     "n512": dict(N=512, m=256, n=512, l=16, n0=32, density=0.10),
     # uneven blocks: m_i ~ U{64..512}, n_i = 2 m_i, l_j ~ U{4..32}, 64 linking vars
     "uneven": dict(N=2048, m=(64, 512), n="2m", l=(4, 32), n0=64, density=0.10),
+    # sensitivity workload: N=256, 256x512 at 10%, 16 links, no linking vars,
+    # nondegenerate optimum
+    "sens": dict(N=256, m=256, n=512, l=16, n0=0, density=0.10, nondegenerate=True),
+    # small nondegenerate instance for dense reference checks
+    "tiny_nd": dict(N=8, m=32, n=64, l=4, n0=0, density=0.30, nondegenerate=True),
 }
 
 
@@ -67,6 +83,7 @@ class Instance:
     ystar: np.ndarray = field(default=None)
     zstar: np.ndarray = field(default=None)
     fstar: float = float("nan")
+    basis: Optional[list] = field(default=None)   # nondegenerate variant: positive x* indices per block
 
     @property
     def n_tot(self) -> int:
@@ -157,12 +174,35 @@ def generate(config="tiny", seed=0, **overrides) -> Instance:
 
     # complementary optimum
     xs = []
-    for i in range(N + 1):
-        ni = int(n[i]) if i < N else n0
-        xi = np.zeros(ni)
-        pos = rng.permutation(ni)[: ni // 2]
-        xi[pos] = rng.uniform(0.5, 2.0, size=pos.size)
-        xs.append(xi)
+    basis = None
+    if cfg.get("nondegenerate", False):
+        if n0 != 0:
+            raise ValueError("the nondegenerate variant needs n0 = 0")
+        basis = []
+        for i in range(N):
+            ni, mi = int(n[i]), int(m[i])
+            lr = int(l[i]) if i < N - 1 else 0
+            ll = int(l[i - 1]) if i > 0 else 0
+            pool = np.arange(ll, ni - lr)
+            if pool.size < mi:
+                raise ValueError("block too narrow for a nondegenerate basis")
+            while True:
+                R = np.sort(rng.choice(pool, size=mi, replace=False))
+                if np.linalg.matrix_rank(A[i][:, R]) == mi:
+                    break
+            Bi = np.concatenate([R, np.arange(ni - lr, ni)])
+            xi = np.zeros(ni)
+            xi[Bi] = rng.uniform(0.5, 2.0, size=Bi.size)
+            xs.append(xi)
+            basis.append(Bi)
+        xs.append(np.zeros(0))
+    else:
+        for i in range(N + 1):
+            ni = int(n[i]) if i < N else n0
+            xi = np.zeros(ni)
+            pos = rng.permutation(ni)[: ni // 2]
+            xi[pos] = rng.uniform(0.5, 2.0, size=pos.size)
+            xs.append(xi)
     xstar = np.concatenate(xs) if xs else np.zeros(0)
     zvals = rng.uniform(0.5, 2.0, size=xstar.size)
     zstar = np.where(xstar == 0.0, zvals, 0.0)
@@ -172,6 +212,7 @@ def generate(config="tiny", seed=0, **overrides) -> Instance:
     inst = Instance(N=N, n0=n0, m=m, n=n, l=l, A=A, C=C, FR=FR, FL=FL, F0=F0,
                     b=np.zeros(m_tot), c=np.zeros(xstar.size))
     inst.xstar, inst.ystar, inst.zstar = xstar, ystar, zstar
+    inst.basis = basis   # per block: the indices of the positive x* entries (nondegenerate only)
     inst.b = apply_A(inst, xstar)
     inst.c = apply_At(inst, ystar) + zstar
     inst.fstar = float(inst.c @ xstar)

@@ -71,3 +71,22 @@ def test_uneven_sizes_and_determinism():
     assert np.all((a.l >= 4) & (a.l <= 32))
     c = gen.generate(cfg, 6)
     assert not np.array_equal(a.b[:10], c.b[:10])
+
+
+def test_nondegenerate_variant_has_square_nonsingular_basis():
+    """tiny_nd: exactly m_tot positive x* entries, the basis matrix square and
+    nonsingular, strict complementarity, and the first l_{i-1} variables of
+    every block outside the basis (A_B block diagonal)."""
+    import numpy as np
+    from oracle import lp
+    inst = gen.generate("tiny_nd", 0)
+    assert inst.n0 == 0 and inst.basis is not None
+    xo, _, _ = lp.offsets(inst)
+    cols = np.concatenate([xo[i] + inst.basis[i] for i in range(inst.N)])
+    assert cols.size == inst.m_tot == int(np.count_nonzero(inst.xstar))
+    AB = lp.full_matrix(inst).toarray()[:, cols]
+    assert np.linalg.matrix_rank(AB) == inst.m_tot
+    assert np.all((inst.xstar > 0) != (inst.zstar > 0))
+    for i in range(1, inst.N):
+        assert np.all(inst.basis[i] >= inst.l[i - 1])
+    assert abs(inst.c @ inst.xstar - inst.b @ inst.ystar) <= 1e-9 * abs(inst.fstar)
