@@ -174,6 +174,32 @@ ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* r
                              int32_t max_refine, double refine_tol, double* bkerr,
                              hipStream_t stream);
 
+/* Transposed solve with the factors of the last ahlp_kkt_factor: (wx, wy, wz)
+ * with
+ *     K' [wx; wy; wz] = [gx; gy; gz],   K = [0 A' I; A 0 0; Z 0 X]
+ * the Newton matrix of Sec. 2.3 at the (x, z) of that factorization.  This is
+ * the adjoint of the interior-point end point: with the barrier parameter
+ * fixed, the KKT conditions of Sec. 2.3 define (x, y, z) as a function of
+ * (b, c) whose derivative is K^-1 [dc; db; 0], so the gradient of a scalar
+ * L(x, y, z) is dL/dc = wx, dL/db = wy for g = (dL/dx, dL/dy, dL/dz).  Since
+ * K' = diag(I, I, Z^-1) K diag(I, I, Z), the call runs one Newton solve of
+ * (gx, gy, z gz), refined as in ahlp_kkt_solve (max_refine, refine_tol, *bkerr
+ * refer to that Newton system), and returns wz = dz / z.  All six vectors are
+ * DEVICE memory (gx, wx, gz, wz: [n_tot]; gy, wy: [m_tot]); outputs must not
+ * alias inputs.  AHLP_ESTATE if no factorization exists. */
+ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double* gy,
+                               const double* gz, double* wx, double* wy, double* wz,
+                               int32_t max_refine, double refine_tol, double* bkerr,
+                               hipStream_t stream);
+
+/* Replaces the right-hand side b and the cost c of the LP (Sec. 2.2) with new
+ * DEVICE vectors b [m_tot] and c [n_tot] (copied; the matrix and the factors
+ * are untouched).  Recomputes the norms the stopping test uses, so it
+ * synchronizes `stream`.  Errors: AHLP_EINVAL for null pointers,
+ * AHLP_ENUMERIC for non-finite entries. */
+ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const double* c,
+                                  hipStream_t stream);
+
 /* The Mehrotra predictor-corrector loop (Sec. 2.3) around factor and solve.
  * x, z: DEVICE [n_tot], y: DEVICE [m_tot]; outputs, and inputs when
  * opts->start == 1.  Synchronous.  res (host) receives the summary.

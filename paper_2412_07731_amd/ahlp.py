@@ -62,6 +62,10 @@ SIGNATURES = {
     "ahlp_kkt_solve": ([C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_double,
                                                           C.POINTER(C.c_double), C.c_void_p],
                        C.c_int),
+    "ahlp_kkt_adjoint": ([C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_double,
+                                                            C.POINTER(C.c_double), C.c_void_p],
+                         C.c_int),
+    "ahlp_problem_set_bc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "ahlp_ipm_solve": ([C.c_void_p, C.POINTER(IpmOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                         C.POINTER(IpmResult), C.c_void_p], C.c_int),
     "ahlp_last_error": ([], C.c_char_p),
@@ -181,6 +185,22 @@ class Problem:
                                     _dptr(dz), int(max_refine), float(refine_tol), C.byref(be),
                                     _stream(stream)))
         return dx, dy, dz, be.value
+
+    def adjoint(self, gx, gy, gz, max_refine=0, refine_tol=1e-10, stream=None, out=None):
+        """(wx, wy, wz, bkerr) with K' w = g at the last factorization (ahlp_kkt_adjoint)."""
+        import torch
+        if out is None:
+            out = (torch.empty_like(gx), torch.empty_like(gy), torch.empty_like(gz))
+        wx, wy, wz = out
+        be = C.c_double(-1.0)
+        _check(lib().ahlp_kkt_adjoint(self.h, _dptr(gx), _dptr(gy), _dptr(gz), _dptr(wx),
+                                      _dptr(wy), _dptr(wz), int(max_refine), float(refine_tol),
+                                      C.byref(be), _stream(stream)))
+        return wx, wy, wz, be.value
+
+    def set_bc(self, b, c, stream=None):
+        """Replace the LP's b and c with device vectors (ahlp_problem_set_bc)."""
+        _check(lib().ahlp_problem_set_bc(self.h, _dptr(b), _dptr(c), _stream(stream)))
 
     def ipm(self, x=None, y=None, z=None, stream=None, **opts):
         import torch

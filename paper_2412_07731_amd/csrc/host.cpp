@@ -192,6 +192,7 @@ struct ahlp_problem_s {
   // predictor/corrector right-hand sides by linearity (padded v-space) and scaled vectors
   double *ta = nullptr, *aw1 = nullptr, *aw2 = nullptr, *tc = nullptr, *w1p = nullptr,
          *w2p = nullptr, *gc = nullptr;
+  double* adj_rz = nullptr;   // z g_z of the transposed solve
   double *rp = nullptr, *rd = nullptr, *rzv = nullptr, *dxa = nullptr, *dya = nullptr,
          *dza = nullptr, *dx = nullptr, *dy = nullptr, *dz = nullptr;
   double *red_part = nullptr, *scal = nullptr;
@@ -947,6 +948,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (double** v : {&p->ta, &p->aw1, &p->aw2, &p->tc}) CHK(M.alloc(v, p->vp_total));
   for (double** v : {&p->w1p, &p->w2p}) CHK(M.alloc(v, p->dp_total));
   CHK(M.alloc(&p->gc, p->n_tot));
+  CHK(M.alloc(&p->adj_rz, p->n_tot));
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
@@ -1027,6 +1029,42 @@ ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* r
     return solve_refined(p, rx, ry, rz, dx, dy, dz, max_refine, refine_tol, kn, bkerr, nullptr, st);
   }
   return solve_once(p, rx, ry, rz, dx, dy, dz, st);
+}
+
+ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double* gy,
+                               const double* gz, double* wx, double* wy, double* wz,
+                               int32_t max_refine, double refine_tol, double* bkerr,
+                               hipStream_t st) {
+  g_err.clear();
+  if (!p || !gx || !gy || !gz || !wx || !wy || !wz) return fail(AHLP_EINVAL, "null argument");
+  if (!p->factored) return fail(AHLP_ESTATE, "adjoint solve before factor");
+  if (wx == gx || wy == gy || wz == gz) return fail(AHLP_EINVAL, "outputs must not alias inputs");
+  // K' w = g  <=>  K (wx, wy, z wz) = (gx, gy, z gz)
+  launch_adj_scale(st, p->n_tot, 0, p->zs, gz, p->adj_rz);
+  HIPCHK(hipGetLastError());
+  CHK(ahlp_kkt_solve(p, gx, gy, p->adj_rz, wx, wy, wz, max_refine, refine_tol, bkerr, st));
+  launch_adj_scale(st, p->n_tot, 1, p->zs, wz, wz);
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const double* c,
+                                  hipStream_t st) {
+  g_err.clear();
+  if (!p || !b || !c) return fail(AHLP_EINVAL, "null argument");
+  HIPCHK(hipMemcpyAsync(p->b, b, sizeof(double) * p->m_tot, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->c, c, sizeof(double) * p->n_tot, hipMemcpyDeviceToDevice, st));
+  // max |b|, max |c| for the stopping test; the sums of squares catch NaN
+  Reds(p).add(RED_MAXABS, p->m_tot, p->b, nullptr, 0).add(RED_MAXABS, p->n_tot, p->c, nullptr, 1)
+      .add(RED_DOT, p->m_tot, p->b, p->b, 2).add(RED_DOT, p->n_tot, p->c, p->c, 3).launch(st);
+  HIPCHK(hipGetLastError());
+  CHK(read_scal(p, 4, st));
+  const double* h = p->h_scal;
+  if (!std::isfinite(h[2]) || !std::isfinite(h[3]))
+    return fail(AHLP_ENUMERIC, "b or c has non-finite entries");
+  p->b_inf = h[0];
+  p->c_inf = h[1];
+  return AHLP_OK;
 }
 
 ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double* x, double* y,

@@ -539,6 +539,17 @@ __global__ void k_axpy(long long n, double a, const double* __restrict__ x,
     y[i] += a * x[i];
 }
 
+// The transposed Newton matrix is a diagonal scaling of the Newton matrix:
+// K' = diag(I, I, Z^-1) K diag(I, I, Z).  K' w = g is therefore solved as the
+// Newton solve of (g_x, g_y, z g_z) followed by w_z = dz / z.  mode 0:
+// out = z v; mode 1: out = v / z (may be in place).
+__global__ void k_adj_scale(long long n, int mode, const double* __restrict__ zs,
+                            const double* v, double* out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = mode ? v[i] / zs[i] : zs[i] * v[i];
+}
+
 // dz = (rz - zs dx) / xs
 __global__ void k_dz(long long n, const double* __restrict__ rz, const double* __restrict__ zs,
                      const double* __restrict__ xs, const double* __restrict__ dx,
@@ -860,6 +871,10 @@ void launch_resid_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long
                        double* w1p, double* xp) {
   hipLaunchKernelGGL(k_resid_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, z,
                      rd, xs, Dp, rzv, rhx, vx, w1p, xp);
+}
+void launch_adj_scale(hipStream_t st, long long n, int mode, const double* zs, const double* v,
+                      double* out) {
+  if (n > 0) hipLaunchKernelGGL(k_adj_scale, dim3(grid1d(n)), dim3(256), 0, st, n, mode, zs, v, out);
 }
 void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y) {
   if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid1d(n)), dim3(256), 0, st, n, a, x, y);

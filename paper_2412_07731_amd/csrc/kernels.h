@@ -179,6 +179,10 @@ void launch_resid_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long
                        const double* xs, const double* Dp, double* rzv, double* rhx, double* vx,
                        double* w1p, double* xp);
 void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y);
+// mode 0: out = zs * v; mode 1: out = v / zs (the diagonal scalings that turn
+// the transposed Newton solve into a Newton solve)
+void launch_adj_scale(hipStream_t st, long long n, int mode, const double* zs, const double* v,
+                      double* out);
 void launch_dz(hipStream_t st, long long n, const double* rz, const double* zs, const double* xs,
                const double* dx, double* dz);
 void launch_res_x(hipStream_t st, long long n, const double* rx, const double* rz,
