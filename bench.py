@@ -9,7 +9,11 @@ iteration runs the whole hot path: residuals, D-scaling and link columns, block
 SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
 factorization, predictor and corrector solves with FP64 refinement.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--profile]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--profile]
+
+The line also carries the sensitivity workload (N=256, nondegenerate): the
+differentiable solve, one backward pass (transposed Newton solve) and 64
+forward derivatives, with the gradient's error against the LP closed forms.
 
 Prints one JSON line.
 """
@@ -90,6 +94,55 @@ def cpu_baseline(inst, iters):
                       f"{dt:.1f} s; NumPy/SciPy OpenBLAS FP64"}
 
 
+def sens_bench(dev, ndir=64, reps=3):
+    """Sensitivity workload: N=256 blocks of 256x512 (10% nonzero, stored
+    dense), 16 links per pair, no linking variables, nondegenerate optimum.
+    Times the differentiable solve (interior point + one factorization at the
+    end point), one backward pass (one transposed Newton solve reusing that
+    factorization) and forward derivatives along ndir directions (db, dc)
+    ~ N(0,1) scaled to 1e-3 |b|, 1e-3 |c| (one Newton solve each)."""
+    import numpy as np
+    import torch
+    from paper_2412_07731_amd import autodiff, gen
+    from paper_2412_07731_amd.ahlp import Problem
+    inst = gen.generate("sens", 0)
+    P = Problem(inst)
+    T = lambda a: torch.tensor(np.asarray(a, dtype=np.float64), device=dev)
+    fwd, bwd = [], []
+    for _ in range(reps):
+        b, c = T(inst.b).requires_grad_(True), T(inst.c).requires_grad_(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, f = autodiff.solve(P, b, c)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd.append(t1 - t)
+        bwd.append(t2 - t1)
+    gb, gc = b.grad.cpu().numpy(), c.grad.cpu().numpy()
+    rng = np.random.default_rng(0)
+    nb, nc = float(np.linalg.norm(inst.b)), float(np.linalg.norm(inst.c))
+    dirs = [(T(rng.standard_normal(inst.m_tot) * 1e-3 * nb), T(rng.standard_normal(inst.n_tot) * 1e-3 * nc))
+            for _ in range(ndir)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for db, dc in dirs:
+        autodiff.jvp(P, db, dc)
+    torch.cuda.synchronize()
+    tj = time.perf_counter() - t
+    P.close()
+    relerr = lambda a, r: float(np.max(np.abs(a - r)) / np.max(np.abs(r)))
+    return {"workload": "sens: N=256 blocks 256x512 (10% nonzero, stored dense), 16 local links per "
+                        "pair, no linking variables, nondegenerate optimum, seed 0",
+            "solve_ms": 1e3 * min(fwd), "backward_ms": 1e3 * min(bwd),
+            "jvp_ms_per_direction": 1e3 * tj / ndir, "directions": ndir,
+            "grad_b_rel_err_vs_ystar": relerr(gb, inst.ystar),
+            "grad_c_rel_err_vs_xstar": relerr(gc, inst.xstar),
+            "objective_rel_err": abs(float(f.detach()) - inst.fstar) / abs(inst.fstar)}
+
+
 def run(P, steps, warmup, **opts):
     import torch
     for _ in range(warmup):
@@ -113,6 +166,7 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for profilers")
     ap.add_argument("--fp32", action="store_true", help="time the FP32+refine path as the main line")
     ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--no-sens", action="store_true", help="skip the sensitivity workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -213,6 +267,8 @@ def main():
             "objective_rel_err_vs_oracle": (abs(r32["primal_obj"] - golden["pobj"]) / max(1.0, abs(golden["pobj"]))
                                             if golden else None),
             "speedup_vs_fp64": (it32 / dt32) / (iters / dt)}
+    if not args.no_sens and not args.profile and not args.fp32:
+        line["sensitivity"] = sens_bench(torch.device("cuda", 0))
     if not args.no_cpu and not args.profile:
         line["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters)
     P.close()
