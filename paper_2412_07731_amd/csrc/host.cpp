@@ -154,6 +154,10 @@ struct ahlp_problem_s {
   double *lval = nullptr, *cval = nullptr;
   int4* syrk_items = nullptr;
   int nsyrk = 0;
+  // block-factor buckets: bf_order[0, n_panel) for the panel kernel, then
+  // n_col blocks for the column kernel, each largest first
+  int* bf_order = nullptr;
+  int n_panel = 0, n_col = 0, rt_panel = 0, rt_col = 0;
   int2* link_items = nullptr;
   int nlink = 0;
   int2 *rowtiles = nullptr, *coltiles = nullptr, *c0tiles = nullptr;
@@ -248,13 +252,23 @@ ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, co
   p->timer.end();
   p->timer.begin(AHLP_ST_FACTOR);
   HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
-  const bool pq_done = launch_block_factor<T>(st, p->blk, p->N, p->max_rt, LB, LINV, p->PQ, p->info);
-  p->timer.end();
-  if (!pq_done) {
-    p->timer.begin(AHLP_ST_SCHUR);
-    launch_schur_contrib<T>(st, p->blk, p->N, LB, p->PQ);
-    p->timer.end();
+  if (p->n_panel > 0 && p->n_col > 0) {
+    // both buckets: the column-kernel bucket beside the panel bucket
+    HIPCHK(hipEventRecord(p->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    launch_block_factor_col<T>(p->side, p->blk, p->bf_order + p->n_panel, p->n_col, p->rt_col, LB,
+                               LINV, p->PQ, p->info);
+    HIPCHK(hipEventRecord(p->ev_join, p->side));
+    launch_block_factor_panel<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, LB, LINV, p->PQ,
+                                 p->info);
+    HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
+  } else {
+    launch_block_factor_panel<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, LB, LINV, p->PQ,
+                                 p->info);
+    launch_block_factor_col<T>(st, p->blk, p->bf_order + p->n_panel, p->n_col, p->rt_col, LB, LINV,
+                               p->PQ, p->info);
   }
+  p->timer.end();
   HIPCHK(hipGetLastError());
   return AHLP_OK;
 }
@@ -794,13 +808,39 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (double v : colabs) p->colabs1_max = std::max(p->colabs1_max, v + 1.0);
 
   // ---- work lists
+  // Uneven blocks: SYRK work goes largest block first, dealt round-robin into
+  // eight chunks (the SYRK kernel gives each XCD a contiguous stretch of the
+  // list, so every XCD gets a similar mix); the block factor runs two buckets
+  // (panel kernel where the bordered block fits, column kernel otherwise),
+  // each largest first.
+  std::vector<int> bysize(N);
+  for (int i = 0; i < N; ++i) bysize[i] = i;
+  std::stable_sort(bysize.begin(), bysize.end(), [&](int a, int c) {
+    const BlockInfo &x = p->hb[a], &y = p->hb[c];
+    if (x.rt != y.rt) return x.rt > y.rt;
+    if (x.mt != y.mt) return x.mt > y.mt;
+    return x.nt > y.nt;
+  });
+  std::vector<int> syrk_order;
+  for (int ch = 0; ch < 8; ++ch)
+    for (int k = ch; k < N; k += 8) syrk_order.push_back(bysize[k]);
+  std::vector<int> hbf;
+  for (int i : bysize)
+    if (block_factor_panel_fits(p->hb[i].rt)) { hbf.push_back(i); p->rt_panel = std::max(p->rt_panel, p->hb[i].rt); }
+  p->n_panel = (int)hbf.size();
+  for (int i : bysize)
+    if (!block_factor_panel_fits(p->hb[i].rt)) { hbf.push_back(i); p->rt_col = std::max(p->rt_col, p->hb[i].rt); }
+  p->n_col = N - p->n_panel;
   std::vector<int4> hsyrk;
   std::vector<int2> hlink, hrow, hcolt, hc0;
-  for (int i = 0; i < N; ++i) {
+  for (int i : syrk_order) {
     const BlockInfo& b = p->hb[i];
     const int MT = (b.mt + 3) / 4;
     for (int r = 0; r < MT; ++r)
       for (int c = 0; c <= r; ++c) hsyrk.push_back(int4{i, r, c, 0});
+  }
+  for (int i = 0; i < N; ++i) {
+    const BlockInfo& b = p->hb[i];
     for (int r = 0; r < b.kt; ++r) hlink.push_back(int2{i, r});
     for (int r = 0; r < b.mt; ++r) hrow.push_back(int2{i, r});
     for (int c = 0; c < b.nt; ++c) hcolt.push_back(int2{i, c});
@@ -865,6 +905,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->b, p->m_tot));
   CHK(M.alloc(&p->c, p->n_tot));
   CHK(M.alloc(&p->syrk_items, p->nsyrk));
+  CHK(M.alloc(&p->bf_order, N));
   CHK(M.alloc(&p->link_items, std::max(p->nlink, 1)));
   CHK(M.alloc(&p->rowtiles, p->nrt));
   CHK(M.alloc(&p->coltiles, p->nct));
@@ -971,6 +1012,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   HIPCHK(hipMemcpyAsync(p->b, d->b, sizeof(double) * p->m_tot, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->c, d->c, sizeof(double) * p->n_tot, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->syrk_items, hsyrk.data(), sizeof(int4) * hsyrk.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->bf_order, hbf.data(), sizeof(int) * hbf.size(), hipMemcpyHostToDevice, st));
   if (!hlink.empty())
     HIPCHK(hipMemcpyAsync(p->link_items, hlink.data(), sizeof(int2) * hlink.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->rowtiles, hrow.data(), sizeof(int2) * hrow.size(), hipMemcpyHostToDevice, st));

@@ -242,10 +242,11 @@ __global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
 // are kept for the solve phase.
 template <typename T>
 __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restrict__ blk,
+                                                      const int* __restrict__ order,
                                                       T* __restrict__ LB, T* __restrict__ LINV,
                                                       DevInfo* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const BlockInfo b = blk[blockIdx.x];
+  const BlockInfo b = blk[order[blockIdx.x]];
   T* panel = reinterpret_cast<T*>(smem_raw);
   T* linv = panel + (size_t)b.rt * TE;
   __shared__ double s_max[4];
@@ -395,12 +396,13 @@ __device__ __forceinline__ BfOp<T> bf_ld(const T* __restrict__ t) {
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
+                                                               const int* __restrict__ order,
                                                                T* __restrict__ LB,
                                                                T* __restrict__ LINV,
                                                                double* __restrict__ PQ,
                                                                DevInfo* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const BlockInfo b = blk[blockIdx.x];
+  const BlockInfo b = blk[order[blockIdx.x]];
   const int mt = b.mt, rt = b.rt;
   T* colbuf = reinterpret_cast<T*>(smem_raw);          // rt tiles: the panel column just factored
   T* li = colbuf + (size_t)rt * TE;                     // L_cc^-1
@@ -536,10 +538,11 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
 // bordered rows of the factor), in FP64 whatever the factor precision.
 template <typename T>
 __global__ __launch_bounds__(256) void k_schur_contrib(const BlockInfo* __restrict__ blk,
+                                                       const int* __restrict__ order,
                                                        const T* __restrict__ LB,
                                                        double* __restrict__ PQ) {
   const int tid = threadIdx.x, lane = tid & 63;
-  schur_rows<T>(blk[blockIdx.x], LB, PQ, __builtin_amdgcn_readfirstlane(tid >> 6), lane);
+  schur_rows<T>(blk[order[blockIdx.x]], LB, PQ, __builtin_amdgcn_readfirstlane(tid >> 6), lane);
 }
 
 // Element (q, q2) of block i's symmetric contribution (lower tiles stored).
@@ -672,32 +675,34 @@ template void launch_link<float>(hipStream_t, const BlockInfo*, const int2*, int
                                  const double*, const double*, const int*, const int*,
                                  const double*, const double*, float*, double*);
 
+// Panel kernel for blocks of at most 4*BF_RMAX bordered tile rows (it also
+// forms their Schur contributions); workgroup w takes block order[w].
 template <typename T>
-bool launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
-                         T* LINV, double* PQ, DevInfo* info) {
-  if (max_rt <= 4 * BF_RMAX) {
-    const size_t shmem = (size_t)(max_rt + 6) * TE * sizeof(T) + 48 * sizeof(T);
-    hipLaunchKernelGGL(k_block_factor_panel<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, PQ,
-                       info);
-    return true;
-  }
+void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
+                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info) {
+  if (n == 0) return;
+  const size_t shmem = (size_t)(max_rt + 6) * TE * sizeof(T) + 48 * sizeof(T);
+  hipLaunchKernelGGL(k_block_factor_panel<T>, dim3(n), dim3(256), shmem, st, blk, order, LB, LINV,
+                     PQ, info);
+}
+// Column-at-a-time kernel (any height), then the Schur contributions.
+template <typename T>
+void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* order, int n,
+                             int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info) {
+  if (n == 0) return;
   const size_t shmem = (size_t)(max_rt + 1) * TE * sizeof(T);
-  hipLaunchKernelGGL(k_block_factor<T>, dim3(N), dim3(256), shmem, st, blk, LB, LINV, info);
-  return false;
+  hipLaunchKernelGGL(k_block_factor<T>, dim3(n), dim3(256), shmem, st, blk, order, LB, LINV, info);
+  hipLaunchKernelGGL(k_schur_contrib<T>, dim3(n), dim3(256), 0, st, blk, order, LB, PQ);
 }
-template bool launch_block_factor<double>(hipStream_t, const BlockInfo*, int, int, double*,
-                                           double*, double*, DevInfo*);
-template bool launch_block_factor<float>(hipStream_t, const BlockInfo*, int, int, float*,
-                                          float*, double*, DevInfo*);
-
-template <typename T>
-void launch_schur_contrib(hipStream_t st, const BlockInfo* blk, int N, const T* LB, double* PQ) {
-  hipLaunchKernelGGL(k_schur_contrib<T>, dim3(N), dim3(256), 0, st, blk, LB, PQ);
-}
-template void launch_schur_contrib<double>(hipStream_t, const BlockInfo*, int, const double*,
-                                           double*);
-template void launch_schur_contrib<float>(hipStream_t, const BlockInfo*, int, const float*,
-                                          double*);
+bool block_factor_panel_fits(int rt) { return rt <= 4 * BF_RMAX; }
+template void launch_block_factor_panel<double>(hipStream_t, const BlockInfo*, const int*, int, int,
+                                                double*, double*, double*, DevInfo*);
+template void launch_block_factor_panel<float>(hipStream_t, const BlockInfo*, const int*, int, int,
+                                               float*, float*, double*, DevInfo*);
+template void launch_block_factor_col<double>(hipStream_t, const BlockInfo*, const int*, int, int,
+                                              double*, double*, double*, DevInfo*);
+template void launch_block_factor_col<float>(hipStream_t, const BlockInfo*, const int*, int, int,
+                                             float*, float*, double*, DevInfo*);
 
 void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
                      const long long* tdoff, const long long* tooff, const long long* eoff,

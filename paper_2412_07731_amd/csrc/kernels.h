@@ -16,13 +16,18 @@ template <typename T>
 void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int n0,
                  const double* A, const double* C, const int* lptr, const int* lcol,
                  const double* lval, const double* Dp, T* LB, double* PQ);
-// Returns true when the kernel also formed the Schur contributions PQ (the
-// panel path); otherwise launch_schur_contrib must follow.
+// Block factorization of the blocks order[0..n) (bordered Cholesky giving L_i
+// and W_i', then the FP64 Schur contributions PQ): the panel kernel for
+// blocks whose bordered tile rows fit (block_factor_panel_fits), the
+// column-at-a-time kernel plus a product pass for any height.  max_rt: the
+// largest bordered tile-row count among the n blocks.
 template <typename T>
-bool launch_block_factor(hipStream_t st, const BlockInfo* blk, int N, int max_rt, T* LB,
-                         T* LINV, double* PQ, DevInfo* info);
+void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
+                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info);
 template <typename T>
-void launch_schur_contrib(hipStream_t st, const BlockInfo* blk, int N, const T* LB, double* PQ);
+void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* order, int n,
+                             int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info);
+bool block_factor_panel_fits(int rt);
 void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
                      const long long* tdoff, const long long* tooff, const long long* eoff,
                      const double* PQ, const double* F0, const long long* loff, double delta,
