@@ -200,6 +200,17 @@ ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double*
 ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const double* c,
                                   hipStream_t stream);
 
+/* How the per-block stages of the factorization (SYRK, link columns, block
+ * Cholesky with W_i and the Schur products; Alg. 2 lines 1-3 of Sec. 3.2) are
+ * launched.  AHLP_LAUNCH_BATCHED (default): each stage is one launch over all
+ * blocks (blocks of uneven size sorted largest first; the block factor in two
+ * buckets, by whether the bordered block fits the panel kernel).
+ * AHLP_LAUNCH_PER_BLOCK: the same kernels, one launch per block and stage, in
+ * block order; the arithmetic per block is identical, so results are bitwise
+ * equal.  It exists to measure what batching gains.  Errors: AHLP_EINVAL. */
+enum { AHLP_LAUNCH_BATCHED = 0, AHLP_LAUNCH_PER_BLOCK = 1 };
+ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode);
+
 /* The Mehrotra predictor-corrector loop (Sec. 2.3) around factor and solve.
  * x, z: DEVICE [n_tot], y: DEVICE [m_tot]; outputs, and inputs when
  * opts->start == 1.  Synchronous.  res (host) receives the summary.

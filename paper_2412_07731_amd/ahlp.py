@@ -66,6 +66,7 @@ SIGNATURES = {
                                                             C.POINTER(C.c_double), C.c_void_p],
                          C.c_int),
     "ahlp_problem_set_bc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "ahlp_problem_set_launch": ([C.c_void_p, C.c_int32], C.c_int),
     "ahlp_ipm_solve": ([C.c_void_p, C.POINTER(IpmOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                         C.POINTER(IpmResult), C.c_void_p], C.c_int),
     "ahlp_last_error": ([], C.c_char_p),
@@ -197,6 +198,10 @@ class Problem:
                                       _dptr(wy), _dptr(wz), int(max_refine), float(refine_tol),
                                       C.byref(be), _stream(stream)))
         return wx, wy, wz, be.value
+
+    def set_launch(self, per_block):
+        """Batched launches (default) or one launch per block (ahlp_problem_set_launch)."""
+        _check(lib().ahlp_problem_set_launch(self.h, 1 if per_block else 0))
 
     def set_bc(self, b, c, stream=None):
         """Replace the LP's b and c with device vectors (ahlp_problem_set_bc)."""

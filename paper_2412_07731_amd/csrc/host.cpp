@@ -158,6 +158,11 @@ struct ahlp_problem_s {
   // n_col blocks for the column kernel, each largest first
   int* bf_order = nullptr;
   int n_panel = 0, n_col = 0, rt_panel = 0, rt_col = 0;
+  // per-block launch mode (the reference the batched launches are compared
+  // with): block i's SYRK items, link items, and its index in an identity list
+  int launch_mode = AHLP_LAUNCH_BATCHED;
+  std::vector<int> syrk_off, syrk_cnt, link_off, link_cnt;
+  int* ident = nullptr;
   int2* link_items = nullptr;
   int nlink = 0;
   int2 *rowtiles = nullptr, *coltiles = nullptr, *c0tiles = nullptr;
@@ -238,8 +243,35 @@ ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
 }
 
 // ------------------------------------------------------------- factor
+// The same kernels, one launch per block and stage, in block order on st:
+// the reference for the batched launches (identical arithmetic per block).
+template <typename T>
+ahlp_status_t factor_blocks_per_block(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV,
+                                      const T* A) {
+  p->timer.begin(AHLP_ST_SYRK);
+  for (int i = 0; i < p->N; ++i) {
+    launch_link<T>(st, p->blk, p->link_items + p->link_off[i], p->link_cnt[i], p->n0, p->A, p->C,
+                   p->lptr, p->lcol, p->lval, p->Dp, LB, p->PQ);
+    launch_syrk<T>(st, p->blk, p->syrk_items + p->syrk_off[i], p->syrk_cnt[i], A, p->Dp, LB,
+                   p->delta);
+  }
+  p->timer.end();
+  p->timer.begin(AHLP_ST_FACTOR);
+  for (int i = 0; i < p->N; ++i) {
+    const int rt = p->hb[i].rt;
+    if (block_factor_panel_fits(rt))
+      launch_block_factor_panel<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info);
+    else
+      launch_block_factor_col<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info);
+  }
+  p->timer.end();
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
 template <typename T>
 ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, const T* A) {
+  if (p->launch_mode == AHLP_LAUNCH_PER_BLOCK) return factor_blocks_per_block<T>(p, st, LB, LINV, A);
   // the link gather (HBM-bound) runs on the side stream while the SYRK
   // (MFMA-bound) runs on st; they write disjoint tiles of LB
   HIPCHK(hipEventRecord(p->ev_fork, st));
@@ -833,14 +865,20 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   p->n_col = N - p->n_panel;
   std::vector<int4> hsyrk;
   std::vector<int2> hlink, hrow, hcolt, hc0;
+  p->syrk_off.assign(N, 0); p->syrk_cnt.assign(N, 0);
+  p->link_off.assign(N, 0); p->link_cnt.assign(N, 0);
   for (int i : syrk_order) {
     const BlockInfo& b = p->hb[i];
     const int MT = (b.mt + 3) / 4;
+    p->syrk_off[i] = (int)hsyrk.size();
     for (int r = 0; r < MT; ++r)
       for (int c = 0; c <= r; ++c) hsyrk.push_back(int4{i, r, c, 0});
+    p->syrk_cnt[i] = (int)hsyrk.size() - p->syrk_off[i];
   }
   for (int i = 0; i < N; ++i) {
     const BlockInfo& b = p->hb[i];
+    p->link_off[i] = (int)hlink.size();
+    p->link_cnt[i] = b.kt;
     for (int r = 0; r < b.kt; ++r) hlink.push_back(int2{i, r});
     for (int r = 0; r < b.mt; ++r) hrow.push_back(int2{i, r});
     for (int c = 0; c < b.nt; ++c) hcolt.push_back(int2{i, c});
@@ -906,6 +944,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->c, p->n_tot));
   CHK(M.alloc(&p->syrk_items, p->nsyrk));
   CHK(M.alloc(&p->bf_order, N));
+  CHK(M.alloc(&p->ident, N));
   CHK(M.alloc(&p->link_items, std::max(p->nlink, 1)));
   CHK(M.alloc(&p->rowtiles, p->nrt));
   CHK(M.alloc(&p->coltiles, p->nct));
@@ -1013,6 +1052,11 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   HIPCHK(hipMemcpyAsync(p->c, d->c, sizeof(double) * p->n_tot, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->syrk_items, hsyrk.data(), sizeof(int4) * hsyrk.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->bf_order, hbf.data(), sizeof(int) * hbf.size(), hipMemcpyHostToDevice, st));
+  {
+    std::vector<int> id(N);
+    for (int i = 0; i < N; ++i) id[i] = i;
+    HIPCHK(hipMemcpyAsync(p->ident, id.data(), sizeof(int) * N, hipMemcpyHostToDevice, st));
+  }
   if (!hlink.empty())
     HIPCHK(hipMemcpyAsync(p->link_items, hlink.data(), sizeof(int2) * hlink.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->rowtiles, hrow.data(), sizeof(int2) * hrow.size(), hipMemcpyHostToDevice, st));
@@ -1087,6 +1131,15 @@ ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double*
   CHK(ahlp_kkt_solve(p, gx, gy, p->adj_rz, wx, wy, wz, max_refine, refine_tol, bkerr, st));
   launch_adj_scale(st, p->n_tot, 1, p->zs, wz, wz);
   HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode) {
+  g_err.clear();
+  if (!p) return fail(AHLP_EINVAL, "null argument");
+  if (mode != AHLP_LAUNCH_BATCHED && mode != AHLP_LAUNCH_PER_BLOCK)
+    return fail(AHLP_EINVAL, "unknown launch mode %d", mode);
+  p->launch_mode = mode;
   return AHLP_OK;
 }
 

@@ -29,13 +29,26 @@ def run(config, seed):
 
 
 def main():
-    out = {"note": "FP64 oracle results; written by tests/golden/make_golden.py",
-           "runs": []}
-    for seed in range(8):
-        out["runs"].append(run("tiny", seed))
-    if "--quick" not in sys.argv:
-        out["runs"].append(run("n512", 0))
+    """No arguments: rewrite the file with tiny (seeds 0-7) and n512 (seed 0).
+    --quick: tiny only.  --add CONFIG:SEED [...]: run just those and merge
+    them into the existing file (e.g. --add uneven:0, the N=2048 workload,
+    which takes minutes and several GB)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_ipm.json")
+    if "--add" in sys.argv:
+        out = json.load(open(path))
+        for spec in sys.argv[sys.argv.index("--add") + 1:]:
+            config, seed = spec.split(":")
+            r = run(config, int(seed))
+            out["runs"] = [q for q in out["runs"] if (q["config"], q["seed"]) != (config, int(seed))]
+            out["runs"].append(r)
+            print(config, seed, r["status"], r["iterations"], r["seconds"], "s", flush=True)
+    else:
+        out = {"note": "FP64 oracle results; written by tests/golden/make_golden.py",
+               "runs": []}
+        for seed in range(8):
+            out["runs"].append(run("tiny", seed))
+        if "--quick" not in sys.argv:
+            out["runs"].append(run("n512", 0))
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print("wrote", path)
