@@ -211,6 +211,22 @@ ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const doubl
 enum { AHLP_LAUNCH_BATCHED = 0, AHLP_LAUNCH_PER_BLOCK = 1 };
 ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode);
 
+/* Chooses the block-factor kernel (Alg. 2 lines 1-2 of Sec. 3.2) for every
+ * bordered tile-row count rt that the problem's blocks have and the panel
+ * kernel can hold (rt <= 20): the panel kernel (panel accumulators in
+ * registers) or the column kernel (one tile column at a time through LDS).
+ * Entries for this GPU architecture found in the text file cache_path (HOST
+ * string, may be NULL) are used as they are; every other rt is measured on the
+ * problem's own blocks of that rt at x = z = 1 (the faster of two timed
+ * launches per kernel, each after rebuilding the blocks' inputs) and, with a
+ * cache_path, appended to the file as "<arch> <rt> <panel|column> <us panel>
+ * <us column>".  *measured (host, may be NULL) receives the number of rt values
+ * timed.  Later factorizations use the choices.  Overwrites the factors
+ * (factor again before solving).  Synchronizes `stream`.  Errors: AHLP_EINVAL
+ * (also for an unwritable cache file), AHLP_EHIP. */
+ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* measured,
+                            hipStream_t stream);
+
 /* The Mehrotra predictor-corrector loop (Sec. 2.3) around factor and solve.
  * x, z: DEVICE [n_tot], y: DEVICE [m_tot]; outputs, and inputs when
  * opts->start == 1.  Synchronous.  res (host) receives the summary.

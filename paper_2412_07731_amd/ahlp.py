@@ -67,6 +67,7 @@ SIGNATURES = {
                          C.c_int),
     "ahlp_problem_set_bc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "ahlp_problem_set_launch": ([C.c_void_p, C.c_int32], C.c_int),
+    "ahlp_autotune": ([C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
     "ahlp_ipm_solve": ([C.c_void_p, C.POINTER(IpmOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                         C.POINTER(IpmResult), C.c_void_p], C.c_int),
     "ahlp_last_error": ([], C.c_char_p),
@@ -198,6 +199,14 @@ class Problem:
                                       _dptr(wy), _dptr(wz), int(max_refine), float(refine_tol),
                                       C.byref(be), _stream(stream)))
         return wx, wy, wz, be.value
+
+    def autotune(self, cache_path=None, stream=None):
+        """Pick the block-factor kernel per bordered tile-row count (ahlp_autotune);
+        returns how many counts were measured (0: all from the cache)."""
+        n = C.c_int32(0)
+        path = cache_path.encode() if cache_path else None
+        _check(lib().ahlp_autotune(self.h, path, C.byref(n), _stream(stream)))
+        return n.value
 
     def set_launch(self, per_block):
         """Batched launches (default) or one launch per block (ahlp_problem_set_launch)."""

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -161,6 +164,9 @@ struct ahlp_problem_s {
   // per-block launch mode (the reference the batched launches are compared
   // with): block i's SYRK items, link items, and its index in an identity list
   int launch_mode = AHLP_LAUNCH_BATCHED;
+  // block-factor kernel per bordered tile-row count (0 panel, 1 column; the
+  // default rule is panel wherever it fits); set by ahlp_autotune
+  std::vector<int> bf_kernel;
   std::vector<int> syrk_off, syrk_cnt, link_off, link_cnt;
   int* ident = nullptr;
   int2* link_items = nullptr;
@@ -243,6 +249,36 @@ ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
 }
 
 // ------------------------------------------------------------- factor
+// Block-factor buckets: blocks largest first (rt, then mt, then nt), the
+// panel-kernel bucket then the column-kernel bucket; sets n_panel, n_col,
+// rt_panel, rt_col.  The kernel per rt follows bf_kernel (autotuned) or the
+// default rule.
+std::vector<int> bf_buckets(ahlp_problem_t p) {
+  const int N = p->N;
+  std::vector<int> bysize(N);
+  for (int i = 0; i < N; ++i) bysize[i] = i;
+  std::stable_sort(bysize.begin(), bysize.end(), [&](int a, int c) {
+    const BlockInfo &x = p->hb[a], &y = p->hb[c];
+    if (x.rt != y.rt) return x.rt > y.rt;
+    if (x.mt != y.mt) return x.mt > y.mt;
+    return x.nt > y.nt;
+  });
+  auto panel = [&](int rt) {
+    if (!block_factor_panel_fits(rt)) return false;
+    const int k = rt < (int)p->bf_kernel.size() ? p->bf_kernel[rt] : -1;
+    return k != 1;
+  };
+  std::vector<int> out;
+  p->rt_panel = p->rt_col = 0;
+  for (int i : bysize)
+    if (panel(p->hb[i].rt)) { out.push_back(i); p->rt_panel = std::max(p->rt_panel, p->hb[i].rt); }
+  p->n_panel = (int)out.size();
+  for (int i : bysize)
+    if (!panel(p->hb[i].rt)) { out.push_back(i); p->rt_col = std::max(p->rt_col, p->hb[i].rt); }
+  p->n_col = N - p->n_panel;
+  return out;
+}
+
 // The same kernels, one launch per block and stage, in block order on st:
 // the reference for the batched launches (identical arithmetic per block).
 template <typename T>
@@ -259,7 +295,7 @@ ahlp_status_t factor_blocks_per_block(ahlp_problem_t p, hipStream_t st, T* LB, T
   p->timer.begin(AHLP_ST_FACTOR);
   for (int i = 0; i < p->N; ++i) {
     const int rt = p->hb[i].rt;
-    if (block_factor_panel_fits(rt))
+    if (block_factor_panel_fits(rt) && p->bf_kernel[rt] != 1)
       launch_block_factor_panel<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info);
     else
       launch_block_factor_col<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info);
@@ -856,13 +892,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   std::vector<int> syrk_order;
   for (int ch = 0; ch < 8; ++ch)
     for (int k = ch; k < N; k += 8) syrk_order.push_back(bysize[k]);
-  std::vector<int> hbf;
-  for (int i : bysize)
-    if (block_factor_panel_fits(p->hb[i].rt)) { hbf.push_back(i); p->rt_panel = std::max(p->rt_panel, p->hb[i].rt); }
-  p->n_panel = (int)hbf.size();
-  for (int i : bysize)
-    if (!block_factor_panel_fits(p->hb[i].rt)) { hbf.push_back(i); p->rt_col = std::max(p->rt_col, p->hb[i].rt); }
-  p->n_col = N - p->n_panel;
+  p->bf_kernel.assign(p->max_rt + 1, -1);
+  std::vector<int> hbf = bf_buckets(p);
   std::vector<int4> hsyrk;
   std::vector<int2> hlink, hrow, hcolt, hc0;
   p->syrk_off.assign(N, 0); p->syrk_cnt.assign(N, 0);
@@ -1131,6 +1162,110 @@ ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double*
   CHK(ahlp_kkt_solve(p, gx, gy, p->adj_rz, wx, wy, wz, max_refine, refine_tol, bkerr, st));
   launch_adj_scale(st, p->n_tot, 1, p->zs, wz, wz);
   HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
+namespace {
+std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+}  // namespace
+
+ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* measured,
+                            hipStream_t st) {
+  g_err.clear();
+  if (!p) return fail(AHLP_EINVAL, "null argument");
+  if (measured) *measured = 0;
+  const std::string arch = arch_name(p->device);
+  // rt values with a choice to make
+  std::vector<int> todo;
+  for (int rt = 1; rt <= p->max_rt; ++rt) {
+    if (!block_factor_panel_fits(rt)) continue;
+    bool present = false;
+    for (const auto& b : p->hb) present = present || b.rt == rt;
+    if (present) todo.push_back(rt);
+  }
+  // cached entries: "<arch> <rt> <panel|column> <us panel> <us column>"
+  std::vector<std::string> keep;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string a, k;
+      int rt = 0;
+      if (line.empty() || line[0] == '#' || !(ls >> a >> rt >> k)) continue;
+      keep.push_back(line);
+      if (a == arch && rt >= 1 && rt <= p->max_rt && (k == "panel" || k == "column"))
+        p->bf_kernel[rt] = k == "panel" ? 0 : 1;
+    }
+  }
+  std::vector<int> need;
+  for (int rt : todo)
+    if (p->bf_kernel[rt] < 0) need.push_back(rt);
+  std::vector<std::string> fresh;
+  if (!need.empty()) {
+    // inputs of the block factor at x = z = 1: D, then M_i and B_i' rebuilt
+    // by the SYRK and the link gather before every timed launch
+    const int saved_mode = p->launch_mode;
+    const double rho = 1e-8, delta = 1e-6;
+    p->delta = delta;
+    launch_fill(st, p->n_tot, 1.0, p->ones);
+    CHK(prep_scaling(p, p->ones, p->ones, rho, st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::vector<int> hblk;
+    for (int rt : need) {
+      hblk.clear();
+      for (int i = 0; i < p->N; ++i)
+        if (p->hb[i].rt == rt) hblk.push_back(i);
+      HIPCHK(hipMemcpyAsync(p->bf_order, hblk.data(), sizeof(int) * hblk.size(), hipMemcpyHostToDevice, st));
+      double best[2] = {1e30, 1e30};
+      for (int rep = 0; rep < 2; ++rep)
+        for (int k = 0; k < 2; ++k) {
+          launch_link<double>(st, p->blk, p->link_items, p->nlink, p->n0, p->A, p->C, p->lptr,
+                              p->lcol, p->lval, p->Dp, p->LB, p->PQ);
+          launch_syrk<double>(st, p->blk, p->syrk_items, p->nsyrk, p->A, p->Dp, p->LB, delta);
+          HIPCHK(hipEventRecord(e0, st));
+          if (k == 0)
+            launch_block_factor_panel<double>(st, p->blk, p->bf_order, (int)hblk.size(), rt, p->LB,
+                                              p->LINV, p->PQ, p->info);
+          else
+            launch_block_factor_col<double>(st, p->blk, p->bf_order, (int)hblk.size(), rt, p->LB,
+                                            p->LINV, p->PQ, p->info);
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          best[k] = std::min(best[k], 1e3 * (double)ms);
+        }
+      p->bf_kernel[rt] = best[0] <= best[1] ? 0 : 1;
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "%s %d %s %.1f %.1f", arch.c_str(), rt,
+                    p->bf_kernel[rt] == 0 ? "panel" : "column", best[0], best[1]);
+      fresh.push_back(buf);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->launch_mode = saved_mode;
+    p->factored = false;   // the tuning runs overwrote the factors
+    if (measured) *measured = (int32_t)need.size();
+    if (cache_path) {
+      std::ofstream out(cache_path);
+      out << "# block-factor kernel per bordered tile-row count: arch rt kernel us_panel us_column\n";
+      for (const auto& l : keep) out << l << "\n";
+      for (const auto& l : fresh) out << l << "\n";
+      if (!out) return fail(AHLP_EINVAL, "cannot write the tuning cache %s", cache_path);
+    }
+  }
+  std::vector<int> hbf = bf_buckets(p);
+  HIPCHK(hipMemcpyAsync(p->bf_order, hbf.data(), sizeof(int) * hbf.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
   return AHLP_OK;
 }
 

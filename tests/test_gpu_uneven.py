@@ -79,3 +79,28 @@ def test_uneven_full_size_against_oracle(dev):
         assert abs(r["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))
     finally:
         P.close()
+
+
+def test_autotune_table(dev, tmp_path):
+    from paper_2412_07731_amd.ahlp import Problem
+    print("case: autotune uneven N=48 seed 1", flush=True)
+    inst = gen.generate("uneven", 1, N=48)
+    path = str(tmp_path / "tune.txt")
+    P = Problem(inst)
+    try:
+        n = P.autotune(path)
+        rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+        assert n >= 1 and len(rows) == n
+        for arch, rt, kern, us_p, us_c in rows:
+            assert 1 <= int(rt) <= 20
+            assert kern == ("panel" if float(us_p) <= float(us_c) else "column")
+        x, y, z, r = P.ipm()
+        assert r["status"] == 0
+        assert abs(r["primal_obj"] - inst.fstar) <= 1e-7 * max(1.0, abs(inst.fstar))
+    finally:
+        P.close()
+    P2 = Problem(inst)
+    try:
+        assert P2.autotune(path) == 0          # every entry from the cache
+    finally:
+        P2.close()
