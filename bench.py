@@ -9,11 +9,12 @@ iteration runs the whole hot path: residuals, D-scaling and link columns, block
 SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
 factorization, predictor and corrector solves with FP64 refinement.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--profile]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--no-uneven] [--profile]
 
 The line also carries the sensitivity workload (N=256, nondegenerate): the
 differentiable solve, one backward pass (transposed Newton solve) and 64
-forward derivatives, with the gradient's error against the LP closed forms.
+forward derivatives, with the gradient's error against the LP closed forms;
+and the uneven-block workload (N=2048) with batched and per-block launches.
 
 Prints one JSON line.
 """
@@ -143,6 +144,50 @@ def sens_bench(dev, ndir=64, reps=3):
             "objective_rel_err": abs(float(f.detach()) - inst.fstar) / abs(inst.fstar)}
 
 
+def uneven_bench(steps=3):
+    """Uneven-block workload: N=2048 blocks, m_i ~ U{64..512}, n_i = 2 m_i (10%
+    nonzero, stored dense), l_j ~ U{4..32}, 64 linking variables, seed 0.
+    FP64 interior-point iterations/s with batched launches (blocks sorted
+    largest first, block factor in two buckets, kernel per bucket autotuned),
+    and one factorization with batched launches against one launch per block
+    and stage (same kernels, bitwise-identical results)."""
+    import torch
+    from paper_2412_07731_amd import gen
+    from paper_2412_07731_amd.ahlp import Problem
+    inst = gen.generate("uneven", 0)
+    P = Problem(inst)
+    out = {"workload": "uneven: N=2048 blocks m_i~U{64..512}, n_i=2m_i (10% nonzero, stored dense), "
+                       "l_j~U{4..32}, 64 linking variables, seed 0", "unit": "IPM iterations/s"}
+    t = time.perf_counter()
+    out["autotuned_rt_values"] = P.autotune()
+    out["autotune_s"] = time.perf_counter() - t
+    P.ipm()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = 0
+    for _ in range(steps):
+        x, _, z, r = P.ipm()
+        its += r["iterations"]
+    torch.cuda.synchronize()
+    out["value"] = its / (time.perf_counter() - t)
+    out["iterations"] = r["iterations"]
+    out["objective_rel_err_vs_known_optimum"] = abs(r["primal_obj"] - inst.fstar) / abs(inst.fstar)
+    # one factorization (a1-a6) at the end point, batched and per block
+    for per_block, reps in ((False, 5), (True, 1)):
+        P.set_launch(per_block=per_block)
+        P.factor(x, z, 1e-8, 1e-6)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            P.factor(x, z, 1e-8, 1e-6)
+        torch.cuda.synchronize()
+        out["factor_ms_per_block" if per_block else "factor_ms_batched"] = 1e3 * (time.perf_counter() - t) / reps
+    P.set_launch(per_block=False)
+    P.close()
+    out["batched_factor_speedup"] = out["factor_ms_per_block"] / out["factor_ms_batched"]
+    return out
+
+
 def run(P, steps, warmup, **opts):
     import torch
     for _ in range(warmup):
@@ -167,6 +212,7 @@ def main():
     ap.add_argument("--fp32", action="store_true", help="time the FP32+refine path as the main line")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-sens", action="store_true", help="skip the sensitivity workload")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-block workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -269,6 +315,8 @@ def main():
             "speedup_vs_fp64": (it32 / dt32) / (iters / dt)}
     if not args.no_sens and not args.profile and not args.fp32:
         line["sensitivity"] = sens_bench(torch.device("cuda", 0))
+    if not args.no_uneven and not args.profile and not args.fp32:
+        line["uneven"] = uneven_bench()
     if not args.no_cpu and not args.profile:
         line["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters)
     P.close()
