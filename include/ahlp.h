@@ -106,6 +106,11 @@ typedef struct {
                           /* 0.1; 0 = only the refine_tol backward error).  FP32 that   */
                           /* cannot reach either test switches the run to FP64 and     */
                           /* the iteration is redone with FP64 factors.                */
+  int32_t graph;          /* 1 = capture each iteration's factorization (a1-a6) as a */
+                          /* hipGraph on the first iteration and replay it (results  */
+                          /* identical to 0); ignored when timing != 0.  The solve   */
+                          /* then runs on a library stream ordered after and before  */
+                          /* the caller's stream.  0 by default                      */
 } ahlp_ipm_opts_t;
 
 /* Stage indices of ahlp_ipm_result_t.t_stage_ms / n_stage. */

@@ -39,7 +39,7 @@ class IpmOpts(C.Structure):
                 ("rho", C.c_double), ("delta", C.c_double), ("max_refine", C.c_int32),
                 ("refine_tol", C.c_double), ("precision", C.c_int), ("mu_switch", C.c_double),
                 ("start", C.c_int32), ("verbose", C.c_int32), ("timing", C.c_int32),
-                ("fp32_accept", C.c_double)]
+                ("fp32_accept", C.c_double), ("graph", C.c_int32)]
 
 
 class IpmResult(C.Structure):

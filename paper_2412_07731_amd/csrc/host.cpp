@@ -217,6 +217,18 @@ struct ahlp_problem_s {
   // the block factor
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // graph mode of ahlp_ipm_solve: the solve runs on gstream (capturable; event
+  // fork/join with the caller's stream) and each iteration's factorization is
+  // a replay of a captured graph, one per precision, recaptured when x, z,
+  // rho or delta change
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_gin = nullptr, ev_gout = nullptr;
+  bool use_graph = false;
+  struct FactorGraph {
+    hipGraphExec_t exec = nullptr;
+    const double *x = nullptr, *z = nullptr;
+    double rho = 0.0, delta = 0.0;
+  } fgraph[2];
   StageTimer timer;
   double rows_bytes = 0.0;      // algorithmic bytes of the timed row passes
   double a_bytes = 0, c_bytes = 0, xv_bytes = 0, x0_bytes = 0, yv_bytes = 0;
@@ -224,6 +236,11 @@ struct ahlp_problem_s {
   // host-side handles (device buffers are released by mem); also runs when
   // creation fails part way
   ~ahlp_problem_s() {
+    for (auto& g : fgraph)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (ev_gin) (void)hipEventDestroy(ev_gin);
+    if (ev_gout) (void)hipEventDestroy(ev_gout);
+    if (gstream) (void)hipStreamDestroy(gstream);
     if (h_scal) (void)hipHostFree(h_scal);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -380,7 +397,8 @@ ahlp_status_t ensure_fp32(ahlp_problem_t p, hipStream_t st) {
 // D-scaling of (x, z) and the info reset (a1); the factor assumes it ran.
 ahlp_status_t prep_scaling(ahlp_problem_t p, const double* x, const double* z, double rho,
                            hipStream_t st) {
-  HIPCHK(hipMemsetAsync(p->info, 0, sizeof(DevInfo), st));
+  static_assert(sizeof(DevInfo) <= sizeof(double), "DevInfo lives in one scalar slot");
+  launch_fill(st, 1, 0.0, reinterpret_cast<double*>(p->info));   // a kernel, not a memset: capturable
   p->timer.begin(AHLP_ST_PREP);
   launch_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, rho, p->Dp, p->xs, p->zs,
               p->info);
@@ -411,6 +429,38 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
   else launch_chain_factor(st, chain_args(p));
   p->timer.end();
   HIPCHK(hipGetLastError());
+  p->factored = true;
+  return AHLP_OK;
+}
+
+// The factorization (prep already done) as a replay of a captured graph.
+ahlp_status_t factor_graphed(ahlp_problem_t p, const double* x, const double* z, int prec,
+                             double rho, double delta, hipStream_t st) {
+  if (prec == AHLP_FP32_REFINE) CHK(ensure_fp32(p, st));   // allocates: never inside a capture
+  auto& g = p->fgraph[prec == AHLP_FP32_REFINE ? 1 : 0];
+  if (!g.exec || g.x != x || g.z != z || g.rho != rho || g.delta != delta) {
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    }
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    const ahlp_status_t s = do_factor(p, x, z, prec, rho, delta, st, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s != AHLP_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(AHLP_EHIP, "graph capture of the factorization: %s", hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(AHLP_EHIP, "graph instantiation: %s", hipGetErrorString(ei));
+    g.x = x; g.z = z; g.rho = rho; g.delta = delta;
+  }
+  HIPCHK(hipGraphLaunch(g.exec, st));
+  p->rho = rho;
+  p->delta = delta;
+  p->fprec = prec;
   p->factored = true;
   return AHLP_OK;
 }
@@ -1062,6 +1112,9 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->adj_rz, p->n_tot));
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_gin, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_gout, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
 
@@ -1108,7 +1161,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   }
   launch_fill(st, p->n_tot, 1.0, p->ones);
   launch_fill(st, p->n_tot, 0.0, p->zerosn);
-  HIPCHK(hipMemsetAsync(p->info, 0, sizeof(DevInfo), st));
+  static_assert(sizeof(DevInfo) <= sizeof(double), "DevInfo lives in one scalar slot");
+  launch_fill(st, 1, 0.0, reinterpret_cast<double*>(p->info));   // a kernel, not a memset: capturable
   if (chain_sh > 64 * 1024) set_chain_smem_limits(chain_sh);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
@@ -1297,10 +1351,30 @@ ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const doubl
   return AHLP_OK;
 }
 
+ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double* x, double* y,
+                             double* z, ahlp_ipm_result_t* res, hipStream_t st);
+
 ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double* x, double* y,
                              double* z, ahlp_ipm_result_t* res, hipStream_t st) {
   g_err.clear();
   if (!p || !o || !x || !y || !z) return fail(AHLP_EINVAL, "null argument");
+  if (o->graph && !o->timing) {
+    // graph mode: run on the library's capturable stream, ordered after and
+    // before the caller's stream by events
+    HIPCHK(hipEventRecord(p->ev_gin, st));
+    HIPCHK(hipStreamWaitEvent(p->gstream, p->ev_gin, 0));
+    p->use_graph = true;
+    const ahlp_status_t s = ipm_solve_impl(p, o, x, y, z, res, p->gstream);
+    p->use_graph = false;
+    HIPCHK(hipEventRecord(p->ev_gout, p->gstream));
+    HIPCHK(hipStreamWaitEvent(st, p->ev_gout, 0));
+    return s;
+  }
+  return ipm_solve_impl(p, o, x, y, z, res, st);
+}
+
+ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double* x, double* y,
+                             double* z, ahlp_ipm_result_t* res, hipStream_t st) {
   const auto t0 = std::chrono::steady_clock::now();
   ahlp_ipm_result_t R;
   std::memset(&R, 0, sizeof R);
@@ -1432,7 +1506,10 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     // FP32 refinement that stagnates or runs out sets *ok = false.
     auto pass = [&](bool f32, bool* ok) -> ahlp_status_t {
       *ok = true;
-      CHK(do_factor(p, x, z, f32 ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st, true));
+      if (p->use_graph)
+        CHK(factor_graphed(p, x, z, f32 ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st));
+      else
+        CHK(do_factor(p, x, z, f32 ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st, true));
       const double atol = f32 ? o->fp32_accept * mu : 0.0;
       auto acceptable = [&](double b) {
         return b <= o->refine_tol || (atol > 0.0 && check_en(p) <= atol);
