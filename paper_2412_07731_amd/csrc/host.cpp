@@ -135,6 +135,19 @@ struct StageTimer {
 
 }  // namespace
 
+// Segments of an interior-point iteration between host synchronizations:
+// A = factorization + predictor (+ check, step lengths, mu_aff), B = corrector
+// (+ check, step lengths), per factor precision; C = step + next residuals.
+enum { SEG_A64 = 0, SEG_A32, SEG_B64, SEG_B32, SEG_C, SEG_COUNT };
+// What a captured segment bakes in besides the problem's own buffers.
+struct SegKey {
+  const double *x, *y, *z;
+  double rho, delta, eta;
+  bool operator==(const SegKey& o) const {
+    return x == o.x && y == o.y && z == o.z && rho == o.rho && delta == o.delta && eta == o.eta;
+  }
+};
+
 struct ahlp_problem_s {
   int device = 0;
   int N = 0, n0 = 0, n0p = 0, P = 0, G = 0;
@@ -218,17 +231,15 @@ struct ahlp_problem_s {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // graph mode of ahlp_ipm_solve: the solve runs on gstream (capturable; event
-  // fork/join with the caller's stream) and each iteration's factorization is
-  // a replay of a captured graph, one per precision, recaptured when x, z,
-  // rho or delta change
+  // fork/join with the caller's stream) and the three host-sync-free segments
+  // of an iteration are replays of captured graphs (see run_segment)
   hipStream_t gstream = nullptr;
   hipEvent_t ev_gin = nullptr, ev_gout = nullptr;
   bool use_graph = false;
-  struct FactorGraph {
+  struct SegGraph {
     hipGraphExec_t exec = nullptr;
-    const double *x = nullptr, *z = nullptr;
-    double rho = 0.0, delta = 0.0;
-  } fgraph[2];
+    SegKey key{};
+  } graphs[SEG_COUNT];
   StageTimer timer;
   double rows_bytes = 0.0;      // algorithmic bytes of the timed row passes
   double a_bytes = 0, c_bytes = 0, xv_bytes = 0, x0_bytes = 0, yv_bytes = 0;
@@ -236,7 +247,7 @@ struct ahlp_problem_s {
   // host-side handles (device buffers are released by mem); also runs when
   // creation fails part way
   ~ahlp_problem_s() {
-    for (auto& g : fgraph)
+    for (auto& g : graphs)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (ev_gin) (void)hipEventDestroy(ev_gin);
     if (ev_gout) (void)hipEventDestroy(ev_gout);
@@ -253,7 +264,7 @@ namespace {
 constexpr int NSCAL = 32;
 // scal slots: 0-5 residual stage, 9 |K| norm, 10-12 step lengths and mu_aff,
 // 20-28 refinement check (|r|, |e|, |d| per block row), 31 device info
-constexpr int S_AP = 10, S_AD = 11, S_MUAFF = 12, S_RN = 20, S_EN = 23, S_DN = 26;
+constexpr int S_AP = 10, S_AD = 11, S_MUAFF = 12, S_SMU = 13, S_RN = 20, S_EN = 23, S_DN = 26;
 static_assert(sizeof(DevInfo) <= sizeof(double), "device info must fit one scal slot");
 
 ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
@@ -433,35 +444,35 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
   return AHLP_OK;
 }
 
-// The factorization (prep already done) as a replay of a captured graph.
-ahlp_status_t factor_graphed(ahlp_problem_t p, const double* x, const double* z, int prec,
-                             double rho, double delta, hipStream_t st) {
-  if (prec == AHLP_FP32_REFINE) CHK(ensure_fp32(p, st));   // allocates: never inside a capture
-  auto& g = p->fgraph[prec == AHLP_FP32_REFINE ? 1 : 0];
-  if (!g.exec || g.x != x || g.z != z || g.rho != rho || g.delta != delta) {
+// Runs fn on st: directly, or in graph mode as a replay of its captured graph
+// (captured on first use and whenever the key changes).  fn must launch work
+// on st only (forks to the side stream join back), without host
+// synchronization, allocation or memset; the kernels and arguments it records
+// are then the same on every replay, so a replay equals a direct run.
+template <typename F>
+ahlp_status_t run_segment(ahlp_problem_t p, int id, const SegKey& key, hipStream_t st, F&& fn) {
+  if (!p->use_graph) return fn();
+  auto& g = p->graphs[id];
+  if (!g.exec || !(g.key == key)) {
     if (g.exec) {
       (void)hipGraphExecDestroy(g.exec);
       g.exec = nullptr;
     }
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-    const ahlp_status_t s = do_factor(p, x, z, prec, rho, delta, st, true);
+    const ahlp_status_t s = fn();
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &graph);
     if (s != AHLP_OK) {
       if (graph) (void)hipGraphDestroy(graph);
       return s;
     }
-    if (e != hipSuccess) return fail(AHLP_EHIP, "graph capture of the factorization: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(AHLP_EHIP, "graph capture: %s", hipGetErrorString(e));
     const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return fail(AHLP_EHIP, "graph instantiation: %s", hipGetErrorString(ei));
-    g.x = x; g.z = z; g.rho = rho; g.delta = delta;
+    g.key = key;
   }
   HIPCHK(hipGraphLaunch(g.exec, st));
-  p->rho = rho;
-  p->delta = delta;
-  p->fprec = prec;
-  p->factored = true;
   return AHLP_OK;
 }
 
@@ -1458,7 +1469,9 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   double mu = 0, pobj = 0, dobj = 0, relgap = 0, pinf = 0, dinf = 0;
   const DevInfo* hinfo = reinterpret_cast<const DevInfo*>(p->h_scal + NSCAL - 1);
   const double* hs = p->h_scal;
-  while (true) {
+  SegKey key{x, y, z, o->rho, o->delta, o->eta};
+  // residuals of the current iterate (the start of every iteration)
+  auto resid_stage = [&]() -> ahlp_status_t {
     p->timer.begin(AHLP_ST_RESID);
     CHK(prep_scaling(p, x, z, o->rho, st));
     apply_At(p, y, 1, p->c, z, p->rd, st);                          // r_d = c - A'y - z
@@ -1479,6 +1492,18 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
         .add(RED_MAXABS, m, p->rp, nullptr, 3).add(RED_MAXABS, n, p->rd, nullptr, 4)
         .add(RED_MAXSUM, n, x, z, 5).launch(st);
     p->timer.end();
+    return AHLP_OK;
+  };
+  // the step with the ratio-test results on the device, then the next
+  // iteration's residuals
+  auto step_resid = [&]() -> ahlp_status_t {
+    launch_step(st, n, o->eta, p->scal + S_AP, p->dx, x);
+    launch_step(st, m, o->eta, p->scal + S_AD, p->dy, y);
+    launch_step(st, n, o->eta, p->scal + S_AD, p->dz, z);
+    return resid_stage();
+  };
+  CHK(resid_stage());
+  while (true) {
     CHK(read_scal(p, NSCAL, st));
     if (hinfo->nonfinite)
       return fail(AHLP_ENUMERIC, "x or z left the positive orthant or became non-finite");
@@ -1506,20 +1531,14 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     // FP32 refinement that stagnates or runs out sets *ok = false.
     auto pass = [&](bool f32, bool* ok) -> ahlp_status_t {
       *ok = true;
-      if (p->use_graph)
-        CHK(factor_graphed(p, x, z, f32 ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st));
-      else
-        CHK(do_factor(p, x, z, f32 ? AHLP_FP32_REFINE : AHLP_FP64, o->rho, o->delta, st, true));
+      const int prec = f32 ? AHLP_FP32_REFINE : AHLP_FP64;
+      if (prec == AHLP_FP32_REFINE) CHK(ensure_fp32(p, st));   // allocates: before any capture
       const double atol = f32 ? o->fp32_accept * mu : 0.0;
       auto acceptable = [&](double b) {
         return b <= o->refine_tol || (atol > 0.0 && check_en(p) <= atol);
       };
       double be = 0.0;
       int steps = 0;
-      // predictor (rz_a = -x z; t_a from the residual pass)
-      launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);
-      CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, st, p->ta));
-      check_pass(p, p->rd, p->rp, p->rzv, p->dxa, p->dza, true, st);
       auto muaff_launch = [&]() {
         Reds Rm(p);
         Rm.add(RED_MUAFF, n, x, p->dxa, S_MUAFF, z, p->dza);
@@ -1527,12 +1546,23 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
         Rm.m.r[0].ps2 = p->scal + S_AD;
         Rm.launch(st);
       };
-      {
+      // factorization and predictor (rz_a = -x z; t_a from the residual pass),
+      // its check, step lengths and mu_aff
+      CHK(run_segment(p, f32 ? SEG_A32 : SEG_A64, key, st, [&]() -> ahlp_status_t {
+        CHK(do_factor(p, x, z, prec, o->rho, o->delta, st, true));
+        launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);
+        CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, st, p->ta));
+        check_pass(p, p->rd, p->rp, p->rzv, p->dxa, p->dza, true, st);
         Reds Rp(p);
         add_check_reds(p, Rp, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, true);
         Rp.add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
         muaff_launch();
-      }
+        return AHLP_OK;
+      }));
+      p->rho = o->rho;
+      p->delta = o->delta;
+      p->fprec = prec;
+      p->factored = true;
       CHK(read_scal(p, NSCAL, st));
       double rn = check_rn(p);
       be = check_bkerr(p, kn, rn);
@@ -1550,18 +1580,19 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       }
       account(be, steps);
       if (o->verbose > 1) fprintf(stderr, "ahlp   predictor bkerr %.2e refine %d\n", be, steps);
-      const double mu_aff = hs[S_MUAFF] / (double)n;
-      const double sigma = std::pow(mu_aff / mu, 3.0);
-      // corrector: rz_c and t_c = t_a - sigma mu A(D/x) + A(D dxa dza / x)
-      launch_rz(st, n, 1, x, z, p->dxa, p->dza, sigma * mu, p->rzv);
-      launch_combine(st, p->vp_total, p->ta, sigma * mu, p->aw1, p->aw2, p->tc);
-      CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, st, p->tc));
-      check_pass(p, p->rd, p->rp, p->rzv, p->dx, p->dz, false, st);
-      {
+      // corrector: sigma mu on the device, rz_c and
+      // t_c = t_a - sigma mu A(D/x) + A(D dxa dza / x), solve, check, step lengths
+      CHK(run_segment(p, f32 ? SEG_B32 : SEG_B64, key, st, [&]() -> ahlp_status_t {
+        launch_sigma_mu(st, p->scal, n, 0, S_MUAFF, S_SMU);
+        launch_rz(st, n, 1, x, z, p->dxa, p->dza, 0.0, p->rzv, p->scal + S_SMU);
+        launch_combine(st, p->vp_total, p->ta, 0.0, p->aw1, p->aw2, p->tc, p->scal + S_SMU);
+        CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, st, p->tc));
+        check_pass(p, p->rd, p->rp, p->rzv, p->dx, p->dz, false, st);
         Reds Rc(p);
         add_check_reds(p, Rc, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, true);
         Rc.add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
-      }
+        return AHLP_OK;
+      }));
       CHK(read_scal(p, NSCAL, st));
       rn = check_rn(p);
       be = check_bkerr(p, kn, rn);
@@ -1595,16 +1626,18 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     }
     if (!ok) CHK(pass(false, &ok));
     total_piv += hinfo->pivots;
+    // the same step lengths as the step kernels take on the device
     const double ap = std::min(1.0, o->eta * hs[S_AP]);
     const double ad = std::min(1.0, o->eta * hs[S_AD]);
-    launch_axpy(st, n, ap, p->dx, x);
-    launch_axpy(st, m, ad, p->dy, y);
-    launch_axpy(st, n, ad, p->dz, z);
     ++k;
     if (ap < 1e-12 && ad < 1e-12) {
+      launch_step(st, n, o->eta, p->scal + S_AP, p->dx, x);
+      launch_step(st, m, o->eta, p->scal + S_AD, p->dy, y);
+      launch_step(st, n, o->eta, p->scal + S_AD, p->dz, z);
       status = AHLP_WSTALL;
       break;
     }
+    CHK(run_segment(p, SEG_C, key, st, step_resid));
   }
   HIPCHK(hipStreamSynchronize(st));
   p->timer.collect();

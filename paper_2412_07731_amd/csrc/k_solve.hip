@@ -591,11 +591,32 @@ __global__ void k_wscaled(const BlockInfo* __restrict__ blk, int N, int n0, long
 
 // out = t - smu a + b
 __global__ void k_combine(long long n, const double* __restrict__ t, double smu,
-                          const double* __restrict__ a, const double* __restrict__ b,
-                          double* __restrict__ out) {
+                          const double* __restrict__ smu_dev, const double* __restrict__ a,
+                          const double* __restrict__ b, double* __restrict__ out) {
+  if (smu_dev) smu = *smu_dev;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     out[i] = (t[i] - smu * a[i]) + b[i];
+}
+
+// Mehrotra's centering target sigma mu = (mu_aff / mu)^3 mu from the reduction
+// slots (sums x'z and (x + a_p dxa)'(z + a_d dza)), on the device so that the
+// corrector needs no host value.  One thread.
+__global__ void k_sigma_mu(double* __restrict__ scal, double inv_n, int s_xz, int s_muaff,
+                           int s_out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double mu = scal[s_xz] * inv_n;
+  const double r = scal[s_muaff] * inv_n / mu;
+  scal[s_out] = r * r * r * mu;
+}
+
+// Step x += min(1, eta * ratio) d with the ratio-test result on the device.
+__global__ void k_step(long long n, double eta, const double* __restrict__ ratio,
+                       const double* __restrict__ d, double* __restrict__ x) {
+  const double a = fmin(1.0, eta * *ratio);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] += a * d[i];
 }
 
 // Copy x0 part of the Schur solution into dx.
@@ -609,7 +630,9 @@ __global__ void k_copy(long long n, const double* __restrict__ src, double* __re
 //   mode 0: rz = -x z;   mode 1: rz = sigma mu - x z - dxa dza  (sigma*mu in *smu)
 __global__ void k_rz(long long n, int mode, const double* __restrict__ x,
                      const double* __restrict__ z, const double* __restrict__ dxa,
-                     const double* __restrict__ dza, double sm, double* __restrict__ rz) {
+                     const double* __restrict__ dza, double sm, const double* __restrict__ sm_dev,
+                     double* __restrict__ rz) {
+  if (sm_dev) sm = *sm_dev;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     double v = -x[i] * z[i];
@@ -757,8 +780,15 @@ void launch_wscaled(hipStream_t st, const BlockInfo* blk, int N, int n0, long lo
                      Dp, w);
 }
 void launch_combine(hipStream_t st, long long n, const double* t, double smu, const double* a,
-                    const double* b, double* out) {
-  hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, st, n, t, smu, a, b, out);
+                    const double* b, double* out, const double* smu_dev) {
+  hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, st, n, t, smu, smu_dev, a, b, out);
+}
+void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out) {
+  hipLaunchKernelGGL(k_sigma_mu, dim3(1), dim3(64), 0, st, scal, 1.0 / (double)n, s_xz, s_muaff, s_out);
+}
+void launch_step(hipStream_t st, long long n, double eta, const double* ratio, const double* d,
+                 double* x) {
+  if (n > 0) hipLaunchKernelGGL(k_step, dim3(grid1d(n)), dim3(256), 0, st, n, eta, ratio, d, x);
 }
 void launch_pad_y(hipStream_t st, const BlockInfo* blk, int N, const double* y, double* yp) {
   hipLaunchKernelGGL(k_pad_y, dim3(N), dim3(256), 0, st, blk, y, yp);
@@ -893,8 +923,9 @@ void launch_copy(hipStream_t st, long long n, const double* src, double* dst) {
   if (n > 0) hipLaunchKernelGGL(k_copy, dim3(grid1d(n)), dim3(256), 0, st, n, src, dst);
 }
 void launch_rz(hipStream_t st, long long n, int mode, const double* x, const double* z,
-               const double* dxa, const double* dza, double smu, double* rz) {
-  hipLaunchKernelGGL(k_rz, dim3(grid1d(n)), dim3(256), 0, st, n, mode, x, z, dxa, dza, smu, rz);
+               const double* dxa, const double* dza, double smu, double* rz, const double* smu_dev) {
+  hipLaunchKernelGGL(k_rz, dim3(grid1d(n)), dim3(256), 0, st, n, mode, x, z, dxa, dza, smu, smu_dev,
+                     rz);
 }
 void launch_fill(hipStream_t st, long long n, double v, double* dst) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(256), 0, st, n, v, dst);

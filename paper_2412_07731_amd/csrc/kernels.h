@@ -137,8 +137,14 @@ void launch_wscaled(hipStream_t st, const BlockInfo* blk, int N, int n0, long lo
                     long long d0off, const double* a, const double* b, const double* xs,
                     const double* Dp, double* w);
 // out = t - smu * a + b over n values
+// out = t - smu a + b; smu from *smu_dev when that is not null
 void launch_combine(hipStream_t st, long long n, const double* t, double smu, const double* a,
-                    const double* b, double* out);
+                    const double* b, double* out, const double* smu_dev = nullptr);
+// scal[s_out] = (mu_aff / mu)^3 mu with mu = scal[s_xz] / n, mu_aff = scal[s_muaff] / n
+void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out);
+// x += min(1, eta * ratio[0]) d
+void launch_step(hipStream_t st, long long n, double eta, const double* ratio, const double* d,
+                 double* x);
 void launch_rows_multi(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
                        const double* A, const double* C, long long d0off, const RowsArgs& ra);
 void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
@@ -194,8 +200,10 @@ void launch_res_x(hipStream_t st, long long n, const double* rx, const double* r
                   const double* g, const double* dx, const double* dz, const double* xs,
                   const double* zs, double* ex, double* ez);
 void launch_copy(hipStream_t st, long long n, const double* src, double* dst);
+// rz = -x z (mode 0) or smu - x z - dxa dza (mode 1); smu from *smu_dev when not null
 void launch_rz(hipStream_t st, long long n, int mode, const double* x, const double* z,
-               const double* dxa, const double* dza, double smu, double* rz);
+               const double* dxa, const double* dza, double smu, double* rz,
+               const double* smu_dev = nullptr);
 void launch_fill(hipStream_t st, long long n, double v, double* dst);
 void launch_addscalar(hipStream_t st, long long n, double v, double* dst);
 void launch_reduce(hipStream_t st, int op, long long n, const double* a, const double* b,
