@@ -106,11 +106,14 @@ typedef struct {
                           /* 0.1; 0 = only the refine_tol backward error).  FP32 that   */
                           /* cannot reach either test switches the run to FP64 and     */
                           /* the iteration is redone with FP64 factors.                */
-  int32_t graph;          /* 1 = capture each iteration's factorization (a1-a6) as a */
-                          /* hipGraph on the first iteration and replay it (results  */
+  int32_t graph;          /* 1 = capture the three parts of an iteration between its */
+                          /* host reads (factorization + predictor, corrector, step  */
+                          /* + residuals) as hipGraphs once and replay them (results */
                           /* identical to 0); ignored when timing != 0.  The solve   */
                           /* then runs on a library stream ordered after and before  */
                           /* the caller's stream.  0 by default                      */
+  int32_t gondzio;        /* at most this many Gondzio centrality correctors per     */
+                          /* iteration after Mehrotra's corrector (0 by default)      */
 } ahlp_ipm_opts_t;
 
 /* Stage indices of ahlp_ipm_result_t.t_stage_ms / n_stage. */
@@ -140,6 +143,7 @@ typedef struct {
   int32_t n_stage[AHLP_ST_COUNT];     /* number of timed launches per stage         */
   double rows_bytes;      /* algorithmic HBM bytes of the timed row passes          */
                           /* (AHLP_ST_AROWS): A and C read, vectors read and written */
+  int32_t correctors;     /* Gondzio correctors kept over the whole run             */
 } ahlp_ipm_result_t;
 
 /* Fills *opts with the defaults listed above. */

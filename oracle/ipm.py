@@ -40,6 +40,14 @@ class Options:
     delta: float = 1e-6
     max_refine: int = 5
     refine_tol: float = 1e-10
+    # Gondzio's multiple centrality correctors after Mehrotra's corrector
+    # (the paper's IPM extends Mehrotra's scheme with them; the constants are
+    # readings): at most `gondzio` correctors per iteration
+    gondzio: int = 0
+    g_beta_min: float = 0.1
+    g_beta_max: float = 10.0
+    g_delta_a: float = 0.1
+    g_gamma: float = 0.1
 
 
 @dataclass
@@ -163,15 +171,46 @@ def solve(inst, opts: Options = None, verbose=False, max_iter=None):
         d, be = solve_refined(inst, f, (rd, rp, rc), kn, opts, stats)
         ap = min(1.0, opts.eta * _ratio_max(x, d[0]))
         ad = min(1.0, opts.eta * _ratio_max(z, d[2]))
+        ncorr = 0
+        for _ in range(opts.gondzio):
+            d, ap, ad, ok = gondzio_corrector(inst, f, x, z, d, ap, ad, sigma * mu, kn, opts, stats)
+            if not ok:
+                break
+            ncorr += 1
         x = x + ap * d[0]
         y = y + ad * d[1]
         z = z + ad * d[2]
         hist.append(dict(k=k, mu=mu, relgap=relgap, pinf=pinf, dinf=dinf,
-                         sigma=sigma, ap=ap, ad=ad, bkerr=be))
+                         sigma=sigma, ap=ap, ad=ad, bkerr=be, correctors=ncorr))
         k += 1
     return Result(status=status, iterations=k, x=x, y=y, z=z, pobj=pobj, dobj=dobj,
                   relgap=relgap, pinf=pinf, dinf=dinf, mu=mu, pivots=stats["pivots"],
                   refine_steps=stats["refine"], max_bkerr=stats["bkerr"], history=hist)
+
+
+def gondzio_corrector(inst, f, x, z, d, ap, ad, smu, kn, opts, stats):
+    """One multiple-centrality corrector (Gondzio).  Aim for step lengths
+    longer by delta_a; at the trial point of those lengths the complementarity
+    products v are moved into [beta_min, beta_max] sigma mu (a product above
+    the box decreases by at most beta_max sigma mu); the correction solves the
+    Newton system with right-hand side (0, 0, t - v).  It is kept when the
+    smaller step length grows by at least gamma delta_a.  Returns the
+    direction, the step lengths and whether the corrector was kept."""
+    if ap >= 1.0 and ad >= 1.0:
+        return d, ap, ad, False
+    at_p = min(1.0, ap + opts.g_delta_a)
+    at_d = min(1.0, ad + opts.g_delta_a)
+    v = (x + at_p * d[0]) * (z + at_d * d[2])
+    lo, hi = opts.g_beta_min * smu, opts.g_beta_max * smu
+    r = np.maximum(np.clip(v, lo, hi) - v, -hi)
+    n, m = x.size, d[1].size
+    dc, _ = solve_refined(inst, f, (np.zeros(n), np.zeros(m), r), kn, opts, stats)
+    dn = tuple(a + b for a, b in zip(d, dc))
+    ap_n = min(1.0, opts.eta * _ratio_max(x, dn[0]))
+    ad_n = min(1.0, opts.eta * _ratio_max(z, dn[2]))
+    if min(ap_n, ad_n) >= min(ap, ad) + opts.g_gamma * opts.g_delta_a:
+        return dn, ap_n, ad_n, True
+    return d, ap, ad, False
 
 
 def _ratio_max(v, dv):

@@ -39,7 +39,7 @@ class IpmOpts(C.Structure):
                 ("rho", C.c_double), ("delta", C.c_double), ("max_refine", C.c_int32),
                 ("refine_tol", C.c_double), ("precision", C.c_int), ("mu_switch", C.c_double),
                 ("start", C.c_int32), ("verbose", C.c_int32), ("timing", C.c_int32),
-                ("fp32_accept", C.c_double), ("graph", C.c_int32)]
+                ("fp32_accept", C.c_double), ("graph", C.c_int32), ("gondzio", C.c_int32)]
 
 
 class IpmResult(C.Structure):
@@ -49,7 +49,7 @@ class IpmResult(C.Structure):
                 ("rel_pinf", C.c_double), ("rel_dinf", C.c_double), ("mu", C.c_double),
                 ("max_bkerr", C.c_double), ("t_total_ms", C.c_double),
                 ("t_stage_ms", C.c_double * 8), ("n_stage", C.c_int32 * 8),
-                ("rows_bytes", C.c_double)]
+                ("rows_bytes", C.c_double), ("correctors", C.c_int32)]
 
 
 # Every exported symbol with its signature (argtypes, restype).

@@ -221,6 +221,8 @@ struct ahlp_problem_s {
   double *ta = nullptr, *aw1 = nullptr, *aw2 = nullptr, *tc = nullptr, *w1p = nullptr,
          *w2p = nullptr, *gc = nullptr;
   double* adj_rz = nullptr;   // z g_z of the transposed solve
+  // Gondzio correctors: right-hand side, candidate direction, zero y-vector
+  double *g_r = nullptr, *g_dx = nullptr, *g_dy = nullptr, *g_dz = nullptr, *zerosm = nullptr;
   double *rp = nullptr, *rd = nullptr, *rzv = nullptr, *dxa = nullptr, *dya = nullptr,
          *dza = nullptr, *dx = nullptr, *dy = nullptr, *dz = nullptr;
   double *red_part = nullptr, *scal = nullptr;
@@ -264,7 +266,8 @@ namespace {
 constexpr int NSCAL = 32;
 // scal slots: 0-5 residual stage, 9 |K| norm, 10-12 step lengths and mu_aff,
 // 20-28 refinement check (|r|, |e|, |d| per block row), 31 device info
-constexpr int S_AP = 10, S_AD = 11, S_MUAFF = 12, S_SMU = 13, S_RN = 20, S_EN = 23, S_DN = 26;
+constexpr int S_AP = 10, S_AD = 11, S_MUAFF = 12, S_SMU = 13, S_GP = 14, S_GD = 15, S_RN = 20,
+              S_EN = 23, S_DN = 26;
 static_assert(sizeof(DevInfo) <= sizeof(double), "device info must fit one scal slot");
 
 ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
@@ -1121,6 +1124,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (double** v : {&p->w1p, &p->w2p}) CHK(M.alloc(v, p->dp_total));
   CHK(M.alloc(&p->gc, p->n_tot));
   CHK(M.alloc(&p->adj_rz, p->n_tot));
+  for (double** v : {&p->g_r, &p->g_dx, &p->g_dz}) CHK(M.alloc(v, p->n_tot));
+  for (double** v : {&p->g_dy, &p->zerosm}) CHK(M.alloc(v, p->m_tot));
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
@@ -1171,6 +1176,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     HIPCHK(hipMemcpyAsync(p->d_suboff, p->suboff.data(), sizeof(long long) * p->G, hipMemcpyHostToDevice, st));
   }
   launch_fill(st, p->n_tot, 1.0, p->ones);
+  launch_fill(st, p->m_tot, 0.0, p->zerosm);
   launch_fill(st, p->n_tot, 0.0, p->zerosn);
   static_assert(sizeof(DevInfo) <= sizeof(double), "DevInfo lives in one scalar slot");
   launch_fill(st, 1, 0.0, reinterpret_cast<double*>(p->info));   // a kernel, not a memset: capturable
@@ -1627,8 +1633,40 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     if (!ok) CHK(pass(false, &ok));
     total_piv += hinfo->pivots;
     // the same step lengths as the step kernels take on the device
-    const double ap = std::min(1.0, o->eta * hs[S_AP]);
-    const double ad = std::min(1.0, o->eta * hs[S_AD]);
+    double ap = std::min(1.0, o->eta * hs[S_AP]);
+    double ad = std::min(1.0, o->eta * hs[S_AD]);
+    // Gondzio's multiple centrality correctors: aim for step lengths longer by
+    // delta_a, move the complementarity products at that trial point into
+    // [beta_min, beta_max] sigma mu, solve with right-hand side (0, 0, t - v)
+    // and keep the corrected direction if the smaller step grows by at least
+    // gamma delta_a (constants as in the oracle)
+    for (int j = 0; j < o->gondzio; ++j) {
+      if (ap >= 1.0 && ad >= 1.0) break;
+      constexpr double beta_min = 0.1, beta_max = 10.0, delta_a = 0.1, gamma = 0.1;
+      const double at_p = std::min(1.0, ap + delta_a), at_d = std::min(1.0, ad + delta_a);
+      launch_gondzio_rhs(st, n, x, z, p->dx, p->dz, at_p, at_d, p->scal + S_SMU, beta_min,
+                         beta_max, p->g_r);
+      double gbe = 0.0;
+      int gsteps = 0;
+      CHK(solve_refined(p, p->zerosn, p->zerosm, p->g_r, p->g_dx, p->g_dy, p->g_dz,
+                        o->max_refine, o->refine_tol, kn, &gbe, &gsteps, st));
+      account(gbe, gsteps);
+      launch_axpy(st, n, 1.0, p->dx, p->g_dx);
+      launch_axpy(st, m, 1.0, p->dy, p->g_dy);
+      launch_axpy(st, n, 1.0, p->dz, p->g_dz);
+      Reds(p).add(RED_RATIO, n, x, p->g_dx, S_GP).add(RED_RATIO, n, z, p->g_dz, S_GD).launch(st);
+      CHK(read_scal(p, NSCAL, st));
+      const double ap_n = std::min(1.0, o->eta * hs[S_GP]);
+      const double ad_n = std::min(1.0, o->eta * hs[S_GD]);
+      if (!(std::min(ap_n, ad_n) >= std::min(ap, ad) + gamma * delta_a)) break;
+      launch_copy(st, n, p->g_dx, p->dx);
+      launch_copy(st, m, p->g_dy, p->dy);
+      launch_copy(st, n, p->g_dz, p->dz);
+      launch_copy(st, 2, p->scal + S_GP, p->scal + S_AP);   // the step kernels read S_AP, S_AD
+      ap = ap_n;
+      ad = ad_n;
+      R.correctors++;
+    }
     ++k;
     if (ap < 1e-12 && ad < 1e-12) {
       launch_step(st, n, o->eta, p->scal + S_AP, p->dx, x);

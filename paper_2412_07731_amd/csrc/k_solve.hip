@@ -610,6 +610,23 @@ __global__ void k_sigma_mu(double* __restrict__ scal, double inv_n, int s_xz, in
   scal[s_out] = r * r * r * mu;
 }
 
+// Right-hand side of a multiple centrality corrector (Gondzio): the
+// complementarity products v at the trial point (x + at_p dx, z + at_d dz)
+// moved into [beta_min, beta_max] sigma mu, a decrease capped at beta_max
+// sigma mu: r = max(clip(v, lo, hi) - v, -hi), sigma mu from *smu.
+__global__ void k_gondzio_rhs(long long n, const double* __restrict__ x,
+                              const double* __restrict__ z, const double* __restrict__ dx,
+                              const double* __restrict__ dz, double at_p, double at_d,
+                              const double* __restrict__ smu, double beta_min, double beta_max,
+                              double* __restrict__ r) {
+  const double lo = beta_min * *smu, hi = beta_max * *smu;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = (x[i] + at_p * dx[i]) * (z[i] + at_d * dz[i]);
+    r[i] = fmax(fmin(fmax(v, lo), hi) - v, -hi);
+  }
+}
+
 // Step x += min(1, eta * ratio) d with the ratio-test result on the device.
 __global__ void k_step(long long n, double eta, const double* __restrict__ ratio,
                        const double* __restrict__ d, double* __restrict__ x) {
@@ -785,6 +802,13 @@ void launch_combine(hipStream_t st, long long n, const double* t, double smu, co
 }
 void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out) {
   hipLaunchKernelGGL(k_sigma_mu, dim3(1), dim3(64), 0, st, scal, 1.0 / (double)n, s_xz, s_muaff, s_out);
+}
+void launch_gondzio_rhs(hipStream_t st, long long n, const double* x, const double* z,
+                        const double* dx, const double* dz, double at_p, double at_d,
+                        const double* smu, double beta_min, double beta_max, double* r) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_gondzio_rhs, dim3(grid1d(n)), dim3(256), 0, st, n, x, z, dx, dz, at_p,
+                       at_d, smu, beta_min, beta_max, r);
 }
 void launch_step(hipStream_t st, long long n, double eta, const double* ratio, const double* d,
                  double* x) {

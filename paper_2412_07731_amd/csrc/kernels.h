@@ -142,6 +142,11 @@ void launch_combine(hipStream_t st, long long n, const double* t, double smu, co
                     const double* b, double* out, const double* smu_dev = nullptr);
 // scal[s_out] = (mu_aff / mu)^3 mu with mu = scal[s_xz] / n, mu_aff = scal[s_muaff] / n
 void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out);
+// r = max(clip(v, lo, hi) - v, -hi), v = (x + at_p dx)(z + at_d dz), [lo, hi] =
+// [beta_min, beta_max] * smu[0] (a Gondzio corrector's right-hand side)
+void launch_gondzio_rhs(hipStream_t st, long long n, const double* x, const double* z,
+                        const double* dx, const double* dz, double at_p, double at_d,
+                        const double* smu, double beta_min, double beta_max, double* r);
 // x += min(1, eta * ratio[0]) d
 void launch_step(hipStream_t st, long long n, double eta, const double* ratio, const double* d,
                  double* x);

@@ -16,32 +16,37 @@ from oracle import ipm  # noqa: E402
 from paper_2412_07731_amd import gen  # noqa: E402
 
 
-def run(config, seed):
+def run(config, seed, gondzio=0):
     inst = gen.generate(config, seed)
     t = time.time()
-    r = ipm.solve(inst)
-    return dict(config=config, seed=seed, status=r.status, iterations=r.iterations,
+    r = ipm.solve(inst, ipm.Options(gondzio=gondzio))
+    return dict(config=config, seed=seed, gondzio=gondzio, status=r.status, iterations=r.iterations,
                 pobj=r.pobj, dobj=r.dobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
                 mu=r.mu, fstar=inst.fstar, refine_steps=r.refine_steps,
                 max_bkerr=r.max_bkerr, pivots=r.pivots,
                 mu_trace=[h["mu"] for h in r.history],
+                correctors=sum(h.get("correctors", 0) for h in r.history),
                 seconds=round(time.time() - t, 2))
 
 
 def main():
     """No arguments: rewrite the file with tiny (seeds 0-7) and n512 (seed 0).
-    --quick: tiny only.  --add CONFIG:SEED [...]: run just those and merge
-    them into the existing file (e.g. --add uneven:0, the N=2048 workload,
-    which takes minutes and several GB)."""
+    --quick: tiny only.  --add CONFIG:SEED[:gK] [...]: run just those (with K
+    Gondzio correctors per iteration if gK is given) and merge them into the
+    existing file (e.g. --add uneven:0, the N=2048 workload, which takes
+    minutes and several GB)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_ipm.json")
     if "--add" in sys.argv:
         out = json.load(open(path))
         for spec in sys.argv[sys.argv.index("--add") + 1:]:
-            config, seed = spec.split(":")
-            r = run(config, int(seed))
-            out["runs"] = [q for q in out["runs"] if (q["config"], q["seed"]) != (config, int(seed))]
+            parts = spec.split(":")
+            config, seed = parts[0], int(parts[1])
+            g = int(parts[2][1:]) if len(parts) > 2 else 0      # CONFIG:SEED:gK = K correctors
+            r = run(config, seed, g)
+            out["runs"] = [q for q in out["runs"]
+                           if (q["config"], q["seed"], q.get("gondzio", 0)) != (config, seed, g)]
             out["runs"].append(r)
-            print(config, seed, r["status"], r["iterations"], r["seconds"], "s", flush=True)
+            print(config, seed, g, r["status"], r["iterations"], r["seconds"], "s", flush=True)
     else:
         out = {"note": "FP64 oracle results; written by tests/golden/make_golden.py",
                "runs": []}

@@ -39,7 +39,7 @@ def test_struct_layouts():
     # 2 int32 + 3 pointers + 7 pointers
     assert ctypes.sizeof(ahlp.Desc) == 8 + 10 * 8
     assert ctypes.sizeof(ahlp.FactorOpts) == 24
-    assert ctypes.sizeof(ahlp.IpmResult) == 5 * 4 + 4 + 8 * 8 + 8 * 8 + 8 * 4 + 8
+    assert ctypes.sizeof(ahlp.IpmResult) == 5 * 4 + 4 + 8 * 8 + 8 * 8 + 8 * 4 + 8 + 8
 
 
 def test_library_fails_loudly_when_missing(monkeypatch, tmp_path):

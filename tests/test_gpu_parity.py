@@ -22,9 +22,9 @@ from paper_2412_07731_amd import gen  # noqa: E402
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_ipm.json")))
 
 
-def golden(config, seed):
+def golden(config, seed, gondzio=0):
     for r in GOLDEN["runs"]:
-        if r["config"] == config and r["seed"] == seed:
+        if r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio:
             return r
     raise KeyError((config, seed))
 

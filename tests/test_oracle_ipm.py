@@ -76,3 +76,57 @@ def test_kkt_norm_is_row_sum_norm(tiny):
     rowabs, colabs = lp.abs_row_col_sums(tiny)
     K = dense_kkt.newton_matrix(tiny, x, z)
     assert abs(lp.kkt_inf_norm(rowabs, colabs, x, z) - np.max(np.abs(K).sum(axis=1))) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_gondzio_reaches_known_optimum(seed):
+    """With up to two Gondzio correctors per iteration the end state is still
+    the generator's optimum and no iteration count grows."""
+    inst = gen.generate("tiny", seed)
+    r0 = ipm.solve(inst)
+    r2 = ipm.solve(inst, ipm.Options(gondzio=2))
+    assert r2.status == "optimal"
+    assert abs(r2.pobj - inst.fstar) <= 1e-7 * max(1.0, abs(inst.fstar))
+    assert r2.iterations <= r0.iterations
+    assert sum(h["correctors"] for h in r2.history) > 0
+
+
+def test_gondzio_corrector_step(tiny):
+    """One corrector at the first iteration: its correction solves the Newton
+    system with right-hand side (0, 0, r) to dense-LU accuracy, the targets
+    v + r lie in [beta_min, beta_max] sigma mu wherever v did not exceed the
+    box, and a kept correction lengthens the smaller step by gamma delta_a."""
+    from oracle import dense_kkt, newton
+    inst = tiny
+    opts = ipm.Options(gondzio=1)
+    rowabs, colabs = lp.abs_row_col_sums(inst)
+    stats = {"pivots": 0, "refine": 0, "bkerr": 0.0}
+    x, y, z = ipm.starting_point(inst, rowabs, colabs, opts, stats)
+    rp = inst.b - lp.matvec(inst, x)
+    rd = inst.c - lp.rmatvec(inst, y) - z
+    mu = float(x @ z) / inst.n_tot
+    f = newton.factor(inst, x, z, opts.rho, opts.delta)
+    kn = lp.kkt_inf_norm(rowabs, colabs, x, z)
+    da, _ = ipm.solve_refined(inst, f, (rd, rp, -x * z), kn, opts, stats)
+    ap_a, ad_a = ipm.ratio(x, da[0]), ipm.ratio(z, da[2])
+    smu = (float((x + ap_a * da[0]) @ (z + ad_a * da[2])) / inst.n_tot / mu) ** 3 * mu
+    d, _ = ipm.solve_refined(inst, f, (rd, rp, smu - x * z - da[0] * da[2]), kn, opts, stats)
+    ap = min(1.0, opts.eta * ipm._ratio_max(x, d[0]))
+    ad = min(1.0, opts.eta * ipm._ratio_max(z, d[2]))
+    dn, ap_n, ad_n, kept = ipm.gondzio_corrector(inst, f, x, z, d, ap, ad, smu, kn, opts, stats)
+    assert kept
+    assert min(ap_n, ad_n) >= min(ap, ad) + opts.g_gamma * opts.g_delta_a
+    at_p, at_d = min(1.0, ap + opts.g_delta_a), min(1.0, ad + opts.g_delta_a)
+    v = (x + at_p * d[0]) * (z + at_d * d[2])
+    lo, hi = opts.g_beta_min * smu, opts.g_beta_max * smu
+    dc = [a - b for a, b in zip(dn, d)]
+    # the correction's right-hand side, recovered from the Newton matrix
+    K = dense_kkt.newton_matrix(inst, x, z)
+    rhs = K @ np.concatenate(dc)
+    n, m = inst.n_tot, inst.m_tot
+    assert np.max(np.abs(rhs[:n + m])) <= 1e-8 * np.max(np.abs(rhs))
+    r = rhs[n + m:]
+    inside = v <= hi
+    assert np.all(v[inside] + r[inside] >= lo * (1 - 1e-8))
+    assert np.all(v[inside] + r[inside] <= hi * (1 + 1e-8))
+    assert np.all(r >= -hi * (1 + 1e-8))
