@@ -14,7 +14,8 @@ factorization, predictor and corrector solves with FP64 refinement.
 The line also carries the sensitivity workload (N=256, nondegenerate): the
 differentiable solve, one backward pass (transposed Newton solve) and 64
 forward derivatives, with the gradient's error against the LP closed forms;
-and the uneven-block workload (N=2048) with batched and per-block launches.
+the uneven-block workload (N=2048) with batched and per-block launches; and
+the N=512 solve with Gondzio correctors.
 
 Prints one JSON line.
 """
@@ -313,6 +314,25 @@ def main():
             "objective_rel_err_vs_oracle": (abs(r32["primal_obj"] - golden["pobj"]) / max(1.0, abs(golden["pobj"]))
                                             if golden else None),
             "speedup_vs_fp64": (it32 / dt32) / (iters / dt)}
+    if not args.profile and not args.fp32:
+        # Gondzio correctors (two at most per iteration): fewer iterations,
+        # more solves per factorization; compared by time to solution
+        dtg, resg = run(P, args.steps, args.warmup, precision=FP64, gondzio=2)
+        itg = sum(r["iterations"] for r in resg)
+        rg = resg[-1]
+        gg = None
+        if os.path.exists(gpath):
+            for r in json.load(open(gpath))["runs"]:
+                if r["config"] == "n512" and r["seed"] == 0 and r.get("gondzio", 0) == 2:
+                    gg = r
+        line["gondzio"] = {
+            "correctors_max": 2, "value": itg / dtg, "unit": "IPM iterations/s",
+            "iterations_per_solve": rg["iterations"], "correctors_per_solve": rg["correctors"],
+            "oracle_iterations": gg["iterations"] if gg else None,
+            "ms_per_solve": 1e3 * dtg / args.steps,
+            "ms_per_solve_without": 1e3 * dt / args.steps,
+            "objective_rel_err_vs_oracle": (abs(rg["primal_obj"] - gg["pobj"]) / max(1.0, abs(gg["pobj"]))
+                                            if gg else None)}
     if not args.no_sens and not args.profile and not args.fp32:
         line["sensitivity"] = sens_bench(torch.device("cuda", 0))
     if not args.no_uneven and not args.profile and not args.fp32:
