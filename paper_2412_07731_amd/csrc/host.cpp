@@ -198,8 +198,9 @@ struct ahlp_problem_s {
   double *Td = nullptr, *To = nullptr, *E = nullptr, *S00 = nullptr, *thrT = nullptr;
   double *CL = nullptr, *CLi = nullptr, *CYn = nullptr, *CZ = nullptr, *CG = nullptr,
          *CSub = nullptr, *Lb = nullptr, *Lbi = nullptr, *S00w = nullptr, *segout = nullptr;
-  // tile path of the Schur factorization (pairs <= 16 rows, n0 <= 64)
-  bool fast = false;
+  // tile path of the Schur factorization (pairs <= 32 rows, n0 <= 64)
+  bool fast = false;          // Schur factor by cyclic reduction (else the segmented chain)
+  int tp = 0;                 // its tiles per pair side
   int t0 = 0, s00_chunk = 16, s00_parts = 0;
   double *BD = nullptr, *BC = nullptr, *BEt = nullptr, *FLi = nullptr, *FXL = nullptr,
          *FXR = nullptr, *FGt = nullptr, *FLb = nullptr, *FLbi = nullptr, *s00part = nullptr;
@@ -387,7 +388,7 @@ ChainArgs chain_args(ahlp_problem_t p) {
 
 BcrArgs bcr_args(ahlp_problem_t p) {
   BcrArgs c{};
-  c.P = p->P; c.n0 = p->n0; c.t0 = p->t0;
+  c.P = p->P; c.n0 = p->n0; c.t0 = p->t0; c.tp = p->tp;
   c.l = p->d_l; c.tdoff = p->d_tdoff; c.tooff = p->d_tooff; c.eoff = p->d_eoff;
   c.Td = p->Td; c.To = p->To; c.E = p->E; c.S00 = p->S00; c.thrT = p->thrT;
   c.BD = p->BD; c.BC = p->BC; c.BEt = p->BEt;
@@ -1073,7 +1074,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->Lb, std::max(n0 * n0, 1)));
   CHK(M.alloc(&p->Lbi, std::max(n0 * n0, 1)));
   CHK(M.alloc(&p->S00w, std::max(n0 * n0, 1)));
-  p->fast = bcr_supported(p->lmax, n0);
+  p->tp = bcr_tiles(p->lmax, n0);
+  p->fast = p->tp > 0;
   for (int i = 0; i < N; ++i) {
     p->a_bytes += 8.0 * p->m[i] * p->n[i];
     p->c_bytes += 8.0 * p->m[i] * n0;
@@ -1085,11 +1087,11 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   if (p->fast) {
     const long long Pt = std::max(P, 1);
     p->s00_parts = P > 0 ? (P + p->s00_chunk - 1) / p->s00_chunk : 0;
-    const long long T0 = std::max(p->t0, 1);
-    for (double** v : {&p->BD, &p->BC, &p->FLi, &p->FXL, &p->FXR}) CHK(M.alloc(v, Pt * 256));
-    CHK(M.alloc(&p->BEt, Pt * T0 * 256));
-    CHK(M.alloc(&p->FGt, Pt * T0 * 256));
-    for (double** v : {&p->br, &p->bw, &p->bup}) CHK(M.alloc(v, Pt * 16));
+    const long long T0 = std::max(p->t0, 1), tp = p->tp;
+    for (double** v : {&p->BD, &p->BC, &p->FLi, &p->FXL, &p->FXR}) CHK(M.alloc(v, Pt * tp * tp * 256));
+    CHK(M.alloc(&p->BEt, Pt * tp * T0 * 256));
+    CHK(M.alloc(&p->FGt, Pt * tp * T0 * 256));
+    for (double** v : {&p->br, &p->bw, &p->bup}) CHK(M.alloc(v, Pt * tp * 16));
     CHK(M.alloc(&p->bpb, Pt * T0 * 16));
     CHK(M.alloc(&p->bu0p, T0 * 16));
     CHK(M.alloc(&p->s00part, (long long)std::max(p->s00_parts, 1) * std::max(p->t0 * p->t0, 1) * 256));

@@ -1,5 +1,6 @@
 // Block cyclic reduction of the Schur complement (a6) for link pairs of at
-// most 16 rows and at most 64 linking variables.
+// most 16 rows and at most 64 linking variables (pairs of up to 32 rows:
+// k_bcr2.hip, which shares the border kernels below).
 //
 // The assembled Schur complement is S = [T E; E' S00] with T block
 // tridiagonal over the P link pairs (App. A) and E, S00 the x_0 border.  T is
@@ -31,6 +32,7 @@
 #include "kernels.h"
 #include "tile_chol.h"
 #include "tile_ops.h"
+#include "bcr_border.h"
 
 namespace ahlp {
 
@@ -191,7 +193,9 @@ __global__ __launch_bounds__(128) void k_bcr_level(BcrArgs c, int lvl, int n) {
         acc_store(c.BEt + (e * c.t0 + q) * 256, et[q]);
       }
   }
-  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
+  // o_l is also the right neighbour of the even pair k - 2: its pivots are
+  // counted there
+  if (threadIdx.x == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
 }
 
 // Narrow levels from lvl (n active pairs) down to one pair, then the final
@@ -257,17 +261,20 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail(BcrArgs c, int lvl
   if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
 }
 
-// Partial sums of Z_j'Z_j = FGt_j FGt_j' over contiguous chunks of pairs.
+// Partial sums of Z_j'Z_j = FGt_j FGt_j' over contiguous chunks of pairs
+// (pair j's tile (q, c) of FGt at (j tp + c) t0 + q).
 __global__ __launch_bounds__(64) void k_bcr_s00_partial(BcrArgs c, int chunk) {
-  const int t0 = c.t0;
+  const int t0 = c.t0, tp = c.tp;
   const int k0 = blockIdx.x * chunk, k1 = min(c.P, k0 + chunk);
   double* out = c.s00part + (long long)blockIdx.x * t0 * t0 * 256;
   for (int q = 0; q < t0; ++q)
     for (int q2 = 0; q2 < t0; ++q2) {
       d4 acc = acc_zero();
       for (int k = k0; k < k1; ++k)
-        acc = mma_xyt(acc, c.FGt + ((long long)k * t0 + q) * 256,
-                      c.FGt + ((long long)k * t0 + q2) * 256, 1.0);
+        for (int cc = 0; cc < tp; ++cc) {
+          const long long base = ((long long)k * tp + cc) * t0;
+          acc = mma_xyt(acc, c.FGt + (base + q) * 256, c.FGt + (base + q2) * 256, 1.0);
+        }
       acc_store(out + (q * t0 + q2) * 256, acc);
     }
 }
@@ -317,44 +324,7 @@ __global__ __launch_bounds__(256) void k_bcr_border(BcrArgs c, int nparts) {
   }
   wave_order();
   const double thr = PIVOT_REL * fmax(s_max, 0.0);
-  int cnt = 0;
-  for (int p = 0; p < t0; ++p) {
-    double* Bpp = B + (p * t0 + p) * 256;
-    cnt += wave_chol_tile<double>(Bpp, Bpp, Ld + p * 256, thr, xbuf);
-    for (int r = p + 1; r < t0; ++r) {
-      d4 acc = mma_xyt(acc_zero(), B + (p * t0 + r) * 256, Ld + p * 256, 1.0);
-      wave_order();
-      acc_store(B + (p * t0 + r) * 256, acc);
-    }
-    wave_order();
-    for (int r = p + 1; r < t0; ++r)
-      for (int cc = p + 1; cc <= r; ++cc) {
-        d4 acc = acc_load(B + (cc * t0 + r) * 256);
-        acc = mma_xyt(acc, B + (p * t0 + r) * 256, B + (p * t0 + cc) * 256, -1.0);
-        wave_order();
-        acc_store(B + (cc * t0 + r) * 256, acc);
-      }
-    wave_order();
-  }
-  // X = L^-1 by block columns
-  for (int cc = 0; cc < t0; ++cc) {
-    for (int r = 0; r < t0; ++r) {
-      if (r < cc) {
-        for (int s = 0; s < 4; ++s) X[(cc * t0 + r) * 256 + 64 * s + lane] = 0.0;
-      } else if (r == cc) {
-        tile_copy(X + (cc * t0 + r) * 256, Ld + r * 256);
-      } else {
-        d4 acc = acc_zero();
-        for (int q = cc; q < r; ++q) acc = mma_xy(acc, B + (q * t0 + r) * 256, X + (cc * t0 + q) * 256, 1.0);
-        acc_store(tmp, acc);
-        wave_order();
-        d4 x = mma_xy(acc_zero(), Ld + r * 256, tmp, -1.0);
-        wave_order();
-        acc_store(X + (cc * t0 + r) * 256, x);
-      }
-      wave_order();
-    }
-  }
+  const int cnt = wave_block_chol(B, t0, X, Ld, tmp, xbuf, thr);
   for (int idx = lane; idx < 256 * t0 * t0; idx += 64) {
     const int tile = idx / 256;
     const int r = tile % t0, cc = tile / t0;
@@ -508,7 +478,7 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail_solve(BcrSolveArgs
   __shared__ double part[64 * TAIL_WAVES];
   __shared__ double s0[16 * BT_MAXT0], w0[16 * BT_MAXT0], u0[16 * BT_MAXT0];
   __shared__ int lv_n[32];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, t0 = c.t0, n0 = c.n0;
+  const int wave = threadIdx.x >> 6;
   const int lvl0 = lvl;
   int nlev = 0;
   for (; n > 1; ++lvl, n = (n + 1) / 2) {
@@ -519,48 +489,7 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail_solve(BcrSolveArgs
   }
   if (n == 1 && wave == 0) bcr_final_fwd(A, lvl, V[0]);
   __syncthreads();
-  // border right-hand side
-  const int nb = 16 * t0;
-  if (nb > 0) {
-    const int nch = (64 * TAIL_WAVES) / nb;
-    const int ch = threadIdx.x / nb, i = threadIdx.x % nb;
-    if (ch < nch) {
-      const int per = (c.P + nch - 1) / nch;
-      const int j0 = ch * per, j1 = min(c.P, j0 + per);
-      double acc = 0.0;
-      for (int j = j0; j < j1; ++j) acc += A.pb[(long long)j * nb + i];
-      part[ch * nb + i] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x < nb) {
-      double acc = 0.0;
-      for (int ch2 = 0; ch2 < nch; ++ch2) acc += part[ch2 * nb + threadIdx.x];
-      s0[threadIdx.x] = (threadIdx.x < n0 ? A.s[A.nl + threadIdx.x] : 0.0) - acc;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      // w0 = Lbi s0, u0 = -Lbi' w0 (lower block-triangular tiles)
-      for (int rr = 0; rr < t0; ++rr) {
-        double acc = 0.0;
-        for (int cc = 0; cc <= rr; ++cc) acc += op_mv(op_load(c.FLbi + (cc * t0 + rr) * 256), s0 + 16 * cc);
-        wave_order();
-        if (lane < 16) w0[16 * rr + lane] = acc;
-        wave_order();
-      }
-      for (int cc = 0; cc < t0; ++cc) {
-        double acc = 0.0;
-        for (int rr = cc; rr < t0; ++rr)
-          acc += op_mtv(op_load(c.FLbi + (cc * t0 + rr) * 256), w0 + 16 * rr, V[0].sc);
-        if (lane < 16) {
-          u0[16 * cc + lane] = -acc;
-          A.u0p[16 * cc + lane] = -acc;
-          if (16 * cc + lane < n0) A.u[A.nl + 16 * cc + lane] = -acc;
-        }
-        wave_order();
-      }
-    }
-    __syncthreads();
-  }
+  bcr_border_solve(A, part, s0, w0, u0, V[0].sc);
   if (c.P >= 1 && wave == 0) bcr_bwd_pair(A, 0, -1, -1, u0, V[0]);
   __syncthreads();
   for (int li = nlev - 1; li >= 0; --li) {
@@ -592,10 +521,15 @@ int tail_level(int P, int* n_out) {
 
 }  // namespace
 
-bool bcr_supported(int lmax, int n0) { return lmax <= 16 && n0 <= 16 * BT_MAXT0; }
+int bcr_tiles(int lmax, int n0) {
+  if (n0 > 16 * BT_MAXT0) return 0;
+  return lmax <= 16 ? 1 : lmax <= 32 ? 2 : 0;
+}
 
 void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk) {
-  if (c.P > 0) {
+  if (c.tp == 2) {
+    launch_bcr2_reduce(st, c);
+  } else if (c.P > 0) {
     const long long tiles = (long long)c.P * (2 + c.t0);
     hipLaunchKernelGGL(k_bcr_init, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, c);
     int nt = 0;
@@ -612,6 +546,10 @@ void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk) 
 }
 
 void launch_bcr_solve(hipStream_t st, const BcrSolveArgs& a) {
+  if (a.c.tp == 2) {
+    launch_bcr2_solve(st, a);
+    return;
+  }
   const int P = a.c.P;
   int nt = 0;
   const int lt = P > 0 ? tail_level(P, &nt) : 0;
@@ -630,6 +568,7 @@ void launch_bcr_solve(hipStream_t st, const BcrSolveArgs& a) {
 void set_bcr_smem_limits() {
   hipFuncSetAttribute((const void*)k_bcr_border, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)border_smem(BT_MAXT0));
+  set_bcr2_smem_limits();
 }
 
 }  // namespace ahlp

@@ -81,13 +81,14 @@ constexpr int SEGRHS_STRIDE = 2 * LMAX + N0MAX;
 // n0 <= 64.  Tiles are 16x16 column-major, padded.
 struct BcrArgs {
   int P, n0, t0;
+  int tp;                                         // tiles per pair side (1 or 2)
   const int* l;
   const long long* tdoff;
   const long long* tooff;
   const long long* eoff;
   const double* Td; const double* To; const double* E; const double* S00; const double* thrT;
-  double* BD; double* BC; double* BEt;            // working tiles (P, P, P*t0)
-  double* FLi; double* FXL; double* FXR; double* FGt;   // factor tiles (P, P, P, P*t0)
+  double* BD; double* BC; double* BEt;            // working tiles (P tp^2, P tp^2, P tp t0)
+  double* FLi; double* FXL; double* FXR; double* FGt;   // factor tiles (same counts)
   double* FLb; double* FLbi;                      // border factor, t0*t0 tiles each
   double* s00part;                                // per chunk of pairs: t0*t0 tiles
   DevInfo* info;
@@ -98,14 +99,21 @@ struct BcrSolveArgs {
   long long nl;
   const double* s;       // right-hand side (exact pair layout, then n0 border values)
   double* u;             // solution, same layout
-  double* r; double* w; double* up;   // padded pair vectors, 16 per pair
+  double* r; double* w; double* up;   // padded pair vectors, 16 tp per pair
   double* pb;            // border partials Z_j' w_j, 16*t0 per pair
   double* u0p;           // border solution, 16*t0
 };
-bool bcr_supported(int lmax, int n0);
+// tiles per pair side of the cyclic-reduction path for these sizes (1 or 2),
+// 0 if it does not apply
+int bcr_tiles(int lmax, int n0);
 void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk);
 void launch_bcr_solve(hipStream_t st, const BcrSolveArgs& a);
 void set_bcr_smem_limits();
+// two-tile pairs (k_bcr2.hip): the reduction of T down to the final pair, and
+// the whole solve
+void launch_bcr2_reduce(hipStream_t st, const BcrArgs& c);
+void launch_bcr2_solve(hipStream_t st, const BcrSolveArgs& a);
+void set_bcr2_smem_limits();
 
 size_t chain_factor_smem(int lmax, int n0);
 void launch_chain_factor(hipStream_t st, const ChainArgs& c);

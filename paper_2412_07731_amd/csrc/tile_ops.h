@@ -135,4 +135,54 @@ __device__ __forceinline__ double vec_get_exact(const double* src, int len) {
   return i < len ? src[i] : 0.0;
 }
 
+// Blocked Cholesky of a t x t matrix of tiles, by one wave.  B holds tile
+// (r, c) at (c t + r) 256 (LDS; only tiles with r >= c are read).  On return
+// those tiles hold the factor L, Ld the inverses of its t diagonal tiles and X
+// (t x t tiles, zero above the diagonal) the block inverse L^-1.  tmp: one
+// tile and xbuf 48 values of LDS scratch.  A pivot <= thr is replaced (the
+// pivot rule); returns the number replaced (all lanes).
+__device__ inline int wave_block_chol(double* B, int t, double* X, double* Ld, double* tmp,
+                                      double* xbuf, double thr) {
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+  for (int p = 0; p < t; ++p) {
+    double* Bpp = B + (p * t + p) * 256;
+    cnt += wave_chol_tile<double>(Bpp, Bpp, Ld + p * 256, thr, xbuf);
+    for (int r = p + 1; r < t; ++r) {
+      d4 acc = mma_xyt(acc_zero(), B + (p * t + r) * 256, Ld + p * 256, 1.0);
+      wave_order();
+      acc_store(B + (p * t + r) * 256, acc);
+    }
+    wave_order();
+    for (int r = p + 1; r < t; ++r)
+      for (int cc = p + 1; cc <= r; ++cc) {
+        d4 acc = acc_load(B + (cc * t + r) * 256);
+        acc = mma_xyt(acc, B + (p * t + r) * 256, B + (p * t + cc) * 256, -1.0);
+        wave_order();
+        acc_store(B + (cc * t + r) * 256, acc);
+      }
+    wave_order();
+  }
+  // X = L^-1 by block columns
+  for (int cc = 0; cc < t; ++cc) {
+    for (int r = 0; r < t; ++r) {
+      if (r < cc) {
+        for (int s = 0; s < 4; ++s) X[(cc * t + r) * 256 + 64 * s + lane] = 0.0;
+      } else if (r == cc) {
+        tile_copy(X + (cc * t + r) * 256, Ld + r * 256);
+      } else {
+        d4 acc = acc_zero();
+        for (int q = cc; q < r; ++q) acc = mma_xy(acc, B + (q * t + r) * 256, X + (cc * t + q) * 256, 1.0);
+        acc_store(tmp, acc);
+        wave_order();
+        d4 x = mma_xy(acc_zero(), Ld + r * 256, tmp, -1.0);
+        wave_order();
+        acc_store(X + (cc * t + r) * 256, x);
+      }
+      wave_order();
+    }
+  }
+  return cnt;
+}
+
 }  // namespace ahlp

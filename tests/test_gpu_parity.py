@@ -74,7 +74,10 @@ SHAPES = [
     dict(N=3, m=17, n=35, l=4, n0=1),             # ragged tiles (17 rows, 35 columns)
     dict(N=6, m=(12, 40), n="2m", l=(1, 20), n0=5),  # uneven blocks and pairs
     dict(N=8, m=32, n=64, l=4, n0=8),              # the tiny workload
-    dict(N=40, m=48, n=96, l=16, n0=32),           # several segments in the chain solve
+    dict(N=40, m=48, n=96, l=16, n0=32),           # one-tile cyclic reduction, six levels
+    dict(N=40, m=(40, 80), n="2m", l=(10, 32), n0=40),  # two-tile pairs (17..32 rows), six levels
+    dict(N=33, m=(36, 60), n="2m", l=(17, 32), n0=64),  # two-tile pairs, full border
+    dict(N=12, m=(48, 80), n="2m", l=(30, 40), n0=6),   # pairs over 32 rows: segmented chain
 ]
 
 
