@@ -27,6 +27,7 @@ __device__ inline void bcr_border_solve(const BcrSolveArgs& A, double* part, dou
     const int per = (c.P + nch - 1) / nch;
     const int j0 = ch * per, j1 = min(c.P, j0 + per);
     double acc = 0.0;
+#pragma unroll 8
     for (int j = j0; j < j1; ++j) acc += A.pb[(long long)j * nb + i];
     part[ch * nb + i] = acc;
   }

@@ -1086,6 +1086,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   p->t0 = (n0 + 15) / 16;
   if (p->fast) {
     const long long Pt = std::max(P, 1);
+    // chunks of at least 16 pairs, at most 64 chunks
+    p->s00_chunk = std::max(16, (P + 63) / 64);
     p->s00_parts = P > 0 ? (P + p->s00_chunk - 1) / p->s00_chunk : 0;
     const long long T0 = std::max(p->t0, 1), tp = p->tp;
     for (double** v : {&p->BD, &p->BC, &p->FLi, &p->FXL, &p->FXR}) CHK(M.alloc(v, Pt * tp * tp * 256));
@@ -1094,7 +1096,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     for (double** v : {&p->br, &p->bw, &p->bup}) CHK(M.alloc(v, Pt * tp * 16));
     CHK(M.alloc(&p->bpb, Pt * T0 * 16));
     CHK(M.alloc(&p->bu0p, T0 * 16));
-    CHK(M.alloc(&p->s00part, (long long)std::max(p->s00_parts, 1) * std::max(p->t0 * p->t0, 1) * 256));
+    CHK(M.alloc(&p->s00part, (long long)(p->s00_parts + 1) * std::max(p->t0 * p->t0, 1) * 256));
     CHK(M.alloc(&p->FLb, (long long)std::max(p->t0 * p->t0, 1) * 256));
     CHK(M.alloc(&p->FLbi, (long long)std::max(p->t0 * p->t0, 1) * 256));
     set_bcr_smem_limits();

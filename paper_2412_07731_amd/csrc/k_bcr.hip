@@ -261,26 +261,40 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail(BcrArgs c, int lvl
   if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
 }
 
-// Partial sums of Z_j'Z_j = FGt_j FGt_j' over contiguous chunks of pairs
-// (pair j's tile (q, c) of FGt at (j tp + c) t0 + q).
+// Partial sums of Z_j'Z_j = FGt_j FGt_j' over contiguous chunks of pairs, one
+// wave per (chunk, border tile (q, q2)).  Pair j's tile (q, c) of FGt is at
+// (j tp + c) t0 + q, so u = j tp + c runs over a chunk's tiles in order.
 __global__ __launch_bounds__(64) void k_bcr_s00_partial(BcrArgs c, int chunk) {
-  const int t0 = c.t0, tp = c.tp;
-  const int k0 = blockIdx.x * chunk, k1 = min(c.P, k0 + chunk);
-  double* out = c.s00part + (long long)blockIdx.x * t0 * t0 * 256;
-  for (int q = 0; q < t0; ++q)
-    for (int q2 = 0; q2 < t0; ++q2) {
-      d4 acc = acc_zero();
-      for (int k = k0; k < k1; ++k)
-        for (int cc = 0; cc < tp; ++cc) {
-          const long long base = ((long long)k * tp + cc) * t0;
-          acc = mma_xyt(acc, c.FGt + (base + q) * 256, c.FGt + (base + q2) * 256, 1.0);
-        }
-      acc_store(out + (q * t0 + q2) * 256, acc);
-    }
+  const int t0 = c.t0, tp = c.tp, nt = t0 * t0;
+  const int part = blockIdx.x / nt, t = blockIdx.x % nt, q = t / t0, q2 = t % t0;
+  const long long u0 = (long long)part * chunk * tp;
+  const long long u1 = (long long)min(c.P, (part + 1) * chunk) * tp;
+  const double* __restrict__ G = c.FGt;
+  d4 acc = acc_zero();
+#pragma unroll 4
+  for (long long u = u0; u < u1; ++u)
+    acc = mma_xyt(acc, G + (u * t0 + q) * 256, G + (u * t0 + q2) * 256, 1.0);
+  acc_store(c.s00part + ((long long)part * nt + t) * 256, acc);
 }
 
-// Border: B = -(S00 - sum of the partials) in t0 x t0 tiles (all four waves,
-// fixed order), then one wave: blocked Cholesky with tile inverses and the
+// Sum of the chunk partials, one thread per element, chunks in order; the
+// sum goes after the nparts partials.
+__global__ __launch_bounds__(256) void k_bcr_s00_sum(BcrArgs c, int nparts) {
+  const int n = c.t0 * c.t0 * 256;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const double* src = c.s00part + idx;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int pp = 0;
+#pragma unroll 4
+  for (; pp + 4 <= nparts; pp += 4)
+    for (int u = 0; u < 4; ++u) acc[u] += src[(long long)(pp + u) * n];
+  for (; pp < nparts; ++pp) acc[0] += src[(long long)pp * n];
+  c.s00part[(long long)nparts * n + idx] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Border: B = -(S00 - sum of Z_j'Z_j) in t0 x t0 tiles (all four waves), then
+// one wave: blocked Cholesky with tile inverses and the
 // block inverse of the factor.
 __global__ __launch_bounds__(256) void k_bcr_border(BcrArgs c, int nparts) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -297,16 +311,8 @@ __global__ __launch_bounds__(256) void k_bcr_border(BcrArgs c, int nparts) {
     const int i = 16 * r + (e & 15), j = 16 * cc + (e >> 4);
     double v;
     if (i < n0 && j < n0) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      const double* src = c.s00part + (long long)(r * t0 + cc) * 256 + e;
-      const long long stride = (long long)t0 * t0 * 256;
-      int pp = 0;
-      for (; pp + 4 <= nparts; pp += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += src[(pp + u) * stride];
-      }
-      for (; pp < nparts; ++pp) acc[0] += src[pp * stride];
-      v = -(c.S00[i + j * n0] - ((acc[0] + acc[1]) + (acc[2] + acc[3])));
+      const double zz = nparts > 0 ? c.s00part[((long long)nparts * t0 * t0 + r * t0 + cc) * 256 + e] : 0.0;
+      v = -(c.S00[i + j * n0] - zz);
     } else {
       v = (i == j) ? 1.0 : 0.0;
     }
@@ -540,7 +546,10 @@ void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk) 
     hipLaunchKernelGGL(k_bcr_tail, dim3(1), dim3(64 * TAIL_WAVES), 0, st, c, lt, nt);
   }
   if (c.n0 > 0) {
-    if (nparts > 0) hipLaunchKernelGGL(k_bcr_s00_partial, dim3(nparts), dim3(64), 0, st, c, chunk);
+    if (nparts > 0) {
+      hipLaunchKernelGGL(k_bcr_s00_partial, dim3(nparts * c.t0 * c.t0), dim3(64), 0, st, c, chunk);
+      hipLaunchKernelGGL(k_bcr_s00_sum, dim3((c.t0 * c.t0 * 256 + 255) / 256), dim3(256), 0, st, c, nparts);
+    }
     hipLaunchKernelGGL(k_bcr_border, dim3(1), dim3(256), border_smem(c.t0), st, c, nparts);
   }
 }

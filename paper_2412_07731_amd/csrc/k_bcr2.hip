@@ -28,10 +28,11 @@ constexpr int TP = 2;                  // tiles per pair side
 constexpr int TB = 16 * TP;            // padded pair size
 constexpr int BLK = TP * TP * 256;     // doubles per pair block
 constexpr int MAXT0 = 4;               // border tiles (n0 <= 64)
-constexpr int MID_WAVES = 8;           // waves of the final-pair and border solve kernel
+constexpr int MID_WAVES = 16;          // waves of the final-pair and border solve kernel
 
-// LDS of one eliminating wave (doubles).  The chol scratch (B, Ld, tmp) is
-// dead once X = L^-1 is formed and is reused for the products.
+// LDS of one eliminating wave (doubles).  The chol scratch (B, Ld, tmp, xbuf)
+// is dead once X = L^-1 is formed and is reused for the products; a
+// workgroup's two regions take 80 KiB, so two workgroups share a CU.
 constexpr int R_X = 0;                         // L^-1, TP x TP tiles
 constexpr int R_B = BLK;                       // working diagonal -> L
 constexpr int R_LD = 2 * BLK;                  // inverted diagonal tiles
@@ -39,9 +40,10 @@ constexpr int R_TMP = R_LD + TP * 256;
 constexpr int R_XL = BLK;                      // X_L (over B)
 constexpr int R_XR = 2 * BLK;                  // X_R (over Ld, tmp)
 constexpr int R_GT = 3 * BLK;                  // Z' (t0 x TP tiles)
-constexpr int R_XBUF = R_GT + MAXT0 * TP * 256;
-constexpr int R_SIZE = R_XBUF + 48;
+constexpr int R_XBUF = R_GT;                   // 48 values (under Z')
+constexpr int R_SIZE = R_GT + MAXT0 * TP * 256;
 static_assert(R_TMP + 256 <= R_GT, "chol scratch overlaps Z'");
+static_assert(2 * R_SIZE * sizeof(double) <= 80 * 1024, "two workgroups per CU");
 
 __device__ __forceinline__ long long et_off(long long j, int q, int cc, int t0) {
   return ((j * TP + cc) * t0 + q) * 256;
@@ -75,42 +77,95 @@ __global__ __launch_bounds__(256) void k_bcr2_init(BcrArgs c) {
   }
 }
 
+// a tile as the B operand of X*Y (element (k, j) of the 16 x 4 slice s)
+__device__ __forceinline__ Op op_load_b(const double* t) {
+  const int lane = threadIdx.x & 63;
+  const int idx = (lane & 15) * TS + (lane >> 4);
+  Op o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[idx + 4 * s];
+  return o;
+}
+__device__ __forceinline__ void op_store(double* t, const Op& o) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) t[64 * s + lane] = o.v[s];
+}
+// acc + alpha * (product of register operands)
+__device__ __forceinline__ d4 mm(d4 acc, const Op& a, const Op& b, double alpha) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma(alpha * a.v[s], b.v[s], acc);
+  return acc;
+}
+
 // Eliminate pair o: blocked Cholesky of its working diagonal, then
 // X_L = L_o^-1 T'[o, L] (if needXL; T'[o, L] is BC[L]),
 // X_R = L_o^-1 T'[R, o]' (if needXR; T'[R, o] is BC[o]) and
-// Z' = E'_o' L_o^-T, all into the wave's LDS region R.  Returns the pivots
-// replaced.
+// Z' = E'_o' L_o^-T, all into the wave's LDS region R.  Every global operand
+// is loaded before the factorization, so the step waits on memory once.
+// Returns the pivots replaced.
 __device__ int elim2(const BcrArgs& c, long long o, long long L, bool needXL, bool needXR,
                      double* R) {
+  const int t0 = c.t0;
   double* X = R + R_X;
   double* B = R + R_B;
   const double* D = c.BD + o * BLK;
-  for (int cc = 0; cc < TP; ++cc)
-    for (int r = cc; r < TP; ++r) tile_copy(B + bt(r, cc), D + bt(r, cc));
-  wave_order();
-  const int cnt = wave_block_chol(B, TP, X, R + R_LD, R + R_TMP, R + R_XBUF, c.thrT[o]);
-  wave_order();
   const double* CL = c.BC + L * BLK;
   const double* Co = c.BC + o * BLK;
+  Op d00 = op_load(D + bt(0, 0)), d10 = op_load(D + bt(1, 0)), d11 = op_load(D + bt(1, 1));
+  Op cl[TP][TP], co[TP][TP], et[TP][MAXT0];
+#pragma unroll
+  for (int q = 0; q < TP; ++q)
+#pragma unroll
+    for (int cc = 0; cc < TP; ++cc) {
+      cl[q][cc] = needXL ? op_load_b(CL + bt(q, cc)) : Op{};
+      co[cc][q] = needXR ? op_load(Co + bt(cc, q)) : Op{};
+    }
+#pragma unroll
+  for (int p = 0; p < TP; ++p)
+#pragma unroll
+    for (int q = 0; q < MAXT0; ++q) et[p][q] = q < t0 ? op_load(c.BEt + et_off(o, q, p, t0)) : Op{};
+  const double thr = c.thrT[o];
+  op_store(B + bt(0, 0), d00);
+  op_store(B + bt(1, 0), d10);
+  op_store(B + bt(1, 1), d11);
+  wave_order();
+  const int cnt = wave_block_chol(B, TP, X, R + R_LD, R + R_TMP, R + R_XBUF, thr);
+  wave_order();
+  Op x[TP][TP];
+#pragma unroll
   for (int r = 0; r < TP; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) x[r][q] = op_load(X + bt(r, q));
+#pragma unroll
+  for (int r = 0; r < TP; ++r)
+#pragma unroll
     for (int cc = 0; cc < TP; ++cc) {
       if (needXL) {
         d4 a = acc_zero();
-        for (int q = 0; q <= r; ++q) a = mma_xy(a, X + bt(r, q), CL + bt(q, cc), 1.0);
+#pragma unroll
+        for (int q = 0; q <= r; ++q) a = mm(a, x[r][q], cl[q][cc], 1.0);
         acc_store(R + R_XL + bt(r, cc), a);
       }
       if (needXR) {
         d4 a = acc_zero();
-        for (int q = 0; q <= r; ++q) a = mma_xyt(a, X + bt(r, q), Co + bt(cc, q), 1.0);
+#pragma unroll
+        for (int q = 0; q <= r; ++q) a = mm(a, x[r][q], co[cc][q], 1.0);
         acc_store(R + R_XR + bt(r, cc), a);
       }
     }
+  // Z'(q, cc) = sum_p E'(q, p) X(cc, p)'; X(cc, p) as the B operand of X*Y'
+  // has the A-operand layout
+#pragma unroll
   for (int cc = 0; cc < TP; ++cc)
-    for (int q = 0; q < c.t0; ++q) {
-      d4 a = acc_zero();
-      for (int p = 0; p <= cc; ++p) a = mma_xyt(a, c.BEt + et_off(o, q, p, c.t0), X + bt(cc, p), 1.0);
-      acc_store(R + R_GT + (cc * c.t0 + q) * 256, a);
-    }
+#pragma unroll
+    for (int q = 0; q < MAXT0; ++q)
+      if (q < t0) {
+        d4 a = acc_zero();
+#pragma unroll
+        for (int p = 0; p <= cc; ++p) a = mm(a, et[p][q], x[cc][p], 1.0);
+        acc_store(R + R_GT + (cc * t0 + q) * 256, a);
+      }
   wave_order();
   return cnt;
 }
@@ -137,6 +192,20 @@ __global__ __launch_bounds__(128) void k_bcr2_level(BcrArgs c, int lvl, int n) {
   const long long s = 1LL << lvl, e = k * s;
   const bool hl = k >= 1, hr = k + 1 < n, hrr = k + 2 < n;
   int cnt = 0;
+  // the even pair's own tiles, loaded before the elimination
+  d4 dp[3], etp[TP][MAXT0];
+  if (wave == 0) {
+    double* D = c.BD + e * BLK;
+    dp[0] = acc_load(D + bt(0, 0));
+    dp[1] = acc_load(D + bt(1, 0));
+    dp[2] = acc_load(D + bt(1, 1));
+  } else {
+#pragma unroll
+    for (int cc = 0; cc < TP; ++cc)
+#pragma unroll
+      for (int q = 0; q < MAXT0; ++q)
+        etp[cc][q] = q < t0 ? acc_load(c.BEt + et_off(e, q, cc, t0)) : acc_zero();
+  }
   if (wave == 0 ? hr : hl) {
     double* R = lds + wave * R_SIZE;
     const long long o = wave == 0 ? (k + 1) * s : (k - 1) * s;
@@ -151,9 +220,11 @@ __global__ __launch_bounds__(128) void k_bcr2_level(BcrArgs c, int lvl, int n) {
   const double* Rl = lds + R_SIZE;   // products of o_l
   if (wave == 0) {
     double* D = c.BD + e * BLK;
+#pragma unroll
     for (int cc = 0; cc < TP; ++cc)
+#pragma unroll
       for (int r = cc; r < TP; ++r) {
-        d4 a = acc_load(D + bt(r, cc));
+        d4 a = dp[cc + r];   // (0,0), (1,0), (1,1)
         if (hl)
           for (int p = 0; p < TP; ++p) a = mma_txy(a, Rl + R_XR + bt(p, r), Rl + R_XR + bt(p, cc), -1.0);
         if (hr)
@@ -168,10 +239,13 @@ __global__ __launch_bounds__(128) void k_bcr2_level(BcrArgs c, int lvl, int n) {
           acc_store(c.BC + e * BLK + bt(r, cc), a);
         }
   } else {
+#pragma unroll
     for (int cc = 0; cc < TP; ++cc)
-      for (int q = 0; q < t0; ++q) {
+#pragma unroll
+      for (int q = 0; q < MAXT0; ++q) {
+        if (q >= t0) continue;
         double* Et = c.BEt + et_off(e, q, cc, t0);
-        d4 a = acc_load(Et);
+        d4 a = etp[cc][q];
         if (hl)
           for (int p = 0; p < TP; ++p)
             a = mma_xy(a, Rl + R_GT + (p * t0 + q) * 256, Rl + R_XR + bt(p, cc), -1.0);
