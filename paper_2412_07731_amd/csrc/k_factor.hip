@@ -56,16 +56,34 @@ __device__ __forceinline__ void tile_copy_t(T* __restrict__ dst, const T* __rest
 
 // ---------------------------------------------------------------- a2: SYRK
 // One 64x64 lower macro tile of one block per workgroup (4 waves, each 32x32 =
-// 2x2 MFMA tiles).  A-row panels are staged through LDS (double buffered); D
-// scales the B operand in registers.  Work items are ordered so that
-// consecutive items of one block land on the same XCD (its private L2 then
-// serves the repeated panel reads).
+// 2x2 MFMA tiles).  Per tile column K of A, the 4 row tiles and 4 column tiles
+// are staged through LDS (double buffered), two tile columns ahead in
+// registers; D scales the B operand in registers.  Work items are ordered so
+// that consecutive items of one block land on the same XCD (its private L2
+// then serves the repeated panel reads).
+//
+// The stage loads are 16-byte vector loads, the same number for every
+// workgroup and every step (rows past the block and columns past its end are
+// clamped to valid tiles and zeroed when the stage is written to LDS), so the
+// compiler waits only for the stage due and never for the one behind it.
+template <typename T> struct Bits;
+template <> struct Bits<double> { typedef long long type; };
+template <> struct Bits<float> { typedef int type; };
+template <typename T>
+__device__ __forceinline__ T keep_if(T v, typename Bits<T>::type m) {
+  return __builtin_bit_cast(T, __builtin_bit_cast(typename Bits<T>::type, v) & m);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
                                               const int4* __restrict__ items, int nitems,
                                               const T* __restrict__ A,
                                               const double* __restrict__ Dp,
                                               T* __restrict__ LB, double delta) {
+  typedef typename Bits<T>::type B;
+  constexpr int E = 16 / sizeof(T);             // elements per 16-byte load
+  constexpr int NJ = 8 * TE / (E * 256);        // loads per thread and stage
+  typedef T V __attribute__((ext_vector_type(E)));
   int w = blockIdx.x;
   int per = gridDim.x / 8;
   int g = (w % 8) * per + (w / 8);
@@ -74,43 +92,57 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   const BlockInfo b = blk[it.x];
   const int R0 = it.y * 4, C0 = it.z * 4;
   const bool diag = (it.y == it.z);
-  __shared__ T sA[2][8][TE];
+  __shared__ __align__(16) T sA[2][8][TE];
   __shared__ double sD[2][TS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const bool active = !(diag && wr < wc);
-  const int ntl = diag ? 4 : 8;
 
   typedef typename Acc<T>::type AT;
   AT acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 2; ++c) acc[a][c] = AT{0, 0, 0, 0};
 
-  // two stages of A in flight: stage K is loaded during iterations K-2, K-1
-  T regs0[8], regs1[8];
-  double dreg0 = 0.0, dreg1 = 0.0;
-  auto load = [&](int K, T* regs, double& dreg) {
+  // load j of a thread: stage tile tl[j] (0-3 row tiles, 4-7 column tiles;
+  // a diagonal item loads its row tiles twice), elements pe[j] .. + E - 1
+  int tl[NJ], pe[NJ];
+  const T* rbase[NJ];
+  B rmask[NJ];
 #pragma unroll
-    for (int tt = 0; tt < 8; ++tt) {
-      if (tt < ntl) {
-        int I = tt < 4 ? R0 + tt : C0 + tt - 4;
-        regs[tt] = (I < b.mt) ? A[a_tile(b, I, K) + tid] : T(0);
-      }
-    }
-    if (tid < TS) dreg = Dp[b.dpoff + (long long)K * TS + tid];
+  for (int j = 0; j < NJ; ++j) {
+    const int f = (tid + 256 * j) * E;
+    tl[j] = f / TE;
+    pe[j] = f % TE;
+    const int I = tl[j] < 4 ? R0 + tl[j] : C0 + tl[j] - 4;
+    rmask[j] = I < b.mt ? B(-1) : B(0);
+    rbase[j] = A + b.aoff + (long long)min(I, b.mt - 1) * b.nt * TE + pe[j];
+  }
+  const double* Dbase = Dp + b.dpoff + (tid & 15);
+  V regs[2][NJ];
+  double dreg[2];
+  auto load = [&](int K, V* r, double& d) {
+    const long long Kc = min(K, b.nt - 1);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) r[j] = *reinterpret_cast<const V*>(rbase[j] + Kc * TE);
+    d = Dbase[Kc * TS];
   };
-  auto step = [&](int K, T* regs, double& dreg) {
+  auto step = [&](int K, V* r, double& d) {
     const int buf = K & 1;
+    const B km = K < b.nt ? B(-1) : B(0);
 #pragma unroll
-    for (int tt = 0; tt < 8; ++tt)
-      if (tt < ntl) sA[buf][tt][tid] = regs[tt];
-    if (tid < TS) sD[buf][tid] = dreg;
+    for (int j = 0; j < NJ; ++j) {
+      V v;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = keep_if<T>(r[j][e], km & rmask[j]);
+      *reinterpret_cast<V*>(&sA[buf][tl[j]][pe[j]]) = v;
+    }
+    if (tid < TS) sD[buf][tid] = keep_if<double>(d, (long long)km);
     __syncthreads();
-    if (K + 2 < b.nt) load(K + 2, regs, dreg);
+    load(K + 2, r, d);
     if (active) {
       const T* ra0 = sA[buf][2 * wr];
       const T* ra1 = sA[buf][2 * wr + 1];
-      const T* cb0 = diag ? sA[buf][2 * wc] : sA[buf][4 + 2 * wc];
+      const T* cb0 = sA[buf][4 + 2 * wc];
       const T* cb1 = cb0 + TE;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -124,11 +156,12 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
       }
     }
   };
-  load(0, regs0, dreg0);
-  if (b.nt > 1) load(1, regs1, dreg1);
+  // pairs of steps, the second of an odd count on zero tiles
+  load(0, regs[0], dreg[0]);
+  load(1, regs[1], dreg[1]);
   for (int K = 0; K < b.nt; K += 2) {
-    step(K, regs0, dreg0);
-    if (K + 1 < b.nt) step(K + 1, regs1, dreg1);
+    step(K, regs[0], dreg[0]);
+    step(K + 1, regs[1], dreg[1]);
   }
   if (!active) return;
 #pragma unroll
