@@ -1,0 +1,244 @@
+"""General arrowhead LPs (Sec. 3.2: inequality rows and variable bounds) in
+the oracle: an exact reformulation into the standard form of Sec. 2.2 with
+the arrowhead structure kept, then the oracle interior-point method.
+
+Test infrastructure only (see package docstring).
+
+The paper states the general form but derives its method without the
+inequality rows and bounds.  This reformulation is the textbook one:
+  * x = lo + x' for a finite lower bound, x = up - x' for an upper bound
+    only, x = x+ - x- for a free variable (all new variables >= 0);
+  * an inequality row d <= r(x) <= f becomes r(x) - t = 0 with a slack t of
+    bounds [d, f], itself reformulated like a variable;
+  * a finite upper bound u' left after the shift becomes a row x' + s = u'.
+Placement (the layout the GPU path uses too): block i's columns are its
+variables, x- of its free variables, the slacks of its inequality rows, of
+link pair i's inequality rows and (block 1) of the x_0-only rows, then the
+upper-bound slacks of those columns in order (block 1: then those of x_0);
+its rows are its equality rows, its inequality rows (block 1: then the x_0
+rows) and the upper-bound rows; x_0 is its variables then x- of its free
+ones; link pair j has its equality rows then its inequality rows.
+
+Built here row by row from the global rows of the general instance and a
+list of standard columns per original variable.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2412_07731_amd.gen import GeneralInstance, Instance, general_matrices
+
+from . import ipm
+
+
+class _Cols:
+    """Standard columns of one block (or x_0): each a (kind, payload) entry."""
+
+    def __init__(self):
+        self.kinds = []     # 'x', 'xm', 't', 's'
+        self.ub = []        # bound of the column after the reformulation
+
+    def add(self, kind, ub):
+        self.kinds.append(kind)
+        self.ub.append(ub)
+        return len(self.kinds) - 1
+
+
+def reformulate(g: GeneralInstance):
+    """Standard-form Instance, and for every original variable its
+    (offset, [(block or -1 for x_0, column, sign)]) so x can be recovered."""
+    N, n0 = g.N, g.n0
+    xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
+    nt = g.n_tot
+    Aeq, beq, Ain, dv, fv = general_matrices(g)
+    Aeq, Ain = Aeq.tocsr(), Ain.tocsr()
+
+    def owner(k):
+        for i in range(N):
+            if xo[i] <= k < xo[i + 1]:
+                return i
+        return -1
+
+    blocks = [_Cols() for _ in range(N)]
+    x0c = _Cols()
+    var = [None] * nt            # (offset, [(blk, col, sign)])
+    # 1. the variables' own columns, block by block, then x_0
+    for k in range(nt):
+        blk = owner(k)
+        cols = blocks[blk] if blk >= 0 else x0c
+        lo, up = g.lo[k], g.up[k]
+        if np.isfinite(lo):
+            c = cols.add('x', up - lo)
+            var[k] = (lo, [(blk, c, 1.0)])
+        elif np.isfinite(up):
+            c = cols.add('x', np.inf)
+            var[k] = (up, [(blk, c, -1.0)])
+        else:
+            c = cols.add('x', np.inf)
+            var[k] = (0.0, [(blk, c, 1.0)])
+    # 2. the minus parts of free variables
+    for k in range(nt):
+        if not np.isfinite(g.lo[k]) and not np.isfinite(g.up[k]):
+            blk = owner(k)
+            cols = blocks[blk] if blk >= 0 else x0c
+            c = cols.add('xm', np.inf)
+            var[k][1].append((blk, c, -1.0))
+    # inequality rows in the global order: blocks, x_0-only, links
+    mi = [g.d[i].size for i in range(N)]
+    li = [g.dl[j].size for j in range(N - 1)]
+    mi0 = g.d0.size
+    ineq_home = []               # block of each inequality row's slack
+    for i in range(N):
+        ineq_home += [i] * mi[i]
+    ineq_home += [0] * mi0
+    for j in range(N - 1):
+        ineq_home += [j] * li[j]
+    # 3. slacks, per block in the documented order: own rows, pair i rows, x_0 rows
+    first = np.concatenate([[0], np.cumsum(mi)]).astype(np.int64)
+    lfirst = int(first[-1]) + mi0 + np.concatenate([[0], np.cumsum(li)]).astype(np.int64)
+    slack = {}                   # inequality row -> (blk, col, sign, offset)
+    for i in range(N):
+        order = list(range(int(first[i]), int(first[i + 1])))
+        if i < N - 1:
+            order += list(range(int(lfirst[i]), int(lfirst[i + 1])))
+        if i == 0:
+            order += list(range(int(first[-1]), int(first[-1]) + mi0))
+        for r in order:
+            if np.isfinite(dv[r]):
+                c = blocks[i].add('t', fv[r] - dv[r] if np.isfinite(fv[r]) else np.inf)
+                slack[r] = (i, c, 1.0, dv[r])
+            else:
+                c = blocks[i].add('t', np.inf)
+                slack[r] = (i, c, -1.0, fv[r])
+    # 4. upper-bound slacks
+    ubrows = [[] for _ in range(N)]   # (column holder block, column) bounded
+    for i in range(N):
+        bounded = [c for c, u in enumerate(blocks[i].ub) if np.isfinite(u)]
+        for c in bounded:
+            s = blocks[i].add('s', np.inf)
+            ubrows[i].append((i, c, s, blocks[i].ub[c]))
+    for c, u in enumerate(x0c.ub):
+        if np.isfinite(u):
+            s = blocks[0].add('s', np.inf)
+            ubrows[0].append((-1, c, s, u))
+
+    ncol = [len(blocks[i].kinds) for i in range(N)]
+    n0s = len(x0c.kinds)
+
+    def std_row(csr, r):
+        """Row r of a global matrix in standard columns: dict per block, x_0
+        part, right-hand side shift."""
+        parts = {}
+        x0 = np.zeros(n0s)
+        shift = 0.0
+        for p in range(csr.indptr[r], csr.indptr[r + 1]):
+            k, a = int(csr.indices[p]), float(csr.data[p])
+            offk, terms = var[k]
+            shift += a * offk
+            for blk, c, sgn in terms:
+                if blk < 0:
+                    x0[c] += a * sgn
+                else:
+                    parts.setdefault(blk, np.zeros(ncol[blk]))[c] += a * sgn
+        return parts, x0, shift
+
+    Ab = [[] for _ in range(N)]
+    Cb = [[] for _ in range(N)]
+    bb = [[] for _ in range(N)]
+
+    def put_block_row(i, parts, x0, rhs):
+        row = parts.get(i, np.zeros(ncol[i]))
+        for blk in parts:
+            if blk != i:
+                raise ValueError("block row touches another block")
+        Ab[i].append(row)
+        Cb[i].append(x0)
+        bb[i].append(rhs)
+
+    mfirst = np.concatenate([[0], np.cumsum(g.m)]).astype(np.int64)
+    for i in range(N):
+        for r in range(int(mfirst[i]), int(mfirst[i + 1])):
+            parts, x0, sh = std_row(Aeq, r)
+            put_block_row(i, parts, x0, beq[r] - sh)
+        rows = list(range(int(first[i]), int(first[i + 1])))
+        if i == 0:
+            rows += list(range(int(first[-1]), int(first[-1]) + mi0))
+        for r in rows:
+            parts, x0, sh = std_row(Ain, r)
+            blk, c, sgn, toff = slack[r]
+            parts.setdefault(blk, np.zeros(ncol[blk]))[c] -= sgn
+            put_block_row(i, parts, x0, toff - sh)
+        for holder, c, s, u in ubrows[i]:
+            row = np.zeros(ncol[i])
+            x0 = np.zeros(n0s)
+            if holder < 0:
+                x0[c] = 1.0
+            else:
+                row[c] = 1.0
+            row[s] = 1.0
+            Ab[i].append(row)
+            Cb[i].append(x0)
+            bb[i].append(u)
+
+    FR, FL, F0r, bl = [], [], [], []
+    lofs = np.concatenate([[0], np.cumsum(g.l)]).astype(np.int64)
+    meq = int(mfirst[-1])
+    for j in range(N - 1):
+        fr, fl, f0, rh = [], [], [], []
+        rows = [('eq', meq + int(lofs[j]) + q) for q in range(int(g.l[j]))]
+        rows += [('in', int(lfirst[j]) + q) for q in range(li[j])]
+        for kind, r in rows:
+            parts, x0, sh = std_row(Aeq if kind == 'eq' else Ain, r)
+            if kind == 'in':
+                blk, c, sgn, toff = slack[r]
+                parts.setdefault(blk, np.zeros(ncol[blk]))[c] -= sgn
+                rhs = toff - sh
+            else:
+                rhs = beq[r] - sh
+            fr.append(parts.get(j, np.zeros(ncol[j])))
+            fl.append(parts.get(j + 1, np.zeros(ncol[j + 1])))
+            f0.append(x0)
+            rh.append(rhs)
+        FR.append(np.array(fr).reshape(len(rows), ncol[j]))
+        FL.append(np.array(fl).reshape(len(rows), ncol[j + 1]))
+        F0r.append(np.array(f0).reshape(len(rows), n0s))
+        bl += rh
+
+    A = [np.array(Ab[i]).reshape(len(Ab[i]), ncol[i]) for i in range(N)]
+    C = [np.array(Cb[i]).reshape(len(Cb[i]), n0s) for i in range(N)]
+    F0 = np.vstack(F0r) if F0r and any(np.any(f) for f in F0r) else None
+    # cost: c_k x_k = c_k off_k + sum c_k sgn x_std
+    cstd = [np.zeros(ncol[i]) for i in range(N)] + [np.zeros(n0s)]
+    const = 0.0
+    for k in range(nt):
+        offk, terms = var[k]
+        const += g.c[k] * offk
+        for blk, c, sgn in terms:
+            cstd[blk if blk >= 0 else N][c] += g.c[k] * sgn
+    inst = Instance(N=N, n0=n0s, m=np.array([a.shape[0] for a in A], dtype=np.int64),
+                    n=np.array(ncol, dtype=np.int64),
+                    l=np.array([f.shape[0] for f in FR], dtype=np.int64), A=A, C=C, FR=FR,
+                    FL=FL, F0=F0, b=np.concatenate([np.concatenate([np.asarray(v) for v in bb])
+                                                    if N else np.zeros(0), np.asarray(bl)]),
+                    c=np.concatenate(cstd))
+    return inst, var, const
+
+
+def recover(g: GeneralInstance, inst: Instance, var, x_std):
+    """x of the general form from a standard-form point."""
+    xo = np.concatenate([[0], np.cumsum(inst.n)]).astype(np.int64)
+    x = np.empty(len(var))
+    for k, (offk, terms) in enumerate(var):
+        v = offk
+        for blk, c, sgn in terms:
+            v += sgn * x_std[(xo[blk] if blk >= 0 else xo[-1]) + c]
+        x[k] = v
+    return x
+
+
+def solve(g: GeneralInstance, opts=None):
+    """Oracle solve of a general instance: (x, objective, ipm result)."""
+    inst, var, _ = reformulate(g)
+    r = ipm.solve(inst, opts) if opts is not None else ipm.solve(inst)
+    x = recover(g, inst, var, r.x)
+    return x, float(g.c @ x), r

@@ -254,3 +254,210 @@ def apply_At(inst: Instance, y: np.ndarray) -> np.ndarray:
         if inst.F0 is not None:
             out[x0s] += inst.F0[lo[j]:lo[j + 1]].T @ yl
     return out
+
+
+# --------------------------------------------------------------------------
+# General arrowhead form (Sec. 3.2): inequality rows and variable bounds.
+#
+#   block rows      A_i x_i + C_i x_0                  = b_i
+#                   d_i <= H_i x_i + G_i x_0 <= f_i            i = 1..N
+#   x_0 rows        d_0 <= G_0 x_0 <= f_0
+#   link rows       FR_j x_j + FL_j x_{j+1} (+ F0_j x_0) = b_Lj
+#                   dl_j <= KR_j x_j + KL_j x_{j+1} <= fl_j    j = 1..N-1
+#   bounds          lo <= x <= up   (entries may be -inf / +inf, lo < up)
+#
+# Inequality sides may be infinite (one side at a time).  x_0-only equality
+# rows and global linking rows are not part of this form.
+
+@dataclass
+class GeneralInstance:
+    N: int
+    n0: int
+    m: np.ndarray                 # equality rows per block [N]
+    n: np.ndarray                 # variables per block [N]
+    l: np.ndarray                 # equality rows per link pair [N-1]
+    A: List[np.ndarray]
+    C: List[np.ndarray]
+    FR: List[np.ndarray]
+    FL: List[np.ndarray]
+    F0: Optional[np.ndarray]
+    b: np.ndarray                 # [sum m + sum l], block rows then link rows
+    H: List[np.ndarray]           # inequality rows of block i: mi_i x n_i
+    G: List[np.ndarray]           # and their x_0 part: mi_i x n0
+    d: List[np.ndarray]
+    f: List[np.ndarray]
+    G0: np.ndarray                # x_0-only inequality rows: mi0 x n0
+    d0: np.ndarray
+    f0: np.ndarray
+    KR: List[np.ndarray]          # inequality rows of link pair j: li_j x n_j
+    KL: List[np.ndarray]          # li_j x n_{j+1}
+    dl: List[np.ndarray]
+    fl: List[np.ndarray]
+    c: np.ndarray                 # [n_tot], canonical order [x_1..x_N, x_0]
+    lo: np.ndarray
+    up: np.ndarray
+    xhat: np.ndarray = field(default=None)   # the interior point the data were drawn around
+
+    @property
+    def n_tot(self) -> int:
+        return int(self.n.sum()) + self.n0
+
+
+def general_matrices(g: GeneralInstance):
+    """The constraint rows of a general instance as global sparse matrices
+    (columns in canonical order): (Aeq, beq, Ain, lower, upper) with equality
+    rows [blocks, links] and inequality rows [blocks, x_0-only, links]."""
+    import scipy.sparse as sp
+    xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
+    nt = g.n_tot
+
+    def place(parts):
+        # parts: list of (rows x width dense array, column offset)
+        rows = parts[0][0].shape[0]
+        M = sp.lil_matrix((rows, nt))
+        for X, off in parts:
+            if X is not None and X.size:
+                M[:, off:off + X.shape[1]] = X
+        return M.tocsr()
+
+    eq = []
+    for i in range(g.N):
+        eq.append(place([(g.A[i], xo[i]), (g.C[i], xo[-1])]))
+    lo_ = np.concatenate([[0], np.cumsum(g.l)]).astype(np.int64)
+    for j in range(g.N - 1):
+        parts = [(g.FR[j], xo[j]), (g.FL[j], xo[j + 1])]
+        if g.F0 is not None:
+            parts.append((g.F0[lo_[j]:lo_[j + 1]], xo[-1]))
+        eq.append(place(parts))
+    ineq, lower, upper = [], [], []
+    for i in range(g.N):
+        ineq.append(place([(g.H[i], xo[i]), (g.G[i], xo[-1])]))
+        lower.append(g.d[i]); upper.append(g.f[i])
+    ineq.append(place([(g.G0, xo[-1])]))
+    lower.append(g.d0); upper.append(g.f0)
+    for j in range(g.N - 1):
+        ineq.append(place([(g.KR[j], xo[j]), (g.KL[j], xo[j + 1])]))
+        lower.append(g.dl[j]); upper.append(g.fl[j])
+    Aeq = sp.vstack(eq).tocsr() if eq else sp.csr_matrix((0, nt))
+    Ain = sp.vstack(ineq).tocsr()
+    return Aeq, g.b.copy(), Ain, np.concatenate(lower), np.concatenate(upper)
+
+
+GENERAL_CONFIGS = {
+    # small: every bound and row kind on a few blocks (dense references finish fast)
+    "g_small": dict(N=6, m=(6, 12), mi=(1, 4), extra=4, l=2, li=1, n0=3, mi0=2, density=0.4),
+    # medium: for the GPU
+    "g_medium": dict(N=64, m=(48, 96), mi=(8, 24), extra=16, l=4, li=2, n0=8, mi0=4, density=0.15),
+}
+
+
+def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
+    """Draw a feasible, bounded general instance.
+
+    Draw order (PCG64(seed)): sizes (m_i, mi_i, then per block n_i = m_i + mi_i
+    + extra), A_i, C_i, H_i, G_i per block, G_0, KR_j, KL_j per pair, then per
+    variable its bound kind and the interior point, then per inequality row
+    its side kind and widths, then y, the inequality multipliers and the
+    reduced costs.
+
+    Bound kinds (probabilities): [0, inf) 0.4, [lo, up] 0.3, [lo, inf) 0.1,
+    (-inf, up] 0.1, free 0.1.  The equality right-hand sides are the rows at
+    an interior point xhat; inequality sides lie 0.1..1 from the row value at
+    xhat (both sides 0.5, lower only 0.25, upper only 0.25).  The cost is
+    c = Aeq'y + Ain'lam + r with lam and r signed as the dual of each bound
+    and row kind requires (free variables r = 0), so the dual is feasible and
+    the LP bounded.
+    """
+    cfg = dict(GENERAL_CONFIGS[config]) if isinstance(config, str) else dict(config)
+    cfg.update(overrides)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N, n0, dens = int(cfg["N"]), int(cfg["n0"]), float(cfg["density"])
+
+    def draw(spec, size):
+        if isinstance(spec, tuple):
+            return rng.integers(spec[0], spec[1] + 1, size=size).astype(np.int64)
+        return np.full(size, spec, dtype=np.int64)
+
+    m = draw(cfg["m"], N)
+    mi = draw(cfg["mi"], N)
+    n = m + mi + int(cfg["extra"])
+    l = draw(cfg["l"], max(N - 1, 0))
+    li = draw(cfg["li"], max(N - 1, 0))
+    mi0 = int(cfg["mi0"])
+
+    A, C, H, G = [], [], [], []
+    for i in range(N):
+        A.append(_sparse_block(rng, int(m[i]), int(n[i]), dens, True))
+        C.append(_sparse_block(rng, int(m[i]), n0, dens, False))
+        H.append(_sparse_block(rng, int(mi[i]), int(n[i]), dens, True))
+        G.append(_sparse_block(rng, int(mi[i]), n0, dens, False))
+    G0 = _sparse_block(rng, mi0, n0, max(dens, 0.5), True) if n0 > 0 else np.zeros((0, 0))
+    if n0 == 0:
+        mi0 = 0
+    FR, FL, KR, KL = [], [], [], []
+    for j in range(N - 1):
+        lj, nj, nk = int(l[j]), int(n[j]), int(n[j + 1])
+        fr = np.zeros((lj, nj)); fl = np.zeros((lj, nk))
+        for k in range(lj):
+            fr[k, nj - lj + k] = 1.0
+            fl[k, k] = -1.0
+        FR.append(fr); FL.append(fl)
+        # inequality links on the next columns in from the boundary
+        kr = np.zeros((int(li[j]), nj)); kl = np.zeros((int(li[j]), nk))
+        for k in range(int(li[j])):
+            kr[k, nj - lj - 1 - k] = rng.uniform(0.5, 1.5)
+            kl[k, lj + k] = -rng.uniform(0.5, 1.5)
+        KR.append(kr); KL.append(kl)
+
+    nt = int(n.sum()) + n0
+    kind = rng.choice(5, size=nt, p=[0.4, 0.3, 0.1, 0.1, 0.1])
+    lo = np.zeros(nt); up = np.full(nt, np.inf); xhat = np.zeros(nt)
+    a = rng.uniform(-1.0, 1.0, size=nt)
+    w = rng.uniform(0.5, 3.0, size=nt)
+    t = rng.uniform(0.2, 0.8, size=nt)
+    for k in range(nt):
+        if kind[k] == 0:
+            lo[k], up[k], xhat[k] = 0.0, np.inf, 0.2 + 1.8 * t[k]
+        elif kind[k] == 1:
+            lo[k], up[k] = a[k], a[k] + w[k]
+            xhat[k] = lo[k] + t[k] * w[k]
+        elif kind[k] == 2:
+            lo[k], up[k], xhat[k] = a[k], np.inf, a[k] + 0.2 + 1.8 * t[k]
+        elif kind[k] == 3:
+            lo[k], up[k], xhat[k] = -np.inf, a[k], a[k] - 0.2 - 1.8 * t[k]
+        else:
+            lo[k], up[k], xhat[k] = -np.inf, np.inf, a[k]
+
+    inst = GeneralInstance(N=N, n0=n0, m=m, n=n, l=l, A=A, C=C, FR=FR, FL=FL, F0=None,
+                           b=np.zeros(int(m.sum() + l.sum())), H=H, G=G, d=[], f=[],
+                           G0=G0, d0=np.zeros(mi0), f0=np.zeros(mi0), KR=KR, KL=KL, dl=[], fl=[],
+                           c=np.zeros(nt), lo=lo, up=up, xhat=xhat)
+    for i in range(N):
+        inst.d.append(np.zeros(int(mi[i]))); inst.f.append(np.zeros(int(mi[i])))
+    for j in range(N - 1):
+        inst.dl.append(np.zeros(int(li[j]))); inst.fl.append(np.zeros(int(li[j])))
+    Aeq, _, Ain, _, _ = general_matrices(inst)
+    inst.b = Aeq @ xhat
+    rhat = Ain @ xhat
+    nin = rhat.size
+    side = rng.choice(3, size=nin, p=[0.5, 0.25, 0.25])
+    wd = rng.uniform(0.1, 1.0, size=nin)
+    wf = rng.uniform(0.1, 1.0, size=nin)
+    dv = np.where(side != 2, rhat - wd, -np.inf)
+    fv = np.where(side != 1, rhat + wf, np.inf)
+    # split the inequality sides back per group (same order as general_matrices)
+    pos = 0
+    for i in range(N):
+        k = int(mi[i]); inst.d[i] = dv[pos:pos + k]; inst.f[i] = fv[pos:pos + k]; pos += k
+    inst.d0 = dv[pos:pos + mi0]; inst.f0 = fv[pos:pos + mi0]; pos += mi0
+    for j in range(N - 1):
+        k = int(li[j]); inst.dl[j] = dv[pos:pos + k]; inst.fl[j] = fv[pos:pos + k]; pos += k
+    # dual-feasible cost
+    y = rng.standard_normal(Aeq.shape[0])
+    lam_raw = rng.uniform(0.0, 1.0, size=nin)
+    lam = np.where(side == 0, rng.standard_normal(nin), np.where(side == 1, lam_raw, -lam_raw))
+    r_raw = rng.uniform(0.0, 1.0, size=nt)
+    r = np.select([kind == 0, kind == 1, kind == 2, kind == 3],
+                  [r_raw, rng.standard_normal(nt), r_raw, -r_raw], default=0.0)
+    inst.c = Aeq.T @ y + Ain.T @ lam + r
+    return inst

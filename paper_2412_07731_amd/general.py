@@ -1,0 +1,217 @@
+"""General arrowhead LPs (inequality rows and variable bounds, the form of
+Sec. 3.2) solved through the standard-form library.
+
+The conversion is exact and keeps the arrowhead structure, so every
+interior-point iteration still runs in libahlp's kernels:
+
+  * a variable with a finite lower bound is shifted, x = lo + x' (x' >= 0);
+    one with only an upper bound is flipped, x = up - x'; a free one is
+    split, x = x+ - x-;
+  * an inequality row d <= r(x) <= f becomes r(x) - t = 0 with a slack t of
+    bounds [d, f] placed in the row's block (the left block for a link pair,
+    the first block for x_0-only rows), converted like a variable;
+  * every remaining finite upper bound u' gets a slack row x' + s = u' in the
+    variable's block (the first block for x_0).
+
+Standard-form layout of block i (columns):
+  1. its n_i variables (x', or x+ of a free variable), in order;
+  2. x- of its free variables, in order;
+  3. t' of its inequality rows, then of the inequality rows of link pair i
+     (pair i joins blocks i and i+1), then (first block only) of the x_0-only
+     inequality rows;
+  4. the upper-bound slacks s of the columns of 1-3 with a finite bound, in
+     column order, then (first block only) those of the x_0 columns.
+Rows of block i: its equality rows, its inequality rows (then, first block,
+the x_0-only ones), then the upper-bound rows in the order of 4.  x_0: its
+n0 columns, then x- of its free entries.  Link pair j: its equality rows,
+then its inequality rows.
+
+Only the primal solution is mapped back; duals of the general form are not.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+
+from .gen import GeneralInstance, Instance
+
+
+@dataclass
+class StandardMap:
+    """x = off + T x_std for each block (and x_0); objective constant."""
+    T: List[np.ndarray]        # per block: n_i x ncol_i, then x_0: n0 x n0_std
+    off: List[np.ndarray]
+    xoff_std: np.ndarray       # block starts in the standard x (length N+1)
+    const: float
+
+
+def _var_map(lo, up):
+    """Per variable: (column sign matrix part, offset, upper bound after the
+    shift or inf, is_free).  Returns T0 (k x (k + nfree)), off, ubound of the
+    k primary columns, and the list of free indices."""
+    k = lo.size
+    free = [v for v in range(k) if not np.isfinite(lo[v]) and not np.isfinite(up[v])]
+    T = np.zeros((k, k + len(free)))
+    off = np.zeros(k)
+    ub = np.full(k, np.inf)
+    for v in range(k):
+        if np.isfinite(lo[v]):
+            T[v, v] = 1.0
+            off[v] = lo[v]
+            ub[v] = up[v] - lo[v]
+        elif np.isfinite(up[v]):
+            T[v, v] = -1.0
+            off[v] = up[v]
+        else:
+            T[v, v] = 1.0
+    for q, v in enumerate(free):
+        T[v, k + q] = -1.0
+    return T, off, ub
+
+
+def _slack_col(dv, fv):
+    """Slack t of a row with sides [d, f]: (sign of t' in t, offset, upper bound of t')."""
+    if np.isfinite(dv):
+        return 1.0, dv, (fv - dv) if np.isfinite(fv) else np.inf
+    return -1.0, fv, np.inf
+
+
+def to_standard(g: GeneralInstance):
+    """The equivalent standard-form Instance and the map back to x."""
+    N, n0 = g.N, g.n0
+    xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
+    # x_0
+    T0, off0, ub0 = _var_map(g.lo[xo[-1]:], g.up[xo[-1]:])
+    n0s = T0.shape[1]
+    ub0_all = np.concatenate([ub0, np.full(n0s - n0, np.inf)])
+    # per block: primary and split columns, then inequality slacks
+    Tb, offb, cols, slk = [], [], [], []
+    for i in range(N):
+        Ti, oi, ubi = _var_map(g.lo[xo[i]:xo[i + 1]], g.up[xo[i]:xo[i + 1]])
+        ub = list(np.concatenate([ubi, np.full(Ti.shape[1] - g.n[i], np.inf)]))
+        rows = [(g.d[i][r], g.f[i][r]) for r in range(g.d[i].size)]
+        if i < N - 1:
+            rows += [(g.dl[i][r], g.fl[i][r]) for r in range(g.dl[i].size)]
+        if i == 0:
+            rows += [(g.d0[r], g.f0[r]) for r in range(g.d0.size)]
+        sl = [_slack_col(dv, fv) for dv, fv in rows]
+        ub += [s[2] for s in sl]
+        Tb.append(Ti)
+        offb.append(oi)
+        cols.append(ub)
+        slk.append(sl)
+    # upper-bound slacks
+    nub = [int(np.isfinite(np.asarray(cols[i])).sum()) for i in range(N)]
+    nub0 = int(np.isfinite(ub0_all).sum())
+    ncol = [len(cols[i]) + nub[i] + (nub0 if i == 0 else 0) for i in range(N)]
+    Tfull = []
+    for i in range(N):
+        T = np.zeros((int(g.n[i]), ncol[i]))
+        T[:, :Tb[i].shape[1]] = Tb[i]
+        Tfull.append(T)
+
+    A, C, bs = [], [], []
+    for i in range(N):
+        nv = Tb[i].shape[1]               # primary + split columns
+        mi = g.d[i].size
+        # equality rows
+        Ai = [g.A[i] @ Tfull[i]]
+        Ci = [g.C[i] @ T0]
+        bi = [g.b[int(g.m[:i].sum()):int(g.m[:i + 1].sum())] - g.A[i] @ offb[i] - g.C[i] @ off0]
+        # inequality rows: r(x) - t = 0  ->  r(x_std) - sgn t' = off_r + off_t
+        Hi = g.H[i] @ Tfull[i]
+        Gi = g.G[i] @ T0
+        rhs = -(g.H[i] @ offb[i]) - g.G[i] @ off0
+        for r in range(mi):
+            sgn, toff, _ = slk[i][r]
+            Hi[r, nv + r] -= sgn
+            rhs[r] += toff
+        Ai.append(Hi); Ci.append(Gi); bi.append(rhs)
+        if i == 0 and g.d0.size:
+            base = nv + mi + (g.dl[0].size if N > 1 else 0)
+            H0 = np.zeros((g.d0.size, ncol[0]))
+            G0 = g.G0 @ T0
+            r0 = -(g.G0 @ off0)
+            for r in range(g.d0.size):
+                sgn, toff, _ = slk[0][mi + (g.dl[0].size if N > 1 else 0) + r]
+                H0[r, base + r] = -sgn
+                r0[r] += toff
+            Ai.append(H0); Ci.append(G0); bi.append(r0)
+        # upper-bound rows
+        ubs = np.asarray(cols[i])
+        fin = np.flatnonzero(np.isfinite(ubs))
+        U = np.zeros((fin.size, ncol[i]))
+        UC = np.zeros((fin.size, n0s))
+        for q, col in enumerate(fin):
+            U[q, col] = 1.0
+            U[q, len(cols[i]) + q] = 1.0
+        ur = ubs[fin]
+        Ai.append(U); Ci.append(UC); bi.append(ur)
+        if i == 0 and nub0:
+            fin0 = np.flatnonzero(np.isfinite(ub0_all))
+            U0 = np.zeros((nub0, ncol[0]))
+            U0C = np.zeros((nub0, n0s))
+            for q, col in enumerate(fin0):
+                U0C[q, col] = 1.0
+                U0[q, len(cols[0]) + nub[0] + q] = 1.0
+            Ai.append(U0); Ci.append(U0C); bi.append(ub0_all[fin0])
+        A.append(np.vstack(Ai)); C.append(np.vstack(Ci)); bs.append(np.concatenate(bi))
+
+    FR, FL, F0rows, bl = [], [], [], []
+    lo_ = np.concatenate([[0], np.cumsum(g.l)]).astype(np.int64)
+    mb = int(g.m.sum())
+    for j in range(N - 1):
+        fr = [g.FR[j] @ Tfull[j]]
+        fl = [g.FL[j] @ Tfull[j + 1]]
+        F0j = g.F0[lo_[j]:lo_[j + 1]] if g.F0 is not None else np.zeros((int(g.l[j]), n0))
+        f0 = [F0j @ T0]
+        rhs = [g.b[mb + lo_[j]: mb + lo_[j + 1]] - g.FR[j] @ offb[j] - g.FL[j] @ offb[j + 1] - F0j @ off0]
+        kr = g.KR[j] @ Tfull[j]
+        kl = g.KL[j] @ Tfull[j + 1]
+        rr = -(g.KR[j] @ offb[j]) - g.KL[j] @ offb[j + 1]
+        nv, mi = Tb[j].shape[1], g.d[j].size
+        for r in range(g.dl[j].size):
+            sgn, toff, _ = slk[j][mi + r]
+            kr[r, nv + mi + r] -= sgn
+            rr[r] += toff
+        fr.append(kr); fl.append(kl); f0.append(np.zeros((g.dl[j].size, n0s))); rhs.append(rr)
+        FR.append(np.vstack(fr)); FL.append(np.vstack(fl)); F0rows.append(np.vstack(f0))
+        bl.append(np.concatenate(rhs))
+
+    ms = np.array([a.shape[0] for a in A], dtype=np.int64)
+    ns = np.array(ncol, dtype=np.int64)
+    ls = np.array([f.shape[0] for f in FR], dtype=np.int64)
+    F0 = np.vstack(F0rows) if F0rows and any(np.any(f) for f in F0rows) else None
+    b = np.concatenate(bs + bl) if (bs or bl) else np.zeros(0)
+    cs = [Tfull[i].T @ g.c[xo[i]:xo[i + 1]] for i in range(N)] + [T0.T @ g.c[xo[-1]:]]
+    const = float(sum(g.c[xo[i]:xo[i + 1]] @ offb[i] for i in range(N)) + g.c[xo[-1]:] @ off0)
+    inst = Instance(N=N, n0=n0s, m=ms, n=ns, l=ls, A=A, C=C, FR=FR, FL=FL, F0=F0, b=b,
+                    c=np.concatenate(cs))
+    mp = StandardMap(T=Tfull + [T0], off=offb + [off0],
+                     xoff_std=np.concatenate([[0], np.cumsum(ns)]).astype(np.int64), const=const)
+    return inst, mp
+
+
+def from_standard(mp: StandardMap, x_std: np.ndarray) -> np.ndarray:
+    """The general-form x of a standard-form point."""
+    N = len(mp.T) - 1
+    parts = [mp.off[i] + mp.T[i] @ x_std[mp.xoff_std[i]:mp.xoff_std[i + 1]] for i in range(N)]
+    parts.append(mp.off[N] + mp.T[N] @ x_std[mp.xoff_std[N]:])
+    return np.concatenate(parts)
+
+
+def solve(g: GeneralInstance, stream=None, **opts):
+    """Solve a general instance on the current HIP device.  Returns
+    (x, objective, result) with x in the general form's variables and the
+    result dictionary of the standard-form interior-point run."""
+    from .ahlp import Problem
+    inst, mp = to_standard(g)
+    P = Problem(inst, stream=stream)
+    try:
+        xs, _, _, res = P.ipm(stream=stream, **opts)
+        x = from_standard(mp, xs.detach().cpu().numpy())
+    finally:
+        P.close()
+    return x, float(g.c @ x), res

@@ -12,11 +12,25 @@ import time
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+from oracle import general as ogeneral  # noqa: E402
 from oracle import ipm  # noqa: E402
 from paper_2412_07731_amd import gen  # noqa: E402
 
 
+def run_general(config, seed):
+    """General-form instance (bounds, inequality rows): the oracle's
+    reformulation and IPM; objective in the general form's variables."""
+    g = gen.generate_general(config, seed)
+    t = time.time()
+    x, f, r = ogeneral.solve(g)
+    return dict(config=config, seed=seed, gondzio=0, status=r.status, iterations=r.iterations,
+                objective=f, pobj_std=r.pobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
+                mu=r.mu, seconds=round(time.time() - t, 2))
+
+
 def run(config, seed, gondzio=0):
+    if config in gen.GENERAL_CONFIGS:
+        return run_general(config, seed)
     inst = gen.generate(config, seed)
     t = time.time()
     r = ipm.solve(inst, ipm.Options(gondzio=gondzio))
@@ -34,7 +48,7 @@ def main():
     --quick: tiny only.  --add CONFIG:SEED[:gK] [...]: run just those (with K
     Gondzio correctors per iteration if gK is given) and merge them into the
     existing file (e.g. --add uneven:0, the N=2048 workload, which takes
-    minutes and several GB)."""
+    minutes and several GB; --add g_medium:0, a general-form instance)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_ipm.json")
     if "--add" in sys.argv:
         out = json.load(open(path))
