@@ -9,13 +9,15 @@ iteration runs the whole hot path: residuals, D-scaling and link columns, block
 SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
 factorization, predictor and corrector solves with FP64 refinement.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--no-uneven] [--profile]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--no-uneven]
+                    [--no-general] [--profile]
 
 The line also carries the sensitivity workload (N=256, nondegenerate): the
 differentiable solve, one backward pass (transposed Newton solve) and 64
 forward derivatives, with the gradient's error against the LP closed forms;
-the uneven-block workload (N=2048) with batched and per-block launches; and
-the N=512 solve with Gondzio correctors.
+the uneven-block workload (N=2048) with batched and per-block launches; the
+general-form workload (inequality rows and bounds, N=256); and the N=512
+solve with Gondzio correctors.
 
 Prints one JSON line.
 """
@@ -189,6 +191,48 @@ def uneven_bench(steps=3):
     return out
 
 
+def general_bench(golden_runs, steps=3):
+    """General-form workload (Sec. 3.2 with inequality rows and bounds):
+    256 blocks of 96..160 equality and 16..48 inequality rows, 8+4 link rows
+    per pair, 16 linking variables, every bound kind; reformulated on the host
+    into the standard arrowhead form (once, timed apart) and solved by
+    libahlp in FP64."""
+    import torch
+    from paper_2412_07731_amd import gen, general
+    from paper_2412_07731_amd.ahlp import Problem
+    g = gen.generate_general("g_large", 0)
+    t = time.perf_counter()
+    inst, mp = general.to_standard(g)
+    conv = time.perf_counter() - t
+    P = Problem(inst)
+    out = {"workload": "g_large: N=256 blocks, 96..160 equality + 16..48 inequality rows, "
+                       "8 equality + 4 inequality link rows per pair, 16 linking variables, "
+                       "bounds of every kind, seed 0",
+           "unit": "IPM iterations/s",
+           "standard_form": {"m_tot": int(inst.m_tot), "n_tot": int(inst.n_tot),
+                             "m_i": [int(inst.m.min()), int(inst.m.max())],
+                             "n_i": [int(inst.n.min()), int(inst.n.max())]},
+           "reformulate_s": conv}
+    P.ipm()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = 0
+    for _ in range(steps):
+        xs, _, _, r = P.ipm()
+        its += r["iterations"]
+    torch.cuda.synchronize()
+    out["value"] = its / (time.perf_counter() - t)
+    out["iterations"] = r["iterations"]
+    x = general.from_standard(mp, xs.detach().cpu().numpy())
+    f = float(g.c @ x)
+    ref = [q for q in golden_runs if q["config"] == "g_large" and q["seed"] == 0]
+    if ref:
+        out["oracle_iterations"] = ref[0]["iterations"]
+        out["objective_rel_err_vs_oracle"] = abs(f - ref[0]["objective"]) / abs(ref[0]["objective"])
+    P.close()
+    return out
+
+
 def run(P, steps, warmup, **opts):
     import torch
     for _ in range(warmup):
@@ -214,6 +258,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-sens", action="store_true", help="skip the sensitivity workload")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-block workload")
+    ap.add_argument("--no-general", action="store_true", help="skip the general-form workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -224,9 +269,11 @@ def main():
     from paper_2412_07731_amd.ahlp import FP32_REFINE, FP64, Problem
 
     golden = None
+    golden_runs = []
     gpath = os.path.join(ROOT, "tests", "golden", "oracle_ipm.json")
     if os.path.exists(gpath):
-        for r in json.load(open(gpath))["runs"]:
+        golden_runs = json.load(open(gpath))["runs"]
+        for r in golden_runs:
             if r["config"] == "n512" and r["seed"] == 0 and r.get("gondzio", 0) == 0:
                 golden = r
     inst = gen.generate("n512", 0)
@@ -337,6 +384,8 @@ def main():
         line["sensitivity"] = sens_bench(torch.device("cuda", 0))
     if not args.no_uneven and not args.profile and not args.fp32:
         line["uneven"] = uneven_bench()
+    if not args.no_general and not args.profile and not args.fp32:
+        line["general"] = general_bench(golden_runs)
     if not args.no_cpu and not args.profile:
         line["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters)
     P.close()

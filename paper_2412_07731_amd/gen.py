@@ -348,6 +348,8 @@ GENERAL_CONFIGS = {
     "g_small": dict(N=6, m=(6, 12), mi=(1, 4), extra=4, l=2, li=1, n0=3, mi0=2, density=0.4),
     # medium: for the GPU
     "g_medium": dict(N=64, m=(48, 96), mi=(8, 24), extra=16, l=4, li=2, n0=8, mi0=4, density=0.15),
+    # large: 256 time blocks of 96..160 equality and 16..48 inequality rows
+    "g_large": dict(N=256, m=(96, 160), mi=(16, 48), extra=32, l=8, li=4, n0=16, mi0=8, density=0.10),
 }
 
 

@@ -5,7 +5,8 @@ reformulation and IPM (tests/golden, written by make_golden.py):
 * the same iteration count, objective within 1e-8 relative, the recovered x
   feasible in the general form within 1e-7 (g_small seeds 0-3: 6 blocks with
   every bound and row kind; g_medium: 64 blocks of 48..96 equality and 8..24
-  inequality rows, 8 linking variables);
+  inequality rows, 8 linking variables; g_large: 256 blocks of 96..160
+  equality and 16..48 inequality rows, 16 linking variables);
 * FP32+refine on g_medium: objective within 1e-8.
 """
 import json
@@ -49,7 +50,7 @@ def violation(g, x):
 
 
 @pytest.mark.parametrize("config,seed", [("g_small", 0), ("g_small", 1), ("g_small", 2),
-                                         ("g_small", 3), ("g_medium", 0)])
+                                         ("g_small", 3), ("g_medium", 0), ("g_large", 0)])
 def test_general_against_oracle(dev, config, seed):
     from paper_2412_07731_amd import general
     print("case: general", config, seed, flush=True)
