@@ -1319,9 +1319,12 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
           HIPCHK(hipEventElapsedTime(&ms, e0, e1));
           best[k] = std::min(best[k], 1e3 * (double)ms);
         }
+      // decided on the values the cache records (to the nanosecond), so a
+      // table read back agrees with its own timings
+      for (double& v : best) v = std::round(v * 1e3) / 1e3;
       p->bf_kernel[rt] = best[0] <= best[1] ? 0 : 1;
       char buf[160];
-      std::snprintf(buf, sizeof buf, "%s %d %s %.1f %.1f", arch.c_str(), rt,
+      std::snprintf(buf, sizeof buf, "%s %d %s %.3f %.3f", arch.c_str(), rt,
                     p->bf_kernel[rt] == 0 ? "panel" : "column", best[0], best[1]);
       fresh.push_back(buf);
     }

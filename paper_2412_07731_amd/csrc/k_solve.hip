@@ -60,7 +60,7 @@ __global__ void k_rhx(const BlockInfo* __restrict__ blk, int N, int n0, long lon
 // ------------------------------------------------------------ block rows
 // Row pass over the dense blocks for up to RV_MAX vectors at once (A is read
 // once):  out_k = base_k + alpha_k (A_i v_k,i [+ C_i v_k,0]).
-// One 16-row tile panel per wave.  A is read in 16-byte pairs: lane l holds
+// One 16-row tile panel per wave.  A is read in 16-byte nontemporal pairs: lane l holds
 // rows 2(l%8), 2(l%8)+1 of tile columns l/8 and 8 + l/8, so a tile costs two
 // loads per lane; the partial sums are reduced over l/8.
 template <int NV>
@@ -78,10 +78,10 @@ __global__ __launch_bounds__(256) void k_rows_nv(const BlockInfo* __restrict__ b
   double acc[NV][2];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k][0] = acc[k][1] = 0.0;
-  const double2* At = reinterpret_cast<const double2*>(A + a_tile(b, I, 0));
+  const dv2* At = reinterpret_cast<const dv2*>(A + a_tile(b, I, 0));
 #pragma unroll 4
   for (int K = 0; K < b.nt; ++K) {
-    const double2 a0 = At[K * 128 + lane], a1 = At[K * 128 + 64 + lane];
+    const dv2 a0 = ld_stream2(At + K * 128 + lane), a1 = ld_stream2(At + K * 128 + 64 + lane);
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const double* xv = ra.v[k] + b.dpoff + K * TS;
@@ -95,8 +95,8 @@ __global__ __launch_bounds__(256) void k_rows_nv(const BlockInfo* __restrict__ b
     if (!ra.with_C[k]) continue;
     const double* x0v = ra.v[k] + d0off;
     for (int Q = 0; Q < b.kt0; ++Q) {
-      const double2* ct = reinterpret_cast<const double2*>(C + c_tile(b, I, Q));
-      const double2 a0 = ct[lane], a1 = ct[64 + lane];
+      const dv2* ct = reinterpret_cast<const dv2*>(C + c_tile(b, I, Q));
+      const dv2 a0 = ld_stream2(ct + lane), a1 = ld_stream2(ct + 64 + lane);
       const double x0 = x0v[Q * TS + cb], x1 = x0v[Q * TS + 8 + cb];
       acc[k][0] += a0.x * x0 + a1.x * x1;
       acc[k][1] += a0.y * x0 + a1.y * x1;
@@ -186,8 +186,8 @@ __global__ __launch_bounds__(256) void k_cols(const BlockInfo* __restrict__ blk,
   const double* yb = yp + b.voff + r2;
 #pragma unroll 8
   for (int I = 0; I < b.mt; ++I) {
-    const double2* tile = reinterpret_cast<const double2*>(A + a_tile(b, I, K));
-    const double2 a0 = tile[lane], a1 = tile[64 + lane];
+    const dv2* tile = reinterpret_cast<const dv2*>(A + a_tile(b, I, K));
+    const dv2 a0 = ld_stream2(tile + lane), a1 = ld_stream2(tile + 64 + lane);
     const double2 yv = *reinterpret_cast<const double2*>(yb + I * TS);
     acc0 += a0.x * yv.x + a0.y * yv.y;
     acc1 += a1.x * yv.x + a1.y * yv.y;
@@ -232,8 +232,8 @@ __global__ __launch_bounds__(256) void k_ccols(const BlockInfo* __restrict__ blk
   const double* yb = yp + b.voff + r2;
 #pragma unroll 8
   for (int I = 0; I < b.mt; ++I) {
-    const double2* tile = reinterpret_cast<const double2*>(C + c_tile(b, I, Q));
-    const double2 a0 = tile[lane], a1 = tile[64 + lane];
+    const dv2* tile = reinterpret_cast<const dv2*>(C + c_tile(b, I, Q));
+    const dv2 a0 = ld_stream2(tile + lane), a1 = ld_stream2(tile + 64 + lane);
     const double2 yv = *reinterpret_cast<const double2*>(yb + I * TS);
     acc0 += a0.x * yv.x + a0.y * yv.y;
     acc1 += a1.x * yv.x + a1.y * yv.y;
