@@ -277,6 +277,39 @@ __global__ __launch_bounds__(256) void k_x0_sum(int N, int n0, long long nl,
 }
 
 // ------------------------------------------------------------ substitutions
+// The block solves walk the mt tile columns of L_i in a dependent chain; the
+// tiles a step reads do not depend on the chain, so each step loads the next
+// step's tiles into registers (two register sets, alternating) while it
+// works.  BS_PF tiles of a column per wave are held (rows p+1+w, p+5+w, ...);
+// rows beyond them, in blocks with more than 4 BS_PF bordered tile rows below
+// the diagonal, are loaded in place.  Loads past either end (column mt after
+// the last forward step, column -1 after the last backward one, rows past
+// rt) are clamped to a valid tile and not used.
+constexpr int BS_PF = 5;
+
+template <typename T>
+struct ColRegs {
+  T t[BS_PF][4];   // tiles (p+1+w+4q, p), element 64 k + lane
+  T li[4];         // inverted diagonal tile p
+};
+
+template <typename T>
+__device__ __forceinline__ void load_col(const BlockInfo& b, const T* __restrict__ LB,
+                                         const T* __restrict__ LINV, int p, int wave, int lane,
+                                         ColRegs<T>& c) {
+  const int pc = max(min(p, b.mt - 1), 0);
+#pragma unroll
+  for (int q = 0; q < BS_PF; ++q) {
+    const int r = max(min(p + 1 + wave + 4 * q, b.rt - 1), pc);
+    const T* L = LB + lb_tile(b, r, pc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c.t[q][k] = L[64 * k + lane];
+  }
+  const T* Li = LINV + b.linvoff + (long long)pc * TE;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c.li[k] = Li[64 * k + lane];
+}
+
 // Forward substitution with the bordered factor of block i: v = L_i^-1 t and,
 // on the bordered rows, qn = -W_i' v.  t is read from tin (padded block-row
 // vector) and v written to tv (tin may equal tv).
@@ -293,20 +326,33 @@ __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nr = TS * b.rt, nm = TS * b.mt;
   for (int r = tid; r < nr; r += blockDim.x) t[r] = (r < nm) ? tin[b.voff + r] : 0.0;
-  __syncthreads();
-  for (int p = 0; p < b.mt; ++p) {
+  // step p with the tiles in c; the next step's go to n
+  auto step = [&](int p, const ColRegs<T>& c, ColRegs<T>& n) {
+    load_col(b, LB, LINV, p + 1, wave, lane, n);
+    __syncthreads();
     if (wave == 0) {
-      const T* Li = LINV + b.linvoff + (long long)p * TE;
       double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) s += (double)Li[64 * k + lane] * t[TS * p + 4 * k + (lane >> 4)];
+      for (int k = 0; k < 4; ++k) s += (double)c.li[k] * t[TS * p + 4 * k + (lane >> 4)];
       s += __shfl_xor(s, 16);
       s += __shfl_xor(s, 32);
       // all lanes have read t[p-block]; lanes 0..15 now overwrite it
       if (lane < 16) t[TS * p + lane] = s;
     }
     __syncthreads();
-    for (int r = p + 1 + wave; r < b.rt; r += 4) {
+#pragma unroll
+    for (int q = 0; q < BS_PF; ++q) {
+      const int r = p + 1 + wave + 4 * q;
+      if (r < b.rt) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += (double)c.t[q][k] * t[TS * p + 4 * k + (lane >> 4)];
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        if (lane < 16) t[TS * r + lane] -= s;
+      }
+    }
+    for (int r = p + 1 + wave + 4 * BS_PF; r < b.rt; r += 4) {
       const T* L = LB + lb_tile(b, r, p);
       double s = 0.0;
 #pragma unroll
@@ -315,8 +361,14 @@ __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__
       s += __shfl_xor(s, 32);
       if (lane < 16) t[TS * r + lane] -= s;
     }
-    __syncthreads();
+  };
+  ColRegs<T> ra, rb;
+  load_col(b, LB, LINV, 0, wave, lane, ra);
+  for (int p = 0; p < b.mt; p += 2) {
+    step(p, ra, rb);
+    if (p + 1 < b.mt) step(p + 1, rb, ra);
   }
+  __syncthreads();
   for (int r = tid; r < nm; r += blockDim.x) tv[b.voff + r] = t[r];
   for (int r = nm + tid; r < nr; r += blockDim.x) qn[b.qoff + (r - nm)] = t[r];
 }
@@ -355,10 +407,20 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
     }
     y[r] = val;
   }
-  __syncthreads();
-  for (int p = b.mt - 1; p >= 0; --p) {
+  auto step = [&](int p, const ColRegs<T>& c, ColRegs<T>& n) {
+    load_col(b, LB, LINV, p - 1, wave, lane, n);
+    __syncthreads();
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = p + 1 + wave; r < b.rt; r += 4) {
+#pragma unroll
+    for (int q = 0; q < BS_PF; ++q) {
+      const int r = p + 1 + wave + 4 * q;
+      if (r < b.rt) {
+        const double yv = y[TS * r + (lane & 15)];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s] += (double)c.t[q][s] * yv;
+      }
+    }
+    for (int r = p + 1 + wave + 4 * BS_PF; r < b.rt; r += 4) {
       const T* L = LB + lb_tile(b, r, p);
       const double yv = y[TS * r + (lane & 15)];
 #pragma unroll
@@ -379,12 +441,11 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
       const int kcol = lane & 15;
       const double w = y[TS * p + kcol] - (part[0][kcol] + part[1][kcol] + part[2][kcol] + part[3][kcol]);
       // element (i, k) of Linv at 64 s + l:  i = l%16, k = 4 s + l/16;  y_p[k] = sum_i Linv[i][k] w[i]
-      const T* Li = LINV + b.linvoff + (long long)p * TE;
       double s4[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const double wi = __shfl(w, lane & 15);
-        double x = (double)Li[64 * s + lane] * wi;
+        double x = (double)c.li[s] * wi;
         x += __shfl_xor(x, 1);
         x += __shfl_xor(x, 2);
         x += __shfl_xor(x, 4);
@@ -398,8 +459,14 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
     }
     __syncthreads();
     if (tid < TS) y[TS * p + tid] = part[0][tid];
-    __syncthreads();
+  };
+  ColRegs<T> ra, rb;
+  load_col(b, LB, LINV, b.mt - 1, wave, lane, ra);
+  for (int p = b.mt - 1; p >= 0; p -= 2) {
+    step(p, ra, rb);
+    if (p >= 1) step(p - 1, rb, ra);
   }
+  __syncthreads();
   for (int r = tid; r < nm; r += blockDim.x) {
     dyp[b.voff + r] = (r < b.m) ? y[r] : 0.0;
     if (r < b.m) dy[b.yoff + r] = y[r];
