@@ -214,6 +214,7 @@ struct ahlp_problem_s {
   // solve workspace
   double *rhx = nullptr, *vx = nullptr, *tv = nullptr, *qn = nullptr, *s = nullptr, *w = nullptr,
          *u = nullptr, *dyp = nullptr, *g = nullptr, *part = nullptr, *segrhs = nullptr,
+         *aty = nullptr, *gdir = nullptr,
          *xp = nullptr;
   // refinement / driver workspace
   double *ex = nullptr, *ey = nullptr, *ez = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;
@@ -577,6 +578,17 @@ void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
   launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
                 mode == 0 ? out : nullptr, mode == 0 ? nullptr : out);
+}
+
+// rd = cvec - A'y - zvec, and g = A'y kept in gout (one column pass)
+void apply_At_both(ahlp_problem_t p, const double* y, const double* cvec, const double* zvec,
+                   double* rd, double* gout, hipStream_t st) {
+  launch_pad_y(st, p->blk, p->N, y, p->dyp);
+  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, y + p->mblk, p->cptr, p->crow,
+              p->cval, 1, cvec, zvec, p->Dp, gout, rd);
+  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
+  launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, y + p->mblk, 1, cvec, zvec, p->x0off,
+                gout, rd);
 }
 
 // out = base + alpha * A x (canonical)
@@ -1127,6 +1139,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (double** v : {&p->ta, &p->aw1, &p->aw2, &p->tc}) CHK(M.alloc(v, p->vp_total));
   for (double** v : {&p->w1p, &p->w2p}) CHK(M.alloc(v, p->dp_total));
   CHK(M.alloc(&p->gc, p->n_tot));
+  CHK(M.alloc(&p->aty, p->n_tot));
+  CHK(M.alloc(&p->gdir, p->n_tot));
   CHK(M.alloc(&p->adj_rz, p->n_tot));
   for (double** v : {&p->g_r, &p->g_dx, &p->g_dz}) CHK(M.alloc(v, p->n_tot));
   for (double** v : {&p->g_dy, &p->zerosm}) CHK(M.alloc(v, p->m_tot));
@@ -1483,11 +1497,15 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   const DevInfo* hinfo = reinterpret_cast<const DevInfo*>(p->h_scal + NSCAL - 1);
   const double* hs = p->h_scal;
   SegKey key{x, y, z, o->rho, o->delta, o->eta};
-  // residuals of the current iterate (the start of every iteration)
-  auto resid_stage = [&]() -> ahlp_status_t {
+  // residuals of the current iterate (the start of every iteration).  A'y is
+  // kept in p->aty: formed by a column pass at the start (full), then
+  // advanced with each step, A'y+ = A'y + alpha_d A'dy, where A'dy is the
+  // solve's own column pass (p->g, refinement corrections included)
+  auto resid_stage = [&](bool full) -> ahlp_status_t {
     p->timer.begin(AHLP_ST_RESID);
     CHK(prep_scaling(p, x, z, o->rho, st));
-    apply_At(p, y, 1, p->c, z, p->rd, st);                          // r_d = c - A'y - z
+    if (full) apply_At_both(p, y, p->c, z, p->rd, p->aty, st);     // r_d = c - A'y - z
+    else launch_rd(st, n, p->c, p->aty, z, p->rd);
     // rz_a = -x z, rhx_a, vx = D rhx_a, w1 = D / x, xp = x (padded)
     launch_resid_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, p->rd, p->xs, p->Dp,
                       p->rzv, p->rhx, p->vx, p->w1p, p->xp);
@@ -1513,9 +1531,10 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     launch_step(st, n, o->eta, p->scal + S_AP, p->dx, x);
     launch_step(st, m, o->eta, p->scal + S_AD, p->dy, y);
     launch_step(st, n, o->eta, p->scal + S_AD, p->dz, z);
-    return resid_stage();
+    launch_step(st, n, o->eta, p->scal + S_AD, p->g, p->aty);
+    return resid_stage(false);
   };
-  CHK(resid_stage());
+  CHK(resid_stage(true));
   while (true) {
     CHK(read_scal(p, NSCAL, st));
     if (hinfo->nonfinite)
@@ -1647,8 +1666,15 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     // [beta_min, beta_max] sigma mu, solve with right-hand side (0, 0, t - v)
     // and keep the corrected direction if the smaller step grows by at least
     // gamma delta_a (constants as in the oracle)
+    // g = A'dy of the direction taken, for the A'y update: each correction
+    // solve leaves its own A'dy_c in p->g, so the sum is kept in p->gdir
+    bool gz_used = false;
     for (int j = 0; j < o->gondzio; ++j) {
       if (ap >= 1.0 && ad >= 1.0) break;
+      if (!gz_used) {
+        launch_copy(st, n, p->g, p->gdir);
+        gz_used = true;
+      }
       constexpr double beta_min = 0.1, beta_max = 10.0, delta_a = 0.1, gamma = 0.1;
       const double at_p = std::min(1.0, ap + delta_a), at_d = std::min(1.0, ad + delta_a);
       launch_gondzio_rhs(st, n, x, z, p->dx, p->dz, at_p, at_d, p->scal + S_SMU, beta_min,
@@ -1670,10 +1696,12 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       launch_copy(st, m, p->g_dy, p->dy);
       launch_copy(st, n, p->g_dz, p->dz);
       launch_copy(st, 2, p->scal + S_GP, p->scal + S_AP);   // the step kernels read S_AP, S_AD
+      launch_axpy(st, n, 1.0, p->g, p->gdir);
       ap = ap_n;
       ad = ad_n;
       R.correctors++;
     }
+    if (gz_used) launch_copy(st, n, p->gdir, p->g);
     ++k;
     if (ap < 1e-12 && ad < 1e-12) {
       launch_step(st, n, o->eta, p->scal + S_AP, p->dx, x);

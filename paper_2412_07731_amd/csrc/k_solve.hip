@@ -627,6 +627,14 @@ __global__ void k_dz(long long n, const double* __restrict__ rz, const double* _
 }
 
 // Refinement residual pieces in x-space: ex = rx - g - dz;  ez = rz - zs dx - xs dz.
+// dual residual from a maintained g = A'y:  rd = c - g - z
+__global__ void k_rd(long long n, const double* __restrict__ c, const double* __restrict__ g,
+                     const double* __restrict__ z, double* __restrict__ rd) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    rd[i] = c[i] - g[i] - z[i];
+}
+
 __global__ void k_res_x(long long n, const double* __restrict__ rx, const double* __restrict__ rz,
                         const double* __restrict__ g, const double* __restrict__ dx,
                         const double* __restrict__ dz, const double* __restrict__ xs,
@@ -1003,6 +1011,10 @@ void launch_axpy(hipStream_t st, long long n, double a, const double* x, double*
 void launch_dz(hipStream_t st, long long n, const double* rz, const double* zs, const double* xs,
                const double* dx, double* dz) {
   hipLaunchKernelGGL(k_dz, dim3(grid1d(n)), dim3(256), 0, st, n, rz, zs, xs, dx, dz);
+}
+void launch_rd(hipStream_t st, long long n, const double* c, const double* g, const double* z,
+               double* rd) {
+  hipLaunchKernelGGL(k_rd, dim3(grid1d(n)), dim3(256), 0, st, n, c, g, z, rd);
 }
 void launch_res_x(hipStream_t st, long long n, const double* rx, const double* rz,
                   const double* g, const double* dx, const double* dz, const double* xs,

@@ -209,6 +209,8 @@ void launch_adj_scale(hipStream_t st, long long n, int mode, const double* zs, c
                       double* out);
 void launch_dz(hipStream_t st, long long n, const double* rz, const double* zs, const double* xs,
                const double* dx, double* dz);
+void launch_rd(hipStream_t st, long long n, const double* c, const double* g, const double* z,
+               double* rd);
 void launch_res_x(hipStream_t st, long long n, const double* rx, const double* rz,
                   const double* g, const double* dx, const double* dz, const double* xs,
                   const double* zs, double* ex, double* ez);
