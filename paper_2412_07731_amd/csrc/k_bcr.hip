@@ -39,7 +39,8 @@ namespace ahlp {
 namespace {
 
 constexpr int BT_MAXT0 = 4;      // border tiles (n0 <= 64)
-constexpr int TAIL_WAVES = 8;    // waves of the single-workgroup tail kernels
+constexpr int TAIL_WAVES = 8;    // waves of the single-workgroup factor tail
+constexpr int TAIL_WAVES_S = 16; // waves of the single-workgroup solve tail
 constexpr int ELIM_LDS = 256 + 256 + 48;   // doubles of LDS per eliminating wave
 
 // ---------------------------------------------------------------- factor
@@ -477,11 +478,11 @@ __global__ __launch_bounds__(256) void k_bcr_bwd(BcrSolveArgs A, int lvl, int n)
 // Narrow forward levels from lvl (n active pairs), the final pair, the border
 // right-hand side s0 - sum_j Z_j'w_j (fixed order), the border solve
 // w0 = Lb^-1 s0, u0 = -Lb^-T w0, the final pair backward and the narrow
-// backward levels.  One workgroup of TAIL_WAVES waves.
-__global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail_solve(BcrSolveArgs A, int lvl, int n) {
+// backward levels.  One workgroup of TAIL_WAVES_S waves.
+__global__ __launch_bounds__(64 * TAIL_WAVES_S) void k_bcr_tail_solve(BcrSolveArgs A, int lvl, int n) {
   const BcrArgs& c = A.c;
-  __shared__ VecLds V[TAIL_WAVES];
-  __shared__ double part[64 * TAIL_WAVES];
+  __shared__ VecLds V[TAIL_WAVES_S];
+  __shared__ double part[64 * TAIL_WAVES_S];
   __shared__ double s0[16 * BT_MAXT0], w0[16 * BT_MAXT0], u0[16 * BT_MAXT0];
   __shared__ int lv_n[32];
   const int wave = threadIdx.x >> 6;
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail_solve(BcrSolveArgs
   for (; n > 1; ++lvl, n = (n + 1) / 2) {
     if (threadIdx.x == 0) lv_n[nlev] = n;
     ++nlev;
-    for (int w = wave; w < (n + 1) / 2; w += TAIL_WAVES) bcr_fwd_even(A, lvl, n, 2 * w, V[wave]);
+    for (int w = wave; w < (n + 1) / 2; w += TAIL_WAVES_S) bcr_fwd_even(A, lvl, n, 2 * w, V[wave]);
     __syncthreads();
   }
   if (n == 1 && wave == 0) bcr_final_fwd(A, lvl, V[0]);
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail_solve(BcrSolveArgs
   for (int li = nlev - 1; li >= 0; --li) {
     const int nn = lv_n[li], lv = lvl0 + li;
     const long long s = 1LL << lv;
-    for (int w = wave; w < nn / 2; w += TAIL_WAVES) {
+    for (int w = wave; w < nn / 2; w += TAIL_WAVES_S) {
       const int k = 2 * w + 1;
       bcr_bwd_pair(A, k * s, (k - 1) * s, k + 1 < nn ? (k + 1) * s : -1, u0, V[wave]);
     }
@@ -513,11 +514,11 @@ size_t border_smem(int t0) {
   return (size_t)(2 * t0 * t0 + t0 + 1) * 256 * sizeof(double) + 48 * sizeof(double);
 }
 
-// first level handled by the tail kernels: the first with at most TAIL_WAVES
-// eliminations
-int tail_level(int P, int* n_out) {
+// first level handled by a tail kernel of `waves` waves: the first with at
+// most that many eliminations
+int tail_level(int P, int waves, int* n_out) {
   int lvl = 0, n = P;
-  while (n > 1 && n / 2 > TAIL_WAVES) {
+  while (n > 1 && n / 2 > waves) {
     ++lvl;
     n = (n + 1) / 2;
   }
@@ -539,7 +540,7 @@ void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk) 
     const long long tiles = (long long)c.P * (2 + c.t0);
     hipLaunchKernelGGL(k_bcr_init, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, c);
     int nt = 0;
-    const int lt = tail_level(c.P, &nt);
+    const int lt = tail_level(c.P, TAIL_WAVES, &nt);
     int n = c.P;
     for (int lvl = 0; lvl < lt; ++lvl, n = (n + 1) / 2)
       hipLaunchKernelGGL(k_bcr_level, dim3((n + 1) / 2), dim3(128), 0, st, c, lvl, n);
@@ -561,11 +562,11 @@ void launch_bcr_solve(hipStream_t st, const BcrSolveArgs& a) {
   }
   const int P = a.c.P;
   int nt = 0;
-  const int lt = P > 0 ? tail_level(P, &nt) : 0;
+  const int lt = P > 0 ? tail_level(P, TAIL_WAVES_S, &nt) : 0;
   int n = P;
   for (int lvl = 0; lvl < lt; ++lvl, n = (n + 1) / 2)
     hipLaunchKernelGGL(k_bcr_fwd, dim3(((n + 1) / 2 + 3) / 4), dim3(256), 0, st, a, lvl, n);
-  hipLaunchKernelGGL(k_bcr_tail_solve, dim3(1), dim3(64 * TAIL_WAVES), 0, st, a, lt, P > 0 ? nt : 0);
+  hipLaunchKernelGGL(k_bcr_tail_solve, dim3(1), dim3(64 * TAIL_WAVES_S), 0, st, a, lt, P > 0 ? nt : 0);
   // wide backward levels, last to first
   for (int lvl = lt - 1; lvl >= 0; --lvl) {
     int nl = P;
