@@ -10,7 +10,7 @@ SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
 factorization, predictor and corrector solves with FP64 refinement.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--no-uneven]
-                    [--no-general] [--profile]
+                    [--no-general] [--profile [n512|uneven|general]]
 
 The line also carries the sensitivity workload (N=256, nondegenerate): the
 differentiable solve, one backward pass (transposed Newton solve) and 64
@@ -253,7 +253,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile", action="store_true", help="short run for profilers")
+    ap.add_argument("--profile", nargs="?", const="n512", default=None,
+                    choices=["n512", "uneven", "general"],
+                    help="short run for profilers: one fully timed n512 solve (default), or one "
+                         "FP64 solve of the uneven or the general-form workload")
     ap.add_argument("--fp32", action="store_true", help="time the FP32+refine path as the main line")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-sens", action="store_true", help="skip the sensitivity workload")
@@ -267,6 +270,28 @@ def main():
     import torch
     from paper_2412_07731_amd import gen
     from paper_2412_07731_amd.ahlp import FP32_REFINE, FP64, Problem
+
+    if args.profile in ("uneven", "general"):
+        # one solve of a secondary workload for the profilers (after one
+        # untimed solve that loads and warms everything)
+        torch.cuda.set_device(0)
+        if args.profile == "uneven":
+            inst = gen.generate("uneven", 0)
+        else:
+            from paper_2412_07731_amd import general
+            inst, _ = general.to_standard(gen.generate_general("g_large", 0))
+        P = Problem(inst)
+        if args.profile == "uneven":
+            P.autotune()
+        P.ipm()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, _, r = P.ipm()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": args.profile, "iterations": r["iterations"],
+                          "status": r["status"], "ms": 1e3 * (time.perf_counter() - t)}))
+        P.close()
+        return
 
     golden = None
     golden_runs = []
