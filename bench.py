@@ -264,8 +264,8 @@ def main():
     ap.add_argument("--no-general", action="store_true", help="skip the general-form workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(every box here has one GPU); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(how it would shard is designed, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2412_07731_amd import gen

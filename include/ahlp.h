@@ -210,7 +210,7 @@ ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const doubl
                                   hipStream_t stream);
 
 /* How the per-block stages of the factorization (SYRK, link columns, block
- * Cholesky with W_i and the Schur products; Alg. 2 lines 1-3 of Sec. 3.2) are
+ * Cholesky with W_i and the Schur products; the per-block steps of Alg. 2, Sec. 3.2) are
  * launched.  AHLP_LAUNCH_BATCHED (default): each stage is one launch over all
  * blocks (blocks of uneven size sorted largest first; the block factor in two
  * buckets, by whether the bordered block fits the panel kernel).
@@ -220,9 +220,10 @@ ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const doubl
 enum { AHLP_LAUNCH_BATCHED = 0, AHLP_LAUNCH_PER_BLOCK = 1 };
 ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode);
 
-/* Chooses the block-factor kernel (Alg. 2 lines 1-2 of Sec. 3.2) for every
- * bordered tile-row count rt that the problem's blocks have and the panel
- * kernel can hold (rt <= 20): the panel kernel (panel accumulators in
+/* Chooses the block-factor kernel (the block factorization and the solve
+ * against the linking columns of Alg. 2, Sec. 3.2) for every bordered
+ * tile-row count rt that the problem's blocks have and the panel kernel can
+ * hold (rt <= 24): the panel kernel (panel accumulators in
  * registers) or the column kernel (one tile column at a time through LDS).
  * Entries for this GPU architecture found in the text file cache_path (HOST
  * string, may be NULL) are used as they are; every other rt is measured on the

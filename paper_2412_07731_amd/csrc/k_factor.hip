@@ -415,7 +415,10 @@ __device__ __forceinline__ void schur_rows(const BlockInfo& b, const T* __restri
 // Two workgroups share a CU, so one block's tile Cholesky overlaps the
 // other's MFMA work.  The kernel ends with the block's Schur contribution
 // (schur_rows), so no separate a5 product pass is needed on this path.
-constexpr int BF_PW = 2, BF_RMAX = 5;
+// BF_RMAX is a template parameter: 5 (blocks of up to 20 tile rows) or 6 (up
+// to 24, where the sixth row's accumulators fill the 256 VGPRs); a launch takes
+// the smaller that fits its widest block.
+constexpr int BF_PW = 2, BF_RMAX_MAX = 6;
 template <typename T>
 struct BfOp { T v[4]; };
 template <typename T>
@@ -427,7 +430,7 @@ __device__ __forceinline__ BfOp<T> bf_ld(const T* __restrict__ t) {
   return o;
 }
 
-template <typename T>
+template <typename T, int BF_RMAX>
 __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
                                                                const int* __restrict__ order,
                                                                T* __restrict__ LB,
@@ -708,15 +711,19 @@ template void launch_link<float>(hipStream_t, const BlockInfo*, const int2*, int
                                  const double*, const double*, const int*, const int*,
                                  const double*, const double*, float*, double*);
 
-// Panel kernel for blocks of at most 4*BF_RMAX bordered tile rows (it also
+// Panel kernel for blocks of at most 4*BF_RMAX_MAX bordered tile rows (it also
 // forms their Schur contributions); workgroup w takes block order[w].
 template <typename T>
 void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
                                int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info) {
   if (n == 0) return;
   const size_t shmem = (size_t)(max_rt + 6) * TE * sizeof(T) + 48 * sizeof(T);
-  hipLaunchKernelGGL(k_block_factor_panel<T>, dim3(n), dim3(256), shmem, st, blk, order, LB, LINV,
-                     PQ, info);
+  if (max_rt <= 20)
+    hipLaunchKernelGGL((k_block_factor_panel<T, 5>), dim3(n), dim3(256), shmem, st, blk, order, LB,
+                       LINV, PQ, info);
+  else
+    hipLaunchKernelGGL((k_block_factor_panel<T, 6>), dim3(n), dim3(256), shmem, st, blk, order, LB,
+                       LINV, PQ, info);
 }
 // Column-at-a-time kernel (any height), then the Schur contributions.
 template <typename T>
@@ -727,7 +734,7 @@ void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* or
   hipLaunchKernelGGL(k_block_factor<T>, dim3(n), dim3(256), shmem, st, blk, order, LB, LINV, info);
   hipLaunchKernelGGL(k_schur_contrib<T>, dim3(n), dim3(256), 0, st, blk, order, LB, PQ);
 }
-bool block_factor_panel_fits(int rt) { return rt <= 4 * BF_RMAX; }
+bool block_factor_panel_fits(int rt) { return rt <= 4 * BF_RMAX_MAX; }
 template void launch_block_factor_panel<double>(hipStream_t, const BlockInfo*, const int*, int, int,
                                                 double*, double*, double*, DevInfo*);
 template void launch_block_factor_panel<float>(hipStream_t, const BlockInfo*, const int*, int, int,

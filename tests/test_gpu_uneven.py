@@ -46,7 +46,7 @@ def test_batched_equals_per_block(dev):
     k = [(int(inst.l[j - 1]) if j > 0 else 0) + (int(inst.l[j]) if j < inst.N - 1 else 0) + inst.n0
          for j in range(inst.N)]
     rt = [(int(m) + 15) // 16 + (kk + 15) // 16 for m, kk in zip(inst.m, k)]
-    assert max(rt) > 20 and min(rt) <= 20          # both factor buckets are used
+    assert max(rt) > 24 and min(rt) <= 24          # both factor buckets are used
     P = Problem(inst)
     try:
         x1, y1, z1, r1 = P.ipm()
@@ -92,7 +92,7 @@ def test_autotune_table(dev, tmp_path):
         rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
         assert n >= 1 and len(rows) == n
         for arch, rt, kern, us_p, us_c in rows:
-            assert 1 <= int(rt) <= 20
+            assert 1 <= int(rt) <= 24
             assert kern == ("panel" if float(us_p) <= float(us_c) else "column")
         x, y, z, r = P.ipm()
         assert r["status"] == 0
