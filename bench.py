@@ -194,7 +194,8 @@ def uneven_bench(steps=3):
 def general_bench(golden_runs, steps=3):
     """General-form workload (Sec. 3.2 with inequality rows and bounds):
     256 blocks of 96..160 equality and 16..48 inequality rows, 8+4 link rows
-    per pair, 16 linking variables, every bound kind; reformulated on the host
+    per pair, 4 global linking rows, 16 linking variables, every bound kind;
+    reformulated on the host
     into the standard arrowhead form (once, timed apart) and solved by
     libahlp in FP64."""
     import torch
@@ -206,8 +207,9 @@ def general_bench(golden_runs, steps=3):
     conv = time.perf_counter() - t
     P = Problem(inst)
     out = {"workload": "g_large: N=256 blocks, 96..160 equality + 16..48 inequality rows, "
-                       "8 equality + 4 inequality link rows per pair, 16 linking variables, "
-                       "bounds of every kind, seed 0",
+                       "8 equality + 4 inequality link rows per pair, 4 global linking rows "
+                       "(2 equalities, 2 inequalities), 16 linking variables, bounds of every "
+                       "kind, seed 0",
            "unit": "IPM iterations/s",
            "standard_form": {"m_tot": int(inst.m_tot), "n_tot": int(inst.n_tot),
                              "m_i": [int(inst.m.min()), int(inst.m.max())],

@@ -10,7 +10,15 @@ inequality rows and bounds.  This reformulation is the textbook one:
     only, x = x+ - x- for a free variable (all new variables >= 0);
   * an inequality row d <= r(x) <= f becomes r(x) - t = 0 with a slack t of
     bounds [d, f], itself reformulated like a variable;
-  * a finite upper bound u' left after the shift becomes a row x' + s = u'.
+  * a finite upper bound u' left after the shift becomes a row x' + s = u';
+  * a global row dg <= sum_i Wg_i x_i + Wg_0 x_0 <= fg is first written as a
+    chain of partial sums s_i = s_{i-1} + Wg_i x_i (free variables of block i;
+    s_1 includes Wg_0 x_0), one row in block 1 and one link row per pair; the
+    last partial sum gets the sides [dg, fg], except for an equality, whose
+    last link row (block row if N = 1) carries dg instead.
+Chaining layout: block i's partial sums follow its own variables (global row
+order); block 1's and every link pair's new rows follow their own equality
+rows.
 Placement (the layout the GPU path uses too): block i's columns are its
 variables, x- of its free variables, the slacks of its inequality rows, of
 link pair i's inequality rows and (block 1) of the x_0-only rows, then the
@@ -44,9 +52,101 @@ class _Cols:
         return len(self.kinds) - 1
 
 
+def chain(g: GeneralInstance):
+    """Global rows as chains of partial sums: an equivalent general instance
+    without global rows, and the positions of the original variables in it."""
+    N, n0, ng = g.N, g.n0, g.ng
+    xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
+    # per block, the partial sums it holds: list of global row indices
+    sums = [[k for k in range(ng) if i < N - 1 or g.dg[k] != g.fg[k]] for i in range(N)]
+    pos = [{k: int(g.n[i]) + q for q, k in enumerate(sums[i])} for i in range(N)]
+    nn = np.array([int(g.n[i]) + len(sums[i]) for i in range(N)], dtype=np.int64)
+
+    def widen(X, i):
+        Y = np.zeros((X.shape[0], int(nn[i])))
+        Y[:, :X.shape[1]] = X
+        return Y
+
+    A = [widen(g.A[i], i) for i in range(N)]
+    C = [g.C[i].copy() for i in range(N)]
+    brows = []
+    mfirst = np.concatenate([[0], np.cumsum(g.m)]).astype(np.int64)
+    for i in range(N):
+        brows.append(list(g.b[mfirst[i]:mfirst[i + 1]]))
+    lfirst = int(mfirst[-1]) + np.concatenate([[0], np.cumsum(g.l)]).astype(np.int64)
+    lrows = [list(g.b[lfirst[j]:lfirst[j + 1]]) for j in range(N - 1)]
+    FR = [widen(g.FR[j], j) for j in range(N - 1)]
+    FL = [widen(g.FL[j], j + 1) for j in range(N - 1)]
+    F0 = None
+    if g.F0 is not None:
+        F0 = [g.F0[lfirst[j] - lfirst[0]:lfirst[j + 1] - lfirst[0]] for j in range(N - 1)]
+    for k in range(ng):
+        # block 1 row: s_{k,1} - Wg_1 x_1 - Wg_0 x_0 = 0, or Wg_1 x_1 + Wg_0 x_0 = dg
+        row = np.zeros(int(nn[0]))
+        if k in pos[0]:
+            row[:int(g.n[0])] = -g.Wg[0][k]
+            row[pos[0][k]] = 1.0
+            rc = -g.Wg0[k] if n0 else np.zeros(0)
+            rhs = 0.0
+        else:
+            row[:int(g.n[0])] = -g.Wg[0][k]
+            rc = -g.Wg0[k] if n0 else np.zeros(0)
+            rhs = -g.dg[k]
+        A[0] = np.vstack([A[0], row])
+        C[0] = np.vstack([C[0], rc.reshape(1, n0)])
+        brows[0].append(rhs)
+    for j in range(N - 1):
+        for k in range(ng):
+            fr = np.zeros(int(nn[j]))
+            fl = np.zeros(int(nn[j + 1]))
+            fr[pos[j][k]] = -1.0
+            fl[:int(g.n[j + 1])] = -g.Wg[j + 1][k]
+            if k in pos[j + 1]:
+                fl[pos[j + 1][k]] = 1.0
+                rhs = 0.0
+            else:
+                rhs = -g.dg[k]
+            FR[j] = np.vstack([FR[j], fr])
+            FL[j] = np.vstack([FL[j], fl])
+            if F0 is not None:
+                F0[j] = np.vstack([F0[j], np.zeros((1, n0))])
+            lrows[j].append(rhs)
+    lo, up, c, keep = [], [], [], []
+    start = 0
+    for i in range(N):
+        own = slice(xo[i], xo[i + 1])
+        lo.append(g.lo[own]); up.append(g.up[own]); c.append(g.c[own])
+        keep.extend(range(start, start + int(g.n[i])))
+        for k in sums[i]:
+            last = i == N - 1
+            lo.append(np.array([g.dg[k] if last else -np.inf]))
+            up.append(np.array([g.fg[k] if last else np.inf]))
+            c.append(np.zeros(1))
+        start += int(nn[i])
+    lo.append(g.lo[xo[-1]:]); up.append(g.up[xo[-1]:]); c.append(g.c[xo[-1]:])
+    keep.extend(range(start, start + n0))
+    b = np.concatenate([np.asarray(r, dtype=float) for r in brows] +
+                       [np.asarray(r, dtype=float) for r in lrows])
+    m = np.array([A[i].shape[0] for i in range(N)], dtype=np.int64)
+    l = np.array([FR[j].shape[0] for j in range(N - 1)], dtype=np.int64)
+    out = GeneralInstance(N=N, n0=n0, m=m, n=nn, l=l, A=A, C=C, FR=FR, FL=FL,
+                          F0=np.vstack(F0) if F0 else None, b=b,
+                          H=[widen(g.H[i], i) for i in range(N)], G=g.G, d=g.d, f=g.f, G0=g.G0,
+                          d0=g.d0, f0=g.f0, KR=[widen(g.KR[j], j) for j in range(N - 1)],
+                          KL=[widen(g.KL[j], j + 1) for j in range(N - 1)], dl=g.dl, fl=g.fl,
+                          c=np.concatenate(c), lo=np.concatenate(lo), up=np.concatenate(up))
+    return out, np.array(keep, dtype=np.int64)
+
+
 def reformulate(g: GeneralInstance):
     """Standard-form Instance, and for every original variable its
-    (offset, [(block or -1 for x_0, column, sign)]) so x can be recovered."""
+    (offset, [(block or -1 for x_0, column, sign)]) so x can be recovered
+    (global rows are chained first; their partial sums are dropped from the
+    list)."""
+    if g.ng:
+        gc, keep = chain(g)
+        inst, var, const = reformulate(gc)
+        return inst, [var[k] for k in keep], const
     N, n0 = g.N, g.n0
     xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
     nt = g.n_tot

@@ -264,10 +264,12 @@ def apply_At(inst: Instance, y: np.ndarray) -> np.ndarray:
 #   x_0 rows        d_0 <= G_0 x_0 <= f_0
 #   link rows       FR_j x_j + FL_j x_{j+1} (+ F0_j x_0) = b_Lj
 #                   dl_j <= KR_j x_j + KL_j x_{j+1} <= fl_j    j = 1..N-1
+#   global rows     dg <= Wg_1 x_1 + ... + Wg_N x_N + Wg_0 x_0 <= fg
+#                   (an equality where dg = fg)
 #   bounds          lo <= x <= up   (entries may be -inf / +inf, lo < up)
 #
 # Inequality sides may be infinite (one side at a time).  x_0-only equality
-# rows and global linking rows are not part of this form.
+# rows are not part of this form.
 
 @dataclass
 class GeneralInstance:
@@ -296,7 +298,15 @@ class GeneralInstance:
     c: np.ndarray                 # [n_tot], canonical order [x_1..x_N, x_0]
     lo: np.ndarray
     up: np.ndarray
+    Wg: List[np.ndarray] = field(default_factory=list)   # global rows, block i part: ng x n_i
+    Wg0: Optional[np.ndarray] = None                      # global rows, x_0 part: ng x n0
+    dg: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    fg: np.ndarray = field(default_factory=lambda: np.zeros(0))
     xhat: np.ndarray = field(default=None)   # the interior point the data were drawn around
+
+    @property
+    def ng(self) -> int:
+        return int(self.dg.size)
 
     @property
     def n_tot(self) -> int:
@@ -306,7 +316,8 @@ class GeneralInstance:
 def general_matrices(g: GeneralInstance):
     """The constraint rows of a general instance as global sparse matrices
     (columns in canonical order): (Aeq, beq, Ain, lower, upper) with equality
-    rows [blocks, links] and inequality rows [blocks, x_0-only, links]."""
+    rows [blocks, links, global equalities] and inequality rows [blocks,
+    x_0-only, links, global inequalities]."""
     import scipy.sparse as sp
     xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
     nt = g.n_tot
@@ -338,18 +349,30 @@ def general_matrices(g: GeneralInstance):
     for j in range(g.N - 1):
         ineq.append(place([(g.KR[j], xo[j]), (g.KL[j], xo[j + 1])]))
         lower.append(g.dl[j]); upper.append(g.fl[j])
+    beq = [g.b]
+    if g.ng:
+        Wrow = place([(g.Wg[i], xo[i]) for i in range(g.N)] + [(g.Wg0, xo[-1])])
+        is_eq = g.dg == g.fg
+        if is_eq.any():
+            eq.append(Wrow[np.flatnonzero(is_eq)])
+            beq.append(g.dg[is_eq])
+        if (~is_eq).any():
+            ineq.append(Wrow[np.flatnonzero(~is_eq)])
+            lower.append(g.dg[~is_eq]); upper.append(g.fg[~is_eq])
     Aeq = sp.vstack(eq).tocsr() if eq else sp.csr_matrix((0, nt))
     Ain = sp.vstack(ineq).tocsr()
-    return Aeq, g.b.copy(), Ain, np.concatenate(lower), np.concatenate(upper)
+    return Aeq, np.concatenate(beq), Ain, np.concatenate(lower), np.concatenate(upper)
 
 
 GENERAL_CONFIGS = {
     # small: every bound and row kind on a few blocks (dense references finish fast)
-    "g_small": dict(N=6, m=(6, 12), mi=(1, 4), extra=4, l=2, li=1, n0=3, mi0=2, density=0.4),
+    "g_small": dict(N=6, m=(6, 12), mi=(1, 4), extra=4, l=2, li=1, n0=3, mi0=2, ng=2, density=0.4),
     # medium: for the GPU
-    "g_medium": dict(N=64, m=(48, 96), mi=(8, 24), extra=16, l=4, li=2, n0=8, mi0=4, density=0.15),
+    "g_medium": dict(N=64, m=(48, 96), mi=(8, 24), extra=16, l=4, li=2, n0=8, mi0=4, ng=2,
+                     density=0.15),
     # large: 256 time blocks of 96..160 equality and 16..48 inequality rows
-    "g_large": dict(N=256, m=(96, 160), mi=(16, 48), extra=32, l=8, li=4, n0=16, mi0=8, density=0.10),
+    "g_large": dict(N=256, m=(96, 160), mi=(16, 48), extra=32, l=8, li=4, n0=16, mi0=8, ng=4,
+                    density=0.10),
 }
 
 
@@ -357,10 +380,12 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     """Draw a feasible, bounded general instance.
 
     Draw order (PCG64(seed)): sizes (m_i, mi_i, then per block n_i = m_i + mi_i
-    + extra), A_i, C_i, H_i, G_i per block, G_0, KR_j, KL_j per pair, then per
-    variable its bound kind and the interior point, then per inequality row
-    its side kind and widths, then y, the inequality multipliers and the
-    reduced costs.
+    + extra), A_i, C_i, H_i, G_i per block, G_0, KR_j, KL_j per pair, the
+    global rows' parts Wg_i (about 3 entries per row and block) and Wg_0, then
+    per variable its bound kind and the interior point, then per inequality
+    row its side kind and widths, then y, the inequality multipliers and the
+    reduced costs.  Global rows 0, 2, ... are equalities, 1, 3, ...
+    inequalities.
 
     Bound kinds (probabilities): [0, inf) 0.4, [lo, up] 0.3, [lo, inf) 0.1,
     (-inf, up] 0.1, free 0.1.  The equality right-hand sides are the rows at
@@ -410,6 +435,12 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
             kr[k, nj - lj - 1 - k] = rng.uniform(0.5, 1.5)
             kl[k, lj + k] = -rng.uniform(0.5, 1.5)
         KR.append(kr); KL.append(kl)
+    # global rows: a few entries in every block (and on x_0); rows 0, 2, ...
+    # are equalities, rows 1, 3, ... inequalities
+    ng = int(cfg.get("ng", 0))
+    Wg = [_sparse_block(rng, ng, int(n[i]), min(dens, 3.0 / float(n[i])), False) for i in range(N)]
+    Wg0 = _sparse_block(rng, ng, n0, min(1.0, max(dens, 0.5)), False)
+    geq = np.arange(ng) % 2 == 0
 
     nt = int(n.sum()) + n0
     kind = rng.choice(5, size=nt, p=[0.4, 0.3, 0.1, 0.1, 0.1])
@@ -433,13 +464,18 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     inst = GeneralInstance(N=N, n0=n0, m=m, n=n, l=l, A=A, C=C, FR=FR, FL=FL, F0=None,
                            b=np.zeros(int(m.sum() + l.sum())), H=H, G=G, d=[], f=[],
                            G0=G0, d0=np.zeros(mi0), f0=np.zeros(mi0), KR=KR, KL=KL, dl=[], fl=[],
-                           c=np.zeros(nt), lo=lo, up=up, xhat=xhat)
+                           c=np.zeros(nt), lo=lo, up=up, Wg=Wg, Wg0=Wg0,
+                           dg=np.zeros(ng), fg=np.where(geq, 0.0, 1.0), xhat=xhat)
     for i in range(N):
         inst.d.append(np.zeros(int(mi[i]))); inst.f.append(np.zeros(int(mi[i])))
     for j in range(N - 1):
         inst.dl.append(np.zeros(int(li[j]))); inst.fl.append(np.zeros(int(li[j])))
     Aeq, _, Ain, _, _ = general_matrices(inst)
-    inst.b = Aeq @ xhat
+    beq = Aeq @ xhat
+    nb = int(m.sum() + l.sum())
+    inst.b = beq[:nb]
+    inst.dg[geq] = beq[nb:]
+    inst.fg[geq] = beq[nb:]
     rhat = Ain @ xhat
     nin = rhat.size
     side = rng.choice(3, size=nin, p=[0.5, 0.25, 0.25])
@@ -454,6 +490,8 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     inst.d0 = dv[pos:pos + mi0]; inst.f0 = fv[pos:pos + mi0]; pos += mi0
     for j in range(N - 1):
         k = int(li[j]); inst.dl[j] = dv[pos:pos + k]; inst.fl[j] = fv[pos:pos + k]; pos += k
+    inst.dg[~geq] = dv[pos:]
+    inst.fg[~geq] = fv[pos:]
     # dual-feasible cost
     y = rng.standard_normal(Aeq.shape[0])
     lam_raw = rng.uniform(0.0, 1.0, size=nin)

@@ -11,7 +11,20 @@ interior-point iteration still runs in libahlp's kernels:
     bounds [d, f] placed in the row's block (the left block for a link pair,
     the first block for x_0-only rows), converted like a variable;
   * every remaining finite upper bound u' gets a slack row x' + s = u' in the
-    variable's block (the first block for x_0).
+    variable's block (the first block for x_0);
+  * a global row dg <= sum_i Wg_i x_i + Wg_0 x_0 <= fg is chained through the
+    blocks: block i gets the partial sum s_i = s_{i-1} + Wg_i x_i as a new
+    free variable (block 1's includes Wg_0 x_0), block 1 a row defining s_1,
+    link pair i a row s_{i+1} - s_i - Wg_{i+1} x_{i+1} = 0, and the last
+    partial sum takes the row's sides as bounds.  An equality row has no last
+    partial sum: its last link row (its block row when N = 1) carries the
+    right-hand side.  Global rows thus become local two-links (done first,
+    by chain_globals).
+
+Layout after chain_globals: block i's variables are its own, then its partial
+sums s_{k,i} for k = 0, 1, ... (where they exist); block 1's equality rows are
+its own, then one per global row; link pair j's equality rows are its own,
+then one per global row.
 
 Standard-form layout of block i (columns):
   1. its n_i variables (x', or x+ of a free variable), in order;
@@ -40,11 +53,13 @@ from .gen import GeneralInstance, Instance
 
 @dataclass
 class StandardMap:
-    """x = off + T x_std for each block (and x_0); objective constant."""
+    """x = off + T x_std for each block (and x_0); objective constant; keep:
+    the original variables among those of the chained form (None: all)."""
     T: List[np.ndarray]        # per block: n_i x ncol_i, then x_0: n0 x n0_std
     off: List[np.ndarray]
     xoff_std: np.ndarray       # block starts in the standard x (length N+1)
     const: float
+    keep: np.ndarray = None
 
 
 def _var_map(lo, up):
@@ -78,8 +93,98 @@ def _slack_col(dv, fv):
     return -1.0, fv, np.inf
 
 
+def chain_globals(g: GeneralInstance) -> GeneralInstance:
+    """The same LP with every global row replaced by a chain of partial sums
+    (local two-links); the original variables stay first in each block."""
+    if g.ng == 0:
+        return g
+    N, n0, ng = g.N, g.n0, g.ng
+    is_eq = g.dg == g.fg
+    # which partial sums exist: s_{k,i} for i < N-1, and the last for inequalities
+    has = np.ones((ng, N), dtype=bool)
+    has[is_eq, N - 1] = False
+    nsum = has.sum(axis=0)                          # new variables per block
+    col = np.cumsum(has, axis=0) - 1                # index of s_{k,i} among block i's sums
+    xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
+    n_new = g.n + nsum
+    lo, up, c = [], [], []
+    for i in range(N):
+        sl = slice(xo[i], xo[i + 1])
+        lo_s = np.full(int(nsum[i]), -np.inf)
+        up_s = np.full(int(nsum[i]), np.inf)
+        if i == N - 1:
+            for k in range(ng):
+                if has[k, i]:
+                    lo_s[col[k, i]] = g.dg[k]
+                    up_s[col[k, i]] = g.fg[k]
+        lo += [g.lo[sl], lo_s]
+        up += [g.up[sl], up_s]
+        c += [g.c[sl], np.zeros(int(nsum[i]))]
+    lo += [g.lo[xo[-1]:]]
+    up += [g.up[xo[-1]:]]
+    c += [g.c[xo[-1]:]]
+    pad = lambda X, i: np.hstack([X, np.zeros((X.shape[0], int(nsum[i])))])
+    A = [pad(g.A[i], i) for i in range(N)]
+    C = [g.C[i].copy() for i in range(N)]
+    H = [pad(g.H[i], i) for i in range(N)]
+    KR = [pad(g.KR[j], j) for j in range(N - 1)]
+    KL = [pad(g.KL[j], j + 1) for j in range(N - 1)]
+    FR = [pad(g.FR[j], j) for j in range(N - 1)]
+    FL = [pad(g.FL[j], j + 1) for j in range(N - 1)]
+    mb = int(g.m.sum())
+    bb = [g.b[int(g.m[:i].sum()):int(g.m[:i + 1].sum())] for i in range(N)]
+    lofs = np.concatenate([[0], np.cumsum(g.l)]).astype(np.int64)
+    bl = [g.b[mb + lofs[j]: mb + lofs[j + 1]] for j in range(N - 1)]
+    F0 = [g.F0[lofs[j]:lofs[j + 1]] if g.F0 is not None else np.zeros((int(g.l[j]), n0))
+          for j in range(N - 1)]
+    # block 1: s_{k,0} - Wg_0 x_1 - Wg0 x_0 = 0 (or, with no s_{k,0}, the row itself)
+    R = np.zeros((ng, int(n_new[0])))
+    R[:, :int(g.n[0])] = -g.Wg[0]
+    RC = -g.Wg0 if n0 else np.zeros((ng, 0))
+    rb = np.zeros(ng)
+    for k in range(ng):
+        if has[k, 0]:
+            R[k, int(g.n[0]) + col[k, 0]] = 1.0
+        else:
+            rb[k] = -g.dg[k]
+    A[0] = np.vstack([A[0], R])
+    C[0] = np.vstack([C[0], RC])
+    bb[0] = np.concatenate([bb[0], rb])
+    # pair j: s_{k,j+1} - s_{k,j} - Wg_{j+1} x_{j+1} = 0 (or = -dg at the end of an equality)
+    for j in range(N - 1):
+        fr = np.zeros((ng, int(n_new[j])))
+        fl = np.zeros((ng, int(n_new[j + 1])))
+        fl[:, :int(g.n[j + 1])] = -g.Wg[j + 1]
+        rj = np.zeros(ng)
+        for k in range(ng):
+            fr[k, int(g.n[j]) + col[k, j]] = -1.0
+            if has[k, j + 1]:
+                fl[k, int(g.n[j + 1]) + col[k, j + 1]] = 1.0
+            else:
+                rj[k] = -g.dg[k]
+        FR[j] = np.vstack([FR[j], fr])
+        FL[j] = np.vstack([FL[j], fl])
+        F0[j] = np.vstack([F0[j], np.zeros((ng, n0))])
+        bl[j] = np.concatenate([bl[j], rj])
+    F0all = np.vstack(F0) if F0 and (g.F0 is not None) else None
+    out = GeneralInstance(
+        N=N, n0=n0, m=g.m + np.eye(N, dtype=np.int64)[0] * ng, n=n_new, l=g.l + ng, A=A, C=C,
+        FR=FR, FL=FL, F0=F0all, b=np.concatenate(bb + bl), H=H, G=[x.copy() for x in g.G],
+        d=g.d, f=g.f, G0=g.G0, d0=g.d0, f0=g.f0, KR=KR, KL=KL, dl=g.dl, fl=g.fl,
+        c=np.concatenate(c), lo=np.concatenate(lo), up=np.concatenate(up))
+    out.orig_cols = np.concatenate([np.arange(xo[i] + np.sum(nsum[:i]), xo[i + 1] + np.sum(nsum[:i]))
+                                    for i in range(N)]
+                                   + [np.arange(int(n_new.sum()), int(n_new.sum()) + n0)])
+    return out
+
+
 def to_standard(g: GeneralInstance):
     """The equivalent standard-form Instance and the map back to x."""
+    if g.ng:
+        gc = chain_globals(g)
+        inst, mp = to_standard(gc)
+        mp.keep = gc.orig_cols
+        return inst, mp
     N, n0 = g.N, g.n0
     xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
     # x_0
@@ -199,7 +304,8 @@ def from_standard(mp: StandardMap, x_std: np.ndarray) -> np.ndarray:
     N = len(mp.T) - 1
     parts = [mp.off[i] + mp.T[i] @ x_std[mp.xoff_std[i]:mp.xoff_std[i + 1]] for i in range(N)]
     parts.append(mp.off[N] + mp.T[N] @ x_std[mp.xoff_std[N]:])
-    return np.concatenate(parts)
+    x = np.concatenate(parts)
+    return x if mp.keep is None else x[mp.keep]
 
 
 def solve(g: GeneralInstance, stream=None, **opts):

@@ -2,14 +2,15 @@
 and variable bounds reformulated into the standard arrowhead form, then the
 oracle IPM), to things other than itself:
 
-* the optimum of the untransformed general LP from SciPy's HiGHS (bounds and
-  two-sided rows handed over as they are), objective within 1e-7 relative
-  (both solvers stop at about 1e-8);
+* the optimum of the untransformed general LP from SciPy's HiGHS (bounds,
+  two-sided rows and global rows handed over as they are), objective within
+  1e-7 relative (both solvers stop at about 1e-8);
 * the recovered x is feasible in the general form: equality rows,
   inequality sides and bounds, within 1e-7;
 * a closed form: min c'x over sum x = s with 0 <= x <= u (and one free
   variable fixed by a second row) is filled greedily in cost order;
-* a planted mistake (upper bounds dropped) fails the HiGHS pin;
+* planted mistakes (upper bounds dropped; a global row's chain without its
+  x_0 part) fail the HiGHS pin;
 * the GPU path's reformulation (paper_2412_07731_amd.general, written
   separately) produces the same standard-form instance.
 """
@@ -46,8 +47,9 @@ def violation(g, x):
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_general_matches_highs(seed):
     g = gen.generate_general("g_small", seed)
-    # every bound and row kind is present
+    # every bound and row kind is present, global rows of both kinds included
     assert np.isinf(g.lo).any() and np.isfinite(g.up).any() and (np.isinf(g.lo) & np.isinf(g.up)).any()
+    assert (g.dg == g.fg).any() and (g.dg != g.fg).any()
     x, f, r = og.solve(g)
     assert r.status == "optimal"
     fh = highs(g)
@@ -101,6 +103,22 @@ def test_planted_mistake_fails():
     bad.up = np.where(np.isfinite(bad.lo), np.inf, bad.up)    # boxes lose their upper side
     x, f, r = og.solve(bad)
     assert r.status != "optimal" or abs(f - fh) > 1e-3 * max(1.0, abs(fh))
+
+
+def test_planted_chain_mistake_fails(monkeypatch):
+    """The chain of a global row loses its x_0 part: the HiGHS pin catches it."""
+    g = gen.generate_general("g_small", 1)
+    fh = highs(g)
+    real = og.chain
+
+    def broken(gg):
+        out, keep = real(gg)
+        out.C[0][-gg.ng:] = 0.0
+        return out, keep
+
+    monkeypatch.setattr(og, "chain", broken)
+    x, f, r = og.solve(g)
+    assert r.status != "optimal" or abs(f - fh) > 1e-4 * max(1.0, abs(fh))
 
 
 @pytest.mark.parametrize("seed", [0, 1])
