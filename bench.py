@@ -208,8 +208,8 @@ def general_bench(golden_runs, steps=3):
     P = Problem(inst)
     out = {"workload": "g_large: N=256 blocks, 96..160 equality + 16..48 inequality rows, "
                        "8 equality + 4 inequality link rows per pair, 4 global linking rows "
-                       "(2 equalities, 2 inequalities), 16 linking variables, bounds of every "
-                       "kind, seed 0",
+                       "(2 equalities, 2 inequalities), 16 linking variables with 8 inequality "
+                       "and 2 equality rows of their own, bounds of every kind, seed 0",
            "unit": "IPM iterations/s",
            "standard_form": {"m_tot": int(inst.m_tot), "n_tot": int(inst.n_tot),
                              "m_i": [int(inst.m.min()), int(inst.m.max())],

@@ -19,6 +19,12 @@ inequality rows and bounds.  This reformulation is the textbook one:
 Chaining layout: block i's partial sums follow its own variables (global row
 order); block 1's and every link pair's new rows follow their own equality
 rows.
+Before all that, equality rows on x_0 alone (A_0 x_0 = b_0, full row rank)
+are eliminated: the basic entries B of x_0 (the first r of a column-pivoted QR
+of A_0) are x_B = B^-1 (b_0 - A_0,N x_N), substituted into every row that
+touches x_0; x_N remain the linking variables with their own bounds, and each
+bounded x_B becomes an x_0-only inequality row on x_N (after the existing
+ones).
 Placement (the layout the GPU path uses too): block i's columns are its
 variables, x- of its free variables, the slacks of its inequality rows, of
 link pair i's inequality rows and (block 1) of the x_0-only rows, then the
@@ -50,6 +56,72 @@ class _Cols:
         self.kinds.append(kind)
         self.ub.append(ub)
         return len(self.kinds) - 1
+
+
+def eliminate_x0(g: GeneralInstance):
+    """x_0-only equality rows eliminated: (instance over x_N, basic indices,
+    nonbasic indices, B^-1 b_0, B^-1 A_0,N)."""
+    import scipy.linalg as sla
+    n0 = g.n0
+    _, _, perm = sla.qr(g.A0, pivoting=True)
+    r = g.A0.shape[0]
+    bas, non = list(perm[:r]), list(perm[r:])
+    Bm = g.A0[:, bas]
+    u = np.linalg.solve(Bm, g.b0)                 # x_B = u - V x_N
+    V = np.linalg.solve(Bm, g.A0[:, non])
+
+    def sub_cols(M):
+        """M x_0 = M[:, non] x_N + M[:, bas] (u - V x_N): (new matrix, constant)."""
+        MB = M[:, bas]
+        return M[:, non] - MB @ V, MB @ u
+
+    C, G = [], []
+    b = g.b.copy()
+    d, f = [], []
+    mfirst = np.concatenate([[0], np.cumsum(g.m)]).astype(np.int64)
+    for i in range(g.N):
+        Ci, ci = sub_cols(g.C[i])
+        C.append(Ci)
+        b[mfirst[i]:mfirst[i + 1]] = b[mfirst[i]:mfirst[i + 1]] - ci
+        Gi, gi = sub_cols(g.G[i])
+        G.append(Gi)
+        d.append(g.d[i] - gi)
+        f.append(g.f[i] - gi)
+    F0 = None
+    if g.F0 is not None:
+        F0, f0c = sub_cols(g.F0)
+        b[int(mfirst[-1]):] = b[int(mfirst[-1]):] - f0c
+    Wg0, dg, fg = g.Wg0, g.dg, g.fg
+    if g.ng:
+        Wg0, wc = sub_cols(g.Wg0)
+        dg, fg = g.dg - wc, g.fg - wc
+    xs = int(g.n.sum())
+    G0rows, d0, f0 = [], [], []
+    if g.G0.shape[0]:
+        G0n, gc0 = sub_cols(g.G0)
+        G0rows.append(G0n)
+        d0.append(g.d0 - gc0)
+        f0.append(g.f0 - gc0)
+    for q, j in enumerate(bas):
+        lo, up = g.lo[xs + j], g.up[xs + j]
+        if np.isfinite(lo) or np.isfinite(up):
+            # x_B,q = u_q - V_q x_N  in [lo, up]  ->  -V_q x_N in [lo - u_q, up - u_q]
+            G0rows.append(-V[q:q + 1])
+            d0.append(np.array([lo - u[q]]))
+            f0.append(np.array([up - u[q]]))
+    c0 = g.c[xs:]
+    cB = c0[bas]
+    out = GeneralInstance(
+        N=g.N, n0=len(non), m=g.m, n=g.n, l=g.l, A=g.A, C=C, FR=g.FR, FL=g.FL, F0=F0, b=b,
+        H=g.H, G=G, d=d, f=f,
+        G0=np.vstack(G0rows) if G0rows else np.zeros((0, len(non))),
+        d0=np.concatenate(d0) if d0 else np.zeros(0), f0=np.concatenate(f0) if f0 else np.zeros(0),
+        KR=g.KR, KL=g.KL, dl=g.dl, fl=g.fl,
+        c=np.concatenate([g.c[:xs], c0[non] - V.T @ cB]),
+        lo=np.concatenate([g.lo[:xs], g.lo[xs:][non]]),
+        up=np.concatenate([g.up[:xs], g.up[xs:][non]]),
+        Wg=g.Wg, Wg0=Wg0, dg=dg, fg=fg)
+    return out, bas, non, u, V
 
 
 def chain(g: GeneralInstance):
@@ -143,6 +215,23 @@ def reformulate(g: GeneralInstance):
     (offset, [(block or -1 for x_0, column, sign)]) so x can be recovered
     (global rows are chained first; their partial sums are dropped from the
     list)."""
+    if g.A0 is not None and g.A0.shape[0]:
+        h, bas, non, u, V = eliminate_x0(g)
+        inst, var, const = reformulate(h)
+        # x_0 entries: x_N,k as reformulated; x_B,q = u_q - V_q x_N
+        xs = int(g.n.sum())
+        full = list(var[:xs]) + [None] * g.n0
+        for k, j in enumerate(non):
+            full[xs + j] = var[xs + k]
+        for q, j in enumerate(bas):
+            off = u[q]
+            terms = []
+            for k in range(len(non)):
+                okk, tk = var[xs + k]
+                off -= V[q, k] * okk
+                terms += [(blk, col, -V[q, k] * sgn) for blk, col, sgn in tk]
+            full[xs + j] = (off, terms)
+        return inst, full, const + 0.0
     if g.ng:
         gc, keep = chain(g)
         inst, var, const = reformulate(gc)

@@ -266,10 +266,10 @@ def apply_At(inst: Instance, y: np.ndarray) -> np.ndarray:
 #                   dl_j <= KR_j x_j + KL_j x_{j+1} <= fl_j    j = 1..N-1
 #   global rows     dg <= Wg_1 x_1 + ... + Wg_N x_N + Wg_0 x_0 <= fg
 #                   (an equality where dg = fg)
+#   x_0 rows        A_0 x_0 = b_0   (full row rank)
 #   bounds          lo <= x <= up   (entries may be -inf / +inf, lo < up)
 #
-# Inequality sides may be infinite (one side at a time).  x_0-only equality
-# rows are not part of this form.
+# Inequality sides may be infinite (one side at a time).
 
 @dataclass
 class GeneralInstance:
@@ -302,6 +302,8 @@ class GeneralInstance:
     Wg0: Optional[np.ndarray] = None                      # global rows, x_0 part: ng x n0
     dg: np.ndarray = field(default_factory=lambda: np.zeros(0))
     fg: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    A0: Optional[np.ndarray] = None                       # x_0-only equality rows: me0 x n0
+    b0: np.ndarray = field(default_factory=lambda: np.zeros(0))
     xhat: np.ndarray = field(default=None)   # the interior point the data were drawn around
 
     @property
@@ -316,8 +318,8 @@ class GeneralInstance:
 def general_matrices(g: GeneralInstance):
     """The constraint rows of a general instance as global sparse matrices
     (columns in canonical order): (Aeq, beq, Ain, lower, upper) with equality
-    rows [blocks, links, global equalities] and inequality rows [blocks,
-    x_0-only, links, global inequalities]."""
+    rows [blocks, links, global equalities, x_0-only] and inequality rows
+    [blocks, x_0-only, links, global inequalities]."""
     import scipy.sparse as sp
     xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
     nt = g.n_tot
@@ -359,6 +361,9 @@ def general_matrices(g: GeneralInstance):
         if (~is_eq).any():
             ineq.append(Wrow[np.flatnonzero(~is_eq)])
             lower.append(g.dg[~is_eq]); upper.append(g.fg[~is_eq])
+    if g.A0 is not None and g.A0.shape[0]:
+        eq.append(place([(g.A0, xo[-1])]))
+        beq.append(g.b0)
     Aeq = sp.vstack(eq).tocsr() if eq else sp.csr_matrix((0, nt))
     Ain = sp.vstack(ineq).tocsr()
     return Aeq, np.concatenate(beq), Ain, np.concatenate(lower), np.concatenate(upper)
@@ -366,13 +371,14 @@ def general_matrices(g: GeneralInstance):
 
 GENERAL_CONFIGS = {
     # small: every bound and row kind on a few blocks (dense references finish fast)
-    "g_small": dict(N=6, m=(6, 12), mi=(1, 4), extra=4, l=2, li=1, n0=3, mi0=2, ng=2, density=0.4),
+    "g_small": dict(N=6, m=(6, 12), mi=(1, 4), extra=4, l=2, li=1, n0=3, mi0=2, ng=2, me0=1,
+                    density=0.4),
     # medium: for the GPU
     "g_medium": dict(N=64, m=(48, 96), mi=(8, 24), extra=16, l=4, li=2, n0=8, mi0=4, ng=2,
-                     density=0.15),
+                     me0=2, density=0.15),
     # large: 256 time blocks of 96..160 equality and 16..48 inequality rows
     "g_large": dict(N=256, m=(96, 160), mi=(16, 48), extra=32, l=8, li=4, n0=16, mi0=8, ng=4,
-                    density=0.10),
+                    me0=2, density=0.10),
 }
 
 
@@ -385,7 +391,8 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     per variable its bound kind and the interior point, then per inequality
     row its side kind and widths, then y, the inequality multipliers and the
     reduced costs.  Global rows 0, 2, ... are equalities, 1, 3, ...
-    inequalities.
+    inequalities.  The x_0-only equality rows A_0 (drawn after the global
+    rows, 60% dense, no zero rows) get b_0 = A_0 x_0 at the interior point.
 
     Bound kinds (probabilities): [0, inf) 0.4, [lo, up] 0.3, [lo, inf) 0.1,
     (-inf, up] 0.1, free 0.1.  The equality right-hand sides are the rows at
@@ -441,6 +448,8 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     Wg = [_sparse_block(rng, ng, int(n[i]), min(dens, 3.0 / float(n[i])), False) for i in range(N)]
     Wg0 = _sparse_block(rng, ng, n0, min(1.0, max(dens, 0.5)), False)
     geq = np.arange(ng) % 2 == 0
+    me0 = int(cfg.get("me0", 0)) if n0 > 1 else 0
+    A0 = _sparse_block(rng, me0, n0, 0.6, True) if me0 else None
 
     nt = int(n.sum()) + n0
     kind = rng.choice(5, size=nt, p=[0.4, 0.3, 0.1, 0.1, 0.1])
@@ -465,7 +474,8 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
                            b=np.zeros(int(m.sum() + l.sum())), H=H, G=G, d=[], f=[],
                            G0=G0, d0=np.zeros(mi0), f0=np.zeros(mi0), KR=KR, KL=KL, dl=[], fl=[],
                            c=np.zeros(nt), lo=lo, up=up, Wg=Wg, Wg0=Wg0,
-                           dg=np.zeros(ng), fg=np.where(geq, 0.0, 1.0), xhat=xhat)
+                           dg=np.zeros(ng), fg=np.where(geq, 0.0, 1.0), A0=A0,
+                           b0=np.zeros(me0), xhat=xhat)
     for i in range(N):
         inst.d.append(np.zeros(int(mi[i]))); inst.f.append(np.zeros(int(mi[i])))
     for j in range(N - 1):
@@ -473,9 +483,11 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     Aeq, _, Ain, _, _ = general_matrices(inst)
     beq = Aeq @ xhat
     nb = int(m.sum() + l.sum())
+    nge = int(geq.sum())
     inst.b = beq[:nb]
-    inst.dg[geq] = beq[nb:]
-    inst.fg[geq] = beq[nb:]
+    inst.dg[geq] = beq[nb:nb + nge]
+    inst.fg[geq] = beq[nb:nb + nge]
+    inst.b0 = beq[nb + nge:]
     rhat = Ain @ xhat
     nin = rhat.size
     side = rng.choice(3, size=nin, p=[0.5, 0.25, 0.25])

@@ -19,7 +19,12 @@ interior-point iteration still runs in libahlp's kernels:
     partial sum takes the row's sides as bounds.  An equality row has no last
     partial sum: its last link row (its block row when N = 1) carries the
     right-hand side.  Global rows thus become local two-links (done first,
-    by chain_globals).
+    by chain_globals);
+  * equality rows on x_0 alone, A_0 x_0 = b_0 (full row rank), are solved for
+    r = rank basic entries of x_0 chosen by a column-pivoted QR of A_0:
+    x_B = B^-1 (b_0 - A_0,N x_N).  x_N stay the linking variables with their
+    bounds, x_B is substituted in every row, and x_B's bounds become x_0-only
+    inequality rows on x_N (done before everything else, by eliminate_x0_rows).
 
 Layout after chain_globals: block i's variables are its own, then its partial
 sums s_{k,i} for k = 0, 1, ... (where they exist); block 1's equality rows are
@@ -60,6 +65,7 @@ class StandardMap:
     xoff_std: np.ndarray       # block starts in the standard x (length N+1)
     const: float
     keep: np.ndarray = None
+    x0map: tuple = None        # (e, E, x_0 start): x_0 = e + E x_N
 
 
 def _var_map(lo, up):
@@ -91,6 +97,64 @@ def _slack_col(dv, fv):
     if np.isfinite(dv):
         return 1.0, dv, (fv - dv) if np.isfinite(fv) else np.inf
     return -1.0, fv, np.inf
+
+
+def eliminate_x0_rows(g: GeneralInstance):
+    """The same LP without x_0-only equality rows: x_0 = e + E x_N.  Returns
+    the reduced instance, e and E."""
+    import copy
+    import scipy.linalg as sla
+    me0 = 0 if g.A0 is None else g.A0.shape[0]
+    n0 = g.n0
+    if me0 == 0:
+        return g, np.zeros(n0), np.eye(n0)
+    _, _, perm = sla.qr(g.A0, pivoting=True)
+    bas, non = perm[:me0], perm[me0:]
+    Binv = np.linalg.inv(g.A0[:, bas])
+    pB = Binv @ g.b0
+    QB = -Binv @ g.A0[:, non]
+    E = np.zeros((n0, non.size))
+    e = np.zeros(n0)
+    E[non, np.arange(non.size)] = 1.0
+    E[bas] = QB
+    e[bas] = pB
+    h = copy.copy(g)
+    xo0 = int(g.n.sum())
+    h.n0 = int(non.size)
+    h.C = [Ci @ E for Ci in g.C]
+    h.G = [Gi @ E for Gi in g.G]
+    h.b = g.b.copy()
+    mb = int(g.m.sum())
+    for i in range(g.N):
+        h.b[int(g.m[:i].sum()):int(g.m[:i + 1].sum())] -= g.C[i] @ e
+    h.d = [g.d[i] - g.G[i] @ e for i in range(g.N)]
+    h.f = [g.f[i] - g.G[i] @ e for i in range(g.N)]
+    if g.F0 is not None:
+        h.F0 = g.F0 @ E
+        h.b[mb:] -= g.F0 @ e
+    if g.ng:
+        h.Wg0 = g.Wg0 @ E
+        h.dg = g.dg - g.Wg0 @ e
+        h.fg = g.fg - g.Wg0 @ e
+    # x_0-only inequality rows: the existing ones, then the bounds of x_B
+    lo0, up0 = g.lo[xo0:], g.up[xo0:]
+    rows = [g.G0 @ E] if g.G0.size else []
+    dd = [g.d0 - g.G0 @ e] if g.G0.size else []
+    ff = [g.f0 - g.G0 @ e] if g.G0.size else []
+    for q, j in enumerate(bas):
+        if np.isfinite(lo0[j]) or np.isfinite(up0[j]):
+            rows.append(QB[q:q + 1])
+            dd.append(np.array([lo0[j] - pB[q]]))
+            ff.append(np.array([up0[j] - pB[q]]))
+    h.G0 = np.vstack(rows) if rows else np.zeros((0, h.n0))
+    h.d0 = np.concatenate(dd) if dd else np.zeros(0)
+    h.f0 = np.concatenate(ff) if ff else np.zeros(0)
+    h.c = np.concatenate([g.c[:xo0], E.T @ g.c[xo0:]])
+    h.lo = np.concatenate([g.lo[:xo0], lo0[non]])
+    h.up = np.concatenate([g.up[:xo0], up0[non]])
+    h.A0 = None
+    h.b0 = np.zeros(0)
+    return h, e, E
 
 
 def chain_globals(g: GeneralInstance) -> GeneralInstance:
@@ -180,6 +244,11 @@ def chain_globals(g: GeneralInstance) -> GeneralInstance:
 
 def to_standard(g: GeneralInstance):
     """The equivalent standard-form Instance and the map back to x."""
+    if g.A0 is not None and g.A0.shape[0]:
+        h, e, E = eliminate_x0_rows(g)
+        inst, mp = to_standard(h)
+        mp.x0map = (e, E, int(g.n.sum()))
+        return inst, mp
     if g.ng:
         gc = chain_globals(g)
         inst, mp = to_standard(gc)
@@ -305,7 +374,12 @@ def from_standard(mp: StandardMap, x_std: np.ndarray) -> np.ndarray:
     parts = [mp.off[i] + mp.T[i] @ x_std[mp.xoff_std[i]:mp.xoff_std[i + 1]] for i in range(N)]
     parts.append(mp.off[N] + mp.T[N] @ x_std[mp.xoff_std[N]:])
     x = np.concatenate(parts)
-    return x if mp.keep is None else x[mp.keep]
+    if mp.keep is not None:
+        x = x[mp.keep]
+    if mp.x0map is not None:
+        e, E, s0 = mp.x0map
+        x = np.concatenate([x[:s0], e + E @ x[s0:]])
+    return x
 
 
 def solve(g: GeneralInstance, stream=None, **opts):

@@ -3,14 +3,15 @@ and variable bounds reformulated into the standard arrowhead form, then the
 oracle IPM), to things other than itself:
 
 * the optimum of the untransformed general LP from SciPy's HiGHS (bounds,
-  two-sided rows and global rows handed over as they are), objective within
-  1e-7 relative (both solvers stop at about 1e-8);
+  two-sided rows, global rows and x_0-only equality rows handed over as they
+  are), objective within 1e-7 relative (both solvers stop at about 1e-8);
 * the recovered x is feasible in the general form: equality rows,
   inequality sides and bounds, within 1e-7;
 * a closed form: min c'x over sum x = s with 0 <= x <= u (and one free
   variable fixed by a second row) is filled greedily in cost order;
 * planted mistakes (upper bounds dropped; a global row's chain without its
-  x_0 part) fail the HiGHS pin;
+  x_0 part; the substitution of eliminated x_0 entries without its constant
+  part) fail the HiGHS pin;
 * the GPU path's reformulation (paper_2412_07731_amd.general, written
   separately) produces the same standard-form instance.
 """
@@ -50,6 +51,7 @@ def test_general_matches_highs(seed):
     # every bound and row kind is present, global rows of both kinds included
     assert np.isinf(g.lo).any() and np.isfinite(g.up).any() and (np.isinf(g.lo) & np.isinf(g.up)).any()
     assert (g.dg == g.fg).any() and (g.dg != g.fg).any()
+    assert g.A0 is not None and g.A0.shape[0] >= 1          # an x_0-only equality row
     x, f, r = og.solve(g)
     assert r.status == "optimal"
     fh = highs(g)
@@ -105,9 +107,28 @@ def test_planted_mistake_fails():
     assert r.status != "optimal" or abs(f - fh) > 1e-3 * max(1.0, abs(fh))
 
 
+@pytest.mark.parametrize("seed", [0, 3])
+def test_planted_x0_elimination_mistake_fails(monkeypatch, seed):
+    """The elimination of x_0-only equality rows drops the constant part of
+    the substitution (x_B = B^-1 b_0 - ...) from the block rows' right-hand
+    sides: the HiGHS pin catches it."""
+    g = gen.generate_general("g_small", seed)
+    fh = highs(g)
+    real = og.eliminate_x0
+
+    def broken(gg):
+        out, bas, non, u, V = real(gg)
+        out.b = gg.b.copy()
+        return out, bas, non, u, V
+
+    monkeypatch.setattr(og, "eliminate_x0", broken)
+    x, f, r = og.solve(g)
+    assert r.status != "optimal" or abs(f - fh) > 1e-4 * max(1.0, abs(fh))
+
+
 def test_planted_chain_mistake_fails(monkeypatch):
     """The chain of a global row loses its x_0 part: the HiGHS pin catches it."""
-    g = gen.generate_general("g_small", 1)
+    g = gen.generate_general("g_small", 2)
     fh = highs(g)
     real = og.chain
 
