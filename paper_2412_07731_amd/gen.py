@@ -372,7 +372,7 @@ def general_matrices(g: GeneralInstance):
 GENERAL_CONFIGS = {
     # small: every bound and row kind on a few blocks (dense references finish fast)
     "g_small": dict(N=6, m=(6, 12), mi=(1, 4), extra=4, l=2, li=1, n0=3, mi0=2, ng=2, me0=1,
-                    density=0.4),
+                    f0=True, density=0.4),
     # medium: for the GPU
     "g_medium": dict(N=64, m=(48, 96), mi=(8, 24), extra=16, l=4, li=2, n0=8, mi0=4, ng=2,
                      me0=2, density=0.15),
@@ -392,7 +392,9 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     row its side kind and widths, then y, the inequality multipliers and the
     reduced costs.  Global rows 0, 2, ... are equalities, 1, 3, ...
     inequalities.  The x_0-only equality rows A_0 (drawn after the global
-    rows, 60% dense, no zero rows) get b_0 = A_0 x_0 at the interior point.
+    rows, 60% dense, no zero rows) get b_0 = A_0 x_0 at the interior point;
+    with f0, the equality link rows get an x_0 part F0 (50% dense), drawn
+    after A_0.
 
     Bound kinds (probabilities): [0, inf) 0.4, [lo, up] 0.3, [lo, inf) 0.1,
     (-inf, up] 0.1, free 0.1.  The equality right-hand sides are the rows at
@@ -450,6 +452,8 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
     geq = np.arange(ng) % 2 == 0
     me0 = int(cfg.get("me0", 0)) if n0 > 1 else 0
     A0 = _sparse_block(rng, me0, n0, 0.6, True) if me0 else None
+    # equality link rows on x_0 (F0), where asked for
+    F0 = _sparse_block(rng, int(l.sum()), n0, 0.5, False) if cfg.get("f0") and n0 else None
 
     nt = int(n.sum()) + n0
     kind = rng.choice(5, size=nt, p=[0.4, 0.3, 0.1, 0.1, 0.1])
@@ -470,7 +474,7 @@ def generate_general(config="g_small", seed=0, **overrides) -> GeneralInstance:
         else:
             lo[k], up[k], xhat[k] = -np.inf, np.inf, a[k]
 
-    inst = GeneralInstance(N=N, n0=n0, m=m, n=n, l=l, A=A, C=C, FR=FR, FL=FL, F0=None,
+    inst = GeneralInstance(N=N, n0=n0, m=m, n=n, l=l, A=A, C=C, FR=FR, FL=FL, F0=F0,
                            b=np.zeros(int(m.sum() + l.sum())), H=H, G=G, d=[], f=[],
                            G0=G0, d0=np.zeros(mi0), f0=np.zeros(mi0), KR=KR, KL=KL, dl=[], fl=[],
                            c=np.zeros(nt), lo=lo, up=up, Wg=Wg, Wg0=Wg0,

@@ -52,6 +52,7 @@ def test_general_matches_highs(seed):
     assert np.isinf(g.lo).any() and np.isfinite(g.up).any() and (np.isinf(g.lo) & np.isinf(g.up)).any()
     assert (g.dg == g.fg).any() and (g.dg != g.fg).any()
     assert g.A0 is not None and g.A0.shape[0] >= 1          # an x_0-only equality row
+    assert g.F0 is not None and np.any(g.F0)                # link rows on x_0
     x, f, r = og.solve(g)
     assert r.status == "optimal"
     fh = highs(g)
