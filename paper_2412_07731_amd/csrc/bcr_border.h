@@ -13,10 +13,15 @@ namespace ahlp {
 // order), w0 = Lb^-1 s0, u0 = -Lb^-T w0; u0 goes to LDS, to A.u0p and to the
 // border part of A.u.  Every thread of the workgroup calls it (it holds
 // barriers); part: blockDim.x doubles, s0 / w0 / u0: 16 t0 each, sc: 16, all
-// LDS.  Wave 0 does the triangular solves with the tiles of Lb^-1 (tile
-// (r, c) at c t0 + r).
-__device__ inline void bcr_border_solve(const BcrSolveArgs& A, double* part, double* s0,
-                                        double* w0, double* u0, double* sc) {
+// LDS.  Wave 0 does the triangular solves with the tiles of Lb^-1: lbi is
+// either the factor's full t0 x t0 array (tile (r, c) at c t0 + r) or, if
+// packed, a copy of its lower triangle (tile (r, c) at r (r + 1) / 2 + c).
+__device__ __forceinline__ int lbi_tile(int r, int c, int t0, bool packed) {
+  return packed ? r * (r + 1) / 2 + c : c * t0 + r;
+}
+__device__ inline void bcr_border_solve(const BcrSolveArgs& A, const double* lbi, bool packed,
+                                        double* part, double* s0, double* w0, double* u0,
+                                        double* sc) {
   const BcrArgs& c = A.c;
   const int t0 = c.t0, n0 = c.n0, nb = 16 * t0;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -41,7 +46,7 @@ __device__ inline void bcr_border_solve(const BcrSolveArgs& A, double* part, dou
   if (wave == 0) {
     for (int rr = 0; rr < t0; ++rr) {
       double acc = 0.0;
-      for (int cc = 0; cc <= rr; ++cc) acc += op_mv(op_load(c.FLbi + (cc * t0 + rr) * 256), s0 + 16 * cc);
+      for (int cc = 0; cc <= rr; ++cc) acc += op_mv(op_load(lbi + lbi_tile(rr, cc, t0, packed) * 256), s0 + 16 * cc);
       wave_order();
       if (lane < 16) w0[16 * rr + lane] = acc;
       wave_order();
@@ -49,7 +54,7 @@ __device__ inline void bcr_border_solve(const BcrSolveArgs& A, double* part, dou
     for (int cc = 0; cc < t0; ++cc) {
       double acc = 0.0;
       for (int rr = cc; rr < t0; ++rr)
-        acc += op_mtv(op_load(c.FLbi + (cc * t0 + rr) * 256), w0 + 16 * rr, sc);
+        acc += op_mtv(op_load(lbi + lbi_tile(rr, cc, t0, packed) * 256), w0 + 16 * rr, sc);
       if (lane < 16) {
         u0[16 * cc + lane] = -acc;
         A.u0p[16 * cc + lane] = -acc;

@@ -345,24 +345,42 @@ __global__ __launch_bounds__(256) void k_bcr_border(BcrArgs c, int nparts) {
 // Forward: r_e -= X_R(o_l)' w_{o_l} + X_L(o_r)' w_{o_r} with w_o = L_o^-1 r_o;
 // backward: u_o = L_o^-T (w_o - X_L u_L - X_R u_R - Z_o u0).  The pair vectors
 // r, w, u are padded to 16 per pair; level 0 reads the exact right-hand side.
+// The wide levels keep them in the global arrays r, w, up; the single-workgroup
+// tail keeps the vectors of its pairs (every 2^lt-th pair, lt its first level)
+// in LDS, slot j >> lt, and writes to global memory only what later launches
+// read: u (and up for the wide backward levels) and the border partials.
 struct VecLds { double v0[16], v1[16], sc[16], ua[16], ub[16]; };
+constexpr int TAIL_SLOTS = 2 * TAIL_WAVES_S + 2;   // pairs at the tail's first level, at most
+struct TailVecs { double r[TAIL_SLOTS * 16], w[TAIL_SLOTS * 16], u[TAIL_SLOTS * 16]; };
+// where the pair vectors of one level live: T == nullptr for a wide level,
+// else the tail's LDS with r read from the global arrays at its first level
+struct VecPlace {
+  TailVecs* T;
+  int shift;     // slot = position << shift at this level
+  bool r_lds;    // r of this level in LDS (not the tail's first level)
+};
 
 __device__ __forceinline__ double rvec(const BcrSolveArgs& A, int lvl, long long j) {
   if (lvl == 0) return vec_get_exact(A.s + A.loff[j], A.c.l[j]);
   return A.r[j * 16 + (threadIdx.x & 15)];
 }
+__device__ __forceinline__ double rget(const BcrSolveArgs& A, const VecPlace& P, int lvl, int k) {
+  if (P.r_lds) return P.T->r[(k << P.shift) * 16 + (threadIdx.x & 15)];
+  return rvec(A, lvl, (long long)k << lvl);
+}
 
 // even position k of level lvl: updates r_e; stores w and the border
 // partial Z'w of its right neighbour (each odd pair has exactly one left one).
 // All loads of the step are issued first.
-__device__ void bcr_fwd_even(const BcrSolveArgs& A, int lvl, int n, int k, VecLds& V) {
+__device__ void bcr_fwd_even(const BcrSolveArgs& A, int lvl, int n, int k, VecLds& V,
+                             const VecPlace& P) {
   const BcrArgs& c = A.c;
   const int lane = threadIdx.x & 63;
   const long long s = 1LL << lvl, e = k * s, ol = (k - 1) * s, orr = (k + 1) * s;
   const bool hl = k >= 1, hr = k + 1 < n;
-  const double re = rvec(A, lvl, e);
-  const double rl = hl ? rvec(A, lvl, ol) : 0.0;
-  const double rr = hr ? rvec(A, lvl, orr) : 0.0;
+  const double re = rget(A, P, lvl, k);
+  const double rl = hl ? rget(A, P, lvl, k - 1) : 0.0;
+  const double rr = hr ? rget(A, P, lvl, k + 1) : 0.0;
   Op lil{}, xrl{}, lir{}, xlr{}, g[BT_MAXT0];
   if (hl) {
     lil = op_load(c.FLi + ol * 256);
@@ -387,7 +405,10 @@ __device__ void bcr_fwd_even(const BcrSolveArgs& A, int lvl, int n, int k, VecLd
   if (hl) acc -= op_mtv(xrl, V.v1, V.sc);
   if (hr) {
     acc -= op_mtv(xlr, V.ub, V.sc);
-    if (lane < 16) A.w[orr * 16 + lane] = wr;
+    if (lane < 16) {
+      if (P.T) P.T->w[((k + 1) << P.shift) * 16 + lane] = wr;
+      else A.w[orr * 16 + lane] = wr;
+    }
 #pragma unroll
     for (int q = 0; q < BT_MAXT0; ++q)
       if (q < c.t0) {
@@ -396,14 +417,18 @@ __device__ void bcr_fwd_even(const BcrSolveArgs& A, int lvl, int n, int k, VecLd
       }
   }
   wave_order();
-  if (lane < 16) A.r[e * 16 + lane] = acc;
+  if (lane < 16) {
+    if (P.T) P.T->r[(k << P.shift) * 16 + lane] = acc;
+    else A.r[e * 16 + lane] = acc;
+  }
 }
 
-// the final pair (j = 0) forward: w_0 and its border partial
-__device__ void bcr_final_fwd(const BcrSolveArgs& A, int lvl, VecLds& V) {
+// the final pair (j = 0) forward: w_0 (to the tail's slot 0) and its border
+// partial
+__device__ void bcr_final_fwd(const BcrSolveArgs& A, int lvl, VecLds& V, const VecPlace& P) {
   const BcrArgs& c = A.c;
   const int lane = threadIdx.x & 63;
-  const double r0 = rvec(A, lvl, 0);
+  const double r0 = rget(A, P, lvl, 0);
   const Op li = op_load(c.FLi);
   Op g[BT_MAXT0];
 #pragma unroll
@@ -414,7 +439,7 @@ __device__ void bcr_final_fwd(const BcrSolveArgs& A, int lvl, VecLds& V) {
   const double w = op_mv(li, V.v0);
   vec_put(V.v1, w);
   wave_order();
-  if (lane < 16) A.w[lane] = w;
+  if (lane < 16) P.T->w[lane] = w;
 #pragma unroll
   for (int q = 0; q < BT_MAXT0; ++q)
     if (q < c.t0) {
@@ -424,17 +449,27 @@ __device__ void bcr_final_fwd(const BcrSolveArgs& A, int lvl, VecLds& V) {
   wave_order();
 }
 
-// u_o from w_o, the neighbours' u (L, R < 0: no such neighbour) and u0
-__device__ void bcr_bwd_pair(const BcrSolveArgs& A, long long o, long long L, long long R,
-                             const double* u0, VecLds& V) {
+// u_o of odd position k of level lvl (n positions) from w_o, the neighbours'
+// u and u0; k = 0, n = 1: the final pair
+__device__ void bcr_bwd_pair(const BcrSolveArgs& A, int lvl, int n, int k, const double* u0,
+                             VecLds& V, const VecPlace& P) {
   const BcrArgs& c = A.c;
-  const int lane = threadIdx.x & 63;
-  const double wv = A.w[o * 16 + (lane & 15)];
-  const double ul = L >= 0 ? A.up[L * 16 + (lane & 15)] : 0.0;
-  const double ur = R >= 0 ? A.up[R * 16 + (lane & 15)] : 0.0;
+  const int lane = threadIdx.x & 63, i16 = lane & 15;
+  const long long s = 1LL << lvl, o = k * s, L = (k - 1) * s, R = (k + 1) * s;
+  const bool hl = k >= 1, hr = k + 1 < n;
+  double wv, ul = 0.0, ur = 0.0;
+  if (P.T) {
+    wv = P.T->w[(k << P.shift) * 16 + i16];
+    if (hl) ul = P.T->u[((k - 1) << P.shift) * 16 + i16];
+    if (hr) ur = P.T->u[((k + 1) << P.shift) * 16 + i16];
+  } else {
+    wv = A.w[o * 16 + i16];
+    if (hl) ul = A.up[L * 16 + i16];
+    if (hr) ur = A.up[R * 16 + i16];
+  }
   Op xl{}, xr{}, g[BT_MAXT0];
-  if (L >= 0) xl = op_load(c.FXL + o * 256);
-  if (R >= 0) xr = op_load(c.FXR + o * 256);
+  if (hl) xl = op_load(c.FXL + o * 256);
+  if (hr) xr = op_load(c.FXR + o * 256);
 #pragma unroll
   for (int q = 0; q < BT_MAXT0; ++q)
     if (q < c.t0) g[q] = op_load(c.FGt + (o * c.t0 + q) * 256);
@@ -443,15 +478,18 @@ __device__ void bcr_bwd_pair(const BcrSolveArgs& A, long long o, long long L, lo
   vec_put(V.ub, ur);
   wave_order();
   double v = wv;
-  if (L >= 0) v -= op_mv(xl, V.ua);
-  if (R >= 0) v -= op_mv(xr, V.ub);
+  if (hl) v -= op_mv(xl, V.ua);
+  if (hr) v -= op_mv(xr, V.ub);
 #pragma unroll
   for (int q = 0; q < BT_MAXT0; ++q)
     if (q < c.t0) v -= op_mtv(g[q], u0 + 16 * q, V.sc);
   vec_put(V.v1, v);
   wave_order();
   const double u = op_mtv(li, V.v1, V.sc);
-  if (lane < 16) A.up[o * 16 + lane] = u;
+  if (lane < 16) {
+    A.up[o * 16 + lane] = u;
+    if (P.T) P.T->u[(k << P.shift) * 16 + lane] = u;
+  }
   if (lane < c.l[o]) A.u[A.loff[o] + lane] = u;
   wave_order();
 }
@@ -460,7 +498,7 @@ __global__ __launch_bounds__(256) void k_bcr_fwd(BcrSolveArgs A, int lvl, int n)
   __shared__ VecLds V[4];
   const int wave = threadIdx.x >> 6, w = blockIdx.x * 4 + wave;
   if (w >= (n + 1) / 2) return;
-  bcr_fwd_even(A, lvl, n, 2 * w, V[wave]);
+  bcr_fwd_even(A, lvl, n, 2 * w, V[wave], VecPlace{nullptr, 0, false});
 }
 
 __global__ __launch_bounds__(256) void k_bcr_bwd(BcrSolveArgs A, int lvl, int n) {
@@ -470,43 +508,64 @@ __global__ __launch_bounds__(256) void k_bcr_bwd(BcrSolveArgs A, int lvl, int n)
   for (int i = threadIdx.x; i < 16 * A.c.t0; i += blockDim.x) u0[i] = A.u0p[i];
   __syncthreads();
   if (w >= n / 2) return;
-  const int k = 2 * w + 1;
-  const long long s = 1LL << lvl;
-  bcr_bwd_pair(A, k * s, (k - 1) * s, k + 1 < n ? (k + 1) * s : -1, u0, V[wave]);
+  bcr_bwd_pair(A, lvl, n, 2 * w + 1, u0, V[wave], VecPlace{nullptr, 0, false});
+}
+
+// lower triangle of the border factor's Lb^-1 tiles into LDS, packed (tile
+// (r, c) at r (r + 1) / 2 + c), by the threads first .. first + count - 1
+__device__ void stage_lbi(const BcrArgs& c, double* lbi, int first, int count) {
+  const int t0 = c.t0;
+  for (int idx = threadIdx.x - first; idx < t0 * (t0 + 1) / 2 * 256; idx += count) {
+    const int tile = idx >> 8, e = idx & 255;
+    int r = 0;
+    while ((r + 1) * (r + 2) / 2 <= tile) ++r;
+    const int cc = tile - r * (r + 1) / 2;
+    lbi[idx] = c.FLbi[(cc * t0 + r) * 256 + e];
+  }
 }
 
 // Narrow forward levels from lvl (n active pairs), the final pair, the border
 // right-hand side s0 - sum_j Z_j'w_j (fixed order), the border solve
 // w0 = Lb^-1 s0, u0 = -Lb^-T w0, the final pair backward and the narrow
-// backward levels.  One workgroup of TAIL_WAVES_S waves.
+// backward levels.  One workgroup of TAIL_WAVES_S waves; the levels are
+// separated by LDS-only barriers, since the pair vectors stay in LDS.  The
+// Lb^-1 tiles are staged in LDS by the waves left idle at the second level.
 __global__ __launch_bounds__(64 * TAIL_WAVES_S) void k_bcr_tail_solve(BcrSolveArgs A, int lvl, int n) {
   const BcrArgs& c = A.c;
   __shared__ VecLds V[TAIL_WAVES_S];
+  __shared__ TailVecs T;
+  __shared__ double lbi[BT_MAXT0 * (BT_MAXT0 + 1) / 2 * 256];
   __shared__ double part[64 * TAIL_WAVES_S];
   __shared__ double s0[16 * BT_MAXT0], w0[16 * BT_MAXT0], u0[16 * BT_MAXT0];
   __shared__ int lv_n[32];
   const int wave = threadIdx.x >> 6;
-  const int lvl0 = lvl;
+  const int lt = lvl;
   int nlev = 0;
+  bool staged = false;
   for (; n > 1; ++lvl, n = (n + 1) / 2) {
+    const int ne = (n + 1) / 2;
     if (threadIdx.x == 0) lv_n[nlev] = n;
-    ++nlev;
-    for (int w = wave; w < (n + 1) / 2; w += TAIL_WAVES_S) bcr_fwd_even(A, lvl, n, 2 * w, V[wave]);
-    __syncthreads();
-  }
-  if (n == 1 && wave == 0) bcr_final_fwd(A, lvl, V[0]);
-  __syncthreads();
-  bcr_border_solve(A, part, s0, w0, u0, V[0].sc);
-  if (c.P >= 1 && wave == 0) bcr_bwd_pair(A, 0, -1, -1, u0, V[0]);
-  __syncthreads();
-  for (int li = nlev - 1; li >= 0; --li) {
-    const int nn = lv_n[li], lv = lvl0 + li;
-    const long long s = 1LL << lv;
-    for (int w = wave; w < nn / 2; w += TAIL_WAVES_S) {
-      const int k = 2 * w + 1;
-      bcr_bwd_pair(A, k * s, (k - 1) * s, k + 1 < nn ? (k + 1) * s : -1, u0, V[wave]);
+    if (nlev == 1 && ne < TAIL_WAVES_S) {
+      if (wave >= ne) stage_lbi(c, lbi, 64 * ne, 64 * (TAIL_WAVES_S - ne));
+      staged = true;
     }
-    __syncthreads();
+    const VecPlace P{&T, lvl - lt, lvl > lt};
+    for (int w = wave; w < ne; w += TAIL_WAVES_S) bcr_fwd_even(A, lvl, n, 2 * w, V[wave], P);
+    ++nlev;
+    lds_barrier();
+  }
+  if (!staged) stage_lbi(c, lbi, 0, blockDim.x);
+  if (n == 1 && wave == 0) bcr_final_fwd(A, lvl, V[0], VecPlace{&T, lvl - lt, lvl > lt});
+  // full barrier: the border sum reads the partials stored to global memory
+  __syncthreads();
+  bcr_border_solve(A, lbi, true, part, s0, w0, u0, V[0].sc);
+  if (c.P >= 1 && wave == 0) bcr_bwd_pair(A, lvl, 1, 0, u0, V[0], VecPlace{&T, lvl - lt, true});
+  lds_barrier();
+  for (int li = nlev - 1; li >= 0; --li) {
+    const int nn = lv_n[li], lv = lt + li;
+    const VecPlace P{&T, li, true};
+    for (int w = wave; w < nn / 2; w += TAIL_WAVES_S) bcr_bwd_pair(A, lv, nn, 2 * w + 1, u0, V[wave], P);
+    lds_barrier();
   }
 }
 

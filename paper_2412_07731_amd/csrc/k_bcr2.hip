@@ -452,7 +452,7 @@ __global__ __launch_bounds__(64 * MID_WAVES) void k_bcr2_mid(BcrSolveArgs A, int
     border_partial(A, 0, V.wl);
   }
   __syncthreads();
-  bcr_border_solve(A, part, s0, w0, u0, V.sc);
+  bcr_border_solve(A, A.c.FLbi, false, part, s0, w0, u0, V.sc);
   if (c.P >= 1 && wave == 0) bwd2_pair(A, 0, -1, -1, u0, V);
 }
 
