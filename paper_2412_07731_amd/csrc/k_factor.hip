@@ -94,9 +94,12 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   const bool diag = (it.y == it.z);
   __shared__ __align__(16) T sA[2][8][TE];
   __shared__ double sD[2][TS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
   const bool active = !(diag && wr < wc);
+  // a wave on the diagonal of a diagonal item skips its upper tile (0, 1)
+  const bool upper = !(diag && wr == wc);
 
   typedef typename Acc<T>::type AT;
   AT acc[2][2];
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
         T dd = (T)sD[buf][4 * s + (lane >> 4)];
         T b0 = cb0[64 * s + lane] * dd, b1 = cb1[64 * s + lane] * dd;
         acc[0][0] = mfma(a0, b0, acc[0][0]);
-        acc[0][1] = mfma(a0, b1, acc[0][1]);
+        if (upper) acc[0][1] = mfma(a0, b1, acc[0][1]);
         acc[1][0] = mfma(a1, b0, acc[1][0]);
         acc[1][1] = mfma(a1, b1, acc[1][1]);
       }
