@@ -781,24 +781,53 @@ __device__ double block_reduce(int op, double v) {
   return r;
 }
 
+// One thread's share of a reduction: elements lo + threadIdx.x + k RED_THREADS
+// below hi, combined in that order; the loads of four of them are issued
+// before they are combined.
+template <int OP, typename R>
+__device__ __forceinline__ double red_term(const R& r, long long i, double s1, double s2) {
+  switch (OP) {
+    case 0: return r.a[i] * r.b[i];
+    case 1: return fabs(r.a[i]);
+    case 2: return (r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY;
+    case 3: return (r.a[i] + s1 * r.b[i]) * (r.c[i] + s2 * r.d[i]);
+    case 4: return r.a[i] + r.b[i];
+    default: return r.a[i];
+  }
+}
+template <int OP, typename R>
+__device__ __forceinline__ double red_chunk_op(const R& r, long long lo, long long hi, double s1,
+                                               double s2) {
+  double v = red_identity(OP);
+  long long i = lo + threadIdx.x;
+  for (; i + 3 * RED_THREADS < hi; i += 4 * RED_THREADS) {
+    double t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = red_term<OP>(r, i + u * RED_THREADS, s1, s2);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v = red_combine(OP, v, t[u]);
+  }
+  for (; i < hi; i += RED_THREADS) v = red_combine(OP, v, red_term<OP>(r, i, s1, s2));
+  return v;
+}
+template <typename R>
+__device__ double red_chunk(const R& r, long long lo, long long hi, double s1, double s2) {
+  switch (r.op) {
+    case 0: return red_chunk_op<0>(r, lo, hi, s1, s2);
+    case 1: return red_chunk_op<1>(r, lo, hi, s1, s2);
+    case 2: return red_chunk_op<2>(r, lo, hi, s1, s2);
+    case 3: return red_chunk_op<3>(r, lo, hi, s1, s2);
+    case 4: return red_chunk_op<4>(r, lo, hi, s1, s2);
+    default: return red_chunk_op<5>(r, lo, hi, s1, s2);
+  }
+}
+
 __global__ __launch_bounds__(RED_THREADS) void k_reduce1(RedArgs r) {
   const long long chunk = (r.n + gridDim.x - 1) / gridDim.x;
   const long long lo = blockIdx.x * chunk;
   const long long hi = lo + chunk < r.n ? lo + chunk : r.n;
   const double s1 = r.s1, s2 = r.s2;
-  double v = red_identity(r.op);
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double t;
-    switch (r.op) {
-      case 0: t = r.a[i] * r.b[i]; break;
-      case 1: t = fabs(r.a[i]); break;
-      case 2: t = (r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY; break;
-      case 3: t = (r.a[i] + s1 * r.b[i]) * (r.c[i] + s2 * r.d[i]); break;
-      case 4: t = r.a[i] + r.b[i]; break;
-      default: t = r.a[i]; break;
-    }
-    v = red_combine(r.op, v, t);
-  }
+  double v = red_chunk(r, lo, hi, s1, s2);
   v = block_reduce(r.op, v);
   if (threadIdx.x == 0) r.partial[blockIdx.x] = v;
 }
@@ -821,19 +850,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_mreduce1(MultiRed m) {
   const long long hi = lo + chunk < r.n ? lo + chunk : r.n;
   const double s1 = r.ps1 ? fmin(1.0, *r.ps1) : r.s1;
   const double s2 = r.ps2 ? fmin(1.0, *r.ps2) : r.s2;
-  double v = red_identity(r.op);
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    double t;
-    switch (r.op) {
-      case 0: t = r.a[i] * r.b[i]; break;
-      case 1: t = fabs(r.a[i]); break;
-      case 2: t = (r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY; break;
-      case 3: t = (r.a[i] + s1 * r.b[i]) * (r.c[i] + s2 * r.d[i]); break;
-      case 4: t = r.a[i] + r.b[i]; break;
-      default: t = r.a[i]; break;
-    }
-    v = red_combine(r.op, v, t);
-  }
+  double v = red_chunk(r, lo, hi, s1, s2);
   v = block_reduce(r.op, v);
   if (threadIdx.x == 0) m.partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = v;
 }
