@@ -1528,10 +1528,9 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   // the step with the ratio-test results on the device, then the next
   // iteration's residuals
   auto step_resid = [&]() -> ahlp_status_t {
-    launch_step(st, n, o->eta, p->scal + S_AP, p->dx, x);
-    launch_step(st, m, o->eta, p->scal + S_AD, p->dy, y);
-    launch_step(st, n, o->eta, p->scal + S_AD, p->dz, z);
-    launch_step(st, n, o->eta, p->scal + S_AD, p->g, p->aty);
+    launch_steps(st, o->eta, StepSet{4, {n, m, n, n},
+                                     {p->scal + S_AP, p->scal + S_AD, p->scal + S_AD, p->scal + S_AD},
+                                     {p->dx, p->dy, p->dz, p->g}, {x, y, z, p->aty}});
     return resid_stage(false);
   };
   CHK(resid_stage(true));
@@ -1704,9 +1703,9 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     if (gz_used) launch_copy(st, n, p->gdir, p->g);
     ++k;
     if (ap < 1e-12 && ad < 1e-12) {
-      launch_step(st, n, o->eta, p->scal + S_AP, p->dx, x);
-      launch_step(st, m, o->eta, p->scal + S_AD, p->dy, y);
-      launch_step(st, n, o->eta, p->scal + S_AD, p->dz, z);
+      launch_steps(st, o->eta, StepSet{3, {n, m, n, 0},
+                                       {p->scal + S_AP, p->scal + S_AD, p->scal + S_AD, nullptr},
+                                       {p->dx, p->dy, p->dz, nullptr}, {x, y, z, nullptr}});
       status = AHLP_WSTALL;
       break;
     }

@@ -703,9 +703,12 @@ __global__ void k_gondzio_rhs(long long n, const double* __restrict__ x,
 }
 
 // Step x += min(1, eta * ratio) d with the ratio-test result on the device.
-__global__ void k_step(long long n, double eta, const double* __restrict__ ratio,
-                       const double* __restrict__ d, double* __restrict__ x) {
-  const double a = fmin(1.0, eta * *ratio);
+__global__ void k_steps(StepSet s, double eta) {
+  const int v = blockIdx.y;
+  const long long n = s.n[v];
+  const double a = fmin(1.0, eta * *s.ratio[v]);
+  const double* __restrict__ d = s.d[v];
+  double* __restrict__ x = s.x[v];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     x[i] += a * d[i];
@@ -902,9 +905,11 @@ void launch_gondzio_rhs(hipStream_t st, long long n, const double* x, const doub
     hipLaunchKernelGGL(k_gondzio_rhs, dim3(grid1d(n)), dim3(256), 0, st, n, x, z, dx, dz, at_p,
                        at_d, smu, beta_min, beta_max, r);
 }
-void launch_step(hipStream_t st, long long n, double eta, const double* ratio, const double* d,
-                 double* x) {
-  if (n > 0) hipLaunchKernelGGL(k_step, dim3(grid1d(n)), dim3(256), 0, st, n, eta, ratio, d, x);
+void launch_steps(hipStream_t st, double eta, const StepSet& s) {
+  long long nmax = 0;
+  for (int v = 0; v < s.cnt; ++v) nmax = s.n[v] > nmax ? s.n[v] : nmax;
+  if (s.cnt > 0 && nmax > 0)
+    hipLaunchKernelGGL(k_steps, dim3(grid1d(nmax), s.cnt), dim3(256), 0, st, s, eta);
 }
 void launch_pad_y(hipStream_t st, const BlockInfo* blk, int N, const double* y, double* yp) {
   hipLaunchKernelGGL(k_pad_y, dim3(N), dim3(256), 0, st, blk, y, yp);

@@ -155,9 +155,15 @@ void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_
 void launch_gondzio_rhs(hipStream_t st, long long n, const double* x, const double* z,
                         const double* dx, const double* dz, double at_p, double at_d,
                         const double* smu, double beta_min, double beta_max, double* r);
-// x += min(1, eta * ratio[0]) d
-void launch_step(hipStream_t st, long long n, double eta, const double* ratio, const double* d,
-                 double* x);
+// up to four step updates in one launch: x[v] += min(1, eta ratio[v][0]) d[v]
+struct StepSet {
+  int cnt;
+  long long n[4];
+  const double* ratio[4];
+  const double* d[4];
+  double* x[4];
+};
+void launch_steps(hipStream_t st, double eta, const StepSet& s);
 void launch_rows_multi(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
                        const double* A, const double* C, long long d0off, const RowsArgs& ra);
 void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
