@@ -97,9 +97,18 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  const bool active = !(diag && wr < wc);
-  // a wave on the diagonal of a diagonal item skips its upper tile (0, 1)
-  const bool upper = !(diag && wr == wc);
+  // output tiles a wave computes: those stored, i.e. inside the block and on
+  // or below the diagonal (a wave on the diagonal of a diagonal item skips
+  // its upper tile (0, 1); waves past a ragged block's last tile row or
+  // column skip theirs)
+  const int I0 = R0 + 2 * wr, J0 = C0 + 2 * wc;
+  bool use[2][2];
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc)
+      use[tr][tc] = I0 + tr < b.mt && J0 + tc < b.mt && I0 + tr >= J0 + tc;
+  const bool active = use[0][0] || use[0][1] || use[1][0] || use[1][1];
 
   typedef typename Acc<T>::type AT;
   AT acc[2][2];
@@ -152,10 +161,10 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
         T a0 = ra0[64 * s + lane], a1 = ra1[64 * s + lane];
         T dd = (T)sD[buf][4 * s + (lane >> 4)];
         T b0 = cb0[64 * s + lane] * dd, b1 = cb1[64 * s + lane] * dd;
-        acc[0][0] = mfma(a0, b0, acc[0][0]);
-        if (upper) acc[0][1] = mfma(a0, b1, acc[0][1]);
-        acc[1][0] = mfma(a1, b0, acc[1][0]);
-        acc[1][1] = mfma(a1, b1, acc[1][1]);
+        if (use[0][0]) acc[0][0] = mfma(a0, b0, acc[0][0]);
+        if (use[0][1]) acc[0][1] = mfma(a0, b1, acc[0][1]);
+        if (use[1][0]) acc[1][0] = mfma(a1, b0, acc[1][0]);
+        if (use[1][1]) acc[1][1] = mfma(a1, b1, acc[1][1]);
       }
     }
   };
@@ -171,8 +180,8 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   for (int tr = 0; tr < 2; ++tr) {
 #pragma unroll
     for (int tc = 0; tc < 2; ++tc) {
-      const int I = R0 + 2 * wr + tr, J = C0 + 2 * wc + tc;
-      if (I >= b.mt || J >= b.mt || I < J) continue;
+      const int I = I0 + tr, J = J0 + tc;
+      if (!use[tr][tc]) continue;
       T* dst = LB + lb_tile(b, I, J);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
