@@ -7,10 +7,11 @@
 // huge value (the pivot rule) and counted.
 //
 // Layout: lane l holds row i = l%16 and columns 4g..4g+3 (g = l/16) of both
-// halves; row j and the multipliers of step j are exchanged through a small
-// LDS buffer (48 values), so a step costs one division, a few LDS accesses and
-// eight FMAs.  The caller's workgroup must be exactly this wave or the other
-// waves must not touch xbuf.
+// halves.  At step j the 16-lane row g already holds columns 4g..4g+3 of every
+// tile row, so row j reaches its lanes by a DPP row broadcast (row_newbcast:j)
+// and the multiplier a_ij / d_j of row i comes from lane (i, j/4) by one lane
+// permute: a step costs one division, one permute, sixteen DPP moves and
+// eight FMAs, with no LDS round trip.
 #pragma once
 
 #include "common.h"
@@ -48,11 +49,65 @@ __device__ __forceinline__ float lane_bcast<float>(float v, int src) {
   return u.f;
 }
 
+// value of lane J of each 16-lane row, in every lane of that row
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+  union { double d; int i[2]; } u, o;
+  u.d = v;
+  o.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], 0x150 + J, 0xF, 0xF, false);
+  o.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], 0x150 + J, 0xF, 0xF, false);
+  return o.d;
+}
+template <int J>
+__device__ __forceinline__ float row_bcast(float v) {
+  union { float f; int i; } u, o;
+  u.f = v;
+  o.i = __builtin_amdgcn_update_dpp(0, u.i, 0x150 + J, 0xF, 0xF, false);
+  return o.f;
+}
+
+// Elimination step J on the lane's row i, column group g.
+template <typename T, int J>
+__device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double thr, int& cnt,
+                                          T& mypiv) {
+  T p = lane_bcast<T>(a[J & 3], J + 16 * (J >> 2));
+  if (!((double)p > thr)) {
+    p = (T)PIVOT_BIG;
+    ++cnt;
+  }
+  const T rp = T(1) / p;
+  if (i == J) mypiv = p;
+  // a_iJ from lane (i, J/4); row J from lane J of this lane's 16-lane row
+  const T aij = __shfl(a[J & 3], i + 16 * (J >> 2));
+  T rj[4], rje[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    rj[r] = row_bcast<J>(a[r]);
+    rje[r] = row_bcast<J>(e[r]);
+  }
+  const T m = (i > J) ? aij * rp : T(0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    a[r] -= m * rj[r];
+    e[r] -= m * rje[r];
+  }
+}
+template <typename T, int J>
+__device__ __forceinline__ void chol_steps(T (&a)[4], T (&e)[4], int i, double thr, int& cnt,
+                                           T& mypiv) {
+  if constexpr (J < 16) {
+    chol_step<T, J>(a, e, i, thr, cnt, mypiv);
+    chol_steps<T, J + 1>(a, e, i, thr, cnt, mypiv);
+  }
+}
+
 // P: input tile (column-major, LDS or global).  L (may alias P) receives the
-// lower factor (upper part zero), Li its inverse; both column-major.  xbuf: 48
-// values of LDS scratch.  Returns the number of replaced pivots (all lanes).
+// lower factor (upper part zero), Li its inverse; both column-major.  xbuf is
+// no longer used (kept in the signature for the callers' LDS layouts).
+// Returns the number of replaced pivots (all lanes).
 template <typename T>
 __device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double thr, T* xbuf) {
+  (void)xbuf;
   const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
   T a[4], e[4];
 #pragma unroll
@@ -62,39 +117,9 @@ __device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double th
   }
   int cnt = 0;
   T mypiv = T(1);
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    T p = lane_bcast<T>(a[j & 3], j + 16 * (j >> 2));
-    if (!((double)p > thr)) {
-      p = (T)PIVOT_BIG;
-      ++cnt;
-    }
-    const T rp = T(1) / p;
-    if (i == j) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        xbuf[4 * g + r] = a[r];
-        xbuf[16 + 4 * g + r] = e[r];
-      }
-      mypiv = p;
-    }
-    if (g == (j >> 2)) xbuf[32 + i] = a[j & 3] * rp;
-    wave_order();
-    const T m = (i > j) ? xbuf[32 + i] : T(0);
-    T rj[4], rje[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      rj[r] = xbuf[4 * g + r];
-      rje[r] = xbuf[16 + 4 * g + r];
-    }
-    wave_order();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      a[r] -= m * rj[r];
-      e[r] -= m * rje[r];
-    }
-  }
+  chol_steps<T, 0>(a, e, i, thr, cnt, mypiv);
   const T s = T(1) / (T)sqrt((double)mypiv);
+  wave_order();   // every lane has read P before L (which may alias it) is written
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int c = 4 * g + r;
