@@ -141,4 +141,49 @@ struct DevInfo {
   int nonfinite;    // x or z not finite / not positive at factor
 };
 
+// Cross-lane sums on the VALU (DPP moves within a 16-lane row, permlane
+// swaps across rows) instead of LDS-pipe permutes.  Each gives every lane the
+// additions of the xor butterfly x += shfl_xor(x, s) over its strides, in the
+// same order, so the results are bitwise the same.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  union { double d; int i[2]; } u, o;
+  u.d = v;
+  o.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], CTRL, 0xF, 0xF, false);
+  o.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], CTRL, 0xF, 0xF, false);
+  return o.d;
+}
+// strides 1, 2, 4, 8: the sum over the lane's 16-lane row.  After the two
+// quad steps every lane of a quad holds the same value, so the half-row and
+// row mirrors read the same values as the xor-4 and xor-8 partners.
+__device__ __forceinline__ double row_sum16(double x) {
+  x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]: lane ^ 1
+  x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]: lane ^ 2
+  x += dpp_mov<0x141>(x);   // row_half_mirror: the other quad of the half row
+  x += dpp_mov<0x140>(x);   // row_mirror: the other half row
+  return x;
+}
+// x_l + x_(l ^ S) for S = 16 or 32: the swap leaves the two values of each
+// lane pair in its two outputs, whose sum is the same in both lanes
+template <int S>
+__device__ __forceinline__ double pair_sum(double x) {
+  union { double d; unsigned i[2]; } u, a, b;
+  u.d = x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if constexpr (S == 16) {
+      const auto r = __builtin_amdgcn_permlane16_swap(u.i[h], u.i[h], false, false);
+      a.i[h] = r[0];
+      b.i[h] = r[1];
+    } else {
+      const auto r = __builtin_amdgcn_permlane32_swap(u.i[h], u.i[h], false, false);
+      a.i[h] = r[0];
+      b.i[h] = r[1];
+    }
+  }
+  return a.d + b.d;
+}
+// strides 16, 32: the sum over lanes l, l ^ 16, l ^ 32, l ^ 48
+__device__ __forceinline__ double col_sum4(double x) { return pair_sum<32>(pair_sum<16>(x)); }
+
 }  // namespace ahlp

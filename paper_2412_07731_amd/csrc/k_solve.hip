@@ -334,8 +334,7 @@ __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) s += (double)c.li[k] * t[TS * p + 4 * k + (lane >> 4)];
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
+      s = col_sum4(s);
       // all lanes have read t[p-block]; lanes 0..15 now overwrite it
       if (lane < 16) t[TS * p + lane] = s;
     }
@@ -347,8 +346,7 @@ __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += (double)c.t[q][k] * t[TS * p + 4 * k + (lane >> 4)];
-        s += __shfl_xor(s, 16);
-        s += __shfl_xor(s, 32);
+        s = col_sum4(s);
         if (lane < 16) t[TS * r + lane] -= s;
       }
     }
@@ -357,8 +355,7 @@ __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) s += (double)L[64 * k + lane] * t[TS * p + 4 * k + (lane >> 4)];
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
+      s = col_sum4(s);
       if (lane < 16) t[TS * r + lane] -= s;
     }
   };
@@ -428,11 +425,7 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      double x = acc[s];
-      x += __shfl_xor(x, 1);
-      x += __shfl_xor(x, 2);
-      x += __shfl_xor(x, 4);
-      x += __shfl_xor(x, 8);
+      const double x = row_sum16(acc[s]);
       if ((lane & 15) == 0) part[wave][4 * s + (lane >> 4)] = x;
     }
     __syncthreads();
@@ -444,13 +437,8 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
       double s4[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const double wi = __shfl(w, lane & 15);
-        double x = (double)c.li[s] * wi;
-        x += __shfl_xor(x, 1);
-        x += __shfl_xor(x, 2);
-        x += __shfl_xor(x, 4);
-        x += __shfl_xor(x, 8);
-        s4[s] = x;
+        // this lane's w is w[lane % 16], the row index i it needs
+        s4[s] = row_sum16((double)c.li[s] * w);
       }
       if ((lane & 15) == 0) {
 #pragma unroll

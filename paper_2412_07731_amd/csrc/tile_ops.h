@@ -96,9 +96,7 @@ __device__ __forceinline__ double op_mv(const Op& X, const double* v) {
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) s += X.v[k] * v[4 * k + (lane >> 4)];
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  return s;
+  return col_sum4(s);
 }
 // y = X' v (v: 16 values in LDS, sc: 16 values of LDS scratch); every lane
 // returns y[lane % 16]
@@ -108,12 +106,7 @@ __device__ __forceinline__ double op_mtv(const Op& X, const double* v, double* s
   double out[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    double x = X.v[s] * vi;
-    x += __shfl_xor(x, 1);
-    x += __shfl_xor(x, 2);
-    x += __shfl_xor(x, 4);
-    x += __shfl_xor(x, 8);
-    out[s] = x;
+    out[s] = row_sum16(X.v[s] * vi);
   }
   wave_order();
   if ((lane & 15) == 0) {
