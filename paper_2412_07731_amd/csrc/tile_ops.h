@@ -98,25 +98,20 @@ __device__ __forceinline__ double op_mv(const Op& X, const double* v) {
   for (int k = 0; k < 4; ++k) s += X.v[k] * v[4 * k + (lane >> 4)];
   return col_sum4(s);
 }
-// y = X' v (v: 16 values in LDS, sc: 16 values of LDS scratch); every lane
-// returns y[lane % 16]
+// y = X' v (v: 16 values in LDS); every lane returns y[lane % 16].  Row g of
+// the wave sums column 4 s + g of X into out[s]; lane (i, any row) takes y[i]
+// from row i % 4, whose lanes i & 12 .. (i & 12) + 3 hold out[i / 4] in the
+// register the lane selects.  sc is not used (kept for the callers' layouts).
 __device__ __forceinline__ double op_mtv(const Op& X, const double* v, double* sc) {
-  const int lane = threadIdx.x & 63;
-  const double vi = v[lane & 15];
+  (void)sc;
+  const int lane = threadIdx.x & 63, i = lane & 15;
+  const double vi = v[i];
   double out[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    out[s] = row_sum16(X.v[s] * vi);
-  }
-  wave_order();
-  if ((lane & 15) == 0) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) sc[4 * s + (lane >> 4)] = out[s];
-  }
-  wave_order();
-  const double r = sc[lane & 15];
-  wave_order();
-  return r;
+  for (int s = 0; s < 4; ++s) out[s] = row_sum16(X.v[s] * vi);
+  const int q = i >> 2;
+  const double sel = q == 0 ? out[0] : q == 1 ? out[1] : q == 2 ? out[2] : out[3];
+  return __shfl(sel, ((i & 3) << 4) | (i & 12));
 }
 __device__ __forceinline__ void vec_put(double* dst, double y) {
   const int lane = threadIdx.x & 63;
