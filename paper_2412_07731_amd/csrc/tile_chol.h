@@ -66,6 +66,17 @@ __device__ __forceinline__ float row_bcast(float v) {
   return o.f;
 }
 
+// 1 / p.  FP64: the hardware reciprocal estimate refined by one
+// Newton-Raphson step (r <- r + r (1 - p r)), a few dependent instructions
+// against the longer correctly rounded division sequence on the step's
+// critical path (pivots are finite: a replaced one is 1e128).  FP32 keeps the
+// division, since a replaced pivot is infinite there and 1 / inf must be 0.
+__device__ __forceinline__ double recip(double p) {
+  const double r = __builtin_amdgcn_rcp(p);
+  return fma(r, fma(-p, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float p) { return 1.0f / p; }
+
 // Elimination step J on the lane's row i, column group g.
 template <typename T, int J>
 __device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double thr, int& cnt,
@@ -75,7 +86,7 @@ __device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double th
     p = (T)PIVOT_BIG;
     ++cnt;
   }
-  const T rp = T(1) / p;
+  const T rp = recip(p);
   if (i == J) mypiv = p;
   // a_iJ from lane (i, J/4); row J from lane J of this lane's 16-lane row
   const T aij = __shfl(a[J & 3], i + 16 * (J >> 2));
