@@ -66,13 +66,15 @@ __device__ __forceinline__ float row_bcast(float v) {
   return o.f;
 }
 
-// 1 / p.  FP64: the hardware reciprocal estimate refined by one
-// Newton-Raphson step (r <- r + r (1 - p r)), a few dependent instructions
-// against the longer correctly rounded division sequence on the step's
-// critical path (pivots are finite: a replaced one is 1e128).  FP32 keeps the
-// division, since a replaced pivot is infinite there and 1 / inf must be 0.
+// 1 / p.  FP64: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps (r <- r + r (1 - p r), each doubling the correct
+// bits), a few dependent instructions against the longer correctly rounded
+// division sequence on the step's critical path (pivots are finite: a
+// replaced one is 1e128).  FP32 keeps the division, since a replaced pivot is
+// infinite there and 1 / inf must be 0.
 __device__ __forceinline__ double recip(double p) {
-  const double r = __builtin_amdgcn_rcp(p);
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
   return fma(r, fma(-p, r, 1.0), r);
 }
 __device__ __forceinline__ float recip(float p) { return 1.0f / p; }
