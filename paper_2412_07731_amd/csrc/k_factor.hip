@@ -431,6 +431,15 @@ __device__ __forceinline__ void schur_rows(const BlockInfo& b, const T* __restri
 // to 24, where the sixth row's accumulators fill the 256 VGPRs); a launch takes
 // the smaller that fits its widest block.
 constexpr int BF_PW = 2, BF_RMAX_MAX = 6;
+// The panel kernel's LDS tiles are column-major with leading dimension 17:
+// the accumulator layout writes a tile by columns across the lanes, which
+// with 16 would put the 16 lanes of a row group in the same bank; with 17
+// they fall in distinct banks, and the operand-layout reads stay contiguous.
+// (The six-rows-per-wave form keeps leading dimension 16: its registers are
+// full, and the padded index arithmetic would spill.)
+template <int BF_RMAX> struct BfLd { static constexpr int LD = BF_RMAX <= 5 ? TS + 1 : TS; };
+template <int LD>
+__device__ __forceinline__ int pidx(int e) { return LD == TS ? e : e + (e >> 4); }   // col 16 + row -> col LD + row
 template <typename T>
 struct BfOp { T v[4]; };
 template <typename T>
@@ -441,6 +450,22 @@ __device__ __forceinline__ BfOp<T> bf_ld(const T* __restrict__ t) {
   for (int s = 0; s < 4; ++s) o.v[s] = t[64 * s + lane];
   return o;
 }
+// the same from an LDS tile of leading dimension LD
+template <typename T, int LD>
+__device__ __forceinline__ BfOp<T> bf_ld_p(const T* __restrict__ t) {
+  const int lane = threadIdx.x & 63;
+  BfOp<T> o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[pidx<LD>(64 * s + lane)];
+  return o;
+}
+// LDS tile of leading dimension LD to a plain tile in global memory
+template <typename T, int LD>
+__device__ __forceinline__ void tile_copy_p(T* __restrict__ dst, const T* __restrict__ src) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) dst[64 * s + lane] = src[pidx<LD>(64 * s + lane)];
+}
 
 template <typename T, int BF_RMAX>
 __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
@@ -450,13 +475,13 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
                                                                double* __restrict__ PQ,
                                                                DevInfo* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int LD = BfLd<BF_RMAX>::LD, TEP = TS * LD;
   const BlockInfo b = blk[order[blockIdx.x]];
   const int mt = b.mt, rt = b.rt;
   T* colbuf = reinterpret_cast<T*>(smem_raw);          // rt tiles: the panel column just factored
-  T* li = colbuf + (size_t)rt * TE;                     // L_cc^-1
-  T* dt = li + TE;                                      // diagonal tile / its factor
-  T* scr = dt + TE;                                     // 4 tiles: per-wave conversion
-  T* xbuf = scr + 4 * TE;                               // 48 values: tile Cholesky
+  T* li = colbuf + (size_t)rt * TEP;                    // L_cc^-1
+  T* dt = li + TEP;                                     // diagonal tile / its factor
+  T* scr = dt + TEP;                                    // 4 tiles: per-wave conversion
   __shared__ double s_max[4];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row and address arithmetic stays scalar
@@ -472,7 +497,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
   __syncthreads();
   const double thr = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
   int cnt = 0;
-  T* myscr = scr + w * TE;
+  T* myscr = scr + w * TEP;
 
   for (int c0 = 0; c0 < mt; c0 += BF_PW) {
     const int pw = min(BF_PW, mt - c0);
@@ -524,34 +549,34 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
         for (int t = 0; t < BF_RMAX; ++t)
           if (t == ot) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) dt[acc_index<T>(lane, k)] = acc[t][j][k];
+            for (int k = 0; k < 4; ++k) dt[pidx<LD>(acc_index<T>(lane, k))] = acc[t][j][k];
           }
         wave_order();
-        cnt += wave_chol_tile<T>(dt, dt, li, thr, xbuf);
-        tile_copy_t(LB + lb_tile(b, c, c), dt);
-        tile_copy_t(LINV + b.linvoff + (long long)c * TE, li);
+        cnt += wave_chol_tile<T, LD>(dt, dt, li, thr, nullptr);
+        tile_copy_p<T, LD>(LB + lb_tile(b, c, c), dt);
+        tile_copy_p<T, LD>(LINV + b.linvoff + (long long)c * TE, li);
       }
       __syncthreads();
       // rows below: L(r, c) = acc(r, c) L_cc^-T
-      const BfOp<T> lio = bf_ld<T>(li);
+      const BfOp<T> lio = bf_ld_p<T, LD>(li);
 #pragma unroll
       for (int t = 0; t < BF_RMAX; ++t) {
         const int r = c0 + w + 4 * t;
         if (r < rt && r > c) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) myscr[acc_index<T>(lane, k)] = acc[t][j][k];
+          for (int k = 0; k < 4; ++k) myscr[pidx<LD>(acc_index<T>(lane, k))] = acc[t][j][k];
           wave_order();
-          const BfOp<T> x = bf_ld<T>(myscr);
+          const BfOp<T> x = bf_ld_p<T, LD>(myscr);
           AT l = AT{0, 0, 0, 0};
 #pragma unroll
           for (int s = 0; s < 4; ++s) l = mfma(x.v[s], lio.v[s], l);
           wave_order();
           T* dst = LB + lb_tile(b, r, c);
-          T* cb = colbuf + (size_t)(r - c0) * TE;
+          T* cb = colbuf + (size_t)(r - c0) * TEP;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             dst[acc_index<T>(lane, k)] = l[k];
-            cb[acc_index<T>(lane, k)] = l[k];
+            cb[pidx<LD>(acc_index<T>(lane, k))] = l[k];
           }
         }
       }
@@ -561,12 +586,12 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
       for (int j2 = 0; j2 < BF_PW; ++j2) {
         if (j2 <= j || j2 >= pw) continue;
         const int c2 = c0 + j2;
-        const BfOp<T> y = bf_ld<T>(colbuf + (size_t)(c2 - c0) * TE);
+        const BfOp<T> y = bf_ld_p<T, LD>(colbuf + (size_t)(c2 - c0) * TEP);
 #pragma unroll
         for (int t = 0; t < BF_RMAX; ++t) {
           const int r = c0 + w + 4 * t;
           if (r < rt && r >= c2) {
-            const BfOp<T> x = bf_ld<T>(colbuf + (size_t)(r - c0) * TE);
+            const BfOp<T> x = bf_ld_p<T, LD>(colbuf + (size_t)(r - c0) * TEP);
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[t][j2] = mfma(-x.v[s], y.v[s], acc[t][j2]);
           }
@@ -729,13 +754,17 @@ template <typename T>
 void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
                                int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info) {
   if (n == 0) return;
-  const size_t shmem = (size_t)(max_rt + 6) * TE * sizeof(T) + 48 * sizeof(T);
-  if (max_rt <= 20)
+  // LDS: the panel column (max_rt tiles), L_cc^-1, the diagonal tile and 4
+  // per-wave tiles, at the form's leading dimension
+  if (max_rt <= 20) {
+    const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<5>::LD * sizeof(T);
     hipLaunchKernelGGL((k_block_factor_panel<T, 5>), dim3(n), dim3(256), shmem, st, blk, order, LB,
                        LINV, PQ, info);
-  else
+  } else {
+    const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<6>::LD * sizeof(T);
     hipLaunchKernelGGL((k_block_factor_panel<T, 6>), dim3(n), dim3(256), shmem, st, blk, order, LB,
                        LINV, PQ, info);
+  }
 }
 // Column-at-a-time kernel (any height), then the Schur contributions.
 template <typename T>

@@ -114,18 +114,19 @@ __device__ __forceinline__ void chol_steps(T (&a)[4], T (&e)[4], int i, double t
   }
 }
 
-// P: input tile (column-major, LDS or global).  L (may alias P) receives the
-// lower factor (upper part zero), Li its inverse; both column-major.  xbuf is
-// no longer used (kept in the signature for the callers' LDS layouts).
-// Returns the number of replaced pivots (all lanes).
-template <typename T>
+// P: input tile (column-major with leading dimension LD, LDS or global).  L
+// (may alias P) receives the lower factor (upper part zero), Li its inverse;
+// both column-major with leading dimension LD.  xbuf is no longer used (kept
+// in the signature for the callers' LDS layouts).  Returns the number of
+// replaced pivots (all lanes).
+template <typename T, int LD = TS>
 __device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double thr, T* xbuf) {
   (void)xbuf;
   const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
   T a[4], e[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    a[r] = P[(4 * g + r) * TS + i];
+    a[r] = P[(4 * g + r) * LD + i];
     e[r] = (4 * g + r == i) ? T(1) : T(0);
   }
   int cnt = 0;
@@ -137,8 +138,8 @@ __device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double th
   for (int r = 0; r < 4; ++r) {
     const int c = 4 * g + r;
     // L' row i = U row i * s, i.e. L[c][i] (zero above the diagonal); Li row i = E row i * s
-    L[i * TS + c] = (c >= i) ? a[r] * s : T(0);
-    Li[c * TS + i] = e[r] * s;
+    L[i * LD + c] = (c >= i) ? a[r] * s : T(0);
+    Li[c * LD + i] = e[r] * s;
   }
   wave_order();
   return cnt;
