@@ -41,7 +41,11 @@ namespace {
 constexpr int BT_MAXT0 = 4;      // border tiles (n0 <= 64)
 constexpr int TAIL_WAVES = 8;    // waves of the single-workgroup factor tail
 constexpr int TAIL_WAVES_S = 16; // waves of the single-workgroup solve tail
-constexpr int ELIM_LDS = 256 + 256 + 48;   // doubles of LDS per eliminating wave
+// LDS tiles of the eliminating kernels are column-major with leading
+// dimension 17: accumulator-layout writes and B-operand reads walk a tile by
+// columns across the lanes, which with 16 would put 16 lanes in one bank
+constexpr int PLD = TS + 1, PTE = TS * PLD;
+constexpr int ELIM_LDS = 2 * PTE;   // doubles of LDS per eliminating wave: the tile, L^-1
 
 // ---------------------------------------------------------------- factor
 // Working tiles from the assembled parts (one wave per tile).
@@ -85,6 +89,33 @@ __device__ __forceinline__ T4 ld_b(const double* __restrict__ t) {
   return o;
 }
 __device__ __forceinline__ T4 t4_zero() { return T4{{0.0, 0.0, 0.0, 0.0}}; }
+// the same operations on padded LDS tiles (element col 16 + row at col 17 + row)
+__device__ __forceinline__ int pe(int e) { return e + (e >> 4); }
+__device__ __forceinline__ void acc_store_l(double* t, const d4& a) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[pe(acc_index<double>(lane, r))] = a[r];
+}
+__device__ __forceinline__ T4 ld_a_l(const double* t) {
+  const int lane = threadIdx.x & 63;
+  T4 o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[pe(64 * s + lane)];
+  return o;
+}
+__device__ __forceinline__ T4 ld_b_l(const double* t) {
+  const int lane = threadIdx.x & 63;
+  const int idx = (lane & 15) * TS + (lane >> 4);
+  T4 o;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o.v[s] = t[pe(idx + 4 * s)];
+  return o;
+}
+__device__ __forceinline__ void tile_copy_l(double* __restrict__ dst, const double* src) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) dst[64 * s + lane] = src[pe(64 * s + lane)];
+}
 // acc + alpha * (product with the given operands)
 __device__ __forceinline__ d4 mm(d4 acc, const T4& a, const T4& b, double alpha) {
 #pragma unroll
@@ -95,12 +126,11 @@ __device__ __forceinline__ d4 mm(d4 acc, const T4& a, const T4& b, double alpha)
 // Eliminate pair o (active neighbours L if needXL, R if hasR): factor its
 // working diagonal and form X_L = L_o^-1 T'[o,L], X_R = L_o^-1 T'[R,o]' and
 // G_q = (L_o^-1 E'_o)' (accumulator layout).  scr: ELIM_LDS doubles of this
-// wave; L_o^-1 is left in scr + 256.  Returns replaced pivots.
+// wave; L_o^-1 is left in scr + PTE (padded).  Returns replaced pivots.
 __device__ int elim_core(const BcrArgs& c, long long o, long long L, bool needXL, bool hasR,
                          double* scr, d4& XL, d4& XR, d4* G) {
   double* cur = scr;
-  double* Li = scr + 256;
-  double* xbuf = scr + 512;
+  double* Li = scr + PTE;
   const double* __restrict__ BC = c.BC;
   const double* __restrict__ BEt = c.BEt;
   const d4 D = acc_load(c.BD + o * 256);
@@ -110,10 +140,10 @@ __device__ int elim_core(const BcrArgs& c, long long o, long long L, bool needXL
   if (hasR) cr = ld_a(BC + o * 256);
 #pragma unroll
   for (int q = 0; q < BT_MAXT0; ++q) et[q] = q < c.t0 ? ld_a(BEt + (o * c.t0 + q) * 256) : t4_zero();
-  acc_store(cur, D);
+  acc_store_l(cur, D);
   wave_order();
-  const int cnt = wave_chol_tile<double>(cur, cur, Li, thr, xbuf);
-  const T4 li = ld_a(Li);
+  const int cnt = wave_chol_tile<double, PLD>(cur, cur, Li, thr, nullptr);
+  const T4 li = ld_a_l(Li);
   XL = needXL ? mm(acc_zero(), li, cl, 1.0) : acc_zero();
   XR = hasR ? mm(acc_zero(), li, cr, 1.0) : acc_zero();
 #pragma unroll
@@ -121,10 +151,10 @@ __device__ int elim_core(const BcrArgs& c, long long o, long long L, bool needXL
   return cnt;
 }
 
-// store the factor of pair o (L^-1 from LDS)
+// store the factor of pair o (L^-1 from its padded LDS tile)
 __device__ void store_factor(const BcrArgs& c, long long o, const double* Li, const d4& XL,
                              const d4& XR, bool hasR, const d4* G) {
-  tile_copy(c.FLi + o * 256, Li);
+  tile_copy_l(c.FLi + o * 256, Li);
   acc_store(c.FXL + o * 256, XL);
   if (hasR) acc_store(c.FXR + o * 256, XR);
 #pragma unroll
@@ -139,7 +169,7 @@ __device__ void store_factor(const BcrArgs& c, long long o, const double* Li, co
 // is split: wave 0 the diagonal and the new coupling, wave 1 the border rows.
 __global__ __launch_bounds__(128) void k_bcr_level(BcrArgs c, int lvl, int n) {
   __shared__ double scr[2][ELIM_LDS];
-  __shared__ double xr_[2][(2 + BT_MAXT0) * 256];   // per wave: X_L, X_R, G_q
+  __shared__ double xr_[2][(2 + BT_MAXT0) * PTE];   // per wave: X_L, X_R, G_q (padded)
   const int wave = threadIdx.x >> 6, k = 2 * blockIdx.x;
   const long long s = 1LL << lvl, e = k * s;
   const bool hl = k >= 1, hr = k + 1 < n, hrr = k + 2 < n;
@@ -162,35 +192,35 @@ __global__ __launch_bounds__(128) void k_bcr_level(BcrArgs c, int lvl, int n) {
     const bool needXL = wave == 0, hasR = wave == 0 ? hrr : true;
     cnt = elim_core(c, o, e, needXL, hasR, scr[wave], XL, XR, G);
     double* x = xr_[wave];
-    acc_store(x, XL);
-    acc_store(x + 256, XR);
+    acc_store_l(x, XL);
+    acc_store_l(x + PTE, XR);
 #pragma unroll
     for (int q = 0; q < BT_MAXT0; ++q)
-      if (q < c.t0) acc_store(x + (2 + q) * 256, G[q]);
-    if (wave == 0) store_factor(c, o, scr[0] + 256, XL, XR, hasR, G);
+      if (q < c.t0) acc_store_l(x + (2 + q) * PTE, G[q]);
+    if (wave == 0) store_factor(c, o, scr[0] + PTE, XL, XR, hasR, G);
   }
   __syncthreads();
   const double* xo = xr_[0];   // products of o_r
   const double* xl = xr_[1];   // products of o_l
   if (wave == 0) {
     d4 D = Dp;
-    const T4 a = hl ? ld_b(xl + 256) : t4_zero();   // X_R(o_l)
-    const T4 b = hr ? ld_b(xo) : t4_zero();         // X_L(o_r)
+    const T4 a = hl ? ld_b_l(xl + PTE) : t4_zero();   // X_R(o_l)
+    const T4 b = hr ? ld_b_l(xo) : t4_zero();         // X_L(o_r)
     if (hl) D = mm(D, a, a, -1.0);
     if (hr) D = mm(D, b, b, -1.0);
     acc_store(c.BD + e * 256, D);
-    if (hr && hrr) acc_store(c.BC + e * 256, mm(acc_zero(), ld_b(xo + 256), b, -1.0));
+    if (hr && hrr) acc_store(c.BC + e * 256, mm(acc_zero(), ld_b_l(xo + PTE), b, -1.0));
   } else {
     d4 et[BT_MAXT0];
 #pragma unroll
     for (int q = 0; q < BT_MAXT0; ++q) et[q] = etp[q];
-    const T4 a = hl ? ld_b(xl + 256) : t4_zero();
-    const T4 b = hr ? ld_b(xo) : t4_zero();
+    const T4 a = hl ? ld_b_l(xl + PTE) : t4_zero();
+    const T4 b = hr ? ld_b_l(xo) : t4_zero();
 #pragma unroll
     for (int q = 0; q < BT_MAXT0; ++q)
       if (q < c.t0) {
-        if (hl) et[q] = mm(et[q], ld_a(xl + (2 + q) * 256), a, -1.0);
-        if (hr) et[q] = mm(et[q], ld_a(xo + (2 + q) * 256), b, -1.0);
+        if (hl) et[q] = mm(et[q], ld_a_l(xl + (2 + q) * PTE), a, -1.0);
+        if (hr) et[q] = mm(et[q], ld_a_l(xo + (2 + q) * PTE), b, -1.0);
         acc_store(c.BEt + (e * c.t0 + q) * 256, et[q]);
       }
   }
@@ -213,7 +243,7 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail(BcrArgs c, int lvl
       const bool hasR = k + 1 < n;
       d4 XL, XR, G[BT_MAXT0];
       cnt += elim_core(c, k * s, (k - 1) * s, true, hasR, scr[wave], XL, XR, G);
-      store_factor(c, k * s, scr[wave] + 256, XL, XR, hasR, G);
+      store_factor(c, k * s, scr[wave] + PTE, XL, XR, hasR, G);
       wave_order();
     }
     __syncthreads();
@@ -254,7 +284,7 @@ __global__ __launch_bounds__(64 * TAIL_WAVES) void k_bcr_tail(BcrArgs c, int lvl
   if (n == 1 && wave == 0) {
     d4 XL, XR, G[BT_MAXT0];
     cnt += elim_core(c, 0, 0, false, false, scr[0], XL, XR, G);
-    tile_copy(c.FLi, scr[0] + 256);
+    tile_copy_l(c.FLi, scr[0] + PTE);
 #pragma unroll
     for (int q = 0; q < BT_MAXT0; ++q)
       if (q < c.t0) acc_store(c.FGt + q * 256, G[q]);
