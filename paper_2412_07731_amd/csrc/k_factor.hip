@@ -435,9 +435,10 @@ constexpr int BF_PW = 2, BF_RMAX_MAX = 6;
 // the accumulator layout writes a tile by columns across the lanes, which
 // with 16 would put the 16 lanes of a row group in the same bank; with 17
 // they fall in distinct banks, and the operand-layout reads stay contiguous.
-// (The six-rows-per-wave form keeps leading dimension 16: its registers are
-// full, and the padded index arithmetic would spill.)
-template <int BF_RMAX> struct BfLd { static constexpr int LD = BF_RMAX <= 5 ? TS + 1 : TS; };
+// Per lane, the padded positions are a base plus a constant: accumulator
+// element r of a double tile at wb + 4 r (float: wb + r), operand element s
+// at rb + 68 s, with the bases computed once.
+template <int BF_RMAX> struct BfLd { static constexpr int LD = TS + 1; };
 template <int LD>
 __device__ __forceinline__ int pidx(int e) { return LD == TS ? e : e + (e >> 4); }   // col 16 + row -> col LD + row
 template <typename T>
@@ -476,6 +477,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
                                                                DevInfo* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int LD = BfLd<BF_RMAX>::LD, TEP = TS * LD;
+  constexpr int AST = sizeof(T) == 8 ? 4 : 1;   // accumulator element stride in a padded tile
   const BlockInfo b = blk[order[blockIdx.x]];
   const int mt = b.mt, rt = b.rt;
   T* colbuf = reinterpret_cast<T*>(smem_raw);          // rt tiles: the panel column just factored
@@ -498,6 +500,20 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
   const double thr = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
   int cnt = 0;
   T* myscr = scr + w * TEP;
+  // padded positions of this lane's accumulator elements (wb + AST r) and
+  // operand elements (rb + 68 s)
+  const int wb = (lane & 15) * LD + (sizeof(T) == 8 ? (lane >> 4) : 4 * (lane >> 4));
+  const int rb = lane + (lane >> 4);
+  auto st_acc = [&](T* t, const AT& a) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[wb + AST * k] = a[k];
+  };
+  auto ld_op = [&](const T* t) {
+    BfOp<T> o;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) o.v[s] = t[rb + 68 * s];
+    return o;
+  };
 
   for (int c0 = 0; c0 < mt; c0 += BF_PW) {
     const int pw = min(BF_PW, mt - c0);
@@ -548,8 +564,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
 #pragma unroll
         for (int t = 0; t < BF_RMAX; ++t)
           if (t == ot) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) dt[pidx<LD>(acc_index<T>(lane, k))] = acc[t][j][k];
+            st_acc(dt, acc[t][j]);
           }
         wave_order();
         cnt += wave_chol_tile<T, LD>(dt, dt, li, thr, nullptr);
@@ -558,15 +573,14 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
       }
       __syncthreads();
       // rows below: L(r, c) = acc(r, c) L_cc^-T
-      const BfOp<T> lio = bf_ld_p<T, LD>(li);
+      const BfOp<T> lio = ld_op(li);
 #pragma unroll
       for (int t = 0; t < BF_RMAX; ++t) {
         const int r = c0 + w + 4 * t;
         if (r < rt && r > c) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) myscr[pidx<LD>(acc_index<T>(lane, k))] = acc[t][j][k];
+          st_acc(myscr, acc[t][j]);
           wave_order();
-          const BfOp<T> x = bf_ld_p<T, LD>(myscr);
+          const BfOp<T> x = ld_op(myscr);
           AT l = AT{0, 0, 0, 0};
 #pragma unroll
           for (int s = 0; s < 4; ++s) l = mfma(x.v[s], lio.v[s], l);
@@ -576,7 +590,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             dst[acc_index<T>(lane, k)] = l[k];
-            cb[pidx<LD>(acc_index<T>(lane, k))] = l[k];
+            cb[wb + AST * k] = l[k];
           }
         }
       }
@@ -586,12 +600,12 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
       for (int j2 = 0; j2 < BF_PW; ++j2) {
         if (j2 <= j || j2 >= pw) continue;
         const int c2 = c0 + j2;
-        const BfOp<T> y = bf_ld_p<T, LD>(colbuf + (size_t)(c2 - c0) * TEP);
+        const BfOp<T> y = ld_op(colbuf + (size_t)(c2 - c0) * TEP);
 #pragma unroll
         for (int t = 0; t < BF_RMAX; ++t) {
           const int r = c0 + w + 4 * t;
           if (r < rt && r >= c2) {
-            const BfOp<T> x = bf_ld_p<T, LD>(colbuf + (size_t)(r - c0) * TEP);
+            const BfOp<T> x = ld_op(colbuf + (size_t)(r - c0) * TEP);
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[t][j2] = mfma(-x.v[s], y.v[s], acc[t][j2]);
           }
