@@ -292,12 +292,16 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
                                                       DevInfo* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const BlockInfo b = blk[order[blockIdx.x]];
+  // LDS tiles with leading dimension 17 (see the panel kernel)
+  constexpr int LD = TS + 1, TEP = TS * LD, AST = sizeof(T) == 8 ? 4 : 1;
   T* panel = reinterpret_cast<T*>(smem_raw);
-  T* linv = panel + (size_t)b.rt * TE;
+  T* linv = panel + (size_t)b.rt * TEP;
   __shared__ double s_max[4];
   __shared__ T xbuf[48];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   typedef typename Acc<T>::type AT;
+  const int wb = (lane & 15) * LD + (sizeof(T) == 8 ? (lane >> 4) : 4 * (lane >> 4));
+  const int rb = lane + (lane >> 4), tb = tid + (tid >> 4);
 
   // pivot threshold from the largest real diagonal entry of M_i
   double md = 0.0;
@@ -323,20 +327,20 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = mfma(-X[64 * s + lane], Y[64 * s + lane], acc);
       }
-      T* dst = panel + (size_t)(r - p) * TE;
+      T* dst = panel + (size_t)(r - p) * TEP;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) dst[acc_index<T>(lane, k)] = acc[k];
+      for (int k = 0; k < 4; ++k) dst[wb + AST * k] = acc[k];
     }
     __syncthreads();
-    if (wave == 0) cnt += wave_chol_tile<T>(panel, panel, linv, thr, xbuf);
+    if (wave == 0) cnt += wave_chol_tile<T, LD>(panel, panel, linv, thr, xbuf);
     __syncthreads();
-    LB[lb_tile(b, p, p) + tid] = panel[tid];
-    LINV[b.linvoff + (long long)p * TE + tid] = linv[tid];
+    LB[lb_tile(b, p, p) + tid] = panel[tb];
+    LINV[b.linvoff + (long long)p * TE + tid] = linv[tb];
     for (int r = p + 1 + wave; r < b.rt; r += 4) {
       AT acc = AT{0, 0, 0, 0};
-      const T* X = panel + (size_t)(r - p) * TE;
+      const T* X = panel + (size_t)(r - p) * TEP;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma(X[64 * s + lane], linv[64 * s + lane], acc);
+      for (int s = 0; s < 4; ++s) acc = mfma(X[rb + 68 * s], linv[rb + 68 * s], acc);
       T* dst = LB + lb_tile(b, r, p);
 #pragma unroll
       for (int k = 0; k < 4; ++k) dst[acc_index<T>(lane, k)] = acc[k];
@@ -785,7 +789,7 @@ template <typename T>
 void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* order, int n,
                              int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info) {
   if (n == 0) return;
-  const size_t shmem = (size_t)(max_rt + 1) * TE * sizeof(T);
+  const size_t shmem = (size_t)(max_rt + 1) * TS * (TS + 1) * sizeof(T);   // padded tiles
   hipLaunchKernelGGL(k_block_factor<T>, dim3(n), dim3(256), shmem, st, blk, order, LB, LINV, info);
   hipLaunchKernelGGL(k_schur_contrib<T>, dim3(n), dim3(256), 0, st, blk, order, LB, PQ);
 }
