@@ -60,7 +60,14 @@ typedef enum {
 
 /* Problem data for ahlp_problem_create.  All arrays are HOST memory, FP64,
  * row-major per block, blocks concatenated in order.  Limits: N >= 1,
- * 1 <= m_i <= n_i, 0 <= l_j <= min(n_j, n_{j+1}, 64), 0 <= n0 <= 128. */
+ * 1 <= m_i <= n_i, 0 <= l_j <= min(n_j, n_{j+1}, 64), 0 <= n0 <= 128, and
+ * every bordered block fits the LDS of one workgroup: with rt_i the 16-row
+ * tiles of m_i plus those of l_{i-1}, l_i and n0 (each rounded up),
+ * (rt_i + 1) * 16 * 17 * 8 bytes <= the device's LDS per workgroup (160 KiB
+ * on gfx950: rt_i <= 74, blocks of up to about 1,180 rows with their links).
+ * The problem is handed over in host memory because create repacks it into
+ * the library's tile layout on the host, once (a reading of the boundary:
+ * every per-iteration call takes device pointers). */
 typedef struct {
   int32_t N;              /* number of diagonal blocks                              */
   int32_t n0;             /* number of linking variables x_0                        */
@@ -144,7 +151,24 @@ typedef struct {
   double rows_bytes;      /* algorithmic HBM bytes of the timed row passes          */
                           /* (AHLP_ST_AROWS): A and C read, vectors read and written */
   int32_t correctors;     /* Gondzio correctors kept over the whole run             */
+  double start_bkerr[2];  /* backward errors of the two starting-point solves       */
+                          /* after refinement (-1 with opts->start == 1)            */
 } ahlp_ipm_result_t;
+
+/* One interior-point iteration of the last ahlp_ipm_solve (see
+ * ahlp_ipm_history). */
+typedef struct {
+  double mu;              /* x'z / n_tot at the top of the iteration                 */
+  double sigma;           /* centring parameter (mu_aff / mu)^3 of Mehrotra's rule     */
+  double alpha_p, alpha_d;/* primal and dual step lengths taken                        */
+  double bkerr_pred;      /* backward error of the predictor direction after          */
+                          /* refinement, on the unregularized Newton system           */
+  double bkerr_corr;      /* the same for the corrector (Mehrotra's direction)        */
+  int32_t refine_pred;    /* refinement corrections of the predictor                  */
+  int32_t refine_corr;    /* refinement corrections of the corrector                  */
+  int32_t fp32;           /* 1 if the blocks of this iteration were factored in FP32  */
+  int32_t correctors;     /* Gondzio correctors kept in this iteration                */
+} ahlp_ipm_iter_t;
 
 /* Fills *opts with the defaults listed above. */
 void ahlp_ipm_default_opts(ahlp_ipm_opts_t* opts);
@@ -201,6 +225,21 @@ ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double*
                                int32_t max_refine, double refine_tol, double* bkerr,
                                hipStream_t stream);
 
+/* Gradient of a scalar L(x*, f*) of the interior-point end point and its
+ * objective f* = c'x* with respect to the LP data, by one transposed solve
+ * with the factors of the last ahlp_kkt_factor (taken at the end point; the
+ * derivative is the one of ahlp_kkt_adjoint, the KKT map of Sec. 2.3 with the
+ * barrier parameter fixed).  With g = dL/dx* + (dL/df*) c:
+ *     K' w = (g, 0, 0),   dL/db = w_y,   dL/dc = w_x + (dL/df*) x*
+ * where x* is the x of that factorization.  gx: DEVICE [n_tot] (dL/dx*; NULL
+ * means zero); gf: dL/df* (host value); grad_b: DEVICE [m_tot] and grad_c:
+ * DEVICE [n_tot], outputs (must not alias gx).  max_refine, refine_tol and
+ * *bkerr as in ahlp_kkt_adjoint.  AHLP_ESTATE if no factorization exists,
+ * AHLP_EINVAL for null outputs or a non-finite gf. */
+ahlp_status_t ahlp_lp_gradient(ahlp_problem_t p, const double* gx, double gf, double* grad_b,
+                               double* grad_c, int32_t max_refine, double refine_tol,
+                               double* bkerr, hipStream_t stream);
+
 /* Replaces the right-hand side b and the cost c of the LP (Sec. 2.2) with new
  * DEVICE vectors b [m_tot] and c [n_tot] (copied; the matrix and the factors
  * are untouched).  Recomputes the norms the stopping test uses, so it
@@ -244,6 +283,14 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
 ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* opts, double* x,
                              double* y, double* z, ahlp_ipm_result_t* res,
                              hipStream_t stream);
+
+/* Per-iteration record of the last ahlp_ipm_solve on p (Sec. 2.3 iteration:
+ * centrality, step lengths and the backward error of each Newton direction).
+ * out: HOST array of cap entries (may be NULL when cap == 0); *count (host)
+ * receives the number of iterations of that run, of which min(cap, *count)
+ * are written.  Errors: AHLP_EINVAL for a null handle or count, cap < 0. */
+ahlp_status_t ahlp_ipm_history(ahlp_problem_t p, ahlp_ipm_iter_t* out, int32_t cap,
+                               int32_t* count);
 
 /* Last error message of this thread ("" when none). */
 const char* ahlp_last_error(void);

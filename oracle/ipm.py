@@ -67,6 +67,10 @@ class Result:
     refine_steps: int = 0
     max_bkerr: float = 0.0
     history: list = field(default_factory=list)
+    # (backward error, corrections) of every refined solve in call order: the
+    # two start-point solves, then per iteration the predictor, the corrector
+    # and any centrality correction
+    solves: list = field(default_factory=list)
 
 
 def newton_residual(inst, x, z, r, d):
@@ -84,6 +88,9 @@ def _inf(*vs):
 
 
 def solve_refined(inst, f, r, knorm, opts, stats):
+    """Newton solve with refinement; returns (d, backward error after the
+    last correction).  stats["solves"] collects (backward error, corrections)
+    per call, in call order."""
     x, z = f.x, f.z
     d = newton.solve(f, *r)
     rnorm = _inf(*r)
@@ -98,6 +105,7 @@ def solve_refined(inst, f, r, knorm, opts, stats):
         steps += 1
     stats["refine"] += steps
     stats["bkerr"] = max(stats["bkerr"], be)
+    stats.setdefault("solves", []).append((be, steps))
     return d, be
 
 
@@ -132,7 +140,10 @@ def starting_point(inst, rowabs, colabs, opts, stats):
     return x0, yt.copy(), z0
 
 
-def solve(inst, opts: Options = None, verbose=False, max_iter=None):
+def solve(inst, opts: Options = None, verbose=False, max_iter=None, keep_iterates=False):
+    """Runs the interior-point method from Mehrotra's starting point.  With
+    keep_iterates every history entry also holds copies of the iterate
+    (x, y, z) at the top of its iteration."""
     opts = opts or Options()
     if max_iter is not None:
         opts = Options(**{**opts.__dict__, "max_iter": max_iter})
@@ -163,7 +174,7 @@ def solve(inst, opts: Options = None, verbose=False, max_iter=None):
         stats["pivots"] += f.pivots
         kn = lp.kkt_inf_norm(rowabs, colabs, x, z)
         xz = x * z
-        da, _ = solve_refined(inst, f, (rd, rp, -xz), kn, opts, stats)
+        da, be_a = solve_refined(inst, f, (rd, rp, -xz), kn, opts, stats)
         ap_aff, ad_aff = ratio(x, da[0]), ratio(z, da[2])
         mu_aff = float((x + ap_aff * da[0]) @ (z + ad_aff * da[2])) / n
         sigma = (mu_aff / mu) ** 3
@@ -177,15 +188,20 @@ def solve(inst, opts: Options = None, verbose=False, max_iter=None):
             if not ok:
                 break
             ncorr += 1
+        hist.append(dict(k=k, mu=mu, relgap=relgap, pinf=pinf, dinf=dinf,
+                         ap_aff=ap_aff, ad_aff=ad_aff, mu_aff=mu_aff,
+                         sigma=sigma, ap=ap, ad=ad, bkerr_pred=be_a, bkerr=be,
+                         correctors=ncorr))
+        if keep_iterates:
+            hist[-1].update(x=x.copy(), y=y.copy(), z=z.copy())
         x = x + ap * d[0]
         y = y + ad * d[1]
         z = z + ad * d[2]
-        hist.append(dict(k=k, mu=mu, relgap=relgap, pinf=pinf, dinf=dinf,
-                         sigma=sigma, ap=ap, ad=ad, bkerr=be, correctors=ncorr))
         k += 1
     return Result(status=status, iterations=k, x=x, y=y, z=z, pobj=pobj, dobj=dobj,
                   relgap=relgap, pinf=pinf, dinf=dinf, mu=mu, pivots=stats["pivots"],
-                  refine_steps=stats["refine"], max_bkerr=stats["bkerr"], history=hist)
+                  refine_steps=stats["refine"], max_bkerr=stats["bkerr"], history=hist,
+                  solves=stats.get("solves", []))
 
 
 def gondzio_corrector(inst, f, x, z, d, ap, ad, smu, kn, opts, stats):

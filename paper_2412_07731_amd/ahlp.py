@@ -49,7 +49,15 @@ class IpmResult(C.Structure):
                 ("rel_pinf", C.c_double), ("rel_dinf", C.c_double), ("mu", C.c_double),
                 ("max_bkerr", C.c_double), ("t_total_ms", C.c_double),
                 ("t_stage_ms", C.c_double * 8), ("n_stage", C.c_int32 * 8),
-                ("rows_bytes", C.c_double), ("correctors", C.c_int32)]
+                ("rows_bytes", C.c_double), ("correctors", C.c_int32),
+                ("start_bkerr", C.c_double * 2)]
+
+
+class IpmIter(C.Structure):
+    _fields_ = [("mu", C.c_double), ("sigma", C.c_double), ("alpha_p", C.c_double),
+                ("alpha_d", C.c_double), ("bkerr_pred", C.c_double), ("bkerr_corr", C.c_double),
+                ("refine_pred", C.c_int32), ("refine_corr", C.c_int32), ("fp32", C.c_int32),
+                ("correctors", C.c_int32)]
 
 
 # Every exported symbol with its signature (argtypes, restype).
@@ -65,11 +73,15 @@ SIGNATURES = {
     "ahlp_kkt_adjoint": ([C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_double,
                                                             C.POINTER(C.c_double), C.c_void_p],
                          C.c_int),
+    "ahlp_lp_gradient": ([C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_int32,
+                          C.c_double, C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "ahlp_problem_set_bc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "ahlp_problem_set_launch": ([C.c_void_p, C.c_int32], C.c_int),
     "ahlp_autotune": ([C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
     "ahlp_ipm_solve": ([C.c_void_p, C.POINTER(IpmOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                         C.POINTER(IpmResult), C.c_void_p], C.c_int),
+    "ahlp_ipm_history": ([C.c_void_p, C.POINTER(IpmIter), C.c_int32, C.POINTER(C.c_int32)],
+                         C.c_int),
     "ahlp_last_error": ([], C.c_char_p),
     "ahlp_problem_sizes": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
@@ -200,6 +212,21 @@ class Problem:
                                       C.byref(be), _stream(stream)))
         return wx, wy, wz, be.value
 
+    def lp_gradient(self, gx, gf, max_refine=10, refine_tol=1e-12, stream=None, out=None):
+        """(dL/db, dL/dc, bkerr) for L(x*, f*) with dL/dx* = gx (device tensor or
+        None) and dL/df* = gf (a number) at the last factorization (ahlp_lp_gradient)."""
+        import torch
+        if out is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+            out = (torch.empty(self.m_tot, dtype=torch.float64, device=dev),
+                   torch.empty(self.n_tot, dtype=torch.float64, device=dev))
+        gb, gc = out
+        be = C.c_double(-1.0)
+        _check(lib().ahlp_lp_gradient(self.h, _dptr(gx) if gx is not None else None, float(gf),
+                                      _dptr(gb), _dptr(gc), int(max_refine), float(refine_tol),
+                                      C.byref(be), _stream(stream)))
+        return gb, gc, be.value
+
     def autotune(self, cache_path=None, stream=None):
         """Pick the block-factor kernel per bordered tile-row count (ahlp_autotune);
         returns how many counts were measured (0: all from the cache)."""
@@ -230,11 +257,21 @@ class Problem:
         code = lib().ahlp_ipm_solve(self.h, C.byref(o), _dptr(x), _dptr(y), _dptr(z), C.byref(r),
                                     _stream(stream))
         _check(code, allow_warn=True)
-        res = {f: getattr(r, f) for f, _ in IpmResult._fields_ if f not in ("t_stage_ms", "n_stage")}
+        res = {f: getattr(r, f) for f, _ in IpmResult._fields_
+               if f not in ("t_stage_ms", "n_stage", "start_bkerr")}
+        res["start_bkerr"] = [r.start_bkerr[0], r.start_bkerr[1]]
         res["status_name"] = STATUS.get(code, str(code))
         res["t_stage_ms"] = {STAGES[i]: r.t_stage_ms[i] for i in range(8)}
         res["n_stage"] = {STAGES[i]: r.n_stage[i] for i in range(8)}
         return x, y, z, res
+
+    def history(self):
+        """Per-iteration records of the last ipm() (ahlp_ipm_history), as dicts."""
+        cnt = C.c_int32(0)
+        _check(lib().ahlp_ipm_history(self.h, None, 0, C.byref(cnt)))
+        buf = (IpmIter * max(cnt.value, 1))()
+        _check(lib().ahlp_ipm_history(self.h, buf, cnt.value, C.byref(cnt)))
+        return [{f: getattr(buf[i], f) for f, _ in IpmIter._fields_} for i in range(cnt.value)]
 
     # --- inspection
     def debug_block(self, i):

@@ -11,7 +11,7 @@ function theorem its derivative is K^-1 [dc; db; 0] with K the Newton matrix
 
   * forward derivatives (jvp) are one Newton solve (ahlp_kkt_solve), and
   * the gradient of a scalar of (x, f = c'x) is one transposed solve
-    (ahlp_kkt_adjoint) with g = (dL/dx + (dL/df) c, 0, 0):
+    (ahlp_lp_gradient) with g = (dL/dx + (dL/df) c, 0, 0):
     dL/db = w_y, dL/dc = w_x + (dL/df) x.
 
 Both reuse one factorization at the end point.  At a nondegenerate optimum
@@ -32,7 +32,8 @@ class LPSolve(torch.autograd.Function):
     """(x, f) = LPSolve.apply(b, c, problem, opts): interior-point solve of the
     problem with right-hand side b and cost c (device float64 vectors), then a
     factorization at the end point that the backward pass reuses.  The problem
-    handle is stateful: run backward before the next factor or solve on it."""
+    handle is stateful: run backward before the next factor or solve on it.
+    f is the library's objective c'x at the end point."""
 
     @staticmethod
     def forward(ctx, b, c, problem, opts):
@@ -40,7 +41,8 @@ class LPSolve(torch.autograd.Function):
         b = b.detach().contiguous()
         c = c.detach().contiguous()
         problem.set_bc(b, c)
-        x, y, z, res = problem.ipm(**opts)
+        ipm_opts = {k: v for k, v in opts.items() if k not in ("adjoint_refine", "adjoint_tol")}
+        x, y, z, res = problem.ipm(**ipm_opts)
         if res["status"] != 0:
             raise RuntimeError(f"interior-point solve ended with {res['status_name']}")
         problem.factor(x, z, rho=opts.get("rho", _IPM_DEFAULTS["rho"]),
@@ -48,23 +50,16 @@ class LPSolve(torch.autograd.Function):
         ctx.problem = problem
         ctx.max_refine = int(opts.get("adjoint_refine", 10))
         ctx.refine_tol = float(opts.get("adjoint_tol", 1e-12))
-        ctx.save_for_backward(x, c)
-        ctx.end_point = (y, z)
-        return x, torch.dot(c, x)
+        f = torch.tensor(res["primal_obj"], dtype=torch.float64, device=x.device)
+        return x, f
 
     @staticmethod
     def backward(ctx, gx, gf):
-        x, c = ctx.saved_tensors
-        P = ctx.problem
-        g = torch.zeros_like(x) if gx is None else gx.contiguous().clone()
-        if gf is not None:
-            g = g + gf * c
-        zy = torch.zeros(P.m_tot, dtype=torch.float64, device=x.device)
-        zx = torch.zeros_like(x)
-        wx, wy, _, _ = P.adjoint(g.contiguous(), zy, zx, max_refine=ctx.max_refine,
-                                 refine_tol=ctx.refine_tol)
-        grad_c = wx if gf is None else wx + gf * x
-        return wy, grad_c, None, None
+        gf = 0.0 if gf is None else float(gf)
+        gx = None if gx is None else gx.contiguous()
+        grad_b, grad_c, _ = ctx.problem.lp_gradient(gx, gf, max_refine=ctx.max_refine,
+                                                     refine_tol=ctx.refine_tol)
+        return grad_b, grad_c, None, None
 
 
 def solve(problem, b, c, **opts):

@@ -140,11 +140,15 @@ struct StageTimer {
 // (+ check, step lengths), per factor precision; C = step + next residuals.
 enum { SEG_A64 = 0, SEG_A32, SEG_B64, SEG_B32, SEG_C, SEG_COUNT };
 // What a captured segment bakes in besides the problem's own buffers.
+// launch_gen counts changes of the launch configuration (block-factor
+// buckets and order, launch mode), which a captured segment also bakes in.
 struct SegKey {
   const double *x, *y, *z;
   double rho, delta, eta;
+  unsigned launch_gen;
   bool operator==(const SegKey& o) const {
-    return x == o.x && y == o.y && z == o.z && rho == o.rho && delta == o.delta && eta == o.eta;
+    return x == o.x && y == o.y && z == o.z && rho == o.rho && delta == o.delta &&
+           eta == o.eta && launch_gen == o.launch_gen;
   }
 };
 
@@ -177,6 +181,7 @@ struct ahlp_problem_s {
   // per-block launch mode (the reference the batched launches are compared
   // with): block i's SYRK items, link items, and its index in an identity list
   int launch_mode = AHLP_LAUNCH_BATCHED;
+  unsigned launch_gen = 0;   // bumped whenever bf_order, the buckets or launch_mode change
   // block-factor kernel per bordered tile-row count (0 panel, 1 column; the
   // default rule is panel wherever it fits); set by ahlp_autotune
   std::vector<int> bf_kernel;
@@ -223,6 +228,7 @@ struct ahlp_problem_s {
   double *ta = nullptr, *aw1 = nullptr, *aw2 = nullptr, *tc = nullptr, *w1p = nullptr,
          *w2p = nullptr, *gc = nullptr;
   double* adj_rz = nullptr;   // z g_z of the transposed solve
+  double *grad_g = nullptr, *grad_wz = nullptr;   // ahlp_lp_gradient: its right-hand side, w_z
   // Gondzio correctors: right-hand side, candidate direction, zero y-vector
   double *g_r = nullptr, *g_dx = nullptr, *g_dy = nullptr, *g_dz = nullptr, *zerosm = nullptr;
   double *rp = nullptr, *rd = nullptr, *rzv = nullptr, *dxa = nullptr, *dya = nullptr,
@@ -245,6 +251,7 @@ struct ahlp_problem_s {
     SegKey key{};
   } graphs[SEG_COUNT];
   StageTimer timer;
+  std::vector<ahlp_ipm_iter_t> hist;   // per-iteration record of the last interior-point run
   double rows_bytes = 0.0;      // algorithmic bytes of the timed row passes
   double a_bytes = 0, c_bytes = 0, xv_bytes = 0, x0_bytes = 0, yv_bytes = 0;
 
@@ -843,6 +850,16 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     b.qoff = qo; qo += 16LL * b.kt;
     p->max_rt = std::max(p->max_rt, b.rt);
   }
+  // the column-at-a-time block factor keeps a bordered block's whole tile
+  // column in LDS: (rt + 1) padded 16 x 17 tiles
+  {
+    const size_t col_sh = (size_t)(p->max_rt + 1) * 16 * 17 * sizeof(double);
+    if (col_sh > (size_t)dev_lds)
+      return fail(AHLP_EINVAL,
+                  "a block with %d bordered tile rows (m_i + l_{i-1} + l_i + n0 up to %d) needs %zu "
+                  "bytes of LDS for its factorization; this device has %d (at most %d tile rows)",
+                  p->max_rt, 16 * p->max_rt, col_sh, dev_lds, dev_lds / (16 * 17 * 8) - 1);
+  }
   p->x0off = xo; p->n_tot = xo + n0;
   p->mblk = yo; p->m_tot = yo + p->nl;
   p->d0off = dpo; p->dp_total = dpo + p->n0p;
@@ -1142,6 +1159,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->aty, p->n_tot));
   CHK(M.alloc(&p->gdir, p->n_tot));
   CHK(M.alloc(&p->adj_rz, p->n_tot));
+  CHK(M.alloc(&p->grad_g, p->n_tot));
+  CHK(M.alloc(&p->grad_wz, p->n_tot));
   for (double** v : {&p->g_r, &p->g_dx, &p->g_dz}) CHK(M.alloc(v, p->n_tot));
   for (double** v : {&p->g_dy, &p->zerosm}) CHK(M.alloc(v, p->m_tot));
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
@@ -1254,6 +1273,27 @@ ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double*
   return AHLP_OK;
 }
 
+ahlp_status_t ahlp_lp_gradient(ahlp_problem_t p, const double* gx, double gf, double* grad_b,
+                               double* grad_c, int32_t max_refine, double refine_tol,
+                               double* bkerr, hipStream_t st) {
+  g_err.clear();
+  if (!p || !grad_b || !grad_c) return fail(AHLP_EINVAL, "null argument");
+  if (!p->factored) return fail(AHLP_ESTATE, "gradient before factor");
+  if (!std::isfinite(gf)) return fail(AHLP_EINVAL, "dL/df must be finite");
+  if (gx == grad_c) return fail(AHLP_EINVAL, "outputs must not alias inputs");
+  // g_x = dL/dx + (dL/df) c
+  if (gx) launch_copy(st, p->n_tot, gx, p->grad_g);
+  else launch_fill(st, p->n_tot, 0.0, p->grad_g);
+  if (gf != 0.0) launch_axpy(st, p->n_tot, gf, p->c, p->grad_g);
+  HIPCHK(hipGetLastError());
+  CHK(ahlp_kkt_adjoint(p, p->grad_g, p->zerosm, p->zerosn, grad_c, grad_b, p->grad_wz, max_refine,
+                       refine_tol, bkerr, st));
+  // dL/dc = w_x + (dL/df) x at the factorization's x
+  if (gf != 0.0) launch_axpy(st, p->n_tot, gf, p->xs, grad_c);
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
 namespace {
 std::string arch_name(int device) {
   hipDeviceProp_t prop;
@@ -1358,6 +1398,7 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
   std::vector<int> hbf = bf_buckets(p);
   HIPCHK(hipMemcpyAsync(p->bf_order, hbf.data(), sizeof(int) * hbf.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
+  ++p->launch_gen;   // captured graphs hold the old buckets: capture again
   return AHLP_OK;
 }
 
@@ -1366,6 +1407,7 @@ ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode) {
   if (!p) return fail(AHLP_EINVAL, "null argument");
   if (mode != AHLP_LAUNCH_BATCHED && mode != AHLP_LAUNCH_PER_BLOCK)
     return fail(AHLP_EINVAL, "unknown launch mode %d", mode);
+  if (mode != p->launch_mode) ++p->launch_gen;
   p->launch_mode = mode;
   return AHLP_OK;
 }
@@ -1424,6 +1466,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
                                  : ~0u;
   p->timer.reset();
   p->rows_bytes = 0.0;
+  p->hist.clear();
+  R.start_bkerr[0] = R.start_bkerr[1] = -1.0;
   const long long n = p->n_tot, m = p->m_tot;
   int total_piv = 0;
   double max_bk = 0.0;
@@ -1454,10 +1498,12 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     CHK(solve_refined(p, p->zerosn, p->b, p->zerosn, p->dxa, p->dya, p->dza, o->max_refine,
                       o->refine_tol, kn, &be, &steps, st));
     account(be, steps);
+    R.start_bkerr[0] = be;
     HIPCHK(hipMemsetAsync(p->rp, 0, sizeof(double) * m, st));
     CHK(solve_refined(p, p->c, p->rp, p->zerosn, p->dx, p->dy, p->dz, o->max_refine,
                       o->refine_tol, kn, &be, &steps, st));
     account(be, steps);
+    R.start_bkerr[1] = be;
     launch_copy(st, n, p->dxa, x);
     launch_copy(st, m, p->dy, y);
     apply_At(p, y, 1, p->c, p->zerosn, z, st);   // z~ = c - A'y~
@@ -1496,7 +1542,7 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   double mu = 0, pobj = 0, dobj = 0, relgap = 0, pinf = 0, dinf = 0;
   const DevInfo* hinfo = reinterpret_cast<const DevInfo*>(p->h_scal + NSCAL - 1);
   const double* hs = p->h_scal;
-  SegKey key{x, y, z, o->rho, o->delta, o->eta};
+  SegKey key{x, y, z, o->rho, o->delta, o->eta, p->launch_gen};
   // residuals of the current iterate (the start of every iteration).  A'y is
   // kept in p->aty: formed by a column pass at the start (full), then
   // advanced with each step, A'y+ = A'y + alpha_d A'dy, where A'dy is the
@@ -1555,6 +1601,9 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     if (k >= o->max_iter) break;
     if (fp32_live && mu < o->mu_switch) fp32_live = false;
     const double kn = knorm_iter;
+    ahlp_ipm_iter_t it;
+    std::memset(&it, 0, sizeof it);
+    it.mu = mu;
 
     // One predictor-corrector pass with FP64 or FP32 factors.  A direction is
     // accepted at backward error <= refine_tol; with FP32 factors also at
@@ -1610,6 +1659,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
         CHK(read_scal(p, NSCAL, st));
       }
       account(be, steps);
+      it.bkerr_pred = be;
+      it.refine_pred = steps;
       if (o->verbose > 1) fprintf(stderr, "ahlp   predictor bkerr %.2e refine %d\n", be, steps);
       // corrector: sigma mu on the device, rz_c and
       // t_c = t_a - sigma mu A(D/x) + A(D dxa dza / x), solve, check, step lengths
@@ -1640,6 +1691,9 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
         CHK(read_scal(p, NSCAL, st));
       }
       account(be, steps);
+      it.bkerr_corr = be;
+      it.refine_corr = steps;
+      it.sigma = hs[S_SMU] / mu;
       if (o->verbose > 1) fprintf(stderr, "ahlp   corrector bkerr %.2e refine %d\n", be, steps);
       return AHLP_OK;
     };
@@ -1648,6 +1702,7 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       CHK(pass(true, &ok));
       if (ok) {
         R.fp32_iterations++;
+        it.fp32 = 1;
       } else {
         // FP32 factors cannot deliver acceptable directions any more: FP64
         // factors from here on, and this iteration is redone with them
@@ -1699,8 +1754,12 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       ap = ap_n;
       ad = ad_n;
       R.correctors++;
+      it.correctors++;
     }
     if (gz_used) launch_copy(st, n, p->gdir, p->g);
+    it.alpha_p = ap;
+    it.alpha_d = ad;
+    p->hist.push_back(it);
     ++k;
     if (ap < 1e-12 && ad < 1e-12) {
       launch_steps(st, o->eta, StepSet{3, {n, m, n, 0},
@@ -1734,6 +1793,17 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (res) *res = R;
   return status;
+}
+
+ahlp_status_t ahlp_ipm_history(ahlp_problem_t p, ahlp_ipm_iter_t* out, int32_t cap,
+                               int32_t* count) {
+  g_err.clear();
+  if (!p || !count) return fail(AHLP_EINVAL, "null argument");
+  if (cap < 0 || (cap > 0 && !out)) return fail(AHLP_EINVAL, "need cap >= 0 and out for cap > 0");
+  *count = (int32_t)p->hist.size();
+  const int32_t w = std::min<int32_t>(cap, *count);
+  for (int32_t i = 0; i < w; ++i) out[i] = p->hist[i];
+  return AHLP_OK;
 }
 
 // ---------------------------------------------------------------- inspection

@@ -1,0 +1,56 @@
+"""Shared checks of the GPU parity tests against the oracle's recorded runs
+(tests/golden/oracle_ipm.json).  Not a test module."""
+import json
+import os
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_ipm.json")))
+
+# Backward-error target of a Newton direction (relative KKT residual on the
+# unregularized Newton system of Sec. 2.3).  Along an interior-point run the
+# oracle itself misses it in the last iterations, where the system is nearly
+# singular, so an iterate passes if its direction is within 10x of the
+# oracle's backward error on the same iterate.
+ETA = 1e-10
+
+
+def golden(config, seed, gondzio=0):
+    for r in GOLDEN["runs"]:
+        if r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio:
+            return r
+    return None
+
+
+def eta_bound(eta_orc):
+    return max(ETA, 10.0 * eta_orc)
+
+
+def check_trajectory(hist, res, g, label, mu_rtol_early=1e-6, mu_rtol_late=1e-2, late=3):
+    """Per-iterate parity of an FP64 interior-point run with the oracle's run
+    of the same instance: the same number of iterations; for every predictor
+    and corrector (and the two start-point solves) a backward error after
+    refinement of at most max(1e-10, 10 eta_orc); mu at the top of every
+    iteration within mu_rtol_early of the oracle's (mu_rtol_late in the last
+    `late` iterations, where the directions are ill-conditioned and rounding
+    differences grow).  Returns (iterates missing 1e-10 itself, worst mu
+    relative difference)."""
+    assert len(hist) == g["iterations"], (label, len(hist), g["iterations"])
+    misses = 0
+    for j, (eg, eo) in enumerate(zip(res["start_bkerr"], g["start_bkerr"])):
+        assert eg <= eta_bound(eo), (label, "start", j, eg, eo)
+        misses += eg > ETA
+    worst_mu = 0.0
+    n = len(hist)
+    for k, h in enumerate(hist):
+        for key in ("bkerr_pred", "bkerr_corr"):
+            eg, eo = h[key], g[key][k]
+            assert eg <= eta_bound(eo), (label, k, key, eg, eo)
+            misses += eg > ETA
+        mo = g["mu_trace"][k]
+        d = abs(h["mu"] - mo) / mo
+        worst_mu = max(worst_mu, d)
+        tol = mu_rtol_late if k >= n - late else mu_rtol_early
+        assert d <= tol, (label, k, "mu", h["mu"], mo)
+    print(f"{label}: {n} iterations, {misses} of {2 * n + 2} solves above eta = {ETA:g} "
+          f"(oracle: {sum(e > ETA for e in g['bkerr_pred'] + g['bkerr_corr'] + g['start_bkerr'])}), "
+          f"worst mu difference {worst_mu:.1e}", flush=True)
+    return misses, worst_mu

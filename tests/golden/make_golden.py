@@ -39,20 +39,33 @@ def run(config, seed, gondzio=0):
                 mu=r.mu, fstar=inst.fstar, refine_steps=r.refine_steps,
                 max_bkerr=r.max_bkerr, pivots=r.pivots,
                 mu_trace=[h["mu"] for h in r.history],
+                sigma_trace=[h["sigma"] for h in r.history],
+                alpha_p=[h["ap"] for h in r.history],
+                alpha_d=[h["ad"] for h in r.history],
+                # backward errors after refinement of the predictor and the
+                # corrector of every iteration, and of the two start solves
+                bkerr_pred=[h["bkerr_pred"] for h in r.history],
+                bkerr_corr=[h["bkerr"] for h in r.history],
+                start_bkerr=[r.solves[0][0], r.solves[1][0]],
                 correctors=sum(h.get("correctors", 0) for h in r.history),
                 seconds=round(time.time() - t, 2))
 
 
 def main():
     """No arguments: rewrite the file with tiny (seeds 0-7) and n512 (seed 0).
-    --quick: tiny only.  --add CONFIG:SEED[:gK] [...]: run just those (with K
+    --quick: tiny only.  --refresh: run again every run the file holds.  --add CONFIG:SEED[:gK] [...]: run just those (with K
     Gondzio correctors per iteration if gK is given) and merge them into the
     existing file (e.g. --add uneven:0, the N=2048 workload, which takes
     minutes and several GB; --add g_medium:0, a general-form instance)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_ipm.json")
-    if "--add" in sys.argv:
+    if "--add" in sys.argv or "--refresh" in sys.argv:
         out = json.load(open(path))
-        for spec in sys.argv[sys.argv.index("--add") + 1:]:
+        if "--refresh" in sys.argv:
+            specs = [f"{q['config']}:{q['seed']}" + (f":g{q['gondzio']}" if q.get("gondzio") else "")
+                     for q in out["runs"]]
+        else:
+            specs = sys.argv[sys.argv.index("--add") + 1:]
+        for spec in specs:
             parts = spec.split(":")
             config, seed = parts[0], int(parts[1])
             g = int(parts[2][1:]) if len(parts) > 2 else 0      # CONFIG:SEED:gK = K correctors

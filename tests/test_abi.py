@@ -34,12 +34,37 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) == set(ahlp.SIGNATURES)
 
 
-def test_struct_layouts():
+STRUCTS = [("ahlp_problem_desc_t", "Desc"), ("ahlp_factor_opts_t", "FactorOpts"),
+           ("ahlp_ipm_opts_t", "IpmOpts"), ("ahlp_ipm_result_t", "IpmResult"),
+           ("ahlp_ipm_iter_t", "IpmIter")]
+
+
+def test_struct_layouts(tmp_path):
+    """Every binding structure has the size and field offsets that the C
+    compiler gives the header's declaration."""
     from paper_2412_07731_amd import ahlp
-    # 2 int32 + 3 pointers + 7 pointers
-    assert ctypes.sizeof(ahlp.Desc) == 8 + 10 * 8
-    assert ctypes.sizeof(ahlp.FactorOpts) == 24
-    assert ctypes.sizeof(ahlp.IpmResult) == 5 * 4 + 4 + 8 * 8 + 8 * 8 + 8 * 4 + 8 + 8
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ahlp.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS:
+        lines.append(f'  printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for f, _ in getattr(ahlp, pyname)._fields_:
+            lines.append(f'  printf("{pyname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("no C compiler or HIP headers")
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I",
+                    os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        pyname, field, val = line.split()
+        S = getattr(ahlp, pyname)
+        got = ctypes.sizeof(S) if field == "size" else getattr(S, field).offset
+        assert got == int(val), (pyname, field, got, val)
 
 
 def test_library_fails_loudly_when_missing(monkeypatch, tmp_path):

@@ -55,3 +55,36 @@ def test_graph_equals_eager(dev, case):
             print(f"{case} prec {prec}: eager {1e3 * te:.1f} ms, graph {1e3 * tg:.1f} ms", flush=True)
     finally:
         P.close()
+
+
+def test_graph_recaptured_after_autotune(dev, tmp_path):
+    """A captured iteration holds the block-factor buckets and their launch
+    geometry.  Autotuning (which can move blocks between the panel and the
+    column kernel) and a change of launch mode must make the next graph run
+    capture again: every graph run equals the eager run of the same
+    configuration bit for bit."""
+    from paper_2412_07731_amd.ahlp import Problem
+    print("case: uneven48 graph + autotune + launch mode", flush=True)
+    inst = gen.generate("uneven", 1, N=48)
+    P = Problem(inst)
+    try:
+        e0 = P.ipm()
+        assert _same(e0, P.ipm(graph=1))
+        # a table that sends every tunable block to the column kernel
+        path = tmp_path / "tune.txt"
+        k = [(int(inst.l[j - 1]) if j > 0 else 0) + (int(inst.l[j]) if j < inst.N - 1 else 0) + inst.n0
+             for j in range(inst.N)]
+        rts = sorted({(int(m) + 15) // 16 + (kk + 15) // 16 for m, kk in zip(inst.m, k)})
+        import torch as _t
+        arch = _t.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        path.write_text("".join(f"{arch} {rt} column 1.0 0.5\n" for rt in rts if rt <= 24))
+        assert P.autotune(str(path)) == 0
+        e1 = P.ipm()
+        g1 = P.ipm(graph=1)
+        assert _same(e1, g1)
+        P.set_launch(per_block=True)
+        g2 = P.ipm(graph=1)
+        P.set_launch(per_block=False)
+        assert _same(e1, g2)
+    finally:
+        P.close()

@@ -6,9 +6,6 @@ the full interior-point run (identical iteration counts, objective within
 1e-8).  Tolerances follow from FP64 rounding of the same block elimination
 (different summation order only) and from the stated parity targets.
 """
-import json
-import os
-
 import numpy as np
 import pytest
 
@@ -18,15 +15,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import dense_kkt, ipm as oipm, newton  # noqa: E402
 from paper_2412_07731_amd import gen  # noqa: E402
-
-GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_ipm.json")))
-
-
-def golden(config, seed, gondzio=0):
-    for r in GOLDEN["runs"]:
-        if r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio:
-            return r
-    raise KeyError((config, seed))
+from tests._parity import check_trajectory, golden  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -161,7 +150,7 @@ def test_ipm_tiny_matches_oracle(dev, seed):
     assert abs(res["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))
     assert abs(res["primal_obj"] - inst.fstar) <= 1e-7 * (1 + abs(inst.fstar))
     assert np.max(np.abs(H(x) - inst.xstar)) <= 1e-6 * (1 + np.max(inst.xstar))
-    assert res["max_bkerr"] <= 1e-6
+    check_trajectory(P.history(), res, g, f"tiny seed {seed}")
     P.close()
 
 
@@ -265,6 +254,7 @@ def test_n512_ipm_fp64(dev, n512):
     assert res["iterations"] == g["iterations"]
     assert abs(res["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))
     assert res["pivots_modified"] == 0
+    check_trajectory(P.history(), res, g, "n512 fp64")
     P.close()
 
 
@@ -281,3 +271,61 @@ def test_n512_ipm_fp32_refine(dev, n512):
     assert res["fp32_iterations"] > 0
     assert err <= 1e-8
     P.close()
+
+
+def _fp32_factor_bounds(A, D, L, W, B, delta):
+    """Backward errors of FP32 block factors against the exact FP64 data
+    (u = 2^-24).  The SYRK forms each M_ij as an n-term FP32 dot product
+    (error <= (n + 2) u (|A| D |A'|)_ij, counting the rounding of A and D to
+    FP32); the blocked Cholesky and the solve against B multiply by computed
+    inverses of 16 x 16 diagonal tiles, whose own error adds a term
+    ~ kappa_tile^2 u |L| |L'| (kappa_tile: the largest condition number of a
+    diagonal tile of L).  Hence, component by component,
+        |L L' - M| <= u ((n + 2) |A| D |A'| + (m + 1 + 4 kappa^2) |L| |L'|)
+        |L W - B|  <= u ((m + 1 + 4 kappa^2) |L| |W| + |B|)
+    (Higham, Accuracy and Stability, Thms 8.5 and 10.3, with the inverse
+    terms of Sec. 14)."""
+    u = 2.0 ** -24
+    m, n = A.shape
+    kap = 1.0
+    for c in range(0, m, 16):
+        Lt = L[c:c + 16, c:c + 16]
+        kap = max(kap, np.linalg.cond(Lt, np.inf))
+    M = (A * D) @ A.T + delta * np.eye(m)
+    absM = (np.abs(A) * D) @ np.abs(A).T
+    lhs_l = np.abs(L @ L.T - M)
+    rhs_l = u * ((n + 2) * absM + (m + 1 + 4 * kap ** 2) * (np.abs(L) @ np.abs(L).T))
+    lhs_w = np.abs(L @ W - B)
+    rhs_w = u * ((m + 1 + 4 * kap ** 2) * (np.abs(L) @ np.abs(W)) + np.abs(B))
+    return lhs_l, rhs_l, lhs_w, rhs_w, kap
+
+
+@pytest.mark.parametrize("config", ["tiny", "n512"])
+def test_fp32_stage_parity(dev, config):
+    """FP32 block factors (SYRK, Cholesky and W_i = L_i^-1 B_i in FP32 MFMA)
+    against the FP64 oracle's blocks: the componentwise backward-error bounds
+    of _fp32_factor_bounds hold, and the forward differences (printed) are of
+    the order of kappa(M_i) u."""
+    from paper_2412_07731_amd.ahlp import FP32_REFINE, Problem
+    inst = gen.generate(config, 0)
+    print("case fp32 stages", config, flush=True)
+    x, z, _ = point(inst, seed=2)
+    P = Problem(inst)
+    try:
+        P.factor(T(x, dev), T(z, dev), 1e-8, 1e-6, precision=FP32_REFINE)
+        xo = inst.xoff()
+        for i in sorted({0, 1, inst.N // 2, inst.N - 1}):
+            Lg, Wg = P.debug_block(i)
+            A = inst.A[i]
+            D = 1.0 / (z[xo[i]:xo[i + 1]] / x[xo[i]:xo[i + 1]] + 1e-8)
+            left, right = newton.link_cols(inst, i)
+            B = np.hstack([(A * D) @ left.T, (A * D) @ right.T, inst.C[i]])
+            ll, rl, lw, rw, kap = _fp32_factor_bounds(A, D, Lg, Wg, B, 1e-6)
+            Lo = np.linalg.cholesky((A * D) @ A.T + 1e-6 * np.eye(A.shape[0]))
+            print(f"  block {i}: |LL'-M| / bound {float(np.max(ll / np.maximum(rl, 1e-300))):.2e}, "
+                  f"|LW-B| / bound {float(np.max(lw / np.maximum(rw, 1e-300))):.2e}, "
+                  f"kappa_tile {kap:.1f}, forward L {rel(Lg, Lo):.1e}", flush=True)
+            assert np.all(ll <= rl), ("L", i)
+            assert np.all(lw <= rw), ("W", i)
+    finally:
+        P.close()

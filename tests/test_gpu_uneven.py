@@ -7,9 +7,6 @@
 * the N=2048 workload against the FP64 oracle (tests/golden): identical
   iteration count, objective within 1e-8; FP32+refine objective within 1e-8.
 """
-import json
-import os
-
 import numpy as np
 import pytest
 
@@ -18,15 +15,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2412_07731_amd import gen  # noqa: E402
-
-GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_ipm.json")))
-
-
-def golden(config, seed, gondzio=0):
-    for r in GOLDEN["runs"]:
-        if r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio:
-            return r
-    return None
+from tests._parity import check_trajectory, golden  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -74,6 +63,7 @@ def test_uneven_full_size_against_oracle(dev):
         assert r["status"] == 0
         assert r["iterations"] == g["iterations"]
         assert abs(r["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))
+        check_trajectory(P.history(), r, g, "uneven fp64")
         x, y, z, r = P.ipm(precision=FP32_REFINE)
         assert r["status"] == 0
         assert abs(r["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))

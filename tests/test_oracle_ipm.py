@@ -130,3 +130,115 @@ def test_gondzio_corrector_step(tiny):
     assert np.all(v[inside] + r[inside] >= lo * (1 - 1e-8))
     assert np.all(v[inside] + r[inside] <= hi * (1 + 1e-8))
     assert np.all(r >= -hi * (1 + 1e-8))
+
+
+def test_start_point_dual_is_least_squares(tiny):
+    """The second start-point solve gives y~ = (AA')^-1 A c, the least-squares
+    solution of A'y = c (A has full row rank), and the start keeps y0 = y~."""
+    e = np.ones(tiny.n_tot)
+    rowabs, colabs = lp.abs_row_col_sums(tiny)
+    stats = {"pivots": 0, "refine": 0, "bkerr": 0.0}
+    x0, y0, z0 = ipm.starting_point(tiny, rowabs, colabs, ipm.Options(), stats)
+    ls = np.linalg.lstsq(lp.full_matrix(tiny).toarray().T, tiny.c, rcond=None)[0]
+    assert np.max(np.abs(y0 - ls)) <= 1e-11 * np.max(np.abs(ls))
+    # x0 - x~ and z0 - z~ are multiples of e (the shift and the centring move
+    # every entry by the same amount)
+    xt = np.linalg.lstsq(lp.full_matrix(tiny).toarray(), tiny.b, rcond=None)[0]
+    zt = tiny.c - lp.rmatvec(tiny, ls)
+    for a, b in ((x0, xt), (z0, zt)):
+        dv = a - b
+        assert np.max(dv) - np.min(dv) <= 1e-10 * (1 + np.max(np.abs(a)))
+    assert np.all(x0 > 0) and np.all(z0 > 0)
+
+
+def _one_row_lp():
+    """min x1 + 3 x2  s.t.  x1 + x2 = 2,  x >= 0 (one block, no links)."""
+    return gen.Instance(N=1, n0=0, m=np.array([1]), n=np.array([2]), l=np.zeros(0, dtype=np.int64),
+                        A=[np.array([[1.0, 1.0]])], C=[np.zeros((1, 0))], FR=[], FL=[], F0=None,
+                        b=np.array([2.0]), c=np.array([1.0, 3.0]),
+                        xstar=np.array([2.0, 0.0]), ystar=np.array([1.0]),
+                        zstar=np.array([0.0, 2.0]), fstar=2.0)
+
+
+def _newton_one_row(x, z, rd, rp, rz):
+    """The Newton system of Sec. 2.3 for a single equality row a'x = b with
+    a = e, solved by hand: dz = rd - dy e, x_i dz_i + z_i dx_i = rz_i, and
+    sum dx = rp give one scalar equation for dy."""
+    w = (rz - x * rd) / z
+    dy = (rp - np.sum(w)) / np.sum(x / z)
+    dz = rd - dy
+    dx = (rz - x * dz) / z
+    return dx, dy, dz
+
+
+def test_mehrotra_worked_example():
+    """Mehrotra's start and the first predictor-corrector iteration on a
+    one-row LP, computed by hand.  Start: x~ = (1, 1), y~ = 2, z~ = (-1, 1);
+    the shift adds 1.5 to z only (x~ >= 0); x'z = 3 after it, so the centring
+    adds 0.5 * 3 / 3 = 0.5 to x and 0.5 * 3 / 2 = 0.75 to z:
+    x0 = (1.5, 1.5), y0 = 2, z0 = (1.25, 3.25).  The iteration then takes the
+    affine direction, its full-step ratio tests, mu_aff, sigma = (mu_aff/mu)^3,
+    the corrector with sigma mu e - XZe - dXa dZa and steps 0.99 of the
+    largest feasible ones."""
+    inst = _one_row_lp()
+    rowabs, colabs = lp.abs_row_col_sums(inst)
+    stats = {"pivots": 0, "refine": 0, "bkerr": 0.0}
+    x0, y0, z0 = ipm.starting_point(inst, rowabs, colabs, ipm.Options(), stats)
+    assert np.allclose(x0, [1.5, 1.5], rtol=0, atol=1e-12)
+    assert np.allclose(y0, [2.0], rtol=0, atol=1e-12)
+    assert np.allclose(z0, [1.25, 3.25], rtol=0, atol=1e-12)
+
+    # first iteration by hand
+    x, y, z = np.array([1.5, 1.5]), 2.0, np.array([1.25, 3.25])
+    mu = x @ z / 2                                     # 3.375
+    rp = 2.0 - x.sum()
+    rd = np.array([1.0, 3.0]) - y - z
+    dxa, dya, dza = _newton_one_row(x, z, rd, rp, -x * z)
+
+    def step_max(v, dv):
+        neg = dv < 0
+        return np.inf if not neg.any() else float(np.min(-v[neg] / dv[neg]))
+
+    apa, ada = min(1.0, step_max(x, dxa)), min(1.0, step_max(z, dza))
+    mu_aff = (x + apa * dxa) @ (z + ada * dza) / 2
+    sigma = (mu_aff / mu) ** 3
+    dx, dy, dz = _newton_one_row(x, z, rd, rp, sigma * mu - x * z - dxa * dza)
+    ap = min(1.0, 0.99 * step_max(x, dx))
+    ad = min(1.0, 0.99 * step_max(z, dz))
+
+    r = ipm.solve(inst, max_iter=1, keep_iterates=True)
+    h = r.history[0]
+    assert abs(h["mu"] - 3.375) <= 1e-12
+    assert abs(h["mu_aff"] - mu_aff) <= 1e-9 * mu
+    assert abs(h["sigma"] - sigma) <= 1e-8 * sigma
+    assert abs(h["ap"] - ap) <= 1e-9 and abs(h["ad"] - ad) <= 1e-9
+    assert np.allclose(r.x, x + ap * dx, rtol=0, atol=1e-9)
+    assert np.allclose(r.y, [y + ad * dy], rtol=0, atol=1e-9)
+    assert np.allclose(r.z, z + ad * dz, rtol=0, atol=1e-9)
+    # and the method ends at the optimum (2, 0)
+    full = ipm.solve(inst)
+    assert full.status == "optimal" and abs(full.pobj - 2.0) <= 1e-8
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_predictor_backward_error_recorded(seed):
+    """Every history entry carries the predictor's and the corrector's backward
+    errors after refinement, each the largest |r - K d| / (|K| |d| + |r|) its
+    solve reached: recomputed here from the kept iterate for the predictor."""
+    from oracle import newton
+    inst = gen.generate("tiny", seed)
+    r = ipm.solve(inst, keep_iterates=True)
+    rowabs, colabs = lp.abs_row_col_sums(inst)
+    for h in r.history[:4]:
+        x, y, z = h["x"], h["y"], h["z"]
+        rhs = (inst.c - lp.rmatvec(inst, y) - z, inst.b - lp.matvec(inst, x), -x * z)
+        f = newton.factor(inst, x, z, 1e-8, 1e-6)
+        kn = lp.kkt_inf_norm(rowabs, colabs, x, z)
+        st = {"pivots": 0, "refine": 0, "bkerr": 0.0}
+        d, be = ipm.solve_refined(inst, f, rhs, kn, ipm.Options(), st)
+        e = ipm.newton_residual(inst, x, z, rhs, d)
+        be2 = max(np.max(np.abs(v)) for v in e) / (kn * max(np.max(np.abs(v)) for v in d)
+                                                  + max(np.max(np.abs(v)) for v in rhs))
+        assert be == h["bkerr_pred"]
+        assert abs(be2 - be) <= 1e-6 * be + 1e-20
+    assert len(r.solves) == 2 + 2 * r.iterations

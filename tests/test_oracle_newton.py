@@ -258,3 +258,38 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(newton, "schur_solve", flipped)
     assert _dense_pin_fails(inst)
     monkeypatch.undo()
+
+
+def test_late_iterate_forward_difference_is_conditioning():
+    """Why the GPU parity of Newton directions is stated through backward
+    errors and the forward-error bound they imply, not a bare elementwise
+    1e-10: at a late interior-point iterate (mu ~ 5e-7) the oracle's refined
+    block solve and a dense LU solve of the same unregularized Newton system
+    both have small backward errors, yet differ element by element by far more
+    than 1e-10, because K is ill-conditioned.  The difference is the one the
+    two residuals imply: |d1 - d2| <= |K^-1| (|e1| + |e2|) componentwise."""
+    from oracle import dense_kkt, ipm
+    inst = gen.generate("tiny", 0)
+    r = ipm.solve(inst, keep_iterates=True)
+    h = min(r.history, key=lambda q: abs(np.log10(q["mu"] / 5e-7)))
+    x, y, z = h["x"], h["y"], h["z"]
+    rhs = (inst.c - lp.rmatvec(inst, y) - z, inst.b - lp.matvec(inst, x), -x * z)
+    rowabs, colabs = lp.abs_row_col_sums(inst)
+    kn = lp.kkt_inf_norm(rowabs, colabs, x, z)
+    st = {"pivots": 0, "refine": 0, "bkerr": 0.0}
+    d1, be1 = ipm.solve_refined(inst, newton.factor(inst, x, z, 1e-8, 1e-6), rhs, kn,
+                                ipm.Options(), st)
+    d2 = dense_kkt.solve_newton(inst, x, z, *rhs)
+    K = dense_kkt.newton_matrix(inst, x, z)
+    R = np.concatenate(rhs)
+    D1, D2 = np.concatenate(d1), np.concatenate(d2)
+    e1, e2 = R - K @ D1, R - K @ D2
+    be2 = np.max(np.abs(e2)) / (kn * np.max(np.abs(D2)) + np.max(np.abs(R)))
+    assert be1 <= 1e-9 and be2 <= 1e-9
+    fwd = np.max(np.abs(D1 - D2)) / np.max(np.abs(D2))
+    assert fwd > 1e-6                                  # far above 1e-10
+    assert np.linalg.cond(K, np.inf) > 1e8
+    eps = np.finfo(float).eps
+    bound = np.abs(np.linalg.inv(K)) @ (np.abs(e1) + np.abs(e2)
+                                        + 64 * eps * (np.abs(R) + np.abs(K) @ (np.abs(D1) + np.abs(D2))))
+    assert np.all(np.abs(D1 - D2) <= 1.01 * bound)
