@@ -82,9 +82,33 @@ def copy_calibration():
     del src, dst
 
 
+def host_cpu():
+    """CPU model, physical cores and logical CPUs of this host (lscpu)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    try:
+        sockets = int(info.get("Socket(s)", "1"))
+        per = int(info.get("Core(s) per socket", "0"))
+        phys = sockets * per if per else None
+    except ValueError:
+        phys = None
+    return {"model": info.get("Model name"), "physical_cores": phys,
+            "logical_cpus": int(info["CPU(s)"]) if info.get("CPU(s)", "").isdigit() else os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
 def cpu_baseline(inst, iters):
     """The FP64 oracle on the host cores: Mehrotra start plus `iters` iterations
-    of the same instance; iterations/sec."""
+    of the same instance; iterations/sec.  `cores` is the number of BLAS
+    threads the oracle ran with (the threads it actually used); the host's
+    CPU model and physical core count are reported beside it."""
     from threadpoolctl import threadpool_info
     from oracle import ipm as oipm
     t = time.perf_counter()
@@ -93,9 +117,9 @@ def cpu_baseline(inst, iters):
     threads = max((i.get("num_threads", 1) for i in threadpool_info()
                    if "numpy" in i.get("filepath", "")), default=1)
     return {"value": r.iterations / dt, "unit": "IPM iterations/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": f"start point + {r.iterations} iterations of the N=512 instance (seed 0), "
-                      f"{dt:.1f} s; NumPy/SciPy OpenBLAS FP64"}
+                      f"{dt:.1f} s; NumPy/SciPy OpenBLAS FP64 on {int(threads)} threads"}
 
 
 def sens_bench(dev, ndir=64, reps=3):
@@ -175,6 +199,19 @@ def uneven_bench(steps=3):
     out["value"] = its / (time.perf_counter() - t)
     out["iterations"] = r["iterations"]
     out["objective_rel_err_vs_known_optimum"] = abs(r["primal_obj"] - inst.fstar) / abs(inst.fstar)
+    # the same with each iteration's three parts replayed as captured graphs
+    ge = P.ipm(graph=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = 0
+    for _ in range(steps):
+        gx, gy, gz, gr = P.ipm(graph=1)
+        its += gr["iterations"]
+    torch.cuda.synchronize()
+    out["graph"] = {"value": its / (time.perf_counter() - t),
+                    "bitwise_equal_to_eager": bool(torch.equal(gx, x) and torch.equal(gz, z)
+                                                   and gr["iterations"] == r["iterations"])}
+    del ge
     # one factorization (a1-a6) at the end point, batched and per block
     for per_block, reps in ((False, 5), (True, 1)):
         P.set_launch(per_block=per_block)
@@ -232,6 +269,87 @@ def general_bench(golden_runs, steps=3):
         out["oracle_iterations"] = ref[0]["iterations"]
         out["objective_rel_err_vs_oracle"] = abs(f - ref[0]["objective"]) / abs(ref[0]["objective"])
     P.close()
+    return out
+
+
+def fp32_leg(P, inst, fl, args, golden, fp64_rate, fp64_t_asm_ms):
+    """FP32 MFMA blocks (a2-a4) with FP64 refinement on the same instance, timed
+    at the same instrumentation level as the FP64 line (HIP events around the
+    factorization stages), under both acceptance rules for FP32 directions:
+    inexact Newton (|r - K d| <= 0.1 mu) and the plain refinement rule
+    (backward error <= 1e-10 or 5 corrections).  For the first: the Schur
+    assembly rate and the block SYRK against the FP32 peak over the FP32
+    factorizations only, and the stage breakdown of one fully timed solve."""
+    import numpy as np
+    from paper_2412_07731_amd.ahlp import FP32_REFINE
+    out = {"unit": "IPM iterations/s"}
+    xstar_n = 1.0 + float(np.max(np.abs(inst.xstar)))
+    for name, acc in (("inexact_newton", 0.1), ("plain_refinement", -1.0)):
+        dt32, res32 = run(P, args.steps, args.warmup, precision=FP32_REFINE, timing=2,
+                          fp32_accept=acc)
+        it32 = sum(r["iterations"] for r in res32)
+        r32 = res32[-1]
+        x = P.ipm(precision=FP32_REFINE, fp32_accept=acc)[0].cpu().numpy()
+        leg = {"fp32_accept": acc, "value": it32 / dt32,
+               "iterations_per_solve": r32["iterations"], "fp32_iterations": r32["fp32_iterations"],
+               "refine_steps_per_solve": r32["refine_steps"],
+               "converged": all(r["status"] == 0 for r in res32),
+               "objective_rel_err_vs_oracle": (abs(r32["primal_obj"] - golden["pobj"])
+                                               / max(1.0, abs(golden["pobj"])) if golden else None),
+               "x_err_vs_known_optimum": float(np.max(np.abs(x - inst.xstar))) / xstar_n,
+               "speedup_vs_fp64": (it32 / dt32) / fp64_rate}
+        if name == "inexact_newton":
+            s32 = {k: sum(r["t_stage32_ms"][k] for r in res32) for k in r32["t_stage32_ms"]}
+            c32 = {k: sum(r["n_stage32"][k] for r in res32) for k in r32["n_stage32"]}
+            s64 = {k: sum(r["t_stage_ms"][k] for r in res32) for k in r32["t_stage_ms"]}
+            c64 = {k: sum(r["n_stage"][k] for r in res32) for k in r32["n_stage"]}
+            n32 = max(c32["syrk"], 1)
+            # a1-a5 of an FP32 factorization: the D-scaling (same kernel in both
+            # precisions), FP32 SYRK and block factor, FP64 assembly
+            t_asm = s64["prep"] / max(c64["prep"], 1) + (s32["syrk"] + s32["factor"] + s32["schur"]) / n32
+            a24 = fl["syrk"] + fl["potrf"] + fl["trsm"]
+            syrk_ms = s32["syrk"] / n32
+            leg["schur_assembly"] = {
+                "gflop_per_factor": fl["total"] / 1e9, "ms_per_factor": t_asm,
+                "tflops": fl["total"] / (t_asm * 1e-3) / 1e12,
+                "a2_a4_tflops": a24 / ((s32["syrk"] + s32["factor"]) / n32 * 1e-3) / 1e12,
+                "a2_a4_frac_of_fp32_peak": a24 / ((s32["syrk"] + s32["factor"]) / n32 * 1e-3) / 1e12
+                / PEAK_FP32_TFLOPS,
+                "speedup_vs_fp64_t_asm": fp64_t_asm_ms / t_asm,
+                "fp32_factorizations_timed": n32}
+            leg["roofline"] = {"kernel": "k_syrk<float> (block SYRK in FP32 MFMA)", "bound": "mfma",
+                               "achieved": fl["syrk"] / (syrk_ms * 1e-3) / 1e12,
+                               "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                               "frac": fl["syrk"] / (syrk_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                               "traffic": None, "flop_per_launch": fl["syrk"],
+                               "avg_launch_ms": syrk_ms}
+            rfull = run(P, 1, 0, precision=FP32_REFINE, timing=1, fp32_accept=acc)[1][0]
+            leg["stage_ms_per_solve"] = rfull["t_stage_ms"]
+            leg["stage_ms_per_solve_fp32_factorizations"] = {
+                k: v for k, v in rfull["t_stage32_ms"].items() if rfull["n_stage32"][k]}
+        out[name] = leg
+    # the headline figures are the inexact-Newton rule's
+    out["value"] = out["inexact_newton"]["value"]
+    out["speedup_vs_fp64"] = out["inexact_newton"]["speedup_vs_fp64"]
+    return out
+
+
+def graph_leg(P, args, iters_expected):
+    """Each interior-point iteration's three host-synchronization-free parts
+    replayed as captured hipGraphs against eager launches, without event
+    timing (graph mode records none): iterations/s of both, and whether the
+    end points are bitwise equal."""
+    import torch
+    from paper_2412_07731_amd.ahlp import FP64
+    out = {}
+    ends = {}
+    for name, g in (("eager", 0), ("graph", 1)):
+        dt, res = run(P, args.steps, args.warmup, precision=FP64, timing=0, graph=g)
+        out[name] = sum(r["iterations"] for r in res) / dt
+        ends[name] = P.ipm(precision=FP64, graph=g)[:3]
+    out["unit"] = "IPM iterations/s"
+    out["bitwise_equal"] = all(torch.equal(a, b) for a, b in zip(ends["eager"], ends["graph"]))
+    out["graph_speedup"] = out["graph"] / out["eager"]
     return out
 
 
@@ -378,16 +496,8 @@ def main():
              "launches_per_solve": n_rows, "timed": "in the extra fully timed solve"}],
     }
     if not args.profile and not args.fp32:
-        dt32, res32 = run(P, args.steps, args.warmup, precision=FP32_REFINE, timing=0)
-        it32 = sum(r["iterations"] for r in res32)
-        r32 = res32[-1]
-        line["fp32_refine"] = {
-            "value": it32 / dt32, "unit": "IPM iterations/s",
-            "iterations_per_solve": r32["iterations"], "fp32_iterations": r32["fp32_iterations"],
-            "refine_steps": r32["refine_steps"], "converged": all(r["status"] == 0 for r in res32),
-            "objective_rel_err_vs_oracle": (abs(r32["primal_obj"] - golden["pobj"]) / max(1.0, abs(golden["pobj"]))
-                                            if golden else None),
-            "speedup_vs_fp64": (it32 / dt32) / (iters / dt)}
+        line["fp32_refine"] = fp32_leg(P, inst, fl, args, golden, iters / dt, t_asm_ms)
+        line["graph"] = graph_leg(P, args, r0["iterations"])
     if not args.profile and not args.fp32:
         # Gondzio correctors (two at most per iteration): fewer iterations,
         # more solves per factorization; compared by time to solution

@@ -112,7 +112,9 @@ typedef struct {
                           /* once |r - K d|_inf <= fp32_accept * mu (inexact Newton;   */
                           /* 0.1; 0 = only the refine_tol backward error).  FP32 that   */
                           /* cannot reach either test switches the run to FP64 and     */
-                          /* the iteration is redone with FP64 factors.                */
+                          /* the iteration is redone with FP64 factors.  < 0: the      */
+                          /* plain rule of FP64 factors (refine until refine_tol or    */
+                          /* max_refine corrections, then keep the last direction)     */
   int32_t graph;          /* 1 = capture the three parts of an iteration between its */
                           /* host reads (factorization + predictor, corrector, step  */
                           /* + residuals) as hipGraphs once and replay them (results */
@@ -153,6 +155,9 @@ typedef struct {
   int32_t correctors;     /* Gondzio correctors kept over the whole run             */
   double start_bkerr[2];  /* backward errors of the two starting-point solves       */
                           /* after refinement (-1 with opts->start == 1)            */
+  double t_stage32_ms[AHLP_ST_COUNT]; /* the part of t_stage_ms recorded while the   */
+  int32_t n_stage32[AHLP_ST_COUNT];   /* blocks were factored in FP32 (SYRK, FACTOR, */
+                                      /* SCHUR), and its number of timed launches  */
 } ahlp_ipm_result_t;
 
 /* One interior-point iteration of the last ahlp_ipm_solve (see

@@ -50,7 +50,8 @@ class IpmResult(C.Structure):
                 ("max_bkerr", C.c_double), ("t_total_ms", C.c_double),
                 ("t_stage_ms", C.c_double * 8), ("n_stage", C.c_int32 * 8),
                 ("rows_bytes", C.c_double), ("correctors", C.c_int32),
-                ("start_bkerr", C.c_double * 2)]
+                ("start_bkerr", C.c_double * 2), ("t_stage32_ms", C.c_double * 8),
+                ("n_stage32", C.c_int32 * 8)]
 
 
 class IpmIter(C.Structure):
@@ -258,8 +259,10 @@ class Problem:
                                     _stream(stream))
         _check(code, allow_warn=True)
         res = {f: getattr(r, f) for f, _ in IpmResult._fields_
-               if f not in ("t_stage_ms", "n_stage", "start_bkerr")}
+               if f not in ("t_stage_ms", "n_stage", "start_bkerr", "t_stage32_ms", "n_stage32")}
         res["start_bkerr"] = [r.start_bkerr[0], r.start_bkerr[1]]
+        res["t_stage32_ms"] = {STAGES[i]: r.t_stage32_ms[i] for i in range(8)}
+        res["n_stage32"] = {STAGES[i]: r.n_stage32[i] for i in range(8)}
         res["status_name"] = STATUS.get(code, str(code))
         res["t_stage_ms"] = {STAGES[i]: r.t_stage_ms[i] for i in range(8)}
         res["n_stage"] = {STAGES[i]: r.n_stage[i] for i in range(8)}

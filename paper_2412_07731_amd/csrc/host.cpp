@@ -76,12 +76,15 @@ struct StageTimer {
   bool on = false;
   unsigned mask = ~0u;        // stages recorded while on (bit per AHLP_ST_*)
   hipStream_t st = nullptr;
-  struct Rec { int stage; hipEvent_t a, b; };
+  bool f32 = false;           // stages recorded now belong to an FP32 factorization
+  struct Rec { int stage; bool f32; hipEvent_t a, b; };
   std::vector<Rec> pending;
   std::vector<size_t> open;   // indices into pending of records not yet ended (nesting)
   std::vector<hipEvent_t> pool;
   double ms[AHLP_ST_COUNT] = {0};
   int cnt[AHLP_ST_COUNT] = {0};
+  double ms32[AHLP_ST_COUNT] = {0};   // the part of ms recorded with f32 set
+  int cnt32[AHLP_ST_COUNT] = {0};
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -99,7 +102,7 @@ struct StageTimer {
       open.push_back(SIZE_MAX);
       return;
     }
-    Rec r{stage, get(), get()};
+    Rec r{stage, f32, get(), get()};
     (void)hipEventRecord(r.a, st);
     open.push_back(pending.size());
     pending.push_back(r);
@@ -117,6 +120,10 @@ struct StageTimer {
       if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
         ms[r.stage] += t;
         cnt[r.stage] += 1;
+        if (r.f32) {
+          ms32[r.stage] += t;
+          cnt32[r.stage] += 1;
+        }
       }
       pool.push_back(r.a);
       pool.push_back(r.b);
@@ -125,7 +132,7 @@ struct StageTimer {
   }
   void reset() {
     collect();
-    for (int i = 0; i < AHLP_ST_COUNT; ++i) { ms[i] = 0; cnt[i] = 0; }
+    for (int i = 0; i < AHLP_ST_COUNT; ++i) { ms[i] = 0; cnt[i] = 0; ms32[i] = 0; cnt32[i] = 0; }
   }
   ~StageTimer() {
     for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -150,6 +157,17 @@ struct SegKey {
     return x == o.x && y == o.y && z == o.z && rho == o.rho && delta == o.delta &&
            eta == o.eta && launch_gen == o.launch_gen;
   }
+};
+
+// Device workspace of one refined Newton solve (Alg. 3 with the refinement
+// loop): the solve-phase vectors, the Schur-solve vectors of either Schur
+// path, the refinement residual and correction, the reduction partials and
+// the scalar slots.
+struct SolveWs {
+  double *rhx, *vx, *tv, *qn, *s, *w, *u, *dyp, *g, *part, *segrhs, *xp;
+  double *br, *bw, *bup, *bpb, *bu0p;
+  double *ex, *ey, *ez, *cx, *cy, *cz, *gc;
+  double *red_part, *scal;
 };
 
 struct ahlp_problem_s {
@@ -209,32 +227,26 @@ struct ahlp_problem_s {
   int t0 = 0, s00_chunk = 16, s00_parts = 0;
   double *BD = nullptr, *BC = nullptr, *BEt = nullptr, *FLi = nullptr, *FXL = nullptr,
          *FXR = nullptr, *FGt = nullptr, *FLb = nullptr, *FLbi = nullptr, *s00part = nullptr;
-  double *br = nullptr, *bw = nullptr, *bup = nullptr, *bpb = nullptr, *bu0p = nullptr;
-  DevInfo* info = nullptr;   // lives in the last slot of scal
+  DevInfo* info = nullptr;   // lives in the last slot of the handle's own ws.scal
   bool factored = false;
   int fprec = AHLP_FP64;
   double rho = 0, delta = 0;
   int pivots_seen = 0;
 
-  // solve workspace
-  double *rhx = nullptr, *vx = nullptr, *tv = nullptr, *qn = nullptr, *s = nullptr, *w = nullptr,
-         *u = nullptr, *dyp = nullptr, *g = nullptr, *part = nullptr, *segrhs = nullptr,
-         *aty = nullptr, *gdir = nullptr,
-         *xp = nullptr;
-  // refinement / driver workspace
-  double *ex = nullptr, *ey = nullptr, *ez = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;
+  // workspace of a refined solve (one allocation at create)
+  SolveWs ws{};
+  double *aty = nullptr, *gdir = nullptr;
   double *ones = nullptr, *zerosn = nullptr;
   // predictor/corrector right-hand sides by linearity (padded v-space) and scaled vectors
   double *ta = nullptr, *aw1 = nullptr, *aw2 = nullptr, *tc = nullptr, *w1p = nullptr,
-         *w2p = nullptr, *gc = nullptr;
+         *w2p = nullptr;
   double* adj_rz = nullptr;   // z g_z of the transposed solve
   double *grad_g = nullptr, *grad_wz = nullptr;   // ahlp_lp_gradient: its right-hand side, w_z
   // Gondzio correctors: right-hand side, candidate direction, zero y-vector
   double *g_r = nullptr, *g_dx = nullptr, *g_dy = nullptr, *g_dz = nullptr, *zerosm = nullptr;
   double *rp = nullptr, *rd = nullptr, *rzv = nullptr, *dxa = nullptr, *dya = nullptr,
          *dza = nullptr, *dx = nullptr, *dy = nullptr, *dz = nullptr;
-  double *red_part = nullptr, *scal = nullptr;
-  double* h_scal = nullptr;   // pinned host mirror of scal
+  double* h_scal = nullptr;   // pinned host mirror of ws.scal
   // side stream (default priority) for the link-column gather, which runs
   // beside the block SYRK: event fork from the caller's stream, join before
   // the block factor
@@ -286,6 +298,35 @@ ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
   p->pivots_seen = h.pivots;
   if (nonfinite) *nonfinite = h.nonfinite != 0;
   return AHLP_OK;
+}
+
+// Places the workspace of one refined solve at base (256-byte aligned
+// pieces, each at least one element) and returns its size in bytes; with
+// base == nullptr only the size.
+size_t solve_ws_layout(const ahlp_problem_s* p, double* base, SolveWs* ws) {
+  size_t off = 0;   // bytes
+  auto take = [&](double** dst, long long count) {
+    if (count < 1) count = 1;
+    if (base && ws) *dst = reinterpret_cast<double*>(reinterpret_cast<char*>(base) + off);
+    off += ((size_t)count * sizeof(double) + 255) / 256 * 256;
+  };
+  SolveWs tmp{};
+  SolveWs& w = ws ? *ws : tmp;
+  const long long n = p->n_tot, m = p->m_tot, nb = p->nl + p->n0;
+  take(&w.rhx, n); take(&w.vx, p->dp_total); take(&w.xp, p->dp_total);
+  take(&w.tv, p->vp_total); take(&w.dyp, p->vp_total); take(&w.qn, p->q_total);
+  take(&w.s, nb); take(&w.w, nb); take(&w.u, nb);
+  take(&w.g, n); take(&w.part, (long long)p->N * std::max(p->n0, 1));
+  take(&w.segrhs, (long long)std::max(p->G, 1) * SEGRHS_STRIDE);
+  take(&w.ex, n); take(&w.ey, m); take(&w.ez, n);
+  take(&w.cx, n); take(&w.cy, m); take(&w.cz, n); take(&w.gc, n);
+  take(&w.red_part, (long long)MAXRED * RED_PARTIALS); take(&w.scal, NSCAL);
+  if (p->fast) {
+    const long long Pt = std::max(p->P, 1), T0 = std::max(p->t0, 1), tp = p->tp;
+    take(&w.br, Pt * tp * 16); take(&w.bw, Pt * tp * 16); take(&w.bup, Pt * tp * 16);
+    take(&w.bpb, Pt * T0 * 16); take(&w.bu0p, T0 * 16);
+  }
+  return off;
 }
 
 // ------------------------------------------------------------- factor
@@ -436,6 +477,7 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
   p->delta = delta;
   p->fprec = prec;
   if (!prepped) CHK(prep_scaling(p, x, z, rho, st));
+  p->timer.f32 = prec == AHLP_FP32_REFINE;
   if (prec == AHLP_FP32_REFINE) {
     CHK(ensure_fp32(p, st));
     CHK(factor_blocks<float>(p, st, p->LB32, p->LINV32, p->A32));
@@ -447,6 +489,7 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
                   p->F0, p->d_loff, delta, p->Dp + p->d0off, p->Td, p->To, p->E, p->S00,
                   p->thrT);
   p->timer.end();
+  p->timer.f32 = false;
   p->timer.begin(AHLP_ST_TFACTOR);
   if (p->fast) launch_bcr_factor(st, bcr_args(p), p->s00_parts, p->s00_chunk);
   else launch_chain_factor(st, chain_args(p));
@@ -489,16 +532,16 @@ ahlp_status_t run_segment(ahlp_problem_t p, int id, const SegKey& key, hipStream
 }
 
 // ------------------------------------------------------------- solve
-// One pass of Alg. 3 (no refinement).  Also leaves g = A' dy in p->g.
+// One pass of Alg. 3 (no refinement).  Also leaves g = A' dy in p->ws.g.
 template <typename T>
 void solve_blocks_fwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV,
                       const double* tin) {
-  launch_block_fwd<T>(st, p->blk, p->N, p->max_rt, LB, LINV, tin, p->tv, p->qn);
+  launch_block_fwd<T>(st, p->blk, p->N, p->max_rt, LB, LINV, tin, p->ws.tv, p->ws.qn);
 }
 template <typename T>
 void solve_blocks_bwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV, double* dy) {
-  launch_block_bwd<T>(st, p->blk, p->N, p->n0, p->nl, p->max_rt, LB, LINV, p->tv, p->u, dy,
-                      p->dyp);
+  launch_block_bwd<T>(st, p->blk, p->N, p->n0, p->nl, p->max_rt, LB, LINV, p->ws.tv, p->ws.u, dy,
+                      p->ws.dyp);
 }
 
 // A row pass (AHLP_ST_AROWS) with its algorithmic bytes: the A tiles, the C
@@ -530,45 +573,45 @@ void rows_pass1(ahlp_problem_t p, const double* v, const double* base, double al
 }
 
 // tpre: precomputed t = r_y + A D rhx (padded v-space) or null; gout receives
-// g = A' dy (default p->g).
+// g = A' dy (default p->ws.g).
 ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
                          double* dx, double* dy, double* dz, hipStream_t st,
                          const double* tpre = nullptr, double* gout = nullptr) {
-  if (!gout) gout = p->g;
+  if (!gout) gout = p->ws.g;
   const bool f32 = p->fprec == AHLP_FP32_REFINE;
   p->timer.begin(AHLP_ST_SOLVE);
-  launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->xs, p->Dp, p->rhx, p->vx);
+  launch_rhx(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->xs, p->Dp, p->ws.rhx, p->ws.vx);
   // t_i = ry_i + A_i D_i rhx_i (padded), s_L = ry_L + F D rhx
   if (!tpre) {
-    rows_pass1(p, p->vx, ry, 1.0, 0, 1, p->tv, st);
-    tpre = p->tv;
+    rows_pass1(p, p->ws.vx, ry, 1.0, 0, 1, p->ws.tv, st);
+    tpre = p->ws.tv;
   }
-  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->vx,
-                  nullptr, nullptr, ry + p->mblk, 1.0, p->s);
+  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.vx,
+                  nullptr, nullptr, ry + p->mblk, 1.0, p->ws.s);
   if (f32) solve_blocks_fwd<float>(p, st, p->LB32, p->LINV32, tpre);
   else solve_blocks_fwd<double>(p, st, p->LB, p->LINV, tpre);
-  launch_schur_rhs(st, p->blk, p->N, p->n0, p->d_l, p->d_loff, p->nl, p->qn, p->rhx + p->x0off,
-                   p->s);
+  launch_schur_rhs(st, p->blk, p->N, p->n0, p->d_l, p->d_loff, p->nl, p->ws.qn, p->ws.rhx + p->x0off,
+                   p->ws.s);
   if (p->fast) {
     BcrSolveArgs a{};
     a.c = bcr_args(p);
-    a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.u = p->u;
-    a.r = p->br; a.w = p->bw; a.up = p->bup; a.pb = p->bpb; a.u0p = p->bu0p;
+    a.loff = p->d_loff; a.nl = p->nl; a.s = p->ws.s; a.u = p->ws.u;
+    a.r = p->ws.br; a.w = p->ws.bw; a.up = p->ws.bup; a.pb = p->ws.bpb; a.u0p = p->ws.bu0p;
     launch_bcr_solve(st, a);
   } else {
     ChainSolveArgs a{};
     a.c = chain_args(p);
-    a.loff = p->d_loff; a.nl = p->nl; a.s = p->s; a.w = p->w; a.u = p->u; a.segrhs = p->segrhs;
+    a.loff = p->d_loff; a.nl = p->nl; a.s = p->ws.s; a.w = p->ws.w; a.u = p->ws.u; a.segrhs = p->ws.segrhs;
     launch_chain_solve(st, a);
   }
   if (f32) solve_blocks_bwd<float>(p, st, p->LB32, p->LINV32, dy);
   else solve_blocks_bwd<double>(p, st, p->LB, p->LINV, dy);
   // dx_i = D_i (A_i' dy_i + F_i' dy_L - rhx_i), dz = (rz - Z dx) / X;  g = A' dy
   const DzArgs dzv{rz, p->zs, p->xs, dz};
-  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, p->u, p->cptr, p->crow, p->cval, 2,
-              p->rhx, nullptr, p->Dp, gout, dx, dzv);
-  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
-  launch_solve_tail(st, p->N, p->n0, p->nl, p->part, p->F0, p->u, p->x0off, p->mblk, gout, dx, dzv,
+  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->ws.dyp, p->ws.u, p->cptr, p->crow, p->cval, 2,
+              p->ws.rhx, nullptr, p->Dp, gout, dx, dzv);
+  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
+  launch_solve_tail(st, p->N, p->n0, p->nl, p->ws.part, p->F0, p->ws.u, p->x0off, p->mblk, gout, dx, dzv,
                     dy);
   p->timer.end();
   HIPCHK(hipGetLastError());
@@ -578,38 +621,38 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
 // g = A' y (canonical), using the padded copy of the block rows.
 void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
               const double* zvec, double* out, hipStream_t st) {
-  launch_pad_y(st, p->blk, p->N, y, p->dyp);
-  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, y + p->mblk, p->cptr, p->crow,
+  launch_pad_y(st, p->blk, p->N, y, p->ws.dyp);
+  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->ws.dyp, y + p->mblk, p->cptr, p->crow,
               p->cval, mode, cvec, zvec, p->Dp, mode == 0 ? out : nullptr,
               mode == 0 ? nullptr : out);
-  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
-  launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
+  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
+  launch_x0_sum(st, p->N, p->n0, p->nl, p->ws.part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
                 mode == 0 ? out : nullptr, mode == 0 ? nullptr : out);
 }
 
 // rd = cvec - A'y - zvec, and g = A'y kept in gout (one column pass)
 void apply_At_both(ahlp_problem_t p, const double* y, const double* cvec, const double* zvec,
                    double* rd, double* gout, hipStream_t st) {
-  launch_pad_y(st, p->blk, p->N, y, p->dyp);
-  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->dyp, y + p->mblk, p->cptr, p->crow,
+  launch_pad_y(st, p->blk, p->N, y, p->ws.dyp);
+  launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->ws.dyp, y + p->mblk, p->cptr, p->crow,
               p->cval, 1, cvec, zvec, p->Dp, gout, rd);
-  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->dyp, p->part);
-  launch_x0_sum(st, p->N, p->n0, p->nl, p->part, p->F0, y + p->mblk, 1, cvec, zvec, p->x0off,
+  launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
+  launch_x0_sum(st, p->N, p->n0, p->nl, p->ws.part, p->F0, y + p->mblk, 1, cvec, zvec, p->x0off,
                 gout, rd);
 }
 
 // out = base + alpha * A x (canonical)
 void apply_A(ahlp_problem_t p, const double* x, const double* base, double alpha, double* out,
              hipStream_t st) {
-  launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->xp, nullptr);
-  rows_pass1(p, p->xp, base, alpha, 1, 0, out, st);
-  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
-                  p->xp + p->d0off, p->F0, base ? base + p->mblk : nullptr, alpha, out + p->mblk);
+  launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->ws.xp, nullptr);
+  rows_pass1(p, p->ws.xp, base, alpha, 1, 0, out, st);
+  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.xp,
+                  p->ws.xp + p->d0off, p->F0, base ? base + p->mblk : nullptr, alpha, out + p->mblk);
 }
 
 ahlp_status_t read_scal(ahlp_problem_t p, int count, hipStream_t st) {
   (void)count;   // the whole slot array (incl. the device info) is copied
-  HIPCHK(hipMemcpyAsync(p->h_scal, p->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(p->h_scal, p->ws.scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   p->timer.collect();
   return AHLP_OK;
@@ -618,7 +661,7 @@ ahlp_status_t read_scal(ahlp_problem_t p, int count, hipStream_t st) {
 void red(ahlp_problem_t p, int op, long long n, const double* a, const double* b, int slot,
          hipStream_t st, const double* c = nullptr, const double* d = nullptr, double s1 = 0,
          double s2 = 0) {
-  launch_reduce(st, op, n, a, b, c, d, s1, s2, p->red_part, p->scal + slot);
+  launch_reduce(st, op, n, a, b, c, d, s1, s2, p->ws.red_part, p->ws.scal + slot);
 }
 
 // Batches independent reductions into one pair of launches.
@@ -626,8 +669,8 @@ struct Reds {
   MultiRed m{};
   Reds(ahlp_problem_t p) {
     m.nred = 0;
-    m.partial = p->red_part;
-    m.out = p->scal;
+    m.partial = p->ws.red_part;
+    m.out = p->ws.scal;
   }
   Reds& add(int op, long long n, const double* a, const double* b, int slot,
             const double* c = nullptr, const double* d = nullptr, double s1 = 0, double s2 = 0) {
@@ -639,24 +682,24 @@ struct Reds {
 };
 
 // Refinement check of d = (dx, dy, dz) against r = (rx, ry, rz) on the
-// unregularized Newton system (p->g holds A'dy):  ex = rx - g - dz,
+// unregularized Newton system (p->ws.g holds A'dy):  ex = rx - g - dz,
 // ey = ry - A dx, ez = rz - Z dx - X dz.  With w2 the same row pass also
 // forms aw2 = A (D dx dz / x) (the corrector's right-hand-side term).
 void check_pass(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
                 const double* dx, const double* dz, bool w2, hipStream_t st) {
   p->timer.begin(AHLP_ST_RESID);
-  launch_check_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->g, dx, dz, p->xs,
-                    p->zs, p->Dp, p->ex, p->ez, p->xp, w2 ? p->w2p : nullptr);
+  launch_check_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->ws.g, dx, dz, p->xs,
+                    p->zs, p->Dp, p->ws.ex, p->ws.ez, p->ws.xp, w2 ? p->w2p : nullptr);
   RowsArgs ra{};
   ra.nv = 1;
-  ra.v[0] = p->xp; ra.base[0] = ry; ra.alpha[0] = -1.0; ra.out[0] = p->ey; ra.with_C[0] = 1;
+  ra.v[0] = p->ws.xp; ra.base[0] = ry; ra.alpha[0] = -1.0; ra.out[0] = p->ws.ey; ra.with_C[0] = 1;
   if (w2) {
     ra.nv = 2;
     ra.v[1] = p->w2p; ra.alpha[1] = 1.0; ra.out[1] = p->aw2; ra.padded[1] = 1;
   }
   rows_pass(p, ra, st);
-  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
-                  p->xp + p->d0off, p->F0, ry + p->mblk, -1.0, p->ey + p->mblk);
+  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.xp,
+                  p->ws.xp + p->d0off, p->F0, ry + p->mblk, -1.0, p->ws.ey + p->mblk);
   p->timer.end();
 }
 
@@ -664,8 +707,8 @@ void check_pass(ahlp_problem_t p, const double* rx, const double* ry, const doub
 void add_check_reds(ahlp_problem_t p, Reds& R, const double* rx, const double* ry,
                     const double* rz, const double* dx, const double* dy, const double* dz,
                     bool first) {
-  R.add(RED_MAXABS, p->n_tot, p->ex, nullptr, S_EN).add(RED_MAXABS, p->m_tot, p->ey, nullptr, S_EN + 1)
-      .add(RED_MAXABS, p->n_tot, p->ez, nullptr, S_EN + 2).add(RED_MAXABS, p->n_tot, dx, nullptr, S_DN)
+  R.add(RED_MAXABS, p->n_tot, p->ws.ex, nullptr, S_EN).add(RED_MAXABS, p->m_tot, p->ws.ey, nullptr, S_EN + 1)
+      .add(RED_MAXABS, p->n_tot, p->ws.ez, nullptr, S_EN + 2).add(RED_MAXABS, p->n_tot, dx, nullptr, S_DN)
       .add(RED_MAXABS, p->m_tot, dy, nullptr, S_DN + 1).add(RED_MAXABS, p->n_tot, dz, nullptr, S_DN + 2);
   if (first)
     R.add(RED_MAXABS, p->n_tot, rx, nullptr, S_RN).add(RED_MAXABS, p->m_tot, ry, nullptr, S_RN + 1)
@@ -700,11 +743,11 @@ ahlp_status_t refine(ahlp_problem_t p, const double* rx, const double* ry, const
                      double abs_tol = 0.0, bool stagnate = false) {
   while (*be > tol && !(abs_tol > 0.0 && check_en(p) <= abs_tol) && *steps < max_refine) {
     const double be_prev = *be;
-    CHK(solve_once(p, p->ex, p->ey, p->ez, p->cx, p->cy, p->cz, st, nullptr, p->gc));
-    launch_axpy(st, p->n_tot, 1.0, p->cx, dx);
-    launch_axpy(st, p->m_tot, 1.0, p->cy, dy);
-    launch_axpy(st, p->n_tot, 1.0, p->cz, dz);
-    launch_axpy(st, p->n_tot, 1.0, p->gc, p->g);
+    CHK(solve_once(p, p->ws.ex, p->ws.ey, p->ws.ez, p->ws.cx, p->ws.cy, p->ws.cz, st, nullptr, p->ws.gc));
+    launch_axpy(st, p->n_tot, 1.0, p->ws.cx, dx);
+    launch_axpy(st, p->m_tot, 1.0, p->ws.cy, dy);
+    launch_axpy(st, p->n_tot, 1.0, p->ws.cz, dz);
+    launch_axpy(st, p->n_tot, 1.0, p->ws.gc, p->ws.g);
     check_pass(p, rx, ry, rz, dx, dz, w2, st);
     Reds R(p);
     add_check_reds(p, R, rx, ry, rz, dx, dy, dz, false);
@@ -745,7 +788,7 @@ ahlp_status_t solve_refined(ahlp_problem_t p, const double* rx, const double* ry
 
 ahlp_status_t kkt_norm(ahlp_problem_t p, hipStream_t st, double* out) {
   red(p, RED_MAXSUM, p->n_tot, p->xs, p->zs, 9, st);
-  HIPCHK(hipMemcpyAsync(p->h_scal + 9, p->scal + 9, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(p->h_scal + 9, p->ws.scal + 9, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   *out = std::max(p->colabs1_max, std::max(p->rowabs_max, p->h_scal[9]));
   return AHLP_OK;
@@ -1122,9 +1165,6 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     for (double** v : {&p->BD, &p->BC, &p->FLi, &p->FXL, &p->FXR}) CHK(M.alloc(v, Pt * tp * tp * 256));
     CHK(M.alloc(&p->BEt, Pt * tp * T0 * 256));
     CHK(M.alloc(&p->FGt, Pt * tp * T0 * 256));
-    for (double** v : {&p->br, &p->bw, &p->bup}) CHK(M.alloc(v, Pt * tp * 16));
-    CHK(M.alloc(&p->bpb, Pt * T0 * 16));
-    CHK(M.alloc(&p->bu0p, T0 * 16));
     CHK(M.alloc(&p->s00part, (long long)(p->s00_parts + 1) * std::max(p->t0 * p->t0, 1) * 256));
     CHK(M.alloc(&p->FLb, (long long)std::max(p->t0 * p->t0, 1) * 256));
     CHK(M.alloc(&p->FLbi, (long long)std::max(p->t0 * p->t0, 1) * 256));
@@ -1134,28 +1174,17 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     CHK(M.alloc(&p->segout, (long long)std::max(p->G, 1) * SEG_STRIDE));
   }
 
-  CHK(M.alloc(&p->rhx, p->n_tot));
-  CHK(M.alloc(&p->vx, p->dp_total));
-  CHK(M.alloc(&p->xp, p->dp_total));
-  CHK(M.alloc(&p->tv, p->vp_total));
-  CHK(M.alloc(&p->dyp, p->vp_total));
-  CHK(M.alloc(&p->qn, p->q_total));
-  CHK(M.alloc(&p->s, p->nl + n0));
-  CHK(M.alloc(&p->w, p->nl + n0));
-  CHK(M.alloc(&p->u, p->nl + n0));
-  CHK(M.alloc(&p->g, p->n_tot));
-  CHK(M.alloc(&p->part, (long long)N * std::max(n0, 1)));
-  CHK(M.alloc(&p->segrhs, (long long)std::max(p->G, 1) * SEGRHS_STRIDE));
-  for (double** v : {&p->ex, &p->ez, &p->cx, &p->cz, &p->ones, &p->zerosn, &p->rd, &p->rzv,
-                     &p->dxa, &p->dza, &p->dx, &p->dz})
+  {
+    double* wsbuf = nullptr;
+    CHK(M.alloc(&wsbuf, (long long)(solve_ws_layout(p, nullptr, nullptr) / sizeof(double))));
+    solve_ws_layout(p, wsbuf, &p->ws);
+  }
+  p->info = reinterpret_cast<DevInfo*>(p->ws.scal + NSCAL - 1);
+  for (double** v : {&p->ones, &p->zerosn, &p->rd, &p->rzv, &p->dxa, &p->dza, &p->dx, &p->dz})
     CHK(M.alloc(v, p->n_tot));
-  for (double** v : {&p->ey, &p->cy, &p->rp, &p->dya, &p->dy}) CHK(M.alloc(v, p->m_tot));
-  CHK(M.alloc(&p->red_part, (long long)MAXRED * RED_PARTIALS));
-  CHK(M.alloc(&p->scal, NSCAL));
-  p->info = reinterpret_cast<DevInfo*>(p->scal + NSCAL - 1);
+  for (double** v : {&p->rp, &p->dya, &p->dy}) CHK(M.alloc(v, p->m_tot));
   for (double** v : {&p->ta, &p->aw1, &p->aw2, &p->tc}) CHK(M.alloc(v, p->vp_total));
   for (double** v : {&p->w1p, &p->w2p}) CHK(M.alloc(v, p->dp_total));
-  CHK(M.alloc(&p->gc, p->n_tot));
   CHK(M.alloc(&p->aty, p->n_tot));
   CHK(M.alloc(&p->gdir, p->n_tot));
   CHK(M.alloc(&p->adj_rz, p->n_tot));
@@ -1237,11 +1266,12 @@ ahlp_status_t ahlp_kkt_factor(ahlp_problem_t p, const double* x, const double* z
   return do_factor(p, x, z, prec, rho, delta, st);
 }
 
-ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* ry,
+namespace {
+// ahlp_kkt_solve on the handle's current workspace p->ws.
+ahlp_status_t kkt_solve_impl(ahlp_problem_t p, const double* rx, const double* ry,
                              const double* rz, double* dx, double* dy, double* dz,
                              int32_t max_refine, double refine_tol, double* bkerr,
                              hipStream_t st) {
-  g_err.clear();
   if (!p || !rx || !ry || !rz || !dx || !dy || !dz) return fail(AHLP_EINVAL, "null argument");
   if (!p->factored) return fail(AHLP_ESTATE, "solve before factor");
   p->timer.st = st;
@@ -1254,6 +1284,15 @@ ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* r
     return solve_refined(p, rx, ry, rz, dx, dy, dz, max_refine, refine_tol, kn, bkerr, nullptr, st);
   }
   return solve_once(p, rx, ry, rz, dx, dy, dz, st);
+}
+}  // namespace
+
+ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* ry,
+                             const double* rz, double* dx, double* dy, double* dz,
+                             int32_t max_refine, double refine_tol, double* bkerr,
+                             hipStream_t st) {
+  g_err.clear();
+  return kkt_solve_impl(p, rx, ry, rz, dx, dy, dz, max_refine, refine_tol, bkerr, st);
 }
 
 ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double* gy,
@@ -1546,7 +1585,7 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   // residuals of the current iterate (the start of every iteration).  A'y is
   // kept in p->aty: formed by a column pass at the start (full), then
   // advanced with each step, A'y+ = A'y + alpha_d A'dy, where A'dy is the
-  // solve's own column pass (p->g, refinement corrections included)
+  // solve's own column pass (p->ws.g, refinement corrections included)
   auto resid_stage = [&](bool full) -> ahlp_status_t {
     p->timer.begin(AHLP_ST_RESID);
     CHK(prep_scaling(p, x, z, o->rho, st));
@@ -1554,17 +1593,17 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     else launch_rd(st, n, p->c, p->aty, z, p->rd);
     // rz_a = -x z, rhx_a, vx = D rhx_a, w1 = D / x, xp = x (padded)
     launch_resid_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, p->rd, p->xs, p->Dp,
-                      p->rzv, p->rhx, p->vx, p->w1p, p->xp);
+                      p->rzv, p->ws.rhx, p->ws.vx, p->w1p, p->ws.xp);
     {
       RowsArgs ra{};
       ra.nv = 3;
-      ra.v[0] = p->xp; ra.base[0] = p->b; ra.alpha[0] = -1.0; ra.out[0] = p->rp; ra.with_C[0] = 1;
-      ra.v[1] = p->vx; ra.alpha[1] = 1.0; ra.out[1] = p->ta; ra.padded[1] = 1; ra.chain[1] = 1;
+      ra.v[0] = p->ws.xp; ra.base[0] = p->b; ra.alpha[0] = -1.0; ra.out[0] = p->rp; ra.with_C[0] = 1;
+      ra.v[1] = p->ws.vx; ra.alpha[1] = 1.0; ra.out[1] = p->ta; ra.padded[1] = 1; ra.chain[1] = 1;
       ra.v[2] = p->w1p; ra.alpha[2] = 1.0; ra.out[2] = p->aw1; ra.padded[2] = 1;
       rows_pass(p, ra, st);
     }
-    launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->xp,
-                    p->xp + p->d0off, p->F0, p->b + p->mblk, -1.0, p->rp + p->mblk);
+    launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.xp,
+                    p->ws.xp + p->d0off, p->F0, p->b + p->mblk, -1.0, p->rp + p->mblk);
     Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, p->c, x, 1).add(RED_DOT, m, p->b, y, 2)
         .add(RED_MAXABS, m, p->rp, nullptr, 3).add(RED_MAXABS, n, p->rd, nullptr, 4)
         .add(RED_MAXSUM, n, x, z, 5).launch(st);
@@ -1575,8 +1614,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   // iteration's residuals
   auto step_resid = [&]() -> ahlp_status_t {
     launch_steps(st, o->eta, StepSet{4, {n, m, n, n},
-                                     {p->scal + S_AP, p->scal + S_AD, p->scal + S_AD, p->scal + S_AD},
-                                     {p->dx, p->dy, p->dz, p->g}, {x, y, z, p->aty}});
+                                     {p->ws.scal + S_AP, p->ws.scal + S_AD, p->ws.scal + S_AD, p->ws.scal + S_AD},
+                                     {p->dx, p->dy, p->dz, p->ws.g}, {x, y, z, p->aty}});
     return resid_stage(false);
   };
   CHK(resid_stage(true));
@@ -1613,7 +1652,11 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       *ok = true;
       const int prec = f32 ? AHLP_FP32_REFINE : AHLP_FP64;
       if (prec == AHLP_FP32_REFINE) CHK(ensure_fp32(p, st));   // allocates: before any capture
-      const double atol = f32 ? o->fp32_accept * mu : 0.0;
+      // fp32_accept < 0: the plain refinement rule for FP32 factors too
+      // (backward error <= refine_tol or max_refine corrections, then the
+      // last direction is kept, as with FP64 factors)
+      const bool plain = f32 && o->fp32_accept < 0.0;
+      const double atol = (f32 && !plain) ? o->fp32_accept * mu : 0.0;
       auto acceptable = [&](double b) {
         return b <= o->refine_tol || (atol > 0.0 && check_en(p) <= atol);
       };
@@ -1622,8 +1665,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       auto muaff_launch = [&]() {
         Reds Rm(p);
         Rm.add(RED_MUAFF, n, x, p->dxa, S_MUAFF, z, p->dza);
-        Rm.m.r[0].ps1 = p->scal + S_AP;
-        Rm.m.r[0].ps2 = p->scal + S_AD;
+        Rm.m.r[0].ps1 = p->ws.scal + S_AP;
+        Rm.m.r[0].ps2 = p->ws.scal + S_AD;
         Rm.launch(st);
       };
       // factorization and predictor (rz_a = -x z; t_a from the residual pass),
@@ -1648,8 +1691,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       be = check_bkerr(p, kn, rn);
       if (!acceptable(be)) {
         CHK(refine(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine, o->refine_tol,
-                   kn, rn, true, &be, &steps, st, atol, f32));
-        if (f32 && !acceptable(be)) {
+                   kn, rn, true, &be, &steps, st, atol, f32 && !plain));
+        if (f32 && !plain && !acceptable(be)) {
           refine_total += steps;   // spent, although the pass is redone in FP64
           *ok = false;
           return AHLP_OK;
@@ -1665,9 +1708,9 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       // corrector: sigma mu on the device, rz_c and
       // t_c = t_a - sigma mu A(D/x) + A(D dxa dza / x), solve, check, step lengths
       CHK(run_segment(p, f32 ? SEG_B32 : SEG_B64, key, st, [&]() -> ahlp_status_t {
-        launch_sigma_mu(st, p->scal, n, 0, S_MUAFF, S_SMU);
-        launch_rz(st, n, 1, x, z, p->dxa, p->dza, 0.0, p->rzv, p->scal + S_SMU);
-        launch_combine(st, p->vp_total, p->ta, 0.0, p->aw1, p->aw2, p->tc, p->scal + S_SMU);
+        launch_sigma_mu(st, p->ws.scal, n, 0, S_MUAFF, S_SMU);
+        launch_rz(st, n, 1, x, z, p->dxa, p->dza, 0.0, p->rzv, p->ws.scal + S_SMU);
+        launch_combine(st, p->vp_total, p->ta, 0.0, p->aw1, p->aw2, p->tc, p->ws.scal + S_SMU);
         CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, st, p->tc));
         check_pass(p, p->rd, p->rp, p->rzv, p->dx, p->dz, false, st);
         Reds Rc(p);
@@ -1681,8 +1724,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       steps = 0;
       if (!acceptable(be)) {
         CHK(refine(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine, o->refine_tol, kn,
-                   rn, false, &be, &steps, st, atol, f32));
-        if (f32 && !acceptable(be)) {
+                   rn, false, &be, &steps, st, atol, f32 && !plain));
+        if (f32 && !plain && !acceptable(be)) {
           refine_total += steps;   // spent, although the pass is redone in FP64
           *ok = false;
           return AHLP_OK;
@@ -1721,17 +1764,17 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     // and keep the corrected direction if the smaller step grows by at least
     // gamma delta_a (constants as in the oracle)
     // g = A'dy of the direction taken, for the A'y update: each correction
-    // solve leaves its own A'dy_c in p->g, so the sum is kept in p->gdir
+    // solve leaves its own A'dy_c in p->ws.g, so the sum is kept in p->gdir
     bool gz_used = false;
     for (int j = 0; j < o->gondzio; ++j) {
       if (ap >= 1.0 && ad >= 1.0) break;
       if (!gz_used) {
-        launch_copy(st, n, p->g, p->gdir);
+        launch_copy(st, n, p->ws.g, p->gdir);
         gz_used = true;
       }
       constexpr double beta_min = 0.1, beta_max = 10.0, delta_a = 0.1, gamma = 0.1;
       const double at_p = std::min(1.0, ap + delta_a), at_d = std::min(1.0, ad + delta_a);
-      launch_gondzio_rhs(st, n, x, z, p->dx, p->dz, at_p, at_d, p->scal + S_SMU, beta_min,
+      launch_gondzio_rhs(st, n, x, z, p->dx, p->dz, at_p, at_d, p->ws.scal + S_SMU, beta_min,
                          beta_max, p->g_r);
       double gbe = 0.0;
       int gsteps = 0;
@@ -1749,21 +1792,21 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       launch_copy(st, n, p->g_dx, p->dx);
       launch_copy(st, m, p->g_dy, p->dy);
       launch_copy(st, n, p->g_dz, p->dz);
-      launch_copy(st, 2, p->scal + S_GP, p->scal + S_AP);   // the step kernels read S_AP, S_AD
-      launch_axpy(st, n, 1.0, p->g, p->gdir);
+      launch_copy(st, 2, p->ws.scal + S_GP, p->ws.scal + S_AP);   // the step kernels read S_AP, S_AD
+      launch_axpy(st, n, 1.0, p->ws.g, p->gdir);
       ap = ap_n;
       ad = ad_n;
       R.correctors++;
       it.correctors++;
     }
-    if (gz_used) launch_copy(st, n, p->gdir, p->g);
+    if (gz_used) launch_copy(st, n, p->gdir, p->ws.g);
     it.alpha_p = ap;
     it.alpha_d = ad;
     p->hist.push_back(it);
     ++k;
     if (ap < 1e-12 && ad < 1e-12) {
       launch_steps(st, o->eta, StepSet{3, {n, m, n, 0},
-                                       {p->scal + S_AP, p->scal + S_AD, p->scal + S_AD, nullptr},
+                                       {p->ws.scal + S_AP, p->ws.scal + S_AD, p->ws.scal + S_AD, nullptr},
                                        {p->dx, p->dy, p->dz, nullptr}, {x, y, z, nullptr}});
       status = AHLP_WSTALL;
       break;
@@ -1786,6 +1829,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   for (int i = 0; i < AHLP_ST_COUNT; ++i) {
     R.t_stage_ms[i] = p->timer.ms[i];
     R.n_stage[i] = p->timer.cnt[i];
+    R.t_stage32_ms[i] = p->timer.ms32[i];
+    R.n_stage32[i] = p->timer.cnt32[i];
   }
   R.rows_bytes = p->rows_bytes;
   p->timer.on = false;

@@ -24,7 +24,7 @@ def eta_bound(eta_orc):
     return max(ETA, 10.0 * eta_orc)
 
 
-def check_trajectory(hist, res, g, label, mu_rtol_early=1e-6, mu_rtol_late=1e-2, late=3):
+def check_trajectory(hist, res, g, label, mu_rtol_early=1e-6, mu_rtol_late=1e-5, late=3):
     """Per-iterate parity of an FP64 interior-point run with the oracle's run
     of the same instance: the same number of iterations; for every predictor
     and corrector (and the two start-point solves) a backward error after

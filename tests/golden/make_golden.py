@@ -48,6 +48,7 @@ def run(config, seed, gondzio=0):
                 bkerr_corr=[h["bkerr"] for h in r.history],
                 start_bkerr=[r.solves[0][0], r.solves[1][0]],
                 correctors=sum(h.get("correctors", 0) for h in r.history),
+                correctors_trace=[h.get("correctors", 0) for h in r.history],
                 seconds=round(time.time() - t, 2))
 
 

@@ -1,10 +1,9 @@
 """GPU parity with Gondzio's multiple centrality correctors (opts.gondzio = 2):
-identical iteration counts and kept-corrector counts, objective within 1e-8 of
+identical iteration counts and kept-corrector counts (per iteration), the
+per-iterate backward-error and mu parity of the runs without correctors,
+objective within 1e-8 of
 the FP64 oracle with the same correctors (tests/golden), on the tiny workload
 (seeds 0-7) and N=512; FP32+refine with correctors reaches the same objective."""
-import json
-import os
-
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -12,15 +11,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2412_07731_amd import gen  # noqa: E402
-
-GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_ipm.json")))
-
-
-def golden(config, seed, gondzio):
-    for r in GOLDEN["runs"]:
-        if r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio:
-            return r
-    return None
+from tests._parity import check_trajectory, golden  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -46,6 +37,9 @@ def test_gondzio_parity(dev, config, seed):
         assert r["iterations"] == g["iterations"]
         assert r["correctors"] == g["correctors"]
         assert abs(r["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))
+        hist = P.history()
+        assert [h["correctors"] for h in hist] == g["correctors_trace"]
+        check_trajectory(hist, r, g, f"{config} seed {seed} gondzio 2")
         if config == "tiny":
             x, y, z, r = P.ipm(gondzio=2, precision=FP32_REFINE)
             assert r["status"] == 0

@@ -72,9 +72,12 @@ def test_graph_recaptured_after_autotune(dev, tmp_path):
         assert _same(e0, P.ipm(graph=1))
         # a table that sends every tunable block to the column kernel
         path = tmp_path / "tune.txt"
-        k = [(int(inst.l[j - 1]) if j > 0 else 0) + (int(inst.l[j]) if j < inst.N - 1 else 0) + inst.n0
-             for j in range(inst.N)]
-        rts = sorted({(int(m) + 15) // 16 + (kk + 15) // 16 for m, kk in zip(inst.m, k)})
+        t16 = lambda v: (int(v) + 15) // 16  # noqa: E731
+        # bordered tile rows of block j: its rows, then each link pair's and
+        # x_0's columns, each rounded up to whole tiles
+        rts = sorted({t16(inst.m[j]) + (t16(inst.l[j - 1]) if j > 0 else 0)
+                      + (t16(inst.l[j]) if j < inst.N - 1 else 0) + t16(inst.n0)
+                      for j in range(inst.N)})
         import torch as _t
         arch = _t.cuda.get_device_properties(0).gcnArchName.split(":")[0]
         path.write_text("".join(f"{arch} {rt} column 1.0 0.5\n" for rt in rts if rt <= 24))
