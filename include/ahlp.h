@@ -212,6 +212,22 @@ ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* r
                              int32_t max_refine, double refine_tol, double* bkerr,
                              hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, results and errors as ahlp_kkt_solve, but the solve's
+ * workspace (solve-phase and Schur-solve vectors, refinement residual and
+ * correction, reduction partials and scalar slots) lives in the library's
+ * static device array of 32 MiB per GPU (held until the process ends) instead
+ * of the handle's.  The call allocates nothing.  Problems whose workspace
+ * exceeds the array are refused with AHLP_EINVAL (the N = 512 workload, 256 x
+ * 512 blocks, needs about 24 MiB).  Every call on one GPU shares that GPU's
+ * array and clears it first: calls that overlap on one GPU (other streams,
+ * other threads, other handles) race and must be ordered by the caller. */
+ahlp_status_t ahlp_kkt_solve_noalloc(ahlp_problem_t p, const double* rx, const double* ry,
+                                     const double* rz, double* dx, double* dy, double* dz,
+                                     int32_t max_refine, double refine_tol, double* bkerr,
+                                     hipStream_t stream);
+
 /* Transposed solve with the factors of the last ahlp_kkt_factor: (wx, wy, wz)
  * with
  *     K' [wx; wy; wz] = [gx; gy; gz],   K = [0 A' I; A 0 0; Z 0 X]

@@ -71,6 +71,9 @@ SIGNATURES = {
     "ahlp_kkt_solve": ([C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_double,
                                                           C.POINTER(C.c_double), C.c_void_p],
                        C.c_int),
+    "ahlp_kkt_solve_noalloc": ([C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_double,
+                                                                  C.POINTER(C.c_double), C.c_void_p],
+                               C.c_int),
     "ahlp_kkt_adjoint": ([C.c_void_p] + [C.c_void_p] * 6 + [C.c_int32, C.c_double,
                                                             C.POINTER(C.c_double), C.c_void_p],
                          C.c_int),
@@ -199,6 +202,20 @@ class Problem:
         _check(lib().ahlp_kkt_solve(self.h, _dptr(rx), _dptr(ry), _dptr(rz), _dptr(dx), _dptr(dy),
                                     _dptr(dz), int(max_refine), float(refine_tol), C.byref(be),
                                     _stream(stream)))
+        return dx, dy, dz, be.value
+
+    def solve_noalloc(self, rx, ry, rz, max_refine=0, refine_tol=1e-10, stream=None, out=None):
+        """ahlp_kkt_solve_noalloc: the solve with its workspace in the library's
+        static device array (no allocation in the call; the outputs are the
+        caller's)."""
+        import torch
+        if out is None:
+            out = (torch.empty_like(rx), torch.empty_like(ry), torch.empty_like(rz))
+        dx, dy, dz = out
+        be = C.c_double(-1.0)
+        _check(lib().ahlp_kkt_solve_noalloc(self.h, _dptr(rx), _dptr(ry), _dptr(rz), _dptr(dx),
+                                            _dptr(dy), _dptr(dz), int(max_refine),
+                                            float(refine_tol), C.byref(be), _stream(stream)))
         return dx, dy, dz, be.value
 
     def adjoint(self, gx, gy, gz, max_refine=0, refine_tol=1e-10, stream=None, out=None):

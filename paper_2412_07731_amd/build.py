@@ -14,7 +14,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libahlp.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["k_factor.hip", "k_chain.hip", "k_bcr.hip", "k_bcr2.hip", "k_solve.hip", "host.cpp"]
+SOURCES = ["k_factor.hip", "k_chain.hip", "k_bcr.hip", "k_bcr2.hip", "k_solve.hip", "noalloc.hip",
+           "host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions are kept out of every kernel

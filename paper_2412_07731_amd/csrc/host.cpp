@@ -233,7 +233,8 @@ struct ahlp_problem_s {
   double rho = 0, delta = 0;
   int pivots_seen = 0;
 
-  // workspace of a refined solve (one allocation at create)
+  // workspace of a refined solve (allocated at create; ahlp_kkt_solve_noalloc
+  // points it into the library's static device array for one call)
   SolveWs ws{};
   double *aty = nullptr, *gdir = nullptr;
   double *ones = nullptr, *zerosn = nullptr;
@@ -302,7 +303,8 @@ ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
 
 // Places the workspace of one refined solve at base (256-byte aligned
 // pieces, each at least one element) and returns its size in bytes; with
-// base == nullptr only the size.
+// base == nullptr only the size.  The handle's own workspace and the static
+// one of ahlp_kkt_solve_noalloc use this one layout.
 size_t solve_ws_layout(const ahlp_problem_s* p, double* base, SolveWs* ws) {
   size_t off = 0;   // bytes
   auto take = [&](double** dst, long long count) {
@@ -853,6 +855,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (int v : p->l) p->lmax = std::max(p->lmax, v);
   int dev_lds = 0;
   HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  // the static workspace's address on this device (kept per device, resolved once)
+  HIPCHK(scratch_setup(p->device));
   const size_t chain_sh = chain_factor_smem(std::max(p->lmax, 1), n0);
   if (chain_sh > (size_t)dev_lds)
     return fail(AHLP_EINVAL, "link pairs (max %d) with %d linking variables exceed the %d bytes of LDS",
@@ -1293,6 +1297,33 @@ ahlp_status_t ahlp_kkt_solve(ahlp_problem_t p, const double* rx, const double* r
                              hipStream_t st) {
   g_err.clear();
   return kkt_solve_impl(p, rx, ry, rz, dx, dy, dz, max_refine, refine_tol, bkerr, st);
+}
+
+ahlp_status_t ahlp_kkt_solve_noalloc(ahlp_problem_t p, const double* rx, const double* ry,
+                                     const double* rz, double* dx, double* dy, double* dz,
+                                     int32_t max_refine, double refine_tol, double* bkerr,
+                                     hipStream_t st) {
+  g_err.clear();
+  if (!p) return fail(AHLP_EINVAL, "null argument");
+  double* base = scratch_device_ptr(p->device);
+  if (!base) return fail(AHLP_ESTATE, "the static workspace of device %d was not set up", p->device);
+  const size_t need = solve_ws_layout(p, nullptr, nullptr);
+  if (need > SCRATCH_BYTES)
+    return fail(AHLP_EINVAL,
+                "this problem's solve needs %zu bytes of workspace; the static workspace holds %zu "
+                "(use ahlp_kkt_solve)", need, (size_t)SCRATCH_BYTES);
+  SolveWs mine{};
+  solve_ws_layout(p, base, &mine);
+  // the array keeps the previous call's contents: start from zeros (a fill
+  // kernel, no memset node if the caller captures the stream)
+  launch_fill(st, (long long)(need / sizeof(double)), 0.0, base);
+  HIPCHK(hipGetLastError());
+  const SolveWs saved = p->ws;
+  p->ws = mine;
+  const ahlp_status_t s =
+      kkt_solve_impl(p, rx, ry, rz, dx, dy, dz, max_refine, refine_tol, bkerr, st);
+  p->ws = saved;
+  return s;
 }
 
 ahlp_status_t ahlp_kkt_adjoint(ahlp_problem_t p, const double* gx, const double* gy,

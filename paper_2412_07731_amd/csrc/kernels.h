@@ -251,4 +251,13 @@ void launch_mreduce(hipStream_t st, const MultiRed& m);
 enum RedOp { RED_DOT = 0, RED_MAXABS = 1, RED_RATIO = 2, RED_MUAFF = 3, RED_MAXSUM = 4, RED_MIN = 5 };
 constexpr int RED_PARTIALS = 256;
 
+// ---- static workspace (noalloc.hip)
+// Size of the per-device static array that ahlp_kkt_solve_noalloc works in.
+constexpr size_t SCRATCH_BYTES = size_t(32) << 20;
+// Resolves the array's device address on `device` (which must be current) and
+// keeps it; later calls return at once.  hipSuccess or the HIP error.
+hipError_t scratch_setup(int device);
+// The kept address for `device`, or nullptr before a successful setup.
+double* scratch_device_ptr(int device);
+
 }  // namespace ahlp
