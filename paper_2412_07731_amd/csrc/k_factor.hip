@@ -484,6 +484,12 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
   constexpr int AST = sizeof(T) == 8 ? 4 : 1;   // accumulator element stride in a padded tile
   const BlockInfo b = blk[order[blockIdx.x]];
   const int mt = b.mt, rt = b.rt;
+  // FP64 keeps every panel tile transposed in its accumulators (X' instead of
+  // X): in the FP64 accumulator layout, register s of X' is exactly the B
+  // operand of K-slice s, so the solve with L_cc^-1 and the panel's own
+  // updates take X' straight from registers.  (The FP32 layout does not line
+  // up this way; it converts through LDS.)
+  constexpr bool TR = sizeof(T) == 8;
   T* colbuf = reinterpret_cast<T*>(smem_raw);          // rt tiles: the panel column just factored
   T* li = colbuf + (size_t)rt * TEP;                    // L_cc^-1
   T* dt = li + TEP;                                     // diagonal tile / its factor
@@ -532,7 +538,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
         if (r < rt && j < pw && r >= c0 + j) {
           const T* src = LB + lb_tile(b, r, c0 + j);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) acc[t][j][k] = src[acc_index<T>(lane, k)];
+          for (int k = 0; k < 4; ++k) acc[t][j][k] = src[TR ? 64 * k + lane : acc_index<T>(lane, k)];
         }
       }
     }
@@ -555,7 +561,9 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
         for (int j = 0; j < BF_PW; ++j)
           if (r < rt && j < pw && r >= c0 + j)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc[t][j] = mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
+            for (int s = 0; s < 4; ++s)
+              acc[t][j] = TR ? mfma(-Bc[j].v[s], Ac[t].v[s], acc[t][j])
+                             : mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
       }
     }
     // factor the panel column by column
@@ -582,19 +590,33 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
       for (int t = 0; t < BF_RMAX; ++t) {
         const int r = c0 + w + 4 * t;
         if (r < rt && r > c) {
-          st_acc(myscr, acc[t][j]);
-          wave_order();
-          const BfOp<T> x = ld_op(myscr);
-          AT l = AT{0, 0, 0, 0};
-#pragma unroll
-          for (int s = 0; s < 4; ++s) l = mfma(x.v[s], lio.v[s], l);
-          wave_order();
           T* dst = LB + lb_tile(b, r, c);
           T* cb = colbuf + (size_t)(r - c0) * TEP;
+          AT l = AT{0, 0, 0, 0};
+          if constexpr (TR) {
+            // L(r, c)' = L_cc^-1 X' with X' in the accumulator registers,
+            // whose element s is the B operand of K-slice s; the result is
+            // again L(r, c)' in accumulator layout (kept for the updates below)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            dst[acc_index<T>(lane, k)] = l[k];
-            cb[wb + AST * k] = l[k];
+            for (int s = 0; s < 4; ++s) l = mfma(lio.v[s], acc[t][j][s], l);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              dst[64 * k + lane] = l[k];
+              cb[rb + 68 * k] = l[k];
+            }
+            acc[t][j] = l;
+          } else {
+            st_acc(myscr, acc[t][j]);
+            wave_order();
+            const BfOp<T> x = ld_op(myscr);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) l = mfma(x.v[s], lio.v[s], l);
+            wave_order();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              dst[acc_index<T>(lane, k)] = l[k];
+              cb[wb + AST * k] = l[k];
+            }
           }
         }
       }
@@ -609,9 +631,16 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
         for (int t = 0; t < BF_RMAX; ++t) {
           const int r = c0 + w + 4 * t;
           if (r < rt && r >= c2) {
-            const BfOp<T> x = ld_op(colbuf + (size_t)(r - c0) * TEP);
+            if constexpr (TR) {
+              // X' -= L(c', c) L(r, c)': A operand from LDS, B operand the
+              // row's own L(r, c)' registers
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc[t][j2] = mfma(-x.v[s], y.v[s], acc[t][j2]);
+              for (int s = 0; s < 4; ++s) acc[t][j2] = mfma(-y.v[s], acc[t][j][s], acc[t][j2]);
+            } else {
+              const BfOp<T> x = ld_op(colbuf + (size_t)(r - c0) * TEP);
+#pragma unroll
+              for (int s = 0; s < 4; ++s) acc[t][j2] = mfma(-x.v[s], y.v[s], acc[t][j2]);
+            }
           }
         }
       }

@@ -9,9 +9,9 @@
 // Layout: lane l holds row i = l%16 and columns 4g..4g+3 (g = l/16) of both
 // halves.  At step j the 16-lane row g already holds columns 4g..4g+3 of every
 // tile row, so row j reaches its lanes by a DPP row broadcast (row_newbcast:j)
-// and the multiplier a_ij / d_j of row i comes from lane (i, j/4) by one lane
-// permute: a step costs one division, one permute, sixteen DPP moves and
-// eight FMAs, with no LDS round trip.
+// and the multiplier a_ij / d_j of row i comes from lane (i, j/4) by two
+// cross-row swaps (permlane16, then permlane32): a step costs one reciprocal,
+// the swaps, sixteen DPP moves and eight FMAs, with no LDS round trip.
 #pragma once
 
 #include "common.h"
@@ -66,6 +66,33 @@ __device__ __forceinline__ float row_bcast(float v) {
   return o.f;
 }
 
+// Value of row group K (lanes 16K..16K+15) in every row group, lane for lane:
+// lane l receives v of lane 16K + l%16.  Two swap steps on the VALU (the
+// permlane16 swap pairs rows 0/1 and 2/3, the permlane32 swap the half
+// waves), instead of a permute through the LDS pipe.
+template <int K>
+__device__ __forceinline__ unsigned rowgroup_bcast_u32(unsigned v) {
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  const unsigned y = (K & 1) ? a[1] : a[0];   // [r0 r0 r2 r2] or [r1 r1 r3 r3]
+  const auto b = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+  return (K & 2) ? b[1] : b[0];
+}
+template <int K>
+__device__ __forceinline__ double rowgroup_bcast(double v) {
+  union { double d; unsigned i[2]; } u;
+  u.d = v;
+  u.i[0] = rowgroup_bcast_u32<K>(u.i[0]);
+  u.i[1] = rowgroup_bcast_u32<K>(u.i[1]);
+  return u.d;
+}
+template <int K>
+__device__ __forceinline__ float rowgroup_bcast(float v) {
+  union { float f; unsigned i; } u;
+  u.f = v;
+  u.i = rowgroup_bcast_u32<K>(u.i);
+  return u.f;
+}
+
 // 1 / p.  FP64: the hardware reciprocal estimate refined by two
 // Newton-Raphson steps (r <- r + r (1 - p r), each doubling the correct
 // bits), a few dependent instructions against the longer correctly rounded
@@ -91,7 +118,7 @@ __device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double th
   const T rp = recip(p);
   if (i == J) mypiv = p;
   // a_iJ from lane (i, J/4); row J from lane J of this lane's 16-lane row
-  const T aij = __shfl(a[J & 3], i + 16 * (J >> 2));
+  const T aij = rowgroup_bcast<J / 4>(a[J & 3]);
   T rj[4], rje[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
