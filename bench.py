@@ -212,6 +212,19 @@ def uneven_bench(steps=3):
                     "bitwise_equal_to_eager": bool(torch.equal(gx, x) and torch.equal(gz, z)
                                                    and gr["iterations"] == r["iterations"])}
     del ge
+    # the panel bucket's stages in one persistent launch
+    P.set_launch(mode="fused")
+    P.ipm()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = 0
+    for _ in range(steps):
+        fx, _, fz, fr = P.ipm()
+        its += fr["iterations"]
+    torch.cuda.synchronize()
+    out["fused_launch"] = {"value": its / (time.perf_counter() - t),
+                           "bitwise_equal_to_eager": bool(torch.equal(fx, x) and torch.equal(fz, z))}
+    P.set_launch(mode="batched")
     # one factorization (a1-a6) at the end point, batched and per block
     for per_block, reps in ((False, 5), (True, 1)):
         P.set_launch(per_block=per_block)
@@ -303,12 +316,15 @@ def fp32_leg(P, inst, fl, args, golden, fp64_rate, fp64_t_asm_ms):
             c32 = {k: sum(r["n_stage32"][k] for r in res32) for k in r32["n_stage32"]}
             s64 = {k: sum(r["t_stage_ms"][k] for r in res32) for k in r32["t_stage_ms"]}
             c64 = {k: sum(r["n_stage"][k] for r in res32) for k in r32["n_stage"]}
-            n32 = max(c32["syrk"], 1)
+            n32 = max(c32["factor"], 1)
+            fused32 = c32["syrk"] == 0
             # a1-a5 of an FP32 factorization: the D-scaling (same kernel in both
-            # precisions), FP32 SYRK and block factor, FP64 assembly
+            # precisions), FP32 SYRK and block factor (one fused launch, or
+            # two), FP64 assembly
             t_asm = s64["prep"] / max(c64["prep"], 1) + (s32["syrk"] + s32["factor"] + s32["schur"]) / n32
             a24 = fl["syrk"] + fl["potrf"] + fl["trsm"]
-            syrk_ms = s32["syrk"] / n32
+            dom32_flop = a24 + fl["schur"] if fused32 else fl["syrk"]
+            syrk_ms = (s32["factor"] if fused32 else s32["syrk"]) / n32
             leg["schur_assembly"] = {
                 "gflop_per_factor": fl["total"] / 1e9, "ms_per_factor": t_asm,
                 "tflops": fl["total"] / (t_asm * 1e-3) / 1e12,
@@ -317,11 +333,14 @@ def fp32_leg(P, inst, fl, args, golden, fp64_rate, fp64_t_asm_ms):
                 / PEAK_FP32_TFLOPS,
                 "speedup_vs_fp64_t_asm": fp64_t_asm_ms / t_asm,
                 "fp32_factorizations_timed": n32}
-            leg["roofline"] = {"kernel": "k_syrk<float> (block SYRK in FP32 MFMA)", "bound": "mfma",
-                               "achieved": fl["syrk"] / (syrk_ms * 1e-3) / 1e12,
+            leg["roofline"] = {"kernel": ("k_factor_fused<float> (link columns, SYRK, Cholesky, "
+                                          "W_i in FP32 MFMA; W_i' W_i in FP64)" if fused32 else
+                                          "k_syrk<float> (block SYRK in FP32 MFMA)"),
+                               "bound": "mfma",
+                               "achieved": dom32_flop / (syrk_ms * 1e-3) / 1e12,
                                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                               "frac": fl["syrk"] / (syrk_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
-                               "traffic": None, "flop_per_launch": fl["syrk"],
+                               "frac": dom32_flop / (syrk_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                               "traffic": None, "flop_per_launch": dom32_flop,
                                "avg_launch_ms": syrk_ms}
             rfull = run(P, 1, 0, precision=FP32_REFINE, timing=1, fp32_accept=acc)[1][0]
             leg["stage_ms_per_solve"] = rfull["t_stage_ms"]
@@ -332,6 +351,28 @@ def fp32_leg(P, inst, fl, args, golden, fp64_rate, fp64_t_asm_ms):
     out["value"] = out["inexact_newton"]["value"]
     out["speedup_vs_fp64"] = out["inexact_newton"]["speedup_vs_fp64"]
     return out
+
+
+def fused_leg(P, fl, args, rate, t_asm_ms):
+    """The factorization's link columns, SYRK, block factor and Schur
+    contributions in one persistent launch (launch mode "fused") against one
+    launch per stage (the line's own figures): iterations/s and the a1-a5 time
+    per factorization, at the same instrumentation level."""
+    from paper_2412_07731_amd.ahlp import FP64
+    P.set_launch(mode="fused")
+    try:
+        dt, res = run(P, args.steps, args.warmup, precision=FP64, timing=2)
+    finally:
+        P.set_launch(mode="batched")
+    its = sum(r["iterations"] for r in res)
+    st = {k: sum(r["t_stage_ms"][k] for r in res) for k in res[0]["t_stage_ms"]}
+    cnt = {k: sum(r["n_stage"][k] for r in res) for k in res[0]["n_stage"]}
+    n = max(cnt["factor"], 1)
+    t = (st["prep"] + st["syrk"] + st["factor"] + st["schur"]) / n
+    return {"value": its / dt, "unit": "IPM iterations/s", "vs_per_stage": (its / dt) / rate,
+            "schur_assembly_ms": t, "schur_assembly_ms_per_stage": t_asm_ms,
+            "frac_of_peak": fl["total"] / (t * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "fused_kernel_ms": st["factor"] / n}
 
 
 def graph_leg(P, args, iters_expected):
@@ -438,13 +479,23 @@ def main():
     ok = all(r["status"] == 0 for r in res)
     st = {k: sum(r["t_stage_ms"][k] for r in res) for k in r0["t_stage_ms"]}
     cnt = {k: sum(r["n_stage"][k] for r in res) for k in r0["n_stage"]}
-    nfact = max(cnt["syrk"], 1)
-    # a1-a5: D-scaling, SYRK (the link-column gather runs beside it on a
-    # second stream), block factor with the Schur contributions, assembly
+    nfact = max(cnt["factor"], 1)
+    # a1-a5: D-scaling, then either one fused launch (link columns, SYRK, block
+    # factor and Schur contributions; stage FACTOR) or the SYRK with the
+    # link-column gather beside it and the block factor, then the assembly
     t_asm_ms = (st["prep"] + st["syrk"] + st["factor"] + st["schur"]) / nfact
     asm_tflops = fl["total"] / (t_asm_ms * 1e-3) / 1e12
-    syrk_ms = st["syrk"] / nfact
-    syrk_tflops = fl["syrk"] / (syrk_ms * 1e-3) / 1e12
+    fused = cnt["syrk"] == 0
+    if fused:
+        dom_name = "k_factor_fused (a1-a5 per block in one persistent launch: link columns, " \
+                   "SYRK M_i = A_i D_i A_i', Cholesky, W_i = L_i^-1 B_i, W_i' W_i)"
+        dom_flop = fl["syrk"] + fl["potrf"] + fl["trsm"] + fl["schur"]
+        dom_ms = st["factor"] / nfact
+    else:
+        dom_name = "k_syrk (block SYRK M_i = A_i D_i A_i')"
+        dom_flop = fl["syrk"]
+        dom_ms = st["syrk"] / nfact
+    dom_tflops = dom_flop / (dom_ms * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if main_prec == FP32_REFINE else PEAK_FP64_TFLOPS
 
     # one more solve with every stage timed (timing=1), outside the timed
@@ -482,11 +533,12 @@ def main():
                            "tflops": asm_tflops, "frac_of_peak": asm_tflops / peak},
         "stage_ms_per_solve": sf, "stage_launches_per_solve": cf,
         "stage_note": "one extra solve with every stage timed, after the timed region",
-        # the dominant kernel by device time: block SYRK (MFMA-bound)
-        "roofline": {"kernel": "k_syrk (block SYRK M_i = A_i D_i A_i')", "bound": "mfma",
-                     "achieved": syrk_tflops, "peak": peak, "unit": "TFLOP/s", "frac": syrk_tflops / peak,
-                     "traffic": measured_traffic("k_syrk", "n512") if main_prec == FP64 else None,
-                     "flop_per_launch": fl["syrk"], "avg_launch_ms": syrk_ms,
+        # the dominant kernel by device time (MFMA-bound)
+        "roofline": {"kernel": dom_name, "bound": "mfma",
+                     "achieved": dom_tflops, "peak": peak, "unit": "TFLOP/s", "frac": dom_tflops / peak,
+                     "traffic": (measured_traffic("k_factor_fused" if fused else "k_syrk", "n512")
+                                 if main_prec == FP64 else None),
+                     "flop_per_launch": dom_flop, "avg_launch_ms": dom_ms,
                      "launches_per_solve": nfact / args.steps},
         "rooflines_other": [
             {"kernel": "k_rows_nv (row pass out_k = base_k + A v_k, 1-3 vectors per read of A)",
@@ -498,6 +550,7 @@ def main():
     if not args.profile and not args.fp32:
         line["fp32_refine"] = fp32_leg(P, inst, fl, args, golden, iters / dt, t_asm_ms)
         line["graph"] = graph_leg(P, args, r0["iterations"])
+        line["fused_launch"] = fused_leg(P, fl, args, iters / dt, t_asm_ms)
     if not args.profile and not args.fp32:
         # Gondzio correctors (two at most per iteration): fewer iterations,
         # more solves per factorization; compared by time to solution

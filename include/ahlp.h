@@ -270,14 +270,22 @@ ahlp_status_t ahlp_problem_set_bc(ahlp_problem_t p, const double* b, const doubl
                                   hipStream_t stream);
 
 /* How the per-block stages of the factorization (SYRK, link columns, block
- * Cholesky with W_i and the Schur products; the per-block steps of Alg. 2, Sec. 3.2) are
- * launched.  AHLP_LAUNCH_BATCHED (default): each stage is one launch over all
- * blocks (blocks of uneven size sorted largest first; the block factor in two
- * buckets, by whether the bordered block fits the panel kernel).
+ * Cholesky with W_i and the Schur products; the per-block steps of Alg. 2,
+ * Sec. 3.2) are launched.  Blocks of uneven size go largest first and the
+ * block factor runs in two buckets, by whether the bordered block fits the
+ * panel kernel.
+ * AHLP_LAUNCH_BATCHED (default): one launch per stage over all blocks (the
+ * SYRK, the link columns on a second stream beside it, the two factor
+ * buckets).
  * AHLP_LAUNCH_PER_BLOCK: the same kernels, one launch per block and stage, in
- * block order; the arithmetic per block is identical, so results are bitwise
- * equal.  It exists to measure what batching gains.  Errors: AHLP_EINVAL. */
-enum { AHLP_LAUNCH_BATCHED = 0, AHLP_LAUNCH_PER_BLOCK = 1 };
+ * block order.
+ * AHLP_LAUNCH_FUSED: the panel bucket in one persistent launch over a
+ * largest-first block queue, in which each CU's workgroup forms the next
+ * block's link columns and SYRK while it factors the previous one; the column
+ * bucket, if any, beside it with one launch per stage.
+ * The arithmetic per block is the same in all three, so results are bitwise
+ * equal.  Errors: AHLP_EINVAL. */
+enum { AHLP_LAUNCH_BATCHED = 0, AHLP_LAUNCH_PER_BLOCK = 1, AHLP_LAUNCH_FUSED = 2 };
 ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode);
 
 /* Chooses the block-factor kernel (the block factorization and the solve

@@ -253,9 +253,15 @@ class Problem:
         _check(lib().ahlp_autotune(self.h, path, C.byref(n), _stream(stream)))
         return n.value
 
-    def set_launch(self, per_block):
-        """Batched launches (default) or one launch per block (ahlp_problem_set_launch)."""
-        _check(lib().ahlp_problem_set_launch(self.h, 1 if per_block else 0))
+    LAUNCH_MODES = {"batched": 0, "per_block": 1, "fused": 2}
+
+    def set_launch(self, per_block=False, mode=None):
+        """How the per-block factorization stages are launched
+        (ahlp_problem_set_launch): mode "batched" (the default: one launch per
+        stage over all blocks), "per_block" or "fused" (the panel bucket in one
+        persistent launch); per_block=True means "per_block"."""
+        m = self.LAUNCH_MODES[mode] if mode is not None else (1 if per_block else 0)
+        _check(lib().ahlp_problem_set_launch(self.h, m))
 
     def set_bc(self, b, c, stream=None):
         """Replace the LP's b and c with device vectors (ahlp_problem_set_bc)."""

@@ -199,6 +199,16 @@ struct ahlp_problem_s {
   // per-block launch mode (the reference the batched launches are compared
   // with): block i's SYRK items, link items, and its index in an identity list
   int launch_mode = AHLP_LAUNCH_BATCHED;
+  int num_cu = 1;
+  int* fused_queue = nullptr;          // the fused launch's block queue counter
+  // host copies of the work lists and the column-kernel bucket's own SYRK and
+  // link items (the fused launch covers the panel bucket)
+  std::vector<int4> h_syrk;
+  std::vector<int2> h_link;
+  std::vector<int> h_bf;
+  int4* col_syrk_items = nullptr;
+  int2* col_link_items = nullptr;
+  int ncol_syrk = 0, ncol_link = 0;
   unsigned launch_gen = 0;   // bumped whenever bf_order, the buckets or launch_mode change
   // block-factor kernel per bordered tile-row count (0 panel, 1 column; the
   // default rule is panel wherever it fits); set by ahlp_autotune
@@ -297,6 +307,8 @@ ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
   HIPCHK(hipMemcpyAsync(&h, p->info, sizeof h, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   p->pivots_seen = h.pivots;
+  if (h.nonfinite & 2)
+    return fail(AHLP_EHIP, "the fused factorization launch gave up waiting for its own stages");
   if (nonfinite) *nonfinite = h.nonfinite != 0;
   return AHLP_OK;
 }
@@ -362,6 +374,35 @@ std::vector<int> bf_buckets(ahlp_problem_t p) {
   return out;
 }
 
+// Block-factor buckets into p->h_bf and bf_order, and the column bucket's
+// own SYRK and link items (the fused launch covers the panel bucket); every
+// captured graph holds the old ones, so the launch generation moves on.
+ahlp_status_t set_buckets(ahlp_problem_t p, hipStream_t st) {
+  p->h_bf = bf_buckets(p);
+  std::vector<int4> cs;
+  std::vector<int2> cl;
+  for (int k = p->n_panel; k < p->N; ++k) {
+    const int i = p->h_bf[k];
+    cs.insert(cs.end(), p->h_syrk.begin() + p->syrk_off[i],
+              p->h_syrk.begin() + p->syrk_off[i] + p->syrk_cnt[i]);
+    cl.insert(cl.end(), p->h_link.begin() + p->link_off[i],
+              p->h_link.begin() + p->link_off[i] + p->link_cnt[i]);
+  }
+  p->ncol_syrk = (int)cs.size();
+  p->ncol_link = (int)cl.size();
+  HIPCHK(hipMemcpyAsync(p->bf_order, p->h_bf.data(), sizeof(int) * p->h_bf.size(),
+                        hipMemcpyHostToDevice, st));
+  if (!cs.empty())
+    HIPCHK(hipMemcpyAsync(p->col_syrk_items, cs.data(), sizeof(int4) * cs.size(),
+                          hipMemcpyHostToDevice, st));
+  if (!cl.empty())
+    HIPCHK(hipMemcpyAsync(p->col_link_items, cl.data(), sizeof(int2) * cl.size(),
+                          hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));   // the host vectors are temporaries
+  ++p->launch_gen;
+  return AHLP_OK;
+}
+
 // The same kernels, one launch per block and stage, in block order on st:
 // the reference for the batched launches (identical arithmetic per block).
 template <typename T>
@@ -388,9 +429,37 @@ ahlp_status_t factor_blocks_per_block(ahlp_problem_t p, hipStream_t st, T* LB, T
   return AHLP_OK;
 }
 
+// The panel bucket fused (link columns, SYRK, block factor and Schur
+// contributions in one persistent launch); the column-kernel bucket, if any,
+// runs its own link, SYRK and column-factor launches on the side stream
+// beside it.
+template <typename T>
+ahlp_status_t factor_blocks_fused(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV,
+                                  const T* A) {
+  p->timer.begin(AHLP_ST_FACTOR);
+  if (p->n_col > 0) {
+    HIPCHK(hipEventRecord(p->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    launch_link<T>(p->side, p->blk, p->col_link_items, p->ncol_link, p->n0, p->A, p->C, p->lptr,
+                   p->lcol, p->lval, p->Dp, LB, p->PQ);
+    launch_syrk<T>(p->side, p->blk, p->col_syrk_items, p->ncol_syrk, A, p->Dp, LB, p->delta);
+    launch_block_factor_col<T>(p->side, p->blk, p->bf_order + p->n_panel, p->n_col, p->rt_col, LB,
+                               LINV, p->PQ, p->info);
+    HIPCHK(hipEventRecord(p->ev_join, p->side));
+  }
+  launch_factor_fused<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, p->fused_queue, p->n0,
+                         A, p->A, p->C, p->lptr, p->lcol, p->lval, p->Dp, LB, LINV, p->PQ,
+                         p->delta, p->info, p->num_cu);
+  if (p->n_col > 0) HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
+  p->timer.end();
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
+}
+
 template <typename T>
 ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, const T* A) {
   if (p->launch_mode == AHLP_LAUNCH_PER_BLOCK) return factor_blocks_per_block<T>(p, st, LB, LINV, A);
+  if (p->launch_mode == AHLP_LAUNCH_FUSED) return factor_blocks_fused<T>(p, st, LB, LINV, A);
   // the link gather (HBM-bound) runs on the side stream while the SYRK
   // (MFMA-bound) runs on st; they write disjoint tiles of LB
   HIPCHK(hipEventRecord(p->ev_fork, st));
@@ -855,6 +924,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (int v : p->l) p->lmax = std::max(p->lmax, v);
   int dev_lds = 0;
   HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  HIPCHK(hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device));
   // the static workspace's address on this device (kept per device, resolved once)
   HIPCHK(scratch_setup(p->device));
   const size_t chain_sh = chain_factor_smem(std::max(p->lmax, 1), n0);
@@ -1034,7 +1104,6 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (int ch = 0; ch < 8; ++ch)
     for (int k = ch; k < N; k += 8) syrk_order.push_back(bysize[k]);
   p->bf_kernel.assign(p->max_rt + 1, -1);
-  std::vector<int> hbf = bf_buckets(p);
   std::vector<int4> hsyrk;
   std::vector<int2> hlink, hrow, hcolt, hc0;
   p->syrk_off.assign(N, 0); p->syrk_cnt.assign(N, 0);
@@ -1057,6 +1126,8 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     for (int q = 0; q < b.kt0; ++q) hc0.push_back(int2{i, q});
   }
   p->nsyrk = (int)hsyrk.size(); p->nlink = (int)hlink.size();
+  p->h_syrk = hsyrk;
+  p->h_link = hlink;
   p->nrt = (int)hrow.size(); p->nct = (int)hcolt.size(); p->nc0 = (int)hc0.size();
 
   // ---- Schur complement geometry and segments
@@ -1115,6 +1186,9 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->b, p->m_tot));
   CHK(M.alloc(&p->c, p->n_tot));
   CHK(M.alloc(&p->syrk_items, p->nsyrk));
+  CHK(M.alloc(&p->col_syrk_items, p->nsyrk));
+  CHK(M.alloc(&p->col_link_items, std::max(p->nlink, 1)));
+  CHK(M.alloc(&p->fused_queue, 1));
   CHK(M.alloc(&p->bf_order, N));
   CHK(M.alloc(&p->ident, N));
   CHK(M.alloc(&p->link_items, std::max(p->nlink, 1)));
@@ -1221,7 +1295,6 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   HIPCHK(hipMemcpyAsync(p->b, d->b, sizeof(double) * p->m_tot, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->c, d->c, sizeof(double) * p->n_tot, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->syrk_items, hsyrk.data(), sizeof(int4) * hsyrk.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(p->bf_order, hbf.data(), sizeof(int) * hbf.size(), hipMemcpyHostToDevice, st));
   {
     std::vector<int> id(N);
     for (int i = 0; i < N; ++i) id[i] = i;
@@ -1252,6 +1325,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   launch_fill(st, 1, 0.0, reinterpret_cast<double*>(p->info));   // a kernel, not a memset: capturable
   if (chain_sh > 64 * 1024) set_chain_smem_limits(chain_sh);
   HIPCHK(hipGetLastError());
+  CHK(set_buckets(p, st));
   HIPCHK(hipStreamSynchronize(st));
   p->timer.st = st;
   *out = up.release();
@@ -1465,17 +1539,14 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
       if (!out) return fail(AHLP_EINVAL, "cannot write the tuning cache %s", cache_path);
     }
   }
-  std::vector<int> hbf = bf_buckets(p);
-  HIPCHK(hipMemcpyAsync(p->bf_order, hbf.data(), sizeof(int) * hbf.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  ++p->launch_gen;   // captured graphs hold the old buckets: capture again
+  CHK(set_buckets(p, st));   // (captured graphs hold the old buckets: they are captured again)
   return AHLP_OK;
 }
 
 ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode) {
   g_err.clear();
   if (!p) return fail(AHLP_EINVAL, "null argument");
-  if (mode != AHLP_LAUNCH_BATCHED && mode != AHLP_LAUNCH_PER_BLOCK)
+  if (mode != AHLP_LAUNCH_BATCHED && mode != AHLP_LAUNCH_PER_BLOCK && mode != AHLP_LAUNCH_FUSED)
     return fail(AHLP_EINVAL, "unknown launch mode %d", mode);
   if (mode != p->launch_mode) ++p->launch_gen;
   p->launch_mode = mode;
@@ -1652,6 +1723,8 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   CHK(resid_stage(true));
   while (true) {
     CHK(read_scal(p, NSCAL, st));
+    if (hinfo->nonfinite & 2)
+      return fail(AHLP_EHIP, "the fused factorization launch gave up waiting for its own stages");
     if (hinfo->nonfinite)
       return fail(AHLP_ENUMERIC, "x or z left the positive orthant or became non-finite");
     const double knorm_iter = std::max(p->colabs1_max, std::max(p->rowabs_max, hs[5]));

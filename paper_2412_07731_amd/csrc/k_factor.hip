@@ -11,6 +11,8 @@
 // in place; this is the partial factorization of the bordered matrix that
 // stops after the m_i pivots of the block (Sec. 3.2 discusses the same
 // construction with an incomplete LU of [K_i L_i'; L_i 0]).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "tile_chol.h"
@@ -199,9 +201,9 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
 // [F_i D_i A_i' ; C_i'] into the bordered rows and F_i D_i F_i' (FP64) into the
 // Schur-contribution tiles.  Link rows are sparse (compressed rows, sorted
 // columns), so the products are gathers rather than GEMMs.
+// Tile row rr of block b's link columns, by 256 threads (t = 0..255).
 template <typename T>
-__global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
-                                              const int2* __restrict__ items, int n0,
+__device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t, int n0,
                                               const double* __restrict__ A,
                                               const double* __restrict__ C,
                                               const int* __restrict__ lptr,
@@ -209,10 +211,8 @@ __global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
                                               const double* __restrict__ lval,
                                               const double* __restrict__ Dp,
                                               T* __restrict__ LB, double* __restrict__ PQ) {
-  const int2 it = items[blockIdx.x];
-  const BlockInfo b = blk[it.x];
-  const int rr = it.y, r = b.mt + rr;
-  const int t = threadIdx.x, ql = t & 15, al = t >> 4;
+  const int r = b.mt + rr;
+  const int ql = t & 15, al = t >> 4;
   const int q = TS * rr + ql;
   int qi;
   bool real;
@@ -276,6 +276,20 @@ __global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
     }
     PQ[pq_tile(b, rr, cc) + t] = v;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
+                                              const int2* __restrict__ items, int n0,
+                                              const double* __restrict__ A,
+                                              const double* __restrict__ C,
+                                              const int* __restrict__ lptr,
+                                              const int* __restrict__ lcol,
+                                              const double* __restrict__ lval,
+                                              const double* __restrict__ Dp,
+                                              T* __restrict__ LB, double* __restrict__ PQ) {
+  const int2 it = items[blockIdx.x];
+  link_tile_row<T>(blk[it.x], it.y, threadIdx.x, n0, A, C, lptr, lcol, lval, Dp, LB, PQ);
 }
 
 // ---------------------------------------------------------------- a3 + a4
@@ -472,17 +486,41 @@ __device__ __forceinline__ void tile_copy_p(T* __restrict__ dst, const T* __rest
   for (int s = 0; s < 4; ++s) dst[64 * s + lane] = src[pidx<LD>(64 * s + lane)];
 }
 
-template <typename T, int BF_RMAX>
-__global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
-                                                               const int* __restrict__ order,
-                                                               T* __restrict__ LB,
-                                                               T* __restrict__ LINV,
-                                                               double* __restrict__ PQ,
-                                                               DevInfo* info) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+// Synchronization of the panel factor's four waves in the standalone kernel:
+// a workgroup barrier, and every panel's inputs are there from the start.
+struct WgSync {
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ bool wait_panel(int) { return true; }
+};
+
+// Largest real diagonal entry of block b's M_i (threads 0..255, all of which
+// call it; s_max: 4 doubles of LDS).
+template <typename T, class Sync>
+__device__ __forceinline__ double block_diag_max(const BlockInfo& b, const T* __restrict__ LB,
+                                                 double* s_max, Sync& sy) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double md = 0.0;
+  for (int idx = tid; idx < b.m; idx += 256) {
+    const int p = idx >> 4, i = idx & 15;
+    md = fmax(md, (double)LB[lb_tile(b, p, p) + i * 17]);
+  }
+  for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off));
+  if (lane == 0) s_max[w] = md;
+  sy.sync();
+  return fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
+}
+
+// The panel factorization of one bordered block by four waves (threads
+// 0..255), with pivot threshold thr; smem_raw is its dynamic LDS.  Sync
+// provides the barrier of the four waves and the wait for the inputs of panel
+// c0 (returns false when the wait was abandoned, and the factorization stops).
+template <typename T, int BF_RMAX, class Sync>
+__device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__ LB,
+                                             T* __restrict__ LINV, double* __restrict__ PQ,
+                                             DevInfo* info, unsigned char* smem_raw, double thr,
+                                             Sync& sy) {
   constexpr int LD = BfLd<BF_RMAX>::LD, TEP = TS * LD;
   constexpr int AST = sizeof(T) == 8 ? 4 : 1;   // accumulator element stride in a padded tile
-  const BlockInfo b = blk[order[blockIdx.x]];
   const int mt = b.mt, rt = b.rt;
   // FP64 keeps every panel tile transposed in its accumulators (X' instead of
   // X): in the FP64 accumulator layout, register s of X' is exactly the B
@@ -494,20 +532,9 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
   T* li = colbuf + (size_t)rt * TEP;                    // L_cc^-1
   T* dt = li + TEP;                                     // diagonal tile / its factor
   T* scr = dt + TEP;                                    // 4 tiles: per-wave conversion
-  __shared__ double s_max[4];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row and address arithmetic stays scalar
   typedef typename Acc<T>::type AT;
-
-  double md = 0.0;
-  for (int idx = tid; idx < b.m; idx += blockDim.x) {
-    const int p = idx >> 4, i = idx & 15;
-    md = fmax(md, (double)LB[lb_tile(b, p, p) + i * 17]);
-  }
-  for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off));
-  if (lane == 0) s_max[w] = md;
-  __syncthreads();
-  const double thr = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
   int cnt = 0;
   T* myscr = scr + w * TEP;
   // padded positions of this lane's accumulator elements (wb + AST r) and
@@ -527,6 +554,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
 
   for (int c0 = 0; c0 < mt; c0 += BF_PW) {
     const int pw = min(BF_PW, mt - c0);
+    if (!sy.wait_panel(c0)) return;
     // rows r = c0 + w + 4 t of this panel owned by the wave
     AT acc[BF_RMAX][BF_PW];
 #pragma unroll
@@ -583,7 +611,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
         tile_copy_p<T, LD>(LB + lb_tile(b, c, c), dt);
         tile_copy_p<T, LD>(LINV + b.linvoff + (long long)c * TE, li);
       }
-      __syncthreads();
+      sy.sync();
       // rows below: L(r, c) = acc(r, c) L_cc^-T
       const BfOp<T> lio = ld_op(li);
 #pragma unroll
@@ -620,7 +648,7 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
           }
         }
       }
-      __syncthreads();
+      sy.sync();
       // the panel's later columns: acc(r, c') -= L(r, c) L(c', c)'
 #pragma unroll
       for (int j2 = 0; j2 < BF_PW; ++j2) {
@@ -644,13 +672,316 @@ __global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* 
           }
         }
       }
-      __syncthreads();
+      sy.sync();
     }
   }
   // the block's Schur contribution while its W' tiles are still in L2 (the
   // loop's last barrier has made every wave's stores visible)
   schur_rows<T>(b, LB, PQ, w, lane);
-  if (tid == 0 && cnt) atomicAdd(&info->pivots, cnt);
+  // each wave counts the pivots of the diagonal tiles it factored
+  if (lane == 0 && cnt) atomicAdd(&info->pivots, cnt);
+}
+
+template <typename T, int BF_RMAX>
+__global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
+                                                               const int* __restrict__ order,
+                                                               T* __restrict__ LB,
+                                                               T* __restrict__ LINV,
+                                                               double* __restrict__ PQ,
+                                                               DevInfo* info) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double s_max[4];
+  const BlockInfo b = blk[order[blockIdx.x]];
+  WgSync sy;
+  const double thr = PIVOT_REL * fmax(block_diag_max<T>(b, LB, s_max, sy), 0.0);
+  panel_factor<T, BF_RMAX>(b, LB, LINV, PQ, info, smem_raw, thr, sy);
+}
+
+// ------------------------------------------------- a1-a5 in one launch
+// One persistent launch for the blocks of the panel bucket: a workgroup of
+// eight waves per CU.  Waves 4-7 (the SYRK team) take blocks from a queue in
+// the bucket's order (largest first) and form, per block, the link columns
+// (link_tile_row), then the diagonal 32x32 wave tiles of M_i, then the
+// off-diagonal ones column by column; waves 0-3 (the factor team) run the
+// panel factorization of the block the SYRK team started, panel by panel as
+// soon as the tile columns it needs are complete, while the SYRK team goes on
+// with the next block.  So a block's latency-bound factorization chain runs
+// beside the next block's MFMA-bound SYRK on the same CU.  Every value is
+// computed by the same arithmetic in the same order as in the separate
+// kernels (k_link, k_syrk, k_block_factor_panel), so the factors are
+// bitwise the same.
+//
+// The two teams meet through LDS only: a ring of two block slots, each with
+// its block, a sequence number and completion counters (link rows, diagonal
+// wave tiles, off-diagonal wave tiles per tile-column pair) and the largest
+// diagonal entry (for the pivot threshold); a producer stores its tiles,
+// fences at workgroup scope and bumps a counter; a consumer waits for the
+// count and fences.  The factor team's own barrier is an LDS counter (a
+// workgroup barrier would also wait for the SYRK team).  Every wait is
+// bounded (about 2^22 sleeps); one that runs out raises the workgroup's abort
+// flag and bit 2 of the info word, every other wait then gives up too, and
+// all waves exit.
+constexpr int FUSED_MTP = 16;                 // tile-column pairs per block (mt <= 32)
+struct FusedSlot {
+  int seq, state;                             // state: 0 free, 1 block, 2 end of queue
+  int blk, link, diag;
+  int cols[FUSED_MTP];                        // off-diagonal wave tiles done per column pair
+  unsigned long long dmax;                    // bits of the largest diagonal entry (>= 0)
+};
+struct FusedCtl {
+  FusedSlot slot[2];
+  int fbar;                                   // factor-team barrier arrivals
+  int abort;
+};
+
+__device__ __forceinline__ int lds_ld(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(int* p, int v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wg_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); }
+__device__ __forceinline__ void wg_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup"); }
+
+// Waits (the whole wave) until cond() holds; false if the wait ran out or the
+// workgroup aborted.  A wait that runs out raises the abort flag.
+template <class F>
+__device__ __forceinline__ bool fused_wait(FusedCtl* ctl, DevInfo* info, F cond) {
+  for (int it = 0; it < (1 << 22); ++it) {
+    if (cond()) {
+      wg_acquire();
+      return true;
+    }
+    if (lds_ld(&ctl->abort)) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    lds_st(&ctl->abort, 1);
+    atomicOr(&info->nonfinite, 2);
+  }
+  return false;
+}
+
+// The factor team's synchronization inside the fused kernel.
+struct TeamSync {
+  FusedCtl* ctl;
+  FusedSlot* slot;
+  DevInfo* info;
+  int gen;     // barrier arrivals this wave has waited for
+  int mtp;     // tile-column pairs of the block
+  bool ok;
+  __device__ __forceinline__ void sync() {
+    wg_release();
+    if ((threadIdx.x & 63) == 0) lds_add(&ctl->fbar, 1);
+    gen += 4;
+    const int g = gen;
+    int* bar = &ctl->fbar;
+    if (!fused_wait(ctl, info, [&]() { return lds_ld(bar) >= g; })) ok = false;
+  }
+  // panel c0 (tile columns c0, c0 + 1) needs the off-diagonal wave tiles of
+  // column pair c0 / 2: pairs below it, mtp - 1 - c0 / 2 of them
+  __device__ __forceinline__ bool wait_panel(int c0) {
+    if (!ok) return false;
+    const int q = c0 >> 1, need = mtp - 1 - q;
+    int* cnt = &slot->cols[q];
+    ok = fused_wait(ctl, info, [&]() { return lds_ld(cnt) >= need; });
+    return ok;
+  }
+};
+
+// One 32x32 wave tile (tile rows 2R, 2R+1, tile columns 2C, 2C+1) of block b's
+// M_i = A_i D_i A_i' (+ delta I), by one wave with operands loaded straight
+// from memory (two K steps in flight).  The per-tile products and their order
+// are those of k_syrk.  Returns the largest real diagonal entry it stored
+// (0 off the diagonal).
+template <typename T>
+__device__ __forceinline__ double syrk_wave_tile(const BlockInfo& b, int R, int C,
+                                                 const T* __restrict__ A,
+                                                 const double* __restrict__ Dp,
+                                                 T* __restrict__ LB, double delta) {
+  const int lane = threadIdx.x & 63;
+  const int I0 = 2 * R, J0 = 2 * C;
+  bool use[2][2];
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc)
+      use[tr][tc] = I0 + tr < b.mt && J0 + tc < b.mt && I0 + tr >= J0 + tc;
+  const T* rp[2];
+  const T* cp[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    rp[u] = A + a_tile(b, min(I0 + u, b.mt - 1), 0) + lane;
+    cp[u] = A + a_tile(b, min(J0 + u, b.mt - 1), 0) + lane;
+  }
+  const double* dp = Dp + b.dpoff + (lane >> 4);
+  typedef typename Acc<T>::type AT;
+  AT acc[2][2];
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc) acc[tr][tc] = AT{0, 0, 0, 0};
+  struct Stage { T a[2][4], c[2][4]; double d[4]; };
+  auto load = [&](int K, Stage& S) {
+    const long long o = (long long)min(K, b.nt - 1) * TE;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        S.a[u][s] = rp[u][o + 64 * s];
+        S.c[u][s] = cp[u][o + 64 * s];
+      }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) S.d[s] = dp[(long long)min(K, b.nt - 1) * TS + 4 * s];
+  };
+  auto step = [&](const Stage& S) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const T dd = (T)S.d[s];
+      const T b0 = S.c[0][s] * dd, b1 = S.c[1][s] * dd;
+      if (use[0][0]) acc[0][0] = mfma(S.a[0][s], b0, acc[0][0]);
+      if (use[0][1]) acc[0][1] = mfma(S.a[0][s], b1, acc[0][1]);
+      if (use[1][0]) acc[1][0] = mfma(S.a[1][s], b0, acc[1][0]);
+      if (use[1][1]) acc[1][1] = mfma(S.a[1][s], b1, acc[1][1]);
+    }
+  };
+  Stage S0, S1;
+  load(0, S0);
+  load(1, S1);
+  for (int K = 0; K < b.nt; K += 2) {
+    step(S0);
+    load(K + 2, S0);
+    if (K + 1 < b.nt) step(S1);
+    load(K + 3, S1);
+  }
+  double dmax = 0.0;
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr) {
+#pragma unroll
+    for (int tc = 0; tc < 2; ++tc) {
+      const int I = I0 + tr, J = J0 + tc;
+      if (!use[tr][tc]) continue;
+      T* dst = LB + lb_tile(b, I, J);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T v = acc[tr][tc][r];
+        const int i = acc_row<T>(lane, r), j = lane & 15;
+        if (I == J && i == j) {
+          const bool real = TS * I + i < b.m;
+          v = real ? (T)(v + delta) : T(1);
+          if (real) dmax = fmax(dmax, (double)v);
+        }
+        dst[acc_index<T>(lane, r)] = v;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
+  return dmax;
+}
+
+template <typename T, int BF_RMAX>
+__global__ __launch_bounds__(512, 1) void k_factor_fused(
+    const BlockInfo* __restrict__ blk, const int* __restrict__ order, int nblk,
+    int* __restrict__ queue, int n0, const T* __restrict__ Aw, const double* __restrict__ A,
+    const double* __restrict__ C, const int* __restrict__ lptr, const int* __restrict__ lcol,
+    const double* __restrict__ lval, const double* __restrict__ Dp, T* __restrict__ LB,
+    T* __restrict__ LINV, double* __restrict__ PQ, double delta, DevInfo* info) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ FusedCtl ctl;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (tid == 0) {
+    for (int s2 = 0; s2 < 2; ++s2) {
+      ctl.slot[s2].seq = s2 - 2;
+      ctl.slot[s2].state = 0;
+    }
+    ctl.fbar = 0;
+    ctl.abort = 0;
+  }
+  __syncthreads();   // the only workgroup barrier: both teams pass it once
+
+  if (wave >= 4) {
+    // ---------------- SYRK team
+    const int sw = wave - 4;
+    for (int k = 0;; ++k) {
+      FusedSlot* sl = &ctl.slot[k & 1];
+      if (sw == 0) {
+        // the leader takes the slot once its previous block (k - 2) is done;
+        // the other waves wait for the slot's new sequence number only (the
+        // leader may already have moved it on when they get here)
+        if (!fused_wait(&ctl, info, [&]() { return lds_ld(&sl->seq) == k - 2 && lds_ld(&sl->state) == 0; }))
+          return;
+        int g = 0;
+        if (lane == 0) g = atomicAdd(queue, 1);
+        g = __shfl(g, 0);
+        if (lane == 0) {
+          if (g < nblk) {
+            sl->blk = order[g];
+            sl->link = 0;
+            sl->diag = 0;
+            for (int q = 0; q < FUSED_MTP; ++q) sl->cols[q] = 0;
+            sl->dmax = 0ull;
+          }
+          lds_st(&sl->state, g < nblk ? 1 : 2);
+        }
+        // the slot's fields before its sequence number
+        wg_release();
+        if (lane == 0) lds_st(&sl->seq, k);
+      }
+      if (!fused_wait(&ctl, info, [&]() { return lds_ld(&sl->seq) == k; })) return;
+      if (lds_ld(&sl->state) == 2) return;
+      const BlockInfo b = blk[sl->blk];
+      // link columns: the team's 256 threads take the tile rows in turn
+      for (int rr = 0; rr < b.kt; ++rr)
+        link_tile_row<T>(b, rr, tid - 256, n0, A, C, lptr, lcol, lval, Dp, LB, PQ);
+      wg_release();
+      if (lane == 0) lds_add(&sl->link, 1);
+      // diagonal wave tiles, then the off-diagonal ones by column pair
+      const int MT = (b.mt + 1) >> 1;
+      for (int R = sw; R < MT; R += 4) {
+        const double dm = syrk_wave_tile<T>(b, R, R, Aw, Dp, LB, delta);
+        if (lane == 0) atomicMax(&sl->dmax, (unsigned long long)__double_as_longlong(dm));
+        wg_release();
+        if (lane == 0) lds_add(&sl->diag, 1);
+      }
+      int e = 0;
+      for (int Cq = 0; Cq < MT - 1; ++Cq)
+        for (int R = Cq + 1; R < MT; ++R, ++e) {
+          if ((e & 3) != sw) continue;
+          syrk_wave_tile<T>(b, R, Cq, Aw, Dp, LB, delta);
+          wg_release();
+          if (lane == 0) lds_add(&sl->cols[Cq], 1);
+        }
+      if (lds_ld(&ctl.abort)) return;
+    }
+  } else {
+    // ---------------- factor team
+    TeamSync sy{&ctl, nullptr, info, 0, 0, true};
+    for (int k = 0;; ++k) {
+      FusedSlot* sl = &ctl.slot[k & 1];
+      if (!fused_wait(&ctl, info, [&]() { return lds_ld(&sl->seq) == k; })) return;
+      if (lds_ld(&sl->state) == 2) return;
+      const BlockInfo b = blk[sl->blk];
+      const int MT = (b.mt + 1) >> 1;
+      if (!fused_wait(&ctl, info, [&]() { return lds_ld(&sl->link) >= 4 && lds_ld(&sl->diag) >= MT; }))
+        return;
+      const double dmax = __longlong_as_double((long long)sl->dmax);
+      const double thr = PIVOT_REL * fmax(dmax, 0.0);
+      sy.slot = sl;
+      sy.mtp = MT;
+      panel_factor<T, BF_RMAX>(b, LB, LINV, PQ, info, smem_raw, thr, sy);
+      if (!sy.ok) return;
+      sy.sync();               // every factor wave is done with the slot
+      if (!sy.ok) return;
+      if (tid == 0) {
+        wg_release();
+        lds_st(&sl->state, 0);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------- a5
@@ -747,6 +1078,10 @@ __global__ __launch_bounds__(256) void k_assemble_s00(const BlockInfo* __restric
   }
 }
 
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0) p[0] = 0;
+}
+
 // FP32 shadow of the constraint blocks (FP32 mode).
 __global__ void k_convert_f32(long long n, const double* __restrict__ src, float* __restrict__ dst) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -813,6 +1148,38 @@ void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* 
                        LINV, PQ, info);
   }
 }
+// The fused launch over the panel bucket (blocks order[0, n), bordered tile
+// rows at most max_rt <= 4 BF_RMAX_MAX, tile columns at most 2 FUSED_MTP):
+// one eight-wave workgroup per CU (at most n).  queue: one int, zeroed here.
+template <typename T>
+void launch_factor_fused(hipStream_t st, const BlockInfo* blk, const int* order, int n,
+                         int max_rt, int* queue, int n0, const T* Aw, const double* A,
+                         const double* C, const int* lptr, const int* lcol, const double* lval,
+                         const double* Dp, T* LB, T* LINV, double* PQ, double delta,
+                         DevInfo* info, int num_cu) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, queue);
+  const int grid = std::min(n, num_cu);
+  if (max_rt <= 20) {
+    const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<5>::LD * sizeof(T);
+    hipLaunchKernelGGL((k_factor_fused<T, 5>), dim3(grid), dim3(512), shmem, st, blk, order, n,
+                       queue, n0, Aw, A, C, lptr, lcol, lval, Dp, LB, LINV, PQ, delta, info);
+  } else {
+    const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<6>::LD * sizeof(T);
+    hipLaunchKernelGGL((k_factor_fused<T, 6>), dim3(grid), dim3(512), shmem, st, blk, order, n,
+                       queue, n0, Aw, A, C, lptr, lcol, lval, Dp, LB, LINV, PQ, delta, info);
+  }
+}
+template void launch_factor_fused<double>(hipStream_t, const BlockInfo*, const int*, int, int, int*,
+                                          int, const double*, const double*, const double*,
+                                          const int*, const int*, const double*, const double*,
+                                          double*, double*, double*, double, DevInfo*, int);
+template void launch_factor_fused<float>(hipStream_t, const BlockInfo*, const int*, int, int, int*,
+                                         int, const float*, const double*, const double*,
+                                         const int*, const int*, const double*, const double*,
+                                         float*, float*, double*, double, DevInfo*, int);
+bool factor_fused_fits(int rt, int mt) { return rt <= 4 * BF_RMAX_MAX && mt <= 2 * FUSED_MTP; }
+
 // Column-at-a-time kernel (any height), then the Schur contributions.
 template <typename T>
 void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* order, int n,

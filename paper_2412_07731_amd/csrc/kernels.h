@@ -28,6 +28,15 @@ template <typename T>
 void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* order, int n,
                              int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info);
 bool block_factor_panel_fits(int rt);
+// a1-a5 for the panel bucket in one persistent launch (link columns, SYRK,
+// panel factorization and Schur contributions); num_cu: compute units.
+template <typename T>
+void launch_factor_fused(hipStream_t st, const BlockInfo* blk, const int* order, int n,
+                         int max_rt, int* queue, int n0, const T* Aw, const double* A,
+                         const double* C, const int* lptr, const int* lcol, const double* lval,
+                         const double* Dp, T* LB, T* LINV, double* PQ, double delta,
+                         DevInfo* info, int num_cu);
+bool factor_fused_fits(int rt, int mt);
 void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
                      const long long* tdoff, const long long* tooff, const long long* eoff,
                      const double* PQ, const double* F0, const long long* loff, double delta,

@@ -241,6 +241,7 @@ def test_n512_direction_sampled(dev, n512):
         Lg, Wg = P.debug_block(i)
         assert rel(Lg, f.L[i]) < 1e-12
         assert rel(Wg, f.W[i]) < 1e-11
+    assert P.pivots() == 0          # also raises if the factorization reported an error
     P.close()
 
 

@@ -94,3 +94,38 @@ def test_autotune_table(dev, tmp_path):
         assert P2.autotune(path) == 0          # every entry from the cache
     finally:
         P2.close()
+
+
+@pytest.mark.parametrize("case", ["tiny", "uneven48", "n512"])
+def test_launch_modes_bitwise(dev, case):
+    """One launch per stage (the default), one launch per block and stage, and
+    the fused persistent launch (link columns, SYRK, block factor and Schur
+    contributions of the panel bucket) give bitwise the same factors and
+    Newton direction."""
+    from paper_2412_07731_amd.ahlp import Problem
+    print("case: launch modes", case, flush=True)
+    inst = gen.generate("uneven", 1, N=48) if case == "uneven48" else gen.generate(case, 0)
+    rng = np.random.default_rng(4)
+    T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa: E731
+    x, z = T(rng.uniform(0.1, 2, inst.n_tot)), T(rng.uniform(0.1, 2, inst.n_tot))
+    r = (T(rng.standard_normal(inst.n_tot)), T(rng.standard_normal(inst.m_tot)),
+         T(rng.standard_normal(inst.n_tot)))
+    blocks = sorted({0, 1, inst.N // 3, inst.N // 2, inst.N - 1})
+    P = Problem(inst)
+    try:
+        out = {}
+        for mode in ("batched", "fused", "per_block"):
+            P.set_launch(mode=mode)
+            P.factor(x, z, 1e-8, 1e-6)
+            d = P.solve(*r, max_refine=2)
+            torch.cuda.synchronize()
+            out[mode] = ([P.debug_block(i) for i in blocks], d)
+        P.set_launch(mode="batched")
+        ref_blocks, ref_d = out["batched"]
+        for mode in ("fused", "per_block"):
+            bl, d = out[mode]
+            for (L1, W1), (L2, W2) in zip(ref_blocks, bl):
+                assert np.array_equal(L1, L2) and np.array_equal(W1, W2), (case, mode)
+            assert all(torch.equal(a, b) for a, b in zip(ref_d[:3], d[:3])), (case, mode)
+    finally:
+        P.close()
