@@ -94,9 +94,12 @@ def jvp(inst, x, z, db, dc, **kw):
 
 def central_path(inst, x, y, z, mu, b, c, tol=1e-15, max_iter=30):
     """Newton's method on F(x, y, z; b, c) = 0 for fixed mu from (x, y, z),
-    with a fraction-to-boundary step (0.9) to keep x, z > 0.  Stops when the
-    scaled residual max(|A'y + z - c|/(1+|c|), |A x - b|/(1+|b|),
-    |x z - mu|/mu) is <= tol or stops decreasing."""
+    with a fraction-to-boundary step (0.9) to keep x, z > 0.  The scaled
+    residual is max(|A'y + z - c|/(1+|c|), |A x - b|/(1+|b|), |x z - mu|/mu).
+    Every Newton step is taken (the first step after a perturbation of (b, c)
+    can raise the complementarity part, measured against the small mu, before
+    the quadratic convergence sets in); it stops when the residual is <= tol
+    or has not improved for three steps, and returns the best point."""
     x, y, z = (np.array(v, dtype=np.float64) for v in (x, y, z))
     bn, cn = 1.0 + _inf(b), 1.0 + _inf(c)
 
@@ -108,8 +111,10 @@ def central_path(inst, x, y, z, mu, b, c, tol=1e-15, max_iter=30):
 
     F = resid(x, y, z)
     best = size(F)
+    bx, by, bz = x, y, z
+    stale = 0
     for _ in range(max_iter):
-        if best <= tol:
+        if best <= tol or stale >= 3:
             break
         r = tuple(-v for v in F)
         d, _ = _solve_k(inst, x, z, r)
@@ -119,13 +124,14 @@ def central_path(inst, x, y, z, mu, b, c, tol=1e-15, max_iter=30):
             neg = dv < 0
             if np.any(neg):
                 a = min(a, 0.9 * float(np.min(-v[neg] / dv[neg])))
-        xn, yn, zn = x + a * dx, y + a * dy, z + a * dz
-        Fn = resid(xn, yn, zn)
-        sn = size(Fn)
-        if not sn < best:
-            break
-        x, y, z, F, best = xn, yn, zn, Fn, sn
-    return x, y, z, best
+        x, y, z = x + a * dx, y + a * dy, z + a * dz
+        F = resid(x, y, z)
+        s = size(F)
+        if s < best:
+            best, bx, by, bz, stale = s, x, y, z, 0
+        else:
+            stale += 1
+    return bx, by, bz, best
 
 
 def _solve_k(inst, x, z, r, rho=1e-8, delta=1e-6, tol=1e-15, max_refine=30):
