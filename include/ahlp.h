@@ -290,18 +290,22 @@ ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode);
 
 /* Chooses the block-factor kernel (the block factorization and the solve
  * against the linking columns of Alg. 2, Sec. 3.2) for every bordered
- * tile-row count rt that the problem's blocks have and the panel kernel can
- * hold (rt <= 24): the panel kernel (panel accumulators in
- * registers) or the column kernel (one tile column at a time through LDS).
- * Entries for this GPU architecture found in the text file cache_path (HOST
- * string, may be NULL) are used as they are; every other rt is measured on the
- * problem's own blocks of that rt at x = z = 1 (the faster of two timed
- * launches per kernel, each after rebuilding the blocks' inputs) and, with a
- * cache_path, appended to the file as "<arch> <rt> <panel|column> <us panel>
- * <us column>".  *measured (host, may be NULL) receives the number of rt values
- * timed.  Later factorizations use the choices.  Overwrites the factors
- * (factor again before solving).  Synchronizes `stream`.  Errors: AHLP_EINVAL
- * (also for an unwritable cache file), AHLP_EHIP. */
+ * tile-row count rt that the problem's blocks have and at least two kernels
+ * can hold (rt <= 40): the panel kernel with four waves per block (panel
+ * accumulators in registers, rt <= 24, two workgroups per CU), the panel
+ * kernel with eight waves (rt <= 40, one per CU) or the column kernel (one
+ * tile column at a time through LDS, any rt).  Without tuning, the first of
+ * these that fits is used.  Entries for this GPU architecture found in the
+ * text file cache_path (HOST string, may be NULL) are used as they are; every
+ * other rt is measured on the problem's own blocks of that rt at x = z = 1
+ * (the faster of two timed launches per kernel, each after rebuilding the
+ * blocks' inputs) and, with a cache_path, appended to the file as
+ * "<arch> <rt> <panel|column|panel8> <us panel> <us column> <us panel8>"
+ * (-1 for a kernel that cannot hold the blocks).  *measured (host, may be
+ * NULL) receives the number of rt values timed.  Later factorizations use the
+ * choices.  Overwrites the factors (factor again before solving).
+ * Synchronizes `stream`.  Errors: AHLP_EINVAL (also for an unwritable cache
+ * file), AHLP_EHIP. */
 ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* measured,
                             hipStream_t stream);
 

@@ -142,6 +142,10 @@ struct StageTimer {
 
 }  // namespace
 
+// Block-factor kernels (bf_kernel entries): the four-wave panel kernel, the
+// column-at-a-time kernel, the eight-wave panel kernel.
+enum { BFK_PANEL = 0, BFK_COLUMN = 1, BFK_PANEL8 = 2 };
+
 // Segments of an interior-point iteration between host synchronizations:
 // A = factorization + predictor (+ check, step lengths, mu_aff), B = corrector
 // (+ check, step lengths), per factor precision; C = step + next residuals.
@@ -192,10 +196,11 @@ struct ahlp_problem_s {
   double *lval = nullptr, *cval = nullptr;
   int4* syrk_items = nullptr;
   int nsyrk = 0;
-  // block-factor buckets: bf_order[0, n_panel) for the panel kernel, then
-  // n_col blocks for the column kernel, each largest first
+  // block-factor buckets: bf_order[0, n_panel) for the four-wave panel
+  // kernel, then n_panel8 blocks for the eight-wave one, then n_col blocks
+  // for the column kernel, each largest first
   int* bf_order = nullptr;
-  int n_panel = 0, n_col = 0, rt_panel = 0, rt_col = 0;
+  int n_panel = 0, n_panel8 = 0, n_col = 0, rt_panel = 0, rt_panel8 = 0, rt_col = 0;
   // per-block launch mode (the reference the batched launches are compared
   // with): block i's SYRK items, link items, and its index in an identity list
   int launch_mode = AHLP_LAUNCH_BATCHED;
@@ -344,10 +349,22 @@ size_t solve_ws_layout(const ahlp_problem_s* p, double* base, SolveWs* ws) {
 }
 
 // ------------------------------------------------------------- factor
+// Block-factor kernel for bordered tile-row count rt: the autotuned choice
+// (bf_kernel) or the default rule, the four-wave panel kernel where it fits,
+// else the eight-wave one, else the column kernel.
+int bf_choice(const ahlp_problem_s* p, int rt) {
+  const int k = rt < (int)p->bf_kernel.size() ? p->bf_kernel[rt] : -1;
+  if (k == BFK_PANEL && block_factor_panel_fits(rt)) return BFK_PANEL;
+  if (k == BFK_PANEL8 && block_factor_panel8_fits(rt)) return BFK_PANEL8;
+  if (k == BFK_COLUMN) return BFK_COLUMN;
+  if (block_factor_panel_fits(rt)) return BFK_PANEL;
+  if (block_factor_panel8_fits(rt)) return BFK_PANEL8;
+  return BFK_COLUMN;
+}
+
 // Block-factor buckets: blocks largest first (rt, then mt, then nt), the
-// panel-kernel bucket then the column-kernel bucket; sets n_panel, n_col,
-// rt_panel, rt_col.  The kernel per rt follows bf_kernel (autotuned) or the
-// default rule.
+// four-wave panel bucket, the eight-wave panel bucket, the column bucket;
+// sets n_* and rt_* of each.
 std::vector<int> bf_buckets(ahlp_problem_t p) {
   const int N = p->N;
   std::vector<int> bysize(N);
@@ -358,19 +375,19 @@ std::vector<int> bf_buckets(ahlp_problem_t p) {
     if (x.mt != y.mt) return x.mt > y.mt;
     return x.nt > y.nt;
   });
-  auto panel = [&](int rt) {
-    if (!block_factor_panel_fits(rt)) return false;
-    const int k = rt < (int)p->bf_kernel.size() ? p->bf_kernel[rt] : -1;
-    return k != 1;
-  };
   std::vector<int> out;
-  p->rt_panel = p->rt_col = 0;
-  for (int i : bysize)
-    if (panel(p->hb[i].rt)) { out.push_back(i); p->rt_panel = std::max(p->rt_panel, p->hb[i].rt); }
-  p->n_panel = (int)out.size();
-  for (int i : bysize)
-    if (!panel(p->hb[i].rt)) { out.push_back(i); p->rt_col = std::max(p->rt_col, p->hb[i].rt); }
-  p->n_col = N - p->n_panel;
+  int* cnt[3] = {&p->n_panel, &p->n_col, &p->n_panel8};
+  int* rtm[3] = {&p->rt_panel, &p->rt_col, &p->rt_panel8};
+  for (int k : {BFK_PANEL, BFK_PANEL8, BFK_COLUMN}) {
+    *cnt[k] = 0;
+    *rtm[k] = 0;
+    for (int i : bysize)
+      if (bf_choice(p, p->hb[i].rt) == k) {
+        out.push_back(i);
+        ++*cnt[k];
+        *rtm[k] = std::max(*rtm[k], p->hb[i].rt);
+      }
+  }
   return out;
 }
 
@@ -418,39 +435,42 @@ ahlp_status_t factor_blocks_per_block(ahlp_problem_t p, hipStream_t st, T* LB, T
   p->timer.end();
   p->timer.begin(AHLP_ST_FACTOR);
   for (int i = 0; i < p->N; ++i) {
-    const int rt = p->hb[i].rt;
-    if (block_factor_panel_fits(rt) && p->bf_kernel[rt] != 1)
-      launch_block_factor_panel<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info);
-    else
+    const int rt = p->hb[i].rt, k = bf_choice(p, rt);
+    if (k == BFK_COLUMN)
       launch_block_factor_col<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info);
+    else
+      launch_block_factor_panel<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info,
+                                   k == BFK_PANEL8 ? 8 : 4);
   }
   p->timer.end();
   HIPCHK(hipGetLastError());
   return AHLP_OK;
 }
 
-// The panel bucket fused (link columns, SYRK, block factor and Schur
-// contributions in one persistent launch); the column-kernel bucket, if any,
-// runs its own link, SYRK and column-factor launches on the side stream
-// beside it.
+// The four-wave panel bucket fused (link columns, SYRK, block factor and
+// Schur contributions in one persistent launch); the other buckets, if any,
+// run their own link, SYRK and factor launches on the side stream beside it.
 template <typename T>
 ahlp_status_t factor_blocks_fused(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV,
                                   const T* A) {
   p->timer.begin(AHLP_ST_FACTOR);
-  if (p->n_col > 0) {
+  const bool rest = p->n_panel8 + p->n_col > 0;
+  if (rest) {
     HIPCHK(hipEventRecord(p->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
     launch_link<T>(p->side, p->blk, p->col_link_items, p->ncol_link, p->n0, p->A, p->C, p->lptr,
                    p->lcol, p->lval, p->Dp, LB, p->PQ);
     launch_syrk<T>(p->side, p->blk, p->col_syrk_items, p->ncol_syrk, A, p->Dp, LB, p->delta);
-    launch_block_factor_col<T>(p->side, p->blk, p->bf_order + p->n_panel, p->n_col, p->rt_col, LB,
-                               LINV, p->PQ, p->info);
+    launch_block_factor_panel<T>(p->side, p->blk, p->bf_order + p->n_panel, p->n_panel8,
+                                 p->rt_panel8, LB, LINV, p->PQ, p->info, 8);
+    launch_block_factor_col<T>(p->side, p->blk, p->bf_order + p->n_panel + p->n_panel8, p->n_col,
+                               p->rt_col, LB, LINV, p->PQ, p->info);
     HIPCHK(hipEventRecord(p->ev_join, p->side));
   }
   launch_factor_fused<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, p->fused_queue, p->n0,
                          A, p->A, p->C, p->lptr, p->lcol, p->lval, p->Dp, LB, LINV, p->PQ,
                          p->delta, p->info, p->num_cu);
-  if (p->n_col > 0) HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
+  if (rest) HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
   p->timer.end();
   HIPCHK(hipGetLastError());
   return AHLP_OK;
@@ -472,12 +492,15 @@ ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, co
   p->timer.end();
   p->timer.begin(AHLP_ST_FACTOR);
   HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
-  if (p->n_panel > 0 && p->n_col > 0) {
-    // both buckets: the column-kernel bucket beside the panel bucket
+  const int nb8 = p->n_panel8, nbc = p->n_col;
+  const int* o8 = p->bf_order + p->n_panel;
+  const int* oc = o8 + nb8;
+  if (p->n_panel > 0 && nb8 + nbc > 0) {
+    // the eight-wave panel and the column buckets beside the four-wave one
     HIPCHK(hipEventRecord(p->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    launch_block_factor_col<T>(p->side, p->blk, p->bf_order + p->n_panel, p->n_col, p->rt_col, LB,
-                               LINV, p->PQ, p->info);
+    launch_block_factor_panel<T>(p->side, p->blk, o8, nb8, p->rt_panel8, LB, LINV, p->PQ, p->info, 8);
+    launch_block_factor_col<T>(p->side, p->blk, oc, nbc, p->rt_col, LB, LINV, p->PQ, p->info);
     HIPCHK(hipEventRecord(p->ev_join, p->side));
     launch_block_factor_panel<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, LB, LINV, p->PQ,
                                  p->info);
@@ -485,8 +508,8 @@ ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, co
   } else {
     launch_block_factor_panel<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, LB, LINV, p->PQ,
                                  p->info);
-    launch_block_factor_col<T>(st, p->blk, p->bf_order + p->n_panel, p->n_col, p->rt_col, LB, LINV,
-                               p->PQ, p->info);
+    launch_block_factor_panel<T>(st, p->blk, o8, nb8, p->rt_panel8, LB, LINV, p->PQ, p->info, 8);
+    launch_block_factor_col<T>(st, p->blk, oc, nbc, p->rt_col, LB, LINV, p->PQ, p->info);
   }
   p->timer.end();
   HIPCHK(hipGetLastError());
@@ -1454,15 +1477,17 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
   if (!p) return fail(AHLP_EINVAL, "null argument");
   if (measured) *measured = 0;
   const std::string arch = arch_name(p->device);
-  // rt values with a choice to make
+  // rt values with a choice to make (at least two kernels can hold them)
   std::vector<int> todo;
   for (int rt = 1; rt <= p->max_rt; ++rt) {
-    if (!block_factor_panel_fits(rt)) continue;
+    if (!block_factor_panel8_fits(rt)) continue;
     bool present = false;
     for (const auto& b : p->hb) present = present || b.rt == rt;
     if (present) todo.push_back(rt);
   }
-  // cached entries: "<arch> <rt> <panel|column> <us panel> <us column>"
+  // cached entries: "<arch> <rt> <panel|column|panel8> <us panel> <us column> [<us panel8>]"
+  // (a time of -1: the kernel cannot hold blocks of that rt)
+  static const char* names[3] = {"panel", "column", "panel8"};
   std::vector<std::string> keep;
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -1473,8 +1498,9 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
       int rt = 0;
       if (line.empty() || line[0] == '#' || !(ls >> a >> rt >> k)) continue;
       keep.push_back(line);
-      if (a == arch && rt >= 1 && rt <= p->max_rt && (k == "panel" || k == "column"))
-        p->bf_kernel[rt] = k == "panel" ? 0 : 1;
+      if (a != arch || rt < 1 || rt > p->max_rt) continue;
+      for (int q = 0; q < 3; ++q)
+        if (k == names[q]) p->bf_kernel[rt] = q;
     }
   }
   std::vector<int> need;
@@ -1498,19 +1524,21 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
       for (int i = 0; i < p->N; ++i)
         if (p->hb[i].rt == rt) hblk.push_back(i);
       HIPCHK(hipMemcpyAsync(p->bf_order, hblk.data(), sizeof(int) * hblk.size(), hipMemcpyHostToDevice, st));
-      double best[2] = {1e30, 1e30};
+      double best[3] = {1e30, 1e30, 1e30};
+      const bool can[3] = {block_factor_panel_fits(rt), true, block_factor_panel8_fits(rt)};
       for (int rep = 0; rep < 2; ++rep)
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 3; ++k) {
+          if (!can[k]) continue;
           launch_link<double>(st, p->blk, p->link_items, p->nlink, p->n0, p->A, p->C, p->lptr,
                               p->lcol, p->lval, p->Dp, p->LB, p->PQ);
           launch_syrk<double>(st, p->blk, p->syrk_items, p->nsyrk, p->A, p->Dp, p->LB, delta);
           HIPCHK(hipEventRecord(e0, st));
-          if (k == 0)
-            launch_block_factor_panel<double>(st, p->blk, p->bf_order, (int)hblk.size(), rt, p->LB,
-                                              p->LINV, p->PQ, p->info);
-          else
+          if (k == BFK_COLUMN)
             launch_block_factor_col<double>(st, p->blk, p->bf_order, (int)hblk.size(), rt, p->LB,
                                             p->LINV, p->PQ, p->info);
+          else
+            launch_block_factor_panel<double>(st, p->blk, p->bf_order, (int)hblk.size(), rt, p->LB,
+                                              p->LINV, p->PQ, p->info, k == BFK_PANEL8 ? 8 : 4);
           HIPCHK(hipEventRecord(e1, st));
           HIPCHK(hipEventSynchronize(e1));
           float ms = 0.f;
@@ -1519,11 +1547,16 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
         }
       // decided on the values the cache records (to the nanosecond), so a
       // table read back agrees with its own timings
-      for (double& v : best) v = std::round(v * 1e3) / 1e3;
-      p->bf_kernel[rt] = best[0] <= best[1] ? 0 : 1;
-      char buf[160];
-      std::snprintf(buf, sizeof buf, "%s %d %s %.3f %.3f", arch.c_str(), rt,
-                    p->bf_kernel[rt] == 0 ? "panel" : "column", best[0], best[1]);
+      int pick = -1;
+      for (int k = 0; k < 3; ++k) {
+        if (!can[k]) continue;
+        best[k] = std::round(best[k] * 1e3) / 1e3;
+        if (pick < 0 || best[k] < best[pick]) pick = k;
+      }
+      p->bf_kernel[rt] = pick;
+      char buf[192];
+      std::snprintf(buf, sizeof buf, "%s %d %s %.3f %.3f %.3f", arch.c_str(), rt, names[pick],
+                    can[0] ? best[0] : -1.0, best[1], can[2] ? best[2] : -1.0);
       fresh.push_back(buf);
     }
     (void)hipEventDestroy(e0);
@@ -1533,7 +1566,8 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
     if (measured) *measured = (int32_t)need.size();
     if (cache_path) {
       std::ofstream out(cache_path);
-      out << "# block-factor kernel per bordered tile-row count: arch rt kernel us_panel us_column\n";
+      out << "# block-factor kernel per bordered tile-row count: arch rt kernel us_panel us_column "
+             "us_panel8\n";
       for (const auto& l : keep) out << l << "\n";
       for (const auto& l : fresh) out << l << "\n";
       if (!out) return fail(AHLP_EINVAL, "cannot write the tuning cache %s", cache_path);

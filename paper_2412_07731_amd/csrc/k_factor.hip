@@ -366,14 +366,14 @@ __global__ __launch_bounds__(256) void k_block_factor(const BlockInfo* __restric
 
 // Schur contribution of block i: PQ = F D F' - X X' with X = W_i' (the
 // bordered rows of the factor), in FP64 whatever the factor precision.  The
-// workgroup's four waves take the tile rows rr = w, w + 4, ...; row rr's tiles
+// workgroup's nw waves take the tile rows rr = w, w + nw, ...; row rr's tiles
 // (rr, cc), cc <= rr, go in groups of SC_G sharing the loads of X(rr, q), and
 // the tiles of step q + 1 are requested before the MFMAs of step q.
 template <typename T>
 __device__ __forceinline__ void schur_rows(const BlockInfo& b, const T* __restrict__ LB,
-                                           double* __restrict__ PQ, int w, int lane) {
+                                           double* __restrict__ PQ, int w, int lane, int nw = 4) {
   constexpr int SC_G = 4;
-  for (int rr = w; rr < b.kt; rr += 4) {
+  for (int rr = w; rr < b.kt; rr += nw) {
     for (int cg = 0; cg <= rr; cg += SC_G) {
       const int ng = min(SC_G, rr + 1 - cg);
       d4 acc[SC_G];
@@ -495,26 +495,29 @@ struct WgSync {
 
 // Largest real diagonal entry of block b's M_i (threads 0..255, all of which
 // call it; s_max: 4 doubles of LDS).
-template <typename T, class Sync>
+template <typename T, int NW, class Sync>
 __device__ __forceinline__ double block_diag_max(const BlockInfo& b, const T* __restrict__ LB,
                                                  double* s_max, Sync& sy) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double md = 0.0;
-  for (int idx = tid; idx < b.m; idx += 256) {
+  for (int idx = tid; idx < b.m; idx += 64 * NW) {
     const int p = idx >> 4, i = idx & 15;
     md = fmax(md, (double)LB[lb_tile(b, p, p) + i * 17]);
   }
   for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off));
   if (lane == 0) s_max[w] = md;
   sy.sync();
-  return fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
+  double r = s_max[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) r = fmax(r, s_max[k]);
+  return r;
 }
 
 // The panel factorization of one bordered block by four waves (threads
 // 0..255), with pivot threshold thr; smem_raw is its dynamic LDS.  Sync
 // provides the barrier of the four waves and the wait for the inputs of panel
 // c0 (returns false when the wait was abandoned, and the factorization stops).
-template <typename T, int BF_RMAX, class Sync>
+template <typename T, int BF_RMAX, int NW, class Sync>
 __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__ LB,
                                              T* __restrict__ LINV, double* __restrict__ PQ,
                                              DevInfo* info, unsigned char* smem_raw, double thr,
@@ -531,7 +534,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
   T* colbuf = reinterpret_cast<T*>(smem_raw);          // rt tiles: the panel column just factored
   T* li = colbuf + (size_t)rt * TEP;                    // L_cc^-1
   T* dt = li + TEP;                                     // diagonal tile / its factor
-  T* scr = dt + TEP;                                    // 4 tiles: per-wave conversion
+  T* scr = dt + TEP;                                    // NW tiles: per-wave conversion
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row and address arithmetic stays scalar
   typedef typename Acc<T>::type AT;
@@ -555,11 +558,11 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
   for (int c0 = 0; c0 < mt; c0 += BF_PW) {
     const int pw = min(BF_PW, mt - c0);
     if (!sy.wait_panel(c0)) return;
-    // rows r = c0 + w + 4 t of this panel owned by the wave
+    // rows r = c0 + w + NW t of this panel owned by the wave
     AT acc[BF_RMAX][BF_PW];
 #pragma unroll
     for (int t = 0; t < BF_RMAX; ++t) {
-      const int r = c0 + w + 4 * t;
+      const int r = c0 + w + NW * t;
 #pragma unroll
       for (int j = 0; j < BF_PW; ++j) {
         acc[t][j] = AT{0, 0, 0, 0};
@@ -576,7 +579,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       BfOp<T> Ac[BF_RMAX], Bc[BF_PW];
 #pragma unroll
       for (int t = 0; t < BF_RMAX; ++t) {
-        const int r = c0 + w + 4 * t;
+        const int r = c0 + w + NW * t;
         if (r < rt) Ac[t] = bf_ld<T>(LB + lb_tile(b, r, k));
       }
 #pragma unroll
@@ -584,7 +587,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
         if (j < pw) Bc[j] = bf_ld<T>(LB + lb_tile(b, c0 + j, k));
 #pragma unroll
       for (int t = 0; t < BF_RMAX; ++t) {
-        const int r = c0 + w + 4 * t;
+        const int r = c0 + w + NW * t;
 #pragma unroll
         for (int j = 0; j < BF_PW; ++j)
           if (r < rt && j < pw && r >= c0 + j)
@@ -599,7 +602,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
     for (int j = 0; j < BF_PW; ++j) {
       if (j >= pw) break;
       const int c = c0 + j;
-      const int ow = (c - c0) & 3, ot = (c - c0) >> 2;
+      const int ow = (c - c0) % NW, ot = (c - c0) / NW;
       if (w == ow) {
 #pragma unroll
         for (int t = 0; t < BF_RMAX; ++t)
@@ -616,7 +619,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       const BfOp<T> lio = ld_op(li);
 #pragma unroll
       for (int t = 0; t < BF_RMAX; ++t) {
-        const int r = c0 + w + 4 * t;
+        const int r = c0 + w + NW * t;
         if (r < rt && r > c) {
           T* dst = LB + lb_tile(b, r, c);
           T* cb = colbuf + (size_t)(r - c0) * TEP;
@@ -657,7 +660,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
         const BfOp<T> y = ld_op(colbuf + (size_t)(c2 - c0) * TEP);
 #pragma unroll
         for (int t = 0; t < BF_RMAX; ++t) {
-          const int r = c0 + w + 4 * t;
+          const int r = c0 + w + NW * t;
           if (r < rt && r >= c2) {
             if constexpr (TR) {
               // X' -= L(c', c) L(r, c)': A operand from LDS, B operand the
@@ -677,24 +680,24 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
   }
   // the block's Schur contribution while its W' tiles are still in L2 (the
   // loop's last barrier has made every wave's stores visible)
-  schur_rows<T>(b, LB, PQ, w, lane);
+  schur_rows<T>(b, LB, PQ, w, lane, NW);
   // each wave counts the pivots of the diagonal tiles it factored
   if (lane == 0 && cnt) atomicAdd(&info->pivots, cnt);
 }
 
-template <typename T, int BF_RMAX>
-__global__ __launch_bounds__(256, 2) void k_block_factor_panel(const BlockInfo* __restrict__ blk,
-                                                               const int* __restrict__ order,
-                                                               T* __restrict__ LB,
-                                                               T* __restrict__ LINV,
-                                                               double* __restrict__ PQ,
-                                                               DevInfo* info) {
+// Standalone panel kernel: NW waves per block (4: two workgroups per CU, for
+// bordered blocks of up to 4 BF_RMAX tile rows; 8: one per CU, up to
+// 8 BF_RMAX).
+template <typename T, int BF_RMAX, int NW>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void k_block_factor_panel(
+    const BlockInfo* __restrict__ blk, const int* __restrict__ order, T* __restrict__ LB,
+    T* __restrict__ LINV, double* __restrict__ PQ, DevInfo* info) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double s_max[4];
+  __shared__ double s_max[NW];
   const BlockInfo b = blk[order[blockIdx.x]];
   WgSync sy;
-  const double thr = PIVOT_REL * fmax(block_diag_max<T>(b, LB, s_max, sy), 0.0);
-  panel_factor<T, BF_RMAX>(b, LB, LINV, PQ, info, smem_raw, thr, sy);
+  const double thr = PIVOT_REL * fmax(block_diag_max<T, NW>(b, LB, s_max, sy), 0.0);
+  panel_factor<T, BF_RMAX, NW>(b, LB, LINV, PQ, info, smem_raw, thr, sy);
 }
 
 // ------------------------------------------------- a1-a5 in one launch
@@ -972,7 +975,7 @@ __global__ __launch_bounds__(512, 1) void k_factor_fused(
       const double thr = PIVOT_REL * fmax(dmax, 0.0);
       sy.slot = sl;
       sy.mtp = MT;
-      panel_factor<T, BF_RMAX>(b, LB, LINV, PQ, info, smem_raw, thr, sy);
+      panel_factor<T, BF_RMAX, 4>(b, LB, LINV, PQ, info, smem_raw, thr, sy);
       if (!sy.ok) return;
       sy.sync();               // every factor wave is done with the slot
       if (!sy.ok) return;
@@ -1130,22 +1133,28 @@ template void launch_link<float>(hipStream_t, const BlockInfo*, const int2*, int
                                  const double*, const double*, const int*, const int*,
                                  const double*, const double*, float*, double*);
 
-// Panel kernel for blocks of at most 4*BF_RMAX_MAX bordered tile rows (it also
-// forms their Schur contributions); workgroup w takes block order[w].
+// Panel kernel (it also forms the blocks' Schur contributions); workgroup w
+// takes block order[w].  Four waves per block for bordered blocks of up to
+// 4 BF_RMAX_MAX tile rows (five rows per wave up to 20, six up to 24), or
+// eight waves (five rows each) for blocks of up to 8 * 5 tile rows.
 template <typename T>
 void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
-                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info) {
+                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info, int waves) {
   if (n == 0) return;
-  // LDS: the panel column (max_rt tiles), L_cc^-1, the diagonal tile and 4
-  // per-wave tiles, at the form's leading dimension
-  if (max_rt <= 20) {
-    const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<5>::LD * sizeof(T);
-    hipLaunchKernelGGL((k_block_factor_panel<T, 5>), dim3(n), dim3(256), shmem, st, blk, order, LB,
-                       LINV, PQ, info);
+  // LDS: the panel column (max_rt tiles), L_cc^-1, the diagonal tile and one
+  // per-wave tile, at the form's leading dimension
+  if (waves == 8) {
+    const size_t shmem = (size_t)(max_rt + 2 + 8) * TS * BfLd<5>::LD * sizeof(T);
+    hipLaunchKernelGGL((k_block_factor_panel<T, 5, 8>), dim3(n), dim3(512), shmem, st, blk, order,
+                       LB, LINV, PQ, info);
+  } else if (max_rt <= 20) {
+    const size_t shmem = (size_t)(max_rt + 2 + 4) * TS * BfLd<5>::LD * sizeof(T);
+    hipLaunchKernelGGL((k_block_factor_panel<T, 5, 4>), dim3(n), dim3(256), shmem, st, blk, order,
+                       LB, LINV, PQ, info);
   } else {
-    const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<6>::LD * sizeof(T);
-    hipLaunchKernelGGL((k_block_factor_panel<T, 6>), dim3(n), dim3(256), shmem, st, blk, order, LB,
-                       LINV, PQ, info);
+    const size_t shmem = (size_t)(max_rt + 2 + 4) * TS * BfLd<6>::LD * sizeof(T);
+    hipLaunchKernelGGL((k_block_factor_panel<T, 6, 4>), dim3(n), dim3(256), shmem, st, blk, order,
+                       LB, LINV, PQ, info);
   }
 }
 // The fused launch over the panel bucket (blocks order[0, n), bordered tile
@@ -1190,10 +1199,11 @@ void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* or
   hipLaunchKernelGGL(k_schur_contrib<T>, dim3(n), dim3(256), 0, st, blk, order, LB, PQ);
 }
 bool block_factor_panel_fits(int rt) { return rt <= 4 * BF_RMAX_MAX; }
+bool block_factor_panel8_fits(int rt) { return rt <= 8 * 5; }
 template void launch_block_factor_panel<double>(hipStream_t, const BlockInfo*, const int*, int, int,
-                                                double*, double*, double*, DevInfo*);
+                                                double*, double*, double*, DevInfo*, int);
 template void launch_block_factor_panel<float>(hipStream_t, const BlockInfo*, const int*, int, int,
-                                               float*, float*, double*, DevInfo*);
+                                               float*, float*, double*, DevInfo*, int);
 template void launch_block_factor_col<double>(hipStream_t, const BlockInfo*, const int*, int, int,
                                               double*, double*, double*, DevInfo*);
 template void launch_block_factor_col<float>(hipStream_t, const BlockInfo*, const int*, int, int,

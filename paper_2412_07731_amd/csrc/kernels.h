@@ -23,11 +23,13 @@ void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int ni
 // largest bordered tile-row count among the n blocks.
 template <typename T>
 void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
-                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info);
+                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info,
+                               int waves = 4);
 template <typename T>
 void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* order, int n,
                              int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info);
-bool block_factor_panel_fits(int rt);
+bool block_factor_panel_fits(int rt);    // the four-wave form
+bool block_factor_panel8_fits(int rt);   // the eight-wave form
 // a1-a5 for the panel bucket in one persistent launch (link columns, SYRK,
 // panel factorization and Schur contributions); num_cu: compute units.
 template <typename T>

@@ -80,7 +80,7 @@ def test_graph_recaptured_after_autotune(dev, tmp_path):
                       for j in range(inst.N)})
         import torch as _t
         arch = _t.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-        path.write_text("".join(f"{arch} {rt} column 1.0 0.5\n" for rt in rts if rt <= 24))
+        path.write_text("".join(f"{arch} {rt} column 1.0 0.5 1.0\n" for rt in rts if rt <= 40))
         assert P.autotune(str(path)) == 0
         e1 = P.ipm()
         g1 = P.ipm(graph=1)

@@ -81,9 +81,15 @@ def test_autotune_table(dev, tmp_path):
         n = P.autotune(path)
         rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
         assert n >= 1 and len(rows) == n
-        for arch, rt, kern, us_p, us_c in rows:
-            assert 1 <= int(rt) <= 24
-            assert kern == ("panel" if float(us_p) <= float(us_c) else "column")
+        kinds = set()
+        for arch, rt, kern, us_p, us_c, us_p8 in rows:
+            assert 1 <= int(rt) <= 40
+            t = {"panel": float(us_p), "column": float(us_c), "panel8": float(us_p8)}
+            t = {k: v for k, v in t.items() if v >= 0}          # -1: the kernel cannot hold them
+            assert t[kern] == min(t.values()), (rt, kern, t)
+            assert (int(rt) <= 24) == ("panel" in t)
+            kinds.add(kern)
+        print("autotuned kernels:", sorted(kinds), flush=True)
         x, y, z, r = P.ipm()
         assert r["status"] == 0
         assert abs(r["primal_obj"] - inst.fstar) <= 1e-7 * max(1.0, abs(inst.fstar))
