@@ -10,7 +10,8 @@ SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
 factorization, predictor and corrector solves with FP64 refinement.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--no-uneven]
-                    [--no-general] [--profile [n512|uneven|general]]
+                    [--no-general] [--profile [n512|uneven|general]] [--fp32]
+                    [--launch batched|fused|per_block]
 
 The line also carries the sensitivity workload (N=256, nondegenerate): the
 differentiable solve, one backward pass (transposed Newton solve) and 64
@@ -419,6 +420,8 @@ def main():
                     help="short run for profilers: one fully timed n512 solve (default), or one "
                          "FP64 solve of the uneven or the general-form workload")
     ap.add_argument("--fp32", action="store_true", help="time the FP32+refine path as the main line")
+    ap.add_argument("--launch", default="batched", choices=["batched", "fused", "per_block"],
+                    help="launch mode of the factorization stages for the main line")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-sens", action="store_true", help="skip the sensitivity workload")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-block workload")
@@ -466,6 +469,7 @@ def main():
     fl = flops(inst)
     torch.cuda.set_device(0)
     P = Problem(inst)
+    P.set_launch(mode=args.launch)
     if args.profile:
         args.steps, args.warmup = 1, 0
         copy_calibration()

@@ -302,8 +302,11 @@ ahlp_status_t ahlp_problem_set_launch(ahlp_problem_t p, int32_t mode);
  * blocks' inputs) and, with a cache_path, appended to the file as
  * "<arch> <rt> <panel|column|panel8> <us panel> <us column> <us panel8>"
  * (-1 for a kernel that cannot hold the blocks).  *measured (host, may be
- * NULL) receives the number of rt values timed.  Later factorizations use the
- * choices.  Overwrites the factors (factor again before solving).
+ * NULL) receives the number of rt values timed.  Since buckets of different
+ * kernels run side by side and share the CUs, the whole factorization is then
+ * timed with these choices and with the default rule, and the faster is
+ * kept for later factorizations.  Overwrites the factors (factor again
+ * before solving).
  * Synchronizes `stream`.  Errors: AHLP_EINVAL (also for an unwritable cache
  * file), AHLP_EHIP. */
 ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* measured,

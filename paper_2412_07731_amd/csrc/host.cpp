@@ -1573,6 +1573,55 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
       if (!out) return fail(AHLP_EINVAL, "cannot write the tuning cache %s", cache_path);
     }
   }
+  // The choices per rt are measured one rt at a time; run together, buckets
+  // interact (a small bucket of eight-wave workgroups holds whole CUs that the
+  // large four-wave bucket beside it would use).  So the whole factorization
+  // is timed with the tuned choices and with the default rule, and the
+  // faster plan is kept.
+  {
+    const std::vector<int> tuned = p->bf_kernel;
+    bool differs = false;
+    for (int rt = 1; rt <= p->max_rt; ++rt) {
+      const int k = tuned[rt];
+      std::vector<int> dflt(p->max_rt + 1, -1);
+      std::swap(p->bf_kernel, dflt);
+      const int d = bf_choice(p, rt);
+      std::swap(p->bf_kernel, dflt);
+      bool present = false;
+      for (const auto& b : p->hb) present = present || b.rt == rt;
+      if (present && k >= 0 && k != d) differs = true;
+    }
+    if (differs) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      const int saved_mode = p->launch_mode;
+      p->launch_mode = AHLP_LAUNCH_BATCHED;
+      p->delta = 1e-6;
+      launch_fill(st, p->n_tot, 1.0, p->ones);
+      CHK(prep_scaling(p, p->ones, p->ones, 1e-8, st));
+      double t_plan[2] = {1e30, 1e30};
+      for (int rep = 0; rep < 3; ++rep)
+        for (int q = 0; q < 2; ++q) {
+          if (q == 0) p->bf_kernel = tuned;
+          else p->bf_kernel.assign(p->max_rt + 1, -1);
+          CHK(set_buckets(p, st));
+          HIPCHK(hipEventRecord(e0, st));
+          CHK(factor_blocks<double>(p, st, p->LB, p->LINV, p->A));
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) t_plan[q] = std::min(t_plan[q], (double)ms);   // rep 0 warms up
+        }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      p->launch_mode = saved_mode;
+      p->factored = false;
+      if (t_plan[0] <= t_plan[1]) p->bf_kernel = tuned;
+      else p->bf_kernel.assign(p->max_rt + 1, -1);
+    }
+  }
   CHK(set_buckets(p, st));   // (captured graphs hold the old buckets: they are captured again)
   return AHLP_OK;
 }
