@@ -6,7 +6,8 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 The GPU library never calls it and there is no CPU fallback built on it.
 
 Modules
-  lp         constraint operator, norms and the full sparse matrix (Sec. 2.2, 3.2)
+  lp         constraint operator, norms and the full sparse matrix (Sec. 2.2, 3.2;
+             block, link and global rows)
   dense_kkt  brute-force dense solves of the Newton system (Sec. 2.3)
   newton     block elimination: factorization Alg. 2, solve Alg. 3 (Sec. 3.2)
   ipm        Mehrotra predictor-corrector driver (Sec. 2.3; constants are readings)
@@ -19,7 +20,10 @@ fusion or reordering beyond the block elimination the paper states.
 
 Parity status
   newton.factor / newton.solve  pinned: dense LU of the full Newton system,
-                                minimum-norm least squares, App. A structure
+                                minimum-norm least squares, App. A structure;
+                                with global rows in the border (the dense layer
+                                of Sec. 4.1): dense LU, the border's inertia
+                                (ng, n0), planted mistakes
   ipm.solve                     pinned: known optimum of the generated LP,
                                 KKT conditions, scipy's HiGHS on small cases;
                                 the iterate trajectory itself is parity unpinned

@@ -56,10 +56,10 @@ def solve_regularized(inst, x, z, rx, ry, rz, rho, delta):
 
 
 def schur_indices(inst):
-    """Indices of (y_L, x_0) inside the augmented vector [x; y]: the unknowns
-    that the block elimination keeps in its Schur complement."""
+    """Indices of (y_L, y_G, x_0) inside the augmented vector [x; y]: the
+    unknowns that the block elimination keeps in its Schur complement."""
     n_tot = int(inst.n.sum()) + inst.n0
     m_blocks = int(inst.m.sum())
-    yl = n_tot + m_blocks + np.arange(int(inst.l.sum()))
+    ylg = n_tot + m_blocks + np.arange(int(inst.l.sum()) + lp.ng(inst))
     x0 = int(inst.n.sum()) + np.arange(inst.n0)
-    return np.concatenate([yl, x0])
+    return np.concatenate([ylg, x0])

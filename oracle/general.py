@@ -33,6 +33,15 @@ its rows are its equality rows, its inequality rows (block 1: then the x_0
 rows) and the upper-bound rows; x_0 is its variables then x- of its free
 ones; link pair j has its equality rows then its inequality rows.
 
+Dense layer (``dense=True``; the HSCA dense layer of Sec. 4.1): global rows
+and the x_0-only equality rows are kept whole as global rows of the standard
+form (Wg_i x_i + ... + Wg_0 x_0 = b_G), neither chained nor eliminated.  An
+inequality global row gets its slack t (bounds [dg, fg]) as a new linking
+variable: Wg x - t = 0, t an x_0 column after x_0's own and x- columns, in
+global row order; its upper-bound slack row (if both sides are finite) goes to
+block 1 like any other x_0 column's.  Global rows of the standard form: those
+of the general instance in order, then the x_0-only equality rows.
+
 Built here row by row from the global rows of the general instance and a
 list of standard columns per original variable.
 """
@@ -210,12 +219,12 @@ def chain(g: GeneralInstance):
     return out, np.array(keep, dtype=np.int64)
 
 
-def reformulate(g: GeneralInstance):
+def reformulate(g: GeneralInstance, dense=False):
     """Standard-form Instance, and for every original variable its
     (offset, [(block or -1 for x_0, column, sign)]) so x can be recovered
-    (global rows are chained first; their partial sums are dropped from the
-    list)."""
-    if g.A0 is not None and g.A0.shape[0]:
+    (global rows are chained first, unless dense; their partial sums are
+    dropped from the list)."""
+    if not dense and g.A0 is not None and g.A0.shape[0]:
         h, bas, non, u, V = eliminate_x0(g)
         inst, var, const = reformulate(h)
         # x_0 entries: x_N,k as reformulated; x_B,q = u_q - V_q x_N
@@ -232,7 +241,7 @@ def reformulate(g: GeneralInstance):
                 terms += [(blk, col, -V[q, k] * sgn) for blk, col, sgn in tk]
             full[xs + j] = (off, terms)
         return inst, full, const + 0.0
-    if g.ng:
+    if not dense and g.ng:
         gc, keep = chain(g)
         inst, var, const = reformulate(gc)
         return inst, [var[k] for k in keep], const
@@ -283,6 +292,7 @@ def reformulate(g: GeneralInstance):
     for j in range(N - 1):
         ineq_home += [j] * li[j]
     # 3. slacks, per block in the documented order: own rows, pair i rows, x_0 rows
+    mfirst_eq = np.concatenate([[0], np.cumsum(g.m)]).astype(np.int64)
     first = np.concatenate([[0], np.cumsum(mi)]).astype(np.int64)
     lfirst = int(first[-1]) + mi0 + np.concatenate([[0], np.cumsum(li)]).astype(np.int64)
     slack = {}                   # inequality row -> (blk, col, sign, offset)
@@ -299,6 +309,33 @@ def reformulate(g: GeneralInstance):
             else:
                 c = blocks[i].add('t', np.inf)
                 slack[r] = (i, c, -1.0, fv[r])
+    # global rows in the order of the general instance, then the x_0-only
+    # equality rows: ('eq', row of Aeq) or ('in', row of Ain); the slacks of
+    # the inequality ones are x_0 columns
+    grows = []
+    if g.ng:
+        ge = int(mfirst_eq[-1]) + int(g.l.sum())
+        gi = int(lfirst[-1])
+        for k in range(g.ng):
+            if g.dg[k] == g.fg[k]:
+                grows.append(('eq', ge))
+                ge += 1
+            else:
+                grows.append(('in', gi))
+                gi += 1
+        a0 = ge
+    else:
+        a0 = int(mfirst_eq[-1]) + int(g.l.sum())
+    if g.A0 is not None and g.A0.shape[0]:
+        grows += [('eq', a0 + q) for q in range(g.A0.shape[0])]
+    for kind, r in grows:
+        if kind == 'in':
+            if np.isfinite(dv[r]):
+                c = x0c.add('t', fv[r] - dv[r] if np.isfinite(fv[r]) else np.inf)
+                slack[r] = (-1, c, 1.0, dv[r])
+            else:
+                c = x0c.add('t', np.inf)
+                slack[r] = (-1, c, -1.0, fv[r])
     # 4. upper-bound slacks
     ubrows = [[] for _ in range(N)]   # (column holder block, column) bounded
     for i in range(N):
@@ -393,6 +430,21 @@ def reformulate(g: GeneralInstance):
         F0r.append(np.array(f0).reshape(len(rows), n0s))
         bl += rh
 
+    Wg = [[] for _ in range(N)]
+    Wg0, bg = [], []
+    for kind, r in grows:
+        parts, x0, sh = std_row(Aeq if kind == 'eq' else Ain, r)
+        if kind == 'in':
+            blk, c, sgn, toff = slack[r]
+            x0[c] -= sgn
+            rhs = toff - sh
+        else:
+            rhs = beq[r] - sh
+        for i in range(N):
+            Wg[i].append(parts.get(i, np.zeros(ncol[i])))
+        Wg0.append(x0)
+        bg.append(rhs)
+
     A = [np.array(Ab[i]).reshape(len(Ab[i]), ncol[i]) for i in range(N)]
     C = [np.array(Cb[i]).reshape(len(Cb[i]), n0s) for i in range(N)]
     F0 = np.vstack(F0r) if F0r and any(np.any(f) for f in F0r) else None
@@ -408,8 +460,12 @@ def reformulate(g: GeneralInstance):
                     n=np.array(ncol, dtype=np.int64),
                     l=np.array([f.shape[0] for f in FR], dtype=np.int64), A=A, C=C, FR=FR,
                     FL=FL, F0=F0, b=np.concatenate([np.concatenate([np.asarray(v) for v in bb])
-                                                    if N else np.zeros(0), np.asarray(bl)]),
+                                                    if N else np.zeros(0), np.asarray(bl),
+                                                    np.asarray(bg)]),
                     c=np.concatenate(cstd))
+    if grows:
+        inst.Wg = [np.array(Wg[i]).reshape(len(grows), ncol[i]) for i in range(N)]
+        inst.Wg0 = np.array(Wg0).reshape(len(grows), n0s)
     return inst, var, const
 
 
@@ -425,9 +481,9 @@ def recover(g: GeneralInstance, inst: Instance, var, x_std):
     return x
 
 
-def solve(g: GeneralInstance, opts=None):
+def solve(g: GeneralInstance, opts=None, dense=False):
     """Oracle solve of a general instance: (x, objective, ipm result)."""
-    inst, var, _ = reformulate(g)
+    inst, var, _ = reformulate(g, dense=dense)
     r = ipm.solve(inst, opts) if opts is not None else ipm.solve(inst)
     x = recover(g, inst, var, r.x)
     return x, float(g.c @ x), r

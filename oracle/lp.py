@@ -1,5 +1,6 @@
 """Constraint operator of the arrowhead LP (Sec. 2.2 standard form, Sec. 3.2
-block structure restricted to equalities and local links, Sec. 3.3).
+block structure restricted to equalities; local links and global linking rows,
+Sec. 3.3).  Rows: the blocks, then the link pairs, then the global rows.
 
 Test infrastructure only (see package docstring).
 """
@@ -16,11 +17,16 @@ def offsets(inst):
     return xo, yo, lo
 
 
+def ng(inst):
+    """Number of global linking rows."""
+    return 0 if getattr(inst, "Wg", None) is None else int(inst.Wg[0].shape[0])
+
+
 def matvec(inst, x):
-    """A x for the full constraint matrix (block rows, then link rows)."""
+    """A x for the full constraint matrix (block rows, link rows, global rows)."""
     xo, yo, lo = offsets(inst)
     x0 = x[xo[-1]:]
-    out = np.empty(int(yo[-1] + lo[-1]))
+    out = np.empty(int(yo[-1] + lo[-1]) + ng(inst))
     for i in range(inst.N):
         out[yo[i]:yo[i + 1]] = inst.A[i] @ x[xo[i]:xo[i + 1]] + inst.C[i] @ x0
     base = yo[-1]
@@ -29,6 +35,12 @@ def matvec(inst, x):
         if inst.F0 is not None:
             r = r + inst.F0[lo[j]:lo[j + 1]] @ x0
         out[base + lo[j]: base + lo[j + 1]] = r
+    gb = int(base + lo[-1])
+    for k in range(ng(inst)):
+        r = 0.0
+        for i in range(inst.N):
+            r += inst.Wg[i][k] @ x[xo[i]:xo[i + 1]]
+        out[gb + k] = r + inst.Wg0[k] @ x0
     return out
 
 
@@ -47,6 +59,11 @@ def rmatvec(inst, y):
         out[xo[j + 1]:xo[j + 2]] += inst.FL[j].T @ yl
         if inst.F0 is not None:
             out[xo[-1]:] += inst.F0[lo[j]:lo[j + 1]].T @ yl
+    if ng(inst):
+        yg = y[int(base + lo[-1]):]
+        for i in range(inst.N):
+            out[xo[i]:xo[i + 1]] += inst.Wg[i].T @ yg
+        out[xo[-1]:] += inst.Wg0.T @ yg
     return out
 
 
@@ -55,7 +72,7 @@ def full_matrix(inst):
     xo, yo, lo = offsets(inst)
     N = inst.N
     n_tot = int(xo[-1]) + inst.n0
-    m_tot = int(yo[-1] + lo[-1])
+    m_tot = int(yo[-1] + lo[-1]) + ng(inst)
     rows = []
     for i in range(N):
         row = [None] * (N + 1)
@@ -70,7 +87,12 @@ def full_matrix(inst):
         link[r, xo[j + 1]:xo[j + 2]] = inst.FL[j]
         if inst.F0 is not None:
             link[r, xo[-1]:] = inst.F0[lo[j]:lo[j + 1]]
-    full = sp.vstack([blocks, link.tocsr()], format="csr")
+    glob = sp.lil_matrix((ng(inst), n_tot))
+    if ng(inst):
+        for i in range(N):
+            glob[:, xo[i]:xo[i + 1]] = inst.Wg[i]
+        glob[:, xo[-1]:] = inst.Wg0
+    full = sp.vstack([blocks, link.tocsr(), glob.tocsr()], format="csr")
     assert full.shape == (m_tot, n_tot)
     return full
 

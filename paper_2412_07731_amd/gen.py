@@ -9,11 +9,13 @@ x >= 0 bounds and local (two-link) linking constraints (Sec. 3.3):
 
     block rows   A_i x_i + C_i x_0                   = b_i      i = 1..N
     link rows    FR_j x_j + FL_j x_{j+1} + F0_j x_0  = b_Lj     j = 1..N-1
+    global rows  Wg_1 x_1 + ... + Wg_N x_N + Wg_0 x_0 = b_G     (optional)
 
 Here ``A_i`` is the paper's B_i, ``C_i`` the paper's A_i (coupling to the
 linking variables x_0), ``FR_j`` the paper's local block F_j and ``FL_j`` the
-paper's F'_j.  Canonical vector order: x = [x_1..x_N, x_0], y = [y_1..y_N, y_L]
-with y_L listing the link pairs in order.
+paper's F'_j; ``Wg_i`` are the global linking rows (the paper's F with
+global support, Sec. 3.3).  Canonical vector order: x = [x_1..x_N, x_0],
+y = [y_1..y_N, y_L, y_G] with y_L listing the link pairs in order.
 
 Known optimum (complementary primal/dual pair chosen first, data derived):
   * x*: in every block exactly floor(n_i/2) entries ~U[0.5, 2], the rest 0;
@@ -25,8 +27,10 @@ Storage-continuity links: row k of pair j has +1 on variable n_j - l_j + k of
 block j and -1 on variable k of block j+1 (energy-system storage balance).
 
 Draw order (fixed; PCG64(seed)): random sizes (m_i, then l_j), then per block
-A_i (mask, values, zero-row redraws) and C_i (mask, values), then x* positions
-and values per block and for x_0, then z* values, then y*.
+A_i (mask, values, zero-row redraws) and C_i (mask, values), then (only with
+ng > 0 global rows) per block and row three distinct columns and their values
+~U[-1, 1], and Wg_0 (mask, values), then x* positions and values per block and
+for x_0, then z* values, then y*.
 
 Nondegenerate variant (``nondegenerate=True``, needs n0 = 0), for the
 sensitivity workload: block i gets exactly m_i + l_i positive x* entries (l_i
@@ -60,6 +64,10 @@ CONFIGS = {
     "sens": dict(N=256, m=256, n=512, l=16, n0=0, density=0.10, nondegenerate=True),
     # small nondegenerate instance for dense reference checks
     "tiny_nd": dict(N=8, m=32, n=64, l=4, n0=0, density=0.30, nondegenerate=True),
+    # global linking rows kept whole (each touches every block and x_0): tiny
+    # with 3 of them, and a mid-size case with 20 (a border of 20 + 16 rows)
+    "tiny_g": dict(N=8, m=32, n=64, l=4, n0=8, density=0.30, ng=3),
+    "mid_g": dict(N=40, m=48, n=96, l=16, n0=16, density=0.10, ng=20),
 }
 
 
@@ -77,8 +85,10 @@ class Instance:
     FR: List[np.ndarray]          # pair j: l_j x n_j      (block j's part)
     FL: List[np.ndarray]          # pair j: l_j x n_{j+1}  (block j+1's part)
     F0: Optional[np.ndarray]      # (sum l) x n0, or None for zero
-    b: np.ndarray
+    b: np.ndarray                 # [block rows, link rows, global rows]
     c: np.ndarray
+    Wg: Optional[List[np.ndarray]] = field(default=None)   # global rows: ng x n_i per block
+    Wg0: Optional[np.ndarray] = field(default=None)        # their x_0 part, ng x n0
     xstar: np.ndarray = field(default=None)
     ystar: np.ndarray = field(default=None)
     zstar: np.ndarray = field(default=None)
@@ -86,12 +96,17 @@ class Instance:
     basis: Optional[list] = field(default=None)   # nondegenerate variant: positive x* indices per block
 
     @property
+    def ng(self) -> int:
+        """Global linking rows (each over every block and x_0)."""
+        return 0 if self.Wg is None else int(self.Wg[0].shape[0])
+
+    @property
     def n_tot(self) -> int:
         return int(self.n.sum()) + self.n0
 
     @property
     def m_tot(self) -> int:
-        return int(self.m.sum()) + int(self.l.sum())
+        return int(self.m.sum()) + int(self.l.sum()) + self.ng
 
     def xoff(self) -> np.ndarray:
         """Start of each block's variables in x (length N+1; last = x_0 start)."""
@@ -172,6 +187,20 @@ def generate(config="tiny", seed=0, **overrides) -> Instance:
         FL.append(fl)
     F0 = None
 
+    # global rows: three random entries per row in every block, ~U[-1, 1],
+    # and the x_0 part at the block density
+    ng = int(cfg.get("ng", 0))
+    Wg = Wg0 = None
+    if ng > 0:
+        Wg = []
+        for i in range(N):
+            W = np.zeros((ng, int(n[i])))
+            for k in range(ng):
+                cols = rng.choice(int(n[i]), size=min(3, int(n[i])), replace=False)
+                W[k, cols] = rng.uniform(-1.0, 1.0, size=cols.size)
+            Wg.append(W)
+        Wg0 = _sparse_block(rng, ng, n0, dens, False)
+
     # complementary optimum
     xs = []
     basis = None
@@ -206,11 +235,11 @@ def generate(config="tiny", seed=0, **overrides) -> Instance:
     xstar = np.concatenate(xs) if xs else np.zeros(0)
     zvals = rng.uniform(0.5, 2.0, size=xstar.size)
     zstar = np.where(xstar == 0.0, zvals, 0.0)
-    m_tot = int(m.sum() + l.sum())
+    m_tot = int(m.sum() + l.sum()) + ng
     ystar = rng.standard_normal(m_tot)
 
     inst = Instance(N=N, n0=n0, m=m, n=n, l=l, A=A, C=C, FR=FR, FL=FL, F0=F0,
-                    b=np.zeros(m_tot), c=np.zeros(xstar.size))
+                    b=np.zeros(m_tot), c=np.zeros(xstar.size), Wg=Wg, Wg0=Wg0)
     inst.xstar, inst.ystar, inst.zstar = xstar, ystar, zstar
     inst.basis = basis   # per block: the indices of the positive x* entries (nondegenerate only)
     inst.b = apply_A(inst, xstar)
@@ -235,6 +264,11 @@ def apply_A(inst: Instance, x: np.ndarray) -> np.ndarray:
         out[s] = inst.FR[j] @ x[xo[j]:xo[j + 1]] + inst.FL[j] @ x[xo[j + 1]:xo[j + 2]]
         if inst.F0 is not None:
             out[s] += inst.F0[lo[j]:lo[j + 1]] @ x0
+    base += lo[-1]
+    for k in range(inst.ng):
+        out[base + k] = sum(inst.Wg[i][k] @ x[xo[i]:xo[i + 1]] for i in range(inst.N))
+        if inst.n0:
+            out[base + k] += inst.Wg0[k] @ x0
     return out
 
 
@@ -253,6 +287,12 @@ def apply_At(inst: Instance, y: np.ndarray) -> np.ndarray:
         out[xo[j + 1]:xo[j + 2]] += inst.FL[j].T @ yl
         if inst.F0 is not None:
             out[x0s] += inst.F0[lo[j]:lo[j + 1]].T @ yl
+    if inst.ng:
+        yg = y[base + lo[-1]:]
+        for i in range(inst.N):
+            out[xo[i]:xo[i + 1]] += inst.Wg[i].T @ yg
+        if inst.n0:
+            out[x0s] += inst.Wg0.T @ yg
     return out
 
 

@@ -13,7 +13,10 @@ oracle IPM), to things other than itself:
   x_0 part; the substitution of eliminated x_0 entries without its constant
   part) fail the HiGHS pin;
 * the GPU path's reformulation (paper_2412_07731_amd.general, written
-  separately) produces the same standard-form instance.
+  separately) produces the same standard-form instance;
+* the dense layer (global rows and x_0-only equality rows kept whole, in the
+  border of S) reaches HiGHS's optimum of the untransformed LP too, and a
+  dropped x_0 part of its global rows fails that pin.
 """
 import numpy as np
 import pytest
@@ -158,3 +161,35 @@ def test_two_reformulations_agree(seed):
     assert abs(mp.const - const) <= 1e-12
     xs = np.random.default_rng(seed).uniform(0, 1, a.n_tot)
     assert np.allclose(general.from_standard(mp, xs), og.recover(g, b, var, xs), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_dense_layer_matches_highs(seed):
+    g = gen.generate_general("g_small", seed)
+    inst, var, _ = og.reformulate(g, dense=True)
+    # the global rows and the x_0-only equality rows stay whole: no chained
+    # partial sums, no eliminated x_0 entries
+    assert inst.ng == g.ng + g.A0.shape[0]
+    assert inst.n0 == g.n0 + int(np.sum(g.dg != g.fg)) + int(np.sum(np.isinf(g.lo[-g.n0:]) & np.isinf(g.up[-g.n0:])))
+    x, f, r = og.solve(g, dense=True)
+    assert r.status == "optimal"
+    fh = highs(g)
+    assert abs(f - fh) <= 1e-7 * max(1.0, abs(fh))
+    assert violation(g, x) <= 1e-7
+
+
+def test_planted_dense_layer_mistake_fails(monkeypatch):
+    """The global rows lose their x_0 part (Wg_0, which also holds the slacks
+    of the inequality global rows): the HiGHS pin catches it."""
+    g = gen.generate_general("g_small", 1)
+    fh = highs(g)
+    real = og.reformulate
+
+    def broken(gg, dense=False):
+        inst, var, const = real(gg, dense=dense)
+        inst.Wg0 = np.zeros_like(inst.Wg0)
+        return inst, var, const
+
+    monkeypatch.setattr(og, "reformulate", broken)
+    x, f, r = og.solve(g, dense=True)
+    assert r.status != "optimal" or abs(f - fh) > 1e-4 * max(1.0, abs(fh))

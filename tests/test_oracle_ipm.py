@@ -28,9 +28,25 @@ def test_tiny_reaches_known_optimum(seed):
     assert r.pivots == 0
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_global_rows_reach_known_optimum(seed):
+    """Global linking rows kept in the border of S (the dense layer): the
+    generated LP's known optimum and the KKT conditions."""
+    inst = gen.generate("tiny_g", seed)
+    assert inst.ng == 3
+    r = ipm.solve(inst)
+    assert r.status == "optimal"
+    f = inst.fstar
+    assert abs(r.pobj - f) <= 1e-7 * (1 + abs(f))
+    assert np.max(np.abs(r.x - inst.xstar)) <= 1e-6 * (1 + np.max(np.abs(inst.xstar)))
+    assert r.relgap <= 1e-8 and r.pinf <= 1e-8 and r.dinf <= 1e-8
+    assert r.pivots == 0
+
+
 @pytest.mark.parametrize("shape", [
     dict(N=3, m=5, n=11, l=2, n0=3, density=0.5),
     dict(N=4, m=(4, 8), n="2m", l=(1, 3), n0=2, density=0.4),
+    dict(N=4, m=(4, 8), n="2m", l=(1, 3), n0=2, density=0.4, ng=3),
 ])
 def test_matches_highs(shape):
     inst = gen.generate(shape, 21)

@@ -6,11 +6,12 @@ things other than itself:
 * a library special case: at x = z = e without regularization the primal step
   for the right-hand side (0, r, 0) is the minimum-norm solution of A dx = r,
   which numpy.linalg.lstsq returns;
-* the Schur complement: its inverse is the (y_L, x_0) block of the inverse of
-  the whole augmented matrix (block elimination leaves that block unchanged);
-  its zero pattern is App. A's (block tridiagonal plus border) and its nonzero
-  count meets App. A's bound; its link part is positive definite and its border
-  Schur complement negative definite.
+* the Schur complement: its inverse is the (y_L, y_G, x_0) block of the inverse
+  of the whole augmented matrix (block elimination leaves that block
+  unchanged); its zero pattern is App. A's (block tridiagonal plus border) and
+  its nonzero count meets App. A's bound; its link part is positive definite
+  and its border Schur complement negative definite, or, with global rows in
+  the border (the dense layer of Sec. 4.1), of inertia (ng, n0).
 """
 import numpy as np
 import pytest
@@ -19,8 +20,8 @@ from oracle import dense_kkt, lp, newton
 from paper_2412_07731_amd import gen
 
 
-def shaped(N, m, n, l, n0, seed=0, dens=0.4, F0=False):
-    inst = gen.generate(dict(N=N, m=m, n=n, l=l, n0=n0, density=dens), seed)
+def shaped(N, m, n, l, n0, seed=0, dens=0.4, F0=False, ng=0):
+    inst = gen.generate(dict(N=N, m=m, n=n, l=l, n0=n0, density=dens, ng=ng), seed)
     if F0:
         rng = np.random.default_rng(seed + 100)
         inst.F0 = rng.uniform(-1, 1, (int(inst.l.sum()), n0))
@@ -45,6 +46,12 @@ SHAPES = [
     dict(N=3, m=7, n=11, l=4, n0=1),
     dict(N=5, m=(3, 9), n="2m", l=(1, 3), n0=2),   # uneven blocks and pairs
     dict(N=8, m=32, n=64, l=4, n0=8),          # the tiny workload
+    # global rows in the border (the dense layer)
+    dict(N=1, m=6, n=12, l=0, n0=0, ng=2),     # border of global rows only
+    dict(N=4, m=6, n=12, l=2, n0=0, ng=1),
+    dict(N=3, m=7, n=11, l=4, n0=1, ng=3),
+    dict(N=5, m=(3, 9), n="2m", l=(1, 3), n0=2, ng=4),
+    dict(N=8, m=32, n=64, l=4, n0=8, ng=3),    # tiny_g
 ]
 
 
@@ -125,7 +132,7 @@ def test_textbook_normal_equations():
     assert rel(dy, dy_ref) < 1e-12
 
 
-@pytest.mark.parametrize("shape", [SHAPES[3], SHAPES[6], SHAPES[7]])
+@pytest.mark.parametrize("shape", [SHAPES[3], SHAPES[6], SHAPES[7], SHAPES[10], SHAPES[11]])
 def test_schur_is_block_of_augmented_inverse(shape):
     inst = shaped(**shape, F0=True)
     x, z, _ = point(inst, seed=5)
@@ -161,6 +168,30 @@ def test_schur_structure_and_signs(tiny):
     assert np.max(np.linalg.eigvalsh(Bs)) < 0
     # symmetric
     assert np.array_equal(S, S.T)
+
+
+@pytest.mark.parametrize("ng", [1, 3])
+def test_dense_layer_structure_and_inertia(ng):
+    """With global rows the border of S is [y_G, x_0]: T keeps App. A's pattern,
+    E and S00 are dense, and the border Schur complement has exactly ng
+    positive and n0 negative eigenvalues (quasi-definite); the border factor
+    reproduces it as Lb diag(I, -I) Lb'."""
+    inst = shaped(N=6, m=10, n=20, l=3, n0=4, seed=3, F0=True, ng=ng)
+    x, z, _ = point(inst, seed=6)
+    f = newton.factor(inst, x, z, 1e-8, 1e-6)
+    S = newton.schur_matrix_dense(f)
+    nl = int(inst.loff()[-1])
+    pair = np.repeat(np.arange(inst.N - 1), inst.l)
+    T = S[:nl, :nl]
+    assert np.all(T[np.abs(pair[:, None] - pair[None, :]) > 1] == 0)
+    assert np.min(np.linalg.eigvalsh(T)) > 0
+    Bs = S[nl:, nl:] - S[nl:, :nl] @ np.linalg.solve(T, S[:nl, nl:])
+    ev = np.linalg.eigvalsh(Bs)
+    assert np.sum(ev > 0) == ng and np.sum(ev < 0) == inst.n0
+    sig = np.concatenate([np.ones(ng), -np.ones(inst.n0)])
+    assert rel((f.Lb * sig) @ f.Lb.T, Bs) < 1e-10
+    assert np.all(np.triu(f.Lb, 1) == 0) and np.all(np.diag(f.Lb) > 0)
+    assert rel(S, S.T) < 1e-15
 
 
 def test_pivot_rule_on_rank_deficient_block():
@@ -256,6 +287,45 @@ def test_planted_mistakes_are_caught(monkeypatch):
         uL, u0 = orig_solve(f, sL, s0)
         return uL, -u0
     monkeypatch.setattr(newton, "schur_solve", flipped)
+    assert _dense_pin_fails(inst)
+    monkeypatch.undo()
+
+
+def test_planted_mistakes_in_the_dense_layer(monkeypatch):
+    inst = shaped(N=4, m=5, n=10, l=2, n0=2, seed=14, F0=True, ng=2)
+    inst.Wg0 = np.random.default_rng(15).uniform(-1, 1, inst.Wg0.shape)
+    assert not _dense_pin_fails(inst)
+
+    # 1. global rows left out of the blocks' bordered columns
+    monkeypatch.setattr(newton, "global_cols", lambda ins, i: np.zeros((0, int(ins.n[i]))))
+    assert _dense_pin_fails(inst)
+    monkeypatch.undo()
+
+    # 2. the border taken as negative definite throughout (no + part)
+    orig_bs = newton.border_solve
+
+    def all_negative(f, t):
+        ng = f.ng
+        f.ng = 0
+        try:
+            return orig_bs(f, t)
+        finally:
+            f.ng = ng
+    monkeypatch.setattr(newton, "border_solve", all_negative)
+    assert _dense_pin_fails(inst)
+    monkeypatch.undo()
+
+    # 3. dropped x_0 part of the global rows (Wg_0)
+    Wg0 = inst.Wg0
+    orig_factor = newton.factor
+
+    def factor_noWg0(ins, *a, **k):
+        ins.Wg0 = np.zeros_like(Wg0)
+        try:
+            return orig_factor(ins, *a, **k)
+        finally:
+            ins.Wg0 = Wg0
+    monkeypatch.setattr(newton, "factor", factor_noWg0)
     assert _dense_pin_fails(inst)
     monkeypatch.undo()
 
