@@ -4,16 +4,21 @@
  * linking structure, on one AMD MI355X (gfx950).
  *
  * The LP (Sec. 2.2 standard form with the block structure of Sec. 3.2,
- * equality rows and local two-link constraints of Sec. 3.3):
+ * equality rows, local two-link constraints and global linking rows of
+ * Sec. 3.3):
  *
  *     min c'x   s.t.  A_i x_i + C_i x_0                        = b_i    i = 0..N-1
  *                     FR_j x_j + FL_j x_{j+1} + F0_j x_0       = b_Lj   j = 0..N-2
+ *                     Wg_0 x_0-block + .. + Wg_{N-1} x_{N-1}-block + Wg0 x_0 = b_G
  *                     x >= 0
  *
  * (A_i is the paper's B_i, C_i its A_i, FR_j its local block F_j, FL_j its F'_j,
- * F0 the local part of its F_0.)  Canonical vector order:
+ * F0 the local part of its F_0; Wg_i and Wg0 are rows of its F and F_0 with
+ * global support, which the Schur complement keeps in its dense border, the
+ * dense layer of Sec. 4.1.)  Canonical vector order:
  *     x, z = [x_0-block .. x_{N-1}-block, x_0]       length n_tot = sum n_i + n0
- *     y    = [y_0 .. y_{N-1}, y_L(pair 0) .. y_L(pair N-2)]   m_tot = sum m_i + sum l_j
+ *     y    = [y_0 .. y_{N-1}, y_L(pair 0) .. y_L(pair N-2), y_G]
+ *                                                   m_tot = sum m_i + sum l_j + ng
  *
  * Conventions for every call:
  *   - Status codes: 0 on success, negative on error, positive for warnings whose
@@ -60,9 +65,10 @@ typedef enum {
 
 /* Problem data for ahlp_problem_create.  All arrays are HOST memory, FP64,
  * row-major per block, blocks concatenated in order.  Limits: N >= 1,
- * 1 <= m_i <= n_i, 0 <= l_j <= min(n_j, n_{j+1}, 64), 0 <= n0 <= 128, and
+ * 1 <= m_i <= n_i, 0 <= l_j <= min(n_j, n_{j+1}, 64), 0 <= n0, 0 <= ng,
+ * ng + n0 <= 128 (the border of the Schur complement), and
  * every bordered block fits the LDS of one workgroup: with rt_i the 16-row
- * tiles of m_i plus those of l_{i-1}, l_i and n0 (each rounded up),
+ * tiles of m_i plus those of l_{i-1}, l_i and ng + n0 (each rounded up),
  * (rt_i + 1) * 16 * 17 * 8 bytes <= the device's LDS per workgroup (160 KiB
  * on gfx950: rt_i <= 74, blocks of up to about 1,180 rows with their links).
  * The problem is handed over in host memory because create repacks it into
@@ -80,8 +86,11 @@ typedef struct {
   const double* FR;       /* concat_j FR_j  (l_j x n_j)      block j's part of pair j */
   const double* FL;       /* concat_j FL_j  (l_j x n_{j+1})  block j+1's part        */
   const double* F0;       /* (sum l) x n0 coupling of link rows to x_0; NULL = 0     */
-  const double* b;        /* [m_tot]                                                 */
+  const double* b;        /* [m_tot]: block rows, link rows, global rows             */
   const double* c;        /* [n_tot]                                                 */
+  int32_t ng;             /* global linking rows (0: none; then Wg, Wg0 unused)      */
+  const double* Wg;       /* concat_i Wg_i  (ng x n_i)   block i's part of them      */
+  const double* Wg0;      /* ng x n0 their x_0 part; NULL = 0                         */
 } ahlp_problem_desc_t;
 
 /* Regularization of the factorization (a reading: the paper leaves pivot

@@ -27,7 +27,7 @@ _f64p = C.POINTER(C.c_double)
 class Desc(C.Structure):
     _fields_ = [("N", C.c_int32), ("n0", C.c_int32), ("m", _i32p), ("n", _i32p), ("l", _i32p),
                 ("A", _f64p), ("C", _f64p), ("FR", _f64p), ("FL", _f64p), ("F0", _f64p),
-                ("b", _f64p), ("c", _f64p)]
+                ("b", _f64p), ("c", _f64p), ("ng", C.c_int32), ("Wg", _f64p), ("Wg0", _f64p)]
 
 
 class FactorOpts(C.Structure):
@@ -153,6 +153,8 @@ class Problem:
     def __init__(self, inst, stream=None):
         L = lib()
         self.N, self.n0 = int(inst.N), int(inst.n0)
+        Wg_list = getattr(inst, "Wg", None)
+        self.ng = 0 if Wg_list is None else int(Wg_list[0].shape[0])
         m = np.ascontiguousarray(inst.m, dtype=np.int32)
         n = np.ascontiguousarray(inst.n, dtype=np.int32)
         l = np.ascontiguousarray(inst.l if len(inst.l) else np.zeros(1), dtype=np.int32)
@@ -162,10 +164,13 @@ class Problem:
         F0 = np.ascontiguousarray(inst.F0, dtype=np.float64) if inst.F0 is not None else None
         b = np.ascontiguousarray(inst.b, dtype=np.float64)
         c = np.ascontiguousarray(inst.c, dtype=np.float64)
-        self._keep = (m, n, l, A, Cm, FR, FL, F0, b, c)
+        Wg = _cat(Wg_list) if self.ng > 0 else None
+        Wg0 = (np.ascontiguousarray(inst.Wg0, dtype=np.float64)
+               if self.ng > 0 and self.n0 > 0 and inst.Wg0 is not None else None)
+        self._keep = (m, n, l, A, Cm, FR, FL, F0, b, c, Wg, Wg0)
         d = Desc(self.N, self.n0, m.ctypes.data_as(_i32p), n.ctypes.data_as(_i32p),
                  l.ctypes.data_as(_i32p), _ptr(A), _ptr(Cm), _ptr(FR), _ptr(FL), _ptr(F0),
-                 _ptr(b), _ptr(c))
+                 _ptr(b), _ptr(c), self.ng, _ptr(Wg), _ptr(Wg0))
         h = C.c_void_p()
         _check(L.ahlp_problem_create(C.byref(d), _stream(stream), C.byref(h)))
         self._keep = None
@@ -175,7 +180,7 @@ class Problem:
         self.n_tot, self.m_tot, self.n_link = nt.value, mt.value, nl.value
         self.m = m.copy()
         self.kdims = [int((inst.l[i - 1] if i >= 1 else 0) + (inst.l[i] if i < self.N - 1 else 0)
-                          + self.n0) for i in range(self.N)]
+                          + self.ng + self.n0) for i in range(self.N)]
 
     def close(self):
         if getattr(self, "h", None):
@@ -308,7 +313,7 @@ class Problem:
         return Lm, W[:, :k]
 
     def debug_schur(self):
-        dim = self.n_link + self.n0
+        dim = self.n_link + self.ng + self.n0
         S = np.zeros((max(dim, 1), max(dim, 1)))
         _check(lib().ahlp_debug_schur(self.h, S.ctypes.data_as(_f64p)))
         return S[:dim, :dim]

@@ -10,8 +10,9 @@
 namespace ahlp {
 
 // s0 = s_0 - sum_j Z_j'w_j (chunks of pairs, then the chunks, in a fixed
-// order), w0 = Lb^-1 s0, u0 = -Lb^-T w0; u0 goes to LDS, to A.u0p and to the
-// border part of A.u.  Every thread of the workgroup calls it (it holds
+// order), w0 = T Lb^-1 s0, u0 = -Lb^-T w0 (T = diag(-1 on the border's global
+// rows, +1 on x_0), the signs of -(S00 - sum Z'Z) = Lb T Lb'); u0 goes to
+// LDS, to A.u0p and to the border part of A.u.  Every thread of the workgroup calls it (it holds
 // barriers); part: blockDim.x doubles, s0 / w0 / u0: 16 t0 each, sc: 16, all
 // LDS.  Wave 0 does the triangular solves with the tiles of Lb^-1: lbi is
 // either the factor's full t0 x t0 array (tile (r, c) at c t0 + r) or, if
@@ -48,7 +49,7 @@ __device__ inline void bcr_border_solve(const BcrSolveArgs& A, const double* lbi
       double acc = 0.0;
       for (int cc = 0; cc <= rr; ++cc) acc += op_mv(op_load(lbi + lbi_tile(rr, cc, t0, packed) * 256), s0 + 16 * cc);
       wave_order();
-      if (lane < 16) w0[16 * rr + lane] = acc;
+      if (lane < 16) w0[16 * rr + lane] = (16 * rr + lane < c.ng) ? -acc : acc;
       wave_order();
     }
     for (int cc = 0; cc < t0; ++cc) {

@@ -18,7 +18,7 @@ constexpr int TE = 256;         // elements per tile
 constexpr double PIVOT_REL = 1e-30;
 constexpr double PIVOT_BIG = 1e128;
 constexpr int LMAX = 64;        // largest link pair handled by the chain kernels
-constexpr int N0MAX = 128;      // largest number of linking variables
+constexpr int N0MAX = 128;      // largest border of S: global rows plus linking variables
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -36,14 +36,16 @@ struct BlockInfo {
   int mt, nt;        // tile counts of the padded block (16 mt x 16 nt)
   int kt, rt;        // link-column tiles (kp = 16 kt) and bordered tile rows mt + kt
   int lL, lR;        // real rows of the left pair (i-1) and right pair (i); 0 at the ends
-  int ktL, ktR, kt0; // tiles of the left, right and x_0 sections of the link columns
+  int ktL, ktR, kt0; // tiles of the left, right and border sections of the link columns;
+                     // the border holds the ng global rows, then the n0 x_0 columns
+  int ng, kc0;       // global rows at the start of the border; tiles of C_i (n0 columns)
   int pairL, pairR;  // pair indices, -1 when absent
   int csr_off;       // this block's kp+1 link-row pointers start here in linkptr
   int csc_off;       // this block's n+1 link-column pointers start here in lcolptr
   long long xoff, yoff;   // offsets in the canonical x and y vectors
   long long dpoff;        // offset in the padded D vector (multiple of 16)
   long long aoff;         // A tiles (mt x nt, row-of-tiles major)
-  long long coff;         // C tiles (mt x kt0)
+  long long coff;         // C tiles (mt x kc0)
   long long lboff;        // bordered factor: lower-trapezoid tile columns, packed
   long long linvoff;      // mt inverted diagonal tiles of L_i
   long long pqoff;        // kt x kt tiles of the Schur contribution F D F' - W'W
@@ -64,22 +66,28 @@ __host__ __device__ inline long long a_tile(const BlockInfo& b, int I, int K) {
   return b.aoff + ((long long)I * b.nt + K) * TE;
 }
 __host__ __device__ inline long long c_tile(const BlockInfo& b, int I, int Q) {
-  return b.coff + ((long long)I * b.kt0 + Q) * TE;
+  return b.coff + ((long long)I * b.kc0 + Q) * TE;
 }
 __host__ __device__ inline long long pq_tile(const BlockInfo& b, int r, int c) {
   return b.pqoff + ((long long)r * b.kt + c) * TE;
 }
 
 // Link-column section of row q (0 <= q < 16 kt): 0 left pair, 1 right pair,
-// 2 x_0; *idx receives the index inside the section and *real whether it is a
-// real (not padding) row.
-__host__ __device__ inline int link_section(const BlockInfo& b, int q, int* idx, int n0, bool* real) {
+// 2 border (global rows, then x_0); *idx receives the index inside the
+// section and *real whether it is a real (not padding) row.  nb: the border's
+// width, ng + n0.
+__host__ __device__ inline int link_section(const BlockInfo& b, int q, int* idx, int nb, bool* real) {
   int qL = TS * b.ktL, qR = TS * b.ktR;
   if (q < qL) { *idx = q; *real = q < b.lL; return 0; }
   q -= qL;
   if (q < qR) { *idx = q; *real = q < b.lR; return 1; }
   q -= qR;
-  *idx = q; *real = q < n0; return 2;
+  *idx = q; *real = q < nb; return 2;
+}
+// Whether link-column row q of a section is a sparse row of F_i (a link row
+// or a global row) rather than a column of C_i.
+__host__ __device__ inline bool link_is_row(const BlockInfo& b, int sec, int idx) {
+  return sec < 2 || idx < b.ng;
 }
 
 // D += A B for a 16x16x4 block: lane l supplies A[l%16][l/16] and B[l/16][l%16];

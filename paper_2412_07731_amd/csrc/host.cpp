@@ -177,11 +177,13 @@ struct SolveWs {
 struct ahlp_problem_s {
   int device = 0;
   int N = 0, n0 = 0, n0p = 0, P = 0, G = 0;
+  int ng = 0, nb = 0;   // global rows; width of the Schur border (ng + n0)
   std::vector<int> m, n, l;
   std::vector<BlockInfo> hb;
   std::vector<long long> loff, tdoff, tooff, eoff, zoff, suboff;
   std::vector<int2> seg;
   long long n_tot = 0, m_tot = 0, nl = 0, mblk = 0, x0off = 0, d0off = 0, dp_total = 0;
+  long long nle = 0;    // link rows plus global rows: the dual rows after the blocks
   long long vp_total = 0, q_total = 0, a_total = 0, c_total = 0, lb_total = 0, linv_total = 0,
             pq_total = 0;
   int max_rt = 0, lmax = 0;
@@ -190,6 +192,8 @@ struct ahlp_problem_s {
 
   // problem data
   BlockInfo* blk = nullptr;
+  // F0: the x_0 coupling of the dual rows after the blocks, (nl + ng) x n0:
+  // the link rows' F0, then the global rows' Wg0 (null when all zero)
   double *A = nullptr, *C = nullptr, *F0 = nullptr, *b = nullptr, *c = nullptr;
   float* A32 = nullptr;
   int *lptr = nullptr, *lcol = nullptr, *cptr = nullptr, *crow = nullptr;
@@ -236,7 +240,7 @@ struct ahlp_problem_s {
   double *Td = nullptr, *To = nullptr, *E = nullptr, *S00 = nullptr, *thrT = nullptr;
   double *CL = nullptr, *CLi = nullptr, *CYn = nullptr, *CZ = nullptr, *CG = nullptr,
          *CSub = nullptr, *Lb = nullptr, *Lbi = nullptr, *S00w = nullptr, *segout = nullptr;
-  // tile path of the Schur factorization (pairs <= 32 rows, n0 <= 64)
+  // tile path of the Schur factorization (pairs <= 32 rows, border <= 64)
   bool fast = false;          // Schur factor by cyclic reduction (else the segmented chain)
   int tp = 0;                 // its tiles per pair side
   int t0 = 0, s00_chunk = 16, s00_parts = 0;
@@ -331,7 +335,7 @@ size_t solve_ws_layout(const ahlp_problem_s* p, double* base, SolveWs* ws) {
   };
   SolveWs tmp{};
   SolveWs& w = ws ? *ws : tmp;
-  const long long n = p->n_tot, m = p->m_tot, nb = p->nl + p->n0;
+  const long long n = p->n_tot, m = p->m_tot, nb = p->nl + p->nb;
   take(&w.rhx, n); take(&w.vx, p->dp_total); take(&w.xp, p->dp_total);
   take(&w.tv, p->vp_total); take(&w.dyp, p->vp_total); take(&w.qn, p->q_total);
   take(&w.s, nb); take(&w.w, nb); take(&w.u, nb);
@@ -427,7 +431,7 @@ ahlp_status_t factor_blocks_per_block(ahlp_problem_t p, hipStream_t st, T* LB, T
                                       const T* A) {
   p->timer.begin(AHLP_ST_SYRK);
   for (int i = 0; i < p->N; ++i) {
-    launch_link<T>(st, p->blk, p->link_items + p->link_off[i], p->link_cnt[i], p->n0, p->A, p->C,
+    launch_link<T>(st, p->blk, p->link_items + p->link_off[i], p->link_cnt[i], p->nb, p->A, p->C,
                    p->lptr, p->lcol, p->lval, p->Dp, LB, p->PQ);
     launch_syrk<T>(st, p->blk, p->syrk_items + p->syrk_off[i], p->syrk_cnt[i], A, p->Dp, LB,
                    p->delta);
@@ -458,7 +462,7 @@ ahlp_status_t factor_blocks_fused(ahlp_problem_t p, hipStream_t st, T* LB, T* LI
   if (rest) {
     HIPCHK(hipEventRecord(p->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    launch_link<T>(p->side, p->blk, p->col_link_items, p->ncol_link, p->n0, p->A, p->C, p->lptr,
+    launch_link<T>(p->side, p->blk, p->col_link_items, p->ncol_link, p->nb, p->A, p->C, p->lptr,
                    p->lcol, p->lval, p->Dp, LB, p->PQ);
     launch_syrk<T>(p->side, p->blk, p->col_syrk_items, p->ncol_syrk, A, p->Dp, LB, p->delta);
     launch_block_factor_panel<T>(p->side, p->blk, p->bf_order + p->n_panel, p->n_panel8,
@@ -467,7 +471,7 @@ ahlp_status_t factor_blocks_fused(ahlp_problem_t p, hipStream_t st, T* LB, T* LI
                                p->rt_col, LB, LINV, p->PQ, p->info);
     HIPCHK(hipEventRecord(p->ev_join, p->side));
   }
-  launch_factor_fused<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, p->fused_queue, p->n0,
+  launch_factor_fused<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, p->fused_queue, p->nb,
                          A, p->A, p->C, p->lptr, p->lcol, p->lval, p->Dp, LB, LINV, p->PQ,
                          p->delta, p->info, p->num_cu);
   if (rest) HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
@@ -484,7 +488,7 @@ ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, co
   // (MFMA-bound) runs on st; they write disjoint tiles of LB
   HIPCHK(hipEventRecord(p->ev_fork, st));
   HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-  launch_link<T>(p->side, p->blk, p->link_items, p->nlink, p->n0, p->A, p->C, p->lptr, p->lcol,
+  launch_link<T>(p->side, p->blk, p->link_items, p->nlink, p->nb, p->A, p->C, p->lptr, p->lcol,
                  p->lval, p->Dp, LB, p->PQ);
   HIPCHK(hipEventRecord(p->ev_join, p->side));
   p->timer.begin(AHLP_ST_SYRK);
@@ -518,7 +522,7 @@ ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, co
 
 ChainArgs chain_args(ahlp_problem_t p) {
   ChainArgs c{};
-  c.P = p->P; c.G = p->G; c.n0 = p->n0;
+  c.P = p->P; c.G = p->G; c.n0 = p->nb; c.ng = p->ng;
   c.l = p->d_l; c.tdoff = p->d_tdoff; c.tooff = p->d_tooff; c.eoff = p->d_eoff;
   c.zoff = p->d_zoff; c.suboff = p->d_suboff; c.seg = p->d_seg;
   c.Td = p->Td; c.To = p->To; c.E = p->E; c.S00 = p->S00; c.thrT = p->thrT;
@@ -531,7 +535,7 @@ ChainArgs chain_args(ahlp_problem_t p) {
 
 BcrArgs bcr_args(ahlp_problem_t p) {
   BcrArgs c{};
-  c.P = p->P; c.n0 = p->n0; c.t0 = p->t0; c.tp = p->tp;
+  c.P = p->P; c.n0 = p->nb; c.ng = p->ng; c.t0 = p->t0; c.tp = p->tp;
   c.l = p->d_l; c.tdoff = p->d_tdoff; c.tooff = p->d_tooff; c.eoff = p->d_eoff;
   c.Td = p->Td; c.To = p->To; c.E = p->E; c.S00 = p->S00; c.thrT = p->thrT;
   c.BD = p->BD; c.BC = p->BC; c.BEt = p->BEt;
@@ -579,9 +583,9 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
     CHK(factor_blocks<double>(p, st, p->LB, p->LINV, p->A));
   }
   p->timer.begin(AHLP_ST_SCHUR);
-  launch_assemble(st, p->blk, p->N, p->n0, p->d_l, p->d_tdoff, p->d_tooff, p->d_eoff, p->PQ,
-                  p->F0, p->d_loff, delta, p->Dp + p->d0off, p->Td, p->To, p->E, p->S00,
-                  p->thrT);
+  launch_assemble(st, p->blk, p->N, p->nb, p->n0, p->nl, p->d_l, p->d_tdoff, p->d_tooff,
+                  p->d_eoff, p->PQ, p->F0, p->d_loff, delta, p->Dp + p->d0off, p->Td, p->To, p->E,
+                  p->S00, p->thrT);
   p->timer.end();
   p->timer.f32 = false;
   p->timer.begin(AHLP_ST_TFACTOR);
@@ -634,8 +638,20 @@ void solve_blocks_fwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LI
 }
 template <typename T>
 void solve_blocks_bwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LINV, double* dy) {
-  launch_block_bwd<T>(st, p->blk, p->N, p->n0, p->nl, p->max_rt, LB, LINV, p->ws.tv, p->ws.u, dy,
+  launch_block_bwd<T>(st, p->blk, p->N, p->nb, p->nl, p->max_rt, LB, LINV, p->ws.tv, p->ws.u, dy,
                       p->ws.dyp);
+}
+
+// The dual rows after the blocks: out = base + alpha (F xp [+ F0 x0]) for the
+// link rows and the global rows (out and base point at the first link row;
+// x0 and the x_0 coupling only when x0 is given).
+void link_global_rows(ahlp_problem_t p, const double* xp, const double* x0, const double* base,
+                      double alpha, double* out, hipStream_t st) {
+  const double* F0 = x0 ? p->F0 : nullptr;
+  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, xp, x0, F0,
+                  base, alpha, out);
+  launch_globalrows(st, p->blk, p->N, p->ng, p->n0, p->nl, p->lptr, p->lcol, p->lval, xp, x0, F0,
+                    base ? base + p->nl : nullptr, alpha, out + p->nl);
 }
 
 // A row pass (AHLP_ST_AROWS) with its algorithmic bytes: the A tiles, the C
@@ -680,11 +696,10 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
     rows_pass1(p, p->ws.vx, ry, 1.0, 0, 1, p->ws.tv, st);
     tpre = p->ws.tv;
   }
-  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.vx,
-                  nullptr, nullptr, ry + p->mblk, 1.0, p->ws.s);
+  link_global_rows(p, p->ws.vx, nullptr, ry + p->mblk, 1.0, p->ws.s, st);
   if (f32) solve_blocks_fwd<float>(p, st, p->LB32, p->LINV32, tpre);
   else solve_blocks_fwd<double>(p, st, p->LB, p->LINV, tpre);
-  launch_schur_rhs(st, p->blk, p->N, p->n0, p->d_l, p->d_loff, p->nl, p->ws.qn, p->ws.rhx + p->x0off,
+  launch_schur_rhs(st, p->blk, p->N, p->nb, p->d_l, p->d_loff, p->nl, p->ws.qn, p->ws.rhx + p->x0off,
                    p->ws.s);
   if (p->fast) {
     BcrSolveArgs a{};
@@ -705,7 +720,7 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->ws.dyp, p->ws.u, p->cptr, p->crow, p->cval, 2,
               p->ws.rhx, nullptr, p->Dp, gout, dx, dzv);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
-  launch_solve_tail(st, p->N, p->n0, p->nl, p->ws.part, p->F0, p->ws.u, p->x0off, p->mblk, gout, dx, dzv,
+  launch_solve_tail(st, p->N, p->n0, p->nle, p->ws.part, p->F0, p->ws.u, p->x0off, p->mblk, gout, dx, dzv,
                     dy);
   p->timer.end();
   HIPCHK(hipGetLastError());
@@ -720,7 +735,7 @@ void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
               p->cval, mode, cvec, zvec, p->Dp, mode == 0 ? out : nullptr,
               mode == 0 ? nullptr : out);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
-  launch_x0_sum(st, p->N, p->n0, p->nl, p->ws.part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
+  launch_x0_sum(st, p->N, p->n0, p->nle, p->ws.part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
                 mode == 0 ? out : nullptr, mode == 0 ? nullptr : out);
 }
 
@@ -731,7 +746,7 @@ void apply_At_both(ahlp_problem_t p, const double* y, const double* cvec, const 
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->ws.dyp, y + p->mblk, p->cptr, p->crow,
               p->cval, 1, cvec, zvec, p->Dp, gout, rd);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
-  launch_x0_sum(st, p->N, p->n0, p->nl, p->ws.part, p->F0, y + p->mblk, 1, cvec, zvec, p->x0off,
+  launch_x0_sum(st, p->N, p->n0, p->nle, p->ws.part, p->F0, y + p->mblk, 1, cvec, zvec, p->x0off,
                 gout, rd);
 }
 
@@ -740,8 +755,8 @@ void apply_A(ahlp_problem_t p, const double* x, const double* base, double alpha
              hipStream_t st) {
   launch_pad_x(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, p->ws.xp, nullptr);
   rows_pass1(p, p->ws.xp, base, alpha, 1, 0, out, st);
-  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.xp,
-                  p->ws.xp + p->d0off, p->F0, base ? base + p->mblk : nullptr, alpha, out + p->mblk);
+  link_global_rows(p, p->ws.xp, p->ws.xp + p->d0off, base ? base + p->mblk : nullptr, alpha,
+                   out + p->mblk, st);
 }
 
 ahlp_status_t read_scal(ahlp_problem_t p, int count, hipStream_t st) {
@@ -792,8 +807,7 @@ void check_pass(ahlp_problem_t p, const double* rx, const double* ry, const doub
     ra.v[1] = p->w2p; ra.alpha[1] = 1.0; ra.out[1] = p->aw2; ra.padded[1] = 1;
   }
   rows_pass(p, ra, st);
-  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.xp,
-                  p->ws.xp + p->d0off, p->F0, ry + p->mblk, -1.0, p->ws.ey + p->mblk);
+  link_global_rows(p, p->ws.xp, p->ws.xp + p->d0off, ry + p->mblk, -1.0, p->ws.ey + p->mblk, st);
   p->timer.end();
 }
 
@@ -924,9 +938,12 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   g_err.clear();
   if (!d || !out) return fail(AHLP_EINVAL, "null argument");
   *out = nullptr;
-  const int N = d->N, n0 = d->n0;
+  const int N = d->N, n0 = d->n0, ng = d->ng;
   if (N < 1) return fail(AHLP_EINVAL, "N must be >= 1 (got %d)", N);
-  if (n0 < 0 || n0 > N0MAX) return fail(AHLP_EINVAL, "n0 must be in [0, %d] (got %d)", N0MAX, n0);
+  if (n0 < 0 || ng < 0 || ng + n0 > N0MAX)
+    return fail(AHLP_EINVAL, "need n0 >= 0, ng >= 0 and ng + n0 <= %d (got n0=%d ng=%d)", N0MAX, n0, ng);
+  if (ng > 0 && !d->Wg) return fail(AHLP_EINVAL, "ng > 0 needs Wg");
+  const int nbw = ng + n0;   // width of the Schur border
   if (!d->m || !d->n || !d->A || !d->b || !d->c) return fail(AHLP_EINVAL, "missing m, n, A, b or c");
   if (N > 1 && (!d->l || !d->FR || !d->FL)) return fail(AHLP_EINVAL, "missing l, FR or FL");
   if (n0 > 0 && !d->C) return fail(AHLP_EINVAL, "n0 > 0 needs C");
@@ -934,6 +951,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   ahlp_problem_t p = up.get();
   HIPCHK(hipGetDevice(&p->device));
   p->N = N; p->n0 = n0; p->n0p = (int)r16(n0); p->P = N - 1;
+  p->ng = ng; p->nb = nbw;
   p->m.assign(d->m, d->m + N);
   p->n.assign(d->n, d->n + N);
   if (N > 1) p->l.assign(d->l, d->l + N - 1);
@@ -950,17 +968,18 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   HIPCHK(hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device));
   // the static workspace's address on this device (kept per device, resolved once)
   HIPCHK(scratch_setup(p->device));
-  const size_t chain_sh = chain_factor_smem(std::max(p->lmax, 1), n0);
+  const size_t chain_sh = chain_factor_smem(std::max(p->lmax, 1), nbw);
   if (chain_sh > (size_t)dev_lds)
-    return fail(AHLP_EINVAL, "link pairs (max %d) with %d linking variables exceed the %d bytes of LDS",
-                p->lmax, n0, dev_lds);
+    return fail(AHLP_EINVAL,
+                "link pairs (max %d) with a border of %d (global rows and linking variables) exceed "
+                "the %d bytes of LDS", p->lmax, nbw, dev_lds);
 
   // ---- geometry
   long long xo = 0, yo = 0, dpo = 0, ao = 0, co = 0, lbo = 0, lio = 0, pqo = 0, vo = 0, qo = 0;
   p->loff.assign(std::max(N, 1), 0);
   for (int j = 0; j < N - 1; ++j) p->loff[j + 1] = p->loff[j] + p->l[j];
   p->nl = N > 1 ? p->loff[N - 1] : 0;
-  const int kt0 = (n0 + 15) / 16;
+  const int kt0 = (nbw + 15) / 16, kc0 = (n0 + 15) / 16;
   p->hb.resize(N);
   int csr_off = 0, csc_off = 0;
   for (int i = 0; i < N; ++i) {
@@ -970,6 +989,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     b.lL = i >= 1 ? p->l[i - 1] : 0;
     b.lR = i <= N - 2 ? p->l[i] : 0;
     b.ktL = (b.lL + 15) / 16; b.ktR = (b.lR + 15) / 16; b.kt0 = kt0;
+    b.ng = ng; b.kc0 = kc0;
     b.kt = b.ktL + b.ktR + b.kt0;
     b.rt = b.mt + b.kt;
     b.pairL = i >= 1 ? i - 1 : -1;
@@ -980,7 +1000,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     b.yoff = yo; yo += b.m;
     b.dpoff = dpo; dpo += 16LL * b.nt;
     b.aoff = ao; ao += 256LL * b.mt * b.nt;
-    b.coff = co; co += 256LL * b.mt * b.kt0;
+    b.coff = co; co += 256LL * b.mt * b.kc0;
     b.lboff = lbo; lbo += 256LL * lb_tiles(b.mt, b.rt);
     b.linvoff = lio; lio += 256LL * b.mt;
     b.pqoff = pqo; pqo += 256LL * b.kt * b.kt;
@@ -996,12 +1016,12 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     const size_t col_sh = (size_t)(p->max_rt + 1) * 16 * 17 * sizeof(double);
     if (col_sh > (size_t)dev_lds)
       return fail(AHLP_EINVAL,
-                  "a block with %d bordered tile rows (m_i + l_{i-1} + l_i + n0 up to %d) needs %zu "
+                  "a block with %d bordered tile rows (m_i + l_{i-1} + l_i + ng + n0 up to %d) needs %zu "
                   "bytes of LDS for its factorization; this device has %d (at most %d tile rows)",
                   p->max_rt, 16 * p->max_rt, col_sh, dev_lds, dev_lds / (16 * 17 * 8) - 1);
   }
   p->x0off = xo; p->n_tot = xo + n0;
-  p->mblk = yo; p->m_tot = yo + p->nl;
+  p->mblk = yo; p->nle = p->nl + ng; p->m_tot = yo + p->nle;
   p->d0off = dpo; p->dp_total = dpo + p->n0p;
   p->a_total = ao; p->c_total = co; p->lb_total = lbo; p->linv_total = lio; p->pq_total = pqo;
   p->vp_total = vo; p->q_total = qo;
@@ -1029,7 +1049,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
           for (int c = 0; c < n0; ++c) {
             const double v = Ci[(long long)r * n0 + c];
             if (!std::isfinite(v)) return fail(AHLP_ENUMERIC, "non-finite C in block %d", i);
-            hC[b.coff + ((long long)(r / 16) * kt0 + c / 16) * 256 + (c % 16) * 16 + r % 16] = v;
+            hC[b.coff + ((long long)(r / 16) * kc0 + c / 16) * 256 + (c % 16) * 16 + r % 16] = v;
             rowabs[b.yoff + r] += std::fabs(v);
             colabs[p->x0off + c] += std::fabs(v);
           }
@@ -1037,12 +1057,14 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
       }
     }
   }
-  // CSR of each block's link sections (rows q in [0, 16 kt), padded rows empty)
+  // CSR of each block's link sections (rows q in [0, 16 kt), padded rows
+  // empty): its part of the left and right pairs' link rows and of the global
+  // rows (the border section's first ng rows)
   std::vector<int> hptr((size_t)csr_off, 0), hcol;
   std::vector<double> hval;
   std::vector<std::vector<std::pair<long long, double>>> colents((size_t)p->x0off);
   {
-    long long froff = 0, floff = 0;
+    long long froff = 0, floff = 0, wgoff = 0;
     std::vector<long long> fr_start(N > 1 ? N - 1 : 1, 0), fl_start(N > 1 ? N - 1 : 1, 0);
     for (int j = 0; j < N - 1; ++j) {
       fr_start[j] = froff; froff += (long long)p->l[j] * p->n[j];
@@ -1054,12 +1076,19 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
         hptr[b.csr_off + q] = (int)hcol.size();
         int qi;
         bool real;
-        const int sec = link_section(b, q, &qi, n0, &real);
-        if (!real || sec == 2) continue;
-        const int pair = sec == 0 ? i - 1 : i;
-        const double* row = sec == 0 ? d->FL + fl_start[pair] + (long long)qi * b.n
-                                     : d->FR + fr_start[pair] + (long long)qi * b.n;
-        const long long grow = p->loff[pair] + qi;   // link row inside y_L
+        const int sec = link_section(b, q, &qi, nbw, &real);
+        if (!real || !link_is_row(b, sec, qi)) continue;
+        const double* row;
+        long long grow;   // row inside the dual rows after the blocks (y_L, then y_G)
+        if (sec == 2) {
+          row = d->Wg + wgoff + (long long)qi * b.n;
+          grow = p->nl + qi;
+        } else {
+          const int pair = sec == 0 ? i - 1 : i;
+          row = sec == 0 ? d->FL + fl_start[pair] + (long long)qi * b.n
+                         : d->FR + fr_start[pair] + (long long)qi * b.n;
+          grow = p->loff[pair] + qi;
+        }
         for (int c = 0; c < b.n; ++c) {
           const double v = row[c];
           if (v == 0.0) continue;
@@ -1072,6 +1101,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
         }
       }
       hptr[b.csr_off + 16 * b.kt] = (int)hcol.size();
+      wgoff += (long long)ng * b.n;
     }
   }
   std::vector<int> hcptr((size_t)csc_off, 0), hcrow;
@@ -1087,11 +1117,20 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     }
     hcptr[b.csc_off + b.n] = (int)hcrow.size();
   }
-  if (d->F0 && n0 > 0) {
-    for (long long r = 0; r < p->nl; ++r)
+  // the x_0 coupling of the dual rows after the blocks: F0, then Wg0
+  std::vector<double> hF0;
+  if (n0 > 0 && ((d->F0 && p->nl > 0) || (ng > 0 && d->Wg0))) {
+    hF0.assign((size_t)(p->nle * n0), 0.0);
+    if (d->F0)
+      for (long long r = 0; r < p->nl; ++r)
+        for (int c = 0; c < n0; ++c) hF0[r * n0 + c] = d->F0[r * n0 + c];
+    if (ng > 0 && d->Wg0)
+      for (long long r = 0; r < ng; ++r)
+        for (int c = 0; c < n0; ++c) hF0[(p->nl + r) * n0 + c] = d->Wg0[r * n0 + c];
+    for (long long r = 0; r < p->nle; ++r)
       for (int c = 0; c < n0; ++c) {
-        const double v = d->F0[r * n0 + c];
-        if (!std::isfinite(v)) return fail(AHLP_ENUMERIC, "non-finite F0");
+        const double v = hF0[r * n0 + c];
+        if (!std::isfinite(v)) return fail(AHLP_ENUMERIC, r < p->nl ? "non-finite F0" : "non-finite Wg0");
         rowabs[p->mblk + r] += std::fabs(v);
         colabs[p->x0off + c] += std::fabs(v);
       }
@@ -1146,7 +1185,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     for (int r = 0; r < b.kt; ++r) hlink.push_back(int2{i, r});
     for (int r = 0; r < b.mt; ++r) hrow.push_back(int2{i, r});
     for (int c = 0; c < b.nt; ++c) hcolt.push_back(int2{i, c});
-    for (int q = 0; q < b.kt0; ++q) hc0.push_back(int2{i, q});
+    for (int q = 0; q < b.kc0; ++q) hc0.push_back(int2{i, q});
   }
   p->nsyrk = (int)hsyrk.size(); p->nlink = (int)hlink.size();
   p->h_syrk = hsyrk;
@@ -1163,7 +1202,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   for (int j = 0; j < P; ++j) {
     p->tdoff[j] = td; td += (long long)p->l[j] * p->l[j];
     p->tooff[j] = to; if (j + 1 < P) to += (long long)p->l[j + 1] * p->l[j];
-    p->eoff[j] = p->loff[j] * n0;
+    p->eoff[j] = p->loff[j] * nbw;
   }
   if (P > 0) {
     int Ls = P <= 8 ? P : std::max(2, (int)std::lround(std::sqrt((double)P)));
@@ -1205,7 +1244,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->cptr, csc_off));
   CHK(M.alloc(&p->crow, std::max<long long>(hcrow.size(), 1)));
   CHK(M.alloc(&p->cval, std::max<long long>(hcval.size(), 1)));
-  if (d->F0 && n0 > 0 && p->nl > 0) CHK(M.alloc(&p->F0, p->nl * n0));
+  if (!hF0.empty()) CHK(M.alloc(&p->F0, p->nle * n0));
   CHK(M.alloc(&p->b, p->m_tot));
   CHK(M.alloc(&p->c, p->n_tot));
   CHK(M.alloc(&p->syrk_items, p->nsyrk));
@@ -1235,19 +1274,19 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->PQ, p->pq_total));
   CHK(M.alloc(&p->Td, std::max(td, 1LL)));
   CHK(M.alloc(&p->To, std::max(to, 1LL)));
-  CHK(M.alloc(&p->E, std::max(p->nl * n0, 1LL)));
-  CHK(M.alloc(&p->S00, std::max(n0 * n0, 1)));
+  CHK(M.alloc(&p->E, std::max(p->nl * nbw, 1LL)));
+  CHK(M.alloc(&p->S00, std::max(nbw * nbw, 1)));
   CHK(M.alloc(&p->thrT, std::max(P, 1)));
   CHK(M.alloc(&p->CL, std::max(td, 1LL)));
   CHK(M.alloc(&p->CLi, std::max(td, 1LL)));
   CHK(M.alloc(&p->CYn, std::max(to, 1LL)));
   CHK(M.alloc(&p->CZ, std::max(zo, 1LL)));
-  CHK(M.alloc(&p->CG, std::max(p->nl * n0, 1LL)));
+  CHK(M.alloc(&p->CG, std::max(p->nl * nbw, 1LL)));
   CHK(M.alloc(&p->CSub, std::max(so, 1LL)));
-  CHK(M.alloc(&p->Lb, std::max(n0 * n0, 1)));
-  CHK(M.alloc(&p->Lbi, std::max(n0 * n0, 1)));
-  CHK(M.alloc(&p->S00w, std::max(n0 * n0, 1)));
-  p->tp = bcr_tiles(p->lmax, n0);
+  CHK(M.alloc(&p->Lb, std::max(nbw * nbw, 1)));
+  CHK(M.alloc(&p->Lbi, std::max(nbw * nbw, 1)));
+  CHK(M.alloc(&p->S00w, std::max(nbw * nbw, 1)));
+  p->tp = bcr_tiles(p->lmax, nbw);
   p->fast = p->tp > 0;
   for (int i = 0; i < N; ++i) {
     p->a_bytes += 8.0 * p->m[i] * p->n[i];
@@ -1256,7 +1295,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     p->yv_bytes += 8.0 * p->m[i];
   }
   p->x0_bytes = 8.0 * n0;
-  p->t0 = (n0 + 15) / 16;
+  p->t0 = (nbw + 15) / 16;
   if (p->fast) {
     const long long Pt = std::max(P, 1);
     // chunks of at least 16 pairs, at most 64 chunks
@@ -1314,7 +1353,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     HIPCHK(hipMemcpyAsync(p->crow, hcrow.data(), sizeof(int) * hcrow.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(p->cval, hcval.data(), sizeof(double) * hcval.size(), hipMemcpyHostToDevice, st));
   }
-  if (p->F0) HIPCHK(hipMemcpyAsync(p->F0, d->F0, sizeof(double) * p->nl * n0, hipMemcpyHostToDevice, st));
+  if (p->F0) HIPCHK(hipMemcpyAsync(p->F0, hF0.data(), sizeof(double) * p->nle * n0, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->b, d->b, sizeof(double) * p->m_tot, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->c, d->c, sizeof(double) * p->n_tot, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->syrk_items, hsyrk.data(), sizeof(int4) * hsyrk.size(), hipMemcpyHostToDevice, st));
@@ -1529,7 +1568,7 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
       for (int rep = 0; rep < 2; ++rep)
         for (int k = 0; k < 3; ++k) {
           if (!can[k]) continue;
-          launch_link<double>(st, p->blk, p->link_items, p->nlink, p->n0, p->A, p->C, p->lptr,
+          launch_link<double>(st, p->blk, p->link_items, p->nlink, p->nb, p->A, p->C, p->lptr,
                               p->lcol, p->lval, p->Dp, p->LB, p->PQ);
           launch_syrk<double>(st, p->blk, p->syrk_items, p->nsyrk, p->A, p->Dp, p->LB, delta);
           HIPCHK(hipEventRecord(e0, st));
@@ -1787,8 +1826,7 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       ra.v[2] = p->w1p; ra.alpha[2] = 1.0; ra.out[2] = p->aw1; ra.padded[2] = 1;
       rows_pass(p, ra, st);
     }
-    launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, p->ws.xp,
-                    p->ws.xp + p->d0off, p->F0, p->b + p->mblk, -1.0, p->rp + p->mblk);
+    link_global_rows(p, p->ws.xp, p->ws.xp + p->d0off, p->b + p->mblk, -1.0, p->rp + p->mblk, st);
     Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, p->c, x, 1).add(RED_DOT, m, p->b, y, 2)
         .add(RED_MAXABS, m, p->rp, nullptr, 3).add(RED_MAXABS, n, p->rd, nullptr, 4)
         .add(RED_MAXSUM, n, x, z, 5).launch(st);
@@ -2080,7 +2118,7 @@ ahlp_status_t ahlp_debug_block(ahlp_problem_t p, int32_t i, double* L, double* W
       for (int c = 0; c < b.m; ++c) L[(long long)r * b.m + c] = (c <= r) ? at(r, c) : 0.0;
   }
   if (W) {
-    const int k = b.lL + b.lR + p->n0;
+    const int k = b.lL + b.lR + p->nb;
     for (int a = 0; a < b.m; ++a)
       for (int col = 0; col < k; ++col) {
         int q;
@@ -2096,7 +2134,7 @@ ahlp_status_t ahlp_debug_block(ahlp_problem_t p, int32_t i, double* L, double* W
 ahlp_status_t ahlp_debug_schur(ahlp_problem_t p, double* S) {
   if (!p || !S) return fail(AHLP_EINVAL, "null argument");
   if (!p->factored) return fail(AHLP_ESTATE, "no factorization");
-  const long long dim = p->nl + p->n0;
+  const long long dim = p->nl + p->nb;
   HIPCHK(hipDeviceSynchronize());
   std::vector<double> Td, To, E, S00;
   auto fetch = [&](std::vector<double>& v, const double* src, long long cnt) -> ahlp_status_t {
@@ -2104,7 +2142,7 @@ ahlp_status_t ahlp_debug_schur(ahlp_problem_t p, double* S) {
     if (cnt > 0) HIPCHK(hipMemcpy(v.data(), src, sizeof(double) * cnt, hipMemcpyDeviceToHost));
     return AHLP_OK;
   };
-  const int P = p->P, n0 = p->n0;
+  const int P = p->P, n0 = p->nb;   // the border: global rows, then x_0
   long long tdn = P > 0 ? p->tdoff[P - 1] + (long long)p->l[P - 1] * p->l[P - 1] : 0;
   long long ton = P > 1 ? p->tooff[P - 2] + (long long)p->l[P - 1] * p->l[P - 2] : 0;
   CHK(fetch(Td, p->Td, tdn));

@@ -171,7 +171,9 @@ __global__ void k_chain_sep_factor(ChainArgs c) {
       __syncthreads();
     }
   }
-  // border: Lb = chol(-(S00')),  Lbi = Lb^-1
+  // border (global rows, then x_0): -(S00') = Lb T Lb' with T = diag(-I, I)
+  // (the global rows' part is positive definite in S00', x_0's negative
+  // definite), Lbi = Lb^-1
   if (n0 > 0) {
     double* B = sm;
     double* Bi = sm + n0 * n0;
@@ -180,11 +182,11 @@ __global__ void k_chain_sep_factor(ChainArgs c) {
     __syncthreads();
     if (threadIdx.x == 0) {
       double md = 0.0;
-      for (int i = 0; i < n0; ++i) md = fmax(md, B[i + i * n0]);
+      for (int i = 0; i < n0; ++i) md = fmax(md, fabs(B[i + i * n0]));
       s_max = md;
     }
     __syncthreads();
-    cnt += sm_chol(B, n0, PIVOT_REL * fmax(s_max, 0.0));
+    cnt += sm_chol_signed(B, n0, c.ng, PIVOT_REL * s_max);
     sm_trinv(B, Bi, n0);
     for (int i = threadIdx.x; i < n0 * n0; i += blockDim.x) {
       c.Lb[i] = B[i];
@@ -256,7 +258,10 @@ __global__ void k_chain_sep_solve(ChainSolveArgs a) {
   }
   double* u0 = a.u + a.nl;
   if (n0 > 0) {
+    // S00' u0 = s0 with -(S00') = Lb T Lb':  u0 = -Lb^-T T Lb^-1 s0
     sm_gemv(w0, nullptr, c.Lbi, n0, false, s0, n0, n0, 1.0);
+    for (int i = threadIdx.x; i < c.ng; i += blockDim.x) w0[i] = -w0[i];
+    __syncthreads();
     sm_gemv(u0, nullptr, c.Lbi, n0, true, w0, n0, n0, -1.0);
   }
   for (int sidx = S - 1; sidx >= 0; --sidx) {

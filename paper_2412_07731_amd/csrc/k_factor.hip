@@ -199,11 +199,12 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
 // ---------------------------------------------------------------- a1: B_i'
 // One workgroup per (block, tile row of the link columns).  Writes B_i' =
 // [F_i D_i A_i' ; C_i'] into the bordered rows and F_i D_i F_i' (FP64) into the
-// Schur-contribution tiles.  Link rows are sparse (compressed rows, sorted
+// Schur-contribution tiles, F_i being block i's part of its two link pairs
+// and of the global rows.  These rows are sparse (compressed rows, sorted
 // columns), so the products are gathers rather than GEMMs.
 // Tile row rr of block b's link columns, by 256 threads (t = 0..255).
 template <typename T>
-__device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t, int n0,
+__device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t, int nb,
                                               const double* __restrict__ A,
                                               const double* __restrict__ C,
                                               const int* __restrict__ lptr,
@@ -216,9 +217,10 @@ __device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t,
   const int q = TS * rr + ql;
   int qi;
   bool real;
-  const int sec = link_section(b, q, &qi, n0, &real);
+  const int sec = link_section(b, q, &qi, nb, &real);
+  const bool is_row = link_is_row(b, sec, qi);
   int p0 = 0, p1 = 0;
-  if (real && sec < 2) {
+  if (real && is_row) {
     p0 = lptr[b.csr_off + q];
     p1 = lptr[b.csr_off + q + 1];
   }
@@ -229,7 +231,7 @@ __device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t,
     double v[LINK_CB];
 #pragma unroll
     for (int u = 0; u < LINK_CB; ++u) v[u] = 0.0;
-    if (real && sec < 2) {
+    if (real && is_row) {
       for (int e = p0; e < p1; ++e) {
         const int j = lcol[e];
         const double coef = lval[e] * Dp[b.dpoff + j];
@@ -241,11 +243,12 @@ __device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t,
         }
       }
     } else if (real) {
-      const double* col = C + c_tile(b, 0, qi >> 4) + (qi & 15) * TS + al;
+      const int qc = qi - b.ng;   // column of C_i
+      const double* col = C + c_tile(b, 0, qc >> 4) + (qc & 15) * TS + al;
 #pragma unroll
       for (int u = 0; u < LINK_CB; ++u) {
         const int c = c0 + u;
-        if (c < b.mt && TS * c + al < b.m) v[u] = col[(long long)c * b.kt0 * TE];
+        if (c < b.mt && TS * c + al < b.m) v[u] = col[(long long)c * b.kc0 * TE];
       }
     }
 #pragma unroll
@@ -257,9 +260,9 @@ __device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t,
     const int q2 = TS * cc + al;
     int qi2;
     bool real2;
-    const int sec2 = link_section(b, q2, &qi2, n0, &real2);
+    const int sec2 = link_section(b, q2, &qi2, nb, &real2);
     double v = 0.0;
-    if (real && real2 && sec < 2 && sec2 < 2) {
+    if (real && real2 && is_row && link_is_row(b, sec2, qi2)) {
       int e1 = p0, e2 = lptr[b.csr_off + q2];
       const int e2end = lptr[b.csr_off + q2 + 1];
       while (e1 < p1 && e2 < e2end) {
@@ -280,7 +283,7 @@ __device__ __forceinline__ void link_tile_row(const BlockInfo& b, int rr, int t,
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
-                                              const int2* __restrict__ items, int n0,
+                                              const int2* __restrict__ items, int nb,
                                               const double* __restrict__ A,
                                               const double* __restrict__ C,
                                               const int* __restrict__ lptr,
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(256) void k_link(const BlockInfo* __restrict__ blk,
                                               const double* __restrict__ Dp,
                                               T* __restrict__ LB, double* __restrict__ PQ) {
   const int2 it = items[blockIdx.x];
-  link_tile_row<T>(blk[it.x], it.y, threadIdx.x, n0, A, C, lptr, lcol, lval, Dp, LB, PQ);
+  link_tile_row<T>(blk[it.x], it.y, threadIdx.x, nb, A, C, lptr, lcol, lval, Dp, LB, PQ);
 }
 
 // ---------------------------------------------------------------- a3 + a4
@@ -888,7 +891,7 @@ __device__ __forceinline__ double syrk_wave_tile(const BlockInfo& b, int R, int 
 template <typename T, int BF_RMAX>
 __global__ __launch_bounds__(512, 1) void k_factor_fused(
     const BlockInfo* __restrict__ blk, const int* __restrict__ order, int nblk,
-    int* __restrict__ queue, int n0, const T* __restrict__ Aw, const double* __restrict__ A,
+    int* __restrict__ queue, int nb, const T* __restrict__ Aw, const double* __restrict__ A,
     const double* __restrict__ C, const int* __restrict__ lptr, const int* __restrict__ lcol,
     const double* __restrict__ lval, const double* __restrict__ Dp, T* __restrict__ LB,
     T* __restrict__ LINV, double* __restrict__ PQ, double delta, DevInfo* info) {
@@ -939,7 +942,7 @@ __global__ __launch_bounds__(512, 1) void k_factor_fused(
       const BlockInfo b = blk[sl->blk];
       // link columns: the team's 256 threads take the tile rows in turn
       for (int rr = 0; rr < b.kt; ++rr)
-        link_tile_row<T>(b, rr, tid - 256, n0, A, C, lptr, lcol, lval, Dp, LB, PQ);
+        link_tile_row<T>(b, rr, tid - 256, nb, A, C, lptr, lcol, lval, Dp, LB, PQ);
       wg_release();
       if (lane == 0) lds_add(&sl->link, 1);
       // diagonal wave tiles, then the off-diagonal ones by column pair
@@ -1006,10 +1009,11 @@ __device__ inline double pq_get(const double* PQ, const BlockInfo& b, int q, int
 }
 
 // One workgroup per link pair j: T_jj (col-major, + delta I), T_{j+1,j}
-// (col-major) and E_j (l_j x n0, col-major), each entry the fixed-order sum of
-// its two contributing blocks, and the pivot threshold of the pair.
+// (col-major) and E_j (l_j x nb, col-major; columns: the global rows, then
+// x_0), each entry the fixed-order sum of its two contributing blocks (plus
+// F0 in the x_0 columns), and the pivot threshold of the pair.
 __global__ __launch_bounds__(256) void k_assemble_pairs(
-    const BlockInfo* __restrict__ blk, int P, int n0, const int* __restrict__ lsz,
+    const BlockInfo* __restrict__ blk, int P, int nb, int n0, const int* __restrict__ lsz,
     const long long* __restrict__ tdoff, const long long* __restrict__ tooff,
     const long long* __restrict__ eoff, const double* __restrict__ PQ,
     const double* __restrict__ F0, const long long* __restrict__ loff, double delta,
@@ -1017,7 +1021,7 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(
     double* __restrict__ thrT) {
   const int j = blockIdx.x;
   const BlockInfo bl = blk[j], br = blk[j + 1];
-  const int l = lsz[j];
+  const int l = lsz[j], ng = nb - n0;
   const int offR = TS * bl.ktL;          // pair j inside block j (its right section)
   const int x0l = TS * (bl.ktL + bl.ktR), x0r = TS * (br.ktL + br.ktR);
   __shared__ double s_max[4];
@@ -1039,10 +1043,10 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(
       To[tooff[j] + idx] = pq_get(PQ, br, offR2 + a, c);
     }
   }
-  for (int idx = threadIdx.x; idx < l * n0; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < l * nb; idx += blockDim.x) {
     const int a = idx % l, c = idx / l;
     double v = pq_get(PQ, bl, offR + a, x0l + c) + pq_get(PQ, br, a, x0r + c);
-    if (F0) v += F0[(loff[j] + a) * n0 + c];
+    if (F0 && c >= ng) v += F0[(loff[j] + a) * n0 + (c - ng)];
     E[eoff[j] + idx] = v;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1053,15 +1057,20 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(
     thrT[j] = PIVOT_REL * fmax(fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3])), 0.0);
 }
 
-// S00 = -D_0^-1 + sum_i (F D F' - W'W)_i[x0, x0]: one workgroup per entry, each
-// thread a fixed strided subset of the blocks, then a fixed reduction tree.
+// S00 (nb x nb; the global rows, then x_0) = K0's border + sum_i (F D F' -
+// W'W)_i[border, border]: K0' holds delta I on the global rows, their x_0 part
+// Wg0 (rows nl.. of the extended F0) off the diagonal, and -D_0^-1 on x_0.
+// One workgroup per entry, each thread a fixed strided subset of the blocks,
+// then a fixed reduction tree.
 __global__ __launch_bounds__(256) void k_assemble_s00(const BlockInfo* __restrict__ blk, int N,
-                                                      int n0, const double* __restrict__ PQ,
+                                                      int nb, int n0, long long nl,
+                                                      const double* __restrict__ PQ,
                                                       const double* __restrict__ D0,
+                                                      const double* __restrict__ F0, double delta,
                                                       double* __restrict__ S00) {
   __shared__ double sh[4];
   const int idx = blockIdx.x;
-  const int a = idx % n0, c = idx / n0;
+  const int a = idx % nb, c = idx / nb, ng = nb - n0;
   if (c > a) return;   // lower triangle computed, mirrored below
   double v = 0.0;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -1074,10 +1083,12 @@ __global__ __launch_bounds__(256) void k_assemble_s00(const BlockInfo* __restric
   if (lane == 0) sh[wave] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = (a == c) ? -1.0 / D0[a] : 0.0;
+    double t = 0.0;
+    if (a == c) t = a < ng ? delta : -1.0 / D0[a - ng];
+    else if (a >= ng && c < ng && F0) t = F0[(nl + c) * n0 + (a - ng)];
     t += ((sh[0] + sh[1]) + (sh[2] + sh[3]));
-    S00[a + c * n0] = t;
-    S00[c + a * n0] = t;
+    S00[a + c * nb] = t;
+    S00[c + a * nb] = t;
   }
 }
 
@@ -1119,11 +1130,11 @@ template void launch_syrk<float>(hipStream_t, const BlockInfo*, const int4*, int
                                  const double*, float*, double);
 
 template <typename T>
-void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int n0,
+void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int nb,
                  const double* A, const double* C, const int* lptr, const int* lcol,
                  const double* lval, const double* Dp, T* LB, double* PQ) {
   if (nitems == 0) return;
-  hipLaunchKernelGGL(k_link<T>, dim3(nitems), dim3(256), 0, st, blk, items, n0, A, C, lptr, lcol,
+  hipLaunchKernelGGL(k_link<T>, dim3(nitems), dim3(256), 0, st, blk, items, nb, A, C, lptr, lcol,
                      lval, Dp, LB, PQ);
 }
 template void launch_link<double>(hipStream_t, const BlockInfo*, const int2*, int, int,
@@ -1162,7 +1173,7 @@ void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* 
 // one eight-wave workgroup per CU (at most n).  queue: one int, zeroed here.
 template <typename T>
 void launch_factor_fused(hipStream_t st, const BlockInfo* blk, const int* order, int n,
-                         int max_rt, int* queue, int n0, const T* Aw, const double* A,
+                         int max_rt, int* queue, int nb, const T* Aw, const double* A,
                          const double* C, const int* lptr, const int* lcol, const double* lval,
                          const double* Dp, T* LB, T* LINV, double* PQ, double delta,
                          DevInfo* info, int num_cu) {
@@ -1172,11 +1183,11 @@ void launch_factor_fused(hipStream_t st, const BlockInfo* blk, const int* order,
   if (max_rt <= 20) {
     const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<5>::LD * sizeof(T);
     hipLaunchKernelGGL((k_factor_fused<T, 5>), dim3(grid), dim3(512), shmem, st, blk, order, n,
-                       queue, n0, Aw, A, C, lptr, lcol, lval, Dp, LB, LINV, PQ, delta, info);
+                       queue, nb, Aw, A, C, lptr, lcol, lval, Dp, LB, LINV, PQ, delta, info);
   } else {
     const size_t shmem = (size_t)(max_rt + 6) * TS * BfLd<6>::LD * sizeof(T);
     hipLaunchKernelGGL((k_factor_fused<T, 6>), dim3(grid), dim3(512), shmem, st, blk, order, n,
-                       queue, n0, Aw, A, C, lptr, lcol, lval, Dp, LB, LINV, PQ, delta, info);
+                       queue, nb, Aw, A, C, lptr, lcol, lval, Dp, LB, LINV, PQ, delta, info);
   }
 }
 template void launch_factor_fused<double>(hipStream_t, const BlockInfo*, const int*, int, int, int*,
@@ -1209,17 +1220,18 @@ template void launch_block_factor_col<double>(hipStream_t, const BlockInfo*, con
 template void launch_block_factor_col<float>(hipStream_t, const BlockInfo*, const int*, int, int,
                                              float*, float*, double*, DevInfo*);
 
-void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
-                     const long long* tdoff, const long long* tooff, const long long* eoff,
-                     const double* PQ, const double* F0, const long long* loff, double delta,
-                     const double* D0, double* Td, double* To, double* E, double* S00,
-                     double* thrT) {
+void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int nb, int n0, long long nl,
+                     const int* lsz, const long long* tdoff, const long long* tooff,
+                     const long long* eoff, const double* PQ, const double* F0,
+                     const long long* loff, double delta, const double* D0, double* Td,
+                     double* To, double* E, double* S00, double* thrT) {
   const int P = N - 1;
   if (P > 0)
-    hipLaunchKernelGGL(k_assemble_pairs, dim3(P), dim3(256), 0, st, blk, P, n0, lsz, tdoff,
+    hipLaunchKernelGGL(k_assemble_pairs, dim3(P), dim3(256), 0, st, blk, P, nb, n0, lsz, tdoff,
                        tooff, eoff, PQ, F0, loff, delta, Td, To, E, thrT);
-  if (n0 > 0)
-    hipLaunchKernelGGL(k_assemble_s00, dim3(n0 * n0), dim3(256), 0, st, blk, N, n0, PQ, D0, S00);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_assemble_s00, dim3(nb * nb), dim3(256), 0, st, blk, N, nb, n0, nl, PQ,
+                       D0, F0, delta, S00);
 }
 
 }  // namespace ahlp

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_rows_nv(const BlockInfo* __restrict__ b
   for (int k = 0; k < NV; ++k) {
     if (!ra.with_C[k]) continue;
     const double* x0v = ra.v[k] + d0off;
-    for (int Q = 0; Q < b.kt0; ++Q) {
+    for (int Q = 0; Q < b.kc0; ++Q) {
       const dv2* ct = reinterpret_cast<const dv2*>(C + c_tile(b, I, Q));
       const dv2 a0 = ld_stream2(ct + lane), a1 = ld_stream2(ct + 64 + lane);
       const double x0 = x0v[Q * TS + cb], x1 = x0v[Q * TS + 8 + cb];
@@ -156,6 +156,37 @@ __global__ void k_linkrows(const BlockInfo* __restrict__ blk, int P, int n0,
       out[o] = (base ? base[o] : 0.0) + alpha * s;
     }
   }
+}
+
+__device__ double block_reduce(int op, double v);
+
+// Global rows: out[k] = base[k] + alpha * (sum_i Wg_i xp_i [+ Wg0 x0]), one
+// workgroup per row.  Block i's part of row k is its border section's sparse
+// row k (the same compressed rows as the link rows); each thread sums a fixed
+// strided subset of the blocks, then a fixed reduction tree.  Wg0 is row
+// nl + k of the extended F0.
+__global__ __launch_bounds__(256) void k_globalrows(const BlockInfo* __restrict__ blk, int N,
+                                                    int n0, long long nl,
+                                                    const int* __restrict__ lptr,
+                                                    const int* __restrict__ lcol,
+                                                    const double* __restrict__ lval,
+                                                    const double* __restrict__ xp,
+                                                    const double* __restrict__ x0,
+                                                    const double* __restrict__ F0,
+                                                    const double* __restrict__ base, double alpha,
+                                                    double* __restrict__ out) {
+  const int k = blockIdx.x;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const BlockInfo& b = blk[i];
+    const int q = TS * (b.ktL + b.ktR) + k;
+    for (int e = lptr[b.csr_off + q]; e < lptr[b.csr_off + q + 1]; ++e)
+      v += lval[e] * xp[b.dpoff + lcol[e]];
+  }
+  if (F0 && x0)
+    for (int c = threadIdx.x; c < n0; c += blockDim.x) v += F0[(nl + k) * n0 + c] * x0[c];
+  const double t = block_reduce(0, v);
+  if (threadIdx.x == 0) out[k] = (base ? base[k] : 0.0) + alpha * t;
 }
 
 // ------------------------------------------------------------ block columns
@@ -374,7 +405,7 @@ __global__ __launch_bounds__(256) void k_block_fwd(const BlockInfo* __restrict__
 // of the Schur solution: left pair, right pair, x_0) fills the bordered rows.
 // Writes dy (canonical) and the padded copy dyp.
 template <typename T>
-__global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__ blk, int n0,
+__global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__ blk, int nb,
                                                    long long nl, const T* __restrict__ LB,
                                                    const T* __restrict__ LINV,
                                                    const double* __restrict__ v,
@@ -394,7 +425,7 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
     } else {
       int qi;
       bool real;
-      const int sec = link_section(b, r - nm, &qi, n0, &real);
+      const int sec = link_section(b, r - nm, &qi, nb, &real);
       val = 0.0;
       if (real) {
         if (sec == 0) val = u[b.loffL + qi];
@@ -461,12 +492,12 @@ __global__ __launch_bounds__(256) void k_block_bwd(const BlockInfo* __restrict__
   }
 }
 
-// Schur right-hand side: s_L[pair j] += qn_j[right section] + qn_{j+1}[left section];
-// s_0 = rhx_0 + sum_i qn_i[x_0 section] (fixed order).
-// Schur right-hand side (Alg. 3): s_L += the two blocks' bordered-row parts of
-// each link pair; s_0 = rhx_0 + sum over blocks (fixed order).  Blocks below
-// npb handle pairs, the next n0 blocks one x_0 entry each.
-__global__ __launch_bounds__(256) void k_schur_rhs(const BlockInfo* __restrict__ blk, int N, int n0,
+// Schur right-hand side (Alg. 3): s_L[pair j] += qn_j[right section] +
+// qn_{j+1}[left section]; the border (global rows, then x_0): s_b += sum_i
+// qn_i[border section] (fixed order), on top of the global rows' part s_b
+// already holds (b < ng) or of rhx_0 (x_0 entries).  Blocks below npb handle
+// pairs, the next nb blocks one border entry each.
+__global__ __launch_bounds__(256) void k_schur_rhs(const BlockInfo* __restrict__ blk, int N, int nb,
                                                    const int* __restrict__ lsz,
                                                    const long long* __restrict__ loff, long long nl,
                                                    int npb, const double* __restrict__ qn,
@@ -488,7 +519,8 @@ __global__ __launch_bounds__(256) void k_schur_rhs(const BlockInfo* __restrict__
     v += qn[b.qoff + TS * (b.ktL + b.ktR) + c];
   }
   const double t = block_reduce(0, v);
-  if (threadIdx.x == 0) s[nl + c] = rhx0[c] + t;
+  const int ng = blk[0].ng;
+  if (threadIdx.x == 0) s[nl + c] = (c < ng ? s[nl + c] : rhx0[c - ng]) + t;
 }
 
 // End of a solve for the x_0 columns and the link rows: g_0 = sum of the
@@ -961,11 +993,11 @@ void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, c
   hipLaunchKernelGGL(k_block_fwd<T>, dim3(N), dim3(256), sh, st, blk, LB, LINV, tin, tv, qn);
 }
 template <typename T>
-void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl,
+void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int nb, long long nl,
                       int max_rt, const T* LB, const T* LINV, const double* v, const double* u,
                       double* dy, double* dyp) {
   const size_t sh = (size_t)TS * max_rt * sizeof(double);
-  hipLaunchKernelGGL(k_block_bwd<T>, dim3(N), dim3(256), sh, st, blk, n0, nl, LB, LINV, v, u, dy,
+  hipLaunchKernelGGL(k_block_bwd<T>, dim3(N), dim3(256), sh, st, blk, nb, nl, LB, LINV, v, u, dy,
                      dyp);
 }
 template void launch_block_fwd<double>(hipStream_t, const BlockInfo*, int, int, const double*,
@@ -978,14 +1010,22 @@ template void launch_block_bwd<double>(hipStream_t, const BlockInfo*, int, int, 
 template void launch_block_bwd<float>(hipStream_t, const BlockInfo*, int, int, long long, int,
                                       const float*, const float*, const double*, const double*,
                                       double*, double*);
-void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
+void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int nb, const int* lsz,
                       const long long* loff, long long nl, const double* qn, const double* rhx0,
                       double* s) {
   const int P = N - 1;
   const int npb = P > 0 ? (P < 1024 ? P : 1024) : 0;
-  if (npb + n0 > 0)
-    hipLaunchKernelGGL(k_schur_rhs, dim3(npb + n0), dim3(256), 0, st, blk, N, n0, lsz, loff, nl,
+  if (npb + nb > 0)
+    hipLaunchKernelGGL(k_schur_rhs, dim3(npb + nb), dim3(256), 0, st, blk, N, nb, lsz, loff, nl,
                        npb, qn, rhx0, s);
+}
+void launch_globalrows(hipStream_t st, const BlockInfo* blk, int N, int ng, int n0, long long nl,
+                       const int* lptr, const int* lcol, const double* lval, const double* xp,
+                       const double* x0, const double* F0, const double* base, double alpha,
+                       double* out) {
+  if (ng > 0)
+    hipLaunchKernelGGL(k_globalrows, dim3(ng), dim3(256), 0, st, blk, N, n0, nl, lptr, lcol, lval,
+                       xp, x0, F0, base, alpha, out);
 }
 void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, const double* part,
                        const double* F0, const double* u, long long x0off, long long mblk,

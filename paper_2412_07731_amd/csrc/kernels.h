@@ -13,7 +13,8 @@ template <typename T>
 void launch_syrk(hipStream_t st, const BlockInfo* blk, const int4* items, int nitems,
                  const T* A, const double* Dp, T* LB, double delta);
 template <typename T>
-void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int n0,
+// nb: width of the border section (global rows, then x_0)
+void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int nitems, int nb,
                  const double* A, const double* C, const int* lptr, const int* lcol,
                  const double* lval, const double* Dp, T* LB, double* PQ);
 // Block factorization of the blocks order[0..n) (bordered Cholesky giving L_i
@@ -34,21 +35,25 @@ bool block_factor_panel8_fits(int rt);   // the eight-wave form
 // panel factorization and Schur contributions); num_cu: compute units.
 template <typename T>
 void launch_factor_fused(hipStream_t st, const BlockInfo* blk, const int* order, int n,
-                         int max_rt, int* queue, int n0, const T* Aw, const double* A,
+                         int max_rt, int* queue, int nb, const T* Aw, const double* A,
                          const double* C, const int* lptr, const int* lcol, const double* lval,
                          const double* Dp, T* LB, T* LINV, double* PQ, double delta,
                          DevInfo* info, int num_cu);
 bool factor_fused_fits(int rt, int mt);
-void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
-                     const long long* tdoff, const long long* tooff, const long long* eoff,
-                     const double* PQ, const double* F0, const long long* loff, double delta,
-                     const double* D0, double* Td, double* To, double* E, double* S00,
-                     double* thrT);
+// T, E (l_j x nb) and S00 (nb x nb) of S; F0: the extended (nl + ng) x n0
+// x_0 coupling (link rows, then the global rows' Wg0), or null
+void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int nb, int n0, long long nl,
+                     const int* lsz, const long long* tdoff, const long long* tooff,
+                     const long long* eoff, const double* PQ, const double* F0,
+                     const long long* loff, double delta, const double* D0, double* Td,
+                     double* To, double* E, double* S00, double* thrT);
 void launch_convert_f32(hipStream_t st, long long n, const double* src, float* dst);
 
-// Schur complement (k_chain.hip)
+// Schur complement (k_chain.hip).  Its border (called n0 in the Schur
+// kernels) is the global rows' duals (the first ng entries, a positive
+// definite part) followed by x_0 (negative definite).
 struct ChainArgs {
-  int P, G, n0;
+  int P, G, n0, ng;
   const int* l;            // [P]
   const long long* tdoff;  // [P]    l_j^2 blocks (T_jj, L_j, L_j^-1)
   const long long* tooff;  // [P-1]  l_{j+1} x l_j blocks (T_{j+1,j}, Yn_j)
@@ -91,7 +96,7 @@ constexpr int SEGRHS_STRIDE = 2 * LMAX + N0MAX;
 // Block cyclic reduction of T and the border (k_bcr.hip), pairs of <= 16 rows,
 // n0 <= 64.  Tiles are 16x16 column-major, padded.
 struct BcrArgs {
-  int P, n0, t0;
+  int P, n0, t0, ng;                              // n0: border width, ng of it global rows
   int tp;                                         // tiles per pair side (1 or 2)
   const int* l;
   const long long* tdoff;
@@ -193,6 +198,11 @@ void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int
                  const int* crow, const double* cval, int mode, const double* cvec,
                  const double* zvec, const double* Dp, double* gout, double* out,
                  const DzArgs& dzv = DzArgs{});
+// global rows: out = base + alpha (Wg xp + Wg0 x0); F0 the extended x_0 coupling
+void launch_globalrows(hipStream_t st, const BlockInfo* blk, int N, int ng, int n0, long long nl,
+                       const int* lptr, const int* lcol, const double* lval, const double* xp,
+                       const double* x0, const double* F0, const double* base, double alpha,
+                       double* out);
 void launch_ccols(hipStream_t st, const BlockInfo* blk, const int2* ctiles, int nctile, int n0,
                   const double* C, const double* yp, double* part);
 void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, const double* part,
@@ -202,10 +212,10 @@ template <typename T>
 void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, const T* LB,
                       const T* LINV, const double* tin, double* tv, double* qn);
 template <typename T>
-void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int n0, long long nl,
+void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int nb, long long nl,
                       int max_rt, const T* LB, const T* LINV, const double* v, const double* u,
                       double* dy, double* dyp);
-void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int n0, const int* lsz,
+void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int nb, const int* lsz,
                       const long long* loff, long long nl, const double* qn, const double* rhx0,
                       double* s);
 void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, const double* part,

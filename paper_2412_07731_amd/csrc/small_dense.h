@@ -82,6 +82,46 @@ __device__ inline int sm_chol(double* A, int n, double thr) {
   return s_cnt;
 }
 
+// Signed lower Cholesky of a quasi-definite matrix, in place: A = L T L' with
+// T = diag(-1 for the first nneg columns, +1 after) and L with a positive
+// diagonal (the pivot of column j is T_jj times the updated diagonal; the
+// pivot rule applies to it).  nneg = 0 is sm_chol.  Returns the number of
+// replaced pivots (same value in every thread).
+__device__ inline int sm_chol_signed(double* A, int n, int nneg, double thr) {
+  __shared__ double s_l;
+  __shared__ int s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  for (int j = 0; j < n; ++j) {
+    const double tj = j < nneg ? -1.0 : 1.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double d = tj * A[j + j * n];
+      if (!(d > thr)) {
+        d = PIVOT_BIG;
+        ++s_cnt;
+      }
+      s_l = sqrt(d);
+      A[j + j * n] = s_l;
+    }
+    __syncthreads();
+    const double ljj = s_l;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[i + j * n] = tj * A[i + j * n] / ljj;
+    __syncthreads();
+    const int r = n - j - 1;
+    for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+      const int i = j + 1 + idx % r, k = j + 1 + idx / r;
+      if (i >= k) A[i + k * n] -= tj * A[i + j * n] * A[k + j * n];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, k = idx / n;
+    if (i < k) A[idx] = 0.0;
+  }
+  __syncthreads();
+  return s_cnt;
+}
+
 // Li = L^-1 for lower triangular L (n x n); one thread per column.
 __device__ inline void sm_trinv(const double* L, double* Li, int n) {
   for (int k = threadIdx.x; k < n; k += blockDim.x) {

@@ -44,6 +44,16 @@ the x_0-only ones), then the upper-bound rows in the order of 4.  x_0: its
 n0 columns, then x- of its free entries.  Link pair j: its equality rows,
 then its inequality rows.
 
+Dense layer (to_standard(g, dense=True)): the global rows and the x_0-only
+equality rows stay whole, as global rows of the standard form, which the
+library keeps in the border of the Schur complement (the dense layer of
+Sec. 4.1) instead of chaining them through the blocks.  An inequality global
+row dg <= r(x) <= fg becomes r(x) - t = 0 with its slack t a new linking
+variable: x_0's columns are its own, x- of its free entries, then these
+slacks in global row order (their upper-bound slacks, when both sides are
+finite, join block 1's like those of the other x_0 columns).  Global rows of
+the standard form: those of g in order, then the x_0-only equality rows.
+
 Only the primal solution is mapped back; duals of the general form are not.
 """
 from __future__ import annotations
@@ -242,24 +252,34 @@ def chain_globals(g: GeneralInstance) -> GeneralInstance:
     return out
 
 
-def to_standard(g: GeneralInstance):
-    """The equivalent standard-form Instance and the map back to x."""
-    if g.A0 is not None and g.A0.shape[0]:
+def to_standard(g: GeneralInstance, dense=False):
+    """The equivalent standard-form Instance and the map back to x (global
+    rows chained, x_0-only equality rows eliminated; with dense, both kept
+    whole as global rows)."""
+    if not dense and g.A0 is not None and g.A0.shape[0]:
         h, e, E = eliminate_x0_rows(g)
         inst, mp = to_standard(h)
         mp.x0map = (e, E, int(g.n.sum()))
         return inst, mp
-    if g.ng:
+    if not dense and g.ng:
         gc = chain_globals(g)
         inst, mp = to_standard(gc)
         mp.keep = gc.orig_cols
         return inst, mp
     N, n0 = g.N, g.n0
     xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
-    # x_0
+    # x_0, then (dense) the slacks of the inequality global rows
     T0, off0, ub0 = _var_map(g.lo[xo[-1]:], g.up[xo[-1]:])
+    gslk = {}
+    if dense:
+        for k in range(g.ng):
+            if g.dg[k] != g.fg[k]:
+                gslk[k] = (T0.shape[1] + len(gslk),) + _slack_col(g.dg[k], g.fg[k])
+        T0 = np.hstack([T0, np.zeros((n0, len(gslk)))])
     n0s = T0.shape[1]
     ub0_all = np.concatenate([ub0, np.full(n0s - n0, np.inf)])
+    for k, (col, _, _, ubk) in gslk.items():
+        ub0_all[col] = ubk
     # per block: primary and split columns, then inequality slacks
     Tb, offb, cols, slk = [], [], [], []
     for i in range(N):
@@ -354,15 +374,41 @@ def to_standard(g: GeneralInstance):
         FR.append(np.vstack(fr)); FL.append(np.vstack(fl)); F0rows.append(np.vstack(f0))
         bl.append(np.concatenate(rhs))
 
+    # global rows (dense): r(x_std) [- sgn t'] = side - r(offsets) [+ offset of t]
+    Wg = [[] for _ in range(N)]
+    Wg0, bg = [], []
+    if dense:
+        for k in range(g.ng):
+            for i in range(N):
+                Wg[i].append(g.Wg[i][k] @ Tfull[i])
+            w0 = g.Wg0[k] @ T0
+            rhs = -sum(g.Wg[i][k] @ offb[i] for i in range(N)) - g.Wg0[k] @ off0
+            if k in gslk:
+                col, sgn, toff, _ = gslk[k]
+                w0[col] -= sgn
+                rhs += toff
+            else:
+                rhs += g.dg[k]
+            Wg0.append(w0)
+            bg.append(rhs)
+        for q in range(0 if g.A0 is None else g.A0.shape[0]):
+            for i in range(N):
+                Wg[i].append(np.zeros(ncol[i]))
+            Wg0.append(g.A0[q] @ T0)
+            bg.append(g.b0[q] - g.A0[q] @ off0)
+
     ms = np.array([a.shape[0] for a in A], dtype=np.int64)
     ns = np.array(ncol, dtype=np.int64)
     ls = np.array([f.shape[0] for f in FR], dtype=np.int64)
     F0 = np.vstack(F0rows) if F0rows and any(np.any(f) for f in F0rows) else None
-    b = np.concatenate(bs + bl) if (bs or bl) else np.zeros(0)
+    b = np.concatenate(bs + bl + [np.asarray(bg, dtype=float)]) if (bs or bl or bg) else np.zeros(0)
     cs = [Tfull[i].T @ g.c[xo[i]:xo[i + 1]] for i in range(N)] + [T0.T @ g.c[xo[-1]:]]
     const = float(sum(g.c[xo[i]:xo[i + 1]] @ offb[i] for i in range(N)) + g.c[xo[-1]:] @ off0)
     inst = Instance(N=N, n0=n0s, m=ms, n=ns, l=ls, A=A, C=C, FR=FR, FL=FL, F0=F0, b=b,
                     c=np.concatenate(cs))
+    if bg:
+        inst.Wg = [np.array(Wg[i]).reshape(len(bg), ncol[i]) for i in range(N)]
+        inst.Wg0 = np.array(Wg0).reshape(len(bg), n0s)
     mp = StandardMap(T=Tfull + [T0], off=offb + [off0],
                      xoff_std=np.concatenate([[0], np.cumsum(ns)]).astype(np.int64), const=const)
     return inst, mp
@@ -382,15 +428,19 @@ def from_standard(mp: StandardMap, x_std: np.ndarray) -> np.ndarray:
     return x
 
 
-def solve(g: GeneralInstance, stream=None, **opts):
+def solve(g: GeneralInstance, stream=None, dense=False, history=False, **opts):
     """Solve a general instance on the current HIP device.  Returns
     (x, objective, result) with x in the general form's variables and the
-    result dictionary of the standard-form interior-point run."""
+    result dictionary of the standard-form interior-point run (with history,
+    also its per-iteration records under "history").  dense: keep the global
+    rows in the border of the Schur complement (see to_standard)."""
     from .ahlp import Problem
-    inst, mp = to_standard(g)
+    inst, mp = to_standard(g, dense=dense)
     P = Problem(inst, stream=stream)
     try:
         xs, _, _, res = P.ipm(stream=stream, **opts)
+        if history:
+            res["history"] = P.history()
         x = from_standard(mp, xs.detach().cpu().numpy())
     finally:
         P.close()

@@ -13,9 +13,10 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracl
 ETA = 1e-10
 
 
-def golden(config, seed, gondzio=0):
+def golden(config, seed, gondzio=0, dense=False):
     for r in GOLDEN["runs"]:
-        if r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio:
+        if (r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio
+                and r.get("dense", False) == dense):
             return r
     return None
 

@@ -17,28 +17,9 @@ from oracle import ipm  # noqa: E402
 from paper_2412_07731_amd import gen  # noqa: E402
 
 
-def run_general(config, seed):
-    """General-form instance (bounds, inequality rows): the oracle's
-    reformulation and IPM; objective in the general form's variables."""
-    g = gen.generate_general(config, seed)
-    t = time.time()
-    x, f, r = ogeneral.solve(g)
-    return dict(config=config, seed=seed, gondzio=0, status=r.status, iterations=r.iterations,
-                objective=f, pobj_std=r.pobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
-                mu=r.mu, seconds=round(time.time() - t, 2))
-
-
-def run(config, seed, gondzio=0):
-    if config in gen.GENERAL_CONFIGS:
-        return run_general(config, seed)
-    inst = gen.generate(config, seed)
-    t = time.time()
-    r = ipm.solve(inst, ipm.Options(gondzio=gondzio))
-    return dict(config=config, seed=seed, gondzio=gondzio, status=r.status, iterations=r.iterations,
-                pobj=r.pobj, dobj=r.dobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
-                mu=r.mu, fstar=inst.fstar, refine_steps=r.refine_steps,
-                max_bkerr=r.max_bkerr, pivots=r.pivots,
-                mu_trace=[h["mu"] for h in r.history],
+def traces(r):
+    """Per-iteration records of an oracle run and its start solves."""
+    return dict(mu_trace=[h["mu"] for h in r.history],
                 sigma_trace=[h["sigma"] for h in r.history],
                 alpha_p=[h["ap"] for h in r.history],
                 alpha_d=[h["ad"] for h in r.history],
@@ -48,33 +29,67 @@ def run(config, seed, gondzio=0):
                 bkerr_corr=[h["bkerr"] for h in r.history],
                 start_bkerr=[r.solves[0][0], r.solves[1][0]],
                 correctors=sum(h.get("correctors", 0) for h in r.history),
-                correctors_trace=[h.get("correctors", 0) for h in r.history],
+                correctors_trace=[h.get("correctors", 0) for h in r.history])
+
+
+def run_general(config, seed, dense=False):
+    """General-form instance (bounds, inequality rows): the oracle's
+    reformulation and IPM; objective in the general form's variables.  With
+    dense, global rows and x_0-only equality rows stay whole in the border of
+    the Schur complement (the dense layer), and the trajectory is recorded."""
+    g = gen.generate_general(config, seed)
+    t = time.time()
+    x, f, r = ogeneral.solve(g, dense=dense)
+    out = dict(config=config, seed=seed, gondzio=0, status=r.status, iterations=r.iterations,
+               objective=f, pobj_std=r.pobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
+               mu=r.mu, seconds=round(time.time() - t, 2))
+    if dense:
+        out.update(dense=True, **traces(r))
+    return out
+
+
+def run(config, seed, gondzio=0, dense=False):
+    if config in gen.GENERAL_CONFIGS:
+        return run_general(config, seed, dense)
+    inst = gen.generate(config, seed)
+    t = time.time()
+    r = ipm.solve(inst, ipm.Options(gondzio=gondzio))
+    return dict(config=config, seed=seed, gondzio=gondzio, status=r.status, iterations=r.iterations,
+                pobj=r.pobj, dobj=r.dobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
+                mu=r.mu, fstar=inst.fstar, refine_steps=r.refine_steps,
+                max_bkerr=r.max_bkerr, pivots=r.pivots, **traces(r),
                 seconds=round(time.time() - t, 2))
 
 
 def main():
     """No arguments: rewrite the file with tiny (seeds 0-7) and n512 (seed 0).
-    --quick: tiny only.  --refresh: run again every run the file holds.  --add CONFIG:SEED[:gK] [...]: run just those (with K
-    Gondzio correctors per iteration if gK is given) and merge them into the
-    existing file (e.g. --add uneven:0, the N=2048 workload, which takes
-    minutes and several GB; --add g_medium:0, a general-form instance)."""
+    --quick: tiny only.  --refresh: run again every run the file holds.
+    --add CONFIG:SEED[:gK|:dense] [...]: run just those (with K Gondzio
+    correctors per iteration if gK is given; a general-form instance through
+    the dense layer with :dense) and merge them into the existing file (e.g.
+    --add uneven:0, the N=2048 workload, which takes minutes and several GB;
+    --add g_medium:0, a general-form instance; --add tiny_g:0, global rows)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_ipm.json")
     if "--add" in sys.argv or "--refresh" in sys.argv:
         out = json.load(open(path))
         if "--refresh" in sys.argv:
             specs = [f"{q['config']}:{q['seed']}" + (f":g{q['gondzio']}" if q.get("gondzio") else "")
-                     for q in out["runs"]]
+                     + (":dense" if q.get("dense") else "") for q in out["runs"]]
         else:
             specs = sys.argv[sys.argv.index("--add") + 1:]
         for spec in specs:
             parts = spec.split(":")
             config, seed = parts[0], int(parts[1])
-            g = int(parts[2][1:]) if len(parts) > 2 else 0      # CONFIG:SEED:gK = K correctors
-            r = run(config, seed, g)
+            dense = "dense" in parts[2:]
+            gk = [q for q in parts[2:] if q.startswith("g")]
+            g = int(gk[0][1:]) if gk else 0      # CONFIG:SEED:gK = K correctors
+            r = run(config, seed, g, dense)
+            key = (config, seed, g, dense)
             out["runs"] = [q for q in out["runs"]
-                           if (q["config"], q["seed"], q.get("gondzio", 0)) != (config, seed, g)]
+                           if (q["config"], q["seed"], q.get("gondzio", 0), q.get("dense", False)) != key]
             out["runs"].append(r)
-            print(config, seed, g, r["status"], r["iterations"], r["seconds"], "s", flush=True)
+            print(config, seed, g, "dense" if dense else "", r["status"], r["iterations"],
+                  r["seconds"], "s", flush=True)
     else:
         out = {"note": "FP64 oracle results; written by tests/golden/make_golden.py",
                "runs": []}

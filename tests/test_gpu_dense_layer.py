@@ -1,0 +1,192 @@
+"""GPU parity of the dense layer (Sec. 4.1): global linking rows kept whole in
+the border of the Schur complement, which becomes quasi-definite (positive on
+the global rows, negative on x_0) and is factored as Lb diag(I, -I) Lb'.
+
+Against the FP64 oracle (which builds the same border independently):
+* stage intermediates (L_i, W_i with the global rows' columns, the assembled
+  S over (y_L, y_G, x_0)) and the Newton direction, on shapes that take every
+  Schur path: one-tile cyclic reduction (borders of 2 to 36 entries, a tile
+  that mixes global rows and x_0), two-tile pairs, pairs over 32 rows and a
+  border over 64 (the segmented chain), a border of global rows only;
+* the direction against dense LU of the whole Newton system;
+* interior-point runs with the oracle's iteration count, objective and
+  per-iterate backward errors (tiny_g seeds 0-3, mid_g), FP32+refine;
+* general-form instances through the dense layer (global rows and x_0-only
+  equality rows kept whole) against the oracle's dense-layer runs;
+* the three launch modes bitwise equal with global rows.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import dense_kkt, newton  # noqa: E402
+from paper_2412_07731_amd import gen  # noqa: E402
+from tests._parity import check_trajectory, golden  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_07731_amd import ahlp
+    ahlp.lib()          # raises if the library is missing: no silent fallback
+    return torch.device("cuda", 0)
+
+
+def T(a, dev):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device=dev)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    s = max(float(np.max(np.abs(b))), 1e-300)
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) / s
+
+
+def shaped(N, m, n, l, n0, ng, seed=0, dens=0.4):
+    inst = gen.generate(dict(N=N, m=m, n=n, l=l, n0=n0, density=dens, ng=ng), seed)
+    rng = np.random.default_rng(seed + 200)
+    if n0 > 0 and (l != 0 and N > 1):
+        inst.F0 = rng.uniform(-1, 1, (int(inst.l.sum()), n0))
+    if n0 > 0:
+        inst.Wg0 = rng.uniform(-1, 1, (ng, n0))
+    return inst
+
+
+def point(inst, seed=1, lo=0.1, hi=2.0):
+    rng = np.random.default_rng(seed)
+    n, m = inst.n_tot, inst.m_tot
+    return (rng.uniform(lo, hi, n), rng.uniform(lo, hi, n),
+            (rng.standard_normal(n), rng.standard_normal(m), rng.standard_normal(n)))
+
+
+SHAPES = [
+    dict(N=1, m=6, n=12, l=0, n0=0, ng=2),              # border of global rows only
+    dict(N=4, m=6, n=12, l=2, n0=0, ng=1),
+    dict(N=3, m=17, n=35, l=4, n0=1, ng=3),             # ragged tiles
+    dict(N=6, m=(12, 40), n="2m", l=(1, 20), n0=5, ng=14),   # two-tile pairs; tile 0 mixes signs
+    dict(N=40, m=48, n=96, l=16, n0=16, ng=20, dens=0.1),    # mid_g: one-tile, 3 border tiles
+    dict(N=12, m=(48, 80), n="2m", l=(30, 40), n0=6, ng=5, dens=0.2),  # pairs over 32 rows: chain
+    dict(N=10, m=40, n=80, l=8, n0=40, ng=30, dens=0.2),     # border of 70 > 64: chain
+]
+
+
+def ids(s):
+    return "N{N}-l{l}-n0{n0}-ng{ng}".format(**s).replace(" ", "")
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[ids(s) for s in SHAPES])
+def test_stages_and_direction(dev, shape):
+    from paper_2412_07731_amd.ahlp import Problem
+    print("case dense layer", ids(shape), flush=True)
+    inst = shaped(**shape)
+    x, z, r = point(inst)
+    rho, delta = 1e-6, 1e-4
+    P = Problem(inst)
+    P.factor(T(x, dev), T(z, dev), rho, delta)
+    dx, dy, dz, _ = P.solve(*(T(v, dev) for v in r))
+    torch.cuda.synchronize()
+    f = newton.factor(inst, x, z, rho, delta)
+    for i in sorted({0, inst.N // 2, inst.N - 1}):
+        Lg, Wg = P.debug_block(i)
+        assert rel(Lg, f.L[i]) < 1e-12, ("L", i)
+        assert rel(Wg, f.W[i]) < 1e-11, ("W", i)
+    S = P.debug_schur()
+    assert rel(S, newton.schur_matrix_dense(f)) < 1e-11
+    d = newton.solve(f, *r)
+    for a, b in zip((dx, dy, dz), d):
+        assert rel(H(a), b) < 1e-10
+    assert P.pivots() == 0
+    P.close()
+
+
+def test_direction_against_dense_lu(dev):
+    from paper_2412_07731_amd.ahlp import Problem
+    print("case dense layer dense LU", flush=True)
+    inst = shaped(N=5, m=(3, 9), n="2m", l=(1, 3), n0=2, ng=4)
+    x, z, r = point(inst, seed=4)
+    P = Problem(inst)
+    P.factor(T(x, dev), T(z, dev), 0.0, 0.0)
+    d = P.solve(*(T(v, dev) for v in r))
+    dd = dense_kkt.solve_newton(inst, x, z, *r)
+    for a, b in zip(d[:3], dd):
+        assert rel(H(a), b) < 1e-10
+    P.close()
+
+
+@pytest.mark.parametrize("config,seed", [("tiny_g", s) for s in range(4)] + [("mid_g", 0)])
+def test_ipm_against_oracle(dev, config, seed):
+    from paper_2412_07731_amd.ahlp import Problem
+    print("case dense layer ipm", config, seed, flush=True)
+    inst = gen.generate(config, seed)
+    g = golden(config, seed)
+    P = Problem(inst)
+    x, y, z, res = P.ipm()
+    assert res["status"] == 0
+    assert res["iterations"] == g["iterations"]
+    assert abs(res["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))
+    assert abs(res["primal_obj"] - inst.fstar) <= 1e-7 * (1 + abs(inst.fstar))
+    check_trajectory(P.history(), res, g, f"{config} seed {seed}")
+    P.close()
+
+
+def test_ipm_fp32_refine(dev):
+    from paper_2412_07731_amd.ahlp import FP32_REFINE, Problem
+    print("case dense layer fp32", flush=True)
+    inst = gen.generate("mid_g", 0)
+    g = golden("mid_g", 0)
+    P = Problem(inst)
+    x, y, z, res = P.ipm(precision=FP32_REFINE)
+    assert res["status"] == 0
+    assert res["fp32_iterations"] > 0
+    assert abs(res["primal_obj"] - g["pobj"]) <= 1e-8 * max(1.0, abs(g["pobj"]))
+    P.close()
+
+
+@pytest.mark.parametrize("config,seed", [("g_small", s) for s in range(4)] + [("g_medium", 0),
+                                                                             ("g_large", 0)])
+def test_general_through_dense_layer(dev, config, seed):
+    from paper_2412_07731_amd import general
+    print("case dense layer general", config, seed, flush=True)
+    g = gen.generate_general(config, seed)
+    ref = golden(config, seed, dense=True)
+    x, f, res = general.solve(g, dense=True, history=True)
+    assert res["status"] == 0
+    assert res["iterations"] == ref["iterations"]
+    assert abs(f - ref["objective"]) <= 1e-8 * max(1.0, abs(ref["objective"]))
+    # mu within 1e-5 (1e-4 in the last three iterations, where mu is below
+    # 1e-8 of its start): the x_0-only equality rows sit in the border with
+    # only the regularization delta on their diagonal, so the border is worse
+    # conditioned than in the standard workloads and rounding differences of
+    # the two summation orders grow faster along the run
+    check_trajectory(res["history"], res, ref, f"{config} seed {seed} dense", mu_rtol_early=1e-5,
+                     mu_rtol_late=1e-4)
+    Aeq, beq, Ain, dv, fv = gen.general_matrices(g)
+    rr = Ain @ x
+    viol = max(float(np.max(np.abs(Aeq @ x - beq), initial=0.0)),
+               float(np.max(np.maximum(dv - rr, 0.0), initial=0.0)),
+               float(np.max(np.maximum(rr - fv, 0.0), initial=0.0)),
+               float(np.max(np.maximum(g.lo - x, 0.0))), float(np.max(np.maximum(x - g.up, 0.0))))
+    assert viol <= 1e-7
+
+
+def test_launch_modes_bitwise(dev):
+    from paper_2412_07731_amd.ahlp import Problem
+    print("case dense layer launch modes", flush=True)
+    inst = gen.generate("mid_g", 0)
+    out = {}
+    for mode in ("batched", "per_block", "fused"):
+        P = Problem(inst)
+        P.set_launch(mode=mode)
+        x, y, z, res = P.ipm(max_iter=4)
+        out[mode] = (H(x), H(y), H(z))
+        P.close()
+    for mode in ("per_block", "fused"):
+        for a, b in zip(out[mode], out["batched"]):
+            assert np.array_equal(a, b), mode

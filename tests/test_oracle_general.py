@@ -146,13 +146,18 @@ def test_planted_chain_mistake_fails(monkeypatch):
     assert r.status != "optimal" or abs(f - fh) > 1e-4 * max(1.0, abs(fh))
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_two_reformulations_agree(seed):
+@pytest.mark.parametrize("seed,dense", [(0, False), (1, False), (0, True), (1, True), (3, True)])
+def test_two_reformulations_agree(seed, dense):
     g = gen.generate_general("g_small", seed)
-    a, mp = general.to_standard(g)
-    b, var, const = og.reformulate(g)
-    assert a.N == b.N and a.n0 == b.n0
+    a, mp = general.to_standard(g, dense=dense)
+    b, var, const = og.reformulate(g, dense=dense)
+    assert a.N == b.N and a.n0 == b.n0 and a.ng == b.ng
     assert np.array_equal(a.m, b.m) and np.array_equal(a.n, b.n) and np.array_equal(a.l, b.l)
+    if dense:
+        assert a.ng > 0
+        assert np.allclose(a.Wg0, b.Wg0, rtol=0, atol=1e-12)
+        for u, v in zip(a.Wg, b.Wg):
+            assert u.shape == v.shape and np.allclose(u, v, rtol=0, atol=1e-12)
     for X, Y in [(a.A, b.A), (a.C, b.C), (a.FR, b.FR), (a.FL, b.FL)]:
         for u, v in zip(X, Y):
             assert u.shape == v.shape and np.allclose(u, v, rtol=0, atol=1e-12)
