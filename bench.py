@@ -10,15 +10,16 @@ SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
 factorization, predictor and corrector solves with FP64 refinement.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--no-uneven]
-                    [--no-general] [--profile [n512|uneven|general]] [--fp32]
+                    [--no-general] [--profile [n512|uneven|general|general_dense]] [--fp32]
                     [--launch batched|fused|per_block]
 
 The line also carries the sensitivity workload (N=256, nondegenerate): the
 differentiable solve, one backward pass (transposed Newton solve) and 64
 forward derivatives, with the gradient's error against the LP closed forms;
 the uneven-block workload (N=2048) with batched and per-block launches; the
-general-form workload (inequality rows and bounds, N=256); and the N=512
-solve with Gondzio correctors.
+general-form workload (inequality rows and bounds, N=256) with its global rows
+chained into two-links and kept whole in the dense layer; and the N=512 solve
+with Gondzio correctors.
 
 Prints one JSON line.
 """
@@ -246,43 +247,54 @@ def general_bench(golden_runs, steps=3):
     """General-form workload (Sec. 3.2 with inequality rows and bounds):
     256 blocks of 96..160 equality and 16..48 inequality rows, 8+4 link rows
     per pair, 4 global linking rows, 16 linking variables, every bound kind;
-    reformulated on the host
-    into the standard arrowhead form (once, timed apart) and solved by
-    libahlp in FP64."""
+    reformulated on the host into the standard arrowhead form (once, timed
+    apart) and solved by libahlp in FP64, twice: with the global rows chained
+    into two-links (the reported value) and with them kept whole in the
+    border of the Schur complement (the dense layer, "dense_layer")."""
     import torch
     from paper_2412_07731_amd import gen, general
     from paper_2412_07731_amd.ahlp import Problem
     g = gen.generate_general("g_large", 0)
-    t = time.perf_counter()
-    inst, mp = general.to_standard(g)
-    conv = time.perf_counter() - t
-    P = Problem(inst)
+
+    def leg(dense):
+        t = time.perf_counter()
+        inst, mp = general.to_standard(g, dense=dense)
+        conv = time.perf_counter() - t
+        P = Problem(inst)
+        out = {"standard_form": {"m_tot": int(inst.m_tot), "n_tot": int(inst.n_tot),
+                                 "m_i": [int(inst.m.min()), int(inst.m.max())],
+                                 "n_i": [int(inst.n.min()), int(inst.n.max())],
+                                 "global_rows": int(inst.ng), "n0": int(inst.n0),
+                                 "link_rows_per_pair": [int(inst.l.min()), int(inst.l.max())]},
+               "reformulate_s": conv}
+        P.ipm()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            xs, _, _, r = P.ipm()
+            its += r["iterations"]
+        torch.cuda.synchronize()
+        out["value"] = its / (time.perf_counter() - t)
+        out["iterations"] = r["iterations"]
+        x = general.from_standard(mp, xs.detach().cpu().numpy())
+        f = float(g.c @ x)
+        ref = [q for q in golden_runs if q["config"] == "g_large" and q["seed"] == 0
+               and bool(q.get("dense", False)) == dense]
+        if ref:
+            out["oracle_iterations"] = ref[0]["iterations"]
+            out["objective_rel_err_vs_oracle"] = abs(f - ref[0]["objective"]) / abs(ref[0]["objective"])
+        P.close()
+        return out
+
     out = {"workload": "g_large: N=256 blocks, 96..160 equality + 16..48 inequality rows, "
                        "8 equality + 4 inequality link rows per pair, 4 global linking rows "
                        "(2 equalities, 2 inequalities), 16 linking variables with 8 inequality "
                        "and 2 equality rows of their own, bounds of every kind, seed 0",
-           "unit": "IPM iterations/s",
-           "standard_form": {"m_tot": int(inst.m_tot), "n_tot": int(inst.n_tot),
-                             "m_i": [int(inst.m.min()), int(inst.m.max())],
-                             "n_i": [int(inst.n.min()), int(inst.n.max())]},
-           "reformulate_s": conv}
-    P.ipm()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    its = 0
-    for _ in range(steps):
-        xs, _, _, r = P.ipm()
-        its += r["iterations"]
-    torch.cuda.synchronize()
-    out["value"] = its / (time.perf_counter() - t)
-    out["iterations"] = r["iterations"]
-    x = general.from_standard(mp, xs.detach().cpu().numpy())
-    f = float(g.c @ x)
-    ref = [q for q in golden_runs if q["config"] == "g_large" and q["seed"] == 0]
-    if ref:
-        out["oracle_iterations"] = ref[0]["iterations"]
-        out["objective_rel_err_vs_oracle"] = abs(f - ref[0]["objective"]) / abs(ref[0]["objective"])
-    P.close()
+           "unit": "IPM iterations/s"}
+    out.update(leg(False))
+    out["dense_layer"] = leg(True)
+    out["dense_layer"]["vs_chained"] = out["dense_layer"]["value"] / out["value"]
     return out
 
 
@@ -416,9 +428,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", nargs="?", const="n512", default=None,
-                    choices=["n512", "uneven", "general"],
+                    choices=["n512", "uneven", "general", "general_dense"],
                     help="short run for profilers: one fully timed n512 solve (default), or one "
-                         "FP64 solve of the uneven or the general-form workload")
+                         "FP64 solve of the uneven or the general-form workload (global rows "
+                         "chained, or kept in the dense layer)")
     ap.add_argument("--fp32", action="store_true", help="time the FP32+refine path as the main line")
     ap.add_argument("--launch", default="batched", choices=["batched", "fused", "per_block"],
                     help="launch mode of the factorization stages for the main line")
@@ -435,7 +448,7 @@ def main():
     from paper_2412_07731_amd import gen
     from paper_2412_07731_amd.ahlp import FP32_REFINE, FP64, Problem
 
-    if args.profile in ("uneven", "general"):
+    if args.profile in ("uneven", "general", "general_dense"):
         # one solve of a secondary workload for the profilers (after one
         # untimed solve that loads and warms everything)
         torch.cuda.set_device(0)
@@ -443,7 +456,8 @@ def main():
             inst = gen.generate("uneven", 0)
         else:
             from paper_2412_07731_amd import general
-            inst, _ = general.to_standard(gen.generate_general("g_large", 0))
+            inst, _ = general.to_standard(gen.generate_general("g_large", 0),
+                                          dense=args.profile == "general_dense")
         P = Problem(inst)
         if args.profile == "uneven":
             P.autotune()

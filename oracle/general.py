@@ -34,8 +34,9 @@ rows) and the upper-bound rows; x_0 is its variables then x- of its free
 ones; link pair j has its equality rows then its inequality rows.
 
 Dense layer (``dense=True``; the HSCA dense layer of Sec. 4.1): global rows
-and the x_0-only equality rows are kept whole as global rows of the standard
-form (Wg_i x_i + ... + Wg_0 x_0 = b_G), neither chained nor eliminated.  An
+are kept whole as global rows of the standard form (Wg_i x_i + ... + Wg_0 x_0
+= b_G), not chained; the x_0-only equality rows are eliminated as above, or,
+with ``x0_border=True``, kept whole as global rows too (Wg_i = 0).  An
 inequality global row gets its slack t (bounds [dg, fg]) as a new linking
 variable: Wg x - t = 0, t an x_0 column after x_0's own and x- columns, in
 global row order; its upper-bound slack row (if both sides are finite) goes to
@@ -219,14 +220,14 @@ def chain(g: GeneralInstance):
     return out, np.array(keep, dtype=np.int64)
 
 
-def reformulate(g: GeneralInstance, dense=False):
+def reformulate(g: GeneralInstance, dense=False, x0_border=False):
     """Standard-form Instance, and for every original variable its
     (offset, [(block or -1 for x_0, column, sign)]) so x can be recovered
     (global rows are chained first, unless dense; their partial sums are
     dropped from the list)."""
-    if not dense and g.A0 is not None and g.A0.shape[0]:
+    if not (dense and x0_border) and g.A0 is not None and g.A0.shape[0]:
         h, bas, non, u, V = eliminate_x0(g)
-        inst, var, const = reformulate(h)
+        inst, var, const = reformulate(h, dense=dense)
         # x_0 entries: x_N,k as reformulated; x_B,q = u_q - V_q x_N
         xs = int(g.n.sum())
         full = list(var[:xs]) + [None] * g.n0
@@ -481,9 +482,9 @@ def recover(g: GeneralInstance, inst: Instance, var, x_std):
     return x
 
 
-def solve(g: GeneralInstance, opts=None, dense=False):
+def solve(g: GeneralInstance, opts=None, dense=False, x0_border=False):
     """Oracle solve of a general instance: (x, objective, ipm result)."""
-    inst, var, _ = reformulate(g, dense=dense)
+    inst, var, _ = reformulate(g, dense=dense, x0_border=x0_border)
     r = ipm.solve(inst, opts) if opts is not None else ipm.solve(inst)
     x = recover(g, inst, var, r.x)
     return x, float(g.c @ x), r

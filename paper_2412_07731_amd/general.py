@@ -44,10 +44,13 @@ the x_0-only ones), then the upper-bound rows in the order of 4.  x_0: its
 n0 columns, then x- of its free entries.  Link pair j: its equality rows,
 then its inequality rows.
 
-Dense layer (to_standard(g, dense=True)): the global rows and the x_0-only
-equality rows stay whole, as global rows of the standard form, which the
-library keeps in the border of the Schur complement (the dense layer of
-Sec. 4.1) instead of chaining them through the blocks.  An inequality global
+Dense layer (to_standard(g, dense=True)): the global rows stay whole, as
+global rows of the standard form, which the library keeps in the border of
+the Schur complement (the dense layer of Sec. 4.1) instead of chaining them
+through the blocks.  The x_0-only equality rows are still eliminated, unless
+x0_border=True keeps them whole as global rows too (with no block part; the
+border then carries rows whose diagonal is only the regularization delta,
+which costs refinement corrections).  An inequality global
 row dg <= r(x) <= fg becomes r(x) - t = 0 with its slack t a new linking
 variable: x_0's columns are its own, x- of its free entries, then these
 slacks in global row order (their upper-bound slacks, when both sides are
@@ -252,13 +255,14 @@ def chain_globals(g: GeneralInstance) -> GeneralInstance:
     return out
 
 
-def to_standard(g: GeneralInstance, dense=False):
+def to_standard(g: GeneralInstance, dense=False, x0_border=False):
     """The equivalent standard-form Instance and the map back to x (global
-    rows chained, x_0-only equality rows eliminated; with dense, both kept
-    whole as global rows)."""
-    if not dense and g.A0 is not None and g.A0.shape[0]:
+    rows chained, x_0-only equality rows eliminated; with dense, the global
+    rows kept whole as global rows, and with x0_border the x_0-only rows
+    too)."""
+    if not (dense and x0_border) and g.A0 is not None and g.A0.shape[0]:
         h, e, E = eliminate_x0_rows(g)
-        inst, mp = to_standard(h)
+        inst, mp = to_standard(h, dense=dense)
         mp.x0map = (e, E, int(g.n.sum()))
         return inst, mp
     if not dense and g.ng:
@@ -428,14 +432,15 @@ def from_standard(mp: StandardMap, x_std: np.ndarray) -> np.ndarray:
     return x
 
 
-def solve(g: GeneralInstance, stream=None, dense=False, history=False, **opts):
+def solve(g: GeneralInstance, stream=None, dense=False, x0_border=False, history=False, **opts):
     """Solve a general instance on the current HIP device.  Returns
     (x, objective, result) with x in the general form's variables and the
     result dictionary of the standard-form interior-point run (with history,
-    also its per-iteration records under "history").  dense: keep the global
-    rows in the border of the Schur complement (see to_standard)."""
+    also its per-iteration records under "history").  dense, x0_border: keep
+    the global rows (and the x_0-only equality rows) in the border of the
+    Schur complement (see to_standard)."""
     from .ahlp import Problem
-    inst, mp = to_standard(g, dense=dense)
+    inst, mp = to_standard(g, dense=dense, x0_border=x0_border)
     P = Problem(inst, stream=stream)
     try:
         xs, _, _, res = P.ipm(stream=stream, **opts)

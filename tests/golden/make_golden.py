@@ -29,28 +29,35 @@ def traces(r):
                 bkerr_corr=[h["bkerr"] for h in r.history],
                 start_bkerr=[r.solves[0][0], r.solves[1][0]],
                 correctors=sum(h.get("correctors", 0) for h in r.history),
-                correctors_trace=[h.get("correctors", 0) for h in r.history])
+                correctors_trace=[h.get("correctors", 0) for h in r.history],
+                # refinement corrections of every solve in call order (the two
+                # start solves, then each iteration's predictor, corrector and
+                # any correctors)
+                refine_trace=[steps for _, steps in r.solves])
 
 
-def run_general(config, seed, dense=False):
+def run_general(config, seed, dense=False, x0_border=False):
     """General-form instance (bounds, inequality rows): the oracle's
     reformulation and IPM; objective in the general form's variables.  With
-    dense, global rows and x_0-only equality rows stay whole in the border of
-    the Schur complement (the dense layer), and the trajectory is recorded."""
+    dense, the global rows stay whole in the border of the Schur complement
+    (the dense layer; with x0_border the x_0-only equality rows too), and the
+    trajectory is recorded."""
     g = gen.generate_general(config, seed)
     t = time.time()
-    x, f, r = ogeneral.solve(g, dense=dense)
+    x, f, r = ogeneral.solve(g, dense=dense, x0_border=x0_border)
     out = dict(config=config, seed=seed, gondzio=0, status=r.status, iterations=r.iterations,
                objective=f, pobj_std=r.pobj, relgap=r.relgap, pinf=r.pinf, dinf=r.dinf,
                mu=r.mu, seconds=round(time.time() - t, 2))
     if dense:
         out.update(dense=True, **traces(r))
+        if x0_border:
+            out["x0_border"] = True
     return out
 
 
-def run(config, seed, gondzio=0, dense=False):
+def run(config, seed, gondzio=0, dense=False, x0_border=False):
     if config in gen.GENERAL_CONFIGS:
-        return run_general(config, seed, dense)
+        return run_general(config, seed, dense, x0_border)
     inst = gen.generate(config, seed)
     t = time.time()
     r = ipm.solve(inst, ipm.Options(gondzio=gondzio))
@@ -64,9 +71,10 @@ def run(config, seed, gondzio=0, dense=False):
 def main():
     """No arguments: rewrite the file with tiny (seeds 0-7) and n512 (seed 0).
     --quick: tiny only.  --refresh: run again every run the file holds.
-    --add CONFIG:SEED[:gK|:dense] [...]: run just those (with K Gondzio
-    correctors per iteration if gK is given; a general-form instance through
-    the dense layer with :dense) and merge them into the existing file (e.g.
+    --add CONFIG:SEED[:gK|:dense|:dense_x0] [...]: run just those (with K
+    Gondzio correctors per iteration if gK is given; a general-form instance
+    through the dense layer with :dense, with its x_0-only rows in the border
+    too with :dense_x0) and merge them into the existing file (e.g.
     --add uneven:0, the N=2048 workload, which takes minutes and several GB;
     --add g_medium:0, a general-form instance; --add tiny_g:0, global rows)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_ipm.json")
@@ -74,22 +82,25 @@ def main():
         out = json.load(open(path))
         if "--refresh" in sys.argv:
             specs = [f"{q['config']}:{q['seed']}" + (f":g{q['gondzio']}" if q.get("gondzio") else "")
-                     + (":dense" if q.get("dense") else "") for q in out["runs"]]
+                     + (":dense_x0" if q.get("x0_border") else ":dense" if q.get("dense") else "")
+                     for q in out["runs"]]
         else:
             specs = sys.argv[sys.argv.index("--add") + 1:]
         for spec in specs:
             parts = spec.split(":")
             config, seed = parts[0], int(parts[1])
-            dense = "dense" in parts[2:]
+            x0b = "dense_x0" in parts[2:]
+            dense = x0b or "dense" in parts[2:]
             gk = [q for q in parts[2:] if q.startswith("g")]
             g = int(gk[0][1:]) if gk else 0      # CONFIG:SEED:gK = K correctors
-            r = run(config, seed, g, dense)
-            key = (config, seed, g, dense)
+            r = run(config, seed, g, dense, x0b)
+            key = (config, seed, g, dense, x0b)
             out["runs"] = [q for q in out["runs"]
-                           if (q["config"], q["seed"], q.get("gondzio", 0), q.get("dense", False)) != key]
+                           if (q["config"], q["seed"], q.get("gondzio", 0), q.get("dense", False),
+                               q.get("x0_border", False)) != key]
             out["runs"].append(r)
-            print(config, seed, g, "dense" if dense else "", r["status"], r["iterations"],
-                  r["seconds"], "s", flush=True)
+            print(config, seed, g, "dense_x0" if x0b else "dense" if dense else "", r["status"],
+                  r["iterations"], r["seconds"], "s", flush=True)
     else:
         out = {"note": "FP64 oracle results; written by tests/golden/make_golden.py",
                "runs": []}

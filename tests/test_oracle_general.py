@@ -14,9 +14,9 @@ oracle IPM), to things other than itself:
   part) fail the HiGHS pin;
 * the GPU path's reformulation (paper_2412_07731_amd.general, written
   separately) produces the same standard-form instance;
-* the dense layer (global rows and x_0-only equality rows kept whole, in the
-  border of S) reaches HiGHS's optimum of the untransformed LP too, and a
-  dropped x_0 part of its global rows fails that pin.
+* the dense layer (global rows kept whole in the border of S, and with
+  x0_border the x_0-only equality rows too) reaches HiGHS's optimum of the
+  untransformed LP, and a dropped x_0 part of its global rows fails that pin.
 """
 import numpy as np
 import pytest
@@ -146,11 +146,12 @@ def test_planted_chain_mistake_fails(monkeypatch):
     assert r.status != "optimal" or abs(f - fh) > 1e-4 * max(1.0, abs(fh))
 
 
-@pytest.mark.parametrize("seed,dense", [(0, False), (1, False), (0, True), (1, True), (3, True)])
-def test_two_reformulations_agree(seed, dense):
+@pytest.mark.parametrize("seed,dense,x0b", [(0, False, False), (1, False, False), (0, True, False),
+                                            (1, True, False), (3, True, True), (1, True, True)])
+def test_two_reformulations_agree(seed, dense, x0b):
     g = gen.generate_general("g_small", seed)
-    a, mp = general.to_standard(g, dense=dense)
-    b, var, const = og.reformulate(g, dense=dense)
+    a, mp = general.to_standard(g, dense=dense, x0_border=x0b)
+    b, var, const = og.reformulate(g, dense=dense, x0_border=x0b)
     assert a.N == b.N and a.n0 == b.n0 and a.ng == b.ng
     assert np.array_equal(a.m, b.m) and np.array_equal(a.n, b.n) and np.array_equal(a.l, b.l)
     if dense:
@@ -168,15 +169,22 @@ def test_two_reformulations_agree(seed, dense):
     assert np.allclose(general.from_standard(mp, xs), og.recover(g, b, var, xs), rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_dense_layer_matches_highs(seed):
+@pytest.mark.parametrize("seed,x0_border", [(0, False), (1, False), (2, False), (3, False),
+                                            (0, True), (1, True), (2, True), (3, True)])
+def test_dense_layer_matches_highs(seed, x0_border):
     g = gen.generate_general("g_small", seed)
-    inst, var, _ = og.reformulate(g, dense=True)
-    # the global rows and the x_0-only equality rows stay whole: no chained
-    # partial sums, no eliminated x_0 entries
-    assert inst.ng == g.ng + g.A0.shape[0]
-    assert inst.n0 == g.n0 + int(np.sum(g.dg != g.fg)) + int(np.sum(np.isinf(g.lo[-g.n0:]) & np.isinf(g.up[-g.n0:])))
-    x, f, r = og.solve(g, dense=True)
+    inst, var, _ = og.reformulate(g, dense=True, x0_border=x0_border)
+    # the global rows stay whole (no chained partial sums); with x0_border so
+    # do the x_0-only equality rows (no eliminated x_0 entries)
+    me0 = g.A0.shape[0]
+    assert inst.ng == g.ng + (me0 if x0_border else 0)
+    x0v = slice(g.n_tot - g.n0, g.n_tot)
+    free0 = np.isinf(g.lo[x0v]) & np.isinf(g.up[x0v])
+    if x0_border:
+        assert inst.n0 == g.n0 + int(np.sum(g.dg != g.fg)) + int(np.sum(free0))
+    else:
+        assert inst.n0 < g.n0 + int(np.sum(g.dg != g.fg)) + int(np.sum(free0))
+    x, f, r = og.solve(g, dense=True, x0_border=x0_border)
     assert r.status == "optimal"
     fh = highs(g)
     assert abs(f - fh) <= 1e-7 * max(1.0, abs(fh))
@@ -190,8 +198,8 @@ def test_planted_dense_layer_mistake_fails(monkeypatch):
     fh = highs(g)
     real = og.reformulate
 
-    def broken(gg, dense=False):
-        inst, var, const = real(gg, dense=dense)
+    def broken(gg, dense=False, x0_border=False):
+        inst, var, const = real(gg, dense=dense, x0_border=x0_border)
         inst.Wg0 = np.zeros_like(inst.Wg0)
         return inst, var, const
 
