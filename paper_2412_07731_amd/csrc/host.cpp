@@ -184,6 +184,7 @@ struct ahlp_problem_s {
   std::vector<int2> seg;
   long long n_tot = 0, m_tot = 0, nl = 0, mblk = 0, x0off = 0, d0off = 0, dp_total = 0;
   long long nle = 0;    // link rows plus global rows: the dual rows after the blocks
+  long long f0first = 0;   // first row of F0 that may be nonzero (nl when only Wg0 is)
   long long vp_total = 0, q_total = 0, a_total = 0, c_total = 0, lb_total = 0, linv_total = 0,
             pq_total = 0;
   int max_rt = 0, lmax = 0;
@@ -198,6 +199,9 @@ struct ahlp_problem_s {
   float* A32 = nullptr;
   int *lptr = nullptr, *lcol = nullptr, *cptr = nullptr, *crow = nullptr;
   double *lval = nullptr, *cval = nullptr;
+  // the global rows as compressed rows over the padded x (index dpoff + column)
+  int *gptr = nullptr, *gidx = nullptr;
+  double* gval = nullptr;
   int4* syrk_items = nullptr;
   int nsyrk = 0;
   // block-factor buckets: bf_order[0, n_panel) for the four-wave panel
@@ -584,7 +588,8 @@ ahlp_status_t do_factor(ahlp_problem_t p, const double* x, const double* z, int 
   }
   p->timer.begin(AHLP_ST_SCHUR);
   launch_assemble(st, p->blk, p->N, p->nb, p->n0, p->nl, p->d_l, p->d_tdoff, p->d_tooff,
-                  p->d_eoff, p->PQ, p->F0, p->d_loff, delta, p->Dp + p->d0off, p->Td, p->To, p->E,
+                  p->d_eoff, p->PQ, p->f0first == 0 ? p->F0 : nullptr, p->F0, p->d_loff, delta,
+                  p->Dp + p->d0off, p->Td, p->To, p->E,
                   p->S00, p->thrT);
   p->timer.end();
   p->timer.f32 = false;
@@ -648,10 +653,9 @@ void solve_blocks_bwd(ahlp_problem_t p, hipStream_t st, const T* LB, const T* LI
 void link_global_rows(ahlp_problem_t p, const double* xp, const double* x0, const double* base,
                       double alpha, double* out, hipStream_t st) {
   const double* F0 = x0 ? p->F0 : nullptr;
-  launch_linkrows(st, p->blk, p->P, p->n0, p->d_l, p->d_loff, p->lptr, p->lcol, p->lval, xp, x0, F0,
+  launch_linkrows(st, p->blk, p->P, p->ng, p->n0, p->d_l, p->d_loff, p->nl, p->lptr, p->lcol,
+                  p->lval, p->gptr, p->gidx, p->gval, xp, x0, F0, p->f0first == 0 ? F0 : nullptr,
                   base, alpha, out);
-  launch_globalrows(st, p->blk, p->N, p->ng, p->n0, p->nl, p->lptr, p->lcol, p->lval, xp, x0, F0,
-                    base ? base + p->nl : nullptr, alpha, out + p->nl);
 }
 
 // A row pass (AHLP_ST_AROWS) with its algorithmic bytes: the A tiles, the C
@@ -720,7 +724,7 @@ ahlp_status_t solve_once(ahlp_problem_t p, const double* rx, const double* ry, c
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->ws.dyp, p->ws.u, p->cptr, p->crow, p->cval, 2,
               p->ws.rhx, nullptr, p->Dp, gout, dx, dzv);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
-  launch_solve_tail(st, p->N, p->n0, p->nle, p->ws.part, p->F0, p->ws.u, p->x0off, p->mblk, gout, dx, dzv,
+  launch_solve_tail(st, p->N, p->n0, p->nle, p->f0first, p->ws.part, p->F0, p->ws.u, p->x0off, p->mblk, gout, dx, dzv,
                     dy);
   p->timer.end();
   HIPCHK(hipGetLastError());
@@ -735,7 +739,7 @@ void apply_At(ahlp_problem_t p, const double* y, int mode, const double* cvec,
               p->cval, mode, cvec, zvec, p->Dp, mode == 0 ? out : nullptr,
               mode == 0 ? nullptr : out);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
-  launch_x0_sum(st, p->N, p->n0, p->nle, p->ws.part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
+  launch_x0_sum(st, p->N, p->n0, p->nle, p->f0first, p->ws.part, p->F0, y + p->mblk, mode, cvec, zvec, p->x0off,
                 mode == 0 ? out : nullptr, mode == 0 ? nullptr : out);
 }
 
@@ -746,7 +750,7 @@ void apply_At_both(ahlp_problem_t p, const double* y, const double* cvec, const 
   launch_cols(st, p->blk, p->coltiles, p->nct, p->A, p->ws.dyp, y + p->mblk, p->cptr, p->crow,
               p->cval, 1, cvec, zvec, p->Dp, gout, rd);
   launch_ccols(st, p->blk, p->c0tiles, p->nc0, p->n0, p->C, p->ws.dyp, p->ws.part);
-  launch_x0_sum(st, p->N, p->n0, p->nle, p->ws.part, p->F0, y + p->mblk, 1, cvec, zvec, p->x0off,
+  launch_x0_sum(st, p->N, p->n0, p->nle, p->f0first, p->ws.part, p->F0, y + p->mblk, 1, cvec, zvec, p->x0off,
                 gout, rd);
 }
 
@@ -1104,6 +1108,26 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
       wgoff += (long long)ng * b.n;
     }
   }
+  // the global rows over the padded x, for the row passes
+  std::vector<int> hgptr((size_t)ng + 1, 0), hgidx;
+  std::vector<double> hgval;
+  if (ng > 0) {
+    if (dpo > (long long)INT32_MAX) return fail(AHLP_EINVAL, "padded x too long for the global rows' index");
+    for (int k = 0; k < ng; ++k) {
+      long long wgoff = 0;
+      for (int i = 0; i < N; ++i) {
+        const BlockInfo& b = p->hb[i];
+        const double* row = d->Wg + wgoff + (long long)k * b.n;
+        for (int c = 0; c < b.n; ++c)
+          if (row[c] != 0.0) {
+            hgidx.push_back((int)(b.dpoff + c));
+            hgval.push_back(row[c]);
+          }
+        wgoff += (long long)ng * b.n;
+      }
+      hgptr[k + 1] = (int)hgidx.size();
+    }
+  }
   std::vector<int> hcptr((size_t)csc_off, 0), hcrow;
   std::vector<double> hcval;
   for (int i = 0; i < N; ++i) {
@@ -1119,6 +1143,13 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   }
   // the x_0 coupling of the dual rows after the blocks: F0, then Wg0
   std::vector<double> hF0;
+  p->f0first = p->nl;
+  if (d->F0 && n0 > 0)
+    for (long long r = 0; r < p->nl * n0; ++r)
+      if (d->F0[r] != 0.0) {
+        p->f0first = 0;
+        break;
+      }
   if (n0 > 0 && ((d->F0 && p->nl > 0) || (ng > 0 && d->Wg0))) {
     hF0.assign((size_t)(p->nle * n0), 0.0);
     if (d->F0)
@@ -1242,6 +1273,9 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->lcol, std::max<long long>(hcol.size(), 1)));
   CHK(M.alloc(&p->lval, std::max<long long>(hval.size(), 1)));
   CHK(M.alloc(&p->cptr, csc_off));
+  CHK(M.alloc(&p->gptr, ng + 1));
+  CHK(M.alloc(&p->gidx, std::max<long long>(hgidx.size(), 1)));
+  CHK(M.alloc(&p->gval, std::max<long long>(hgval.size(), 1)));
   CHK(M.alloc(&p->crow, std::max<long long>(hcrow.size(), 1)));
   CHK(M.alloc(&p->cval, std::max<long long>(hcval.size(), 1)));
   if (!hF0.empty()) CHK(M.alloc(&p->F0, p->nle * n0));
@@ -1349,6 +1383,11 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     HIPCHK(hipMemcpyAsync(p->lval, hval.data(), sizeof(double) * hval.size(), hipMemcpyHostToDevice, st));
   }
   HIPCHK(hipMemcpyAsync(p->cptr, hcptr.data(), sizeof(int) * csc_off, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->gptr, hgptr.data(), sizeof(int) * (ng + 1), hipMemcpyHostToDevice, st));
+  if (!hgidx.empty()) {
+    HIPCHK(hipMemcpyAsync(p->gidx, hgidx.data(), sizeof(int) * hgidx.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->gval, hgval.data(), sizeof(double) * hgval.size(), hipMemcpyHostToDevice, st));
+  }
   if (!hcrow.empty()) {
     HIPCHK(hipMemcpyAsync(p->crow, hcrow.data(), sizeof(int) * hcrow.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(p->cval, hcval.data(), sizeof(double) * hcval.size(), hipMemcpyHostToDevice, st));

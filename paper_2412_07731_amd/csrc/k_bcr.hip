@@ -33,7 +33,6 @@
 #include "tile_chol.h"
 #include "tile_ops.h"
 #include "bcr_border.h"
-#include "small_dense.h"
 
 namespace ahlp {
 
@@ -328,9 +327,8 @@ __global__ __launch_bounds__(256) void k_bcr_s00_sum(BcrArgs c, int nparts) {
 // Border: B = -(S00 - sum of Z_j'Z_j) in t0 x t0 tiles (all four waves), then
 // one wave: blocked Cholesky with tile inverses and the block inverse of the
 // factor.  With global rows in the border (c.ng > 0) B is quasi-definite
-// (negative definite on the global rows, positive on x_0) and the whole
-// workgroup factors it entry by entry as B = Lb T Lb', T = diag(-I, I), then
-// inverts Lb.
+// (negative definite on the global rows, positive on x_0) and the
+// factorization is the signed one, B = Lb T Lb' with T = diag(-I, I).
 __global__ __launch_bounds__(256) void k_bcr_border(BcrArgs c, int nparts) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n0 = c.n0, t0 = c.t0, lane = threadIdx.x & 63;
@@ -354,45 +352,20 @@ __global__ __launch_bounds__(256) void k_bcr_border(BcrArgs c, int nparts) {
     B[idx] = v;
   }
   __syncthreads();
-  if (c.ng > 0) {
-    const int nbp = 16 * t0;
-    double* M = X;    // column-major nbp x nbp copy, then Lb
-    double* Mi = B;   // Lb^-1, column-major
-    for (int idx = threadIdx.x; idx < nbp * nbp; idx += blockDim.x) {
-      const int i = idx % nbp, j = idx / nbp;
-      M[idx] = B[((j >> 4) * t0 + (i >> 4)) * 256 + (j & 15) * 16 + (i & 15)];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double md = 0.0;
-      for (int i = 0; i < n0; ++i) md = fmax(md, fabs(M[i + i * nbp]));
-      s_max = md;
-    }
-    __syncthreads();
-    const int cnt = sm_chol_signed(M, nbp, c.ng, PIVOT_REL * s_max);
-    sm_trinv(M, Mi, nbp);
-    for (int idx = threadIdx.x; idx < 256 * t0 * t0; idx += blockDim.x) {
-      const int tile = idx / 256, e = idx % 256;
-      const int r = tile % t0, cc = tile / t0;
-      const int i = 16 * r + (e & 15), j = 16 * cc + (e >> 4);
-      c.FLb[idx] = M[i + j * nbp];
-      c.FLbi[idx] = Mi[i + j * nbp];
-    }
-    if (threadIdx.x == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
-    return;
-  }
   if (threadIdx.x >= 64) return;   // one wave from here on (wave-scope ordering only)
   if (lane == 0) {
     double md = 0.0;
     for (int i = 0; i < n0; ++i) {
       const int r = i >> 4;
-      md = fmax(md, B[(r * t0 + r) * 256 + (i & 15) * 17]);
+      md = fmax(md, fabs(B[(r * t0 + r) * 256 + (i & 15) * 17]));
     }
     s_max = md;
   }
   wave_order();
-  const double thr = PIVOT_REL * fmax(s_max, 0.0);
-  const int cnt = wave_block_chol(B, t0, X, Ld, tmp, xbuf, thr);
+  const double thr = PIVOT_REL * s_max;
+  // the global rows' part of B is negative definite: signed factorization there
+  const unsigned long long neg = c.ng >= 64 ? ~0ull : ((1ull << c.ng) - 1ull);
+  const int cnt = wave_block_chol(B, t0, X, Ld, tmp, xbuf, thr, neg);
   for (int idx = lane; idx < 256 * t0 * t0; idx += 64) {
     const int tile = idx / 256;
     const int r = tile % t0, cc = tile / t0;

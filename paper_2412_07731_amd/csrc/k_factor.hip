@@ -1222,13 +1222,13 @@ template void launch_block_factor_col<float>(hipStream_t, const BlockInfo*, cons
 
 void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int nb, int n0, long long nl,
                      const int* lsz, const long long* tdoff, const long long* tooff,
-                     const long long* eoff, const double* PQ, const double* F0,
-                     const long long* loff, double delta, const double* D0, double* Td,
-                     double* To, double* E, double* S00, double* thrT) {
+                     const long long* eoff, const double* PQ, const double* F0L,
+                     const double* F0, const long long* loff, double delta, const double* D0,
+                     double* Td, double* To, double* E, double* S00, double* thrT) {
   const int P = N - 1;
   if (P > 0)
     hipLaunchKernelGGL(k_assemble_pairs, dim3(P), dim3(256), 0, st, blk, P, nb, n0, lsz, tdoff,
-                       tooff, eoff, PQ, F0, loff, delta, Td, To, E, thrT);
+                       tooff, eoff, PQ, F0L, loff, delta, Td, To, E, thrT);
   if (nb > 0)
     hipLaunchKernelGGL(k_assemble_s00, dim3(nb * nb), dim3(256), 0, st, blk, N, nb, n0, nl, PQ,
                        D0, F0, delta, S00);

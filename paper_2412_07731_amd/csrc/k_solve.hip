@@ -132,61 +132,53 @@ __global__ __launch_bounds__(256) void k_rows_nv(const BlockInfo* __restrict__ b
   }
 }
 
-// Link rows: out[j-th pair, row a] = base + alpha * (FR_j xp_j + FL_j xp_{j+1} [+ F0 x0]).
-__global__ void k_linkrows(const BlockInfo* __restrict__ blk, int P, int n0,
-                           const int* __restrict__ lsz, const long long* __restrict__ loff,
-                           const int* __restrict__ lptr, const int* __restrict__ lcol,
-                           const double* __restrict__ lval, const double* __restrict__ xp,
-                           const double* __restrict__ x0, const double* __restrict__ F0,
-                           const double* __restrict__ base, double alpha,
-                           double* __restrict__ out) {
-  for (int j = blockIdx.x; j < P; j += gridDim.x) {
+// The dual rows after the blocks, out = base + alpha * (F xp [+ F0 x0]),
+// 256 threads per workgroup: the link rows, out[pair j, row a] = base + alpha
+// (FR_j xp_j + FL_j xp_{j+1} [+ F0 x0]), a pair per workgroup (its first wave)
+// in the first gridP workgroups; then global row k by workgroup gridP + k,
+// out[nl + k] = base +
+// alpha (sum_i Wg_i xp_i [+ Wg0 x0]), its entries kept as one compressed row
+// over the padded x (gptr, gidx, gval): each thread a fixed strided share,
+// then a fixed reduction tree.  F0 (when given) is the extended (nl + ng) x n0
+// coupling; F0L the same pointer, or null when the link rows' part of it is
+// zero.
+__device__ double block_reduce(int op, double v);
+__global__ __launch_bounds__(256) void k_linkrows(
+    const BlockInfo* __restrict__ blk, int P, int gridP, int n0, const int* __restrict__ lsz,
+    const long long* __restrict__ loff, long long nl, const int* __restrict__ lptr,
+    const int* __restrict__ lcol, const double* __restrict__ lval, const int* __restrict__ gptr,
+    const int* __restrict__ gidx, const double* __restrict__ gval, const double* __restrict__ xp,
+    const double* __restrict__ x0, const double* __restrict__ F0, const double* __restrict__ F0L,
+    const double* __restrict__ base, double alpha, double* __restrict__ out) {
+  if ((int)blockIdx.x >= gridP) {
+    const int k = blockIdx.x - gridP;
+    double v = 0.0;
+    const int e1 = gptr[k + 1];
+    for (int e = gptr[k] + threadIdx.x; e < e1; e += blockDim.x) v += gval[e] * xp[gidx[e]];
+    if (F0 && x0)
+      for (int c = threadIdx.x; c < n0; c += blockDim.x) v += F0[(nl + k) * n0 + c] * x0[c];
+    const double t = block_reduce(0, v);
+    if (threadIdx.x == 0) out[nl + k] = (base ? base[nl + k] : 0.0) + alpha * t;
+    return;
+  }
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  for (int j = blockIdx.x; j < P; j += gridP) {
     const BlockInfo bl = blk[j], br = blk[j + 1];
     const int l = lsz[j];
-    for (int a = threadIdx.x; a < l; a += blockDim.x) {
+    for (int a = lane; a < l; a += 64) {
       double s = 0.0;
       const int qr = TS * bl.ktL + a;   // right section of block j
       for (int e = lptr[bl.csr_off + qr]; e < lptr[bl.csr_off + qr + 1]; ++e)
         s += lval[e] * xp[bl.dpoff + lcol[e]];
       for (int e = lptr[br.csr_off + a]; e < lptr[br.csr_off + a + 1]; ++e)
         s += lval[e] * xp[br.dpoff + lcol[e]];
-      if (F0 && x0)
-        for (int c = 0; c < n0; ++c) s += F0[(loff[j] + a) * n0 + c] * x0[c];
+      if (F0L && x0)
+        for (int c = 0; c < n0; ++c) s += F0L[(loff[j] + a) * n0 + c] * x0[c];
       const long long o = loff[j] + a;
       out[o] = (base ? base[o] : 0.0) + alpha * s;
     }
   }
-}
-
-__device__ double block_reduce(int op, double v);
-
-// Global rows: out[k] = base[k] + alpha * (sum_i Wg_i xp_i [+ Wg0 x0]), one
-// workgroup per row.  Block i's part of row k is its border section's sparse
-// row k (the same compressed rows as the link rows); each thread sums a fixed
-// strided subset of the blocks, then a fixed reduction tree.  Wg0 is row
-// nl + k of the extended F0.
-__global__ __launch_bounds__(256) void k_globalrows(const BlockInfo* __restrict__ blk, int N,
-                                                    int n0, long long nl,
-                                                    const int* __restrict__ lptr,
-                                                    const int* __restrict__ lcol,
-                                                    const double* __restrict__ lval,
-                                                    const double* __restrict__ xp,
-                                                    const double* __restrict__ x0,
-                                                    const double* __restrict__ F0,
-                                                    const double* __restrict__ base, double alpha,
-                                                    double* __restrict__ out) {
-  const int k = blockIdx.x;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const BlockInfo& b = blk[i];
-    const int q = TS * (b.ktL + b.ktR) + k;
-    for (int e = lptr[b.csr_off + q]; e < lptr[b.csr_off + q + 1]; ++e)
-      v += lval[e] * xp[b.dpoff + lcol[e]];
-  }
-  if (F0 && x0)
-    for (int c = threadIdx.x; c < n0; c += blockDim.x) v += F0[(nl + k) * n0 + c] * x0[c];
-  const double t = block_reduce(0, v);
-  if (threadIdx.x == 0) out[k] = (base ? base[k] : 0.0) + alpha * t;
 }
 
 // ------------------------------------------------------------ block columns
@@ -286,7 +278,7 @@ __global__ __launch_bounds__(256) void k_ccols(const BlockInfo* __restrict__ blk
 // g0[c] = sum_i part[i][c] + (F0' yL)[c] with one workgroup per column: each
 // thread sums a fixed strided subset, then a fixed tree; then by mode as k_cols.
 __device__ double block_reduce(int op, double v);
-__global__ __launch_bounds__(256) void k_x0_sum(int N, int n0, long long nl,
+__global__ __launch_bounds__(256) void k_x0_sum(int N, int n0, long long nl, long long f0first,
                                                 const double* __restrict__ part,
                                                 const double* __restrict__ F0,
                                                 const double* __restrict__ yL, int mode,
@@ -298,7 +290,7 @@ __global__ __launch_bounds__(256) void k_x0_sum(int N, int n0, long long nl,
   double v = 0.0;
   for (int i = threadIdx.x; i < N; i += blockDim.x) v += part[(long long)i * n0 + c];
   if (F0)
-    for (long long r = threadIdx.x; r < nl; r += blockDim.x) v += F0[r * n0 + c] * yL[r];
+    for (long long r = f0first + threadIdx.x; r < nl; r += blockDim.x) v += F0[r * n0 + c] * yL[r];
   const double g = block_reduce(0, v);
   if (threadIdx.x == 0) {
     const long long o = x0off + c;
@@ -527,7 +519,7 @@ __global__ __launch_bounds__(256) void k_schur_rhs(const BlockInfo* __restrict__
 // per-block partials C_i' dy_i + F0' dy_L (fixed order), dx_0 = u_0 and
 // dz_0 = (rz_0 - z_0 dx_0) / x_0 (blocks below n0, one entry each); the
 // remaining blocks copy the link part u_L of the Schur solution into dy.
-__global__ __launch_bounds__(256) void k_solve_tail(int N, int n0, long long nl,
+__global__ __launch_bounds__(256) void k_solve_tail(int N, int n0, long long nl, long long f0first,
                                                     const double* __restrict__ part,
                                                     const double* __restrict__ F0,
                                                     const double* __restrict__ u, long long x0off,
@@ -539,7 +531,7 @@ __global__ __launch_bounds__(256) void k_solve_tail(int N, int n0, long long nl,
     double v = 0.0;
     for (int i = threadIdx.x; i < N; i += blockDim.x) v += part[(long long)i * n0 + c];
     if (F0)
-      for (long long r = threadIdx.x; r < nl; r += blockDim.x) v += F0[r * n0 + c] * u[r];
+      for (long long r = f0first + threadIdx.x; r < nl; r += blockDim.x) v += F0[r * n0 + c] * u[r];
     const double g = block_reduce(0, v);
     if (threadIdx.x == 0) {
       const long long o = x0off + c;
@@ -956,14 +948,15 @@ void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int
   ra.with_C[0] = with_C; ra.padded[0] = padded_out; ra.chain[0] = 0;
   launch_rows_multi(st, blk, rowtiles, nrt, A, C, d0off, ra);
 }
-void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int n0, const int* lsz,
-                     const long long* loff, const int* lptr, const int* lcol,
-                     const double* lval, const double* xp, const double* x0, const double* F0,
-                     const double* base, double alpha, double* out) {
-  if (P <= 0) return;
-  const int grid = P < 1024 ? P : 1024;
-  hipLaunchKernelGGL(k_linkrows, dim3(grid), dim3(64), 0, st, blk, P, n0, lsz, loff, lptr, lcol,
-                     lval, xp, x0, F0, base, alpha, out);
+void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int ng, int n0,
+                     const int* lsz, const long long* loff, long long nl, const int* lptr,
+                     const int* lcol, const double* lval, const int* gptr, const int* gidx,
+                     const double* gval, const double* xp, const double* x0, const double* F0,
+                     const double* F0L, const double* base, double alpha, double* out) {
+  const int gridP = P > 0 ? (P < 1024 ? P : 1024) : 0;
+  if (gridP + ng <= 0) return;
+  hipLaunchKernelGGL(k_linkrows, dim3(gridP + ng), dim3(256), 0, st, blk, P, gridP, n0, lsz, loff,
+                     nl, lptr, lcol, lval, gptr, gidx, gval, xp, x0, F0, F0L, base, alpha, out);
 }
 void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int nct,
                  const double* A, const double* yp, const double* yL, const int* cptr,
@@ -979,12 +972,13 @@ void launch_ccols(hipStream_t st, const BlockInfo* blk, const int2* ctiles, int 
     hipLaunchKernelGGL(k_ccols, dim3((nctile + 3) / 4), dim3(256), 0, st, blk, ctiles, nctile, n0,
                        C, yp, part);
 }
-void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, const double* part,
-                   const double* F0, const double* yL, int mode, const double* cvec,
-                   const double* zvec, long long x0off, double* gout, double* out) {
+void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, long long f0first,
+                   const double* part, const double* F0, const double* yL, int mode,
+                   const double* cvec, const double* zvec, long long x0off, double* gout,
+                   double* out) {
   if (n0 > 0)
-    hipLaunchKernelGGL(k_x0_sum, dim3(n0), dim3(256), 0, st, N, n0, nl, part, F0, yL, mode, cvec,
-                       zvec, x0off, gout, out);
+    hipLaunchKernelGGL(k_x0_sum, dim3(n0), dim3(256), 0, st, N, n0, nl, f0first, part, F0, yL, mode,
+                       cvec, zvec, x0off, gout, out);
 }
 template <typename T>
 void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, const T* LB,
@@ -1019,23 +1013,15 @@ void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int nb, const
     hipLaunchKernelGGL(k_schur_rhs, dim3(npb + nb), dim3(256), 0, st, blk, N, nb, lsz, loff, nl,
                        npb, qn, rhx0, s);
 }
-void launch_globalrows(hipStream_t st, const BlockInfo* blk, int N, int ng, int n0, long long nl,
-                       const int* lptr, const int* lcol, const double* lval, const double* xp,
-                       const double* x0, const double* F0, const double* base, double alpha,
-                       double* out) {
-  if (ng > 0)
-    hipLaunchKernelGGL(k_globalrows, dim3(ng), dim3(256), 0, st, blk, N, n0, nl, lptr, lcol, lval,
-                       xp, x0, F0, base, alpha, out);
-}
-void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, const double* part,
-                       const double* F0, const double* u, long long x0off, long long mblk,
-                       double* gout, double* dx, const DzArgs& dzv, double* dy) {
+void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, long long f0first,
+                       const double* part, const double* F0, const double* u, long long x0off,
+                       long long mblk, double* gout, double* dx, const DzArgs& dzv, double* dy) {
   long long nb = (nl + 255) / 256;
   if (nb > 64) nb = 64;
   const int grid = n0 + (int)nb;
   if (grid > 0)
-    hipLaunchKernelGGL(k_solve_tail, dim3(grid), dim3(256), 0, st, N, n0, nl, part, F0, u, x0off,
-                       mblk, gout, dx, dzv, dy);
+    hipLaunchKernelGGL(k_solve_tail, dim3(grid), dim3(256), 0, st, N, n0, nl, f0first, part, F0, u,
+                       x0off, mblk, gout, dx, dzv, dy);
 }
 void launch_check_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
                        long long d0off, const double* rx, const double* rz, const double* g,

@@ -41,12 +41,13 @@ void launch_factor_fused(hipStream_t st, const BlockInfo* blk, const int* order,
                          DevInfo* info, int num_cu);
 bool factor_fused_fits(int rt, int mt);
 // T, E (l_j x nb) and S00 (nb x nb) of S; F0: the extended (nl + ng) x n0
-// x_0 coupling (link rows, then the global rows' Wg0), or null
+// x_0 coupling (link rows, then the global rows' Wg0), or null; F0L: the same
+// pointer, or null when its link rows are zero
 void launch_assemble(hipStream_t st, const BlockInfo* blk, int N, int nb, int n0, long long nl,
                      const int* lsz, const long long* tdoff, const long long* tooff,
-                     const long long* eoff, const double* PQ, const double* F0,
-                     const long long* loff, double delta, const double* D0, double* Td,
-                     double* To, double* E, double* S00, double* thrT);
+                     const long long* eoff, const double* PQ, const double* F0L,
+                     const double* F0, const long long* loff, double delta, const double* D0,
+                     double* Td, double* To, double* E, double* S00, double* thrT);
 void launch_convert_f32(hipStream_t st, long long n, const double* src, float* dst);
 
 // Schur complement (k_chain.hip).  Its border (called n0 in the Schur
@@ -185,10 +186,14 @@ void launch_rows_multi(hipStream_t st, const BlockInfo* blk, const int2* rowtile
 void launch_rows(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
                  const double* A, const double* C, const double* xp, long long d0off,
                  const double* base, double alpha, int with_C, int padded_out, double* out);
-void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int n0, const int* lsz,
-                     const long long* loff, const int* lptr, const int* lcol,
-                     const double* lval, const double* xp, const double* x0, const double* F0,
-                     const double* base, double alpha, double* out);
+// the dual rows after the blocks (link rows, then global rows):
+// out = base + alpha (F xp [+ F0 x0]); F0 the extended (nl + ng) x n0 coupling,
+// F0L the same or null when its link rows are zero
+void launch_linkrows(hipStream_t st, const BlockInfo* blk, int P, int ng, int n0,
+                     const int* lsz, const long long* loff, long long nl, const int* lptr,
+                     const int* lcol, const double* lval, const int* gptr, const int* gidx,
+                     const double* gval, const double* xp, const double* x0, const double* F0,
+                     const double* F0L, const double* base, double alpha, double* out);
 // Optional fused output of the column pass (mode 2): dz = (rz - zs dx) / xs
 struct DzArgs {
   const double* rz; const double* zs; const double* xs; double* dz;
@@ -198,16 +203,13 @@ void launch_cols(hipStream_t st, const BlockInfo* blk, const int2* coltiles, int
                  const int* crow, const double* cval, int mode, const double* cvec,
                  const double* zvec, const double* Dp, double* gout, double* out,
                  const DzArgs& dzv = DzArgs{});
-// global rows: out = base + alpha (Wg xp + Wg0 x0); F0 the extended x_0 coupling
-void launch_globalrows(hipStream_t st, const BlockInfo* blk, int N, int ng, int n0, long long nl,
-                       const int* lptr, const int* lcol, const double* lval, const double* xp,
-                       const double* x0, const double* F0, const double* base, double alpha,
-                       double* out);
 void launch_ccols(hipStream_t st, const BlockInfo* blk, const int2* ctiles, int nctile, int n0,
                   const double* C, const double* yp, double* part);
-void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, const double* part,
-                   const double* F0, const double* yL, int mode, const double* cvec,
-                   const double* zvec, long long x0off, double* gout, double* out);
+// F0 rows below f0first are zero (skipped)
+void launch_x0_sum(hipStream_t st, int N, int n0, long long nl, long long f0first,
+                   const double* part, const double* F0, const double* yL, int mode,
+                   const double* cvec, const double* zvec, long long x0off, double* gout,
+                   double* out);
 template <typename T>
 void launch_block_fwd(hipStream_t st, const BlockInfo* blk, int N, int max_rt, const T* LB,
                       const T* LINV, const double* tin, double* tv, double* qn);
@@ -218,9 +220,9 @@ void launch_block_bwd(hipStream_t st, const BlockInfo* blk, int N, int nb, long 
 void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int nb, const int* lsz,
                       const long long* loff, long long nl, const double* qn, const double* rhx0,
                       double* s);
-void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, const double* part,
-                       const double* F0, const double* u, long long x0off, long long mblk,
-                       double* gout, double* dx, const DzArgs& dzv, double* dy);
+void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, long long f0first,
+                       const double* part, const double* F0, const double* u, long long x0off,
+                       long long mblk, double* gout, double* dx, const DzArgs& dzv, double* dy);
 void launch_check_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
                        long long d0off, const double* rx, const double* rz, const double* g,
                        const double* dx, const double* dz, const double* xs, const double* zs,

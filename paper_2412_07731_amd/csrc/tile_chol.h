@@ -106,14 +106,24 @@ __device__ __forceinline__ double recip(double p) {
 }
 __device__ __forceinline__ float recip(float p) { return 1.0f / p; }
 
-// Elimination step J on the lane's row i, column group g.
-template <typename T, int J>
+// Elimination step J on the lane's row i, column group g.  SG: signed
+// (quasi-definite) form, where column J's pivot must have the sign of its bit
+// in neg (set: negative); the rule applies to the pivot times that sign.
+template <typename T, int J, bool SG>
 __device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double thr, int& cnt,
-                                          T& mypiv) {
+                                          T& mypiv, unsigned neg) {
   T p = lane_bcast<T>(a[J & 3], J + 16 * (J >> 2));
-  if (!((double)p > thr)) {
-    p = (T)PIVOT_BIG;
-    ++cnt;
+  if constexpr (SG) {
+    const T tj = ((neg >> J) & 1u) ? T(-1) : T(1);
+    if (!((double)(tj * p) > thr)) {
+      p = tj * (T)PIVOT_BIG;
+      ++cnt;
+    }
+  } else {
+    if (!((double)p > thr)) {
+      p = (T)PIVOT_BIG;
+      ++cnt;
+    }
   }
   const T rp = recip(p);
   if (i == J) mypiv = p;
@@ -132,12 +142,12 @@ __device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double th
     e[r] -= m * rje[r];
   }
 }
-template <typename T, int J>
+template <typename T, int J, bool SG>
 __device__ __forceinline__ void chol_steps(T (&a)[4], T (&e)[4], int i, double thr, int& cnt,
-                                           T& mypiv) {
+                                           T& mypiv, unsigned neg) {
   if constexpr (J < 16) {
-    chol_step<T, J>(a, e, i, thr, cnt, mypiv);
-    chol_steps<T, J + 1>(a, e, i, thr, cnt, mypiv);
+    chol_step<T, J, SG>(a, e, i, thr, cnt, mypiv, neg);
+    chol_steps<T, J + 1, SG>(a, e, i, thr, cnt, mypiv, neg);
   }
 }
 
@@ -145,9 +155,12 @@ __device__ __forceinline__ void chol_steps(T (&a)[4], T (&e)[4], int i, double t
 // (may alias P) receives the lower factor (upper part zero), Li its inverse;
 // both column-major with leading dimension LD.  xbuf is no longer used (kept
 // in the signature for the callers' LDS layouts).  Returns the number of
-// replaced pivots (all lanes).
-template <typename T, int LD = TS>
-__device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double thr, T* xbuf) {
+// replaced pivots (all lanes).  SG: the signed factorization of a
+// quasi-definite tile, P = L S L' with S = diag(-1 where neg has the column's
+// bit, +1 elsewhere); with D the elimination's pivots, L = L1 |D|^(1/2).
+template <typename T, int LD = TS, bool SG = false>
+__device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double thr, T* xbuf,
+                                              unsigned neg = 0) {
   (void)xbuf;
   const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
   T a[4], e[4];
@@ -158,14 +171,21 @@ __device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double th
   }
   int cnt = 0;
   T mypiv = T(1);
-  chol_steps<T, 0>(a, e, i, thr, cnt, mypiv);
+  chol_steps<T, 0, SG>(a, e, i, thr, cnt, mypiv, neg);
+  T si = T(1);
+  if constexpr (SG) {
+    si = ((neg >> i) & 1u) ? T(-1) : T(1);
+    mypiv *= si;
+  }
   const T s = T(1) / (T)sqrt((double)mypiv);
+  const T sl = SG ? si * s : s;
   wave_order();   // every lane has read P before L (which may alias it) is written
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int c = 4 * g + r;
-    // L' row i = U row i * s, i.e. L[c][i] (zero above the diagonal); Li row i = E row i * s
-    L[i * LD + c] = (c >= i) ? a[r] * s : T(0);
+    // L' row i = U row i * s (times the row's sign if SG), i.e. L[c][i] (zero
+    // above the diagonal); Li row i = E row i * s
+    L[i * LD + c] = (c >= i) ? a[r] * sl : T(0);
     Li[c * LD + i] = e[r] * s;
   }
   wave_order();

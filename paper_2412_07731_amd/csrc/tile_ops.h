@@ -68,6 +68,18 @@ __device__ __forceinline__ d4 mma_xyt(d4 acc, const double* X, const double* Y, 
   for (int s = 0; s < 4; ++s) acc = mfma(alpha * X[64 * s + lane], Y[64 * s + lane], acc);
   return acc;
 }
+// acc += alpha X S Y' with S = diag(-1 where neg has the bit of the inner
+// index, +1 elsewhere)
+__device__ __forceinline__ d4 mma_xsyt(d4 acc, const double* X, const double* Y, double alpha,
+                                       unsigned neg) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double f = ((neg >> (4 * s + (lane >> 4))) & 1u) ? -alpha : alpha;
+    acc = mfma(f * X[64 * s + lane], Y[64 * s + lane], acc);
+  }
+  return acc;
+}
 // acc += alpha X Y
 __device__ __forceinline__ d4 mma_xy(d4 acc, const double* X, const double* Y, double alpha) {
   const int lane = threadIdx.x & 63;
@@ -128,16 +140,22 @@ __device__ __forceinline__ double vec_get_exact(const double* src, int len) {
 // those tiles hold the factor L, Ld the inverses of its t diagonal tiles and X
 // (t x t tiles, zero above the diagonal) the block inverse L^-1.  tmp: one
 // tile and xbuf 48 values of LDS scratch.  A pivot <= thr is replaced (the
-// pivot rule); returns the number replaced (all lanes).
+// pivot rule); returns the number replaced (all lanes).  With neg != 0 (bit j:
+// row j's sign is negative) B is quasi-definite and the factorization signed,
+// B = L S L' with S = diag(-1 on neg's bits, +1 elsewhere): tile column p is
+// L_rp = B_rp L_pp^-T S_p, and the trailing update subtracts L_rp S_p L_cp'.
 __device__ inline int wave_block_chol(double* B, int t, double* X, double* Ld, double* tmp,
-                                      double* xbuf, double thr) {
+                                      double* xbuf, double thr, unsigned long long neg = 0) {
   const int lane = threadIdx.x & 63;
   int cnt = 0;
   for (int p = 0; p < t; ++p) {
     double* Bpp = B + (p * t + p) * 256;
-    cnt += wave_chol_tile<double>(Bpp, Bpp, Ld + p * 256, thr, xbuf);
+    const unsigned np = (unsigned)((neg >> (16 * p)) & 0xFFFFull);
+    if (neg) cnt += wave_chol_tile<double, TS, true>(Bpp, Bpp, Ld + p * 256, thr, xbuf, np);
+    else cnt += wave_chol_tile<double>(Bpp, Bpp, Ld + p * 256, thr, xbuf);
     for (int r = p + 1; r < t; ++r) {
       d4 acc = mma_xyt(acc_zero(), B + (p * t + r) * 256, Ld + p * 256, 1.0);
+      if (neg && ((np >> (lane & 15)) & 1u)) acc = -acc;   // times S_p (column lane % 16)
       wave_order();
       acc_store(B + (p * t + r) * 256, acc);
     }
@@ -145,7 +163,8 @@ __device__ inline int wave_block_chol(double* B, int t, double* X, double* Ld, d
     for (int r = p + 1; r < t; ++r)
       for (int cc = p + 1; cc <= r; ++cc) {
         d4 acc = acc_load(B + (cc * t + r) * 256);
-        acc = mma_xyt(acc, B + (p * t + r) * 256, B + (p * t + cc) * 256, -1.0);
+        if (neg) acc = mma_xsyt(acc, B + (p * t + r) * 256, B + (p * t + cc) * 256, -1.0, np);
+        else acc = mma_xyt(acc, B + (p * t + r) * 256, B + (p * t + cc) * 256, -1.0);
         wave_order();
         acc_store(B + (cc * t + r) * 256, acc);
       }
@@ -172,5 +191,6 @@ __device__ inline int wave_block_chol(double* B, int t, double* X, double* Ld, d
   }
   return cnt;
 }
+
 
 }  // namespace ahlp

@@ -21,15 +21,25 @@ def golden(config, seed, gondzio=0, dense=False, x0_border=False):
     return None
 
 
-def eta_bound(eta_orc):
-    return max(ETA, 10.0 * eta_orc)
+# Refinement corrections per solve (the interior-point default of both sides).
+MAX_REFINE = 5
+
+
+def eta_bound(eta_orc, budget_limited=False):
+    """Bound on the GPU's backward error for a solve where the oracle reached
+    eta_orc.  Where the oracle used its whole refinement budget and still
+    missed 1e-10 (a slowly contracting refinement late in a run), the final
+    backward error is set by that budget, and the two sides' can differ by
+    more: there the bound is 100 eta_orc."""
+    return max(ETA, (100.0 if budget_limited else 10.0) * eta_orc)
 
 
 def check_trajectory(hist, res, g, label, mu_rtol_early=1e-6, mu_rtol_late=1e-5, late=3):
     """Per-iterate parity of an FP64 interior-point run with the oracle's run
     of the same instance: the same number of iterations; for every predictor
     and corrector (and the two start-point solves) a backward error after
-    refinement of at most max(1e-10, 10 eta_orc); mu at the top of every
+    refinement of at most max(1e-10, 10 eta_orc) (100 eta_orc where the
+    oracle's refinement ran out of corrections, see eta_bound); mu at the top of every
     iteration within mu_rtol_early of the oracle's (mu_rtol_late in the last
     `late` iterations, where the directions are ill-conditioned and rounding
     differences grow).  Where the oracle's run records its refinement counts
@@ -41,17 +51,21 @@ def check_trajectory(hist, res, g, label, mu_rtol_early=1e-6, mu_rtol_late=1e-5,
     difference)."""
     assert len(hist) == g["iterations"], (label, len(hist), g["iterations"])
     misses = 0
+    rt = g.get("refine_trace") if not g.get("correctors") else None
+
+    def capped(idx, eo):     # the oracle's solve idx used its whole budget and missed 1e-10
+        return rt is not None and rt[idx] >= MAX_REFINE and eo > ETA
+
     for j, (eg, eo) in enumerate(zip(res["start_bkerr"], g["start_bkerr"])):
-        assert eg <= eta_bound(eo), (label, "start", j, eg, eo)
+        assert eg <= eta_bound(eo, capped(j, eo)), (label, "start", j, eg, eo)
         misses += eg > ETA
     worst_mu = 0.0
     n = len(hist)
-    rt = g.get("refine_trace") if not g.get("correctors") else None
     branch = None
     for k, h in enumerate(hist):
-        for key in ("bkerr_pred", "bkerr_corr"):
+        for q, key in enumerate(("bkerr_pred", "bkerr_corr")):
             eg, eo = h[key], g[key][k]
-            assert eg <= eta_bound(eo), (label, k, key, eg, eo)
+            assert eg <= eta_bound(eo, capped(2 + 2 * k + q, eo)), (label, k, key, eg, eo)
             misses += eg > ETA
         if branch is None:
             mo = g["mu_trace"][k]
