@@ -11,6 +11,8 @@ Modules
   dense_kkt  brute-force dense solves of the Newton system (Sec. 2.3)
   newton     block elimination: factorization Alg. 2, solve Alg. 3 (Sec. 3.2)
   ipm        Mehrotra predictor-corrector driver (Sec. 2.3; constants are readings)
+  bounded    the same driver with upper bounds inside the iteration (slacks and
+             duals of their own; Q = W/S in the reduced Newton system)
   sensitivity  derivatives of the mu-fixed KKT map w.r.t. (b, c): forward and
              transposed Newton solves, central-path re-solve for differences
 
@@ -28,6 +30,9 @@ Parity status
                                 KKT conditions, scipy's HiGHS on small cases;
                                 the iterate trajectory itself is parity unpinned
                                 (the paper prints no iterates or counts)
+  bounded.solve                 pinned: dense LU of the whole Newton system with
+                                bounds, planted mistakes, known optimum with
+                                active bounds, HiGHS (also on general forms)
   sensitivity.*                 pinned: dense LU of K', the adjoint identity,
                                 central differences of the central-path map,
                                 LP closed forms at a nondegenerate optimum

@@ -63,3 +63,39 @@ def schur_indices(inst):
     ylg = n_tot + m_blocks + np.arange(int(inst.l.sum()) + lp.ng(inst))
     x0 = int(inst.n.sum()) + np.arange(inst.n0)
     return np.concatenate([ylg, x0])
+
+
+def solve_newton_bounded(inst, x, z, s, w, U, rd, rp, ru, rxz, rsw):
+    """Dense LU of the whole Newton system with upper bounds (unknowns dx, dy,
+    dz and ds, dw of the bounded variables U):
+        A'dy + dz - E dw = r_d,  A dx = r_p,  E'dx + ds = r_u,
+        Z dx + X dz = r_xz,  W ds + S dw = r_sw,
+    E the columns of the identity on U.  Returns (dx, dy, dz, ds, dw) with ds,
+    dw zero off U."""
+    A = lp.full_matrix(inst).toarray()
+    m, n = A.shape
+    idx = np.flatnonzero(U)
+    k = idx.size
+    E = np.zeros((n, k))
+    E[idx, np.arange(k)] = 1.0
+    ox, oy, oz, os_, ow = 0, n, n + m, 2 * n + m, 2 * n + m + k
+    N = 2 * n + m + 2 * k
+    K = np.zeros((N, N))
+    # rows in the order of the equations above, columns in that of the unknowns
+    K[ox:ox + n, oy:oy + m] = A.T
+    K[ox:ox + n, oz:oz + n] = np.eye(n)
+    K[ox:ox + n, ow:ow + k] = -E
+    K[oy:oy + m, ox:ox + n] = A
+    K[oz:oz + n, ox:ox + n] = np.diag(z)
+    K[oz:oz + n, oz:oz + n] = np.diag(x)
+    K[os_:os_ + k, ox:ox + n] = E.T
+    K[os_:os_ + k, os_:os_ + k] = np.eye(k)
+    K[ow:ow + k, os_:os_ + k] = np.diag(w[idx])
+    K[ow:ow + k, ow:ow + k] = np.diag(s[idx])
+    rhs = np.concatenate([rd, rp, rxz, ru[idx], rsw[idx]])
+    d = np.linalg.solve(K, rhs)
+    ds = np.zeros(n)
+    dw = np.zeros(n)
+    ds[idx] = d[os_:os_ + k]
+    dw[idx] = d[ow:ow + k]
+    return d[ox:ox + n], d[oy:oy + m], d[oz:oz + n], ds, dw

@@ -43,6 +43,12 @@ global row order; its upper-bound slack row (if both sides are finite) goes to
 block 1 like any other x_0 column's.  Global rows of the standard form: those
 of the general instance in order, then the x_0-only equality rows.
 
+Bounds inside the iteration (``bounds=True``): the finite upper bounds left
+after the shifts are not turned into rows x' + s = u'; the standard form keeps
+them as upper bounds of its columns (Instance.ub, +inf elsewhere), which the
+interior-point method handles with slacks and duals of its own
+(oracle/bounded.py).  Everything else is laid out as above.
+
 Built here row by row from the global rows of the general instance and a
 list of standard columns per original variable.
 """
@@ -220,14 +226,14 @@ def chain(g: GeneralInstance):
     return out, np.array(keep, dtype=np.int64)
 
 
-def reformulate(g: GeneralInstance, dense=False, x0_border=False):
+def reformulate(g: GeneralInstance, dense=False, x0_border=False, bounds=False):
     """Standard-form Instance, and for every original variable its
     (offset, [(block or -1 for x_0, column, sign)]) so x can be recovered
     (global rows are chained first, unless dense; their partial sums are
     dropped from the list)."""
     if not (dense and x0_border) and g.A0 is not None and g.A0.shape[0]:
         h, bas, non, u, V = eliminate_x0(g)
-        inst, var, const = reformulate(h, dense=dense)
+        inst, var, const = reformulate(h, dense=dense, bounds=bounds)
         # x_0 entries: x_N,k as reformulated; x_B,q = u_q - V_q x_N
         xs = int(g.n.sum())
         full = list(var[:xs]) + [None] * g.n0
@@ -244,7 +250,7 @@ def reformulate(g: GeneralInstance, dense=False, x0_border=False):
         return inst, full, const + 0.0
     if not dense and g.ng:
         gc, keep = chain(g)
-        inst, var, const = reformulate(gc)
+        inst, var, const = reformulate(gc, bounds=bounds)
         return inst, [var[k] for k in keep], const
     N, n0 = g.N, g.n0
     xo = np.concatenate([[0], np.cumsum(g.n)]).astype(np.int64)
@@ -337,14 +343,14 @@ def reformulate(g: GeneralInstance, dense=False, x0_border=False):
             else:
                 c = x0c.add('t', np.inf)
                 slack[r] = (-1, c, -1.0, fv[r])
-    # 4. upper-bound slacks
+    # 4. upper-bound slacks (rows), unless the bounds stay bounds
     ubrows = [[] for _ in range(N)]   # (column holder block, column) bounded
-    for i in range(N):
+    for i in (range(N) if not bounds else []):
         bounded = [c for c, u in enumerate(blocks[i].ub) if np.isfinite(u)]
         for c in bounded:
             s = blocks[i].add('s', np.inf)
             ubrows[i].append((i, c, s, blocks[i].ub[c]))
-    for c, u in enumerate(x0c.ub):
+    for c, u in enumerate(x0c.ub if not bounds else []):
         if np.isfinite(u):
             s = blocks[0].add('s', np.inf)
             ubrows[0].append((-1, c, s, u))
@@ -467,6 +473,9 @@ def reformulate(g: GeneralInstance, dense=False, x0_border=False):
     if grows:
         inst.Wg = [np.array(Wg[i]).reshape(len(grows), ncol[i]) for i in range(N)]
         inst.Wg0 = np.array(Wg0).reshape(len(grows), n0s)
+    if bounds:
+        inst.ub = np.concatenate([np.asarray(blocks[i].ub, dtype=float) for i in range(N)]
+                                 + [np.asarray(x0c.ub, dtype=float)])
     return inst, var, const
 
 
@@ -482,9 +491,13 @@ def recover(g: GeneralInstance, inst: Instance, var, x_std):
     return x
 
 
-def solve(g: GeneralInstance, opts=None, dense=False, x0_border=False):
+def solve(g: GeneralInstance, opts=None, dense=False, x0_border=False, bounds=False):
     """Oracle solve of a general instance: (x, objective, ipm result)."""
-    inst, var, _ = reformulate(g, dense=dense, x0_border=x0_border)
-    r = ipm.solve(inst, opts) if opts is not None else ipm.solve(inst)
+    inst, var, _ = reformulate(g, dense=dense, x0_border=x0_border, bounds=bounds)
+    if bounds:
+        from . import bounded
+        r = bounded.solve(inst, opts)
+    else:
+        r = ipm.solve(inst, opts) if opts is not None else ipm.solve(inst)
     x = recover(g, inst, var, r.x)
     return x, float(g.c @ x), r

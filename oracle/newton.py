@@ -161,15 +161,18 @@ def schur_matrix_dense(f: Factor):
     return S
 
 
-def factor(inst, x, z, rho=0.0, delta=0.0):
-    """Alg. 2 for the normal-equation arrowhead form above."""
+def factor(inst, x, z, rho=0.0, delta=0.0, q=None):
+    """Alg. 2 for the normal-equation arrowhead form above.  q (>= 0, one per
+    variable): an extra diagonal of the (x, x) block, -(X^-1 Z + Q + rho I),
+    which is where upper bounds handled inside the iteration enter (q = w / s,
+    0 for a variable without one); D = (Z/X + q + rho)^-1."""
     x = np.asarray(x, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
     if not (np.all(np.isfinite(x)) and np.all(np.isfinite(z))):
         raise FloatingPointError("non-finite x or z")
     if np.any(x <= 0) or np.any(z <= 0):
         raise FloatingPointError("x and z must be positive")
-    D = 1.0 / (z / x + rho)
+    D = 1.0 / (z / x + rho) if q is None else 1.0 / (z / x + q + rho)
     xo, yo, lo = lp.offsets(inst)
     N, n0, ng = inst.N, inst.n0, lp.ng(inst)
     f = Factor(inst=inst, x=x, z=z, D=D, rho=rho, delta=delta, ng=ng)

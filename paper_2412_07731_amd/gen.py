@@ -30,7 +30,9 @@ Draw order (fixed; PCG64(seed)): random sizes (m_i, then l_j), then per block
 A_i (mask, values, zero-row redraws) and C_i (mask, values), then (only with
 ng > 0 global rows) per block and row three distinct columns and their values
 ~U[-1, 1], and Wg_0 (mask, values), then x* positions and values per block and
-for x_0, then z* values, then y*.
+for x_0, then z* values, then y*, then (only with ub_frac > 0) the bounded
+mask, the at-bound mask, the slacks of the inactive bounds and the duals w* of
+the active ones, one draw of each per variable.
 
 Nondegenerate variant (``nondegenerate=True``, needs n0 = 0), for the
 sensitivity workload: block i gets exactly m_i + l_i positive x* entries (l_i
@@ -68,6 +70,10 @@ CONFIGS = {
     # with 3 of them, and a mid-size case with 20 (a border of 20 + 16 rows)
     "tiny_g": dict(N=8, m=32, n=64, l=4, n0=8, density=0.30, ng=3),
     "mid_g": dict(N=40, m=48, n=96, l=16, n0=16, density=0.10, ng=20),
+    # upper bounds on 40% of the variables (0 <= x <= u), some active at the
+    # optimum: tiny, and 64 blocks of 96x192
+    "tiny_b": dict(N=8, m=32, n=64, l=4, n0=8, density=0.30, ub_frac=0.4),
+    "mid_b": dict(N=64, m=96, n=192, l=8, n0=16, density=0.10, ub_frac=0.4),
 }
 
 
@@ -89,6 +95,7 @@ class Instance:
     c: np.ndarray
     Wg: Optional[List[np.ndarray]] = field(default=None)   # global rows: ng x n_i per block
     Wg0: Optional[np.ndarray] = field(default=None)        # their x_0 part, ng x n0
+    ub: Optional[np.ndarray] = field(default=None)         # upper bounds [n_tot] (inf: none)
     xstar: np.ndarray = field(default=None)
     ystar: np.ndarray = field(default=None)
     zstar: np.ndarray = field(default=None)
@@ -238,12 +245,29 @@ def generate(config="tiny", seed=0, **overrides) -> Instance:
     m_tot = int(m.sum() + l.sum()) + ng
     ystar = rng.standard_normal(m_tot)
 
+    # upper bounds (only with ub_frac > 0): a variable is bounded with
+    # probability ub_frac; a bounded positive x*_j is at its bound with
+    # probability 1/2 (u = x*, dual w* ~U[0.5, 2]), else u = x* + ~U[0.5, 2]
+    ub = wstar = None
+    frac = float(cfg.get("ub_frac", 0.0))
+    if frac > 0.0:
+        nt = xstar.size
+        bmask = rng.random(nt) < frac
+        at = (rng.random(nt) < 0.5) & (xstar > 0.0)
+        slack = rng.uniform(0.5, 2.0, size=nt)
+        wv = rng.uniform(0.5, 2.0, size=nt)
+        ub = np.where(bmask, np.where(at, xstar, xstar + slack), np.inf)
+        wstar = np.where(bmask & at, wv, 0.0)
+
     inst = Instance(N=N, n0=n0, m=m, n=n, l=l, A=A, C=C, FR=FR, FL=FL, F0=F0,
-                    b=np.zeros(m_tot), c=np.zeros(xstar.size), Wg=Wg, Wg0=Wg0)
+                    b=np.zeros(m_tot), c=np.zeros(xstar.size), Wg=Wg, Wg0=Wg0, ub=ub)
     inst.xstar, inst.ystar, inst.zstar = xstar, ystar, zstar
     inst.basis = basis   # per block: the indices of the positive x* entries (nondegenerate only)
     inst.b = apply_A(inst, xstar)
     inst.c = apply_At(inst, ystar) + zstar
+    if wstar is not None:
+        inst.c = inst.c - wstar      # dual of the active upper bounds: A'y* + z* - w* = c
+        inst.wstar = wstar
     inst.fstar = float(inst.c @ xstar)
     return inst
 
