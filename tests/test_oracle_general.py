@@ -198,8 +198,8 @@ def test_planted_dense_layer_mistake_fails(monkeypatch):
     fh = highs(g)
     real = og.reformulate
 
-    def broken(gg, dense=False, x0_border=False):
-        inst, var, const = real(gg, dense=dense, x0_border=x0_border)
+    def broken(gg, dense=False, x0_border=False, bounds=False):
+        inst, var, const = real(gg, dense=dense, x0_border=x0_border, bounds=bounds)
         inst.Wg0 = np.zeros_like(inst.Wg0)
         return inst, var, const
 
