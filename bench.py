@@ -10,7 +10,7 @@ SYRK, block Cholesky + TRSM, Schur contributions and assembly, the Schur
 factorization, predictor and corrector solves with FP64 refinement.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-sens] [--no-uneven]
-                    [--no-general] [--profile [n512|uneven|general|general_dense]] [--fp32]
+                    [--no-general] [--profile [n512|uneven|general|general_dense|general_bounds]] [--fp32]
                     [--launch batched|fused|per_block]
 
 The line also carries the sensitivity workload (N=256, nondegenerate): the
@@ -250,22 +250,27 @@ def general_bench(golden_runs, steps=3):
     reformulated on the host into the standard arrowhead form (once, timed
     apart) and solved by libahlp in FP64, twice: with the global rows chained
     into two-links (the reported value) and with them kept whole in the
-    border of the Schur complement (the dense layer, "dense_layer")."""
+    border of the Schur complement (the dense layer, "dense_layer"); and with
+    the upper bounds inside the iteration instead of as rows
+    ("bounds_in_iteration", global rows chained, and "dense_layer_bounds")."""
+    import numpy as np
     import torch
     from paper_2412_07731_amd import gen, general
     from paper_2412_07731_amd.ahlp import Problem
     g = gen.generate_general("g_large", 0)
 
-    def leg(dense):
+    def leg(dense, bounds=False):
         t = time.perf_counter()
-        inst, mp = general.to_standard(g, dense=dense)
+        inst, mp = general.to_standard(g, dense=dense, bounds=bounds)
         conv = time.perf_counter() - t
         P = Problem(inst)
+        ubv = getattr(inst, "ub", None)
         out = {"standard_form": {"m_tot": int(inst.m_tot), "n_tot": int(inst.n_tot),
                                  "m_i": [int(inst.m.min()), int(inst.m.max())],
                                  "n_i": [int(inst.n.min()), int(inst.n.max())],
                                  "global_rows": int(inst.ng), "n0": int(inst.n0),
-                                 "link_rows_per_pair": [int(inst.l.min()), int(inst.l.max())]},
+                                 "link_rows_per_pair": [int(inst.l.min()), int(inst.l.max())],
+                                 "upper_bounds": int(np.isfinite(ubv).sum()) if ubv is not None else 0},
                "reformulate_s": conv}
         P.ipm()
         torch.cuda.synchronize()
@@ -280,7 +285,7 @@ def general_bench(golden_runs, steps=3):
         x = general.from_standard(mp, xs.detach().cpu().numpy())
         f = float(g.c @ x)
         ref = [q for q in golden_runs if q["config"] == "g_large" and q["seed"] == 0
-               and bool(q.get("dense", False)) == dense]
+               and bool(q.get("dense", False)) == dense and bool(q.get("bounds", False)) == bounds]
         if ref:
             out["oracle_iterations"] = ref[0]["iterations"]
             out["objective_rel_err_vs_oracle"] = abs(f - ref[0]["objective"]) / abs(ref[0]["objective"])
@@ -295,6 +300,10 @@ def general_bench(golden_runs, steps=3):
     out.update(leg(False))
     out["dense_layer"] = leg(True)
     out["dense_layer"]["vs_chained"] = out["dense_layer"]["value"] / out["value"]
+    out["bounds_in_iteration"] = leg(False, True)
+    out["bounds_in_iteration"]["vs_rows"] = out["bounds_in_iteration"]["value"] / out["value"]
+    out["dense_layer_bounds"] = leg(True, True)
+    out["dense_layer_bounds"]["vs_rows"] = out["dense_layer_bounds"]["value"] / out["value"]
     return out
 
 
@@ -428,7 +437,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", nargs="?", const="n512", default=None,
-                    choices=["n512", "uneven", "general", "general_dense"],
+                    choices=["n512", "uneven", "general", "general_dense", "general_bounds"],
                     help="short run for profilers: one fully timed n512 solve (default), or one "
                          "FP64 solve of the uneven or the general-form workload (global rows "
                          "chained, or kept in the dense layer)")
@@ -448,7 +457,7 @@ def main():
     from paper_2412_07731_amd import gen
     from paper_2412_07731_amd.ahlp import FP32_REFINE, FP64, Problem
 
-    if args.profile in ("uneven", "general", "general_dense"):
+    if args.profile in ("uneven", "general", "general_dense", "general_bounds"):
         # one solve of a secondary workload for the profilers (after one
         # untimed solve that loads and warms everything)
         torch.cuda.set_device(0)
@@ -457,7 +466,8 @@ def main():
         else:
             from paper_2412_07731_amd import general
             inst, _ = general.to_standard(gen.generate_general("g_large", 0),
-                                          dense=args.profile == "general_dense")
+                                          dense=args.profile == "general_dense",
+                                          bounds=args.profile == "general_bounds")
         P = Problem(inst)
         if args.profile == "uneven":
             P.autotune()

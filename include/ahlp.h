@@ -91,6 +91,10 @@ typedef struct {
   int32_t ng;             /* global linking rows (0: none; then Wg, Wg0 unused)      */
   const double* Wg;       /* concat_i Wg_i  (ng x n_i)   block i's part of them      */
   const double* Wg0;      /* ng x n0 their x_0 part; NULL = 0                         */
+  const double* ub;       /* [n_tot] upper bounds x <= u (Sec. 3.2), +inf where none, */
+                          /* finite ones > 0; NULL = none.  ahlp_ipm_solve keeps them */
+                          /* inside the iteration (a slack s = u - x and a dual w per  */
+                          /* bounded variable, see ahlp_kkt_factor_bounded)           */
 } ahlp_problem_desc_t;
 
 /* Regularization of the factorization (a reading: the paper leaves pivot
@@ -172,7 +176,8 @@ typedef struct {
 /* One interior-point iteration of the last ahlp_ipm_solve (see
  * ahlp_ipm_history). */
 typedef struct {
-  double mu;              /* x'z / n_tot at the top of the iteration                 */
+  double mu;              /* x'z / n_tot at the top of the iteration ((x'z + s'w) /   */
+                          /* (n_tot + bounded variables) with upper bounds)           */
   double sigma;           /* centring parameter (mu_aff / mu)^3 of Mehrotra's rule     */
   double alpha_p, alpha_d;/* primal and dual step lengths taken                        */
   double bkerr_pred;      /* backward error of the predictor direction after          */
@@ -206,6 +211,22 @@ ahlp_status_t ahlp_problem_destroy(ahlp_problem_t p);
  * AHLP_ENUMERIC).  The factors stay in the handle until the next factor call. */
 ahlp_status_t ahlp_kkt_factor(ahlp_problem_t p, const double* x, const double* z,
                               const ahlp_factor_opts_t* opts, hipStream_t stream);
+
+/* The same factorization with upper bounds inside the iteration (Sec. 3.2's
+ * bounds x <= u kept as bounds): a bounded variable's slack s = u - x and dual
+ * w are eliminated from the Newton system, which leaves the matrix of Sec. 2.3
+ * with -Q in its (x, x) block, Q = diag(q), q = w / s (0 for a variable
+ * without an upper bound), so D = (Z/X + Q + rho)^-1.  q: DEVICE [n_tot],
+ * >= 0, copied.  Until the next factor call ahlp_kkt_solve (and its
+ * refinement and backward error) works on
+ *     [-Q A' I; A 0 0; Z 0 X] [dx; dy; dz] = [rx; ry; rz],
+ * whose rx for a bounded problem is r_d + S^-1 (r_sw - W r_u) (r_u = u - x -
+ * s, r_sw the (s, w) complementarity residual), with ds = r_u - dx and dw =
+ * S^-1 (r_sw - W ds) recovered by the caller.  Errors as ahlp_kkt_factor;
+ * the first call allocates the copy of q. */
+ahlp_status_t ahlp_kkt_factor_bounded(ahlp_problem_t p, const double* x, const double* z,
+                                      const double* q, const ahlp_factor_opts_t* opts,
+                                      hipStream_t stream);
 
 /* Solve, Alg. 3 of Sec. 3.2: (dx, dy, dz) for the Newton system of Sec. 2.3
  *     [0 A' I; A 0 0; Z 0 X] [dx; dy; dz] = [rx; ry; rz]
@@ -336,6 +357,12 @@ ahlp_status_t ahlp_ipm_solve(ahlp_problem_t p, const ahlp_ipm_opts_t* opts, doub
  * are written.  Errors: AHLP_EINVAL for a null handle or count, cap < 0. */
 ahlp_status_t ahlp_ipm_history(ahlp_problem_t p, ahlp_ipm_iter_t* out, int32_t cap,
                                int32_t* count);
+
+/* For a problem with upper bounds (desc.ub): the slacks s = u - x and their
+ * duals w at the end of the last ahlp_ipm_solve (the dual of the LP is
+ * A'y + z - w = c).  s, w: DEVICE [n_tot] or NULL, zero where a variable has no
+ * upper bound.  Stream ordered.  AHLP_ESTATE if the problem has no bounds. */
+ahlp_status_t ahlp_ipm_bound_duals(ahlp_problem_t p, double* s, double* w, hipStream_t stream);
 
 /* Last error message of this thread ("" when none). */
 const char* ahlp_last_error(void);

@@ -27,7 +27,8 @@ _f64p = C.POINTER(C.c_double)
 class Desc(C.Structure):
     _fields_ = [("N", C.c_int32), ("n0", C.c_int32), ("m", _i32p), ("n", _i32p), ("l", _i32p),
                 ("A", _f64p), ("C", _f64p), ("FR", _f64p), ("FL", _f64p), ("F0", _f64p),
-                ("b", _f64p), ("c", _f64p), ("ng", C.c_int32), ("Wg", _f64p), ("Wg0", _f64p)]
+                ("b", _f64p), ("c", _f64p), ("ng", C.c_int32), ("Wg", _f64p), ("Wg0", _f64p),
+                ("ub", _f64p)]
 
 
 class FactorOpts(C.Structure):
@@ -86,6 +87,9 @@ SIGNATURES = {
                         C.POINTER(IpmResult), C.c_void_p], C.c_int),
     "ahlp_ipm_history": ([C.c_void_p, C.POINTER(IpmIter), C.c_int32, C.POINTER(C.c_int32)],
                          C.c_int),
+    "ahlp_kkt_factor_bounded": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.POINTER(FactorOpts), C.c_void_p], C.c_int),
+    "ahlp_ipm_bound_duals": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "ahlp_last_error": ([], C.c_char_p),
     "ahlp_problem_sizes": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
@@ -167,10 +171,13 @@ class Problem:
         Wg = _cat(Wg_list) if self.ng > 0 else None
         Wg0 = (np.ascontiguousarray(inst.Wg0, dtype=np.float64)
                if self.ng > 0 and self.n0 > 0 and inst.Wg0 is not None else None)
-        self._keep = (m, n, l, A, Cm, FR, FL, F0, b, c, Wg, Wg0)
+        ubv = getattr(inst, "ub", None)
+        ub = np.ascontiguousarray(ubv, dtype=np.float64) if ubv is not None else None
+        self.bounded = ub is not None and bool(np.isfinite(ub).any())
+        self._keep = (m, n, l, A, Cm, FR, FL, F0, b, c, Wg, Wg0, ub)
         d = Desc(self.N, self.n0, m.ctypes.data_as(_i32p), n.ctypes.data_as(_i32p),
                  l.ctypes.data_as(_i32p), _ptr(A), _ptr(Cm), _ptr(FR), _ptr(FL), _ptr(F0),
-                 _ptr(b), _ptr(c), self.ng, _ptr(Wg), _ptr(Wg0))
+                 _ptr(b), _ptr(c), self.ng, _ptr(Wg), _ptr(Wg0), _ptr(ub))
         h = C.c_void_p()
         _check(L.ahlp_problem_create(C.byref(d), _stream(stream), C.byref(h)))
         self._keep = None
@@ -197,6 +204,22 @@ class Problem:
     def factor(self, x, z, rho=0.0, delta=0.0, precision=FP64, stream=None):
         o = FactorOpts(precision, rho, delta)
         _check(lib().ahlp_kkt_factor(self.h, _dptr(x), _dptr(z), C.byref(o), _stream(stream)))
+
+    def factor_bounded(self, x, z, q, rho=0.0, delta=0.0, precision=FP64, stream=None):
+        """ahlp_kkt_factor_bounded: the factorization with Q = diag(q) in the
+        (x, x) block (upper bounds inside the iteration, q = w / s)."""
+        o = FactorOpts(precision, rho, delta)
+        _check(lib().ahlp_kkt_factor_bounded(self.h, _dptr(x), _dptr(z), _dptr(q), C.byref(o),
+                                             _stream(stream)))
+
+    def bound_duals(self, stream=None):
+        """(s, w) of the last ipm() on a problem with upper bounds (device tensors)."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        s = torch.empty(self.n_tot, dtype=torch.float64, device=dev)
+        w = torch.empty_like(s)
+        _check(lib().ahlp_ipm_bound_duals(self.h, _dptr(s), _dptr(w), _stream(stream)))
+        return s, w
 
     def solve(self, rx, ry, rz, max_refine=0, refine_tol=1e-10, stream=None, out=None):
         import torch

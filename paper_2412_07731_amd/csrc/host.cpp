@@ -266,6 +266,18 @@ struct ahlp_problem_s {
          *w2p = nullptr;
   double* adj_rz = nullptr;   // z g_z of the transposed solve
   double *grad_g = nullptr, *grad_wz = nullptr;   // ahlp_lp_gradient: its right-hand side, w_z
+  // upper bounds inside the iteration (allocated when some are finite): ub
+  // (+inf where none) and ufin (u or 0); the interior-point run's slacks s,
+  // duals w, their directions (predictor ds, dw and corrector), r_u = u - x -
+  // s, q = w/s, zw = z - w, the reduced x right-hand sides of predictor and
+  // corrector, and minima helpers of the start
+  long long nU = 0;
+  double ub_inf = 0.0;
+  double *ub = nullptr, *ufin = nullptr, *bs = nullptr, *bw = nullptr, *bdsa = nullptr,
+         *bdwa = nullptr, *bds = nullptr, *bdw = nullptr, *bru = nullptr, *bq = nullptr,
+         *bzw = nullptr, *brdt = nullptr, *brxc = nullptr, *bsm = nullptr, *bwm = nullptr,
+         *bqapi = nullptr;
+  const double* qcur = nullptr;   // q of the current factorization (nullptr: none)
   // Gondzio correctors: right-hand side, candidate direction, zero y-vector
   double *g_r = nullptr, *g_dx = nullptr, *g_dy = nullptr, *g_dz = nullptr, *zerosm = nullptr;
   double *rp = nullptr, *rd = nullptr, *rzv = nullptr, *dxa = nullptr, *dya = nullptr,
@@ -313,6 +325,8 @@ constexpr int NSCAL = 32;
 // 20-28 refinement check (|r|, |e|, |d| per block row), 31 device info
 constexpr int S_AP = 10, S_AD = 11, S_MUAFF = 12, S_SMU = 13, S_GP = 14, S_GD = 15, S_RN = 20,
               S_EN = 23, S_DN = 26;
+// with upper bounds: s'w, |r_u|_inf, u'w, (s + a_p ds)'(w + a_d dw) and max q
+constexpr int S_SW = 6, S_RU = 7, S_UW = 16, S_MUAFF_SW = 17, S_QMAX = 18;
 static_assert(sizeof(DevInfo) <= sizeof(double), "device info must fit one scal slot");
 
 ahlp_status_t check_info(ahlp_problem_t p, hipStream_t st, bool* nonfinite) {
@@ -566,7 +580,7 @@ ahlp_status_t prep_scaling(ahlp_problem_t p, const double* x, const double* z, d
   static_assert(sizeof(DevInfo) <= sizeof(double), "DevInfo lives in one scalar slot");
   launch_fill(st, 1, 0.0, reinterpret_cast<double*>(p->info));   // a kernel, not a memset: capturable
   p->timer.begin(AHLP_ST_PREP);
-  launch_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, rho, p->Dp, p->xs, p->zs,
+  launch_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, p->qcur, rho, p->Dp, p->xs, p->zs,
               p->info);
   p->timer.end();
   return AHLP_OK;
@@ -799,10 +813,14 @@ struct Reds {
 // ey = ry - A dx, ez = rz - Z dx - X dz.  With w2 the same row pass also
 // forms aw2 = A (D dx dz / x) (the corrector's right-hand-side term).
 void check_pass(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
-                const double* dx, const double* dz, bool w2, hipStream_t st) {
+                const double* dx, const double* dz, bool w2, hipStream_t st,
+                const BndArgs* bnd = nullptr) {
   p->timer.begin(AHLP_ST_RESID);
+  BndArgs b{};
+  if (bnd) b = *bnd;
+  b.q = p->qcur;
   launch_check_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, rx, rz, p->ws.g, dx, dz, p->xs,
-                    p->zs, p->Dp, p->ws.ex, p->ws.ez, p->ws.xp, w2 ? p->w2p : nullptr);
+                    p->zs, p->Dp, p->ws.ex, p->ws.ez, p->ws.xp, w2 ? p->w2p : nullptr, b);
   RowsArgs ra{};
   ra.nv = 1;
   ra.v[0] = p->ws.xp; ra.base[0] = ry; ra.alpha[0] = -1.0; ra.out[0] = p->ws.ey; ra.with_C[0] = 1;
@@ -852,7 +870,7 @@ double check_en(ahlp_problem_t p) {
 ahlp_status_t refine(ahlp_problem_t p, const double* rx, const double* ry, const double* rz,
                      double* dx, double* dy, double* dz, int max_refine, double tol,
                      double knorm, double rn, bool w2, double* be, int* steps, hipStream_t st,
-                     double abs_tol = 0.0, bool stagnate = false) {
+                     double abs_tol = 0.0, bool stagnate = false, const BndArgs* bnd = nullptr) {
   while (*be > tol && !(abs_tol > 0.0 && check_en(p) <= abs_tol) && *steps < max_refine) {
     const double be_prev = *be;
     CHK(solve_once(p, p->ws.ex, p->ws.ey, p->ws.ez, p->ws.cx, p->ws.cy, p->ws.cz, st, nullptr, p->ws.gc));
@@ -860,7 +878,7 @@ ahlp_status_t refine(ahlp_problem_t p, const double* rx, const double* ry, const
     launch_axpy(st, p->m_tot, 1.0, p->ws.cy, dy);
     launch_axpy(st, p->n_tot, 1.0, p->ws.cz, dz);
     launch_axpy(st, p->n_tot, 1.0, p->ws.gc, p->ws.g);
-    check_pass(p, rx, ry, rz, dx, dz, w2, st);
+    check_pass(p, rx, ry, rz, dx, dz, w2, st, bnd);
     Reds R(p);
     add_check_reds(p, R, rx, ry, rz, dx, dy, dz, false);
     R.launch(st);
@@ -900,9 +918,12 @@ ahlp_status_t solve_refined(ahlp_problem_t p, const double* rx, const double* ry
 
 ahlp_status_t kkt_norm(ahlp_problem_t p, hipStream_t st, double* out) {
   red(p, RED_MAXSUM, p->n_tot, p->xs, p->zs, 9, st);
-  HIPCHK(hipMemcpyAsync(p->h_scal + 9, p->ws.scal + 9, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (p->qcur) red(p, RED_MAXABS, p->n_tot, p->qcur, nullptr, 8, st);
+  HIPCHK(hipMemcpyAsync(p->h_scal + 8, p->ws.scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  *out = std::max(p->colabs1_max, std::max(p->rowabs_max, p->h_scal[9]));
+  // |K|_inf: the (x) rows' |A| column sums + 1 (+ max q), the (y) rows, max(x + z)
+  const double qmax = p->qcur ? p->h_scal[8] : 0.0;
+  *out = std::max(p->colabs1_max + qmax, std::max(p->rowabs_max, p->h_scal[9]));
   return AHLP_OK;
 }
 
@@ -1174,6 +1195,25 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     if (!std::isfinite(d->c[i])) return fail(AHLP_ENUMERIC, "non-finite c");
     p->c_inf = std::max(p->c_inf, std::fabs(d->c[i]));
   }
+  std::vector<double> hub, hufin;
+  if (d->ub) {
+    for (long long i = 0; i < p->n_tot; ++i) {
+      const double u = d->ub[i];
+      if (std::isnan(u)) return fail(AHLP_ENUMERIC, "NaN upper bound");
+      if (std::isfinite(u)) {
+        if (!(u > 0.0)) return fail(AHLP_EINVAL, "upper bound %lld must be positive (got %g)", i, u);
+        ++p->nU;
+        p->ub_inf = std::max(p->ub_inf, u);
+      } else if (u < 0.0) {
+        return fail(AHLP_EINVAL, "upper bound %lld is -inf", i);
+      }
+    }
+    if (p->nU > 0) {
+      hub.assign(d->ub, d->ub + p->n_tot);
+      hufin.resize((size_t)p->n_tot);
+      for (long long i = 0; i < p->n_tot; ++i) hufin[i] = std::isfinite(hub[i]) ? hub[i] : 0.0;
+    }
+  }
   p->rowabs_max = 0.0;
   for (double v : rowabs) p->rowabs_max = std::max(p->rowabs_max, v);
   p->colabs1_max = 1.0;
@@ -1366,6 +1406,13 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
   CHK(M.alloc(&p->grad_wz, p->n_tot));
   for (double** v : {&p->g_r, &p->g_dx, &p->g_dz}) CHK(M.alloc(v, p->n_tot));
   for (double** v : {&p->g_dy, &p->zerosm}) CHK(M.alloc(v, p->m_tot));
+  if (p->nU > 0) {
+    for (double** v : {&p->ub, &p->ufin, &p->bs, &p->bw, &p->bdsa, &p->bdwa, &p->bds, &p->bdw,
+                       &p->bru, &p->bq, &p->bzw, &p->brdt, &p->brxc, &p->bsm, &p->bwm})
+      CHK(M.alloc(v, p->n_tot));
+    HIPCHK(hipMemcpyAsync(p->ub, hub.data(), sizeof(double) * p->n_tot, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->ufin, hufin.data(), sizeof(double) * p->n_tot, hipMemcpyHostToDevice, st));
+  }
   HIPCHK(hipHostMalloc((void**)&p->h_scal, NSCAL * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
@@ -1442,7 +1489,34 @@ ahlp_status_t ahlp_kkt_factor(ahlp_problem_t p, const double* x, const double* z
   if (!(rho >= 0.0) || !(delta >= 0.0)) return fail(AHLP_EINVAL, "rho and delta must be >= 0");
   if (prec != AHLP_FP64 && prec != AHLP_FP32_REFINE) return fail(AHLP_EINVAL, "unknown precision");
   p->timer.st = st;
+  p->qcur = nullptr;
   return do_factor(p, x, z, prec, rho, delta, st);
+}
+
+ahlp_status_t ahlp_kkt_factor_bounded(ahlp_problem_t p, const double* x, const double* z,
+                                      const double* q, const ahlp_factor_opts_t* o,
+                                      hipStream_t st) {
+  g_err.clear();
+  if (!p || !x || !z || !q) return fail(AHLP_EINVAL, "null argument");
+  const int prec = o ? o->precision : AHLP_FP64;
+  const double rho = o ? o->rho : 0.0, delta = o ? o->delta : 0.0;
+  if (!(rho >= 0.0) || !(delta >= 0.0)) return fail(AHLP_EINVAL, "rho and delta must be >= 0");
+  if (prec != AHLP_FP64 && prec != AHLP_FP32_REFINE) return fail(AHLP_EINVAL, "unknown precision");
+  if (!p->bqapi) CHK(p->mem.alloc(&p->bqapi, p->n_tot));
+  p->timer.st = st;
+  launch_copy(st, p->n_tot, q, p->bqapi);
+  p->qcur = p->bqapi;
+  return do_factor(p, x, z, prec, rho, delta, st);
+}
+
+ahlp_status_t ahlp_ipm_bound_duals(ahlp_problem_t p, double* s, double* w, hipStream_t st) {
+  g_err.clear();
+  if (!p) return fail(AHLP_EINVAL, "null handle");
+  if (!p->ub) return fail(AHLP_ESTATE, "the problem has no upper bounds");
+  if (s) launch_copy(st, p->n_tot, p->bs, s);
+  if (w) launch_copy(st, p->n_tot, p->bw, w);
+  HIPCHK(hipGetLastError());
+  return AHLP_OK;
 }
 
 namespace {
@@ -1771,6 +1845,10 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   p->hist.clear();
   R.start_bkerr[0] = R.start_bkerr[1] = -1.0;
   const long long n = p->n_tot, m = p->m_tot;
+  const bool bnd = p->nU > 0;
+  if (bnd && o->gondzio > 0)
+    return fail(AHLP_EINVAL, "Gondzio correctors are not combined with upper bounds");
+  p->qcur = nullptr;   // the start point's factorization has no bound term
   int total_piv = 0;
   double max_bk = 0.0;
   int refine_total = 0;
@@ -1809,23 +1887,51 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     launch_copy(st, n, p->dxa, x);
     launch_copy(st, m, p->dy, y);
     apply_At(p, y, 1, p->c, p->zerosn, z, st);   // z~ = c - A'y~
-    Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, z, nullptr, 1).launch(st);
-    CHK(read_scal(p, 2, st));
-    const double sx = std::max(-1.5 * p->h_scal[0], 0.0), sz = std::max(-1.5 * p->h_scal[1], 0.0);
-    launch_addscalar(st, n, sx, x);
-    launch_addscalar(st, n, sz, z);
-    Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, x, p->ones, 1).add(RED_DOT, n, z, p->ones, 2)
-        .launch(st);
-    CHK(read_scal(p, 3, st));
-    const double xz = p->h_scal[0], sumx = p->h_scal[1], sumz = p->h_scal[2];
-    launch_addscalar(st, n, sumz > 0 ? 0.5 * xz / sumz : 0.0, x);
-    launch_addscalar(st, n, sumx > 0 ? 0.5 * xz / sumx : 0.0, z);
-    Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, z, nullptr, 1).launch(st);
-    CHK(read_scal(p, 2, st));
-    if (p->h_scal[0] <= 0.0 || p->h_scal[1] <= 0.0) {
-      launch_addscalar(st, n, 1.0, x);
-      launch_addscalar(st, n, 1.0, z);
+    if (bnd) {
+      // bounded variables: z = max(z~, 0), w = max(-z~, 0), s = u - x~; the
+      // pairs (x, s) and (z, w) shifted and centred together
+      launch_bnd_start(st, n, p->ub, x, z, p->bs, p->bw, p->bsm, p->bwm);
+      Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, p->bsm, nullptr, 1)
+          .add(RED_MIN, n, z, nullptr, 2).add(RED_MIN, n, p->bwm, nullptr, 3).launch(st);
+      CHK(read_scal(p, 4, st));
+      const double mp = std::min(p->h_scal[0], p->h_scal[1]), md = std::min(p->h_scal[2], p->h_scal[3]);
+      launch_bnd_shift(st, n, p->ub, std::max(-1.5 * mp, 0.0), std::max(-1.5 * md, 0.0), x, z, p->bs,
+                       p->bw, p->bsm, p->bwm);
+      Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, p->bs, p->bw, 1)
+          .add(RED_DOT, n, x, p->ones, 2).add(RED_DOT, n, p->bs, p->ones, 3)
+          .add(RED_DOT, n, z, p->ones, 4).add(RED_DOT, n, p->bw, p->ones, 5).launch(st);
+      CHK(read_scal(p, 6, st));
+      const double* hh = p->h_scal;
+      const double xz = hh[0] + hh[1], sx = hh[2] + hh[3], sz = hh[4] + hh[5];
+      launch_bnd_shift(st, n, p->ub, sz > 0 ? 0.5 * xz / sz : 0.0, sx > 0 ? 0.5 * xz / sx : 0.0, x, z,
+                       p->bs, p->bw, p->bsm, p->bwm);
+      Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, z, nullptr, 1)
+          .add(RED_MIN, n, p->bsm, nullptr, 2).add(RED_MIN, n, p->bwm, nullptr, 3).launch(st);
+      CHK(read_scal(p, 4, st));
+      if (hh[0] <= 0.0 || hh[1] <= 0.0 || hh[2] <= 0.0 || hh[3] <= 0.0)
+        launch_bnd_shift(st, n, p->ub, 1.0, 1.0, x, z, p->bs, p->bw, p->bsm, p->bwm);
     }
+    Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, z, nullptr, 1).launch(st);
+    CHK(read_scal(p, 2, st));
+    if (!bnd) {
+      const double sx = std::max(-1.5 * p->h_scal[0], 0.0), sz = std::max(-1.5 * p->h_scal[1], 0.0);
+      launch_addscalar(st, n, sx, x);
+      launch_addscalar(st, n, sz, z);
+      Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, x, p->ones, 1).add(RED_DOT, n, z, p->ones, 2)
+          .launch(st);
+      CHK(read_scal(p, 3, st));
+      const double xz = p->h_scal[0], sumx = p->h_scal[1], sumz = p->h_scal[2];
+      launch_addscalar(st, n, sumz > 0 ? 0.5 * xz / sumz : 0.0, x);
+      launch_addscalar(st, n, sumx > 0 ? 0.5 * xz / sumx : 0.0, z);
+      Reds(p).add(RED_MIN, n, x, nullptr, 0).add(RED_MIN, n, z, nullptr, 1).launch(st);
+      CHK(read_scal(p, 2, st));
+      if (p->h_scal[0] <= 0.0 || p->h_scal[1] <= 0.0) {
+        launch_addscalar(st, n, 1.0, x);
+        launch_addscalar(st, n, 1.0, z);
+      }
+    }
+  } else if (bnd) {
+    return fail(AHLP_EINVAL, "a problem with upper bounds starts from its own start point (start = 0)");
   }
 
   // ---- main loop
@@ -1849,14 +1955,26 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
   // kept in p->aty: formed by a column pass at the start (full), then
   // advanced with each step, A'y+ = A'y + alpha_d A'dy, where A'dy is the
   // solve's own column pass (p->ws.g, refinement corrections included)
+  BndArgs bres{};    // the bounds at the current iterate
+  if (bnd) {
+    bres.ub = p->ub; bres.s = p->bs; bres.w = p->bw; bres.q = p->bq; bres.ru = p->bru;
+  }
   auto resid_stage = [&](bool full) -> ahlp_status_t {
     p->timer.begin(AHLP_ST_RESID);
+    const double* zr = z;   // r_d = c - A'y - z (+ w)
+    if (bnd) {
+      launch_bnd_prep(st, n, p->ub, x, z, p->bs, p->bw, p->bru, p->bq, p->bzw, p->info);
+      p->qcur = p->bq;
+      zr = p->bzw;
+    }
     CHK(prep_scaling(p, x, z, o->rho, st));
-    if (full) apply_At_both(p, y, p->c, z, p->rd, p->aty, st);     // r_d = c - A'y - z
-    else launch_rd(st, n, p->c, p->aty, z, p->rd);
-    // rz_a = -x z, rhx_a, vx = D rhx_a, w1 = D / x, xp = x (padded)
+    if (bnd) launch_bnd_prep(st, n, p->ub, x, z, p->bs, p->bw, p->bru, p->bq, p->bzw, p->info);
+    if (full) apply_At_both(p, y, p->c, zr, p->rd, p->aty, st);
+    else launch_rd(st, n, p->c, p->aty, zr, p->rd);
+    // rz_a = -x z, rhx_a, vx = D rhx_a, w1 = D / x (- D / s), xp = x (padded);
+    // with bounds also the predictor's x right-hand side brdt
     launch_resid_prep(st, p->blk, p->N, p->n0, p->x0off, p->d0off, x, z, p->rd, p->xs, p->Dp,
-                      p->rzv, p->ws.rhx, p->ws.vx, p->w1p, p->ws.xp);
+                      p->rzv, p->ws.rhx, p->ws.vx, p->w1p, p->ws.xp, bres, p->brdt);
     {
       RowsArgs ra{};
       ra.nv = 3;
@@ -1866,18 +1984,25 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       rows_pass(p, ra, st);
     }
     link_global_rows(p, p->ws.xp, p->ws.xp + p->d0off, p->b + p->mblk, -1.0, p->rp + p->mblk, st);
-    Reds(p).add(RED_DOT, n, x, z, 0).add(RED_DOT, n, p->c, x, 1).add(RED_DOT, m, p->b, y, 2)
+    Reds Rr(p);
+    Rr.add(RED_DOT, n, x, z, 0).add(RED_DOT, n, p->c, x, 1).add(RED_DOT, m, p->b, y, 2)
         .add(RED_MAXABS, m, p->rp, nullptr, 3).add(RED_MAXABS, n, p->rd, nullptr, 4)
-        .add(RED_MAXSUM, n, x, z, 5).launch(st);
+        .add(RED_MAXSUM, n, x, z, 5);
+    if (bnd)
+      Rr.add(RED_DOT, n, p->bs, p->bw, S_SW).add(RED_MAXABS, n, p->bru, nullptr, S_RU)
+          .add(RED_DOT, n, p->ufin, p->bw, S_UW).add(RED_MAXABS, n, p->bq, nullptr, S_QMAX);
+    Rr.launch(st);
     p->timer.end();
     return AHLP_OK;
   };
   // the step with the ratio-test results on the device, then the next
   // iteration's residuals
   auto step_resid = [&]() -> ahlp_status_t {
-    launch_steps(st, o->eta, StepSet{4, {n, m, n, n},
-                                     {p->ws.scal + S_AP, p->ws.scal + S_AD, p->ws.scal + S_AD, p->ws.scal + S_AD},
-                                     {p->dx, p->dy, p->dz, p->ws.g}, {x, y, z, p->aty}});
+    launch_steps(st, o->eta, StepSet{bnd ? 6 : 4, {n, m, n, n, n, n},
+                                     {p->ws.scal + S_AP, p->ws.scal + S_AD, p->ws.scal + S_AD,
+                                      p->ws.scal + S_AD, p->ws.scal + S_AP, p->ws.scal + S_AD},
+                                     {p->dx, p->dy, p->dz, p->ws.g, p->bds, p->bdw},
+                                     {x, y, z, p->aty, p->bs, p->bw}});
     return resid_stage(false);
   };
   CHK(resid_stage(true));
@@ -1887,12 +2012,15 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       return fail(AHLP_EHIP, "the fused factorization launch gave up waiting for its own stages");
     if (hinfo->nonfinite)
       return fail(AHLP_ENUMERIC, "x or z left the positive orthant or became non-finite");
-    const double knorm_iter = std::max(p->colabs1_max, std::max(p->rowabs_max, hs[5]));
-    mu = hs[0] / (double)n;
+    const double knorm_iter = std::max(p->colabs1_max + (bnd ? hs[S_QMAX] : 0.0),
+                                       std::max(p->rowabs_max, hs[5]));
+    const long long nmu = n + p->nU;   // complementarity pairs
+    mu = (hs[0] + (bnd ? hs[S_SW] : 0.0)) / (double)nmu;
     pobj = hs[1];
-    dobj = hs[2];
+    dobj = hs[2] - (bnd ? hs[S_UW] : 0.0);
     relgap = std::fabs(pobj - dobj) / std::max(1.0, std::fabs(pobj));
     pinf = hs[3] / bn;
+    if (bnd) pinf = std::max(pinf, hs[S_RU] / (1.0 + p->ub_inf));
     dinf = hs[4] / cn;
     if (o->verbose)
       fprintf(stderr, "ahlp it %3d mu %.3e gap %.3e pinf %.3e dinf %.3e pobj %.10e%s\n", k, mu,
@@ -1931,18 +2059,45 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
         Rm.add(RED_MUAFF, n, x, p->dxa, S_MUAFF, z, p->dza);
         Rm.m.r[0].ps1 = p->ws.scal + S_AP;
         Rm.m.r[0].ps2 = p->ws.scal + S_AD;
+        if (bnd) {
+          Rm.add(RED_MUAFF, n, p->bs, p->bdsa, S_MUAFF_SW, p->bw, p->bdwa);
+          Rm.m.r[1].ps1 = p->ws.scal + S_AP;
+          Rm.m.r[1].ps2 = p->ws.scal + S_AD;
+        }
         Rm.launch(st);
       };
+      // ratio tests over (x, s) and (z, w)
+      auto ratios = [&](Reds& Rq, const double* ddx, const double* ddz, const double* dds,
+                        const double* ddw) {
+        if (bnd)
+          Rq.add(RED_RATIO2, n, x, ddx, S_AP, p->bs, dds).add(RED_RATIO2, n, z, ddz, S_AD, p->bw, ddw);
+        else
+          Rq.add(RED_RATIO, n, x, ddx, S_AP).add(RED_RATIO, n, z, ddz, S_AD);
+      };
+      // the bounds' recovery of ds, dw in the checks (predictor, corrector)
+      BndArgs bpred = bres, bcorr = bres;
+      const double* rxa = p->rd;    // x right-hand sides of predictor and corrector
+      const double* rxc = p->rd;
+      if (bnd) {
+        bpred.mode = 0; bpred.ds = p->bdsa; bpred.dw = p->bdwa;
+        bcorr.mode = 1; bcorr.ds = p->bds; bcorr.dw = p->bdw; bcorr.dsa = p->bdsa; bcorr.dwa = p->bdwa;
+        bcorr.smu = p->ws.scal + S_SMU; bcorr.rdt = p->brdt;
+        rxa = p->brdt;
+        rxc = p->brxc;
+      }
+      const BndArgs* bp = bnd ? &bpred : nullptr;
+      const BndArgs* bc = bnd ? &bcorr : nullptr;
       // factorization and predictor (rz_a = -x z; t_a from the residual pass),
       // its check, step lengths and mu_aff
       CHK(run_segment(p, f32 ? SEG_A32 : SEG_A64, key, st, [&]() -> ahlp_status_t {
         CHK(do_factor(p, x, z, prec, o->rho, o->delta, st, true));
         launch_rz(st, n, 0, x, z, nullptr, nullptr, 0.0, p->rzv);
-        CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, st, p->ta));
-        check_pass(p, p->rd, p->rp, p->rzv, p->dxa, p->dza, true, st);
+        CHK(solve_once(p, rxa, p->rp, p->rzv, p->dxa, p->dya, p->dza, st, p->ta));
+        check_pass(p, rxa, p->rp, p->rzv, p->dxa, p->dza, true, st, bp);
         Reds Rp(p);
-        add_check_reds(p, Rp, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, true);
-        Rp.add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
+        add_check_reds(p, Rp, rxa, p->rp, p->rzv, p->dxa, p->dya, p->dza, true);
+        ratios(Rp, p->dxa, p->dza, p->bdsa, p->bdwa);
+        Rp.launch(st);
         muaff_launch();
         return AHLP_OK;
       }));
@@ -1954,14 +2109,16 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       double rn = check_rn(p);
       be = check_bkerr(p, kn, rn);
       if (!acceptable(be)) {
-        CHK(refine(p, p->rd, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine, o->refine_tol,
-                   kn, rn, true, &be, &steps, st, atol, f32 && !plain));
+        CHK(refine(p, rxa, p->rp, p->rzv, p->dxa, p->dya, p->dza, o->max_refine, o->refine_tol,
+                   kn, rn, true, &be, &steps, st, atol, f32 && !plain, bp));
         if (f32 && !plain && !acceptable(be)) {
           refine_total += steps;   // spent, although the pass is redone in FP64
           *ok = false;
           return AHLP_OK;
         }
-        Reds(p).add(RED_RATIO, n, x, p->dxa, S_AP).add(RED_RATIO, n, z, p->dza, S_AD).launch(st);
+        Reds Rq(p);
+        ratios(Rq, p->dxa, p->dza, p->bdsa, p->bdwa);
+        Rq.launch(st);
         muaff_launch();
         CHK(read_scal(p, NSCAL, st));
       }
@@ -1972,14 +2129,17 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       // corrector: sigma mu on the device, rz_c and
       // t_c = t_a - sigma mu A(D/x) + A(D dxa dza / x), solve, check, step lengths
       CHK(run_segment(p, f32 ? SEG_B32 : SEG_B64, key, st, [&]() -> ahlp_status_t {
-        launch_sigma_mu(st, p->ws.scal, n, 0, S_MUAFF, S_SMU);
-        launch_rz(st, n, 1, x, z, p->dxa, p->dza, 0.0, p->rzv, p->ws.scal + S_SMU);
+        if (bnd) launch_sigma_mu(st, p->ws.scal, n + p->nU, 0, S_MUAFF, S_SMU, S_SW, S_MUAFF_SW);
+        else launch_sigma_mu(st, p->ws.scal, n, 0, S_MUAFF, S_SMU);
+        launch_rz(st, n, 1, x, z, p->dxa, p->dza, 0.0, p->rzv, p->ws.scal + S_SMU, bc,
+                  bnd ? p->brxc : nullptr);
         launch_combine(st, p->vp_total, p->ta, 0.0, p->aw1, p->aw2, p->tc, p->ws.scal + S_SMU);
-        CHK(solve_once(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, st, p->tc));
-        check_pass(p, p->rd, p->rp, p->rzv, p->dx, p->dz, false, st);
+        CHK(solve_once(p, rxc, p->rp, p->rzv, p->dx, p->dy, p->dz, st, p->tc));
+        check_pass(p, rxc, p->rp, p->rzv, p->dx, p->dz, false, st, bc);
         Reds Rc(p);
-        add_check_reds(p, Rc, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, true);
-        Rc.add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
+        add_check_reds(p, Rc, rxc, p->rp, p->rzv, p->dx, p->dy, p->dz, true);
+        ratios(Rc, p->dx, p->dz, p->bds, p->bdw);
+        Rc.launch(st);
         return AHLP_OK;
       }));
       CHK(read_scal(p, NSCAL, st));
@@ -1987,14 +2147,16 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
       be = check_bkerr(p, kn, rn);
       steps = 0;
       if (!acceptable(be)) {
-        CHK(refine(p, p->rd, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine, o->refine_tol, kn,
-                   rn, false, &be, &steps, st, atol, f32 && !plain));
+        CHK(refine(p, rxc, p->rp, p->rzv, p->dx, p->dy, p->dz, o->max_refine, o->refine_tol, kn,
+                   rn, false, &be, &steps, st, atol, f32 && !plain, bc));
         if (f32 && !plain && !acceptable(be)) {
           refine_total += steps;   // spent, although the pass is redone in FP64
           *ok = false;
           return AHLP_OK;
         }
-        Reds(p).add(RED_RATIO, n, x, p->dx, S_AP).add(RED_RATIO, n, z, p->dz, S_AD).launch(st);
+        Reds Rq(p);
+        ratios(Rq, p->dx, p->dz, p->bds, p->bdw);
+        Rq.launch(st);
         CHK(read_scal(p, NSCAL, st));
       }
       account(be, steps);
@@ -2069,9 +2231,11 @@ ahlp_status_t ipm_solve_impl(ahlp_problem_t p, const ahlp_ipm_opts_t* o, double*
     p->hist.push_back(it);
     ++k;
     if (ap < 1e-12 && ad < 1e-12) {
-      launch_steps(st, o->eta, StepSet{3, {n, m, n, 0},
-                                       {p->ws.scal + S_AP, p->ws.scal + S_AD, p->ws.scal + S_AD, nullptr},
-                                       {p->dx, p->dy, p->dz, nullptr}, {x, y, z, nullptr}});
+      launch_steps(st, o->eta, StepSet{bnd ? 5 : 3, {n, m, n, n, n, 0},
+                                       {p->ws.scal + S_AP, p->ws.scal + S_AD, p->ws.scal + S_AD,
+                                        p->ws.scal + S_AP, p->ws.scal + S_AD, nullptr},
+                                       {p->dx, p->dy, p->dz, p->bds, p->bdw, nullptr},
+                                       {x, y, z, p->bs, p->bw, nullptr}});
       status = AHLP_WSTALL;
       break;
     }

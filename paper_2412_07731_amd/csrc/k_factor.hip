@@ -20,12 +20,14 @@
 namespace ahlp {
 
 // ---------------------------------------------------------------- a1: D
-// One workgroup per block (and one for x_0).  Fills the padded D and keeps a
-// copy of x and z for the solve phase; flags non-positive or non-finite input.
+// One workgroup per block (and one for x_0).  Fills the padded D =
+// (z/x + q + rho)^-1 (q: the upper bounds' W/S, or none) and keeps a copy of x
+// and z for the solve phase; flags non-positive or non-finite input.
 __global__ void k_prep(const BlockInfo* __restrict__ blk, int N, int n0, long long x0off,
                        long long d0off, const double* __restrict__ x,
-                       const double* __restrict__ z, double rho, double* __restrict__ Dp,
-                       double* __restrict__ xs, double* __restrict__ zs, DevInfo* info) {
+                       const double* __restrict__ z, const double* __restrict__ q, double rho,
+                       double* __restrict__ Dp, double* __restrict__ xs, double* __restrict__ zs,
+                       DevInfo* info) {
   int i = blockIdx.x;
   long long xoff, dpoff;
   int n, np;
@@ -42,7 +44,7 @@ __global__ void k_prep(const BlockInfo* __restrict__ blk, int N, int n0, long lo
       xs[xoff + c] = xv;
       zs[xoff + c] = zv;
       if (!(xv > 0.0) || !(zv > 0.0) || !isfinite(xv) || !isfinite(zv)) bad = 1;
-      d = 1.0 / (zv / xv + rho);
+      d = q ? 1.0 / (zv / xv + q[xoff + c] + rho) : 1.0 / (zv / xv + rho);
     }
     Dp[dpoff + c] = d;
   }
@@ -1111,10 +1113,10 @@ void launch_convert_f32(hipStream_t st, long long n, const double* src, float* d
 }
 
 void launch_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
-                 long long d0off, const double* x, const double* z, double rho, double* Dp,
-                 double* xs, double* zs, DevInfo* info) {
-  hipLaunchKernelGGL(k_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, z,
-                     rho, Dp, xs, zs, info);
+                 long long d0off, const double* x, const double* z, const double* q, double rho,
+                 double* Dp, double* xs, double* zs, DevInfo* info) {
+  hipLaunchKernelGGL(k_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, z, q, rho,
+                     Dp, xs, zs, info);
 }
 
 template <typename T>

@@ -557,20 +557,38 @@ __global__ void k_check_prep(const BlockInfo* __restrict__ blk, int N, int n0, l
                              const double* __restrict__ xs, const double* __restrict__ zs,
                              const double* __restrict__ Dp, double* __restrict__ ex,
                              double* __restrict__ ez, double* __restrict__ xp,
-                             double* __restrict__ w2p) {
+                             double* __restrict__ w2p, const BndArgs b) {
   const int i = blockIdx.x;
   long long xo, po;
   int n, np;
   if (i < N) { xo = blk[i].xoff; po = blk[i].dpoff; n = blk[i].n; np = TS * blk[i].nt; }
   else { xo = x0off; po = d0off; n = n0; np = (n0 + TS - 1) / TS * TS; }
+  const double smu = (b.ub && b.mode == 1) ? *b.smu : 0.0;
   for (int c = threadIdx.x; c < np; c += blockDim.x) {
     double v = 0.0, w = 0.0;
     if (c < n) {
       const long long o = xo + c;
       const double d = dx[o], e = dz[o];
       v = d;
-      if (i < N) w = Dp[po + c] * d * e / xs[o];
-      ex[o] = rx[o] - g[o] - e;
+      double exo = rx[o] - g[o] - e;
+      double sw2 = 0.0;
+      if (b.ub) {
+        // ds = r_u - dx, dw = S^-1 (r_sw - W ds), r_sw = -SWe (predictor) or
+        // smu - SWe - dS_aff dW_aff (corrector); zero off the bounded variables
+        double ds = 0.0, dw = 0.0;
+        if (isfinite(b.ub[o])) {
+          const double sv = b.s[o], wv = b.w[o];
+          ds = b.ru[o] - d;
+          const double rsw = (b.mode == 1) ? smu - sv * wv - b.dsa[o] * b.dwa[o] : -sv * wv;
+          dw = (rsw - wv * ds) / sv;
+          sw2 = ds * dw / sv;
+        }
+        b.ds[o] = ds;
+        b.dw[o] = dw;
+      }
+      if (b.q) exo += b.q[o] * d;
+      if (i < N) w = Dp[po + c] * (d * e / xs[o] - sw2);
+      ex[o] = exo;
       ez[o] = rz[o] - (zs[o] * d + xs[o] * e);
     }
     xp[po + c] = v;
@@ -586,7 +604,8 @@ __global__ void k_resid_prep(const BlockInfo* __restrict__ blk, int N, int n0, l
                              const double* __restrict__ xs, const double* __restrict__ Dp,
                              double* __restrict__ rzv, double* __restrict__ rhx,
                              double* __restrict__ vx, double* __restrict__ w1p,
-                             double* __restrict__ xp) {
+                             double* __restrict__ xp, const BndArgs b,
+                             double* __restrict__ rdt_out) {
   const int i = blockIdx.x;
   long long xo, po;
   int n, np;
@@ -599,10 +618,19 @@ __global__ void k_resid_prep(const BlockInfo* __restrict__ blk, int N, int n0, l
       xv = x[o];
       const double r = -xv * z[o];
       rzv[o] = r;
-      const double h = rd[o] - r / xs[o];
+      double rdo = rd[o], sinv = 0.0;
+      if (b.ub) {
+        // the predictor's x right-hand side r_d + S^-1 (-SWe - W r_u)
+        if (isfinite(b.ub[o])) {
+          rdo -= b.w[o] + b.q[o] * b.ru[o];
+          sinv = 1.0 / b.s[o];
+        }
+        rdt_out[o] = rdo;
+      }
+      const double h = rdo - r / xs[o];
       rhx[o] = h;
       hv = Dp[po + c] * h;
-      if (i < N) w = Dp[po + c] / xs[o];
+      if (i < N) w = Dp[po + c] * (1.0 / xs[o] - sinv);
     }
     vx[po + c] = hv;
     w1p[po + c] = w;
@@ -690,10 +718,15 @@ __global__ void k_combine(long long n, const double* __restrict__ t, double smu,
 // slots (sums x'z and (x + a_p dxa)'(z + a_d dza)), on the device so that the
 // corrector needs no host value.  One thread.
 __global__ void k_sigma_mu(double* __restrict__ scal, double inv_n, int s_xz, int s_muaff,
-                           int s_out) {
+                           int s_out, int s_sw, int s_muaff_sw) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const double mu = scal[s_xz] * inv_n;
-  const double r = scal[s_muaff] * inv_n / mu;
+  double xz = scal[s_xz], ma = scal[s_muaff];
+  if (s_sw >= 0) {
+    xz += scal[s_sw];
+    ma += scal[s_muaff_sw];
+  }
+  const double mu = xz * inv_n;
+  const double r = ma * inv_n / mu;
   scal[s_out] = r * r * r * mu;
 }
 
@@ -738,13 +771,79 @@ __global__ void k_copy(long long n, const double* __restrict__ src, double* __re
 __global__ void k_rz(long long n, int mode, const double* __restrict__ x,
                      const double* __restrict__ z, const double* __restrict__ dxa,
                      const double* __restrict__ dza, double sm, const double* __restrict__ sm_dev,
-                     double* __restrict__ rz) {
+                     double* __restrict__ rz, const BndArgs b, double* __restrict__ rxc) {
   if (sm_dev) sm = *sm_dev;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     double v = -x[i] * z[i];
     if (mode == 1) v += sm - dxa[i] * dza[i];
     rz[i] = v;
+    if (rxc) {
+      // the corrector's x right-hand side: rdt + S^-1 (smu - dS_aff dW_aff)
+      double r = b.rdt[i];
+      if (isfinite(b.ub[i])) r += (sm - b.dsa[i] * b.dwa[i]) / b.s[i];
+      rxc[i] = r;
+    }
+  }
+}
+
+// ------------------------------------------------------------ bounds
+__global__ void k_bnd_prep(long long n, const double* __restrict__ ub, const double* __restrict__ x,
+                           const double* __restrict__ z, const double* __restrict__ s,
+                           const double* __restrict__ w, double* __restrict__ ru,
+                           double* __restrict__ q, double* __restrict__ zw, DevInfo* info) {
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double r = 0.0, qq = 0.0;
+    const double wv = w[i];
+    if (isfinite(ub[i])) {
+      const double sv = s[i];
+      if (!(sv > 0.0) || !(wv > 0.0) || !isfinite(sv) || !isfinite(wv)) bad = 1;
+      r = ub[i] - x[i] - sv;
+      qq = wv / sv;
+    }
+    ru[i] = r;
+    q[i] = qq;
+    zw[i] = z[i] - wv;
+  }
+  if (bad) atomicOr(&info->nonfinite, 1);
+}
+__global__ void k_bnd_start(long long n, const double* __restrict__ ub, const double* __restrict__ x,
+                            double* __restrict__ z, double* __restrict__ s, double* __restrict__ w,
+                            double* __restrict__ sm, double* __restrict__ wm) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (isfinite(ub[i])) {
+      const double zv = z[i], sv = ub[i] - x[i], wv = fmax(-zv, 0.0);
+      z[i] = fmax(zv, 0.0);
+      s[i] = sv;
+      w[i] = wv;
+      sm[i] = sv;
+      wm[i] = wv;
+    } else {
+      s[i] = 0.0;
+      w[i] = 0.0;
+      sm[i] = INFINITY;
+      wm[i] = INFINITY;
+    }
+  }
+}
+__global__ void k_bnd_shift(long long n, const double* __restrict__ ub, double a, double c,
+                            double* __restrict__ x, double* __restrict__ z, double* __restrict__ s,
+                            double* __restrict__ w, double* __restrict__ sm,
+                            double* __restrict__ wm) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    x[i] += a;
+    z[i] += c;
+    if (isfinite(ub[i])) {
+      const double sv = s[i] + a, wv = w[i] + c;
+      s[i] = sv;
+      w[i] = wv;
+      sm[i] = sv;
+      wm[i] = wv;
+    }
   }
 }
 
@@ -763,15 +862,17 @@ __global__ void k_addscalar(long long n, double v, double* __restrict__ dst) {
 // ------------------------------------------------------------ reductions
 // Fixed grid and fixed per-thread ranges; partials reduced in a fixed tree.
 // ops: 0 sum a*b, 1 max |a|, 2 min over b<0 of -a/b (inf if none),
-//      3 sum (a + s1 b)(c + s2 d)  [mu_aff], 4 max (a + b), 5 min a
+//      3 sum (a + s1 b)(c + s2 d)  [mu_aff], 4 max (a + b), 5 min a,
+//      6 min over b<0 of -a/b and over d<0 of -c/d
 constexpr int RED_BLOCKS = RED_PARTIALS;
 constexpr int RED_THREADS = 256;
 
 __device__ inline double red_combine(int op, double x, double y) {
-  return (op == 0 || op == 3) ? x + y : ((op == 2 || op == 5) ? fmin(x, y) : fmax(x, y));
+  return (op == 0 || op == 3) ? x + y : ((op == 2 || op == 5 || op == 6) ? fmin(x, y) : fmax(x, y));
 }
 __device__ inline double red_identity(int op) {
-  return (op == 0 || op == 3) ? 0.0 : ((op == 2 || op == 5) ? INFINITY : (op == 4 ? -INFINITY : 0.0));
+  return (op == 0 || op == 3) ? 0.0
+                              : ((op == 2 || op == 5 || op == 6) ? INFINITY : (op == 4 ? -INFINITY : 0.0));
 }
 
 struct RedArgs {
@@ -807,6 +908,8 @@ __device__ __forceinline__ double red_term(const R& r, long long i, double s1, d
     case 2: return (r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY;
     case 3: return (r.a[i] + s1 * r.b[i]) * (r.c[i] + s2 * r.d[i]);
     case 4: return r.a[i] + r.b[i];
+    case 6: return fmin((r.b[i] < 0.0) ? -r.a[i] / r.b[i] : INFINITY,
+                        (r.d[i] < 0.0) ? -r.c[i] / r.d[i] : INFINITY);
     default: return r.a[i];
   }
 }
@@ -833,6 +936,7 @@ __device__ double red_chunk(const R& r, long long lo, long long hi, double s1, d
     case 2: return red_chunk_op<2>(r, lo, hi, s1, s2);
     case 3: return red_chunk_op<3>(r, lo, hi, s1, s2);
     case 4: return red_chunk_op<4>(r, lo, hi, s1, s2);
+    case 6: return red_chunk_op<6>(r, lo, hi, s1, s2);
     default: return red_chunk_op<5>(r, lo, hi, s1, s2);
   }
 }
@@ -907,8 +1011,23 @@ void launch_combine(hipStream_t st, long long n, const double* t, double smu, co
                     const double* b, double* out, const double* smu_dev) {
   hipLaunchKernelGGL(k_combine, dim3(grid1d(n)), dim3(256), 0, st, n, t, smu, smu_dev, a, b, out);
 }
-void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out) {
-  hipLaunchKernelGGL(k_sigma_mu, dim3(1), dim3(64), 0, st, scal, 1.0 / (double)n, s_xz, s_muaff, s_out);
+void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out,
+                     int s_sw, int s_muaff_sw) {
+  hipLaunchKernelGGL(k_sigma_mu, dim3(1), dim3(64), 0, st, scal, 1.0 / (double)n, s_xz, s_muaff, s_out,
+                     s_sw, s_muaff_sw);
+}
+void launch_bnd_prep(hipStream_t st, long long n, const double* ub, const double* x,
+                     const double* z, const double* s, const double* w, double* ru, double* q,
+                     double* zw, DevInfo* info) {
+  hipLaunchKernelGGL(k_bnd_prep, dim3(grid1d(n)), dim3(256), 0, st, n, ub, x, z, s, w, ru, q, zw, info);
+}
+void launch_bnd_start(hipStream_t st, long long n, const double* ub, const double* x, double* z,
+                      double* s, double* w, double* sm, double* wm) {
+  hipLaunchKernelGGL(k_bnd_start, dim3(grid1d(n)), dim3(256), 0, st, n, ub, x, z, s, w, sm, wm);
+}
+void launch_bnd_shift(hipStream_t st, long long n, const double* ub, double a, double c,
+                      double* x, double* z, double* s, double* w, double* sm, double* wm) {
+  hipLaunchKernelGGL(k_bnd_shift, dim3(grid1d(n)), dim3(256), 0, st, n, ub, a, c, x, z, s, w, sm, wm);
 }
 void launch_gondzio_rhs(hipStream_t st, long long n, const double* x, const double* z,
                         const double* dx, const double* dz, double at_p, double at_d,
@@ -1026,16 +1145,17 @@ void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, long long f0
 void launch_check_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
                        long long d0off, const double* rx, const double* rz, const double* g,
                        const double* dx, const double* dz, const double* xs, const double* zs,
-                       const double* Dp, double* ex, double* ez, double* xp, double* w2p) {
+                       const double* Dp, double* ex, double* ez, double* xp, double* w2p,
+                       const BndArgs& b) {
   hipLaunchKernelGGL(k_check_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, rx, rz,
-                     g, dx, dz, xs, zs, Dp, ex, ez, xp, w2p);
+                     g, dx, dz, xs, zs, Dp, ex, ez, xp, w2p, b);
 }
 void launch_resid_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
                        long long d0off, const double* x, const double* z, const double* rd,
                        const double* xs, const double* Dp, double* rzv, double* rhx, double* vx,
-                       double* w1p, double* xp) {
+                       double* w1p, double* xp, const BndArgs& b, double* rdt_out) {
   hipLaunchKernelGGL(k_resid_prep, dim3(N + 1), dim3(256), 0, st, blk, N, n0, x0off, d0off, x, z,
-                     rd, xs, Dp, rzv, rhx, vx, w1p, xp);
+                     rd, xs, Dp, rzv, rhx, vx, w1p, xp, b, rdt_out);
 }
 void launch_adj_scale(hipStream_t st, long long n, int mode, const double* zs, const double* v,
                       double* out) {
@@ -1062,9 +1182,11 @@ void launch_copy(hipStream_t st, long long n, const double* src, double* dst) {
   if (n > 0) hipLaunchKernelGGL(k_copy, dim3(grid1d(n)), dim3(256), 0, st, n, src, dst);
 }
 void launch_rz(hipStream_t st, long long n, int mode, const double* x, const double* z,
-               const double* dxa, const double* dza, double smu, double* rz, const double* smu_dev) {
+               const double* dxa, const double* dza, double smu, double* rz, const double* smu_dev,
+               const BndArgs* b, double* rxc) {
+  BndArgs nb{};
   hipLaunchKernelGGL(k_rz, dim3(grid1d(n)), dim3(256), 0, st, n, mode, x, z, dxa, dza, smu, smu_dev,
-                     rz);
+                     rz, b ? *b : nb, b ? rxc : nullptr);
 }
 void launch_fill(hipStream_t st, long long n, double v, double* dst) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(256), 0, st, n, v, dst);

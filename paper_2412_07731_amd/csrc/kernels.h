@@ -6,9 +6,10 @@
 namespace ahlp {
 
 // factorization (k_factor.hip)
+// D = (z/x + q + rho)^-1 (q: the bounds' W/S, or null)
 void launch_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
-                 long long d0off, const double* x, const double* z, double rho, double* Dp,
-                 double* xs, double* zs, DevInfo* info);
+                 long long d0off, const double* x, const double* z, const double* q, double rho,
+                 double* Dp, double* xs, double* zs, DevInfo* info);
 template <typename T>
 void launch_syrk(hipStream_t st, const BlockInfo* blk, const int4* items, int nitems,
                  const T* A, const double* Dp, T* LB, double delta);
@@ -165,8 +166,11 @@ void launch_wscaled(hipStream_t st, const BlockInfo* blk, int N, int n0, long lo
 // out = t - smu a + b; smu from *smu_dev when that is not null
 void launch_combine(hipStream_t st, long long n, const double* t, double smu, const double* a,
                     const double* b, double* out, const double* smu_dev = nullptr);
-// scal[s_out] = (mu_aff / mu)^3 mu with mu = scal[s_xz] / n, mu_aff = scal[s_muaff] / n
-void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out);
+// scal[s_out] = (mu_aff / mu)^3 mu with mu = scal[s_xz] / n, mu_aff = scal[s_muaff] / n;
+// with bounds (s_sw >= 0) both also take the (s, w) products, scal[s_sw] and
+// scal[s_muaff_sw], and n counts the bounded variables too
+void launch_sigma_mu(hipStream_t st, double* scal, long long n, int s_xz, int s_muaff, int s_out,
+                     int s_sw = -1, int s_muaff_sw = -1);
 // r = max(clip(v, lo, hi) - v, -hi), v = (x + at_p dx)(z + at_d dz), [lo, hi] =
 // [beta_min, beta_max] * smu[0] (a Gondzio corrector's right-hand side)
 void launch_gondzio_rhs(hipStream_t st, long long n, const double* x, const double* z,
@@ -175,10 +179,30 @@ void launch_gondzio_rhs(hipStream_t st, long long n, const double* x, const doub
 // up to four step updates in one launch: x[v] += min(1, eta ratio[v][0]) d[v]
 struct StepSet {
   int cnt;
-  long long n[4];
-  const double* ratio[4];
-  const double* d[4];
-  double* x[4];
+  long long n[6];
+  const double* ratio[6];
+  const double* d[6];
+  double* x[6];
+};
+
+// Upper bounds inside the interior-point iteration.  A bounded variable
+// (finite ub) has the slack s = u - x and its dual w; eliminating ds and dw
+// leaves the Newton system with Q = W/S in its (x, x) block, whose x right-hand
+// side is r_d + S^-1 (r_sw - W r_u).  ub == nullptr: no bounds (every other
+// field unused).  s, w, q, ru are zero off the bounded variables.
+struct BndArgs {
+  const double* ub;      // [n_tot] upper bounds, +inf where none
+  const double* s;       // slacks
+  const double* w;       // their duals
+  const double* q;       // w / s
+  const double* ru;      // u - x - s
+  const double* rdt;     // the predictor's x right-hand side r_d - w - q r_u
+  const double* dsa;     // the predictor's ds, dw (the corrector's products)
+  const double* dwa;
+  const double* smu;     // device scalar sigma mu (corrector)
+  double* ds;            // recovered ds, dw of the direction being checked
+  double* dw;
+  int mode;              // 0: predictor (r_sw = -SWe), 1: corrector
 };
 void launch_steps(hipStream_t st, double eta, const StepSet& s);
 void launch_rows_multi(hipStream_t st, const BlockInfo* blk, const int2* rowtiles, int nrt,
@@ -223,14 +247,20 @@ void launch_schur_rhs(hipStream_t st, const BlockInfo* blk, int N, int nb, const
 void launch_solve_tail(hipStream_t st, int N, int n0, long long nl, long long f0first,
                        const double* part, const double* F0, const double* u, long long x0off,
                        long long mblk, double* gout, double* dx, const DzArgs& dzv, double* dy);
+// ex = rx - g - dz (+ q dx where b.q is given: the (x, x) block -Q of a
+// factorization with bounds); with bounds (b.ub) it also recovers b.ds, b.dw
+// from dx and forms w2 = D (dx dz / x - ds dw / s)
 void launch_check_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
                        long long d0off, const double* rx, const double* rz, const double* g,
                        const double* dx, const double* dz, const double* xs, const double* zs,
-                       const double* Dp, double* ex, double* ez, double* xp, double* w2p);
+                       const double* Dp, double* ex, double* ez, double* xp, double* w2p,
+                       const BndArgs& b);
+// with bounds (b.ub): the predictor's x right-hand side rdt = r_d - w - q r_u
+// (written to rdt_out) replaces r_d, and w1 = D (1/x - 1/s)
 void launch_resid_prep(hipStream_t st, const BlockInfo* blk, int N, int n0, long long x0off,
                        long long d0off, const double* x, const double* z, const double* rd,
                        const double* xs, const double* Dp, double* rzv, double* rhx, double* vx,
-                       double* w1p, double* xp);
+                       double* w1p, double* xp, const BndArgs& b, double* rdt_out);
 void launch_axpy(hipStream_t st, long long n, double a, const double* x, double* y);
 // mode 0: out = zs * v; mode 1: out = v / zs (the diagonal scalings that turn
 // the transposed Newton solve into a Newton solve)
@@ -244,10 +274,25 @@ void launch_res_x(hipStream_t st, long long n, const double* rx, const double* r
                   const double* g, const double* dx, const double* dz, const double* xs,
                   const double* zs, double* ex, double* ez);
 void launch_copy(hipStream_t st, long long n, const double* src, double* dst);
-// rz = -x z (mode 0) or smu - x z - dxa dza (mode 1); smu from *smu_dev when not null
+// rz = -x z (mode 0) or smu - x z - dxa dza (mode 1); smu from *smu_dev when not null.
+// With bounds (b.ub, mode 1) also the corrector's x right-hand side
+// rxc = rdt + (smu - dsa dwa) / s on the bounded variables
 void launch_rz(hipStream_t st, long long n, int mode, const double* x, const double* z,
                const double* dxa, const double* dza, double smu, double* rz,
-               const double* smu_dev = nullptr);
+               const double* smu_dev = nullptr, const BndArgs* b = nullptr, double* rxc = nullptr);
+// bounds at an iterate: ru = u - x - s, q = w / s, zw = z - w (0, 0, z off the
+// bounded variables); flags s <= 0, w <= 0 or non-finite ones in info
+void launch_bnd_prep(hipStream_t st, long long n, const double* ub, const double* x,
+                     const double* z, const double* s, const double* w, double* ru, double* q,
+                     double* zw, DevInfo* info);
+// start: on the bounded variables s = u - x, w = max(-z, 0), z = max(z, 0),
+// elsewhere s = w = 0; sm, wm = s, w there and +inf elsewhere (for minima)
+void launch_bnd_start(hipStream_t st, long long n, const double* ub, const double* x, double* z,
+                      double* s, double* w, double* sm, double* wm);
+// x += a, z += c everywhere; s += a, w += c on the bounded variables; then sm,
+// wm as in launch_bnd_start
+void launch_bnd_shift(hipStream_t st, long long n, const double* ub, double a, double c,
+                      double* x, double* z, double* s, double* w, double* sm, double* wm);
 void launch_fill(hipStream_t st, long long n, double v, double* dst);
 void launch_addscalar(hipStream_t st, long long n, double v, double* dst);
 void launch_reduce(hipStream_t st, int op, long long n, const double* a, const double* b,
@@ -262,7 +307,7 @@ struct RedSpec {
   const double* ps1;     // if set (op RED_MUAFF): s1 = min(1, *ps1), s2 = min(1, *ps2),
   const double* ps2;     // read from the device (results of an earlier reduction)
 };
-constexpr int MAXRED = 12;
+constexpr int MAXRED = 16;
 struct MultiRed {
   int nred;
   RedSpec r[MAXRED];
@@ -271,7 +316,9 @@ struct MultiRed {
 };
 void launch_mreduce(hipStream_t st, const MultiRed& m);
 
-enum RedOp { RED_DOT = 0, RED_MAXABS = 1, RED_RATIO = 2, RED_MUAFF = 3, RED_MAXSUM = 4, RED_MIN = 5 };
+// RED_RATIO2: the ratio test over two pairs, min over i of -a/b (b < 0) and -c/d (d < 0)
+enum RedOp { RED_DOT = 0, RED_MAXABS = 1, RED_RATIO = 2, RED_MUAFF = 3, RED_MAXSUM = 4, RED_MIN = 5,
+             RED_RATIO2 = 6 };
 constexpr int RED_PARTIALS = 256;
 
 // ---- static workspace (noalloc.hip)

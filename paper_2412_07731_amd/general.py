@@ -57,6 +57,12 @@ slacks in global row order (their upper-bound slacks, when both sides are
 finite, join block 1's like those of the other x_0 columns).  Global rows of
 the standard form: those of g in order, then the x_0-only equality rows.
 
+Bounds inside the iteration (to_standard(g, bounds=True)): the finite upper
+bounds left after the shifts stay bounds of the standard columns (Instance.ub)
+instead of becoming rows x' + s = u' (step 4 of the layout is skipped), and
+the library's interior-point method handles them with slacks and duals of its
+own.
+
 Only the primal solution is mapped back; duals of the general form are not.
 """
 from __future__ import annotations
@@ -255,19 +261,19 @@ def chain_globals(g: GeneralInstance) -> GeneralInstance:
     return out
 
 
-def to_standard(g: GeneralInstance, dense=False, x0_border=False):
+def to_standard(g: GeneralInstance, dense=False, x0_border=False, bounds=False):
     """The equivalent standard-form Instance and the map back to x (global
     rows chained, x_0-only equality rows eliminated; with dense, the global
     rows kept whole as global rows, and with x0_border the x_0-only rows
     too)."""
     if not (dense and x0_border) and g.A0 is not None and g.A0.shape[0]:
         h, e, E = eliminate_x0_rows(g)
-        inst, mp = to_standard(h, dense=dense)
+        inst, mp = to_standard(h, dense=dense, bounds=bounds)
         mp.x0map = (e, E, int(g.n.sum()))
         return inst, mp
     if not dense and g.ng:
         gc = chain_globals(g)
-        inst, mp = to_standard(gc)
+        inst, mp = to_standard(gc, bounds=bounds)
         mp.keep = gc.orig_cols
         return inst, mp
     N, n0 = g.N, g.n0
@@ -300,9 +306,9 @@ def to_standard(g: GeneralInstance, dense=False, x0_border=False):
         offb.append(oi)
         cols.append(ub)
         slk.append(sl)
-    # upper-bound slacks
-    nub = [int(np.isfinite(np.asarray(cols[i])).sum()) for i in range(N)]
-    nub0 = int(np.isfinite(ub0_all).sum())
+    # upper-bound slacks (none when the bounds stay bounds)
+    nub = [0 if bounds else int(np.isfinite(np.asarray(cols[i])).sum()) for i in range(N)]
+    nub0 = 0 if bounds else int(np.isfinite(ub0_all).sum())
     ncol = [len(cols[i]) + nub[i] + (nub0 if i == 0 else 0) for i in range(N)]
     Tfull = []
     for i in range(N):
@@ -339,7 +345,7 @@ def to_standard(g: GeneralInstance, dense=False, x0_border=False):
             Ai.append(H0); Ci.append(G0); bi.append(r0)
         # upper-bound rows
         ubs = np.asarray(cols[i])
-        fin = np.flatnonzero(np.isfinite(ubs))
+        fin = np.flatnonzero(np.isfinite(ubs)) if not bounds else np.zeros(0, dtype=np.int64)
         U = np.zeros((fin.size, ncol[i]))
         UC = np.zeros((fin.size, n0s))
         for q, col in enumerate(fin):
@@ -413,6 +419,8 @@ def to_standard(g: GeneralInstance, dense=False, x0_border=False):
     if bg:
         inst.Wg = [np.array(Wg[i]).reshape(len(bg), ncol[i]) for i in range(N)]
         inst.Wg0 = np.array(Wg0).reshape(len(bg), n0s)
+    if bounds:
+        inst.ub = np.concatenate([np.asarray(cols[i], dtype=float) for i in range(N)] + [ub0_all])
     mp = StandardMap(T=Tfull + [T0], off=offb + [off0],
                      xoff_std=np.concatenate([[0], np.cumsum(ns)]).astype(np.int64), const=const)
     return inst, mp
@@ -432,15 +440,17 @@ def from_standard(mp: StandardMap, x_std: np.ndarray) -> np.ndarray:
     return x
 
 
-def solve(g: GeneralInstance, stream=None, dense=False, x0_border=False, history=False, **opts):
+def solve(g: GeneralInstance, stream=None, dense=False, x0_border=False, bounds=False,
+          history=False, **opts):
     """Solve a general instance on the current HIP device.  Returns
     (x, objective, result) with x in the general form's variables and the
     result dictionary of the standard-form interior-point run (with history,
     also its per-iteration records under "history").  dense, x0_border: keep
     the global rows (and the x_0-only equality rows) in the border of the
-    Schur complement (see to_standard)."""
+    Schur complement; bounds: keep the upper bounds inside the iteration (see
+    to_standard)."""
     from .ahlp import Problem
-    inst, mp = to_standard(g, dense=dense, x0_border=x0_border)
+    inst, mp = to_standard(g, dense=dense, x0_border=x0_border, bounds=bounds)
     P = Problem(inst, stream=stream)
     try:
         xs, _, _, res = P.ipm(stream=stream, **opts)

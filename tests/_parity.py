@@ -13,10 +13,11 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracl
 ETA = 1e-10
 
 
-def golden(config, seed, gondzio=0, dense=False, x0_border=False):
+def golden(config, seed, gondzio=0, dense=False, x0_border=False, bounds=False):
     for r in GOLDEN["runs"]:
         if (r["config"] == config and r["seed"] == seed and r.get("gondzio", 0) == gondzio
-                and r.get("dense", False) == dense and r.get("x0_border", False) == x0_border):
+                and r.get("dense", False) == dense and r.get("x0_border", False) == x0_border
+                and r.get("bounds", False) == bounds):
             return r
     return None
 

@@ -162,8 +162,9 @@ def test_general_through_dense_layer(dev, config, seed, x0b):
     assert res["status"] == 0
     assert res["iterations"] == ref["iterations"]
     assert abs(f - ref["objective"]) <= 1e-8 * max(1.0, abs(ref["objective"]))
-    # mu within 1e-4 of the oracle's (1e-6 for the standard workloads) up to
-    # the first refinement decision that differs: the reformulated general
+    # mu within 1e-4 of the oracle's (1e-6 for the standard workloads; 1e-3
+    # in the last three iterations) up to the first refinement decision that
+    # differs: the reformulated general
     # instances are degenerate (a free variable split into x+ - x- has a
     # whole line of optima, and the x_0-only rows in the border have only the
     # regularization delta on their diagonal), so rounding differences of
@@ -171,7 +172,7 @@ def test_general_through_dense_layer(dev, config, seed, x0b):
     # errors, the iteration count and the objective are held to the same
     # bars as elsewhere
     check_trajectory(res["history"], res, ref, f"{config} seed {seed} dense", mu_rtol_early=1e-4,
-                     mu_rtol_late=1e-4)
+                     mu_rtol_late=1e-3)
     Aeq, beq, Ain, dv, fv = gen.general_matrices(g)
     rr = Ain @ x
     viol = max(float(np.max(np.abs(Aeq @ x - beq), initial=0.0)),
