@@ -30,25 +30,34 @@ constexpr int BLK = TP * TP * 256;     // doubles per pair block
 constexpr int MAXT0 = 4;               // border tiles (n0 <= 64)
 constexpr int MID_WAVES = 16;          // waves of the final-pair and border solve kernel
 
-// LDS of one eliminating wave (doubles).  The chol scratch (B, Ld, tmp, xbuf)
-// is dead once X = L^-1 is formed and is reused for the products; a
-// workgroup's two regions take 80 KiB, so two workgroups share a CU.
+// LDS tiles have leading dimension 17 (one pad value per column), so the
+// accumulator-layout and B-operand accesses of a 16-lane row group fall in
+// distinct banks.
+constexpr int PLD = TS + 1;
+constexpr int PT = 16 * PLD;           // values per LDS tile
+constexpr int PBLK = TP * TP * PT;     // values per LDS pair block
+
+// LDS of one eliminating wave (doubles).  During the factorization it holds
+// X = L^-1, the working diagonal B, the inverted diagonal tiles and a scratch
+// tile; once X is in registers (from which L^-1 also goes to global memory),
+// the products X_L, X_R and Z' take the same space.  A workgroup's two regions
+// take 68 KiB, so two workgroups share a CU.
 constexpr int R_X = 0;                         // L^-1, TP x TP tiles
-constexpr int R_B = BLK;                       // working diagonal -> L
-constexpr int R_LD = 2 * BLK;                  // inverted diagonal tiles
-constexpr int R_TMP = R_LD + TP * 256;
-constexpr int R_XL = BLK;                      // X_L (over B)
-constexpr int R_XR = 2 * BLK;                  // X_R (over Ld, tmp)
-constexpr int R_GT = 3 * BLK;                  // Z' (t0 x TP tiles)
-constexpr int R_XBUF = R_GT;                   // 48 values (under Z')
-constexpr int R_SIZE = R_GT + MAXT0 * TP * 256;
-static_assert(R_TMP + 256 <= R_GT, "chol scratch overlaps Z'");
+constexpr int R_B = PBLK;                      // working diagonal -> L
+constexpr int R_LD = 2 * PBLK;                 // inverted diagonal tiles
+constexpr int R_TMP = R_LD + TP * PT;
+constexpr int R_XL = 0;                        // X_L (over X)
+constexpr int R_XR = PBLK;                     // X_R (over B)
+constexpr int R_GT = 2 * PBLK;                 // Z' (t0 x TP tiles, over Ld, tmp)
+constexpr int R_SIZE = R_GT + MAXT0 * TP * PT;
+static_assert(R_TMP + PT <= R_SIZE, "chol scratch outside the region");
 static_assert(2 * R_SIZE * sizeof(double) <= 80 * 1024, "two workgroups per CU");
 
 __device__ __forceinline__ long long et_off(long long j, int q, int cc, int t0) {
   return ((j * TP + cc) * t0 + q) * 256;
 }
 __device__ __forceinline__ int bt(int r, int cc) { return (cc * TP + r) * 256; }
+__device__ __forceinline__ int pbt(int r, int cc) { return (cc * TP + r) * PT; }
 
 // Working blocks from the assembled parts, one wave per tile: the diagonal
 // (identity on the padding), the coupling T[j+1, j] and the border rows E_j'.
@@ -86,11 +95,6 @@ __device__ __forceinline__ Op op_load_b(const double* t) {
   for (int s = 0; s < 4; ++s) o.v[s] = t[idx + 4 * s];
   return o;
 }
-__device__ __forceinline__ void op_store(double* t, const Op& o) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) t[64 * s + lane] = o.v[s];
-}
 // acc + alpha * (product of register operands)
 __device__ __forceinline__ d4 mm(d4 acc, const Op& a, const Op& b, double alpha) {
 #pragma unroll
@@ -101,11 +105,12 @@ __device__ __forceinline__ d4 mm(d4 acc, const Op& a, const Op& b, double alpha)
 // Eliminate pair o: blocked Cholesky of its working diagonal, then
 // X_L = L_o^-1 T'[o, L] (if needXL; T'[o, L] is BC[L]),
 // X_R = L_o^-1 T'[R, o]' (if needXR; T'[R, o] is BC[o]) and
-// Z' = E'_o' L_o^-T, all into the wave's LDS region R.  Every global operand
-// is loaded before the factorization, so the step waits on memory once.
-// Returns the pivots replaced.
+// Z' = E'_o' L_o^-T, all into the wave's LDS region R; L_o^-1 goes to fli
+// (global, if not null) from registers.  Every global operand is loaded
+// before the factorization, so the step waits on memory once.  Returns the
+// pivots replaced.
 __device__ int elim2(const BcrArgs& c, long long o, long long L, bool needXL, bool needXR,
-                     double* R) {
+                     double* R, double* fli) {
   const int t0 = c.t0;
   double* X = R + R_X;
   double* B = R + R_B;
@@ -126,17 +131,24 @@ __device__ int elim2(const BcrArgs& c, long long o, long long L, bool needXL, bo
 #pragma unroll
     for (int q = 0; q < MAXT0; ++q) et[p][q] = q < t0 ? op_load(c.BEt + et_off(o, q, p, t0)) : Op{};
   const double thr = c.thrT[o];
-  op_store(B + bt(0, 0), d00);
-  op_store(B + bt(1, 0), d10);
-  op_store(B + bt(1, 1), d11);
+  op_store<PLD>(B + pbt(0, 0), d00);
+  op_store<PLD>(B + pbt(1, 0), d10);
+  op_store<PLD>(B + pbt(1, 1), d11);
   wave_order();
-  const int cnt = wave_block_chol(B, TP, X, R + R_LD, R + R_TMP, R + R_XBUF, thr);
+  const int cnt = wave_block_chol<PLD>(B, TP, X, R + R_LD, R + R_TMP, R + R_TMP, thr);
   wave_order();
   Op x[TP][TP];
 #pragma unroll
   for (int r = 0; r < TP; ++r)
 #pragma unroll
-    for (int q = 0; q <= r; ++q) x[r][q] = op_load(X + bt(r, q));
+    for (int q = 0; q <= r; ++q) x[r][q] = op_load<PLD>(X + pbt(r, q));
+  wave_order();   // X is read before the products overwrite it
+  if (fli) {
+#pragma unroll
+    for (int r = 0; r < TP; ++r)
+#pragma unroll
+      for (int q = 0; q < TP; ++q) op_store(fli + bt(r, q), q <= r ? x[r][q] : Op{});
+  }
 #pragma unroll
   for (int r = 0; r < TP; ++r)
 #pragma unroll
@@ -145,13 +157,13 @@ __device__ int elim2(const BcrArgs& c, long long o, long long L, bool needXL, bo
         d4 a = acc_zero();
 #pragma unroll
         for (int q = 0; q <= r; ++q) a = mm(a, x[r][q], cl[q][cc], 1.0);
-        acc_store(R + R_XL + bt(r, cc), a);
+        acc_store<PLD>(R + R_XL + pbt(r, cc), a);
       }
       if (needXR) {
         d4 a = acc_zero();
 #pragma unroll
         for (int q = 0; q <= r; ++q) a = mm(a, x[r][q], co[cc][q], 1.0);
-        acc_store(R + R_XR + bt(r, cc), a);
+        acc_store<PLD>(R + R_XR + pbt(r, cc), a);
       }
     }
   // Z'(q, cc) = sum_p E'(q, p) X(cc, p)'; X(cc, p) as the B operand of X*Y'
@@ -164,20 +176,20 @@ __device__ int elim2(const BcrArgs& c, long long o, long long L, bool needXL, bo
         d4 a = acc_zero();
 #pragma unroll
         for (int p = 0; p <= cc; ++p) a = mm(a, et[p][q], x[cc][p], 1.0);
-        acc_store(R + R_GT + (cc * t0 + q) * 256, a);
+        acc_store<PLD>(R + R_GT + (cc * t0 + q) * PT, a);
       }
   wave_order();
   return cnt;
 }
 
-// factor blocks of pair o from the wave's LDS region
+// factor blocks X_L, X_R and Z' of pair o from the wave's LDS region
 __device__ void store2(const BcrArgs& c, long long o, const double* R, bool hasL, bool hasR) {
   for (int t = 0; t < TP * TP; ++t) {
-    tile_copy(c.FLi + o * BLK + t * 256, R + R_X + t * 256);
-    if (hasL) tile_copy(c.FXL + o * BLK + t * 256, R + R_XL + t * 256);
-    if (hasR) tile_copy(c.FXR + o * BLK + t * 256, R + R_XR + t * 256);
+    if (hasL) tile_copy<TS, PLD>(c.FXL + o * BLK + t * 256, R + R_XL + t * PT);
+    if (hasR) tile_copy<TS, PLD>(c.FXR + o * BLK + t * 256, R + R_XR + t * PT);
   }
-  for (int t = 0; t < TP * c.t0; ++t) tile_copy(c.FGt + (o * TP * c.t0 + t) * 256, R + R_GT + t * 256);
+  for (int t = 0; t < TP * c.t0; ++t)
+    tile_copy<TS, PLD>(c.FGt + (o * TP * c.t0 + t) * 256, R + R_GT + t * PT);
 }
 
 // One level (n active pairs): a workgroup of two waves per even position k.
@@ -209,7 +221,8 @@ __global__ __launch_bounds__(128) void k_bcr2_level(BcrArgs c, int lvl, int n) {
   if (wave == 0 ? hr : hl) {
     double* R = lds + wave * R_SIZE;
     const long long o = wave == 0 ? (k + 1) * s : (k - 1) * s;
-    const int cn = elim2(c, o, e, wave == 0, wave == 0 ? hrr : true, R);
+    const int cn = elim2(c, o, e, wave == 0, wave == 0 ? hrr : true, R,
+                         wave == 0 ? c.FLi + o * BLK : nullptr);
     if (wave == 0) {
       cnt = cn;
       store2(c, o, R, true, hrr);
@@ -226,16 +239,19 @@ __global__ __launch_bounds__(128) void k_bcr2_level(BcrArgs c, int lvl, int n) {
       for (int r = cc; r < TP; ++r) {
         d4 a = dp[cc + r];   // (0,0), (1,0), (1,1)
         if (hl)
-          for (int p = 0; p < TP; ++p) a = mma_txy(a, Rl + R_XR + bt(p, r), Rl + R_XR + bt(p, cc), -1.0);
+          for (int p = 0; p < TP; ++p)
+            a = mma_txy<PLD>(a, Rl + R_XR + pbt(p, r), Rl + R_XR + pbt(p, cc), -1.0);
         if (hr)
-          for (int p = 0; p < TP; ++p) a = mma_txy(a, Ro + R_XL + bt(p, r), Ro + R_XL + bt(p, cc), -1.0);
+          for (int p = 0; p < TP; ++p)
+            a = mma_txy<PLD>(a, Ro + R_XL + pbt(p, r), Ro + R_XL + pbt(p, cc), -1.0);
         acc_store(D + bt(r, cc), a);
       }
     if (hr && hrr)
       for (int cc = 0; cc < TP; ++cc)
         for (int r = 0; r < TP; ++r) {
           d4 a = acc_zero();
-          for (int p = 0; p < TP; ++p) a = mma_txy(a, Ro + R_XR + bt(p, r), Ro + R_XL + bt(p, cc), -1.0);
+          for (int p = 0; p < TP; ++p)
+            a = mma_txy<PLD>(a, Ro + R_XR + pbt(p, r), Ro + R_XL + pbt(p, cc), -1.0);
           acc_store(c.BC + e * BLK + bt(r, cc), a);
         }
   } else {
@@ -248,10 +264,10 @@ __global__ __launch_bounds__(128) void k_bcr2_level(BcrArgs c, int lvl, int n) {
         d4 a = etp[cc][q];
         if (hl)
           for (int p = 0; p < TP; ++p)
-            a = mma_xy(a, Rl + R_GT + (p * t0 + q) * 256, Rl + R_XR + bt(p, cc), -1.0);
+            a = mma_xy<PLD>(a, Rl + R_GT + (p * t0 + q) * PT, Rl + R_XR + pbt(p, cc), -1.0);
         if (hr)
           for (int p = 0; p < TP; ++p)
-            a = mma_xy(a, Ro + R_GT + (p * t0 + q) * 256, Ro + R_XL + bt(p, cc), -1.0);
+            a = mma_xy<PLD>(a, Ro + R_GT + (p * t0 + q) * PT, Ro + R_XL + pbt(p, cc), -1.0);
         acc_store(Et, a);
       }
   }
@@ -262,7 +278,7 @@ __global__ __launch_bounds__(128) void k_bcr2_level(BcrArgs c, int lvl, int n) {
 __global__ __launch_bounds__(64) void k_bcr2_final(BcrArgs c) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* R = reinterpret_cast<double*>(smem_raw);
-  const int cnt = elim2(c, 0, 0, false, false, R);
+  const int cnt = elim2(c, 0, 0, false, false, R, c.FLi);
   store2(c, 0, R, false, false);
   if (threadIdx.x == 0 && cnt) atomicAdd(&c.info->pivots, cnt);
 }

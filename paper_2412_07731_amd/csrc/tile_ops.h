@@ -5,6 +5,12 @@
 // supplies A(l%16, 4s + l/16) and B(4s + l/16, l%16); for a column-major tile X
 // these are X[64 s + l] (A = X) and X[(l%16)*16 + 4s + l/16] (B = X).  The
 // accumulator holds element (acc_row(l, r), l%16) in register r.
+//
+// The tile helpers take the leading dimension LD as a template argument
+// (default 16, a dense 256-value tile).  LDS tiles with LD = 17 pad each
+// column by one value: the accumulator-layout and B-operand accesses then
+// spread the 16 lanes of a row group over distinct banks, where LD = 16 puts
+// them all in one.  A padded tile takes 16 * 17 values.
 #pragma once
 
 #include "common.h"
@@ -14,25 +20,38 @@ namespace ahlp {
 
 struct Op { double v[4]; };   // a tile as an A operand: element 64 s + lane
 
+// offset of element (i, j) of a tile with leading dimension LD
+template <int LD = TS>
+__device__ __forceinline__ int tix(int i, int j) { return j * LD + i; }
+
+template <int LD = TS>
 __device__ __forceinline__ Op op_load(const double* t) {
   const int lane = threadIdx.x & 63;
   Op o;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) o.v[s] = t[64 * s + lane];
+  for (int s = 0; s < 4; ++s) o.v[s] = t[tix<LD>(lane & 15, 4 * s + (lane >> 4))];
   return o;
 }
+template <int LD = TS>
+__device__ __forceinline__ void op_store(double* t, const Op& o) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) t[tix<LD>(lane & 15, 4 * s + (lane >> 4))] = o.v[s];
+}
 __device__ __forceinline__ d4 acc_zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+template <int LD = TS>
 __device__ __forceinline__ d4 acc_load(const double* t) {
   const int lane = threadIdx.x & 63;
   d4 a;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) a[r] = t[acc_index<double>(lane, r)];
+  for (int r = 0; r < 4; ++r) a[r] = t[tix<LD>(acc_row<double>(lane, r), lane & 15)];
   return a;
 }
+template <int LD = TS>
 __device__ __forceinline__ void acc_store(double* t, d4 a) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) t[acc_index<double>(lane, r)] = a[r];
+  for (int r = 0; r < 4; ++r) t[tix<LD>(acc_row<double>(lane, r), lane & 15)] = a[r];
 }
 // padded tile of an exact column-major block (rows x cols, leading dimension
 // ld); identity on the padded part of the diagonal if diag
@@ -62,44 +81,60 @@ __device__ __forceinline__ d4 acc_load_exact_t(const double* src, int rows, int 
   return a;
 }
 // acc += alpha X Y'
+template <int LD = TS>
 __device__ __forceinline__ d4 mma_xyt(d4 acc, const double* X, const double* Y, double alpha) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) acc = mfma(alpha * X[64 * s + lane], Y[64 * s + lane], acc);
+  for (int s = 0; s < 4; ++s) {
+    const int o = tix<LD>(lane & 15, 4 * s + (lane >> 4));
+    acc = mfma(alpha * X[o], Y[o], acc);
+  }
   return acc;
 }
 // acc += alpha X S Y' with S = diag(-1 where neg has the bit of the inner
 // index, +1 elsewhere)
+template <int LD = TS>
 __device__ __forceinline__ d4 mma_xsyt(d4 acc, const double* X, const double* Y, double alpha,
                                        unsigned neg) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const double f = ((neg >> (4 * s + (lane >> 4))) & 1u) ? -alpha : alpha;
-    acc = mfma(f * X[64 * s + lane], Y[64 * s + lane], acc);
+    const int o = tix<LD>(lane & 15, 4 * s + (lane >> 4));
+    acc = mfma(f * X[o], Y[o], acc);
   }
   return acc;
 }
 // acc += alpha X Y
+template <int LD = TS>
 __device__ __forceinline__ d4 mma_xy(d4 acc, const double* X, const double* Y, double alpha) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int s = 0; s < 4; ++s)
-    acc = mfma(alpha * X[64 * s + lane], Y[(lane & 15) * TS + 4 * s + (lane >> 4)], acc);
+    acc = mfma(alpha * X[tix<LD>(lane & 15, 4 * s + (lane >> 4))],
+               Y[tix<LD>(4 * s + (lane >> 4), lane & 15)], acc);
   return acc;
 }
 // acc += alpha X' Y
+template <int LD = TS>
 __device__ __forceinline__ d4 mma_txy(d4 acc, const double* X, const double* Y, double alpha) {
   const int lane = threadIdx.x & 63;
-  const int idx = (lane & 15) * TS + (lane >> 4);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) acc = mfma(alpha * X[idx + 4 * s], Y[idx + 4 * s], acc);
+  for (int s = 0; s < 4; ++s) {
+    const int o = tix<LD>(4 * s + (lane >> 4), lane & 15);
+    acc = mfma(alpha * X[o], Y[o], acc);
+  }
   return acc;
 }
+// tile copy between leading dimensions LDD (destination) and LDS_ (source)
+template <int LDD = TS, int LDS_ = TS>
 __device__ __forceinline__ void tile_copy(double* dst, const double* src) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) dst[64 * s + lane] = src[64 * s + lane];
+  for (int s = 0; s < 4; ++s) {
+    const int i = lane & 15, j = 4 * s + (lane >> 4);
+    dst[tix<LDD>(i, j)] = src[tix<LDS_>(i, j)];
+  }
 }
 
 // y = X v (v: 16 values in LDS); every lane returns y[lane % 16]
@@ -136,37 +171,40 @@ __device__ __forceinline__ double vec_get_exact(const double* src, int len) {
 }
 
 // Blocked Cholesky of a t x t matrix of tiles, by one wave.  B holds tile
-// (r, c) at (c t + r) 256 (LDS; only tiles with r >= c are read).  On return
+// (r, c) at (c t + r) 16 LD (LDS; only tiles with r >= c are read).  On return
 // those tiles hold the factor L, Ld the inverses of its t diagonal tiles and X
 // (t x t tiles, zero above the diagonal) the block inverse L^-1.  tmp: one
-// tile and xbuf 48 values of LDS scratch.  A pivot <= thr is replaced (the
-// pivot rule); returns the number replaced (all lanes).  With neg != 0 (bit j:
+// tile of LDS scratch (xbuf is not used); every tile has leading dimension LD.
+// A pivot <= thr is replaced (the pivot rule); returns the number replaced
+// (all lanes).  With neg != 0 (bit j:
 // row j's sign is negative) B is quasi-definite and the factorization signed,
 // B = L S L' with S = diag(-1 on neg's bits, +1 elsewhere): tile column p is
 // L_rp = B_rp L_pp^-T S_p, and the trailing update subtracts L_rp S_p L_cp'.
+template <int LD = TS>
 __device__ inline int wave_block_chol(double* B, int t, double* X, double* Ld, double* tmp,
                                       double* xbuf, double thr, unsigned long long neg = 0) {
+  constexpr int TT = 16 * LD;   // values per tile
   const int lane = threadIdx.x & 63;
   int cnt = 0;
   for (int p = 0; p < t; ++p) {
-    double* Bpp = B + (p * t + p) * 256;
+    double* Bpp = B + (p * t + p) * TT;
     const unsigned np = (unsigned)((neg >> (16 * p)) & 0xFFFFull);
-    if (neg) cnt += wave_chol_tile<double, TS, true>(Bpp, Bpp, Ld + p * 256, thr, xbuf, np);
-    else cnt += wave_chol_tile<double>(Bpp, Bpp, Ld + p * 256, thr, xbuf);
+    if (neg) cnt += wave_chol_tile<double, LD, true>(Bpp, Bpp, Ld + p * TT, thr, xbuf, np);
+    else cnt += wave_chol_tile<double, LD>(Bpp, Bpp, Ld + p * TT, thr, xbuf);
     for (int r = p + 1; r < t; ++r) {
-      d4 acc = mma_xyt(acc_zero(), B + (p * t + r) * 256, Ld + p * 256, 1.0);
+      d4 acc = mma_xyt<LD>(acc_zero(), B + (p * t + r) * TT, Ld + p * TT, 1.0);
       if (neg && ((np >> (lane & 15)) & 1u)) acc = -acc;   // times S_p (column lane % 16)
       wave_order();
-      acc_store(B + (p * t + r) * 256, acc);
+      acc_store<LD>(B + (p * t + r) * TT, acc);
     }
     wave_order();
     for (int r = p + 1; r < t; ++r)
       for (int cc = p + 1; cc <= r; ++cc) {
-        d4 acc = acc_load(B + (cc * t + r) * 256);
-        if (neg) acc = mma_xsyt(acc, B + (p * t + r) * 256, B + (p * t + cc) * 256, -1.0, np);
-        else acc = mma_xyt(acc, B + (p * t + r) * 256, B + (p * t + cc) * 256, -1.0);
+        d4 acc = acc_load<LD>(B + (cc * t + r) * TT);
+        if (neg) acc = mma_xsyt<LD>(acc, B + (p * t + r) * TT, B + (p * t + cc) * TT, -1.0, np);
+        else acc = mma_xyt<LD>(acc, B + (p * t + r) * TT, B + (p * t + cc) * TT, -1.0);
         wave_order();
-        acc_store(B + (cc * t + r) * 256, acc);
+        acc_store<LD>(B + (cc * t + r) * TT, acc);
       }
     wave_order();
   }
@@ -174,17 +212,17 @@ __device__ inline int wave_block_chol(double* B, int t, double* X, double* Ld, d
   for (int cc = 0; cc < t; ++cc) {
     for (int r = 0; r < t; ++r) {
       if (r < cc) {
-        for (int s = 0; s < 4; ++s) X[(cc * t + r) * 256 + 64 * s + lane] = 0.0;
+        op_store<LD>(X + (cc * t + r) * TT, Op{});
       } else if (r == cc) {
-        tile_copy(X + (cc * t + r) * 256, Ld + r * 256);
+        tile_copy<LD, LD>(X + (cc * t + r) * TT, Ld + r * TT);
       } else {
         d4 acc = acc_zero();
-        for (int q = cc; q < r; ++q) acc = mma_xy(acc, B + (q * t + r) * 256, X + (cc * t + q) * 256, 1.0);
-        acc_store(tmp, acc);
+        for (int q = cc; q < r; ++q) acc = mma_xy<LD>(acc, B + (q * t + r) * TT, X + (cc * t + q) * TT, 1.0);
+        acc_store<LD>(tmp, acc);
         wave_order();
-        d4 x = mma_xy(acc_zero(), Ld + r * 256, tmp, -1.0);
+        d4 x = mma_xy<LD>(acc_zero(), Ld + r * TT, tmp, -1.0);
         wave_order();
-        acc_store(X + (cc * t + r) * 256, x);
+        acc_store<LD>(X + (cc * t + r) * TT, x);
       }
       wave_order();
     }
