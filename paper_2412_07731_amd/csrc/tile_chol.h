@@ -6,12 +6,20 @@
 // L^-1 of the Cholesky factor P = L L'.  A pivot d_j <= thr is replaced by a
 // huge value (the pivot rule) and counted.
 //
-// Layout: lane l holds row i = l%16 and columns 4g..4g+3 (g = l/16) of both
-// halves.  At step j the 16-lane row g already holds columns 4g..4g+3 of every
-// tile row, so row j reaches its lanes by a DPP row broadcast (row_newbcast:j)
-// and the multiplier a_ij / d_j of row i comes from lane (i, j/4) by two
-// cross-row swaps (permlane16, then permlane32): a step costs one reciprocal,
-// the swaps, sixteen DPP moves and eight FMAs, with no LDS round trip.
+// Both halves share one 16x16 array C: U is upper triangular and E unit lower
+// triangular, and step j zeroes column j of U below the diagonal exactly where
+// E gets its first nonzero there.  So C holds U on and above the diagonal and
+// E below it; at step j row i > j is updated with the pivot row of C (its
+// part left of column j is row j of E, its part right of it row j of U) and
+// its entry in column j becomes E's, -m_ij.  Every value is the one the
+// separate halves produce, with half the broadcasts and FMAs per step.
+//
+// Layout: lane l holds row i = l%16 and columns 4g..4g+3 (g = l/16).  At step
+// j the 16-lane row g already holds columns 4g..4g+3 of every tile row, so row
+// j reaches its lanes by a DPP row broadcast (row_newbcast:j) and the
+// multiplier a_ij / d_j of row i comes from lane (i, j/4) by two cross-row
+// swaps (permlane16, then permlane32): a step costs one reciprocal, the swaps,
+// eight DPP moves and four FMAs, with no LDS round trip.
 #pragma once
 
 #include "common.h"
@@ -50,19 +58,20 @@ __device__ __forceinline__ float lane_bcast<float>(float v, int src) {
 }
 
 // value of lane J of each 16-lane row, in every lane of that row
+// (row_newbcast writes every lane, so the move needs no old value)
 template <int J>
 __device__ __forceinline__ double row_bcast(double v) {
   union { double d; int i[2]; } u, o;
   u.d = v;
-  o.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], 0x150 + J, 0xF, 0xF, false);
-  o.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], 0x150 + J, 0xF, 0xF, false);
+  o.i[0] = __builtin_amdgcn_mov_dpp(u.i[0], 0x150 + J, 0xF, 0xF, false);
+  o.i[1] = __builtin_amdgcn_mov_dpp(u.i[1], 0x150 + J, 0xF, 0xF, false);
   return o.d;
 }
 template <int J>
 __device__ __forceinline__ float row_bcast(float v) {
   union { float f; int i; } u, o;
   u.f = v;
-  o.i = __builtin_amdgcn_update_dpp(0, u.i, 0x150 + J, 0xF, 0xF, false);
+  o.i = __builtin_amdgcn_mov_dpp(u.i, 0x150 + J, 0xF, 0xF, false);
   return o.f;
 }
 
@@ -106,11 +115,12 @@ __device__ __forceinline__ double recip(double p) {
 }
 __device__ __forceinline__ float recip(float p) { return 1.0f / p; }
 
-// Elimination step J on the lane's row i, column group g.  SG: signed
-// (quasi-definite) form, where column J's pivot must have the sign of its bit
-// in neg (set: negative); the rule applies to the pivot times that sign.
+// Elimination step J on the lane's row i, column group g, of the combined
+// array a.  SG: signed (quasi-definite) form, where column J's pivot must have
+// the sign of its bit in neg (set: negative); the rule applies to the pivot
+// times that sign.
 template <typename T, int J, bool SG>
-__device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double thr, int& cnt,
+__device__ __forceinline__ void chol_step(T (&a)[4], int i, int g, double thr, int& cnt,
                                           T& mypiv, unsigned neg) {
   T p = lane_bcast<T>(a[J & 3], J + 16 * (J >> 2));
   if constexpr (SG) {
@@ -129,25 +139,23 @@ __device__ __forceinline__ void chol_step(T (&a)[4], T (&e)[4], int i, double th
   if (i == J) mypiv = p;
   // a_iJ from lane (i, J/4); row J from lane J of this lane's 16-lane row
   const T aij = rowgroup_bcast<J / 4>(a[J & 3]);
-  T rj[4], rje[4];
+  T rj[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    rj[r] = row_bcast<J>(a[r]);
-    rje[r] = row_bcast<J>(e[r]);
-  }
+  for (int r = 0; r < 4; ++r) rj[r] = row_bcast<J>(a[r]);
   const T m = (i > J) ? aij * rp : T(0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    a[r] -= m * rj[r];
-    e[r] -= m * rje[r];
+    const T u = a[r] - m * rj[r];
+    // column J of a row below the pivot: E's entry 0 - m * E(J, J) = 0 - m
+    a[r] = (r == (J & 3) && g == (J >> 2) && i > J) ? T(0) - m : u;
   }
 }
 template <typename T, int J, bool SG>
-__device__ __forceinline__ void chol_steps(T (&a)[4], T (&e)[4], int i, double thr, int& cnt,
+__device__ __forceinline__ void chol_steps(T (&a)[4], int i, int g, double thr, int& cnt,
                                            T& mypiv, unsigned neg) {
   if constexpr (J < 16) {
-    chol_step<T, J, SG>(a, e, i, thr, cnt, mypiv, neg);
-    chol_steps<T, J + 1, SG>(a, e, i, thr, cnt, mypiv, neg);
+    chol_step<T, J, SG>(a, i, g, thr, cnt, mypiv, neg);
+    chol_steps<T, J + 1, SG>(a, i, g, thr, cnt, mypiv, neg);
   }
 }
 
@@ -163,15 +171,12 @@ __device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double th
                                               unsigned neg = 0) {
   (void)xbuf;
   const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
-  T a[4], e[4];
+  T a[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    a[r] = P[(4 * g + r) * LD + i];
-    e[r] = (4 * g + r == i) ? T(1) : T(0);
-  }
+  for (int r = 0; r < 4; ++r) a[r] = P[(4 * g + r) * LD + i];
   int cnt = 0;
   T mypiv = T(1);
-  chol_steps<T, 0, SG>(a, e, i, thr, cnt, mypiv, neg);
+  chol_steps<T, 0, SG>(a, i, g, thr, cnt, mypiv, neg);
   T si = T(1);
   if constexpr (SG) {
     si = ((neg >> i) & 1u) ? T(-1) : T(1);
@@ -184,9 +189,11 @@ __device__ __forceinline__ int wave_chol_tile(const T* P, T* L, T* Li, double th
   for (int r = 0; r < 4; ++r) {
     const int c = 4 * g + r;
     // L' row i = U row i * s (times the row's sign if SG), i.e. L[c][i] (zero
-    // above the diagonal); Li row i = E row i * s
+    // above the diagonal); Li row i = E row i * s (E: unit diagonal, zero
+    // above it)
+    const T e = c < i ? a[r] : (c == i ? T(1) : T(0));
     L[i * LD + c] = (c >= i) ? a[r] * sl : T(0);
-    Li[c * LD + i] = e[r] * s;
+    Li[c * LD + i] = e * s;
   }
   wave_order();
   return cnt;
