@@ -518,15 +518,23 @@ __device__ __forceinline__ double block_diag_max(const BlockInfo& b, const T* __
   return r;
 }
 
-// The panel factorization of one bordered block by four waves (threads
-// 0..255), with pivot threshold thr; smem_raw is its dynamic LDS.  Sync
-// provides the barrier of the four waves and the wait for the inputs of panel
-// c0 (returns false when the wait was abandoned, and the factorization stops).
+// The panel factorization of one bordered block by NW waves, with pivot
+// threshold thr; smem_raw is its dynamic LDS.  Sync provides the barrier of
+// the waves and the wait for the inputs of panel c0 (returns false when the
+// wait was abandoned, and the factorization stops).
+//
+// The block's Schur contribution PQ - W_i'W_i (W_i' = the bordered rows) is a
+// sum over the tile columns q.  In FP64, when its kt(kt+1)/2 tiles fit in the
+// sch_cap LDS tiles after the per-wave ones, the waves that never factor a
+// diagonal tile (w >= BF_PW) add column q's terms while a later column's
+// diagonal tile is being factored, from the panel column buffer that still
+// holds column q: the same products in the same order as schur_rows at the
+// end, which otherwise re-reads every W tile from memory.
 template <typename T, int BF_RMAX, int NW, class Sync>
 __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__ LB,
                                              T* __restrict__ LINV, double* __restrict__ PQ,
                                              DevInfo* info, unsigned char* smem_raw, double thr,
-                                             Sync& sy) {
+                                             Sync& sy, int sch_cap = 0) {
   constexpr int LD = BfLd<BF_RMAX>::LD, TEP = TS * LD;
   constexpr int AST = sizeof(T) == 8 ? 4 : 1;   // accumulator element stride in a padded tile
   const int mt = b.mt, rt = b.rt;
@@ -559,6 +567,43 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
     for (int s = 0; s < 4; ++s) o.v[s] = t[rb + 68 * s];
     return o;
   };
+  // Schur contribution in the factorization's gaps (FP64): tile u of the
+  // kt(kt+1)/2 lower tiles (row-major over (rr, cc), cc <= rr) belongs to
+  // worker wave BF_PW + u % (NW - BF_PW), which alone reads and writes it
+  const int kt = b.kt, nst = kt * (kt + 1) / 2;
+  const bool sgap = TR && NW > BF_PW && nst > 0 && nst <= sch_cap;
+  double* sacc = reinterpret_cast<double*>(scr + NW * TEP);   // nst tiles, accumulator layout
+  int qpend = -1, qc0 = 0;   // column whose terms are pending, and its panel's first column
+  auto schur_col = [&](int q, int c0q) {
+    int rr = 0, cc = 0;
+    for (int u = 0; u < nst; ++u) {
+      if (u % (NW - BF_PW) == w - BF_PW) {
+        const BfOp<T> x = ld_op(colbuf + (size_t)(mt + rr - c0q) * TEP);
+        const BfOp<T> y = ld_op(colbuf + (size_t)(mt + cc - c0q) * TEP);
+        double* t = sacc + (size_t)u * TEP;
+        d4 a;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = t[wb + 4 * k];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a = mfma(-(double)x.v[s], (double)y.v[s], a);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[wb + 4 * k] = a[k];
+      }
+      if (++cc > rr) { ++rr; cc = 0; }
+    }
+    (void)q;
+  };
+  if (sgap && w >= BF_PW) {
+    int rr = 0, cc = 0;
+    for (int u = 0; u < nst; ++u) {
+      if (u % (NW - BF_PW) == w - BF_PW) {
+        const double* src = PQ + pq_tile(b, rr, cc);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sacc[(size_t)u * TEP + wb + 4 * k] = src[acc_index<double>(lane, k)];
+      }
+      if (++cc > rr) { ++rr; cc = 0; }
+    }
+  }
 
   for (int c0 = 0; c0 < mt; c0 += BF_PW) {
     const int pw = min(BF_PW, mt - c0);
@@ -608,6 +653,8 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       if (j >= pw) break;
       const int c = c0 + j;
       const int ow = (c - c0) % NW, ot = (c - c0) / NW;
+      // the previous column's Schur terms while wave ow factors this one
+      if (sgap && w >= BF_PW && qpend >= 0) schur_col(qpend, qc0);
       if (w == ow) {
 #pragma unroll
         for (int t = 0; t < BF_RMAX; ++t)
@@ -657,6 +704,8 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
         }
       }
       sy.sync();
+      qpend = c;
+      qc0 = c0;
       // the panel's later columns: acc(r, c') -= L(r, c) L(c', c)'
 #pragma unroll
       for (int j2 = 0; j2 < BF_PW; ++j2) {
@@ -683,9 +732,25 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       sy.sync();
     }
   }
-  // the block's Schur contribution while its W' tiles are still in L2 (the
-  // loop's last barrier has made every wave's stores visible)
-  schur_rows<T>(b, LB, PQ, w, lane, NW);
+  if (sgap) {
+    // the last column's terms, then the worker waves' tiles to PQ
+    if (w >= BF_PW) {
+      if (qpend >= 0) schur_col(qpend, qc0);
+      int rr = 0, cc = 0;
+      for (int u = 0; u < nst; ++u) {
+        if (u % (NW - BF_PW) == w - BF_PW) {
+          double* dst = PQ + pq_tile(b, rr, cc);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) dst[acc_index<double>(lane, k)] = sacc[(size_t)u * TEP + wb + 4 * k];
+        }
+        if (++cc > rr) { ++rr; cc = 0; }
+      }
+    }
+  } else {
+    // the block's Schur contribution while its W' tiles are still in L2 (the
+    // loop's last barrier has made every wave's stores visible)
+    schur_rows<T>(b, LB, PQ, w, lane, NW);
+  }
   // each wave counts the pivots of the diagonal tiles it factored
   if (lane == 0 && cnt) atomicAdd(&info->pivots, cnt);
 }
@@ -696,13 +761,13 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
 template <typename T, int BF_RMAX, int NW>
 __global__ __launch_bounds__(64 * NW, 8 / NW) void k_block_factor_panel(
     const BlockInfo* __restrict__ blk, const int* __restrict__ order, T* __restrict__ LB,
-    T* __restrict__ LINV, double* __restrict__ PQ, DevInfo* info) {
+    T* __restrict__ LINV, double* __restrict__ PQ, DevInfo* info, int sch_cap) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double s_max[NW];
   const BlockInfo b = blk[order[blockIdx.x]];
   WgSync sy;
   const double thr = PIVOT_REL * fmax(block_diag_max<T, NW>(b, LB, s_max, sy), 0.0);
-  panel_factor<T, BF_RMAX, NW>(b, LB, LINV, PQ, info, smem_raw, thr, sy);
+  panel_factor<T, BF_RMAX, NW>(b, LB, LINV, PQ, info, smem_raw, thr, sy, sch_cap);
 }
 
 // ------------------------------------------------- a1-a5 in one launch
@@ -1155,19 +1220,25 @@ void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* 
                                int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info, int waves) {
   if (n == 0) return;
   // LDS: the panel column (max_rt tiles), L_cc^-1, the diagonal tile and one
-  // per-wave tile, at the form's leading dimension
+  // per-wave tile, at the form's leading dimension; in FP64 then as many
+  // Schur-contribution tiles as fit beside it without lowering the
+  // occupancy the launch bounds ask for (two four-wave workgroups or one
+  // eight-wave workgroup per CU, of the CU's 160 KiB)
+  const size_t tile = (size_t)TS * BfLd<5>::LD * sizeof(T);
+  const size_t base = (size_t)(max_rt + 2 + waves) * tile;
+  const size_t budget = (waves == 8 ? 156 : 78) * 1024;
+  int cap = 0;
+  if (sizeof(T) == 8 && budget > base) cap = (int)((budget - base) / tile);
+  const size_t shmem = base + (size_t)cap * tile;
   if (waves == 8) {
-    const size_t shmem = (size_t)(max_rt + 2 + 8) * TS * BfLd<5>::LD * sizeof(T);
     hipLaunchKernelGGL((k_block_factor_panel<T, 5, 8>), dim3(n), dim3(512), shmem, st, blk, order,
-                       LB, LINV, PQ, info);
+                       LB, LINV, PQ, info, cap);
   } else if (max_rt <= 20) {
-    const size_t shmem = (size_t)(max_rt + 2 + 4) * TS * BfLd<5>::LD * sizeof(T);
     hipLaunchKernelGGL((k_block_factor_panel<T, 5, 4>), dim3(n), dim3(256), shmem, st, blk, order,
-                       LB, LINV, PQ, info);
+                       LB, LINV, PQ, info, cap);
   } else {
-    const size_t shmem = (size_t)(max_rt + 2 + 4) * TS * BfLd<6>::LD * sizeof(T);
     hipLaunchKernelGGL((k_block_factor_panel<T, 6, 4>), dim3(n), dim3(256), shmem, st, blk, order,
-                       LB, LINV, PQ, info);
+                       LB, LINV, PQ, info, cap);
   }
 }
 // The fused launch over the panel bucket (blocks order[0, n), bordered tile
