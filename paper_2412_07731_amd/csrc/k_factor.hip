@@ -494,6 +494,7 @@ __device__ __forceinline__ void tile_copy_p(T* __restrict__ dst, const T* __rest
 // Synchronization of the panel factor's four waves in the standalone kernel:
 // a workgroup barrier, and every panel's inputs are there from the start.
 struct WgSync {
+  static constexpr bool kPrefetch = true;
   __device__ __forceinline__ void sync() { __syncthreads(); }
   __device__ __forceinline__ bool wait_panel(int) { return true; }
 };
@@ -605,6 +606,34 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
     }
   }
 
+  // Prefetch into L2 (standalone kernel): the next panel's input tiles (the
+  // SYRK's and the link gather's, written long before and mostly out of L2
+  // by now) are requested while the current panel's second diagonal tile is
+  // factored.  One lane touches each 128-byte line, with a direct-to-LDS
+  // load into a scratch area nobody reads, so no registers are held.  (A
+  // wave's next LDS write waits for its direct-to-LDS loads, so the
+  // factoring wave issues none.)
+  constexpr int LPT = TE * (int)sizeof(T) / 128;   // lines per tile
+  constexpr int TPI = 64 / LPT;                     // tiles per prefetch instruction
+  __shared__ __align__(16) unsigned char pf_sink[256];
+  auto touch = [&](bool valid, const T* tile) {
+    if (valid)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(reinterpret_cast<const char*>(tile) + (lane % LPT) * 128),
+          (__attribute__((address_space(3))) void*)pf_sink, 4, 0, 0);
+  };
+  // tiles of panel n0 (column n0 + j, rows n0 + j .. rt - 1), dealt to the
+  // NW - 1 waves other than skip
+  auto prefetch_panel = [&](int n0, int skip) {
+    const int npw = min(BF_PW, mt - n0);
+    const int me = w < skip ? w : w - 1;
+    const int n1 = rt - n0, ntile = n1 + (npw > 1 ? n1 - 1 : 0);
+    for (int u0 = me * TPI; u0 < ntile; u0 += (NW - 1) * TPI) {
+      const int u = u0 + lane / LPT;
+      const int j = u < n1 ? 0 : 1, r = u < n1 ? n0 + u : n0 + 1 + (u - n1);
+      touch(u < ntile, LB + lb_tile(b, min(r, rt - 1), n0 + j));
+    }
+  };
   for (int c0 = 0; c0 < mt; c0 += BF_PW) {
     const int pw = min(BF_PW, mt - c0);
     if (!sy.wait_panel(c0)) return;
@@ -655,6 +684,8 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       const int ow = (c - c0) % NW, ot = (c - c0) / NW;
       // the previous column's Schur terms while wave ow factors this one
       if (sgap && w >= BF_PW && qpend >= 0) schur_col(qpend, qc0);
+      if (Sync::kPrefetch && j == BF_PW - 1 && c0 + BF_PW < mt && w != ow)
+        prefetch_panel(c0 + BF_PW, ow);
       if (w == ow) {
 #pragma unroll
         for (int t = 0; t < BF_RMAX; ++t)
@@ -840,6 +871,7 @@ __device__ __forceinline__ bool fused_wait(FusedCtl* ctl, DevInfo* info, F cond)
 
 // The factor team's synchronization inside the fused kernel.
 struct TeamSync {
+  static constexpr bool kPrefetch = false;   // the SYRK team's tiles are still in L2
   FusedCtl* ctl;
   FusedSlot* slot;
   DevInfo* info;
