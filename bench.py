@@ -307,6 +307,24 @@ def general_bench(golden_runs, steps=3):
     return out
 
 
+def ceilings():
+    """Measured ceilings of this device (ahlp_ceiling_mfma, ahlp_ceiling_hbm_read):
+    the MFMA instructions of the factorization on dependency-free streams, and
+    a streaming read of 2 GiB; the rooflines' frac_of_measured divide by these,
+    their frac by the published peaks."""
+    import torch
+    from paper_2412_07731_amd import ahlp as A
+    buf = torch.zeros(1 << 28, dtype=torch.float64, device="cuda")
+    out = {"mfma_f64_tflops": A.ceiling_mfma(A.FP64),
+           "mfma_f32_tflops": A.ceiling_mfma(A.FP32_REFINE),
+           "hbm_read_gbs": A.ceiling_hbm_read(buf),
+           "published": {"mfma_f64_tflops": PEAK_FP64_TFLOPS, "mfma_f32_tflops": PEAK_FP32_TFLOPS,
+                         "hbm_gbs": PEAK_HBM_GBS}}
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
 def fp32_leg(P, inst, fl, args, golden, fp64_rate, fp64_t_asm_ms):
     """FP32 MFMA blocks (a2-a4) with FP64 refinement on the same instance, timed
     at the same instrumentation level as the FP64 line (HIP events around the
@@ -575,8 +593,16 @@ def main():
              "bytes_per_launch": rows_bytes_avg, "avg_launch_ms": rows_ms,
              "launches_per_solve": n_rows, "timed": "in the extra fully timed solve"}],
     }
+    if not args.profile:
+        c = line["ceilings"] = ceilings()
+        cm = c["mfma_f32_tflops"] if main_prec == FP32_REFINE else c["mfma_f64_tflops"]
+        line["roofline"]["frac_of_measured"] = dom_tflops / cm
+        line["schur_assembly"]["frac_of_measured"] = asm_tflops / c["mfma_f64_tflops"]
+        line["rooflines_other"][0]["frac_of_measured"] = rows_gbs / c["hbm_read_gbs"]
     if not args.profile and not args.fp32:
         line["fp32_refine"] = fp32_leg(P, inst, fl, args, golden, iters / dt, t_asm_ms)
+        r32 = line["fp32_refine"]["inexact_newton"]["roofline"]
+        r32["frac_of_measured"] = r32["achieved"] / line["ceilings"]["mfma_f32_tflops"]
         line["graph"] = graph_leg(P, args, r0["iterations"])
         line["fused_launch"] = fused_leg(P, fl, args, iters / dt, t_asm_ms)
     if not args.profile and not args.fp32:

@@ -367,6 +367,27 @@ ahlp_status_t ahlp_ipm_bound_duals(ahlp_problem_t p, double* s, double* w, hipSt
 /* Last error message of this thread ("" when none). */
 const char* ahlp_last_error(void);
 
+/* ---- device ceilings (measurement aids, not part of the method) ----------
+ * Achievable rates of this device, so that kernels can be reported against
+ * measured ceilings beside the published peaks.  Both synchronize `stream`
+ * and allocate a small device buffer of their own. */
+
+/* Throughput of the MFMA instruction the factorization kernels use
+ * (precision AHLP_FP64: v_mfma_f64_16x16x4f64; AHLP_FP32_REFINE:
+ * v_mfma_f32_16x16x4f32), on eight independent accumulators per wave, eight
+ * waves per SIMD, on every CU, no memory traffic: *tflops in TFLOP/s, the
+ * best of three timed launches after one untimed.  AHLP_EINVAL for another
+ * precision or a null pointer. */
+ahlp_status_t ahlp_ceiling_mfma(int32_t precision, double* tflops, hipStream_t stream);
+
+/* HBM read bandwidth of a streaming pass over the DEVICE buffer buf of n
+ * doubles (16-byte aligned, n >= 2; make it much larger than the caches, a
+ * GiB or more), with 16-byte nontemporal loads: *gbps in GB/s (1e9 bytes),
+ * the best of three timed passes after one untimed.  The contents are read,
+ * never written.  AHLP_EINVAL for null or misaligned pointers or n < 2. */
+ahlp_status_t ahlp_ceiling_hbm_read(const double* buf, int64_t n, double* gbps,
+                                    hipStream_t stream);
+
 /* ---- inspection (tests and profiling; synchronize the stream) ------------
  * Copy intermediate results of the last factorization to HOST memory in the
  * canonical dense layouts below.  They exist so that every stage can be

@@ -96,6 +96,8 @@ SIGNATURES = {
     "ahlp_debug_block": ([C.c_void_p, C.c_int32, _f64p, _f64p], C.c_int),
     "ahlp_debug_schur": ([C.c_void_p, _f64p], C.c_int),
     "ahlp_debug_pivots": ([C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
+    "ahlp_ceiling_mfma": ([C.c_int32, C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "ahlp_ceiling_hbm_read": ([C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p], C.c_int),
 }
 
 _lib = None
@@ -149,6 +151,22 @@ def _dptr(t):
     import torch
     assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "need contiguous cuda float64"
     return C.c_void_p(t.data_ptr())
+
+
+def ceiling_mfma(precision=FP64, stream=None):
+    """ahlp_ceiling_mfma: the device's measured MFMA throughput (TFLOP/s) for
+    the instruction the factorization uses in this precision."""
+    v = C.c_double()
+    _check(lib().ahlp_ceiling_mfma(int(precision), C.byref(v), _stream(stream)))
+    return v.value
+
+
+def ceiling_hbm_read(buf, stream=None):
+    """ahlp_ceiling_hbm_read: streaming read bandwidth (GB/s) over the
+    contiguous cuda float64 tensor buf (make it a GiB or more)."""
+    v = C.c_double()
+    _check(lib().ahlp_ceiling_hbm_read(_dptr(buf), int(buf.numel()), C.byref(v), _stream(stream)))
+    return v.value
 
 
 class Problem:

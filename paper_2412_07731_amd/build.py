@@ -15,6 +15,7 @@ LIB = os.path.join(HERE, "libahlp.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["k_factor.hip", "k_chain.hip", "k_bcr.hip", "k_bcr2.hip", "k_solve.hip", "noalloc.hip",
+           "k_ceiling.hip",
            "host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

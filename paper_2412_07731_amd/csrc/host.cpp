@@ -2290,6 +2290,83 @@ ahlp_status_t ahlp_problem_sizes(ahlp_problem_t p, int64_t* n_tot, int64_t* m_to
   return AHLP_OK;
 }
 
+// Device ceilings: one untimed launch, then the best of three timed ones.
+namespace {
+struct CeilBuf {
+  double* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~CeilBuf() {
+    if (out) (void)hipFree(out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+ahlp_status_t ceil_grid(int per_cu, int* grid) {
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *grid = std::max(cus, 1) * per_cu;
+  return AHLP_OK;
+}
+}  // namespace
+
+ahlp_status_t ahlp_ceiling_mfma(int32_t precision, double* tflops, hipStream_t stream) {
+  if (!tflops) return fail(AHLP_EINVAL, "null argument");
+  if (precision != AHLP_FP64 && precision != AHLP_FP32_REFINE)
+    return fail(AHLP_EINVAL, "unknown precision %d", precision);
+  const bool f32 = precision == AHLP_FP32_REFINE;
+  int grid = 0;
+  CHK(ceil_grid(8, &grid));   // eight four-wave workgroups per CU: eight waves per SIMD
+  const int iters = f32 ? 2048 : 1024;   // multiples of the kernel's sixteen rounds per trip
+  CeilBuf cb;
+  HIPCHK(hipMalloc(&cb.out, (size_t)grid * sizeof(double)));
+  HIPCHK(hipEventCreate(&cb.e0));
+  HIPCHK(hipEventCreate(&cb.e1));
+  launch_ceiling_mfma(stream, f32, grid, iters, cb.out);
+  float best = 0.f;
+  for (int rep = 0; rep < 3; ++rep) {
+    HIPCHK(hipEventRecord(cb.e0, stream));
+    launch_ceiling_mfma(stream, f32, grid, iters, cb.out);
+    HIPCHK(hipEventRecord(cb.e1, stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(cb.e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, cb.e0, cb.e1));
+    if (rep == 0 || ms < best) best = ms;
+  }
+  // per wave and iteration eight 16x16x4 products of 2048 flops
+  const double flop = (double)grid * 4 * iters * 8 * 2048.0;
+  *tflops = best > 0.f ? flop / (best * 1e-3) / 1e12 : 0.0;
+  return AHLP_OK;
+}
+
+ahlp_status_t ahlp_ceiling_hbm_read(const double* buf, int64_t n, double* gbps,
+                                    hipStream_t stream) {
+  if (!buf || !gbps || n < 2 || (reinterpret_cast<uintptr_t>(buf) & 15))
+    return fail(AHLP_EINVAL, "null or misaligned buffer, or n < 2");
+  int grid = 0;
+  CHK(ceil_grid(16, &grid));
+  CeilBuf cb;
+  HIPCHK(hipMalloc(&cb.out, (size_t)grid * sizeof(double)));
+  HIPCHK(hipEventCreate(&cb.e0));
+  HIPCHK(hipEventCreate(&cb.e1));
+  launch_ceiling_read(stream, buf, n, grid, cb.out);
+  float best = 0.f;
+  for (int rep = 0; rep < 3; ++rep) {
+    HIPCHK(hipEventRecord(cb.e0, stream));
+    launch_ceiling_read(stream, buf, n, grid, cb.out);
+    HIPCHK(hipEventRecord(cb.e1, stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(cb.e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, cb.e0, cb.e1));
+    if (rep == 0 || ms < best) best = ms;
+  }
+  const double bytes = (double)(n / 2) * 16.0;
+  *gbps = best > 0.f ? bytes / (best * 1e-3) / 1e9 : 0.0;
+  return AHLP_OK;
+}
+
 ahlp_status_t ahlp_debug_pivots(ahlp_problem_t p, int32_t* count) {
   if (!p || !count) return fail(AHLP_EINVAL, "null argument");
   CHK(check_info(p, p->timer.st, nullptr));

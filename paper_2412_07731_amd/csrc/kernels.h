@@ -127,6 +127,9 @@ int bcr_tiles(int lmax, int n0);
 void launch_bcr_factor(hipStream_t st, const BcrArgs& c, int nparts, int chunk);
 void launch_bcr_solve(hipStream_t st, const BcrSolveArgs& a);
 void set_bcr_smem_limits();
+// device ceilings (k_ceiling.hip): grid workgroups of 256 threads
+void launch_ceiling_mfma(hipStream_t st, bool fp32, int grid, int iters, double* out);
+void launch_ceiling_read(hipStream_t st, const double* buf, long long n, int grid, double* out);
 // two-tile pairs (k_bcr2.hip): the reduction of T down to the final pair, and
 // the whole solve
 void launch_bcr2_reduce(hipStream_t st, const BcrArgs& c);
