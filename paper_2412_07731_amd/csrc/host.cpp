@@ -187,7 +187,7 @@ struct ahlp_problem_s {
   long long f0first = 0;   // first row of F0 that may be nonzero (nl when only Wg0 is)
   long long vp_total = 0, q_total = 0, a_total = 0, c_total = 0, lb_total = 0, linv_total = 0,
             pq_total = 0;
-  int max_rt = 0, lmax = 0;
+  int max_rt = 0, lmax = 0, max_kt = 0;
   double colabs1_max = 1.0, rowabs_max = 0.0, b_inf = 0.0, c_inf = 0.0;
   DevMem mem;
 
@@ -462,7 +462,7 @@ ahlp_status_t factor_blocks_per_block(ahlp_problem_t p, hipStream_t st, T* LB, T
       launch_block_factor_col<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info);
     else
       launch_block_factor_panel<T>(st, p->blk, p->ident + i, 1, rt, LB, LINV, p->PQ, p->info,
-                                   k == BFK_PANEL8 ? 8 : 4);
+                                   k == BFK_PANEL8 ? 8 : 4, p->max_kt);
   }
   p->timer.end();
   HIPCHK(hipGetLastError());
@@ -484,7 +484,7 @@ ahlp_status_t factor_blocks_fused(ahlp_problem_t p, hipStream_t st, T* LB, T* LI
                    p->lcol, p->lval, p->Dp, LB, p->PQ);
     launch_syrk<T>(p->side, p->blk, p->col_syrk_items, p->ncol_syrk, A, p->Dp, LB, p->delta);
     launch_block_factor_panel<T>(p->side, p->blk, p->bf_order + p->n_panel, p->n_panel8,
-                                 p->rt_panel8, LB, LINV, p->PQ, p->info, 8);
+                                 p->rt_panel8, LB, LINV, p->PQ, p->info, 8, p->max_kt);
     launch_block_factor_col<T>(p->side, p->blk, p->bf_order + p->n_panel + p->n_panel8, p->n_col,
                                p->rt_col, LB, LINV, p->PQ, p->info);
     HIPCHK(hipEventRecord(p->ev_join, p->side));
@@ -521,16 +521,18 @@ ahlp_status_t factor_blocks(ahlp_problem_t p, hipStream_t st, T* LB, T* LINV, co
     // the eight-wave panel and the column buckets beside the four-wave one
     HIPCHK(hipEventRecord(p->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    launch_block_factor_panel<T>(p->side, p->blk, o8, nb8, p->rt_panel8, LB, LINV, p->PQ, p->info, 8);
+    launch_block_factor_panel<T>(p->side, p->blk, o8, nb8, p->rt_panel8, LB, LINV, p->PQ, p->info, 8,
+                                 p->max_kt);
     launch_block_factor_col<T>(p->side, p->blk, oc, nbc, p->rt_col, LB, LINV, p->PQ, p->info);
     HIPCHK(hipEventRecord(p->ev_join, p->side));
     launch_block_factor_panel<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, LB, LINV, p->PQ,
-                                 p->info);
+                                 p->info, 4, p->max_kt);
     HIPCHK(hipStreamWaitEvent(st, p->ev_join, 0));
   } else {
     launch_block_factor_panel<T>(st, p->blk, p->bf_order, p->n_panel, p->rt_panel, LB, LINV, p->PQ,
-                                 p->info);
-    launch_block_factor_panel<T>(st, p->blk, o8, nb8, p->rt_panel8, LB, LINV, p->PQ, p->info, 8);
+                                 p->info, 4, p->max_kt);
+    launch_block_factor_panel<T>(st, p->blk, o8, nb8, p->rt_panel8, LB, LINV, p->PQ, p->info, 8,
+                                 p->max_kt);
     launch_block_factor_col<T>(st, p->blk, oc, nbc, p->rt_col, LB, LINV, p->PQ, p->info);
   }
   p->timer.end();
@@ -1034,6 +1036,7 @@ ahlp_status_t ahlp_problem_create(const ahlp_problem_desc_t* d, hipStream_t st,
     b.voff = vo; vo += 16LL * b.mt;
     b.qoff = qo; qo += 16LL * b.kt;
     p->max_rt = std::max(p->max_rt, b.rt);
+    p->max_kt = std::max(p->max_kt, b.kt);
   }
   // the column-at-a-time block factor keeps a bordered block's whole tile
   // column in LDS: (rt + 1) padded 16 x 17 tiles
@@ -1690,7 +1693,8 @@ ahlp_status_t ahlp_autotune(ahlp_problem_t p, const char* cache_path, int32_t* m
                                             p->LINV, p->PQ, p->info);
           else
             launch_block_factor_panel<double>(st, p->blk, p->bf_order, (int)hblk.size(), rt, p->LB,
-                                              p->LINV, p->PQ, p->info, k == BFK_PANEL8 ? 8 : 4);
+                                              p->LINV, p->PQ, p->info, k == BFK_PANEL8 ? 8 : 4,
+                                              p->max_kt);
           HIPCHK(hipEventRecord(e1, st));
           HIPCHK(hipEventSynchronize(e1));
           float ms = 0.f;

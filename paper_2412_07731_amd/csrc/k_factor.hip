@@ -525,8 +525,9 @@ __device__ __forceinline__ double block_diag_max(const BlockInfo& b, const T* __
 // wait was abandoned, and the factorization stops).
 //
 // The block's Schur contribution PQ - W_i'W_i (W_i' = the bordered rows) is a
-// sum over the tile columns q.  In FP64, when its kt(kt+1)/2 tiles fit in the
-// sch_cap LDS tiles after the per-wave ones, the waves that never factor a
+// sum over the tile columns q, in FP64 in both precisions.  When its
+// kt(kt+1)/2 FP64 tiles fit in the sch_cap LDS tiles after the per-wave
+// ones, the waves that never factor a
 // diagonal tile (w >= BF_PW) add column q's terms while a later column's
 // diagonal tile is being factored, from the panel column buffer that still
 // holds column q: the same products in the same order as schur_rows at the
@@ -572,8 +573,9 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
   // kt(kt+1)/2 lower tiles (row-major over (rr, cc), cc <= rr) belongs to
   // worker wave BF_PW + u % (NW - BF_PW), which alone reads and writes it
   const int kt = b.kt, nst = kt * (kt + 1) / 2;
-  const bool sgap = TR && NW > BF_PW && nst > 0 && nst <= sch_cap;
+  const bool sgap = NW > BF_PW && nst > 0 && nst <= sch_cap;
   double* sacc = reinterpret_cast<double*>(scr + NW * TEP);   // nst tiles, accumulator layout
+  const int sb = (lane & 15) * LD + (lane >> 4);   // FP64 accumulator element k at sb + 4 k
   int qpend = -1, qc0 = 0;   // column whose terms are pending, and its panel's first column
   auto schur_col = [&](int q, int c0q) {
     int rr = 0, cc = 0;
@@ -584,11 +586,11 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
         double* t = sacc + (size_t)u * TEP;
         d4 a;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] = t[wb + 4 * k];
+        for (int k = 0; k < 4; ++k) a[k] = t[sb + 4 * k];
 #pragma unroll
         for (int s = 0; s < 4; ++s) a = mfma(-(double)x.v[s], (double)y.v[s], a);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) t[wb + 4 * k] = a[k];
+        for (int k = 0; k < 4; ++k) t[sb + 4 * k] = a[k];
       }
       if (++cc > rr) { ++rr; cc = 0; }
     }
@@ -600,7 +602,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       if (u % (NW - BF_PW) == w - BF_PW) {
         const double* src = PQ + pq_tile(b, rr, cc);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sacc[(size_t)u * TEP + wb + 4 * k] = src[acc_index<double>(lane, k)];
+        for (int k = 0; k < 4; ++k) sacc[(size_t)u * TEP + sb + 4 * k] = src[acc_index<double>(lane, k)];
       }
       if (++cc > rr) { ++rr; cc = 0; }
     }
@@ -772,7 +774,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
         if (u % (NW - BF_PW) == w - BF_PW) {
           double* dst = PQ + pq_tile(b, rr, cc);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) dst[acc_index<double>(lane, k)] = sacc[(size_t)u * TEP + wb + 4 * k];
+          for (int k = 0; k < 4; ++k) dst[acc_index<double>(lane, k)] = sacc[(size_t)u * TEP + sb + 4 * k];
         }
         if (++cc > rr) { ++rr; cc = 0; }
       }
@@ -1249,19 +1251,22 @@ template void launch_link<float>(hipStream_t, const BlockInfo*, const int2*, int
 // eight waves (five rows each) for blocks of up to 8 * 5 tile rows.
 template <typename T>
 void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
-                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info, int waves) {
+                               int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info, int waves,
+                               int max_kt) {
   if (n == 0) return;
   // LDS: the panel column (max_rt tiles), L_cc^-1, the diagonal tile and one
-  // per-wave tile, at the form's leading dimension; in FP64 then as many
+  // per-wave tile, at the form's leading dimension; then as many FP64
   // Schur-contribution tiles as fit beside it without lowering the
   // occupancy the launch bounds ask for (two four-wave workgroups or one
   // eight-wave workgroup per CU, of the CU's 160 KiB)
   const size_t tile = (size_t)TS * BfLd<5>::LD * sizeof(T);
   const size_t base = (size_t)(max_rt + 2 + waves) * tile;
   const size_t budget = (waves == 8 ? 156 : 78) * 1024;
+  const size_t tile64 = (size_t)TS * BfLd<5>::LD * sizeof(double);
   int cap = 0;
-  if (sizeof(T) == 8 && budget > base) cap = (int)((budget - base) / tile);
-  const size_t shmem = base + (size_t)cap * tile;
+  if (budget > base) cap = (int)((budget - base) / tile64);
+  if (max_kt >= 0) cap = std::min(cap, max_kt * (max_kt + 1) / 2);
+  const size_t shmem = base + (size_t)cap * tile64;
   if (waves == 8) {
     hipLaunchKernelGGL((k_block_factor_panel<T, 5, 8>), dim3(n), dim3(512), shmem, st, blk, order,
                        LB, LINV, PQ, info, cap);
@@ -1317,9 +1322,9 @@ void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* or
 bool block_factor_panel_fits(int rt) { return rt <= 4 * BF_RMAX_MAX; }
 bool block_factor_panel8_fits(int rt) { return rt <= 8 * 5; }
 template void launch_block_factor_panel<double>(hipStream_t, const BlockInfo*, const int*, int, int,
-                                                double*, double*, double*, DevInfo*, int);
+                                                double*, double*, double*, DevInfo*, int, int);
 template void launch_block_factor_panel<float>(hipStream_t, const BlockInfo*, const int*, int, int,
-                                               float*, float*, double*, DevInfo*, int);
+                                               float*, float*, double*, DevInfo*, int, int);
 template void launch_block_factor_col<double>(hipStream_t, const BlockInfo*, const int*, int, int,
                                               double*, double*, double*, DevInfo*);
 template void launch_block_factor_col<float>(hipStream_t, const BlockInfo*, const int*, int, int,

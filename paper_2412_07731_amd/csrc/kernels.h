@@ -22,11 +22,13 @@ void launch_link(hipStream_t st, const BlockInfo* blk, const int2* items, int ni
 // and W_i', then the FP64 Schur contributions PQ): the panel kernel for
 // blocks whose bordered tile rows fit (block_factor_panel_fits), the
 // column-at-a-time kernel plus a product pass for any height.  max_rt: the
-// largest bordered tile-row count among the n blocks.
+// largest bordered tile-row count among the n blocks; max_kt (if >= 0) an
+// upper bound on their link-column tile counts, which sizes the LDS for the
+// Schur contribution.
 template <typename T>
 void launch_block_factor_panel(hipStream_t st, const BlockInfo* blk, const int* order, int n,
                                int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info,
-                               int waves = 4);
+                               int waves = 4, int max_kt = -1);
 template <typename T>
 void launch_block_factor_col(hipStream_t st, const BlockInfo* blk, const int* order, int n,
                              int max_rt, T* LB, T* LINV, double* PQ, DevInfo* info);
