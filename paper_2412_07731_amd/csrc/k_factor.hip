@@ -569,15 +569,15 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
     for (int s = 0; s < 4; ++s) o.v[s] = t[rb + 68 * s];
     return o;
   };
-  // Schur contribution in the factorization's gaps (FP64): tile u of the
-  // kt(kt+1)/2 lower tiles (row-major over (rr, cc), cc <= rr) belongs to
+  // Schur contribution in the factorization's gaps (FP64 accumulators in
+  // LDS): tile u of the kt(kt+1)/2 lower tiles (row-major over (rr, cc), cc <= rr) belongs to
   // worker wave BF_PW + u % (NW - BF_PW), which alone reads and writes it
   const int kt = b.kt, nst = kt * (kt + 1) / 2;
   const bool sgap = NW > BF_PW && nst > 0 && nst <= sch_cap;
   double* sacc = reinterpret_cast<double*>(scr + NW * TEP);   // nst tiles, accumulator layout
   const int sb = (lane & 15) * LD + (lane >> 4);   // FP64 accumulator element k at sb + 4 k
   int qpend = -1, qc0 = 0;   // column whose terms are pending, and its panel's first column
-  auto schur_col = [&](int q, int c0q) {
+  auto schur_col = [&](int c0q) {   // the pending column, factored in the panel at c0q
     int rr = 0, cc = 0;
     for (int u = 0; u < nst; ++u) {
       if (u % (NW - BF_PW) == w - BF_PW) {
@@ -594,7 +594,6 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       }
       if (++cc > rr) { ++rr; cc = 0; }
     }
-    (void)q;
   };
   if (sgap && w >= BF_PW) {
     int rr = 0, cc = 0;
@@ -685,7 +684,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       const int c = c0 + j;
       const int ow = (c - c0) % NW, ot = (c - c0) / NW;
       // the previous column's Schur terms while wave ow factors this one
-      if (sgap && w >= BF_PW && qpend >= 0) schur_col(qpend, qc0);
+      if (sgap && w >= BF_PW && qpend >= 0) schur_col(qc0);
       if (Sync::kPrefetch && j == BF_PW - 1 && c0 + BF_PW < mt && w != ow)
         prefetch_panel(c0 + BF_PW, ow);
       if (w == ow) {
@@ -768,7 +767,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
   if (sgap) {
     // the last column's terms, then the worker waves' tiles to PQ
     if (w >= BF_PW) {
-      if (qpend >= 0) schur_col(qpend, qc0);
+      if (qpend >= 0) schur_col(qc0);
       int rr = 0, cc = 0;
       for (int u = 0; u < nst; ++u) {
         if (u % (NW - BF_PW) == w - BF_PW) {
