@@ -62,7 +62,8 @@ __device__ __forceinline__ void tile_copy_t(T* __restrict__ dst, const T* __rest
 // One 64x64 lower macro tile of one block per workgroup (4 waves, each 32x32 =
 // 2x2 MFMA tiles).  Per tile column K of A, the 4 row tiles and 4 column tiles
 // are staged through LDS (double buffered), two tile columns ahead in
-// registers; D scales the B operand in registers.  Work items are ordered so
+// registers; D scales the column tiles as they are staged (the B operand's
+// product with D formed once per element instead of once per wave).  Work items are ordered so
 // that consecutive items of one block land on the same XCD (its private L2
 // then serves the repeated panel reads).
 //
@@ -97,7 +98,6 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   const int R0 = it.y * 4, C0 = it.z * 4;
   const bool diag = (it.y == it.z);
   __shared__ __align__(16) T sA[2][8][TE];
-  __shared__ double sD[2][TS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
@@ -133,7 +133,9 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
     rmask[j] = I < b.mt ? B(-1) : B(0);
     rbase[j] = A + b.aoff + (long long)min(I, b.mt - 1) * b.nt * TE + pe[j];
   }
-  const double* Dbase = Dp + b.dpoff + (tid & 15);
+  // the elements a thread stages lie in column ((E tid) mod 256) / 16 of
+  // their tiles, whatever the load j, so one D value per K serves them all
+  const double* Dbase = Dp + b.dpoff + (((tid * E) & (TE - 1)) >> 4);
   V regs[2][NJ];
   double dreg[2];
   auto load = [&](int K, V* r, double& d) {
@@ -149,10 +151,12 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
     for (int j = 0; j < NJ; ++j) {
       V v;
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = keep_if<T>(r[j][e], km & rmask[j]);
+      for (int e = 0; e < E; ++e) {
+        v[e] = keep_if<T>(r[j][e], km & rmask[j]);
+        if (tl[j] >= 4) v[e] = v[e] * (T)keep_if<double>(d, (long long)km);
+      }
       *reinterpret_cast<V*>(&sA[buf][tl[j]][pe[j]]) = v;
     }
-    if (tid < TS) sD[buf][tid] = keep_if<double>(d, (long long)km);
     __syncthreads();
     load(K + 2, r, d);
     if (active) {
@@ -163,8 +167,7 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         T a0 = ra0[64 * s + lane], a1 = ra1[64 * s + lane];
-        T dd = (T)sD[buf][4 * s + (lane >> 4)];
-        T b0 = cb0[64 * s + lane] * dd, b1 = cb1[64 * s + lane] * dd;
+        T b0 = cb0[64 * s + lane], b1 = cb1[64 * s + lane];
         if (use[0][0]) acc[0][0] = mfma(a0, b0, acc[0][0]);
         if (use[0][1]) acc[0][1] = mfma(a0, b1, acc[0][1]);
         if (use[1][0]) acc[1][0] = mfma(a1, b0, acc[1][0]);
