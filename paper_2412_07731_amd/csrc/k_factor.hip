@@ -97,7 +97,6 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   const BlockInfo b = blk[it.x];
   const int R0 = it.y * 4, C0 = it.z * 4;
   const bool diag = (it.y == it.z);
-  __shared__ __align__(16) T sA[2][8][TE];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
@@ -119,55 +118,58 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 2; ++c) acc[a][c] = AT{0, 0, 0, 0};
 
-  // load j of a thread: stage tile tl[j] (0-3 row tiles, 4-7 column tiles;
-  // a diagonal item loads its row tiles twice), elements pe[j] .. + E - 1
-  int tl[NJ], pe[NJ];
+  // load j of a thread: stage tile (f / 256) (0-3 row tiles, 4-7 column
+  // tiles; a diagonal item loads its row tiles twice), elements f % 256 ..
+  // + E - 1, f = (tid + 256 j) E.  Consecutive threads take consecutive 16
+  // bytes, so a wave's load j fills 1 KiB of one tile: a direct-to-LDS load
+  // writes it at the wave's base plus 16 bytes per lane, with no registers
+  // in between.  Rows past the block read the last row tile again; the
+  // products that would use them are skipped.
   const T* rbase[NJ];
-  B rmask[NJ];
+  int ltile[NJ], lpe0[NJ];   // the wave's LDS destination of load j
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
-    const int f = (tid + 256 * j) * E;
-    tl[j] = f / TE;
-    pe[j] = f % TE;
-    const int I = tl[j] < 4 ? R0 + tl[j] : C0 + tl[j] - 4;
-    rmask[j] = I < b.mt ? B(-1) : B(0);
-    rbase[j] = A + b.aoff + (long long)min(I, b.mt - 1) * b.nt * TE + pe[j];
+    const int f = (tid + 256 * j) * E, f0 = (64 * wave + 256 * j) * E;
+    const int tl = f / TE;
+    const int I = tl < 4 ? R0 + tl : C0 + tl - 4;
+    rbase[j] = A + b.aoff + (long long)min(I, b.mt - 1) * b.nt * TE + f % TE;
+    ltile[j] = f0 / TE;
+    lpe0[j] = f0 % TE;
   }
-  // the elements a thread stages lie in column ((E tid) mod 256) / 16 of
-  // their tiles, whatever the load j, so one D value per K serves them all
-  const double* Dbase = Dp + b.dpoff + (((tid * E) & (TE - 1)) >> 4);
-  V regs[2][NJ];
-  double dreg[2];
-  auto load = [&](int K, V* r, double& d) {
+  // two stage buffers as distinct arrays, so that loads into one do not make
+  // the compiler wait before reads of the other
+  __shared__ __align__(16) T sA0[8][TE];
+  __shared__ __align__(16) T sA1[8][TE];
+  __shared__ double sD0[TS], sD1[TS];
+  const double* Dbase = Dp + b.dpoff + (tid & 15);
+  double dreg = 0.0;
+  auto stage = [&](auto bufc, int K) {   // stage K's tiles into buffer bufc
+    constexpr int BUF = decltype(bufc)::value;
     const long long Kc = min(K, b.nt - 1);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) r[j] = *reinterpret_cast<const V*>(rbase[j] + Kc * TE);
-    d = Dbase[Kc * TS];
-  };
-  auto step = [&](int K, V* r, double& d) {
-    const int buf = K & 1;
-    const B km = K < b.nt ? B(-1) : B(0);
-#pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      V v;
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        v[e] = keep_if<T>(r[j][e], km & rmask[j]);
-        if (tl[j] >= 4) v[e] = v[e] * (T)keep_if<double>(d, (long long)km);
-      }
-      *reinterpret_cast<V*>(&sA[buf][tl[j]][pe[j]]) = v;
+      T* dst = BUF ? &sA1[ltile[j]][lpe0[j]] : &sA0[ltile[j]][lpe0[j]];
+      __builtin_amdgcn_global_load_lds((const void*)(rbase[j] + Kc * TE),
+                                       (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
-    __syncthreads();
-    load(K + 2, r, d);
-    if (active) {
-      const T* ra0 = sA[buf][2 * wr];
-      const T* ra1 = sA[buf][2 * wr + 1];
-      const T* cb0 = sA[buf][4 + 2 * wc];
+    dreg = Dbase[Kc * TS];
+  };
+  auto step = [&](auto bufc, int K) {
+    constexpr int BUF = decltype(bufc)::value;
+    double* sD = BUF ? sD1 : sD0;
+    if (tid < TS) sD[tid] = dreg;
+    __syncthreads();   // stage K landed (each wave waited for its own loads)
+    if (K + 1 < b.nt) stage(std::integral_constant<int, 1 - BUF>{}, K + 1);
+    if (active && K < b.nt) {
+      const T* ra0 = BUF ? sA1[2 * wr] : sA0[2 * wr];
+      const T* ra1 = BUF ? sA1[2 * wr + 1] : sA0[2 * wr + 1];
+      const T* cb0 = BUF ? sA1[4 + 2 * wc] : sA0[4 + 2 * wc];
       const T* cb1 = cb0 + TE;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         T a0 = ra0[64 * s + lane], a1 = ra1[64 * s + lane];
-        T b0 = cb0[64 * s + lane], b1 = cb1[64 * s + lane];
+        T dd = (T)sD[4 * s + (lane >> 4)];
+        T b0 = cb0[64 * s + lane] * dd, b1 = cb1[64 * s + lane] * dd;
         if (use[0][0]) acc[0][0] = mfma(a0, b0, acc[0][0]);
         if (use[0][1]) acc[0][1] = mfma(a0, b1, acc[0][1]);
         if (use[1][0]) acc[1][0] = mfma(a1, b0, acc[1][0]);
@@ -175,12 +177,10 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
       }
     }
   };
-  // pairs of steps, the second of an odd count on zero tiles
-  load(0, regs[0], dreg[0]);
-  load(1, regs[1], dreg[1]);
+  stage(std::integral_constant<int, 0>{}, 0);
   for (int K = 0; K < b.nt; K += 2) {
-    step(K, regs[0], dreg[0]);
-    step(K + 1, regs[1], dreg[1]);
+    step(std::integral_constant<int, 0>{}, K);
+    step(std::integral_constant<int, 1>{}, K + 1);
   }
   if (!active) return;
 #pragma unroll
