@@ -158,7 +158,10 @@ __global__ __launch_bounds__(256) void k_syrk(const BlockInfo* __restrict__ blk,
     constexpr int BUF = decltype(bufc)::value;
     double* sD = BUF ? sD1 : sD0;
     if (tid < TS) sD[tid] = dreg;
-    __syncthreads();   // stage K landed (each wave waited for its own loads)
+    // every wave's direct-to-LDS loads of stage K complete before the barrier
+    // (the barrier's own fence orders LDS and need not wait for them)
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
     if (K + 1 < b.nt) stage(std::integral_constant<int, 1 - BUF>{}, K + 1);
     if (active && K < b.nt) {
       const T* ra0 = BUF ? sA1[2 * wr] : sA0[2 * wr];
