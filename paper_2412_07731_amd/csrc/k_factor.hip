@@ -460,6 +460,7 @@ __device__ __forceinline__ void schur_rows(const BlockInfo& b, const T* __restri
 // to 24, where the sixth row's accumulators fill the 256 VGPRs); a launch takes
 // the smaller that fits its widest block.
 constexpr int BF_PW = 2, BF_RMAX_MAX = 6;
+static_assert(BF_PW == 2, "the pipelined panel update takes its steps in pairs");
 // The panel kernel's LDS tiles are column-major with leading dimension 17:
 // the accumulator layout writes a tile by columns across the lanes, which
 // with 16 would put the 16 lanes of a row group in the same bank; with 17
@@ -493,8 +494,11 @@ __device__ __forceinline__ BfOp<T> bf_ld_p(const T* __restrict__ t) {
 template <typename T, int LD>
 __device__ __forceinline__ void tile_copy_p(T* __restrict__ dst, const T* __restrict__ src) {
   const int lane = threadIdx.x & 63;
+  T v[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) dst[64 * s + lane] = src[pidx<LD>(64 * s + lane)];
+  for (int s = 0; s < 4; ++s) v[s] = src[pidx<LD>(64 * s + lane)];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) dst[64 * s + lane] = v[s];
 }
 
 // Synchronization of the panel factor's four waves in the standalone kernel:
@@ -659,30 +663,107 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
         }
       }
     }
-    // left-looking update with the tile columns before the panel (all loads
-    // of a step issued together)
-    for (int k = 0; k < c0; ++k) {
-      BfOp<T> Ac[BF_RMAX], Bc[BF_PW];
+    // left-looking update with the tile columns before the panel
+    if constexpr (BF_RMAX <= 5 && sizeof(T) == 4) {
+      // FP32, software-pipelined: step k + 1's tiles are requested while step k's
+      // products run.  A row's registers take its next tile as soon as the
+      // row's products have been issued; the two panel-column tiles, which
+      // every row needs first, are double-buffered.  Every load is
+      // unconditional, so that the compiler waits for exactly the tiles a
+      // product needs: a wave with fewer than BF_RMAX rows in the panel loads
+      // the panel's first tile row (already in its cache) for the others, and
+      // the last step requests its own tiles again.  (In FP64, where each
+      // product takes twice as long, the same loop measured no faster:
+      // the two blocks sharing the CU keep the matrix pipe busy while one
+      // waits for its tiles.)
+      int nrow = rt - c0 - w;
+      nrow = nrow > 0 ? min(BF_RMAX, (nrow + NW - 1) / NW) : 0;
+      BfOp<T> Ac[BF_RMAX], B0[BF_PW], B1[BF_PW];
+      auto ld_b = [&](BfOp<T>* Bc, int k) {
+#pragma unroll
+        for (int j = 0; j < BF_PW; ++j) Bc[j] = bf_ld<T>(LB + lb_tile(b, min(c0 + j, rt - 1), k));
+      };
+      auto ld_a = [&](int t, int k) {
+        Ac[t] = bf_ld<T>(LB + lb_tile(b, t < nrow ? c0 + w + NW * t : c0, k));
+      };
+      // the row's products (the row's tile is negated rather than the shared
+      // column tiles: the same products, fewer registers held)
+      auto row_mm = [&](int t, const BfOp<T>* Bc) {
+        const int r = c0 + w + NW * t;
+        if (t < nrow) {
+#pragma unroll
+          for (int j = 0; j < BF_PW; ++j)
+            if (j < pw && r >= c0 + j)
+#pragma unroll
+              for (int s = 0; s < 4; ++s)
+                acc[t][j] = TR ? mfma(Bc[j].v[s], -Ac[t].v[s], acc[t][j])
+                               : mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
+        }
+      };
+      // the order of issue is fixed (no scheduling across these points)
+      auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
+      // (issued in the first panel too, where nothing uses them: loads under
+      // a branch would make the compiler wait for every earlier tile)
+      fence();
+      ld_b(B0, 0);
 #pragma unroll
       for (int t = 0; t < BF_RMAX; ++t) {
-        const int r = c0 + w + NW * t;
-        if (r < rt) Ac[t] = bf_ld<T>(LB + lb_tile(b, r, k));
+        fence();
+        ld_a(t, 0);
       }
+      fence();
+      for (int k = 0; k < c0; k += BF_PW) {   // c0 is a multiple of BF_PW = 2
+        fence();
+        ld_b(B1, k + 1);
 #pragma unroll
-      for (int j = 0; j < BF_PW; ++j)
-        if (j < pw) Bc[j] = bf_ld<T>(LB + lb_tile(b, c0 + j, k));
+        for (int t = 0; t < BF_RMAX; ++t) {
+          fence();
+          row_mm(t, B0);
+          fence();
+          ld_a(t, k + 1);
+        }
+        const int k2 = min(k + 2, c0 - 1);
+        fence();
+        ld_b(B0, k2);
 #pragma unroll
-      for (int t = 0; t < BF_RMAX; ++t) {
-        const int r = c0 + w + NW * t;
+        for (int t = 0; t < BF_RMAX; ++t) {
+          fence();
+          row_mm(t, B1);
+          fence();
+          ld_a(t, k2);
+        }
+        fence();
+      }
+    } else {
+      // all loads of a step issued together
+      for (int k = 0; k < c0; ++k) {
+        BfOp<T> Ac[BF_RMAX], Bc[BF_PW];
+#pragma unroll
+        for (int t = 0; t < BF_RMAX; ++t) {
+          const int r = c0 + w + NW * t;
+          if (r < rt) Ac[t] = bf_ld<T>(LB + lb_tile(b, r, k));
+        }
 #pragma unroll
         for (int j = 0; j < BF_PW; ++j)
-          if (r < rt && j < pw && r >= c0 + j)
+          if (j < pw) Bc[j] = bf_ld<T>(LB + lb_tile(b, c0 + j, k));
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-              acc[t][j] = TR ? mfma(-Bc[j].v[s], Ac[t].v[s], acc[t][j])
-                             : mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
+        for (int t = 0; t < BF_RMAX; ++t) {
+          const int r = c0 + w + NW * t;
+#pragma unroll
+          for (int j = 0; j < BF_PW; ++j)
+            if (r < rt && j < pw && r >= c0 + j)
+#pragma unroll
+              for (int s = 0; s < 4; ++s)
+                acc[t][j] = TR ? mfma(-Bc[j].v[s], Ac[t].v[s], acc[t][j])
+                               : mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
+        }
       }
     }
+    // Every input and update load of the panel has been consumed.  Saying so
+    // once here keeps the compiler's conservative wait for them (it cannot
+    // tell a zero-trip update loop from a full one) out of the solves below,
+    // where the outstanding memory operations are the previous rows' stores.
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     // factor the panel column by column
 #pragma unroll
     for (int j = 0; j < BF_PW; ++j) {
@@ -701,8 +782,6 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
           }
         wave_order();
         cnt += wave_chol_tile<T, LD>(dt, dt, li, thr, nullptr);
-        tile_copy_p<T, LD>(LB + lb_tile(b, c, c), dt);
-        tile_copy_p<T, LD>(LINV + b.linvoff + (long long)c * TE, li);
       }
       sy.sync();
       // rows below: L(r, c) = acc(r, c) L_cc^-T
@@ -740,6 +819,13 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
             }
           }
         }
+      }
+      // the diagonal tile's factor and inverse, needed only after the kernel,
+      // go out now, off the chain (dt and li stay untouched until the next
+      // barrier)
+      if (w == ow) {
+        tile_copy_p<T, LD>(LB + lb_tile(b, c, c), dt);
+        tile_copy_p<T, LD>(LINV + b.linvoff + (long long)c * TE, li);
       }
       sy.sync();
       qpend = c;
