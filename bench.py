@@ -308,16 +308,20 @@ def general_bench(golden_runs, steps=3):
 
 
 def ceilings():
-    """Measured ceilings of this device (ahlp_ceiling_mfma, ahlp_ceiling_hbm_read):
-    the MFMA instructions of the factorization on dependency-free streams, and
-    a streaming read of 2 GiB; the rooflines' frac_of_measured divide by these,
-    their frac by the published peaks."""
+    """Measured ceilings of this device (ahlp_ceiling_mfma, ahlp_ceiling_hbm_read,
+    ahlp_ceiling_tile_chol): the MFMA instructions of the factorization on
+    dependency-free streams, a streaming read of 2 GiB, and the latency of the
+    block factor's one-wave tile Cholesky (16 of which are on every block's
+    chain) alone on its SIMD and beside an FP64 MFMA stream; the rooflines'
+    frac_of_measured divide by the first two, their frac by the published peaks."""
     import torch
     from paper_2412_07731_amd import ahlp as A
     buf = torch.zeros(1 << 28, dtype=torch.float64, device="cuda")
     out = {"mfma_f64_tflops": A.ceiling_mfma(A.FP64),
            "mfma_f32_tflops": A.ceiling_mfma(A.FP32_REFINE),
            "hbm_read_gbs": A.ceiling_hbm_read(buf),
+           "tile_chol_us": {"alone": A.ceiling_tile_chol(False),
+                            "beside_fp64_mfma": A.ceiling_tile_chol(True)},
            "published": {"mfma_f64_tflops": PEAK_FP64_TFLOPS, "mfma_f32_tflops": PEAK_FP32_TFLOPS,
                          "hbm_gbs": PEAK_HBM_GBS}}
     del buf

@@ -369,7 +369,7 @@ const char* ahlp_last_error(void);
 
 /* ---- device ceilings (measurement aids, not part of the method) ----------
  * Achievable rates of this device, so that kernels can be reported against
- * measured ceilings beside the published peaks.  Both synchronize `stream`
+ * measured ceilings beside the published peaks.  They synchronize `stream`
  * and allocate a small device buffer of their own. */
 
 /* Throughput of the MFMA instruction the factorization kernels use
@@ -387,6 +387,18 @@ ahlp_status_t ahlp_ceiling_mfma(int32_t precision, double* tflops, hipStream_t s
  * never written.  AHLP_EINVAL for null or misaligned pointers or n < 2. */
 ahlp_status_t ahlp_ceiling_hbm_read(const double* buf, int64_t n, double* gbps,
                                     hipStream_t stream);
+
+/* Latency of the block factor's one-wave 16x16 tile Cholesky (FP64, the
+ * elimination of the diagonal tile that sits on each block's dependency
+ * chain, Alg. 2's factorization of M_i): one wave per CU factors an LDS tile
+ * 256 times; *us_per_tile in microseconds, the best of three timed launches
+ * after one untimed.  beside_mfma = 1 adds four waves per workgroup that
+ * stream FP64 MFMAs meanwhile, one of them on the factoring wave's SIMD (as
+ * a co-resident block's wave is in the factor); 0 leaves the SIMD to the
+ * factoring wave.  AHLP_EINVAL for a null pointer or beside_mfma other than
+ * 0 or 1. */
+ahlp_status_t ahlp_ceiling_tile_chol(int32_t beside_mfma, double* us_per_tile,
+                                     hipStream_t stream);
 
 /* ---- inspection (tests and profiling; synchronize the stream) ------------
  * Copy intermediate results of the last factorization to HOST memory in the

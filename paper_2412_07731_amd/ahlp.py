@@ -98,6 +98,7 @@ SIGNATURES = {
     "ahlp_debug_pivots": ([C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
     "ahlp_ceiling_mfma": ([C.c_int32, C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "ahlp_ceiling_hbm_read": ([C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "ahlp_ceiling_tile_chol": ([C.c_int32, C.POINTER(C.c_double), C.c_void_p], C.c_int),
 }
 
 _lib = None
@@ -166,6 +167,14 @@ def ceiling_hbm_read(buf, stream=None):
     contiguous cuda float64 tensor buf (make it a GiB or more)."""
     v = C.c_double()
     _check(lib().ahlp_ceiling_hbm_read(_dptr(buf), int(buf.numel()), C.byref(v), _stream(stream)))
+    return v.value
+
+
+def ceiling_tile_chol(beside_mfma=False, stream=None):
+    """ahlp_ceiling_tile_chol: microseconds per one-wave FP64 tile Cholesky,
+    alone on its SIMD or beside a wave that streams FP64 MFMAs."""
+    v = C.c_double()
+    _check(lib().ahlp_ceiling_tile_chol(int(bool(beside_mfma)), C.byref(v), _stream(stream)))
     return v.value
 
 

@@ -2371,6 +2371,35 @@ ahlp_status_t ahlp_ceiling_hbm_read(const double* buf, int64_t n, double* gbps,
   return AHLP_OK;
 }
 
+ahlp_status_t ahlp_ceiling_tile_chol(int32_t beside_mfma, double* us_per_tile,
+                                     hipStream_t stream) {
+  if (!us_per_tile) return fail(AHLP_EINVAL, "null argument");
+  if (beside_mfma != 0 && beside_mfma != 1) return fail(AHLP_EINVAL, "beside_mfma must be 0 or 1");
+  int grid = 0;
+  CHK(ceil_grid(1, &grid));   // one workgroup per CU
+  const int iters = 256;
+  CeilBuf cb;
+  HIPCHK(hipMalloc(&cb.out, (size_t)grid * sizeof(double)));
+  HIPCHK(hipEventCreate(&cb.e0));
+  HIPCHK(hipEventCreate(&cb.e1));
+  launch_ceiling_chol(stream, beside_mfma == 1, grid, iters, cb.out);
+  float best = 0.f;
+  for (int rep = 0; rep < 3; ++rep) {
+    HIPCHK(hipEventRecord(cb.e0, stream));
+    launch_ceiling_chol(stream, beside_mfma == 1, grid, iters, cb.out);
+    HIPCHK(hipEventRecord(cb.e1, stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(cb.e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, cb.e0, cb.e1));
+    if (rep == 0 || ms < best) best = ms;
+  }
+  // the launch lasts as long as the factoring waves' loop (the streaming
+  // waves stop at its flag)
+  *us_per_tile = (double)best * 1e3 / iters;
+  return AHLP_OK;
+}
+
 ahlp_status_t ahlp_debug_pivots(ahlp_problem_t p, int32_t* count) {
   if (!p || !count) return fail(AHLP_EINVAL, "null argument");
   CHK(check_info(p, p->timer.st, nullptr));

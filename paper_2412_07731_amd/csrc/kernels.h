@@ -132,6 +132,8 @@ void set_bcr_smem_limits();
 // device ceilings (k_ceiling.hip): grid workgroups of 256 threads
 void launch_ceiling_mfma(hipStream_t st, bool fp32, int grid, int iters, double* out);
 void launch_ceiling_read(hipStream_t st, const double* buf, long long n, int grid, double* out);
+// grid workgroups of one factoring wave (and four MFMA-streaming waves if beside)
+void launch_ceiling_chol(hipStream_t st, bool beside, int grid, int iters, double* out);
 // two-tile pairs (k_bcr2.hip): the reduction of T down to the final pair, and
 // the whole solve
 void launch_bcr2_reduce(hipStream_t st, const BcrArgs& c);

@@ -1,6 +1,8 @@
-"""The device-ceiling measurement aids (ahlp_ceiling_mfma, ahlp_ceiling_hbm_read):
-positive rates no higher than the device can deliver (the published MI355X
-figures with 5% slack for clock variation), and refusal of bad arguments."""
+"""The device-ceiling measurement aids (ahlp_ceiling_mfma, ahlp_ceiling_hbm_read,
+ahlp_ceiling_tile_chol): positive rates no higher than the device can deliver
+(the published MI355X figures with 5% slack for clock variation), a tile
+Cholesky latency within the bounds its instruction count allows, and refusal
+of bad arguments."""
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -38,3 +40,18 @@ def test_hbm_read_ceiling(dev):
     v = ahlp.C.c_double()
     assert ahlp.lib().ahlp_ceiling_hbm_read(None, 1 << 20, ahlp.C.byref(v), None) == -1
     assert ahlp.lib().ahlp_ceiling_hbm_read(ahlp._dptr(buf), 1, ahlp.C.byref(v), None) == -1
+
+
+def test_tile_chol_latency(dev):
+    print("case: tile Cholesky latency, alone and beside an MFMA stream", flush=True)
+    alone = ahlp.ceiling_tile_chol(False)
+    beside = ahlp.ceiling_tile_chol(True)
+    print(f"  alone {alone:.2f} us, beside FP64 MFMAs {beside:.2f} us", flush=True)
+    # 16 dependent elimination steps of at least ~40 instructions issue in no
+    # less than 16*40*4 cycles (0.1 us at 2.4 GHz); far more than 50 us would
+    # mean the loop is not what is timed
+    assert 0.1 < alone < 50.0
+    assert 0.1 < beside < 50.0
+    v = ahlp.C.c_double()
+    assert ahlp.lib().ahlp_ceiling_tile_chol(0, None, None) == -1
+    assert ahlp.lib().ahlp_ceiling_tile_chol(2, ahlp.C.byref(v), None) == -1
