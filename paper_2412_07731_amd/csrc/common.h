@@ -107,27 +107,6 @@ __device__ inline f4 mfma(float a, float b, f4 c) {
 #endif
 }
 
-// FP64 4x4x4 MFMA with 4 blocks: on gfx950 it issues at the full FP64 matrix
-// rate, twice the rate of the 16x16x4 form (measured with a throughput probe).
-// Lane l supplies A(block (l/4)%4, row l%4, k l/16) and B(block (l/4)%4, col
-// l%4, k l/16) and receives D(block (l/4)%4, row l/16, col l%4).  Four of them
-// (instruction n = row block n of the 16x16 tile, the blocks = its four column
-// blocks) make one 16x16x4 product with the same accumulator layout as the
-// 16x16x4 form: B is the 16x16x4 B operand and instruction n takes
-// A(4n + l%4, k l/16).
-__device__ inline double mfma4(double a, double b, double c) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-#else
-  return c;
-#endif
-}
-// Index in a column-major 16x16 tile of the A value lane l supplies to the
-// n-th 4x4x4 instruction of K-slice s (columns 4s..4s+3).
-__host__ __device__ inline int a4_index(int lane, int s, int n) {
-  return 64 * s + 16 * (lane >> 4) + 4 * n + (lane & 3);
-}
-
 template <typename T> struct Acc;
 template <> struct Acc<double> { typedef d4 type; };
 template <> struct Acc<float> { typedef f4 type; };
