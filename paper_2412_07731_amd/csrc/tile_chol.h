@@ -58,14 +58,13 @@ __device__ __forceinline__ float lane_bcast<float>(float v, int src) {
 }
 
 // value of lane J of each 16-lane row, in every lane of that row
-// (row_newbcast writes every lane, so the move needs no old value)
+// (row_newbcast writes every lane, so the move needs no old value; it is the
+// one DPP control with a 64-bit move, one instruction for a double)
 template <int J>
 __device__ __forceinline__ double row_bcast(double v) {
-  union { double d; int i[2]; } u, o;
-  u.d = v;
-  o.i[0] = __builtin_amdgcn_mov_dpp(u.i[0], 0x150 + J, 0xF, 0xF, false);
-  o.i[1] = __builtin_amdgcn_mov_dpp(u.i[1], 0x150 + J, 0xF, 0xF, false);
-  return o.d;
+  const long long x = __builtin_bit_cast(long long, v);
+  const long long y = __builtin_amdgcn_mov_dpp(x, 0x150 + J, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, y);
 }
 template <int J>
 __device__ __forceinline__ float row_bcast(float v) {
