@@ -131,13 +131,15 @@ struct DevInfo {
 // Cross-lane sums on the VALU (DPP moves within a 16-lane row, permlane
 // swaps across rows) instead of LDS-pipe permutes.  Each gives every lane the
 // additions of the xor butterfly x += shfl_xor(x, s) over its strides, in the
-// same order, so the results are bitwise the same.
+// same order, so the results are bitwise the same.  The controls used here
+// (quad permutations, row mirrors) give every lane a source, so a move needs
+// no old value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
   union { double d; int i[2]; } u, o;
   u.d = v;
-  o.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], CTRL, 0xF, 0xF, false);
-  o.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], CTRL, 0xF, 0xF, false);
+  o.i[0] = __builtin_amdgcn_mov_dpp(u.i[0], CTRL, 0xF, 0xF, false);
+  o.i[1] = __builtin_amdgcn_mov_dpp(u.i[1], CTRL, 0xF, 0xF, false);
   return o.d;
 }
 // strides 1, 2, 4, 8: the sum over the lane's 16-lane row.  After the two
