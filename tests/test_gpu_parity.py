@@ -301,7 +301,13 @@ def _fp32_factor_bounds(A, D, L, W, B, delta):
     return lhs_l, rhs_l, lhs_w, rhs_w, kap
 
 
-@pytest.mark.parametrize("config", ["tiny", "n512"])
+# ragged blocks of 70-150 rows (5-10 tile rows, odd counts among them) with
+# 4-20 link rows per pair: one-column last panels and waves with fewer rows
+# than the panel kernel's maximum, in the FP32 panel factor's pipelined update
+RAGGED_FP32 = dict(N=6, m=(70, 150), n="2m", l=(4, 20), n0=5, density=0.3)
+
+
+@pytest.mark.parametrize("config", ["tiny", "n512", RAGGED_FP32], ids=["tiny", "n512", "ragged"])
 def test_fp32_stage_parity(dev, config):
     """FP32 block factors (SYRK, Cholesky and W_i = L_i^-1 B_i in FP32 MFMA)
     against the FP64 oracle's blocks: the componentwise backward-error bounds
