@@ -686,8 +686,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
       auto ld_a = [&](int t, int k) {
         Ac[t] = bf_ld<T>(LB + lb_tile(b, t < nrow ? c0 + w + NW * t : c0, k));
       };
-      // the row's products (the row's tile is negated rather than the shared
-      // column tiles: the same products, fewer registers held)
+      // the row's products
       auto row_mm = [&](int t, const BfOp<T>* Bc) {
         const int r = c0 + w + NW * t;
         if (t < nrow) {
@@ -695,9 +694,7 @@ __device__ __forceinline__ void panel_factor(const BlockInfo& b, T* __restrict__
           for (int j = 0; j < BF_PW; ++j)
             if (j < pw && r >= c0 + j)
 #pragma unroll
-              for (int s = 0; s < 4; ++s)
-                acc[t][j] = TR ? mfma(Bc[j].v[s], -Ac[t].v[s], acc[t][j])
-                               : mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
+              for (int s = 0; s < 4; ++s) acc[t][j] = mfma(-Ac[t].v[s], Bc[j].v[s], acc[t][j]);
         }
       };
       // the order of issue is fixed (no scheduling across these points)
